@@ -1,0 +1,218 @@
+"""CPU oracle for the R-distance -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU engine never imports, links or
+calls it, and the two share no code.
+
+The arithmetic lives in ``rdist_oracle.c`` (plain IEEE double, no FMA
+contraction, unblocked Gauss-Jordan without pivoting, libm ``log``).  This
+wrapper only marshals numpy arrays through ctypes.
+
+Paper: Jing & Meister, arXiv 2308.07403.  Convention (Sec. 2): ``A[i, j] = 1``
+iff edge ``j -> i``; ``D[i, j]`` is the distance from ``j`` to ``i``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rdist_oracle.c")
+_LIB = os.path.join(_HERE, "librdist_oracle.so")
+
+OK, E_ARG, E_ADJ, E_NOT_DD, E_PIVOT, E_NOMEM = 0, 1, 2, 3, 4, 5
+UNREACHABLE = 0x7FFF
+ETA = 1e-9      # ceil(R - eta): the reading of the rounded distance at exact integers
+BETA = 1e-10    # band around a threshold k + eta that is reported as ambiguous
+FW_INF = 0x3FFFFFFF
+
+_CFLAGS = ["-O2", "-ftree-vectorize", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-std=c11"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain IEEE double, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        i32, f64, i64 = ctypes.c_int, ctypes.c_double, ctypes.c_int64
+        L.orc_prepare.argtypes = [P, i32, f64, P, P, P]
+        L.orc_prepare.restype = i32
+        L.orc_build_m.argtypes = [P, i32, f64, P]
+        L.orc_gj_steps.argtypes = [P, i32, i32, i32, P]
+        L.orc_gj_steps.restype = i32
+        L.orc_gj_invert.argtypes = [P, i32, P]
+        L.orc_gj_invert.restype = i32
+        L.orc_readout.argtypes = [P, i32, f64, f64, f64, P, P]
+        L.orc_solve.argtypes = [P, i32, f64, f64, f64, P, P, P, P, P, P]
+        L.orc_solve.restype = i32
+        L.orc_next_hop.argtypes = [P, P, i32, i32, i32]
+        L.orc_next_hop.restype = i32
+        L.orc_path.argtypes = [P, P, i32, i32, i32, i32, P]
+        L.orc_bfs.argtypes = [P, i32, P, P]
+        L.orc_floyd_warshall.argtypes = [P, i32, i32, i32, P]
+        L.orc_num_threads.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _adj(A) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.uint8)
+    assert A.ndim == 2 and A.shape[0] == A.shape[1]
+    return A
+
+
+@dataclass
+class Prep:
+    status: int
+    delta: int
+    gamma: float
+    outdeg: np.ndarray
+
+
+def prepare(A, gamma_arg: float) -> Prep:
+    """Validation, out-degrees, Delta, gain and the gate (gamma * Delta < 1)."""
+    A = _adj(A)
+    n = A.shape[0]
+    outdeg = np.zeros(max(n, 1), dtype=np.int32)
+    delta = np.zeros(1, dtype=np.int32)
+    gamma = np.zeros(1, dtype=np.float64)
+    st = lib().orc_prepare(_p(A), n, float(gamma_arg), _p(outdeg), _p(delta), _p(gamma))
+    return Prep(int(st), int(delta[0]), float(gamma[0]), outdeg[:n])
+
+
+def build_m(A, gamma: float) -> np.ndarray:
+    A = _adj(A)
+    n = A.shape[0]
+    M = np.empty((n, n), dtype=np.float64)
+    lib().orc_build_m(_p(A), n, float(gamma), _p(M))
+    return M
+
+
+def gj_inverse(M, count_swaps: bool = False):
+    """Unblocked Gauss-Jordan inverse, no pivoting.  Returns (Y, would_swap)."""
+    Y = np.array(M, dtype=np.float64, order="C", copy=True)
+    sw = np.zeros(1, dtype=np.int64)
+    st = lib().orc_gj_invert(_p(Y), Y.shape[0], _p(sw) if count_swaps else None)
+    if st != OK:
+        raise ArithmeticError(f"oracle Gauss-Jordan failed with status {st}")
+    return Y, int(sw[0])
+
+
+def gj_steps_inplace(M: np.ndarray, k0: int, k1: int) -> int:
+    """Run elimination steps k0..k1-1 in place (used to time a bounded sample)."""
+    assert M.flags.c_contiguous and M.dtype == np.float64
+    return int(lib().orc_gj_steps(_p(M), M.shape[0], int(k0), int(k1), None))
+
+
+@dataclass
+class Readout:
+    D: np.ndarray
+    unreachable: int
+    subnormal: int
+    saturated: int
+    ambiguous: int
+    negative: int
+
+
+def readout(Y, gamma: float, eta: float = ETA, beta: float = BETA) -> Readout:
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    n = Y.shape[0]
+    D = np.empty((n, n), dtype=np.int16)
+    c = np.zeros(5, dtype=np.int64)
+    lib().orc_readout(_p(Y), n, float(gamma), float(eta), float(beta), _p(D), _p(c))
+    return Readout(D, *[int(x) for x in c])
+
+
+@dataclass
+class Solution:
+    status: int
+    delta: int
+    gamma: float
+    D: np.ndarray
+    Y: np.ndarray | None
+    unreachable: int = 0
+    subnormal: int = 0
+    saturated: int = 0
+    ambiguous: int = 0
+    negative: int = 0
+    would_swap: int = 0
+
+
+def solve(A, gamma_arg: float, keep_y: bool = True, eta: float = ETA, beta: float = BETA) -> Solution:
+    """Full oracle pipeline: gate, M = I - gamma*A, Gauss-Jordan inverse, readout."""
+    A = _adj(A)
+    n = A.shape[0]
+    D = np.empty((n, n), dtype=np.int16)
+    Y = np.empty((n, n), dtype=np.float64) if keep_y else None
+    delta = np.zeros(1, dtype=np.int32)
+    gamma = np.zeros(1, dtype=np.float64)
+    c = np.zeros(5, dtype=np.int64)
+    sw = np.zeros(1, dtype=np.int64)
+    st = lib().orc_solve(_p(A), n, float(gamma_arg), float(eta), float(beta), _p(D),
+                         _p(Y) if keep_y else None, _p(delta), _p(gamma), _p(c), _p(sw))
+    return Solution(int(st), int(delta[0]), float(gamma[0]), D, Y if st == OK else None,
+                    *[int(x) for x in c], int(sw[0]))
+
+
+def next_hop(A, Y, cur: int, goal: int) -> int:
+    A = _adj(A)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    return int(lib().orc_next_hop(_p(A), _p(Y), A.shape[0], int(cur), int(goal)))
+
+
+def path(A, Y, cur: int, goal: int, max_hops: int) -> np.ndarray:
+    A = _adj(A)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    out = np.empty(max_hops + 1, dtype=np.int32)
+    lib().orc_path(_p(A), _p(Y), A.shape[0], int(cur), int(goal), int(max_hops), _p(out))
+    return out
+
+
+def paths(A, Y, pairs, max_hops: int) -> np.ndarray:
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    return np.stack([path(A, Y, int(s), int(g), max_hops) for s, g in pairs]) if len(pairs) else \
+        np.empty((0, max_hops + 1), dtype=np.int32)
+
+
+def bfs(A):
+    """(dist, count): shortest-path lengths j -> i (-1 unreachable) and path counts S_ij."""
+    A = _adj(A)
+    n = A.shape[0]
+    dist = np.empty((n, n), dtype=np.int32)
+    cnt = np.empty((n, n), dtype=np.float64)
+    lib().orc_bfs(_p(A), n, _p(dist), _p(cnt))
+    return dist, cnt
+
+
+def floyd_warshall(A, k_steps: int | None = None) -> np.ndarray:
+    """Min-plus APSP baseline; ``k_steps`` limits the relaxation to a bounded sample."""
+    A = _adj(A)
+    n = A.shape[0]
+    dist = np.empty((n, n), dtype=np.int32)
+    lib().orc_floyd_warshall(_p(A), n, 0, n if k_steps is None else int(k_steps), _p(dist))
+    return dist
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())

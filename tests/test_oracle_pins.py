@@ -1,0 +1,428 @@
+"""Pins for the CPU oracle: checks against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None of them re-types the oracle's own
+formula: they use the paper's printed worked example, closed forms, exact
+integer walk counts, theorems checked by brute force, a library inverse
+(LAPACK through numpy) and a library shortest-path routine (scipy).
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse.csgraph as csg
+
+import graphgen as gg
+import oracle
+from conftest import read_golden
+
+EPS = np.finfo(np.float64).eps
+DBL_MIN = np.finfo(np.float64).tiny
+
+
+def rdist_ungated(A, gamma):
+    """Oracle arithmetic without the diagonal-dominance gate (for theorem checks)."""
+    Y, _ = oracle.gj_inverse(oracle.build_m(A, gamma))
+    return Y, oracle.readout(Y, gamma).D
+
+
+def bfs_scipy(A):
+    """Distance from j to i at [i, j] (-1 unreachable), via scipy's BFS."""
+    d = csg.shortest_path(np.ascontiguousarray(A.T, dtype=np.float64), unweighted=True, directed=True)
+    d = d.T
+    out = np.where(np.isinf(d), -1, d).astype(np.int64)
+    return out
+
+
+def diameter(dist):
+    return int(dist[dist >= 0].max())
+
+
+# ---------------------------------------------------------------------------
+# The paper's worked example (Sec. 4.1.1): undirected path on three vertices
+# ---------------------------------------------------------------------------
+
+def _p3_fixture():
+    rows = read_golden("p3_worked_example.txt")
+    cases, gamma = [], None
+    for k, v in rows:
+        if k == "gamma":
+            gamma = Fraction(v)
+        elif k == "Y":
+            Y = [[Fraction(t) for t in r.split()] for r in v.split("|")]
+            cases.append((gamma, Y))
+    meta = dict((k, v) for k, v in rows if k in ("A", "critical_gain", "eigenvalues"))
+    return cases, meta
+
+
+def test_p3_printed_closed_form():
+    cases, meta = _p3_fixture()
+    A = np.array([[int(t) for t in r.split()] for r in meta["A"].split("|")], dtype=np.uint8)
+    assert np.array_equal(A, gg.undirected_path3())
+    assert len(cases) == 2
+    for gamma, Yq in cases:
+        sol = oracle.solve(A, float(gamma))
+        assert sol.status == oracle.OK
+        Yx = np.array([[float(q) for q in r] for r in Yq])
+        assert np.max(np.abs(sol.Y - Yx) / Yx) < 4 * EPS
+        # below gamma = 1/2 the rounded R-distance is the graph distance
+        assert np.array_equal(sol.D, np.array([[0, 1, 2], [1, 0, 1], [2, 1, 0]]))
+
+
+def test_p3_critical_gain_and_failure_above_half():
+    _, meta = _p3_fixture()
+    A = gg.undirected_path3()
+    ev = np.sort(np.linalg.eigvalsh(A.astype(np.float64)))
+    assert np.allclose(ev, [float(x) for x in meta["eigenvalues"].split()], atol=1e-14)
+    assert abs(1.0 / ev.max() - float(meta["critical_gain"])) < 1e-15
+    truth = bfs_scipy(A)
+    # globally correct just below 1/2 ...
+    _, D = rdist_ungated(A, 0.499)
+    assert np.array_equal(D, truth)
+    # ... but not between 1/2 and the critical gain (Y_12 = g/(1-2g^2) > 1)
+    Y, D = rdist_ungated(A, 0.6)
+    assert not np.array_equal(D, truth)
+    assert Y[0, 1] > 1.0
+    # the gate refuses gamma * Delta >= 1 (Delta = 2 here)
+    assert oracle.solve(A, 0.5).status == oracle.E_NOT_DD
+    # approaching the critical gain the R-distance of adjacent vertices diverges to -inf
+    g = 0.7071
+    Y, _ = rdist_ungated(A, g)
+    assert math.log(Y[0, 1]) / math.log(g) < -10
+
+
+# ---------------------------------------------------------------------------
+# Closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("gamma", [0.1, 0.5, 0.9])
+def test_directed_path(gamma):
+    n = 40
+    A = gg.directed_path(n)          # j -> j+1, so A is sub-diagonal
+    sol = oracle.solve(A, gamma)
+    assert sol.status == oracle.OK and sol.delta == 1
+    i, j = np.indices((n, n))
+    d = i - j
+    below = d >= 0
+    expect = np.where(below, np.power(gamma, np.where(below, d, 0).astype(np.float64)), 0.0)
+    assert np.all(sol.Y[~below] == 0.0)
+    rel = np.abs(sol.Y[below] - expect[below]) / expect[below]
+    assert rel.max() < 64 * EPS
+    assert np.array_equal(sol.D[below], d[below])           # exact integers: the eta reading
+    assert np.all(sol.D[~below] == oracle.UNREACHABLE)
+
+
+def test_directed_cycle():
+    n, gamma = 30, 0.3
+    A = gg.directed_cycle(n)
+    sol = oracle.solve(A, gamma)
+    i, j = np.indices((n, n))
+    d = (i - j) % n
+    expect = gamma ** d / (1.0 - gamma ** n)
+    assert np.max(np.abs(sol.Y - expect) / expect) < 128 * EPS
+    assert np.array_equal(sol.D, d)
+
+
+def test_complete_digraph_sherman_morrison():
+    n = 50
+    A = gg.complete_digraph(n)
+    sol = oracle.solve(A, -0.5)
+    assert sol.delta == n - 1
+    g = sol.gamma
+    assert g == 0.5 / (n - 1)
+    expect = (np.eye(n) + g * np.ones((n, n)) / (1.0 - (n - 1) * g)) / (1.0 + g)
+    assert np.max(np.abs(sol.Y - expect) / expect) < 64 * n * EPS
+    assert np.array_equal(sol.D, 1 - np.eye(n, dtype=np.int16))
+
+
+# ---------------------------------------------------------------------------
+# Identities and invariants
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(3))
+def test_inverse_identities_and_theorem4_identity(seed):
+    A = gg.erdos_renyi(150, 0.05, gg.rng_for("pin", seed))
+    sol = oracle.solve(A, -0.5)
+    Y, g = sol.Y, sol.gamma
+    M = np.eye(A.shape[0]) - g * A
+    n = A.shape[0]
+    scale = np.abs(Y).max()
+    assert np.abs(M @ Y - np.eye(n)).max() < 8 * n * EPS * scale
+    assert np.abs(Y @ M - np.eye(n)).max() < 8 * n * EPS * scale
+    # proof of Theorem 4: Y_gi = gamma * sum_j Y_gj A_ji for i != g
+    R = g * (Y @ A)
+    off = ~np.eye(n, dtype=bool)
+    assert np.all(np.abs(Y[off] - R[off]) <= 8 * n * EPS * np.maximum(Y[off], 1e-300) + 1e-300)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_truncated_neumann_series(seed):
+    rng = gg.rng_for("pin", 100 + seed)
+    n = int(rng.integers(4, 12))
+    A = gg.erdos_renyi(n, 0.3, rng)
+    prep = oracle.prepare(A, -0.5)
+    g, delta = prep.gamma, max(prep.delta, 1)
+    Y, _ = oracle.gj_inverse(oracle.build_m(A, g))
+    K = 40
+    # exact integer walk counts N^(k) = A^k (Sec. 3.1), summed with gamma^k
+    Ak = np.eye(n, dtype=np.int64)
+    S = np.zeros((n, n))
+    for k in range(K + 1):
+        S += (g ** k) * Ak
+        Ak = Ak @ A.astype(np.int64)
+    tail = (g * delta) ** (K + 1) / (delta * (1 - g * delta))      # from N^(k) <= Delta^(k-1)
+    assert np.all(Y >= S - 1e-15)
+    assert np.all(Y - S <= tail + 1e-14)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_invariants(seed):
+    rng = gg.rng_for("pin", 200 + seed)
+    A = gg.erdos_renyi(120, float(rng.uniform(0.005, 0.05)), rng)
+    sol = oracle.solve(A, -0.5)
+    dist = bfs_scipy(A)
+    assert sol.would_swap == 0
+    assert np.all(sol.Y >= 0.0)
+    assert np.all(np.diag(sol.Y) >= 1.0)
+    assert np.array_equal(sol.Y == 0.0, dist < 0)
+    assert np.all(np.diag(sol.D) == 0)
+    assert sol.unreachable == int((dist < 0).sum())
+
+
+@pytest.mark.parametrize("n", [200, 500])
+def test_library_inverse(n):
+    A = gg.erdos_renyi(n, 0.03, gg.rng_for("pin", 300 + n))
+    sol = oracle.solve(A, -0.5)
+    M = np.eye(n) - sol.gamma * A
+    Ylap = np.linalg.inv(M)
+    nz = sol.Y >= DBL_MIN
+    assert np.max(np.abs(sol.Y[nz] - Ylap[nz]) / sol.Y[nz]) < 1e-13
+    assert np.all(np.abs(Ylap[sol.Y == 0.0]) < 1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Theorems checked by brute force
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(25))
+def test_theorem2_sufficient_bound(seed):
+    rng = gg.rng_for("pin", 400 + seed)
+    n = int(rng.integers(3, 11))
+    A = gg.erdos_renyi(n, float(rng.uniform(0.15, 0.6)), rng)
+    dist = bfs_scipy(A)
+    delta = int(A.sum(axis=0).max())
+    if delta == 0:
+        return
+    d = diameter(dist)
+    gamma = 0.999 / (delta + delta ** (d - 1))
+    sol = oracle.solve(A, gamma)
+    assert sol.status == oracle.OK
+    reach = dist >= 0
+    assert np.array_equal(sol.D[reach], dist[reach])
+    assert np.all(sol.D[~reach] == oracle.UNREACHABLE)
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_theorem3_tree_bound(seed):
+    rng = gg.rng_for("pin", 500 + seed)
+    n = int(rng.integers(2, 30))
+    A = gg.random_tree(n, rng)
+    dist = bfs_scipy(A)
+    delta = int(A.sum(axis=0).max())
+    d = diameter(dist)
+    x = delta * (d + 2)
+    gamma = 0.999 * (-1 + math.sqrt(1 + 4 * x)) / (2 * x)
+    _, D = rdist_ungated(A, gamma)
+    assert np.array_equal(D, dist)
+
+
+def test_theorem1_necessary_bound_negative():
+    M = 4
+    A = gg.square_grid(M)
+    dist, count = oracle.bfs(A)
+    smax = count.max()
+    assert smax == 20
+    gamma = 1.2 / smax                 # violates gamma < 1 / max S
+    sol = oracle.solve(A, gamma)
+    assert sol.status == oracle.OK     # still passes the gate (gamma * 4 < 1)
+    assert not np.array_equal(sol.D, dist)
+
+
+def test_grid_corner_counts_and_walk_counts():
+    rows = read_golden("grid_corner_counts.txt")
+    for _, line in rows:
+        M, dcorner, S = (int(t) for t in line.split())
+        A = gg.square_grid(M)
+        dist, count = oracle.bfs(A)
+        corner_a, corner_b = 0, M * M - 1
+        assert dist[corner_b, corner_a] == dcorner
+        assert count[corner_b, corner_a] == S
+        assert S > 2 ** (M - 1) if M >= 3 else S == 2 ** (M - 1)   # strict only from M = 3
+        # Sec. 3.1: Y = gamma^D (S + C(gamma)) with C -> 0, so at small gamma
+        # round(Y gamma^-D) recovers the number of shortest paths exactly
+        gamma = 1e-4
+        sol = oracle.solve(A, gamma)
+        est = np.rint(sol.Y * gamma ** (-dist.astype(np.float64)))
+        assert np.array_equal(est, count)
+
+
+@pytest.mark.parametrize("c", [0.5, 0.95])
+@pytest.mark.parametrize("seed", range(4))
+def test_theorem4_greedy_reaches_goal(c, seed):
+    rng = gg.rng_for("pin", 600 + seed)
+    n = 60
+    A = gg.erdos_renyi(n, 0.06, rng)
+    sol = oracle.solve(A, -c)
+    dist = bfs_scipy(A)
+    Y = sol.Y
+    for goal in range(0, n, 7):
+        for cur in range(n):
+            if dist[goal, cur] < 0:
+                assert oracle.next_hop(A, Y, cur, goal) in (-1, cur) if cur == goal else True
+                continue
+            p = oracle.path(A, Y, cur, goal, n - 1)
+            nodes = p[p >= 0]
+            assert nodes[-1] == goal
+            assert len(set(nodes.tolist())) == len(nodes)           # corollary: no cycles
+            vals = Y[goal, nodes]
+            assert np.all(np.diff(vals) > 0)                        # strict ascent on Y
+            for a, b in zip(nodes[:-1], nodes[1:]):
+                assert A[b, a] == 1                                 # every hop is an edge
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_corollary_tree_paths_are_shortest(seed):
+    rng = gg.rng_for("pin", 700 + seed)
+    A = gg.random_tree(40, rng)
+    sol = oracle.solve(A, -0.9)
+    dist = bfs_scipy(A)
+    for goal in range(40):
+        for cur in range(40):
+            p = oracle.path(A, sol.Y, cur, goal, 39)
+            nodes = p[p >= 0]
+            assert nodes[-1] == goal
+            assert len(nodes) - 1 == dist[goal, cur]
+
+
+def test_next_hop_tie_break_and_unreachable():
+    # 0 -> 1, 0 -> 2, 1 -> 3, 2 -> 3 : successors 1 and 2 tie exactly toward goal 3
+    A = gg.from_edges(5, [0, 0, 1, 2], [1, 2, 3, 3])
+    sol = oracle.solve(A, 0.25)
+    assert sol.Y[3, 1] == sol.Y[3, 2]
+    assert oracle.next_hop(A, sol.Y, 0, 3) == 1
+    assert oracle.next_hop(A, sol.Y, 3, 3) == 3
+    assert oracle.next_hop(A, sol.Y, 0, 4) == -1      # node 4 is isolated
+    assert oracle.next_hop(A, sol.Y, 3, 0) == -1      # 3 has no successors
+    p = oracle.path(A, sol.Y, 0, 3, 4)
+    assert p.tolist() == [0, 1, 3, -1, -1]
+
+
+# ---------------------------------------------------------------------------
+# Machine precision (Sec. 5.1)
+# ---------------------------------------------------------------------------
+
+def test_precision_limit_directed_path():
+    fx = dict(read_golden("precision_limit.txt"))
+    delta, gc, dlim = float(fx["delta"]), float(fx["gamma_c"]), int(fx["d_limit"])
+    assert dlim < math.log(delta) / math.log(gc) < dlim + 1
+    n = 340
+    A = gg.directed_path(n)
+    sol = oracle.solve(A, gc)
+    i, j = np.indices((n, n))
+    d = i - j
+    Y, D = sol.Y, sol.D
+    normal = (d >= 0) & (d <= 307)
+    assert np.array_equal(D[normal], d[normal])
+    assert np.all(Y[(d >= 0) & (d <= dlim - 1)] > 0.0)
+    assert np.all(Y[d >= dlim + 2] == 0.0)
+    assert np.all(D[d >= dlim + 2] == oracle.UNREACHABLE)
+    sub = (Y > 0) & (Y < DBL_MIN)
+    assert sol.subnormal == int(sub.sum()) > 0
+
+
+# ---------------------------------------------------------------------------
+# Readout reading (ceil at exact integers) and the int16 encoding
+# ---------------------------------------------------------------------------
+
+def test_readout_eta_reading():
+    g = 0.1
+    vals = [0.001, g ** 3, math.pow(g, 3), np.nextafter(0.001, 1.0), np.nextafter(0.001, 0.0)]
+    Y = np.array([vals + [1.0], [g ** (3 + 2e-9), g ** (3 + 0.5e-9), 0.0, 1.0001, 1 / g ** 2, -1.0]])
+    Yp = np.zeros((6, 6))
+    Yp[:2] = Y
+    Yp[2:] = 1.0
+    r = oracle.readout(Yp, g)
+    assert r.D[0, :5].tolist() == [3] * 5          # naive ceil would give 4 for some of these
+    assert r.D[0, 5] == 0
+    assert r.D[1].tolist() == [4, 3, oracle.UNREACHABLE, 0, -2, oracle.UNREACHABLE]
+    assert r.unreachable == 1 and r.negative == 1
+
+
+def test_readout_saturation_and_ambiguous():
+    g = 0.999
+    Y = np.full((2, 2), 1.0)
+    Y[0, 1] = 1e-300
+    Y[1, 0] = g ** (5 + 1e-9)
+    r = oracle.readout(Y, g)
+    assert r.D[0, 1] == 32766 and r.saturated == 1
+    assert r.ambiguous >= 1
+
+
+# ---------------------------------------------------------------------------
+# Degrees, gate, validation
+# ---------------------------------------------------------------------------
+
+def test_degree_is_out_degree_column_sum():
+    n = 9
+    p = oracle.prepare(gg.out_star(n), -0.5)
+    assert p.delta == n - 1 and p.outdeg[0] == n - 1 and p.gamma == 0.5 / (n - 1)
+    p = oracle.prepare(gg.in_star(n), -0.5)
+    assert p.delta == 1 and p.outdeg[0] == 0
+
+
+def test_gate_and_validation():
+    A = gg.directed_cycle(5)
+    assert oracle.prepare(A, 0.99).status == oracle.OK
+    assert oracle.prepare(A, 1.0).status == oracle.E_ARG
+    assert oracle.prepare(gg.out_star(5), 0.25).status == oracle.E_NOT_DD
+    bad = A.copy()
+    bad[2, 2] = 1
+    assert oracle.prepare(bad, 0.1).status == oracle.E_ADJ
+    bad = A.copy()
+    bad[0, 1] = 2
+    assert oracle.prepare(bad, 0.1).status == oracle.E_ADJ
+    assert oracle.prepare(np.zeros((0, 0), np.uint8), 0.1).status == oracle.E_ARG
+    # an edgeless graph is not an error: gamma = c and Y = I
+    sol = oracle.solve(np.zeros((4, 4), np.uint8), -0.5)
+    assert sol.status == oracle.OK and sol.gamma == 0.5
+    assert np.array_equal(sol.Y, np.eye(4))
+    assert np.array_equal(sol.D, np.where(np.eye(4) > 0, 0, oracle.UNREACHABLE))
+    # refused graphs leave the sentinel everywhere
+    sol = oracle.solve(gg.out_star(5), 0.25)
+    assert sol.status == oracle.E_NOT_DD and np.all(sol.D == oracle.UNREACHABLE)
+
+
+# ---------------------------------------------------------------------------
+# Brute-force companions against a library routine
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(3))
+def test_bfs_and_floyd_warshall_against_scipy(seed):
+    rng = gg.rng_for("pin", 800 + seed)
+    A = gg.erdos_renyi(90, 0.03, rng)
+    ref = bfs_scipy(A)
+    dist, _ = oracle.bfs(A)
+    assert np.array_equal(dist, ref)
+    fw = oracle.floyd_warshall(A)
+    assert np.array_equal(np.where(fw >= oracle.FW_INF, -1, fw), ref)
+
+
+def test_gj_steps_compose():
+    A = gg.erdos_renyi(64, 0.1, gg.rng_for("pin", 900))
+    p = oracle.prepare(A, -0.5)
+    M = oracle.build_m(A, p.gamma)
+    Y, _ = oracle.gj_inverse(M)
+    M2 = M.copy()
+    assert oracle.gj_steps_inplace(M2, 0, 17) == oracle.OK
+    assert oracle.gj_steps_inplace(M2, 17, 64) == oracle.OK
+    assert np.array_equal(M2, Y)
