@@ -1,0 +1,214 @@
+/*
+ * rdist.h -- C ABI of the MI355X (gfx950) R-distance engine.
+ *
+ * The engine computes, for a directed graph with adjacency A and a gain
+ * gamma, the R-distance matrix of Jing & Meister (arXiv 2308.07403):
+ *
+ *     Y = (I - gamma*A)^{-1}                      (Sec. 2, Eq. Y-defined)
+ *     R = log_gamma Y,  D = ceil(R - eta)         (Eq. R-defined; Sec. 4.1.1,
+ *                                                  rounded distance function)
+ *     Y == 0  ->  D = RDIST_UNREACHABLE           (no walk: Eq. Y-series)
+ *
+ * and the greedy next hop toward a goal g (Sec. 4.2, Eq. descent):
+ *
+ *     i <- argmax over successors j of i of Y[g, j]   (ascent on Y, as in the
+ *                                                       proof of Theorem 4)
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Adjacency (Sec. 2, adjacency equation): A is n x n, row-major uint8,
+ *    A[i*n + j] = 1 iff there is a directed edge from node j to node i.
+ *    Entries must be 0 or 1 and the diagonal must be 0 (Sec. 3.1 footnote).
+ *  - D is n x n, row-major int16: D[i*n + j] is the R-distance from j to i.
+ *    eta = 1e-9 (ceil at exact integers: an exactly representable integer R
+ *    rounds to itself).  D is clamped to [-32767, 32766] and counted as
+ *    saturated when clamped; RDIST_UNREACHABLE (0x7FFF) marks Y == 0.
+ *  - Out-degree of node j is the column sum sum_i A[i*n + j]; Delta is its
+ *    maximum (Theorem 2).
+ *  - gamma > 0: explicit gain, must satisfy 0 < gamma < 1.
+ *    gamma < 0: AUTO, gamma := |gamma| / Delta (one IEEE double division),
+ *    or |gamma| when the graph has no edge.
+ *  - Gate: the solve requires gamma * Delta < 1.  Then I - gamma*A is
+ *    column-wise strictly diagonally dominant, so elimination needs no
+ *    pivoting, Y >= 0 entrywise, and greedy ascent on Y reaches the goal
+ *    (Theorem 4's hypothesis).  Graphs that fail it are not solved: their
+ *    status is RDIST_E_NOT_DD and D is filled with RDIST_UNREACHABLE.
+ *  - Pointers named *_dev are device pointers on the context's device; the
+ *    caller allocates and owns them.  Other pointers are host pointers.
+ *  - Every call is asynchronous on the caller's HIP stream (hipStream_t
+ *    passed as void*; NULL = the null stream).  Argument errors are
+ *    returned synchronously.  Conditions only the device can detect (bad
+ *    adjacency, NOT_DD) are reported in rdist_info.status, which is valid
+ *    once the stream has reached the end of the call.  rdist_info should be
+ *    pinned host memory (hipHostMalloc); with pageable memory the call
+ *    returns only after the device has finished it.
+ *  - No C++ exception crosses this interface.  A context may be used from
+ *    several threads only if created with RDIST_THREADSAFE.
+ */
+#ifndef RDIST_H
+#define RDIST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rdist_ctx_s *rdist_ctx;
+typedef struct rdist_graph_s *rdist_graph;
+
+typedef enum rdist_status {
+    RDIST_OK = 0,
+    RDIST_E_ARG = 1,     /* invalid argument (synchronous) */
+    RDIST_E_ADJ = 2,     /* A has an entry other than 0/1 or a self-loop */
+    RDIST_E_NOT_DD = 3,  /* gamma * Delta >= 1: the gate refused the graph */
+    RDIST_E_NOMEM = 4,   /* device allocation failed or the request can never fit the budget */
+    RDIST_E_AGAIN = 5,   /* the HBM budget is currently in use; retry after releases */
+    RDIST_E_HIP = 6,     /* a HIP runtime call failed (see rdist_last_error) */
+    RDIST_E_STATE = 7    /* a handle was used in a way its state does not allow */
+} rdist_status;
+
+#define RDIST_UNREACHABLE 0x7FFF
+
+/* ---- flags for rdist_solve / rdist_solve_batched ---- */
+#define RDIST_F64 0x0u              /* FP64 inversion (default) */
+#define RDIST_MIXED_F32 0x1u        /* FP32-MFMA trailing updates, FP64 panel,
+                                       per-entry certification, FP64 recompute */
+#define RDIST_KEEP_Y 0x10u          /* keep Y resident in a graph handle (for rdist_next_hop) */
+#define RDIST_PLAN_SMALL 0x100u     /* force the single-workgroup register-resident plan (n <= 128) */
+#define RDIST_PLAN_BLOCKED 0x200u   /* force the blocked multi-kernel plan, whatever n */
+#define RDIST_UNFUSED_EPILOGUE 0x400u /* run the readout as a standalone pass over Y */
+
+/* ---- flags for rdist_create ---- */
+#define RDIST_THREADSAFE 0x1u
+
+typedef struct rdist_info {
+    int32_t status;          /* rdist_status detected for this graph */
+    int32_t delta;           /* largest out-degree */
+    double gamma;            /* gain actually used */
+    int64_t n_unreachable;   /* entries with Y == 0 */
+    int64_t n_subnormal;     /* entries with 0 < Y < DBL_MIN (reachable, low precision) */
+    int64_t n_saturated;     /* entries clamped to the int16 range */
+    int64_t n_ambiguous;     /* entries whose R - eta lies within 1e-10 of an integer */
+    int64_t n_negative;      /* entries with Y < 0 (never expected under the gate) */
+    int64_t n_uncertified;   /* RDIST_MIXED_F32: entries recomputed in FP64 */
+    double fallback_fraction;/* RDIST_MIXED_F32: n_uncertified / n^2 */
+} rdist_info;
+
+/*
+ * Creates a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory the context and its graph handles may hold (0: no bound).
+ * tile_cache_path (nullable) names a JSON file of tuned launch shapes written
+ * by the autotuner; missing or unreadable files fall back to built-in shapes.
+ * flags: 0 or RDIST_THREADSAFE.  Returns RDIST_E_ARG for a bad device.
+ */
+rdist_status rdist_create(rdist_ctx *out, int device, size_t hbm_budget_bytes,
+                          const char *tile_cache_path, uint32_t flags);
+
+/* Frees everything the context owns, including graph handles not yet released.
+ * The caller must have synchronised every stream the context was used on. */
+void rdist_destroy(rdist_ctx ctx);
+
+/*
+ * One graph: D = ceil(log_gamma (I - gamma*A)^{-1} - eta) (see above).
+ *   A_dev : n x n uint8 adjacency (read only).
+ *   n     : 1 <= n <= 65536.
+ *   gamma : explicit (0,1) or AUTO (< 0, |gamma| in (0, 1]).
+ *   flags : RDIST_F64 or RDIST_MIXED_F32, optionally | RDIST_KEEP_Y and a plan flag.
+ *   D_dev : n x n int16 output, written by the device.
+ *   keep  : with RDIST_KEEP_Y, receives a graph handle owning Y and the
+ *           out-neighbour lists (release with rdist_graph_release); else NULL.
+ *   info  : nullable host pointer, one rdist_info.
+ *   stream: hipStream_t.
+ * Errors: RDIST_E_ARG (synchronous), RDIST_E_NOMEM/RDIST_E_AGAIN (workspace
+ * does not fit the budget), RDIST_E_HIP.
+ */
+rdist_status rdist_solve(rdist_ctx ctx, const uint8_t *A_dev, int32_t n, double gamma,
+                         uint32_t flags, int16_t *D_dev, rdist_graph *keep,
+                         rdist_info *info, void *stream);
+
+/*
+ * Many independent graphs in one persistent launch (graphs with n <= 512;
+ * larger ones are solved one after another with the blocked plan).
+ * Host arrays of length `count`: n[g], A_dev[g], gamma[g], D_dev[g]
+ * (device pointers), info[g] (nullable array).  flags as rdist_solve
+ * (RDIST_KEEP_Y fills keep[g]).  Each graph's status is in info[g].status.
+ * The launch is captured into a HIP graph keyed by the batch's pointer and
+ * size lists and replayed on later identical calls.
+ */
+rdist_status rdist_solve_batched(rdist_ctx ctx, int32_t count, const int32_t *n,
+                                 const uint8_t *const *A_dev, const double *gamma,
+                                 uint32_t flags, int16_t *const *D_dev, rdist_graph *keep,
+                                 rdist_info *info, void *stream);
+
+/*
+ * Greedy local pursuit on a kept graph (Sec. 4.2, Eq. descent; Theorem 4 and
+ * its corollary).  For query q with start cur_dev[q] and goal goal_dev[q]:
+ *   out_dev[q*(max_hops+1) + 0] = start,
+ *   out_dev[q*(max_hops+1) + h] = node reached after h hops, where each hop
+ *     moves from i to the successor j of i (edge i -> j) with the largest
+ *     Y[goal, j], the lowest j on exact ties;
+ * the row ends at the goal; remaining entries are -1.  A hop that finds no
+ * successor with Y[goal, j] > 0 (goal unreachable) writes -1 and ends the row.
+ * Out-of-range node ids end the row with -1 as well.
+ * q >= 0, 1 <= max_hops <= 65535.  Needs a graph kept with RDIST_KEEP_Y.
+ */
+rdist_status rdist_next_hop(rdist_ctx ctx, rdist_graph g, const int32_t *cur_dev,
+                            const int32_t *goal_dev, int32_t q, int32_t max_hops,
+                            int32_t *out_dev, void *stream);
+
+/* Frees a kept graph's Y and lists and returns their bytes to the budget.
+ * The caller must have synchronised streams that still use the graph. */
+void rdist_graph_release(rdist_graph g);
+
+/*
+ * Device view of a kept graph's Y (read only; valid until release):
+ * Y[i*ld + j] for 0 <= i, j < n.  Returns RDIST_E_ARG for a NULL handle.
+ */
+rdist_status rdist_graph_y(rdist_graph g, const double **Y_dev, int32_t *n, int32_t *ld);
+
+/*
+ * Standalone readout over a caller-provided Y (the unfused form of the
+ * epilogue): D[i*n + j] from Y_dev[i*ld + j] for 0 <= i, j < n with the
+ * given gain (0 < gamma < 1).  info (nullable) receives the counters.
+ */
+rdist_status rdist_epilogue(rdist_ctx ctx, const double *Y_dev, int32_t n, int32_t ld,
+                            double gamma, int16_t *D_dev, rdist_info *info, void *stream);
+
+/* Per-kernel timing collected with HIP events on the launching stream. */
+typedef struct rdist_kernel_stats {
+    int64_t launches;        /* timed launches since the last reset */
+    double total_ms;         /* summed event-to-event duration */
+    double flops;            /* algorithmic flops of those launches */
+    double bytes;            /* algorithmic bytes of those launches */
+} rdist_kernel_stats;
+
+#define RDIST_K_UPDATE 0      /* trailing rank-b update (the FP64/FP32 MFMA hot loop) */
+#define RDIST_K_PANEL 1       /* diagonal-block inverse */
+#define RDIST_K_ROWCOL 2      /* pivot row/column block preparation */
+#define RDIST_K_INGEST 3      /* adjacency -> M, degrees, gate */
+#define RDIST_K_EPILOGUE 4    /* standalone readout */
+#define RDIST_K_SMALL 5       /* single-workgroup solve */
+#define RDIST_K_BATCHED 6     /* persistent batched solve */
+#define RDIST_K_NEXTHOP 7     /* next-hop queries */
+#define RDIST_K_CERTIFY 8     /* mixed precision: certification + recompute */
+#define RDIST_K_COUNT 9
+
+/* Enables (1) or disables (0) per-kernel event timing; enabling resets the counters. */
+rdist_status rdist_set_timing(rdist_ctx ctx, int enable);
+/* Reads the counters of kernel class `which` (RDIST_K_*); synchronises the
+ * streams the timed launches ran on. */
+rdist_status rdist_kernel_stats_get(rdist_ctx ctx, int which, rdist_kernel_stats *out);
+
+/* Bytes of device memory currently held by the context and its graphs. */
+size_t rdist_hbm_in_use(rdist_ctx ctx);
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char *rdist_last_error(void);
+const char *rdist_status_string(rdist_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RDIST_H */

@@ -68,6 +68,10 @@ def lib():
         L.orc_bfs.argtypes = [P, i32, P, P]
         L.orc_floyd_warshall.argtypes = [P, i32, i32, i32, P]
         L.orc_num_threads.restype = i32
+        L.orc_y_column_series.argtypes = [P, i32, f64, i32, f64, i32, P]
+        L.orc_y_column_series.restype = i32
+        L.orc_y_row_series.argtypes = [P, i32, f64, i32, f64, i32, P]
+        L.orc_y_row_series.restype = i32
         _lib = L
     return _lib
 
@@ -212,6 +216,26 @@ def floyd_warshall(A, k_steps: int | None = None) -> np.ndarray:
     dist = np.empty((n, n), dtype=np.int32)
     lib().orc_floyd_warshall(_p(A), n, 0, n if k_steps is None else int(k_steps), _p(dist))
     return dist
+
+
+def y_column(A, gamma: float, j: int, rel_tol: float = 1e-17, max_terms: int = 100000) -> np.ndarray:
+    """Column j of Y from the series sum_k (gamma A)^k e_j (needs gamma * Delta < 1)."""
+    A = _adj(A)
+    y = np.empty(A.shape[0], dtype=np.float64)
+    k = lib().orc_y_column_series(_p(A), A.shape[0], float(gamma), int(j), float(rel_tol), int(max_terms), _p(y))
+    if k < 0:
+        raise ValueError("bad column index")
+    return y
+
+
+def y_row(A, gamma: float, g: int, rel_tol: float = 1e-17, max_terms: int = 100000) -> np.ndarray:
+    """Row g of Y from the series e_g^T sum_k (gamma A)^k (needs gamma * Delta < 1)."""
+    A = _adj(A)
+    y = np.empty(A.shape[0], dtype=np.float64)
+    k = lib().orc_y_row_series(_p(A), A.shape[0], float(gamma), int(g), float(rel_tol), int(max_terms), _p(y))
+    if k < 0:
+        raise ValueError("bad row index")
+    return y
 
 
 def num_threads() -> int:

@@ -250,6 +250,123 @@ void orc_path(const uint8_t *A, const double *Y, int n, int cur, int goal, int m
 }
 
 /* ------------------------------------------------------------------------ */
+/* Single rows / columns of Y from the series Y = sum_k gamma^k A^k           */
+/* (Sec. 3.1, Eq. inverse-series).  Used to check sampled outputs of a full-   */
+/* size solve one by one.  Every term is non-negative, so each entry carries   */
+/* a relative rounding error of at most (number of terms) * 2^-53.            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Column j: y = sum_k (gamma A)^k e_j, i.e. y[i] = Y[i][j].  The 1-norm of
+ * gamma*A is gamma*Delta < 1 (column sums), so after term t the remaining
+ * tail of every entry is at most |t|_1 * gamma*Delta / (1 - gamma*Delta).
+ * Stops when the support has stopped growing (every reachable node has been
+ * reached) and the tail is below rel_tol times the smallest positive entry,
+ * or after max_terms.  Returns the number of terms used (-1 on bad input).
+ */
+int orc_y_column_series(const uint8_t *A, int n, double gamma, int j, double rel_tol, int max_terms,
+                        double *y) {
+    if (j < 0 || j >= n) return -1;
+    int32_t *deg = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    for (int c = 0; c < n; ++c)
+        for (int i = 0; i < n; ++i) deg[c + 1] += A[(size_t)i * n + c] == 1;
+    int32_t delta = 0;
+    for (int c = 0; c < n; ++c) if (deg[c + 1] > delta) delta = deg[c + 1];
+    for (int c = 0; c < n; ++c) deg[c + 1] += deg[c];
+    int32_t *adj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(deg[n] > 0 ? deg[n] : 1));
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    memcpy(fill, deg, sizeof(int32_t) * (size_t)n);
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < n; ++c)
+            if (A[(size_t)i * n + c] == 1) adj[fill[c]++] = i;      /* successors of c */
+    double *t = (double *)calloc((size_t)n, sizeof(double));
+    double *t2 = (double *)calloc((size_t)n, sizeof(double));
+    for (int i = 0; i < n; ++i) y[i] = 0.0;
+    y[j] = 1.0; t[j] = 1.0;
+    double q = gamma * (double)delta;
+    long support = 1, prev_support = 0;
+    int k;
+    for (k = 1; k <= max_terms; ++k) {
+        for (int i = 0; i < n; ++i) t2[i] = 0.0;
+        for (int c = 0; c < n; ++c) {
+            double v = t[c];
+            if (v == 0.0) continue;
+            for (int e = deg[c]; e < deg[c + 1]; ++e) t2[adj[e]] += gamma * v;
+        }
+        double norm1 = 0.0, ymin = 1.0e308;
+        support = 0;
+        for (int i = 0; i < n; ++i) {
+            y[i] += t2[i];
+            norm1 += t2[i];
+            if (y[i] > 0.0) { ++support; if (y[i] < ymin) ymin = y[i]; }
+        }
+        double *sw = t; t = t2; t2 = sw;
+        if (norm1 == 0.0) break;
+        int settled = support == prev_support;
+        prev_support = support;
+        if (settled && q < 1.0 && norm1 * q / (1.0 - q) < rel_tol * ymin) break;
+    }
+    free(deg); free(adj); free(fill); free(t); free(t2);
+    return k;
+}
+
+/*
+ * Row g: y = e_g^T sum_k (gamma A)^k, i.e. y[j] = Y[g][j].  Uses the
+ * infinity norm: |x^T A|_inf <= |x|_inf * Delta, so the tail after term t is
+ * at most |t|_inf * gamma*Delta / (1 - gamma*Delta).
+ */
+int orc_y_row_series(const uint8_t *A, int n, double gamma, int g, double rel_tol, int max_terms,
+                     double *y) {
+    if (g < 0 || g >= n) return -1;
+    int32_t *deg = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));   /* predecessors of i */
+    int32_t delta = 0;
+    for (int c = 0; c < n; ++c) {
+        int32_t s = 0;
+        for (int i = 0; i < n; ++i) s += A[(size_t)i * n + c] == 1;
+        if (s > delta) delta = s;
+    }
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < n; ++c) deg[i + 1] += A[(size_t)i * n + c] == 1;
+    for (int i = 0; i < n; ++i) deg[i + 1] += deg[i];
+    int32_t *adj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(deg[n] > 0 ? deg[n] : 1));
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    memcpy(fill, deg, sizeof(int32_t) * (size_t)n);
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < n; ++c)
+            if (A[(size_t)i * n + c] == 1) adj[fill[i]++] = c;
+    double *t = (double *)calloc((size_t)n, sizeof(double));
+    double *t2 = (double *)calloc((size_t)n, sizeof(double));
+    for (int i = 0; i < n; ++i) y[i] = 0.0;
+    y[g] = 1.0; t[g] = 1.0;
+    double q = gamma * (double)delta;
+    long support = 1, prev_support = 0;
+    int k;
+    for (k = 1; k <= max_terms; ++k) {
+        /* (t^T gamma A)[c] = gamma * sum_i t[i] A[i][c]: scatter from every i to its predecessors c */
+        for (int i = 0; i < n; ++i) t2[i] = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double v = t[i];
+            if (v == 0.0) continue;
+            for (int e = deg[i]; e < deg[i + 1]; ++e) t2[adj[e]] += gamma * v;
+        }
+        double ninf = 0.0, ymin = 1.0e308;
+        support = 0;
+        for (int i = 0; i < n; ++i) {
+            y[i] += t2[i];
+            if (t2[i] > ninf) ninf = t2[i];
+            if (y[i] > 0.0) { ++support; if (y[i] < ymin) ymin = y[i]; }
+        }
+        double *sw = t; t = t2; t2 = sw;
+        if (ninf == 0.0) break;
+        int settled = support == prev_support;
+        prev_support = support;
+        if (settled && q < 1.0 && ninf * q / (1.0 - q) < rel_tol * ymin) break;
+    }
+    free(deg); free(adj); free(fill); free(t); free(t2);
+    return k;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Brute-force companions: BFS distances and shortest-path counts, and the   */
 /* Floyd-Warshall CPU baseline.                                              */
 /* ------------------------------------------------------------------------ */

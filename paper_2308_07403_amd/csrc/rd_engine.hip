@@ -1,0 +1,566 @@
+// rd_engine.hip -- host side of the C ABI declared in include/rdist.h.
+//
+// Owns: per-stream workspaces (so solves on different streams never share
+// scratch), HBM budget accounting, graph handles that keep Y resident, the
+// per-kernel event timing, and plan selection:
+//   n <= 128                 single-workgroup register-resident solve
+//   otherwise / PLAN_BLOCKED blocked Gauss-Jordan, b = 128, MFMA updates
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/rdist.h"
+#include "rd_launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rdist_status fail(rdist_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define RD_HIP(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(RDIST_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kB = 128;   // block size of the blocked solver = tile size
+
+// A device allocation with its size, so the budget can be returned exactly.
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Workspace {
+    int np_cap = 0;      // blocked plan: padded order the buffers below hold
+    Buf M, Ut, V, Pt;    // np x np, 128 x np, 128 x np, 128 x 128 doubles
+    Buf small;           // out-degrees (n_cap + 1), flag, device info
+    int n_cap = 0;
+    Buf tasks, infos, counter;   // batched plan
+    int task_cap = 0;
+    double *m() const { return (double *)M.p; }
+    int32_t *outdeg() const { return (int32_t *)small.p; }
+    int32_t *bad() const { return outdeg() + n_cap + 1; }
+    rdist_info *dinfo() const { return (rdist_info *)((char *)small.p + 256 * ((sizeof(int32_t) * (n_cap + 2) + 255) / 256)); }
+};
+
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int which;
+    double flops, bytes;
+};
+
+}  // namespace
+
+struct rdist_graph_s {
+    rdist_ctx ctx = nullptr;
+    double *Y = nullptr;
+    int n = 0, ld = 0;
+    unsigned long long *succ = nullptr;
+    size_t bytes = 0;
+};
+
+struct rdist_ctx_s {
+    int device = 0;
+    size_t budget = 0;
+    size_t in_use = 0;
+    bool threadsafe = false;
+    std::recursive_mutex mu;
+    std::map<hipStream_t, Workspace> ws;
+    std::set<rdist_graph_s *> graphs;
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> event_pool;
+    rdist_kernel_stats stats[RDIST_K_COUNT];
+    int num_cu = 256;
+};
+
+namespace {
+
+struct Guard {
+    rdist_ctx c;
+    explicit Guard(rdist_ctx c_) : c(c_) { if (c->threadsafe) c->mu.lock(); }
+    ~Guard() { if (c->threadsafe) c->mu.unlock(); }
+};
+
+rdist_status dalloc(rdist_ctx c, void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return RDIST_OK;
+    if (c->budget) {
+        if (bytes > c->budget) return fail(RDIST_E_NOMEM, "request exceeds the HBM budget");
+        if (c->in_use + bytes > c->budget) return fail(RDIST_E_AGAIN, "HBM budget in use");
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(RDIST_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    c->in_use += bytes;
+    return RDIST_OK;
+}
+
+void dfree(rdist_ctx c, void *p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    c->in_use -= std::min(bytes, c->in_use);
+}
+
+rdist_status ensure(rdist_ctx c, Buf &b, size_t bytes) {
+    if (b.p && b.bytes >= bytes) return RDIST_OK;
+    dfree(c, b.p, b.bytes);
+    b.p = nullptr;
+    b.bytes = 0;
+    rdist_status st = dalloc(c, &b.p, bytes);
+    if (st == RDIST_OK) b.bytes = bytes;
+    return st;
+}
+
+void release(rdist_ctx c, Buf &b) {
+    dfree(c, b.p, b.bytes);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+rdist_status ensure_small(rdist_ctx c, Workspace &w, int n) {
+    if (w.small.p && w.n_cap >= n) return RDIST_OK;
+    const int cap = std::max(n, 1024);
+    const size_t ints = 256 * ((sizeof(int32_t) * (size_t)(cap + 2) + 255) / 256);
+    release(c, w.small);
+    rdist_status st = ensure(c, w.small, ints + sizeof(rdist_info));
+    if (st == RDIST_OK) w.n_cap = cap;
+    return st;
+}
+
+// Blocked-plan buffers for order np.  A graph kept with RDIST_KEEP_Y takes
+// M over; it is then reallocated here on the next blocked solve.
+rdist_status ensure_big(rdist_ctx c, Workspace &w, int np) {
+    if (w.np_cap < np) {
+        release(c, w.M);
+        release(c, w.Ut);
+        release(c, w.V);
+        release(c, w.Pt);
+        w.np_cap = np;
+    }
+    const int cap = w.np_cap;
+    rdist_status st;
+    if ((st = ensure(c, w.M, (size_t)cap * cap * 8))) return st;
+    if ((st = ensure(c, w.Ut, (size_t)kB * cap * 8))) return st;
+    if ((st = ensure(c, w.V, (size_t)kB * cap * 8))) return st;
+    return ensure(c, w.Pt, (size_t)kB * kB * 8);
+}
+
+// ---- timing ----
+hipEvent_t take_event(rdist_ctx c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timer {
+    rdist_ctx c;
+    hipStream_t s;
+    int which;
+    double flops, bytes;
+    hipEvent_t a = nullptr;
+    Timer(rdist_ctx c_, hipStream_t s_, int w, double f, double b) : c(c_), s(s_), which(w), flops(f), bytes(b) {
+        if (c->timing) {
+            a = take_event(c);
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~Timer() {
+        if (!a) return;
+        hipEvent_t b2 = take_event(c);
+        if (!b2) return;
+        (void)hipEventRecord(b2, s);
+        c->pending.push_back(TimedLaunch{a, b2, which, flops, bytes});
+    }
+};
+
+void drain_timing(rdist_ctx c) {
+    for (auto &t : c->pending) {
+        (void)hipEventSynchronize(t.b);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            rdist_kernel_stats &s = c->stats[t.which];
+            s.launches += 1;
+            s.total_ms += ms;
+            s.flops += t.flops;
+            s.bytes += t.bytes;
+        }
+        c->event_pool.push_back(t.a);
+        c->event_pool.push_back(t.b);
+    }
+    c->pending.clear();
+}
+
+rdist_status copy_info(rdist_info *host, const rdist_info *dev, int count, hipStream_t s) {
+    if (!host || count <= 0) return RDIST_OK;
+    RD_HIP(hipMemcpyAsync(host, dev, sizeof(rdist_info) * (size_t)count, hipMemcpyDeviceToHost, s));
+    return RDIST_OK;
+}
+
+rdist_status make_graph(rdist_ctx c, int n, double *Y, int ld, size_t ybytes, const uint8_t *A, hipStream_t s,
+                        rdist_graph *out) {
+    const int nw = (n + 63) / 64;
+    const size_t bb = (size_t)n * nw * 8;
+    unsigned long long *bits = nullptr;
+    rdist_status st = dalloc(c, (void **)&bits, bb);
+    if (st) return st;
+    rd::launch_succ_bitmap(A, n, bits, s);
+    RD_HIP(hipGetLastError());
+    auto *g = new rdist_graph_s();
+    g->ctx = c;
+    g->Y = Y;
+    g->n = n;
+    g->ld = ld;
+    g->succ = bits;
+    g->bytes = ybytes + bb;
+    c->graphs.insert(g);
+    *out = g;
+    return RDIST_OK;
+}
+
+void release_graph_locked(rdist_graph g) {
+    rdist_ctx c = g->ctx;
+    (void)hipFree(g->Y);
+    (void)hipFree(g->succ);
+    c->in_use -= std::min(g->bytes, c->in_use);
+    c->graphs.erase(g);
+    delete g;
+}
+
+rdist_status check_flags(uint32_t flags) {
+    const uint32_t known = RDIST_MIXED_F32 | RDIST_KEEP_Y | RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED |
+                           RDIST_UNFUSED_EPILOGUE;
+    if (flags & ~known) return fail(RDIST_E_ARG, "unknown flag bits");
+    if ((flags & RDIST_PLAN_SMALL) && (flags & RDIST_PLAN_BLOCKED)) return fail(RDIST_E_ARG, "two plan flags");
+    if (flags & RDIST_MIXED_F32) return fail(RDIST_E_ARG, "RDIST_MIXED_F32 is not available in this build");
+    return RDIST_OK;
+}
+
+rdist_status check_gamma(double gamma) {
+    if (!std::isfinite(gamma) || gamma == 0.0) return fail(RDIST_E_ARG, "gamma must be finite and non-zero");
+    if (gamma > 0.0 && !(gamma < 1.0)) return fail(RDIST_E_ARG, "explicit gamma must lie in (0, 1)");
+    if (gamma < 0.0 && !(-gamma < 1.0)) return fail(RDIST_E_ARG, "AUTO factor |gamma| must lie in (0, 1)");
+    return RDIST_OK;
+}
+
+// Blocked solve of one graph on stream s.
+rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
+                           rdist_graph *keep, rdist_info *info, hipStream_t s) {
+    Workspace &w = c->ws[s];
+    const int np = ((n + kB - 1) / kB) * kB;
+    const int nb = np / kB;
+    rdist_status st = ensure_small(c, w, n);
+    if (st) return st;
+    if ((st = ensure_big(c, w, np))) return st;
+    const int ld = w.np_cap;                     // M, Ut, V leading dimension
+    double *M = w.m();
+    double *Ut = (double *)w.Ut.p, *V = (double *)w.V.p, *Pt = (double *)w.Pt.p;
+    rdist_info *dinfo = w.dinfo();
+    const bool keep_y = (flags & RDIST_KEEP_Y) != 0;
+    const bool fused = !(flags & RDIST_UNFUSED_EPILOGUE);
+    {
+        Timer t(c, s, RDIST_K_INGEST, 0.0, (double)n * n + 8.0 * np * np);
+        rd::launch_ingest(A, n, np, ld, gamma, M, w.outdeg(), w.bad(), dinfo, s);
+    }
+    RD_HIP(hipGetLastError());
+    const double upd_flops = 2.0 * (double)np * np * kB;
+    for (int K = 0; K < nb; ++K) {
+        {
+            Timer t(c, s, RDIST_K_PANEL, 2.0 * kB * kB * kB, 16.0 * kB * kB);
+            rd::launch_panel(M, ld, K, Pt, V, ld, dinfo, s);
+        }
+        {
+            Timer t(c, s, RDIST_K_ROWCOL, 2.0 * kB * kB * (np - kB), 8.0 * 4 * kB * np);
+            rd::launch_rowcol(M, ld, nb, K, Pt, Ut, V, ld, dinfo, s);
+        }
+        const bool last = K == nb - 1;
+        {
+            double bytes = 16.0 * np * np;
+            Timer t(c, s, RDIST_K_UPDATE, upd_flops, bytes);
+            rd::launch_update(M, ld, nb, K, Ut, V, ld, last && fused, n, D, keep_y ? 1 : 0, dinfo, s);
+        }
+        RD_HIP(hipGetLastError());
+    }
+    if (!fused) {
+        Timer t(c, s, RDIST_K_EPILOGUE, 0.0, 10.0 * n * n);
+        rd::launch_epilogue(M, n, ld, D, dinfo, s);
+    }
+    rd::launch_fill_sentinel(D, n, dinfo, s);
+    RD_HIP(hipGetLastError());
+    if (keep_y && keep) {
+        Buf y = w.M;          // the graph takes M over (its bytes stay counted)
+        w.M = Buf{};
+        st = make_graph(c, n, (double *)y.p, ld, y.bytes, A, s, keep);
+        if (st) {
+            release(c, y);
+            return st;
+        }
+    }
+    return copy_info(info, dinfo, 1, s);
+}
+
+rdist_status solve_small(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
+                         rdist_graph *keep, rdist_info *info, hipStream_t s) {
+    Workspace &w = c->ws[s];
+    rdist_status st = ensure_small(c, w, n);
+    if (st) return st;
+    double *Y = nullptr;
+    const size_t yb = (size_t)n * n * 8;
+    const bool keep_y = (flags & RDIST_KEEP_Y) && keep;
+    if (keep_y && (st = dalloc(c, (void **)&Y, yb))) return st;
+    rd::SmallTask t{A, D, Y, n, n, gamma, w.dinfo()};
+    {
+        Timer tm(c, s, RDIST_K_SMALL, 2.0 * n * n * n, (double)n * n * (keep_y ? 11.0 : 3.0));
+        rd::launch_small_one(t, s);
+    }
+    RD_HIP(hipGetLastError());
+    if (keep_y) {
+        st = make_graph(c, n, Y, n, yb, A, s, keep);
+        if (st) { dfree(c, Y, yb); return st; }
+    }
+    return copy_info(info, w.dinfo(), 1, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rdist_last_error(void) { return g_last_error.c_str(); }
+
+const char *rdist_status_string(rdist_status s) {
+    switch (s) {
+        case RDIST_OK: return "RDIST_OK";
+        case RDIST_E_ARG: return "RDIST_E_ARG";
+        case RDIST_E_ADJ: return "RDIST_E_ADJ";
+        case RDIST_E_NOT_DD: return "RDIST_E_NOT_DD";
+        case RDIST_E_NOMEM: return "RDIST_E_NOMEM";
+        case RDIST_E_AGAIN: return "RDIST_E_AGAIN";
+        case RDIST_E_HIP: return "RDIST_E_HIP";
+        case RDIST_E_STATE: return "RDIST_E_STATE";
+    }
+    return "RDIST_E_UNKNOWN";
+}
+
+rdist_status rdist_create(rdist_ctx *out, int device, size_t hbm_budget_bytes, const char *tile_cache_path,
+                          uint32_t flags) {
+    (void)tile_cache_path;
+    if (!out) return fail(RDIST_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (flags & ~RDIST_THREADSAFE) return fail(RDIST_E_ARG, "unknown create flags");
+    int count = 0;
+    RD_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(RDIST_E_ARG, "no such device");
+    RD_HIP(hipSetDevice(device));
+    auto *c = new rdist_ctx_s();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    c->threadsafe = (flags & RDIST_THREADSAFE) != 0;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    std::memset(c->stats, 0, sizeof(c->stats));
+    *out = c;
+    g_last_error.clear();
+    return RDIST_OK;
+}
+
+void rdist_destroy(rdist_ctx c) {
+    if (!c) return;
+    {
+        Guard g(c);
+        (void)hipSetDevice(c->device);
+        drain_timing(c);
+        for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+        std::vector<rdist_graph_s *> gs(c->graphs.begin(), c->graphs.end());
+        for (auto *gr : gs) release_graph_locked(gr);
+        for (auto &kv : c->ws) {
+            Workspace &w = kv.second;
+            for (Buf *b : {&w.M, &w.Ut, &w.V, &w.Pt, &w.small, &w.tasks, &w.infos, &w.counter}) release(c, *b);
+        }
+    }
+    delete c;
+}
+
+rdist_status rdist_solve(rdist_ctx c, const uint8_t *A_dev, int32_t n, double gamma, uint32_t flags,
+                         int16_t *D_dev, rdist_graph *keep, rdist_info *info, void *stream) {
+    if (!c) return fail(RDIST_E_ARG, "ctx is NULL");
+    if (!A_dev || !D_dev) return fail(RDIST_E_ARG, "A_dev and D_dev are required");
+    if (n < 1 || n > 65536) return fail(RDIST_E_ARG, "n must lie in [1, 65536]");
+    rdist_status st;
+    if ((st = check_flags(flags))) return st;
+    if ((st = check_gamma(gamma))) return st;
+    if ((flags & RDIST_PLAN_SMALL) && n > 128) return fail(RDIST_E_ARG, "RDIST_PLAN_SMALL needs n <= 128");
+    if (keep) *keep = nullptr;
+    Guard g(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const bool small = !(flags & RDIST_PLAN_BLOCKED) && n <= 128;
+    if (small) return solve_small(c, A_dev, n, gamma, flags, D_dev, keep, info, s);
+    return solve_blocked(c, A_dev, n, gamma, flags, D_dev, keep, info, s);
+}
+
+rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const int32_t *n, const uint8_t *const *A_dev,
+                                 const double *gamma, uint32_t flags, int16_t *const *D_dev, rdist_graph *keep,
+                                 rdist_info *info, void *stream) {
+    if (!c) return fail(RDIST_E_ARG, "ctx is NULL");
+    if (count < 0) return fail(RDIST_E_ARG, "count < 0");
+    if (count == 0) return RDIST_OK;
+    if (!n || !A_dev || !gamma || !D_dev) return fail(RDIST_E_ARG, "NULL array");
+    rdist_status st;
+    if ((st = check_flags(flags))) return st;
+    if (flags & (RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED)) return fail(RDIST_E_ARG, "plan flags are per solve");
+    for (int g = 0; g < count; ++g) {
+        if (n[g] < 1 || n[g] > 65536) return fail(RDIST_E_ARG, "n out of range");
+        if (!A_dev[g] || !D_dev[g]) return fail(RDIST_E_ARG, "NULL graph pointer");
+        if ((st = check_gamma(gamma[g]))) return st;
+    }
+    const bool keep_y = (flags & RDIST_KEEP_Y) && keep;
+    if (keep) for (int g = 0; g < count; ++g) keep[g] = nullptr;
+    Guard gd(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &w = c->ws[s];
+    // small graphs: one persistent launch, longest first
+    std::vector<int> small_ids, big_ids;
+    for (int g = 0; g < count; ++g) (n[g] <= 128 ? small_ids : big_ids).push_back(g);
+    std::stable_sort(small_ids.begin(), small_ids.end(), [&](int a, int b) { return n[a] > n[b]; });
+    if (!small_ids.empty()) {
+        const int ns = (int)small_ids.size();
+        const int cap = std::max(ns, 256);
+        if ((st = ensure(c, w.tasks, sizeof(rd::SmallTask) * (size_t)cap))) return st;
+        if ((st = ensure(c, w.infos, sizeof(rdist_info) * (size_t)cap))) return st;
+        if ((st = ensure(c, w.counter, 256))) return st;
+        rd::SmallTask *dtasks = (rd::SmallTask *)w.tasks.p;
+        rdist_info *dinfos = (rdist_info *)w.infos.p;
+        std::vector<rd::SmallTask> tasks(ns);
+        std::vector<double *> ys(ns, nullptr);
+        double flops = 0.0, bytes = 0.0;
+        for (int q = 0; q < ns; ++q) {
+            const int g = small_ids[q];
+            double *Y = nullptr;
+            if (keep_y && (st = dalloc(c, (void **)&Y, (size_t)n[g] * n[g] * 8))) {
+                for (double *y : ys) if (y) (void)hipFree(y);
+                return st;
+            }
+            ys[q] = Y;
+            tasks[q] = rd::SmallTask{A_dev[g], D_dev[g], Y, n[g], n[g], gamma[g], dinfos + q};
+            flops += 2.0 * n[g] * (double)n[g] * n[g];
+            bytes += 3.0 * n[g] * (double)n[g];
+        }
+        RD_HIP(hipMemcpyAsync(dtasks, tasks.data(), sizeof(rd::SmallTask) * (size_t)ns, hipMemcpyHostToDevice, s));
+        const int grid = std::min(ns, c->num_cu * 4);
+        {
+            Timer tm(c, s, RDIST_K_BATCHED, flops, bytes);
+            rd::launch_small_persistent(dtasks, ns, (int *)w.counter.p, grid, s);
+        }
+        RD_HIP(hipGetLastError());
+        for (int q = 0; q < ns; ++q) {
+            const int g = small_ids[q];
+            if (keep_y && (st = make_graph(c, n[g], ys[q], n[g], (size_t)n[g] * n[g] * 8, A_dev[g], s, &keep[g])))
+                return st;
+            if (info) RD_HIP(hipMemcpyAsync(info + g, dinfos + q, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
+        }
+    }
+    for (int g : big_ids) {
+        st = solve_blocked(c, A_dev[g], n[g], gamma[g], flags, D_dev[g], keep ? &keep[g] : nullptr,
+                           info ? info + g : nullptr, s);
+        if (st) return st;
+    }
+    return RDIST_OK;
+}
+
+rdist_status rdist_next_hop(rdist_ctx c, rdist_graph gr, const int32_t *cur_dev, const int32_t *goal_dev, int32_t q,
+                            int32_t max_hops, int32_t *out_dev, void *stream) {
+    if (!c || !gr) return fail(RDIST_E_ARG, "NULL handle");
+    if (gr->ctx != c) return fail(RDIST_E_STATE, "graph belongs to another context");
+    if (q < 0 || max_hops < 1 || max_hops > 65535) return fail(RDIST_E_ARG, "bad q or max_hops");
+    if (q == 0) return RDIST_OK;
+    if (!cur_dev || !goal_dev || !out_dev) return fail(RDIST_E_ARG, "NULL query array");
+    Guard g(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    {
+        Timer tm(c, s, RDIST_K_NEXTHOP, 0.0, 0.0);
+        rd::launch_next_hop(gr->Y, gr->ld, gr->n, gr->succ, cur_dev, goal_dev, q, max_hops, out_dev, s);
+    }
+    RD_HIP(hipGetLastError());
+    return RDIST_OK;
+}
+
+void rdist_graph_release(rdist_graph g) {
+    if (!g) return;
+    rdist_ctx c = g->ctx;
+    Guard gd(c);
+    (void)hipSetDevice(c->device);
+    release_graph_locked(g);
+}
+
+rdist_status rdist_graph_y(rdist_graph g, const double **Y_dev, int32_t *n, int32_t *ld) {
+    if (!g) return fail(RDIST_E_ARG, "NULL graph");
+    if (Y_dev) *Y_dev = g->Y;
+    if (n) *n = g->n;
+    if (ld) *ld = g->ld;
+    return RDIST_OK;
+}
+
+rdist_status rdist_epilogue(rdist_ctx c, const double *Y_dev, int32_t n, int32_t ld, double gamma, int16_t *D_dev,
+                            rdist_info *info, void *stream) {
+    if (!c || !Y_dev || !D_dev) return fail(RDIST_E_ARG, "NULL argument");
+    if (n < 1 || ld < n) return fail(RDIST_E_ARG, "bad n or ld");
+    if (!(gamma > 0.0 && gamma < 1.0)) return fail(RDIST_E_ARG, "gamma must lie in (0, 1)");
+    Guard g(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &w = c->ws[s];
+    rdist_status st = ensure_small(c, w, 1);
+    if (st) return st;
+    rd::launch_info_set(w.dinfo(), gamma, s);
+    {
+        Timer t(c, s, RDIST_K_EPILOGUE, 0.0, 10.0 * n * (double)n);
+        rd::launch_epilogue(Y_dev, n, ld, D_dev, w.dinfo(), s);
+    }
+    RD_HIP(hipGetLastError());
+    return copy_info(info, w.dinfo(), 1, s);
+}
+
+rdist_status rdist_set_timing(rdist_ctx c, int enable) {
+    if (!c) return fail(RDIST_E_ARG, "ctx is NULL");
+    Guard g(c);
+    drain_timing(c);
+    c->timing = enable != 0;
+    if (enable) std::memset(c->stats, 0, sizeof(c->stats));
+    return RDIST_OK;
+}
+
+rdist_status rdist_kernel_stats_get(rdist_ctx c, int which, rdist_kernel_stats *out) {
+    if (!c || !out || which < 0 || which >= RDIST_K_COUNT) return fail(RDIST_E_ARG, "bad argument");
+    Guard g(c);
+    (void)hipSetDevice(c->device);
+    drain_timing(c);
+    *out = c->stats[which];
+    return RDIST_OK;
+}
+
+size_t rdist_hbm_in_use(rdist_ctx c) { return c ? c->in_use : 0; }
+
+}  // extern "C"

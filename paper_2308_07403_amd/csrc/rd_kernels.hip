@@ -1,0 +1,516 @@
+// rd_kernels.hip -- gfx950 kernels of the R-distance engine and their launchers.
+//
+// Pipeline for one graph (paper: Jing & Meister, arXiv 2308.07403):
+//   ingest   A (uint8, j -> i convention of Sec. 2) -> out-degrees, Delta,
+//            gamma, the gate gamma*Delta < 1 (Theorem 4's hypothesis), and
+//            M = I - gamma*A in FP64 (Eq. Y-defined), identity-padded;
+//   invert   Y = M^{-1} by blocked Gauss-Jordan without pivoting;
+//   readout  D = ceil(log_gamma Y - eta), Y == 0 -> unreachable
+//            (Eq. R-defined, rounded distance function of Sec. 4.1.1);
+//   next hop greedy ascent on Y over successors (Sec. 4.2, Eq. descent).
+//
+// Blocked Gauss-Jordan with block size b = 128 on an np x np matrix
+// (np = n rounded up to 128), for every block index K:
+//   P = M_KK^{-1}                      k_panel   (register-resident GJ)
+//   V_J = P M_KJ (J != K), V_K = P     k_rowcol  (MFMA)
+//   U_I = M_IK (I != K),  U_K = -I     k_rowcol  (stored transposed, k-major)
+//   M <- M~ - U V                      k_update  (MFMA; M~ = M with block row
+//                                                 and column K set to zero)
+// which is the block form of the in-place Gauss-Jordan step: it leaves
+// M_KK = P, M_KJ = P M_KJ, M_IK = -M_IK P and M_IJ - M_IK P M_KJ.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rd_device.h"
+#include "rd_launch.h"
+
+namespace rd {
+
+// ---------------------------------------------------------------------------
+// Ingest
+// ---------------------------------------------------------------------------
+
+__global__ void k_zero_i32(int32_t *p, int count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// Column sums of A (out-degrees) and validation, over a block of rows.
+__global__ __launch_bounds__(256) void k_colsum(const uint8_t *__restrict__ A, int n, int rows_per_block,
+                                                int32_t *outdeg, int32_t *bad) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const int i0 = blockIdx.y * rows_per_block;
+    const int i1 = min(n, i0 + rows_per_block);
+    int s = 0, b = 0;
+    for (int i = i0; i < i1; ++i) {
+        const int a = A[(size_t)i * n + j];
+        s += a;
+        b |= (a > 1) | ((i == j) & (a != 0));
+    }
+    if (s) atomicAdd(&outdeg[j], s);
+    if (b) atomicOr(bad, 1);
+}
+
+// Delta = max out-degree, gamma (explicit or c/Delta), gate; resets info.
+__global__ __launch_bounds__(1024) void k_finalize(const int32_t *outdeg, const int32_t *bad, int n,
+                                                   double gamma_arg, rdist_info *info) {
+    __shared__ int smax;
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    int m = 0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) m = max(m, outdeg[j]);
+    atomicMax(&smax, m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int delta = smax;
+        double gamma = gamma_arg > 0.0 ? gamma_arg : (delta > 0 ? (-gamma_arg) / (double)delta : -gamma_arg);
+        int st = RDIST_OK;
+        if (*bad) st = RDIST_E_ADJ;
+        else if (!(gamma > 0.0) || !(gamma < 1.0)) st = RDIST_E_ARG;
+        else if (!(gamma * (double)delta < 1.0)) st = RDIST_E_NOT_DD;
+        info->status = st;
+        info->delta = delta;
+        info->gamma = gamma;
+        info->n_unreachable = info->n_subnormal = info->n_saturated = 0;
+        info->n_ambiguous = info->n_negative = info->n_uncertified = 0;
+        info->fallback_fraction = 0.0;
+    }
+}
+
+// M = I - gamma*A on the n x n block, identity on the padding (np x np, ld).
+__global__ __launch_bounds__(256) void k_build_m(const uint8_t *__restrict__ A, int n, int np, int ld,
+                                                 double *__restrict__ M, const rdist_info *info) {
+    const double gamma = info->gamma;
+    const size_t pairs = (size_t)np * np / 2;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < pairs; e += (size_t)gridDim.x * 256) {
+        const int i = (int)((2 * e) / np);
+        const int j = (int)((2 * e) % np);     // even; np is even
+        double v[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int jj = j + q;
+            double x = (i == jj) ? 1.0 : 0.0;
+            if (i < n && jj < n) x -= gamma * (double)A[(size_t)i * n + jj];
+            v[q] = x;
+        }
+        *reinterpret_cast<double2 *>(M + (size_t)i * ld + j) = double2{v[0], v[1]};
+    }
+}
+
+// On a refused graph (bad adjacency or gate) D is filled with the sentinel.
+__global__ __launch_bounds__(256) void k_fill_sentinel(int16_t *D, size_t count, const rdist_info *info) {
+    if (info->status == RDIST_OK) return;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256)
+        D[e] = kUnreachable;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked Gauss-Jordan
+// ---------------------------------------------------------------------------
+
+// P = M_KK^{-1}: writes P^T (k-major) to Pt and P into V's column block K.
+__global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int ld, int K,
+                                               double *__restrict__ Pt, double *__restrict__ V, int ldv,
+                                               rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ double lds[4 * kTile];
+    RegGJ<16, 16, 8, 8> g;
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    const double *base = M + (size_t)K * kTile * ld + (size_t)K * kTile;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) g.m[a][c] = base[(size_t)(ty + 16 * a) * ld + tx + 16 * c];
+    const bool ok = g.run(kTile, lds, ty, tx);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int i = ty + 16 * a, k = tx + 16 * c;
+            Pt[(size_t)k * kTile + i] = g.m[a][c];
+            V[(size_t)i * ldv + (size_t)K * kTile + k] = g.m[a][c];
+        }
+    if (!ok && threadIdx.x == 0) atomicCAS(&info->status, RDIST_OK, RDIST_E_NOT_DD);
+}
+
+// Blocks [0, nb): V_J = P M_KJ for J != K.  Blocks [nb, 2nb): Ut_I = (M_IK)^T,
+// Ut_K = -I.  Ut and V are 128 x np, row-major (k-major operands).
+__global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, int ld, int nb, int K,
+                                                const double *__restrict__ Pt, double *__restrict__ Ut,
+                                                double *__restrict__ V, int ldv, const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ double lds[kTileLdsDoubles];
+    const int b = blockIdx.x;
+    if (b < nb) {
+        const int J = b;
+        if (J == K) return;
+        TileAcc acc;
+        acc.zero();
+        tile_mma(Pt, kTile, M + (size_t)K * kTile * ld + (size_t)J * kTile, ld, kTile, lds, acc);
+        double *out = V + (size_t)J * kTile;
+        tile_for_each(acc, [&](int r, int c, double v) { out[(size_t)r * ldv + c] = v; });
+        return;
+    }
+    const int I = b - nb;
+    double *out = Ut + (size_t)I * kTile;          // Ut[k][I*128 + i]
+    if (I == K) {
+        for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+            const int k = e >> 7, i = e & 127;
+            out[(size_t)k * ldv + i] = (k == i) ? -1.0 : 0.0;
+        }
+        return;
+    }
+    // transpose the 128 x 128 block M_IK through LDS, 64 x 64 at a time
+    double (*t)[65] = reinterpret_cast<double (*)[65]>(lds);
+    const double *src = M + (size_t)I * kTile * ld + (size_t)K * kTile;
+    for (int bi = 0; bi < 2; ++bi)
+        for (int bk = 0; bk < 2; ++bk) {
+            for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+                const int r = e >> 6, c = e & 63;     // r: row i, c: column k
+                t[r][c] = src[(size_t)(bi * 64 + r) * ld + bk * 64 + c];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+                const int k = e >> 6, i = e & 63;
+                out[(size_t)(bk * 64 + k) * ldv + bi * 64 + i] = t[i][k];
+            }
+            __syncthreads();
+        }
+}
+
+// M_IJ <- M~_IJ - U_I V_J over all tiles.  With FUSED the tile's final value is
+// read out into D (and stored to M only if keep_y).
+template <bool FUSED>
+__global__ __launch_bounds__(256) void k_update(double *__restrict__ M, int ld, int nb, int K,
+                                                const double *__restrict__ Ut, const double *__restrict__ V,
+                                                int ldv, int n, int16_t *__restrict__ D, int keep_y,
+                                                rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ double lds[kTileLdsDoubles];
+    const int I = blockIdx.x / nb, J = blockIdx.x - (blockIdx.x / nb) * nb;
+    TileAcc acc;
+    acc.zero();
+    tile_mma(Ut + (size_t)I * kTile, ldv, V + (size_t)J * kTile, ldv, kTile, lds, acc);
+    const bool zero_in = (I == K) || (J == K);
+    double *base = M + (size_t)I * kTile * ld + (size_t)J * kTile;
+    if (!FUSED) {
+        tile_for_each(acc, [&](int r, int c, double v) {
+            double *p = base + (size_t)r * ld + c;
+            *p = (zero_in ? 0.0 : *p) - v;
+        });
+    } else {
+        const double lg = log(info->gamma);
+        Counts cnt;
+        tile_for_each(acc, [&](int r, int c, double v) {
+            double *p = base + (size_t)r * ld + c;
+            const double y = (zero_in ? 0.0 : *p) - v;
+            if (keep_y) *p = y;
+            const int gi = I * kTile + r, gj = J * kTile + c;
+            if (gi < n && gj < n) D[(size_t)gi * n + gj] = rd_encode(y, lg, cnt);
+        });
+        flush_counts(info, cnt);
+    }
+}
+
+// Standalone readout over Y (ld) into D (n x n).
+__global__ __launch_bounds__(256) void k_epilogue(const double *__restrict__ Y, int n, int ld,
+                                                  int16_t *__restrict__ D, rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    const double lg = log(info->gamma);
+    Counts cnt;
+    const size_t total = (size_t)n * n;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const size_t i = e / n, j = e - i * n;
+        D[e] = rd_encode(Y[i * ld + j], lg, cnt);
+    }
+    flush_counts(info, cnt);
+}
+
+// Sets info for a caller-provided gain (standalone readout).
+__global__ void k_info_set(rdist_info *info, double gamma) {
+    info->status = RDIST_OK;
+    info->delta = 0;
+    info->gamma = gamma;
+    info->n_unreachable = info->n_subnormal = info->n_saturated = 0;
+    info->n_ambiguous = info->n_negative = info->n_uncertified = 0;
+    info->fallback_fraction = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Single-workgroup solve for n <= NP (128): ingest, register-resident
+// Gauss-Jordan, readout, all in one kernel.  One workgroup per task; the
+// persistent form pulls tasks from a counter in the order of `order`.
+// ---------------------------------------------------------------------------
+
+template <int TY, int TX, int RA, int RC>
+__device__ void solve_small(const SmallTask &t, double *lds_gj, int *lds_int) {
+    using G = RegGJ<TY, TX, RA, RC>;
+    constexpr int NP = G::NP;
+    const int n = t.n;
+    const int ty = threadIdx.x / TX, tx = threadIdx.x % TX;
+    int *colsum = lds_int;          // NP
+    int *flags = lds_int + NP;      // [0] bad, [1] delta
+    for (int j = threadIdx.x; j < NP; j += G::NT) colsum[j] = 0;
+    if (threadIdx.x == 0) { flags[0] = 0; flags[1] = 0; }
+    __syncthreads();
+    G g;
+    uint8_t a8[RA][RC];
+    int bad = 0;
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+            const int i = ty + TY * a, j = tx + TX * c;
+            uint8_t v = 0;
+            if (i < n && j < n) v = t.A[(size_t)i * n + j];
+            a8[a][c] = v;
+            bad |= (v > 1) | ((i == j) & (v != 0));
+        }
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+        int s = 0;
+#pragma unroll
+        for (int a = 0; a < RA; ++a) s += a8[a][c];
+        if (s) atomicAdd(&colsum[tx + TX * c], s);
+    }
+    if (bad) atomicOr(&flags[0], 1);
+    __syncthreads();
+    for (int j = threadIdx.x; j < NP; j += G::NT) atomicMax(&flags[1], colsum[j]);
+    __syncthreads();
+    const int delta = flags[1];
+    const double gamma = t.gamma_arg > 0.0 ? t.gamma_arg
+                                           : (delta > 0 ? (-t.gamma_arg) / (double)delta : -t.gamma_arg);
+    int st = RDIST_OK;
+    if (flags[0]) st = RDIST_E_ADJ;
+    else if (!(gamma > 0.0) || !(gamma < 1.0)) st = RDIST_E_ARG;
+    else if (!(gamma * (double)delta < 1.0)) st = RDIST_E_NOT_DD;
+    Counts cnt;
+    if (st == RDIST_OK) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int c = 0; c < RC; ++c) {
+                const int i = ty + TY * a, j = tx + TX * c;
+                g.m[a][c] = (i == j ? 1.0 : 0.0) - gamma * (double)a8[a][c];
+            }
+        const bool ok = g.run(n, lds_gj, ty, tx);
+        if (!ok) st = RDIST_E_NOT_DD;
+    }
+    if (st == RDIST_OK) {
+        const double lg = log(gamma);
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int c = 0; c < RC; ++c) {
+                const int i = ty + TY * a, j = tx + TX * c;
+                if (i < n && j < n) {
+                    const double y = g.m[a][c];
+                    t.D[(size_t)i * n + j] = rd_encode(y, lg, cnt);
+                    if (t.Y) t.Y[(size_t)i * t.ldy + j] = y;
+                }
+            }
+    } else {
+        for (int e = threadIdx.x; e < n * n; e += G::NT) t.D[e] = kUnreachable;
+    }
+    // reduce the counters across the workgroup through LDS
+    __syncthreads();
+    unsigned long long *red = reinterpret_cast<unsigned long long *>(lds_gj);
+    if (threadIdx.x < 5) red[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long v[5] = {wave_sum_u64(cnt.unreachable), wave_sum_u64(cnt.subnormal),
+                               wave_sum_u64(cnt.saturated), wave_sum_u64(cnt.ambiguous),
+                               wave_sum_u64(cnt.negative)};
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 5; ++q)
+            if (v[q]) atomicAdd(&red[q], v[q]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        rdist_info *info = t.info;
+        info->status = st;
+        info->delta = delta;
+        info->gamma = gamma;
+        info->n_unreachable = (int64_t)red[0];
+        info->n_subnormal = (int64_t)red[1];
+        info->n_saturated = (int64_t)red[2];
+        info->n_ambiguous = (int64_t)red[3];
+        info->n_negative = (int64_t)red[4];
+        info->n_uncertified = 0;
+        info->fallback_fraction = 0.0;
+    }
+    __syncthreads();
+}
+
+template <int TY, int TX, int RA, int RC>
+__global__ __launch_bounds__(TY *TX) void k_small_one(SmallTask t) {
+    constexpr int NP = TY * RA;
+    __shared__ double lds_gj[4 * NP];
+    __shared__ int lds_int[NP + 2];
+    solve_small<TY, TX, RA, RC>(t, lds_gj, lds_int);
+}
+
+// Persistent form: each workgroup pulls task indices from *counter.
+__global__ __launch_bounds__(256) void k_small_persistent(const SmallTask *__restrict__ tasks, int count,
+                                                          int *counter) {
+    __shared__ double lds_gj[4 * 128];
+    __shared__ int lds_int[128 + 2];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int idx = next;
+        __syncthreads();
+        if (idx >= count) break;
+        const SmallTask t = tasks[idx];
+        if (t.n <= 64) solve_small<16, 16, 4, 4>(t, lds_gj, lds_int);
+        else solve_small<16, 16, 8, 8>(t, lds_gj, lds_int);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Successor bitmaps: bit b of word w in row i is set iff there is an edge
+// i -> 64w + b, i.e. A[(64w + b) * n + i] == 1.  Row i is nw = ceil(n/64)
+// 64-bit words; its size is known up front, so no host synchronisation is
+// needed to allocate it.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_succ_bitmap(const uint8_t *__restrict__ A, int n, int nw,
+                                                     unsigned long long *__restrict__ bits) {
+    const int i = blockIdx.x * 256 + threadIdx.x;   // consecutive i read consecutive bytes of row j
+    const int w = blockIdx.y;
+    if (i >= n) return;
+    unsigned long long word = 0;
+    const int j0 = w * 64;
+    const int j1 = min(n, j0 + 64);
+    for (int j = j0; j < j1; ++j)
+        if (A[(size_t)j * n + i] == 1) word |= 1ull << (j - j0);
+    bits[(size_t)i * nw + w] = word;
+}
+
+// ---------------------------------------------------------------------------
+// Next hop: one wavefront per query (Sec. 4.2, Eq. descent as ascent on Y).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_next_hop(const double *__restrict__ Y, int ld, int n,
+                                                  const unsigned long long *__restrict__ bits, int nw,
+                                                  const int32_t *__restrict__ cur, const int32_t *__restrict__ goal,
+                                                  int q, int max_hops, int32_t *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= q) return;
+    int32_t *o = out + (size_t)w * (max_hops + 1);
+    for (int h = lane; h <= max_hops; h += 64) o[h] = -1;
+    int c = cur[w];
+    const int g = goal[w];
+    if (c < 0 || c >= n || g < 0 || g >= n) return;
+    if (lane == 0) o[0] = c;
+    const double *yg = Y + (size_t)g * ld;
+    for (int h = 1; h <= max_hops; ++h) {
+        if (c == g) break;
+        double bv = -1.0;
+        int bj = 0x7fffffff;
+        const unsigned long long *row = bits + (size_t)c * nw;
+        for (int ww = lane; ww < nw; ww += 64) {
+            unsigned long long word = row[ww];
+            while (word) {
+                const int b = __ffsll((long long)word) - 1;
+                word &= word - 1;
+                const int j = ww * 64 + b;
+                const double v = yg[j];
+                if (v > bv || (v == bv && j < bj)) { bv = v; bj = j; }
+            }
+        }
+        for (int s = 32; s > 0; s >>= 1) {
+            const double ov = __shfl_xor(bv, s, 64);
+            const int oj = __shfl_xor(bj, s, 64);
+            if (ov > bv || (ov == bv && oj < bj)) { bv = ov; bj = oj; }
+        }
+        if (!(bv > 0.0)) {
+            if (lane == 0) o[h] = -1;
+            break;
+        }
+        c = bj;
+        if (lane == 0) o[h] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
+                   int32_t *bad, rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_i32, dim3((n + 1 + 255) / 256), dim3(256), 0, s, outdeg, n);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, bad, 1);
+    const int rows = 256;
+    hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256, (n + rows - 1) / rows), dim3(256), 0, s, A, n, rows,
+                       outdeg, bad);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, outdeg, bad, n, gamma_arg, info);
+    const size_t pairs = (size_t)np * np / 2;
+    const int blocks = (int)std::min<size_t>((pairs + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_build_m, dim3(blocks), dim3(256), 0, s, A, n, np, ld, M, info);
+}
+
+void launch_fill_sentinel(int16_t *D, int n, const rdist_info *info, hipStream_t s) {
+    const size_t count = (size_t)n * n;
+    const int blocks = (int)std::min<size_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_sentinel, dim3(blocks), dim3(256), 0, s, D, count, info);
+}
+
+void launch_panel(const double *M, int ld, int K, double *Pt, double *V, int ldv, rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_panel, dim3(1), dim3(256), 0, s, M, ld, K, Pt, V, ldv, info);
+}
+
+void launch_rowcol(const double *M, int ld, int nb, int K, const double *Pt, double *Ut, double *V, int ldv,
+                   const rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_rowcol, dim3(2 * nb), dim3(256), 0, s, M, ld, nb, K, Pt, Ut, V, ldv, info);
+}
+
+void launch_update(double *M, int ld, int nb, int K, const double *Ut, const double *V, int ldv, bool fused,
+                   int n, int16_t *D, int keep_y, rdist_info *info, hipStream_t s) {
+    if (fused)
+        hipLaunchKernelGGL(k_update<true>, dim3(nb * nb), dim3(256), 0, s, M, ld, nb, K, Ut, V, ldv, n, D, keep_y,
+                           info);
+    else
+        hipLaunchKernelGGL(k_update<false>, dim3(nb * nb), dim3(256), 0, s, M, ld, nb, K, Ut, V, ldv, n, D,
+                           keep_y, info);
+}
+
+void launch_epilogue(const double *Y, int n, int ld, int16_t *D, rdist_info *info, hipStream_t s) {
+    const size_t total = (size_t)n * n;
+    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((total + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_epilogue, dim3(blocks), dim3(256), 0, s, Y, n, ld, D, info);
+}
+
+void launch_info_set(rdist_info *info, double gamma, hipStream_t s) {
+    hipLaunchKernelGGL(k_info_set, dim3(1), dim3(1), 0, s, info, gamma);
+}
+
+void launch_small_one(const SmallTask &t, hipStream_t s) {
+    if (t.n <= 32)
+        hipLaunchKernelGGL((k_small_one<8, 8, 4, 4>), dim3(1), dim3(64), 0, s, t);
+    else if (t.n <= 64)
+        hipLaunchKernelGGL((k_small_one<16, 16, 4, 4>), dim3(1), dim3(256), 0, s, t);
+    else
+        hipLaunchKernelGGL((k_small_one<16, 16, 8, 8>), dim3(1), dim3(256), 0, s, t);
+}
+
+void launch_small_persistent(const SmallTask *tasks, int count, int *counter, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, counter, 1);
+    hipLaunchKernelGGL(k_small_persistent, dim3(grid), dim3(256), 0, s, tasks, count, counter);
+}
+
+void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s) {
+    const int nw = (n + 63) / 64;
+    hipLaunchKernelGGL(k_succ_bitmap, dim3((n + 255) / 256, nw), dim3(256), 0, s, A, n, nw, bits);
+}
+
+void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
+                     const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s) {
+    if (q <= 0) return;
+    const int nw = (n + 63) / 64;
+    hipLaunchKernelGGL(k_next_hop, dim3((q + 3) / 4), dim3(256), 0, s, Y, ld, n, bits, nw, cur, goal, q, max_hops,
+                       out);
+}
+
+}  // namespace rd

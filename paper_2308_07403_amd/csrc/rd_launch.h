@@ -1,0 +1,40 @@
+// rd_launch.h -- host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "../../include/rdist.h"
+
+namespace rd {
+
+// One graph for the single-workgroup solver (n <= 128).
+struct SmallTask {
+    const uint8_t *A;      // n x n adjacency
+    int16_t *D;            // n x n distances
+    double *Y;             // nullable: n x ldy inverse
+    int32_t n;
+    int32_t ldy;
+    double gamma_arg;      // explicit (> 0) or AUTO (< 0)
+    rdist_info *info;      // device
+};
+
+void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
+                   int32_t *bad, rdist_info *info, hipStream_t s);
+void launch_fill_sentinel(int16_t *D, int n, const rdist_info *info, hipStream_t s);
+void launch_panel(const double *M, int ld, int K, double *Pt, double *V, int ldv, rdist_info *info, hipStream_t s);
+void launch_rowcol(const double *M, int ld, int nb, int K, const double *Pt, double *Ut, double *V, int ldv,
+                   const rdist_info *info, hipStream_t s);
+void launch_update(double *M, int ld, int nb, int K, const double *Ut, const double *V, int ldv, bool fused,
+                   int n, int16_t *D, int keep_y, rdist_info *info, hipStream_t s);
+void launch_epilogue(const double *Y, int n, int ld, int16_t *D, rdist_info *info, hipStream_t s);
+void launch_info_set(rdist_info *info, double gamma, hipStream_t s);
+void launch_small_one(const SmallTask &t, hipStream_t s);
+void launch_small_persistent(const SmallTask *tasks, int count, int *counter, int grid, hipStream_t s);
+void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s);
+void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
+                     const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s);
+
+}  // namespace rd

@@ -1,0 +1,290 @@
+"""ctypes binding of the gfx950 R-distance engine (``include/rdist.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``librdist.so``.  torch supplies device memory and streams.  If the
+library is missing this module raises at import time; there is no fallback.
+
+Raw entry points keep the C names (``rdist_create``, ``rdist_solve``,
+``rdist_solve_batched``, ``rdist_next_hop``, ...); ``Context`` wraps them for
+torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librdist.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP engine first "
+        "(python -m paper_2308_07403_amd.build); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_hip = ctypes.CDLL("libamdhip64.so")
+_hip.hipMemcpy2D.restype = ctypes.c_int
+
+# ---- status codes and flags (include/rdist.h) ----
+RDIST_OK, RDIST_E_ARG, RDIST_E_ADJ, RDIST_E_NOT_DD = 0, 1, 2, 3
+RDIST_E_NOMEM, RDIST_E_AGAIN, RDIST_E_HIP, RDIST_E_STATE = 4, 5, 6, 7
+RDIST_UNREACHABLE = 0x7FFF
+RDIST_F64 = 0x0
+RDIST_MIXED_F32 = 0x1
+RDIST_KEEP_Y = 0x10
+RDIST_PLAN_SMALL = 0x100
+RDIST_PLAN_BLOCKED = 0x200
+RDIST_UNFUSED_EPILOGUE = 0x400
+RDIST_THREADSAFE = 0x1
+(RDIST_K_UPDATE, RDIST_K_PANEL, RDIST_K_ROWCOL, RDIST_K_INGEST, RDIST_K_EPILOGUE, RDIST_K_SMALL,
+ RDIST_K_BATCHED, RDIST_K_NEXTHOP, RDIST_K_CERTIFY, RDIST_K_COUNT) = range(10)
+
+STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_ADJ", 3: "E_NOT_DD", 4: "E_NOMEM", 5: "E_AGAIN",
+                6: "E_HIP", 7: "E_STATE"}
+
+
+class rdist_info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("delta", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("n_unreachable", ctypes.c_int64),
+        ("n_subnormal", ctypes.c_int64),
+        ("n_saturated", ctypes.c_int64),
+        ("n_ambiguous", ctypes.c_int64),
+        ("n_negative", ctypes.c_int64),
+        ("n_uncertified", ctypes.c_int64),
+        ("fallback_fraction", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rdist_kernel_stats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+INFO_SIZE = ctypes.sizeof(rdist_info)
+assert INFO_SIZE == 72, INFO_SIZE
+
+_P = ctypes.c_void_p
+_lib.rdist_create.argtypes = [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_size_t, ctypes.c_char_p, ctypes.c_uint32]
+_lib.rdist_create.restype = ctypes.c_int
+_lib.rdist_destroy.argtypes = [_P]
+_lib.rdist_destroy.restype = None
+_lib.rdist_solve.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_uint32, _P, ctypes.POINTER(_P),
+                             _P, _P]
+_lib.rdist_solve.restype = ctypes.c_int
+_lib.rdist_solve_batched.argtypes = [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_uint32, _P, _P, _P, _P]
+_lib.rdist_solve_batched.restype = ctypes.c_int
+_lib.rdist_next_hop.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]
+_lib.rdist_next_hop.restype = ctypes.c_int
+_lib.rdist_graph_release.argtypes = [_P]
+_lib.rdist_graph_release.restype = None
+_lib.rdist_graph_y.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+_lib.rdist_graph_y.restype = ctypes.c_int
+_lib.rdist_epilogue.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P, _P, _P]
+_lib.rdist_epilogue.restype = ctypes.c_int
+_lib.rdist_set_timing.argtypes = [_P, ctypes.c_int]
+_lib.rdist_set_timing.restype = ctypes.c_int
+_lib.rdist_kernel_stats_get.argtypes = [_P, ctypes.c_int, ctypes.POINTER(rdist_kernel_stats)]
+_lib.rdist_kernel_stats_get.restype = ctypes.c_int
+_lib.rdist_hbm_in_use.argtypes = [_P]
+_lib.rdist_hbm_in_use.restype = ctypes.c_size_t
+_lib.rdist_last_error.argtypes = []
+_lib.rdist_last_error.restype = ctypes.c_char_p
+_lib.rdist_status_string.argtypes = [ctypes.c_int]
+_lib.rdist_status_string.restype = ctypes.c_char_p
+
+# Raw C entry points under their C names.
+rdist_create = _lib.rdist_create
+rdist_destroy = _lib.rdist_destroy
+rdist_solve = _lib.rdist_solve
+rdist_solve_batched = _lib.rdist_solve_batched
+rdist_next_hop = _lib.rdist_next_hop
+rdist_graph_release = _lib.rdist_graph_release
+rdist_graph_y = _lib.rdist_graph_y
+rdist_epilogue = _lib.rdist_epilogue
+rdist_set_timing = _lib.rdist_set_timing
+rdist_kernel_stats_get = _lib.rdist_kernel_stats_get
+rdist_hbm_in_use = _lib.rdist_hbm_in_use
+rdist_last_error = _lib.rdist_last_error
+rdist_status_string = _lib.rdist_status_string
+
+EXPORTS = ("rdist_create", "rdist_destroy", "rdist_solve", "rdist_solve_batched", "rdist_next_hop",
+           "rdist_graph_release", "rdist_graph_y", "rdist_epilogue", "rdist_set_timing",
+           "rdist_kernel_stats_get", "rdist_hbm_in_use", "rdist_last_error", "rdist_status_string")
+
+
+class RdistError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = rdist_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} {msg}")
+        self.status = status
+
+
+def _check(st: int, where: str):
+    if st != RDIST_OK:
+        raise RdistError(st, where)
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class PinnedInfo:
+    """rdist_info records in pinned host memory (written asynchronously by the device)."""
+
+    def __init__(self, count: int = 1):
+        self.count = count
+        self.buf = torch.zeros(count * INFO_SIZE, dtype=torch.uint8, pin_memory=True)
+        self.ptr = self.buf.data_ptr()
+
+    def at(self, i: int = 0) -> int:
+        return self.ptr + i * INFO_SIZE
+
+    def get(self, i: int = 0) -> rdist_info:
+        return rdist_info.from_address(self.at(i))
+
+
+@dataclass
+class Graph:
+    """A kept graph: device-resident Y (+ successor bitmaps) owned by the engine."""
+    ctx: "Context"
+    handle: int
+    n: int
+
+    def y(self) -> torch.Tensor:
+        """Copy of Y (n x n float64) on the device."""
+        yp, n, ld = _P(), ctypes.c_int32(), ctypes.c_int32()
+        _check(rdist_graph_y(self.handle, ctypes.byref(yp), ctypes.byref(n), ctypes.byref(ld)), "rdist_graph_y")
+        out = torch.empty((n.value, n.value), dtype=torch.float64, device=self.ctx.device)
+        torch.cuda.synchronize(self.ctx.device)
+        err = _hip.hipMemcpy2D(_P(out.data_ptr()), ctypes.c_size_t(8 * n.value), yp,
+                               ctypes.c_size_t(8 * ld.value), ctypes.c_size_t(8 * n.value),
+                               ctypes.c_size_t(n.value), 3)   # hipMemcpyDeviceToDevice
+        if err != 0:
+            raise RuntimeError(f"hipMemcpy2D failed with {err}")
+        return out
+
+    def release(self):
+        if self.handle:
+            rdist_graph_release(self.handle)
+            self.handle = 0
+
+
+class Context:
+    """One engine context on a device (owns workspaces, budget, kept graphs)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, tile_cache: str | None = None,
+                 threadsafe: bool = False):
+        self.device = torch.device("cuda", device)
+        h = _P()
+        _check(rdist_create(ctypes.byref(h), device, hbm_budget,
+                            tile_cache.encode() if tile_cache else None,
+                            RDIST_THREADSAFE if threadsafe else 0), "rdist_create")
+        self.handle = h.value
+        self.info = PinnedInfo(1)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            rdist_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- solves ----
+    def solve_async(self, A: torch.Tensor, gamma: float, flags: int = RDIST_F64, D: torch.Tensor | None = None,
+                    keep: bool = False, info: PinnedInfo | None = None, info_index: int = 0, stream=None):
+        """Enqueues one solve; returns (D, Graph or None).  info is filled when the stream gets there."""
+        assert A.is_cuda and A.dtype == torch.uint8 and A.dim() == 2 and A.shape[0] == A.shape[1]
+        A = A.contiguous()
+        n = A.shape[0]
+        if D is None:
+            D = torch.empty((n, n), dtype=torch.int16, device=A.device)
+        assert D.is_cuda and D.dtype == torch.int16 and D.is_contiguous() and D.numel() == n * n
+        if keep:
+            flags |= RDIST_KEEP_Y
+        g = _P()
+        info = info or self.info
+        st = rdist_solve(self.handle, A.data_ptr(), n, float(gamma), flags, D.data_ptr(),
+                         ctypes.byref(g) if keep else None, info.at(info_index), _stream_ptr(stream))
+        _check(st, "rdist_solve")
+        graph = Graph(self, g.value, n) if keep else None
+        return D, graph
+
+    def solve(self, A: torch.Tensor, gamma: float, flags: int = RDIST_F64, D: torch.Tensor | None = None,
+              keep: bool = False, stream=None):
+        """Synchronous convenience: returns (D, info dict, Graph or None)."""
+        D, graph = self.solve_async(A, gamma, flags, D, keep, self.info, 0, stream)
+        (stream or torch.cuda.current_stream()).synchronize()
+        return D, self.info.get(0).as_dict(), graph
+
+    def solve_batched(self, As, gamma, flags: int = RDIST_F64, Ds=None, keep: bool = False, stream=None,
+                      info: PinnedInfo | None = None, sync: bool = True):
+        count = len(As)
+        ns = (ctypes.c_int32 * count)(*[int(a.shape[0]) for a in As])
+        aptr = (ctypes.c_void_p * count)(*[a.data_ptr() for a in As])
+        if Ds is None:
+            Ds = [torch.empty((int(a.shape[0]),) * 2, dtype=torch.int16, device=a.device) for a in As]
+        dptr = (ctypes.c_void_p * count)(*[d.data_ptr() for d in Ds])
+        gam = gamma if hasattr(gamma, "__len__") else [gamma] * count
+        gptr = (ctypes.c_double * count)(*[float(x) for x in gam])
+        info = info or PinnedInfo(count)
+        keeps = (ctypes.c_void_p * count)() if keep else None
+        if keep:
+            flags |= RDIST_KEEP_Y
+        st = rdist_solve_batched(self.handle, count, ns, aptr, gptr, flags, dptr, keeps, info.ptr,
+                                 _stream_ptr(stream))
+        _check(st, "rdist_solve_batched")
+        graphs = [Graph(self, keeps[i], int(As[i].shape[0])) for i in range(count)] if keep else None
+        if sync:
+            (stream or torch.cuda.current_stream()).synchronize()
+        return Ds, info, graphs
+
+    def next_hop(self, graph: Graph, cur: torch.Tensor, goal: torch.Tensor, max_hops: int = 1,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        q = int(cur.numel())
+        cur = cur.to(device=self.device, dtype=torch.int32).contiguous()
+        goal = goal.to(device=self.device, dtype=torch.int32).contiguous()
+        if out is None:
+            out = torch.empty((q, max_hops + 1), dtype=torch.int32, device=self.device)
+        st = rdist_next_hop(self.handle, graph.handle, cur.data_ptr(), goal.data_ptr(), q, max_hops,
+                            out.data_ptr(), _stream_ptr(stream))
+        _check(st, "rdist_next_hop")
+        return out
+
+    def epilogue(self, Y: torch.Tensor, gamma: float, n: int | None = None, D: torch.Tensor | None = None,
+                 stream=None):
+        assert Y.is_cuda and Y.dtype == torch.float64 and Y.stride(1) == 1
+        n = n or Y.shape[0]
+        if D is None:
+            D = torch.empty((n, n), dtype=torch.int16, device=Y.device)
+        st = rdist_epilogue(self.handle, Y.data_ptr(), n, Y.stride(0), float(gamma), D.data_ptr(),
+                            self.info.at(0), _stream_ptr(stream))
+        _check(st, "rdist_epilogue")
+        return D
+
+    # ---- timing ----
+    def set_timing(self, on: bool):
+        _check(rdist_set_timing(self.handle, 1 if on else 0), "rdist_set_timing")
+
+    def kernel_stats(self, which: int) -> dict:
+        s = rdist_kernel_stats()
+        _check(rdist_kernel_stats_get(self.handle, which, ctypes.byref(s)), "rdist_kernel_stats_get")
+        return {"launches": s.launches, "total_ms": s.total_ms, "flops": s.flops, "bytes": s.bytes}
+
+    def hbm_in_use(self) -> int:
+        return int(rdist_hbm_in_use(self.handle))

@@ -1,0 +1,311 @@
+"""GPU parity: the HIP engine against the CPU oracle on identical seeded inputs.
+
+Bars: D bit-exact (integer output); Y within 1e-12 relative per entry for
+entries at or above DBL_MIN, exact zeros where the oracle has zeros.
+Next hop: every hop picks a successor whose oracle Y[goal, j] is the maximum
+up to 1e-10 relative, and the same successor as the oracle whenever the
+oracle's best and second best differ by more than that.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2308_07403_amd import rdist as R  # noqa: E402
+
+DBL_MIN = np.finfo(np.float64).tiny
+Y_TOL = 1e-12
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def dev(A):
+    return torch.from_numpy(np.ascontiguousarray(A)).cuda()
+
+
+def check_against_oracle(ctx, A, gamma, flags=0, keep=True, label=""):
+    note(f"[parity] {label} n={A.shape[0]} gamma={gamma} flags={flags:#x}")
+    sol = oracle.solve(A, gamma)
+    D, info, g = ctx.solve(dev(A), gamma, flags=flags, keep=keep)
+    Dh = D.cpu().numpy()
+    assert info["status"] == sol.status, (info, sol.status)
+    if sol.status != oracle.OK:
+        assert np.all(Dh == R.RDIST_UNREACHABLE)
+        return sol, Dh, None, g
+    assert info["delta"] == sol.delta
+    assert info["gamma"] == sol.gamma
+    bad = Dh != sol.D
+    if bad.any():
+        idx = np.argwhere(bad)[:10]
+        Yg = g.y().cpu().numpy() if g else None
+        detail = [(int(i), int(j), int(Dh[i, j]), int(sol.D[i, j]), float(sol.Y[i, j]),
+                   float(Yg[i, j]) if Yg is not None else None) for i, j in idx]
+        pytest.fail(f"{label}: {int(bad.sum())} D mismatches, first: {detail}")
+    assert info["n_unreachable"] == sol.unreachable
+    assert info["n_subnormal"] == sol.subnormal
+    assert info["n_saturated"] == sol.saturated
+    assert info["n_negative"] == 0
+    Yh = None
+    if keep:
+        Yh = g.y().cpu().numpy()
+        assert np.array_equal(Yh == 0.0, sol.Y == 0.0)
+        nz = sol.Y >= DBL_MIN
+        if nz.any():
+            rel = np.abs(Yh[nz] - sol.Y[nz]) / sol.Y[nz]
+            assert rel.max() <= Y_TOL, rel.max()
+    return sol, Dh, Yh, g
+
+
+# ---------------------------------------------------------------------------
+# Single-workgroup plan (n <= 128): configuration C1 and edge cases
+# ---------------------------------------------------------------------------
+
+def test_c1_er64_all_seeds(ctx):
+    for s in range(100):
+        A = gg.c1_graph(s)
+        _, _, _, g = check_against_oracle(ctx, A, gg.C1_GAMMA, label=f"c1 seed {s}")
+        g.release()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 31, 32, 33, 63, 64, 65, 100, 127, 128])
+def test_small_plan_sizes(ctx, n):
+    A = gg.erdos_renyi(n, min(0.5, 4.0 / max(n, 1)), gg.rng_for("parity", n))
+    _, _, _, g = check_against_oracle(ctx, A, -0.5, label="small sizes")
+    g.release()
+
+
+@pytest.mark.parametrize("gamma", [0.05, 0.5, 0.9])
+def test_small_directed_path_exact_integers(ctx, gamma):
+    A = gg.directed_path(100)
+    _, Dh, _, g = check_against_oracle(ctx, A, gamma, label="path")
+    i, j = np.indices(A.shape)
+    assert np.array_equal(Dh[i >= j], (i - j)[i >= j])
+    g.release()
+
+
+def test_small_precision_limit_path(ctx):
+    A = gg.directed_path(128)
+    _, _, _, g = check_against_oracle(ctx, A, 0.003, label="underflow path")   # 0.003^127 underflows
+    g.release()
+
+
+def test_small_structured(ctx):
+    for A, gam, lab in [(gg.undirected_path3(), 0.25, "p3"), (gg.directed_cycle(50), 0.3, "cycle"),
+                        (gg.complete_digraph(100), -0.5, "K100"), (gg.square_grid(8), 0.1, "grid8"),
+                        (gg.binary_tree(6), -0.5, "tree"), (np.zeros((20, 20), np.uint8), -0.5, "edgeless")]:
+        _, _, _, g = check_against_oracle(ctx, A, gam, label=lab)
+        g.release()
+
+
+def test_small_refusals(ctx):
+    check_against_oracle(ctx, gg.out_star(20), 0.25, keep=False, label="not DD")
+    bad = gg.directed_cycle(10)
+    bad[3, 3] = 1
+    D, info, _ = ctx.solve(dev(bad), 0.1)
+    assert info["status"] == R.RDIST_E_ADJ
+    assert torch.all(D == R.RDIST_UNREACHABLE)
+
+
+# ---------------------------------------------------------------------------
+# Blocked plan (128-blocks, MFMA updates, fused readout)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,p", [(129, 0.05), (200, 0.05), (256, 0.03), (300, 0.2), (640, 0.01)])
+def test_blocked_plan_er(ctx, n, p):
+    A = gg.erdos_renyi(n, p, gg.rng_for("parity", 1000 + n))
+    _, _, _, g = check_against_oracle(ctx, A, -0.5, label="blocked er")
+    g.release()
+
+
+def test_blocked_plan_forced_on_small_graph(ctx):
+    A = gg.c1_graph(7)
+    _, D1, _, g1 = check_against_oracle(ctx, A, gg.C1_GAMMA, flags=R.RDIST_PLAN_BLOCKED, label="forced blocked")
+    g1.release()
+
+
+@pytest.mark.parametrize("family", ["lattice", "rgg", "tree", "path"])
+def test_blocked_plan_families(ctx, family):
+    rng = gg.rng_for("parity", 2000 + len(family))
+    n = 400
+    A = {"lattice": lambda: gg.grid_lattice_deleted(n, rng), "rgg": lambda: gg.random_geometric(n, rng),
+         "tree": lambda: gg.random_tree(n, rng), "path": lambda: gg.directed_path(n)}[family]()
+    _, _, _, g = check_against_oracle(ctx, A, -0.5, label=f"blocked {family}")
+    g.release()
+
+
+def test_blocked_unfused_epilogue_matches_fused(ctx):
+    A = gg.erdos_renyi(384, 0.03, gg.rng_for("parity", 3000))
+    _, D1, _, g = check_against_oracle(ctx, A, -0.5, label="fused")
+    g.release()
+    _, D2, _, g = check_against_oracle(ctx, A, -0.5, flags=R.RDIST_UNFUSED_EPILOGUE, label="unfused")
+    g.release()
+    assert np.array_equal(D1, D2)
+
+
+def test_blocked_refusal_fills_sentinel(ctx):
+    check_against_oracle(ctx, gg.out_star(300), 0.25, keep=False, label="blocked not DD")
+
+
+@pytest.mark.parametrize("seed,fresh", [(0, False), (1, True)])
+def test_c2_subsample_2048(ctx, seed, fresh):
+    """The n = 2048 graphs of the C2 density, solved with the same blocked kernels as n = 8192."""
+    A = gg.c2_subsample(seed, fresh=fresh)
+    _, _, _, g = check_against_oracle(ctx, A, -0.5, label=f"c2 subsample {seed} fresh={fresh}")
+    g.release()
+
+
+# ---------------------------------------------------------------------------
+# Standalone readout on identical Y
+# ---------------------------------------------------------------------------
+
+def test_epilogue_on_oracle_y(ctx):
+    A = gg.erdos_renyi(300, 0.05, gg.rng_for("parity", 4000))
+    sol = oracle.solve(A, -0.5)
+    Y = sol.Y.copy()
+    g = sol.gamma
+    # planted values: exact powers, zero, subnormal, huge-distance, ties to thresholds
+    Y[0, :6] = [g ** 3, 0.0, 5e-320, 1.0, g ** (2 + 2e-9), g ** (2 + 0.5e-9)]
+    r = oracle.readout(Y, g)
+    Yd = torch.from_numpy(Y).cuda()
+    D = ctx.epilogue(Yd, g)
+    torch.cuda.synchronize()
+    info = ctx.info.get(0).as_dict()
+    assert np.array_equal(D.cpu().numpy(), r.D)
+    assert info["n_unreachable"] == r.unreachable and info["n_subnormal"] == r.subnormal
+
+
+# ---------------------------------------------------------------------------
+# Next hop
+# ---------------------------------------------------------------------------
+
+def check_paths(A, Yo, pairs, out, max_hops, tol=1e-10):
+    n = A.shape[0]
+    for (cur, goal), row in zip(pairs, out):
+        ref = oracle.path(A, Yo, int(cur), int(goal), max_hops)
+        if np.array_equal(ref, row):
+            continue
+        # divergence is allowed only at a near-tie of the oracle's Y
+        assert row[0] == cur
+        c = int(cur)
+        for h in range(1, max_hops + 1):
+            if c == goal:
+                assert row[h] == -1
+                break
+            succ = np.nonzero(A[:, c])[0]
+            vals = Yo[goal, succ]
+            if len(succ) == 0 or vals.max() <= 0:
+                assert row[h] == -1
+                break
+            j = int(row[h])
+            assert j in succ
+            best = vals.max()
+            assert Yo[goal, j] >= (1 - tol) * best
+            top2 = np.sort(vals)[-2] if len(vals) > 1 else -np.inf
+            if best - top2 > tol * best:
+                assert j == succ[np.argmax(vals)]
+            c = j
+
+
+@pytest.mark.parametrize("family,n", [("er", 100), ("lattice", 300), ("rgg", 250), ("tree", 120)])
+def test_next_hop_paths(ctx, family, n):
+    rng = gg.rng_for("parity", 5000 + n)
+    A = {"er": lambda: gg.erdos_renyi(n, 0.05, rng), "lattice": lambda: gg.grid_lattice_deleted(n, rng),
+         "rgg": lambda: gg.random_geometric(n, rng), "tree": lambda: gg.random_tree(n, rng)}[family]()
+    sol, _, Yh, g = check_against_oracle(ctx, A, -0.5, label=f"next-hop {family}")
+    pairs = rng.integers(0, n, size=(64, 2)).astype(np.int32)
+    pairs[0] = [5, 5]
+    max_hops = n - 1
+    out = ctx.next_hop(g, torch.from_numpy(pairs[:, 0]), torch.from_numpy(pairs[:, 1]), max_hops)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    check_paths(A, sol.Y, pairs, out, max_hops)
+    # single hop view
+    one = ctx.next_hop(g, torch.from_numpy(pairs[:, 0]), torch.from_numpy(pairs[:, 1]), 1).cpu().numpy()
+    assert np.array_equal(one[:, 0], pairs[:, 0])
+    g.release()
+
+
+def test_next_hop_bad_ids(ctx):
+    A = gg.directed_cycle(10)
+    _, _, _, g = check_against_oracle(ctx, A, 0.5, label="cycle")
+    cur = torch.tensor([-1, 3, 20, 2], dtype=torch.int32)
+    goal = torch.tensor([2, 99, 1, 2], dtype=torch.int32)
+    out = ctx.next_hop(g, cur, goal, 4).cpu().numpy()
+    assert (out[:3] == -1).all()
+    assert out[3].tolist() == [2, -1, -1, -1, -1]
+    g.release()
+
+
+# ---------------------------------------------------------------------------
+# Batched persistent plan
+# ---------------------------------------------------------------------------
+
+def test_batched_small_graphs(ctx):
+    specs = [s for s in gg.c3_specs(256, batch_index=7) if s.n <= 128][:96]
+    As = [s.build() for s in specs]
+    note(f"[parity] batched count={len(As)}")
+    Ds, info, graphs = ctx.solve_batched([dev(A) for A in As], -0.5, keep=True)
+    for k, (A, D) in enumerate(zip(As, Ds)):
+        sol = oracle.solve(A, -0.5)
+        assert info.get(k).status == sol.status
+        assert np.array_equal(D.cpu().numpy(), sol.D), f"graph {k} n={A.shape[0]}"
+        Yh = graphs[k].y().cpu().numpy()
+        nz = sol.Y >= DBL_MIN
+        assert np.max(np.abs(Yh[nz] - sol.Y[nz]) / sol.Y[nz]) <= Y_TOL
+        graphs[k].release()
+
+
+def test_batched_mixed_sizes_and_refusal(ctx):
+    As = [gg.erdos_renyi(n, 0.08, gg.rng_for("parity", 6000 + n)) for n in (40, 300, 90, 130, 17)]
+    As.append(gg.out_star(50))
+    gam = [-0.5] * 5 + [0.25]
+    Ds, info, _ = ctx.solve_batched([dev(A) for A in As], gam)
+    for k, A in enumerate(As):
+        sol = oracle.solve(A, gam[k])
+        assert info.get(k).status == sol.status
+        assert np.array_equal(Ds[k].cpu().numpy(), sol.D)
+
+
+# ---------------------------------------------------------------------------
+# Synchronous errors and the budget
+# ---------------------------------------------------------------------------
+
+def test_argument_errors(ctx):
+    A = dev(gg.c1_graph(0))
+    D = torch.empty((64, 64), dtype=torch.int16, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    assert R.rdist_solve(ctx.handle, A.data_ptr(), 0, 0.1, 0, D.data_ptr(), None, None, s) == R.RDIST_E_ARG
+    assert R.rdist_solve(ctx.handle, A.data_ptr(), 64, 1.5, 0, D.data_ptr(), None, None, s) == R.RDIST_E_ARG
+    assert R.rdist_solve(ctx.handle, A.data_ptr(), 64, -1.0, 0, D.data_ptr(), None, None, s) == R.RDIST_E_ARG
+    assert R.rdist_solve(ctx.handle, None, 64, 0.1, 0, D.data_ptr(), None, None, s) == R.RDIST_E_ARG
+    assert R.rdist_solve(ctx.handle, A.data_ptr(), 200, 0.1, R.RDIST_PLAN_SMALL, D.data_ptr(), None, None,
+                         s) == R.RDIST_E_ARG
+    assert R.rdist_solve(ctx.handle, A.data_ptr(), 64, 0.1, 0x8000, D.data_ptr(), None, None, s) == R.RDIST_E_ARG
+
+
+def test_budget_refusal():
+    c = R.Context(0, hbm_budget=1 << 20)
+    A = dev(gg.erdos_renyi(1024, 0.01, gg.rng_for("parity", 7000)))
+    with pytest.raises(R.RdistError) as e:
+        c.solve(A, -0.5)
+    assert e.value.status == R.RDIST_E_NOMEM
+    c.close()

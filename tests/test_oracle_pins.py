@@ -426,3 +426,28 @@ def test_gj_steps_compose():
     assert oracle.gj_steps_inplace(M2, 0, 17) == oracle.OK
     assert oracle.gj_steps_inplace(M2, 17, 64) == oracle.OK
     assert np.array_equal(M2, Y)
+
+
+# ---------------------------------------------------------------------------
+# Series rows/columns (Eq. inverse-series) against the Gauss-Jordan oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(3))
+def test_series_rows_and_columns_match_gauss_jordan(seed):
+    rng = gg.rng_for("pin", 1000 + seed)
+    A = [gg.erdos_renyi(150, 0.04, rng), gg.grid_lattice_deleted(150, rng), gg.random_geometric(150, rng)][seed]
+    sol = oracle.solve(A, -0.5)
+    for idx in (0, 17, 149):
+        col = oracle.y_column(A, sol.gamma, idx)
+        row = oracle.y_row(A, sol.gamma, idx)
+        for got, ref in ((col, sol.Y[:, idx]), (row, sol.Y[idx, :])):
+            assert np.array_equal(got == 0.0, ref == 0.0)
+            nz = ref > 0
+            assert np.max(np.abs(got[nz] - ref[nz]) / ref[nz]) < 1e-13
+
+
+def test_series_directed_path_exact_powers():
+    A = gg.directed_path(30)
+    col = oracle.y_column(A, 0.5, 3)
+    assert np.array_equal(col[3:], 0.5 ** np.arange(27))
+    assert np.all(col[:3] == 0.0)
