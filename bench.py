@@ -1,0 +1,273 @@
+"""Benchmark of the R-distance engine on MI355X.
+
+Default workload (one step = one full solve through the C ABI):
+  ER(8192, 0.02) directed graph, gamma = 0.5 / max out-degree, FP64 blocked
+  Gauss-Jordan on the FP64 matrix cores with the int16 readout fused into the
+  last update.  Inputs (adjacency and output buffer) are resident in HBM
+  before the timed region.
+
+Prints ONE JSON line: graphs/s (whole job), ms per step, effective TFLOP/s
+(2 n^3 / t), p50/p99 step latency, the roofline of the dominant kernel (the
+trailing-update kernel, timed with HIP events on its launch stream inside
+the library), and the CPU oracle timed on a bounded sample of the same solve.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+UPDATE_SOURCES = ["paper_2308_07403_amd/csrc/rd_kernels.hip", "paper_2308_07403_amd/csrc/rd_device.h"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_sha(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(profile_name: str, sha: str):
+    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE),
+    scaled by a copy kernel of known size; None if missing or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", profile_name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"source_sha:\s*([0-9a-f]+)", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_b or m_sha.group(1) != sha:
+        return None
+    return float(m_b.group(1))
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def cpu_baseline_c2(A: np.ndarray, gjsteps: int, rows: int):
+    """The oracle as it stands, on a bounded sample of the same n = 8192 solve:
+    gate + M build on the whole graph, `gjsteps` of the n Gauss-Jordan steps,
+    the readout of `rows` rows; scaled to one full solve (every GJ step and
+    every readout row costs the same)."""
+    import oracle
+    n = A.shape[0]
+    t0 = time.perf_counter()
+    prep = oracle.prepare(A, -0.5)
+    M = oracle.build_m(A, prep.gamma)
+    t1 = time.perf_counter()
+    oracle.gj_steps_inplace(M, 0, gjsteps)
+    t2 = time.perf_counter()
+    oracle.readout(np.ascontiguousarray(M[:rows, :rows]), prep.gamma)   # rows x rows entries
+    t3 = time.perf_counter()
+    t_full = (t1 - t0) + (t2 - t1) * n / gjsteps + (t3 - t2) * (n * n) / (rows * rows)
+    sampled = (t1 - t0) + (t2 - t1) + (t3 - t2)
+    return {
+        "value": 1.0 / t_full, "unit": "graphs/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": (f"n=8192 C2 graph: gate+M build in full, {gjsteps} of {n} Gauss-Jordan steps, "
+                   f"readout of {rows}x{rows} entries; scaled linearly to one solve "
+                   f"({sampled:.1f} s sampled, {t_full:.0f} s extrapolated)"),
+    }
+
+
+def cpu_floyd_warshall_c2(A: np.ndarray, ksteps: int):
+    import oracle
+    n = A.shape[0]
+    t0 = time.perf_counter()
+    oracle.floyd_warshall(A, k_steps=ksteps)
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / (t * n / ksteps), "unit": "graphs/s", "cores": oracle.num_threads(),
+            "sample": f"{ksteps} of {n} Floyd-Warshall relaxation rounds, scaled to all {n}"}
+
+
+def bench_c2(args, torch, R, gg):
+    n = 8192
+    A_np = gg.c2_graph(0)
+    A = torch.from_numpy(A_np).cuda()
+    D = torch.empty((n, n), dtype=torch.int16, device="cuda")
+    ctx = R.Context(0)
+    stream = torch.cuda.current_stream()
+    info = R.PinnedInfo(1)
+    log(f"[bench] c2 n={n}: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        ctx.solve_async(A, -0.5, R.RDIST_F64, D, info=info, stream=stream)
+    torch.cuda.synchronize()
+    st = info.get(0)
+    assert st.status == 0, st.as_dict()
+    ctx.set_timing(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    log(f"[bench] timed {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        ctx.solve_async(A, -0.5, R.RDIST_F64, D, info=info, stream=stream)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    upd = ctx.kernel_stats(R.RDIST_K_UPDATE)
+    edge = ctx.kernel_stats(R.RDIST_K_UPDATE_EDGE)
+    panel = ctx.kernel_stats(R.RDIST_K_PANEL)
+    rowcol = ctx.kernel_stats(R.RDIST_K_ROWCOL)
+    ingest = ctx.kernel_stats(R.RDIST_K_INGEST)
+    ctx.set_timing(False)
+    st = info.get(0).as_dict()
+    # next-hop on a kept solve (not part of the step)
+    _, g = ctx.solve_async(A, -0.5, R.RDIST_F64, D, keep=True, info=info, stream=stream)
+    rng = gg.rng_for("bench", 5)
+    pairs = torch.from_numpy(rng.integers(0, n, size=(64, 2)).astype(np.int32)).cuda()
+    cur, goal = pairs[:, 0].contiguous(), pairs[:, 1].contiguous()
+    out_paths = ctx.next_hop(g, cur, goal, max_hops=64, stream=stream)      # warm-up call
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.next_hop(g, cur, goal, max_hops=64, out=out_paths, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    nh_ms = e0.elapsed_time(e1)
+    g.release()
+    ctx.close()
+
+    flops = 2.0 * n ** 3
+    ms = wall * 1000.0 / args.steps
+    per_launch_flops = upd["flops"] / max(upd["launches"], 1)
+    avg_ms = upd["total_ms"] / max(upd["launches"], 1)
+    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
+    sha = source_sha(UPDATE_SOURCES)
+    traffic = read_traffic("k_update_c2_n8192_pmc.md", sha)
+    out = {
+        "metric": "APSP graphs/s + eff. TFLOP/s at n=8192 (FP64 vs mixed), p50/p99 latency",
+        "value": args.steps / wall,
+        "unit": "graphs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "C2: directed ER(n=8192, p=0.02), gamma=0.5/max_out_degree, FP64 blocked "
+                               "Gauss-Jordan on FP64 MFMA + fused int16 D readout",
+                   "n": n, "p": 0.02, "gamma": st["gamma"], "delta": st["delta"], "seed": "c2/0"},
+        "eff_tflops": flops / (ms * 1e-3) / 1e12,
+        "frac_fp64_peak_whole_solve": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+        "p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
+        "roofline": {"bound": "mfma", "kernel": "k_update<kRest> (FP64 MFMA rank-b trailing update, all tiles "
+                                                "outside the next block's row and column)",
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": traffic, "avg_launch_ms": avg_ms, "launches": upd["launches"],
+                     "flops_per_launch": per_launch_flops, "source_sha": sha},
+        "kernel_ms_per_step": {k: v["total_ms"] / args.steps for k, v in
+                               (("update_rest", upd), ("update_edge_and_last", edge), ("panel", panel),
+                                ("rowcol", rowcol), ("ingest", ingest))},
+        "next_hop_64_paths_ms": nh_ms,
+        "mixed": None,
+        "solve_info": {k: st[k] for k in ("status", "n_unreachable", "n_subnormal", "n_ambiguous")},
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline_c2(A_np, args.cpu_gj_steps, args.cpu_rows)
+        out["cpu_floyd_warshall"] = cpu_floyd_warshall_c2(A_np, args.cpu_fw_steps)
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
+def bench_c1(args, torch, R, gg):
+    import oracle
+    As = [torch.from_numpy(gg.c1_graph(s)).cuda() for s in range(100)]
+    D = torch.empty((64, 64), dtype=torch.int16, device="cuda")
+    ctx = R.Context(0)
+    stream = torch.cuda.current_stream()
+    info = R.PinnedInfo(1)
+    for A in As[: args.warmup * 10 + 1]:
+        ctx.solve_async(A, gg.C1_GAMMA, 0, D, info=info, stream=stream)
+    torch.cuda.synchronize()
+    lat = []
+    for k in range(args.steps * 10):
+        t0 = time.perf_counter()
+        ctx.solve_async(As[k % 100], gg.C1_GAMMA, 0, D, info=info, stream=stream)
+        stream.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = args.steps * 100
+    for k in range(reps):
+        ctx.solve_async(As[k % 100], gg.C1_GAMMA, 0, D, info=info, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    A0 = gg.c1_graph(0)
+    t0 = time.perf_counter()
+    for _ in range(200):
+        oracle.solve(A0, gg.C1_GAMMA, keep_y=False)
+    tc = (time.perf_counter() - t0) / 200
+    return {"metric": "C1 single-solve latency and back-to-back graphs/s (n=64)", "value": reps / wall,
+            "unit": "graphs/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / reps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "C1: ER(64, 0.1), gamma=0.05, 100 seeds"},
+            "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "cpu_baseline": {"value": 1.0 / tc, "unit": "graphs/s", "cores": oracle.num_threads(),
+                             "kind": "oracle", "sample": "200 solves of the seed-0 graph"}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (reference for HBM counters)")
+    ap.add_argument("--cpu-gj-steps", type=int, default=256)
+    ap.add_argument("--cpu-rows", type=int, default=2048)
+    ap.add_argument("--cpu-fw-steps", type=int, default=128)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this engine runs on one GPU; multi-GPU runs are not supported "
+              "(independent graphs would shard across GPUs with no exchange)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import graphgen as gg
+    from paper_2308_07403_amd import rdist as R
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
+        del src, dst
+    out = {"c2": bench_c2, "c1": bench_c1}[args.workload](args, torch, R, gg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -79,6 +79,8 @@ typedef enum rdist_status {
 #define RDIST_PLAN_SMALL 0x100u     /* force the single-workgroup register-resident plan (n <= 128) */
 #define RDIST_PLAN_BLOCKED 0x200u   /* force the blocked multi-kernel plan, whatever n */
 #define RDIST_UNFUSED_EPILOGUE 0x400u /* run the readout as a standalone pass over Y */
+#define RDIST_BLOCK_128 0x800u      /* blocked plan: force block width b = 128 */
+#define RDIST_BLOCK_256 0x1000u     /* blocked plan: force block width b = 256 (default for n > 1024) */
 
 /* ---- flags for rdist_create ---- */
 #define RDIST_THREADSAFE 0x1u
@@ -184,7 +186,8 @@ typedef struct rdist_kernel_stats {
     double bytes;            /* algorithmic bytes of those launches */
 } rdist_kernel_stats;
 
-#define RDIST_K_UPDATE 0      /* trailing rank-b update (the FP64/FP32 MFMA hot loop) */
+#define RDIST_K_UPDATE 0      /* trailing rank-b update over all tiles outside the next block's
+                                 row and column (the FP64/FP32 MFMA hot loop) */
 #define RDIST_K_PANEL 1       /* diagonal-block inverse */
 #define RDIST_K_ROWCOL 2      /* pivot row/column block preparation */
 #define RDIST_K_INGEST 3      /* adjacency -> M, degrees, gate */
@@ -193,7 +196,9 @@ typedef struct rdist_kernel_stats {
 #define RDIST_K_BATCHED 6     /* persistent batched solve */
 #define RDIST_K_NEXTHOP 7     /* next-hop queries */
 #define RDIST_K_CERTIFY 8     /* mixed precision: certification + recompute */
-#define RDIST_K_COUNT 9
+#define RDIST_K_UPDATE_EDGE 9 /* update of the next block's row and column (lookahead) and the
+                                 last, readout-fused update */
+#define RDIST_K_COUNT 10
 
 /* Enables (1) or disables (0) per-kernel event timing; enabling resets the counters. */
 rdist_status rdist_set_timing(rdist_ctx ctx, int enable);

@@ -90,54 +90,52 @@ struct RegGJ {
 
     // LDS scratch: 4 * NP doubles (pivot row and column, double-buffered).
     // Returns false (uniformly) if a pivot is not strictly positive.
+    // Step k = TY*ka + kt: the pivot row is register row ka of the lanes with
+    // ty == kt, the pivot column register column ka of the lanes with
+    // tx == kt (square thread grid).  The loop over ka is unrolled, so the
+    // register indices are compile-time and the fix-ups of the pivot row and
+    // column are a few lane selects; every entry costs one FMA per step.
     __device__ __forceinline__ bool run(int nsteps, double *lds, int ty, int tx) {
+        static_assert(TY == TX && RA == RC, "square thread grid and register tile");
         bool ok = true;
-        for (int k = 0; k < nsteps; ++k) {
-            double *rb = lds + (k & 1) * (2 * NP);
-            double *cb = rb + NP;
-            const int ka = k / TY, kty = k - ka * TY;
-            const int kc = k / TX, ktx = k - kc * TX;
-            if (ty == kty) {
+#pragma unroll
+        for (int ka = 0; ka < RA; ++ka) {
+            for (int kt = 0; kt < TY; ++kt) {
+                const int k = ka * TY + kt;
+                if (k >= nsteps) break;
+                double *rb = lds + (k & 1) * (2 * NP);
+                double *cb = rb + NP;
+                const bool rowk = ty == kt, colk = tx == kt;
+                if (rowk) {
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) rb[tx + TX * c] = m[ka][c];
+                }
+                if (colk) {
+#pragma unroll
+                    for (int a = 0; a < RA; ++a) cb[ty + TY * a] = m[a][ka];
+                }
+                __syncthreads();
+                const double p = cb[k];
+                ok = ok && (p > 0.0);
+                const double rp = 1.0 / p;
+                double ci[RA], rj[RC];
+#pragma unroll
+                for (int a = 0; a < RA; ++a) ci[a] = cb[ty + TY * a];
+#pragma unroll
+                for (int c = 0; c < RC; ++c) rj[c] = rb[tx + TX * c] * rp;
+                // pivot row: old entries become 0 and c_k = -1, so M'[k][j] = r_j;
+                // pivot column: old entries become 0 and r_k = 1/p, so M'[i][k] = -M[i][k]/p
+                ci[ka] = rowk ? -1.0 : ci[ka];
+                rj[ka] = colk ? rp : rj[ka];
+#pragma unroll
+                for (int c = 0; c < RC; ++c) m[ka][c] = rowk ? 0.0 : m[ka][c];
+#pragma unroll
+                for (int a = 0; a < RA; ++a) m[a][ka] = colk ? 0.0 : m[a][ka];
 #pragma unroll
                 for (int a = 0; a < RA; ++a)
-                    if (a == ka) {
 #pragma unroll
-                        for (int c = 0; c < RC; ++c) rb[tx + TX * c] = m[a][c];
-                    }
+                    for (int c = 0; c < RC; ++c) m[a][c] = fma(-ci[a], rj[c], m[a][c]);
             }
-            if (tx == ktx) {
-#pragma unroll
-                for (int c = 0; c < RC; ++c)
-                    if (c == kc) {
-#pragma unroll
-                        for (int a = 0; a < RA; ++a) cb[ty + TY * a] = m[a][c];
-                    }
-            }
-            __syncthreads();
-            const double p = cb[k];
-            ok = ok && (p > 0.0);
-            const double rp = 1.0 / p;
-            double ci[RA], rj[RC];
-            bool rowk[RA], colk[RC];
-#pragma unroll
-            for (int a = 0; a < RA; ++a) {
-                rowk[a] = (a == ka) && (ty == kty);
-                double v = cb[ty + TY * a];
-                ci[a] = rowk[a] ? -1.0 : v;
-            }
-#pragma unroll
-            for (int c = 0; c < RC; ++c) {
-                colk[c] = (c == kc) && (tx == ktx);
-                double v = rb[tx + TX * c] * rp;
-                rj[c] = colk[c] ? rp : v;
-            }
-#pragma unroll
-            for (int a = 0; a < RA; ++a)
-#pragma unroll
-                for (int c = 0; c < RC; ++c) {
-                    double o = (rowk[a] || colk[c]) ? 0.0 : m[a][c];
-                    m[a][c] = fma(-ci[a], rj[c], o);
-                }
         }
         return ok;
     }
@@ -193,45 +191,66 @@ __device__ __forceinline__ void tile_store_chunk(double *As, double *Bs, const d
     for (int q = 0; q < 4; ++q) { pa[q] = ra[q]; pb[q] = rb[q]; }
 }
 
+__device__ __forceinline__ void tile_load_frags(const double *As, const double *Bs, int kk, int r0, int c0,
+                                                int kr, double a[4], double b[4]) {
+    const double *ar = As + (kk * 4 + kr) * kLdsRow;
+    const double *br = Bs + (kk * 4 + kr) * kLdsRow;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { a[q] = ar[r0 + 16 * q]; b[q] = br[c0 + 16 * q]; }
+}
+
+// One k-chunk (kKC = 16, four MFMA k-steps).  Fragments are loaded one k-step
+// ahead; the scheduling barriers stop the compiler from hoisting every load
+// of the chunk (which would not fit next to the 128 accumulator VGPRs).
 __device__ __forceinline__ void tile_mma_chunk(const double *As, const double *Bs, TileAcc &acc) {
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int r0 = (w >> 1) * 64 + (lane & 15);
     const int c0 = (w & 1) * 64 + (lane & 15);
     const int kr = lane >> 4;
+    double a[2][4], b[2][4];
+    tile_load_frags(As, Bs, 0, r0, c0, kr, a[0], b[0]);
 #pragma unroll
     for (int kk = 0; kk < kKC / 4; ++kk) {
-        const double *ar = As + (kk * 4 + kr) * kLdsRow;
-        const double *br = Bs + (kk * 4 + kr) * kLdsRow;
-        double a[4], b[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) { a[q] = ar[r0 + 16 * q]; b[q] = br[c0 + 16 * q]; }
+        const int cur = kk & 1;
+        if (kk + 1 < kKC / 4) tile_load_frags(As, Bs, kk + 1, r0, c0, kr, a[cur ^ 1], b[cur ^ 1]);
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                acc.v[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], acc.v[p][q], 0, 0, 0);
+                acc.v[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][p], b[cur][q], acc.v[p][q], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// acc += A_k^T B_k over k in [0, kdim), kdim a multiple of kKC.
+// acc += A_k^T B_k over k in [0, KDIM), KDIM a multiple of kKC (a template
+// parameter: with a run-time trip count the register allocator spills).
 // lds: kTileLdsDoubles doubles.  Ends with a barrier (LDS reusable afterwards).
+template <int KDIM>
 __device__ __forceinline__ void tile_mma(const double *__restrict__ Ak, int lda,
-                                         const double *__restrict__ Bk, int ldb, int kdim,
+                                         const double *__restrict__ Bk, int ldb,
                                          double *lds, TileAcc &acc) {
-    double *As[2] = {lds, lds + 2 * kLdsChunk};
-    double *Bs[2] = {lds + kLdsChunk, lds + 3 * kLdsChunk};
-    double2 ra[4], rb[4];
-    tile_load_chunk(Ak, lda, Bk, ldb, 0, ra, rb);
-    tile_store_chunk(As[0], Bs[0], ra, rb);
+    static_assert(KDIM % kKC == 0, "inner dimension");
+    // buffer q: A at lds + 2q*chunk, B right after it
+    {
+        double2 ra[4], rb[4];
+        tile_load_chunk(Ak, lda, Bk, ldb, 0, ra, rb);
+        tile_store_chunk(lds, lds + kLdsChunk, ra, rb);
+    }
     __syncthreads();
-    const int nchunks = kdim / kKC;
+    constexpr int nchunks = KDIM / kKC;
+#pragma unroll
     for (int ch = 0; ch < nchunks; ++ch) {
-        const int cur = ch & 1;
-        const bool more = ch + 1 < nchunks;
-        if (more) tile_load_chunk(Ak, lda, Bk, ldb, (ch + 1) * kKC, ra, rb);
-        tile_mma_chunk(As[cur], Bs[cur], acc);
-        if (more) tile_store_chunk(As[cur ^ 1], Bs[cur ^ 1], ra, rb);
+        double *cur = lds + (ch & 1) * (2 * kLdsChunk);
+        double *nxt = lds + ((ch + 1) & 1) * (2 * kLdsChunk);
+        if (ch + 1 < nchunks) {
+            double2 ra[4], rb[4];
+            tile_load_chunk(Ak, lda, Bk, ldb, (ch + 1) * kKC, ra, rb);
+            tile_mma_chunk(cur, cur + kLdsChunk, acc);
+            tile_store_chunk(nxt, nxt + kLdsChunk, ra, rb);
+        } else {
+            tile_mma_chunk(cur, cur + kLdsChunk, acc);
+        }
         __syncthreads();
     }
 }
@@ -244,11 +263,15 @@ __device__ __forceinline__ void tile_for_each(TileAcc &acc, F &&f) {
     const int rbase = (w >> 1) * 64 + (lane >> 4);
     const int cbase = (w & 1) * 64 + (lane & 15);
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 4; ++p) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) f(rbase + 16 * p + 4 * r, cbase + 16 * q, acc.v[p][q][r]);
+        // keep at most one group of 16 entries' memory traffic in flight: the
+        // accumulators already hold 128 VGPRs
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 }  // namespace rd

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -45,11 +46,15 @@ struct Buf {
 
 struct Workspace {
     int np_cap = 0;      // blocked plan: padded order the buffers below hold
-    Buf M, Ut, V, Pt;    // np x np, 128 x np, 128 x np, 128 x 128 doubles
+    Buf M;               // np x np
+    Buf Ut[2], V[2];     // 256 x np each (double-buffered by step parity)
+    Buf Pt[2];           // 256 x 256
+    Buf S, Ut2, V2, Pt2; // scratch of the 256-block inverse (256^2, 128x256, 128x256, 128^2)
     Buf small;           // out-degrees (n_cap + 1), flag, device info
     int n_cap = 0;
     Buf tasks, infos, counter;   // batched plan
-    int task_cap = 0;
+    hipStream_t aux = nullptr;   // lookahead stream (default priority)
+    hipEvent_t ev_edge = nullptr, ev_panel = nullptr;
     double *m() const { return (double *)M.p; }
     int32_t *outdeg() const { return (int32_t *)small.p; }
     int32_t *bad() const { return outdeg() + n_cap + 1; }
@@ -149,17 +154,31 @@ rdist_status ensure_small(rdist_ctx c, Workspace &w, int n) {
 rdist_status ensure_big(rdist_ctx c, Workspace &w, int np) {
     if (w.np_cap < np) {
         release(c, w.M);
-        release(c, w.Ut);
-        release(c, w.V);
-        release(c, w.Pt);
+        for (int q = 0; q < 2; ++q) { release(c, w.Ut[q]); release(c, w.V[q]); }
         w.np_cap = np;
     }
     const int cap = w.np_cap;
     rdist_status st;
     if ((st = ensure(c, w.M, (size_t)cap * cap * 8))) return st;
-    if ((st = ensure(c, w.Ut, (size_t)kB * cap * 8))) return st;
-    if ((st = ensure(c, w.V, (size_t)kB * cap * 8))) return st;
-    return ensure(c, w.Pt, (size_t)kB * kB * 8);
+    for (int q = 0; q < 2; ++q) {
+        if ((st = ensure(c, w.Ut[q], (size_t)256 * cap * 8))) return st;
+        if ((st = ensure(c, w.V[q], (size_t)256 * cap * 8))) return st;
+        if ((st = ensure(c, w.Pt[q], (size_t)256 * 256 * 8))) return st;
+    }
+    if ((st = ensure(c, w.S, (size_t)256 * 256 * 8))) return st;
+    if ((st = ensure(c, w.Ut2, (size_t)128 * 256 * 8))) return st;
+    if ((st = ensure(c, w.V2, (size_t)128 * 256 * 8))) return st;
+    if ((st = ensure(c, w.Pt2, (size_t)128 * 128 * 8))) return st;
+    if (!w.aux) {
+        if (hipStreamCreateWithFlags(&w.aux, hipStreamNonBlocking) != hipSuccess) {
+            w.aux = nullptr;
+            return fail(RDIST_E_HIP, "hipStreamCreateWithFlags failed");
+        }
+        if (hipEventCreateWithFlags(&w.ev_edge, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&w.ev_panel, hipEventDisableTiming) != hipSuccess)
+            return fail(RDIST_E_HIP, "hipEventCreateWithFlags failed");
+    }
+    return RDIST_OK;
 }
 
 // ---- timing ----
@@ -250,8 +269,9 @@ void release_graph_locked(rdist_graph g) {
 
 rdist_status check_flags(uint32_t flags) {
     const uint32_t known = RDIST_MIXED_F32 | RDIST_KEEP_Y | RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED |
-                           RDIST_UNFUSED_EPILOGUE;
+                           RDIST_UNFUSED_EPILOGUE | RDIST_BLOCK_128 | RDIST_BLOCK_256;
     if (flags & ~known) return fail(RDIST_E_ARG, "unknown flag bits");
+    if ((flags & RDIST_BLOCK_128) && (flags & RDIST_BLOCK_256)) return fail(RDIST_E_ARG, "two block widths");
     if ((flags & RDIST_PLAN_SMALL) && (flags & RDIST_PLAN_BLOCKED)) return fail(RDIST_E_ARG, "two plan flags");
     if (flags & RDIST_MIXED_F32) return fail(RDIST_E_ARG, "RDIST_MIXED_F32 is not available in this build");
     return RDIST_OK;
@@ -264,18 +284,64 @@ rdist_status check_gamma(double gamma) {
     return RDIST_OK;
 }
 
-// Blocked solve of one graph on stream s.
+// Block width of the blocked plan, in 128-tiles: 2 (b = 256) for large
+// graphs (half the passes over the matrix), 1 otherwise; the RDIST_BLOCK_*
+// flags override it.
+int block_tiles(int n, uint32_t flags) {
+    if (flags & RDIST_BLOCK_128) return 1;
+    if (flags & RDIST_BLOCK_256) return 2;
+    return n > 1024 ? 2 : 1;
+}
+
+// P = M_KK^{-1} for the block at tile K0 (m tiles wide) into Pt (P^T) and
+// V's block columns, then the block's V row tiles and Ut, all on stream st.
+void enqueue_panel(rdist_ctx c, Workspace &w, int ld, int nt, int K0, int m, int par, rdist_info *dinfo,
+                   hipStream_t st) {
+    double *M = w.m();
+    double *Pt = (double *)w.Pt[par].p, *Ut = (double *)w.Ut[par].p, *V = (double *)w.V[par].p;
+    const double b = 128.0 * m;
+    {
+        Timer t(c, st, RDIST_K_PANEL, 2.0 * b * b * b, 16.0 * b * b);
+        if (m == 1) {
+            rd::launch_panel(M, ld, K0, Pt, V, ld, dinfo, st);
+        } else {
+            double *S = (double *)w.S.p, *Ut2 = (double *)w.Ut2.p, *V2 = (double *)w.V2.p, *Pt2 = (double *)w.Pt2.p;
+            rd::launch_copy_block(M, ld, K0, 256, S, dinfo, st);
+            for (int k2 = 0; k2 < 2; ++k2) {
+                rd::launch_panel(S, 256, k2, Pt2, V2, 256, dinfo, st);
+                rd::launch_rowcol(S, 256, 2, k2, 1, Pt2, Ut2, V2, 256, dinfo, st);
+                rd::launch_update(rd::kUpdateAll, S, 256, 2, k2, 1, 0, Ut2, V2, 256, false, 0, nullptr, 0, dinfo, st);
+            }
+            rd::launch_panel_finish(S, 256, K0, Pt, V, ld, dinfo, st);
+        }
+    }
+    {
+        Timer t(c, st, RDIST_K_ROWCOL, 2.0 * b * b * (nt * 128.0 - b), 8.0 * 4 * b * nt * 128.0);
+        rd::launch_rowcol(M, ld, nt, K0, m, Pt, Ut, V, ld, dinfo, st);
+    }
+}
+
+// Blocked solve of one graph on stream s: blocks of b = 128*m columns.
+// Step K's update is split into the next block's tile rows and columns (EDGE)
+// and all other tiles (REST).  EDGE and the next block's inverse and
+// row/column preparation run on the auxiliary stream while REST runs on s:
+//   aux: EDGE(K) -> panel(K+1) -> rowcol(K+1) -> record ev_panel
+//   s  : REST(K) -> record ev_edge ; wait ev_panel
+//   aux: wait ev_edge (EDGE(K+1) needs all of step K)
+// U, V and P^T are double-buffered by step parity, so step K+1's preparation
+// never overwrites what step K's update still reads.
 rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
                            rdist_graph *keep, rdist_info *info, hipStream_t s) {
     Workspace &w = c->ws[s];
-    const int np = ((n + kB - 1) / kB) * kB;
-    const int nb = np / kB;
+    const int m = block_tiles(n, flags);
+    const int bw = 128 * m;
+    const int np = ((n + bw - 1) / bw) * bw;
+    const int nt = np / kB, nbk = np / bw;
     rdist_status st = ensure_small(c, w, n);
     if (st) return st;
     if ((st = ensure_big(c, w, np))) return st;
     const int ld = w.np_cap;                     // M, Ut, V leading dimension
     double *M = w.m();
-    double *Ut = (double *)w.Ut.p, *V = (double *)w.V.p, *Pt = (double *)w.Pt.p;
     rdist_info *dinfo = w.dinfo();
     const bool keep_y = (flags & RDIST_KEEP_Y) != 0;
     const bool fused = !(flags & RDIST_UNFUSED_EPILOGUE);
@@ -284,21 +350,35 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
         rd::launch_ingest(A, n, np, ld, gamma, M, w.outdeg(), w.bad(), dinfo, s);
     }
     RD_HIP(hipGetLastError());
-    const double upd_flops = 2.0 * (double)np * np * kB;
-    for (int K = 0; K < nb; ++K) {
-        {
-            Timer t(c, s, RDIST_K_PANEL, 2.0 * kB * kB * kB, 16.0 * kB * kB);
-            rd::launch_panel(M, ld, K, Pt, V, ld, dinfo, s);
-        }
-        {
-            Timer t(c, s, RDIST_K_ROWCOL, 2.0 * kB * kB * (np - kB), 8.0 * 4 * kB * np);
-            rd::launch_rowcol(M, ld, nb, K, Pt, Ut, V, ld, dinfo, s);
-        }
-        const bool last = K == nb - 1;
-        {
-            double bytes = 16.0 * np * np;
-            Timer t(c, s, RDIST_K_UPDATE, upd_flops, bytes);
-            rd::launch_update(M, ld, nb, K, Ut, V, ld, last && fused, n, D, keep_y ? 1 : 0, dinfo, s);
+    enqueue_panel(c, w, ld, nt, 0, m, 0, dinfo, s);
+    if (nbk > 1) {
+        RD_HIP(hipEventRecord(w.ev_edge, s));
+        RD_HIP(hipStreamWaitEvent(w.aux, w.ev_edge, 0));
+    }
+    const double tile_flops = 2.0 * kB * kB * bw;
+    for (int K = 0; K < nbk; ++K) {
+        const int par = K & 1;
+        const int K0 = K * m;
+        const double *Ut = (const double *)w.Ut[par].p, *V = (const double *)w.V[par].p;
+        if (K + 1 < nbk) {
+            const int L0 = K0 + m;
+            const int te = rd::update_tiles(rd::kUpdateEdge, nt, m), tr = rd::update_tiles(rd::kUpdateRest, nt, m);
+            {
+                Timer t(c, w.aux, RDIST_K_UPDATE_EDGE, tile_flops * te, 16.0 * kB * kB * te);
+                rd::launch_update(rd::kUpdateEdge, M, ld, nt, K0, m, L0, Ut, V, ld, false, n, D, 0, dinfo, w.aux);
+            }
+            enqueue_panel(c, w, ld, nt, L0, m, par ^ 1, dinfo, w.aux);
+            RD_HIP(hipEventRecord(w.ev_panel, w.aux));
+            {
+                Timer t(c, s, RDIST_K_UPDATE, tile_flops * tr, 16.0 * kB * kB * tr);
+                rd::launch_update(rd::kUpdateRest, M, ld, nt, K0, m, L0, Ut, V, ld, false, n, D, 0, dinfo, s);
+            }
+            RD_HIP(hipEventRecord(w.ev_edge, s));
+            RD_HIP(hipStreamWaitEvent(s, w.ev_panel, 0));
+            RD_HIP(hipStreamWaitEvent(w.aux, w.ev_edge, 0));
+        } else {
+            Timer t(c, s, RDIST_K_UPDATE_EDGE, tile_flops * nt * nt, 16.0 * kB * kB * nt * nt);
+            rd::launch_update(rd::kUpdateAll, M, ld, nt, K0, m, 0, Ut, V, ld, fused, n, D, keep_y ? 1 : 0, dinfo, s);
         }
         RD_HIP(hipGetLastError());
     }
@@ -395,7 +475,12 @@ void rdist_destroy(rdist_ctx c) {
         for (auto *gr : gs) release_graph_locked(gr);
         for (auto &kv : c->ws) {
             Workspace &w = kv.second;
-            for (Buf *b : {&w.M, &w.Ut, &w.V, &w.Pt, &w.small, &w.tasks, &w.infos, &w.counter}) release(c, *b);
+            for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.S, &w.Ut2, &w.V2,
+                           &w.Pt2, &w.small, &w.tasks, &w.infos, &w.counter})
+                release(c, *b);
+            if (w.ev_edge) (void)hipEventDestroy(w.ev_edge);
+            if (w.ev_panel) (void)hipEventDestroy(w.ev_panel);
+            if (w.aux) (void)hipStreamDestroy(w.aux);
         }
     }
     delete c;

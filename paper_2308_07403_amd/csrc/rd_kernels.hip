@@ -109,63 +109,90 @@ __global__ __launch_bounds__(256) void k_fill_sentinel(int16_t *D, size_t count,
 // Blocked Gauss-Jordan
 // ---------------------------------------------------------------------------
 
-// P = M_KK^{-1}: writes P^T (k-major) to Pt and P into V's column block K.
+// P = M_KK^{-1}: writes P into V's column block K and P^T (k-major) to Pt.
+// Loads and the P store are coalesced straight from registers (lanes with
+// consecutive tx hold consecutive columns); P^T goes through a 64 x 65 LDS
+// quadrant.  About 37 KiB of LDS and under 192 VGPRs, so the kernel fits in
+// the slot of one update workgroup and can run beside the update kernels.
 __global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int ld, int K,
                                                double *__restrict__ Pt, double *__restrict__ V, int ldv,
                                                rdist_info *info) {
     if (info->status != RDIST_OK) return;
-    __shared__ double lds[4 * kTile];
+    __shared__ double piv[4 * kTile];
+    __shared__ double tq[64][65];
+    const double *base = M + (size_t)K * kTile * ld + (size_t)K * kTile;
     RegGJ<16, 16, 8, 8> g;
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-    const double *base = M + (size_t)K * kTile * ld + (size_t)K * kTile;
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
         for (int c = 0; c < 8; ++c) g.m[a][c] = base[(size_t)(ty + 16 * a) * ld + tx + 16 * c];
-    const bool ok = g.run(kTile, lds, ty, tx);
+    const bool ok = g.run(kTile, piv, ty, tx);
+    double *vk = V + (size_t)K * kTile;
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int i = ty + 16 * a, k = tx + 16 * c;
-            Pt[(size_t)k * kTile + i] = g.m[a][c];
-            V[(size_t)i * ldv + (size_t)K * kTile + k] = g.m[a][c];
+        for (int c = 0; c < 8; ++c) vk[(size_t)(ty + 16 * a) * ldv + tx + 16 * c] = g.m[a][c];
+    // P^T one 64 x 64 quadrant at a time: rows a in [4qa, 4qa+4), columns c in [4qc, 4qc+4)
+#pragma unroll
+    for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+        for (int qc = 0; qc < 2; ++qc) {
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) tq[ty + 16 * a][tx + 16 * c] = g.m[4 * qa + a][4 * qc + c];
+            __syncthreads();
+            for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+                const int r = e >> 6, cc = e & 63;   // Pt[64qc + r][64qa + cc] = P[64qa + cc][64qc + r]
+                Pt[(size_t)(64 * qc + r) * kTile + 64 * qa + cc] = tq[cc][r];
+            }
         }
     if (!ok && threadIdx.x == 0) atomicCAS(&info->status, RDIST_OK, RDIST_E_NOT_DD);
 }
 
-// Blocks [0, nb): V_J = P M_KJ for J != K.  Blocks [nb, 2nb): Ut_I = (M_IK)^T,
-// Ut_K = -I.  Ut and V are 128 x np, row-major (k-major operands).
-__global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, int ld, int nb, int K,
+// Step with block width b = 128*m whose block starts at tile K0 (tiles are
+// 128 x 128; nt tiles per side).  Pt is P^T (b x b, row-major, ld b).
+// Blocks [0, m*nt): V tile (r, J) = rows 128r.. of P times M_KJ (J outside
+// the block; the block's own V is P, written by the panel).
+// Blocks [m*nt, m*nt + nt): Ut_I = (M_IK)^T (b x 128) for I outside the
+// block, and -I for the block's own rows.  Ut and V are b x np, row-major.
+template <int MT>
+__global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, int ld, int nt, int K0,
                                                 const double *__restrict__ Pt, double *__restrict__ Ut,
                                                 double *__restrict__ V, int ldv, const rdist_info *info) {
+    constexpr int m = MT;
     if (info->status != RDIST_OK) return;
     __shared__ double lds[kTileLdsDoubles];
-    const int b = blockIdx.x;
-    if (b < nb) {
-        const int J = b;
-        if (J == K) return;
+    const int bdim = m * kTile;
+    const int blk = blockIdx.x;
+    if (blk < m * nt) {
+        const int r = blk / nt, J = blk - (blk / nt) * nt;
+        if (J >= K0 && J < K0 + m) return;
         TileAcc acc;
         acc.zero();
-        tile_mma(Pt, kTile, M + (size_t)K * kTile * ld + (size_t)J * kTile, ld, kTile, lds, acc);
-        double *out = V + (size_t)J * kTile;
-        tile_for_each(acc, [&](int r, int c, double v) { out[(size_t)r * ldv + c] = v; });
+        tile_mma<MT * kTile>(Pt + (size_t)r * kTile, bdim, M + (size_t)K0 * kTile * ld + (size_t)J * kTile, ld, lds,
+                             acc);
+        double *out = V + (size_t)r * kTile * ldv + (size_t)J * kTile;
+        tile_for_each(acc, [&](int rr, int c, double v) { out[(size_t)rr * ldv + c] = v; });
         return;
     }
-    const int I = b - nb;
+    const int I = blk - m * nt;
     double *out = Ut + (size_t)I * kTile;          // Ut[k][I*128 + i]
-    if (I == K) {
-        for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+    if (I >= K0 && I < K0 + m) {
+        const int off = (I - K0) * kTile;
+        for (int e = threadIdx.x; e < bdim * kTile; e += 256) {
             const int k = e >> 7, i = e & 127;
-            out[(size_t)k * ldv + i] = (k == i) ? -1.0 : 0.0;
+            out[(size_t)k * ldv + i] = (k == off + i) ? -1.0 : 0.0;
         }
         return;
     }
-    // transpose the 128 x 128 block M_IK through LDS, 64 x 64 at a time
+    // transpose the 128 x b block M_IK through LDS, 64 x 64 at a time
     double (*t)[65] = reinterpret_cast<double (*)[65]>(lds);
-    const double *src = M + (size_t)I * kTile * ld + (size_t)K * kTile;
+    const double *src = M + (size_t)I * kTile * ld + (size_t)K0 * kTile;
     for (int bi = 0; bi < 2; ++bi)
-        for (int bk = 0; bk < 2; ++bk) {
+        for (int bk = 0; bk < 2 * m; ++bk) {
             for (int e = threadIdx.x; e < 64 * 64; e += 256) {
                 const int r = e >> 6, c = e & 63;     // r: row i, c: column k
                 t[r][c] = src[(size_t)(bi * 64 + r) * ld + bk * 64 + c];
@@ -179,20 +206,52 @@ __global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, in
         }
 }
 
-// M_IJ <- M~_IJ - U_I V_J over all tiles.  With FUSED the tile's final value is
-// read out into D (and stored to M only if keep_y).
-template <bool FUSED>
-__global__ __launch_bounds__(256) void k_update(double *__restrict__ M, int ld, int nb, int K,
-                                                const double *__restrict__ Ut, const double *__restrict__ V,
-                                                int ldv, int n, int16_t *__restrict__ D, int keep_y,
-                                                rdist_info *info) {
+// Tile sets of one update: ALL tiles; EDGE = the tiles in the tile rows or
+// tile columns [L0, L0 + m) (the next block, updated first for lookahead);
+// REST = all other tiles.
+enum { kAll = 0, kEdge = 1, kRest = 2 };
+
+template <int MODE>
+__device__ __forceinline__ void update_tile_index(int b, int nt, int L0, int m, int &I, int &J) {
+    if (MODE == kAll) {
+        I = b / nt;
+        J = b - I * nt;
+    } else if (MODE == kEdge) {
+        if (b < m * nt) {
+            I = L0 + b / nt;
+            J = b - (b / nt) * nt;
+        } else {
+            const int q = b - m * nt;
+            const int Ip = q / m;
+            J = L0 + (q - Ip * m);
+            I = Ip < L0 ? Ip : Ip + m;
+        }
+    } else {
+        const int w = nt - m;
+        const int Ip = b / w, Jp = b - (b / w) * w;
+        I = Ip < L0 ? Ip : Ip + m;
+        J = Jp < L0 ? Jp : Jp + m;
+    }
+}
+
+// M_IJ <- M~_IJ - U_I V_J (inner dimension kdim = b) over the tiles of MODE,
+// M~ = M with the current block's tile rows and columns [K0, K0 + m) zeroed.
+// With FUSED the tile's final value is read out into D (and stored to M only
+// if keep_y).
+template <int MODE, bool FUSED, int MT>
+__global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int ld, int nt, int K0, int L0,
+                                                   const double *__restrict__ Ut, const double *__restrict__ V,
+                                                   int ldv, int n, int16_t *__restrict__ D, int keep_y,
+                                                   rdist_info *info) {
+    constexpr int m = MT;
     if (info->status != RDIST_OK) return;
     __shared__ double lds[kTileLdsDoubles];
-    const int I = blockIdx.x / nb, J = blockIdx.x - (blockIdx.x / nb) * nb;
+    int I, J;
+    update_tile_index<MODE>(blockIdx.x, nt, L0, m, I, J);
     TileAcc acc;
     acc.zero();
-    tile_mma(Ut + (size_t)I * kTile, ldv, V + (size_t)J * kTile, ldv, kTile, lds, acc);
-    const bool zero_in = (I == K) || (J == K);
+    tile_mma<MT * kTile>(Ut + (size_t)I * kTile, ldv, V + (size_t)J * kTile, ldv, lds, acc);
+    const bool zero_in = (I >= K0 && I < K0 + m) || (J >= K0 && J < K0 + m);
     double *base = M + (size_t)I * kTile * ld + (size_t)J * kTile;
     if (!FUSED) {
         tile_for_each(acc, [&](int r, int c, double v) {
@@ -210,6 +269,38 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ M, int ld, 
             if (gi < n && gj < n) D[(size_t)gi * n + gj] = rd_encode(y, lg, cnt);
         });
         flush_counts(info, cnt);
+    }
+}
+
+// S (b x b, ld b) = the diagonal block of M starting at tile K0.
+__global__ __launch_bounds__(256) void k_copy_block(const double *__restrict__ M, int ld, int K0, int b,
+                                                    double *__restrict__ S, const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    const double *src = M + (size_t)K0 * kTile * ld + (size_t)K0 * kTile;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < b * b; e += gridDim.x * 256) {
+        const int r = e / b, c = e - (e / b) * b;
+        S[e] = src[(size_t)r * ld + c];
+    }
+}
+
+// From P (b x b in S): Pt = P^T (ld b) and V's block columns [K0, K0 + m).
+__global__ __launch_bounds__(256) void k_panel_finish(const double *__restrict__ S, int b, int K0,
+                                                      double *__restrict__ Pt, double *__restrict__ V, int ldv,
+                                                      const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ double t[64][65];
+    const int nb64 = b / 64;
+    const int bi = blockIdx.x / nb64, bj = blockIdx.x - (blockIdx.x / nb64) * nb64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        const double v = S[(size_t)(bi * 64 + r) * b + bj * 64 + c];
+        t[r][c] = v;
+        V[(size_t)(bi * 64 + r) * ldv + (size_t)K0 * kTile + bj * 64 + c] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;       // Pt[bj*64 + r][bi*64 + c] = P[bi*64 + c][bj*64 + r]
+        Pt[(size_t)(bj * 64 + r) * b + bi * 64 + c] = t[c][r];
     }
 }
 
@@ -244,7 +335,7 @@ __global__ void k_info_set(rdist_info *info, double gamma) {
 // ---------------------------------------------------------------------------
 
 template <int TY, int TX, int RA, int RC>
-__device__ void solve_small(const SmallTask &t, double *lds_gj, int *lds_int) {
+__device__ __forceinline__ void solve_small(const SmallTask &t, double *lds_gj, int *lds_int) {
     using G = RegGJ<TY, TX, RA, RC>;
     constexpr int NP = G::NP;
     const int n = t.n;
@@ -461,19 +552,54 @@ void launch_panel(const double *M, int ld, int K, double *Pt, double *V, int ldv
     hipLaunchKernelGGL(k_panel, dim3(1), dim3(256), 0, s, M, ld, K, Pt, V, ldv, info);
 }
 
-void launch_rowcol(const double *M, int ld, int nb, int K, const double *Pt, double *Ut, double *V, int ldv,
-                   const rdist_info *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_rowcol, dim3(2 * nb), dim3(256), 0, s, M, ld, nb, K, Pt, Ut, V, ldv, info);
+void launch_rowcol(const double *M, int ld, int nt, int K0, int m, const double *Pt, double *Ut, double *V,
+                   int ldv, const rdist_info *info, hipStream_t s) {
+    if (m == 1)
+        hipLaunchKernelGGL(k_rowcol<1>, dim3(2 * nt), dim3(256), 0, s, M, ld, nt, K0, Pt, Ut, V, ldv, info);
+    else
+        hipLaunchKernelGGL(k_rowcol<2>, dim3(3 * nt), dim3(256), 0, s, M, ld, nt, K0, Pt, Ut, V, ldv, info);
 }
 
-void launch_update(double *M, int ld, int nb, int K, const double *Ut, const double *V, int ldv, bool fused,
-                   int n, int16_t *D, int keep_y, rdist_info *info, hipStream_t s) {
+int update_tiles(int mode, int nt, int m) {
+    if (mode == kAll) return nt * nt;
+    if (mode == kEdge) return 2 * m * nt - m * m;
+    return (nt - m) * (nt - m);
+}
+
+template <int MT>
+static void launch_update_t(int mode, double *M, int ld, int nt, int K0, int L0, const double *Ut, const double *V,
+                            int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info, hipStream_t s) {
+    const int tiles = update_tiles(mode, nt, MT);
+    if (tiles <= 0) return;
+    const dim3 g(tiles), bl(256);
     if (fused)
-        hipLaunchKernelGGL(k_update<true>, dim3(nb * nb), dim3(256), 0, s, M, ld, nb, K, Ut, V, ldv, n, D, keep_y,
+        hipLaunchKernelGGL((k_update<kAll, true, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y, info);
+    else if (mode == kAll)
+        hipLaunchKernelGGL((k_update<kAll, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
+                           info);
+    else if (mode == kEdge)
+        hipLaunchKernelGGL((k_update<kEdge, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
                            info);
     else
-        hipLaunchKernelGGL(k_update<false>, dim3(nb * nb), dim3(256), 0, s, M, ld, nb, K, Ut, V, ldv, n, D,
-                           keep_y, info);
+        hipLaunchKernelGGL((k_update<kRest, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
+                           info);
+}
+
+void launch_update(int mode, double *M, int ld, int nt, int K0, int m, int L0, const double *Ut, const double *V,
+                   int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info, hipStream_t s) {
+    if (m == 1)
+        launch_update_t<1>(mode, M, ld, nt, K0, L0, Ut, V, ldv, fused, n, D, keep_y, info, s);
+    else
+        launch_update_t<2>(mode, M, ld, nt, K0, L0, Ut, V, ldv, fused, n, D, keep_y, info, s);
+}
+
+void launch_copy_block(const double *M, int ld, int K0, int b, double *S, const rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_block, dim3(std::min(1024, b * b / 256)), dim3(256), 0, s, M, ld, K0, b, S, info);
+}
+
+void launch_panel_finish(const double *S, int b, int K0, double *Pt, double *V, int ldv, const rdist_info *info,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_panel_finish, dim3((b / 64) * (b / 64)), dim3(256), 0, s, S, b, K0, Pt, V, ldv, info);
 }
 
 void launch_epilogue(const double *Y, int n, int ld, int16_t *D, rdist_info *info, hipStream_t s) {

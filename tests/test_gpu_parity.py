@@ -129,10 +129,12 @@ def test_small_refusals(ctx):
 # Blocked plan (128-blocks, MFMA updates, fused readout)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,p", [(129, 0.05), (200, 0.05), (256, 0.03), (300, 0.2), (640, 0.01)])
-def test_blocked_plan_er(ctx, n, p):
+@pytest.mark.parametrize("bw", [R.RDIST_BLOCK_128, R.RDIST_BLOCK_256])
+@pytest.mark.parametrize("n,p", [(129, 0.05), (200, 0.05), (256, 0.03), (300, 0.2), (640, 0.01), (1000, 0.02)])
+def test_blocked_plan_er(ctx, n, p, bw):
+    """Ragged tails, one to eight blocks, both block widths (lookahead on from two blocks)."""
     A = gg.erdos_renyi(n, p, gg.rng_for("parity", 1000 + n))
-    _, _, _, g = check_against_oracle(ctx, A, -0.5, label="blocked er")
+    _, _, _, g = check_against_oracle(ctx, A, -0.5, flags=bw, label=f"blocked er bw={bw:#x}")
     g.release()
 
 
@@ -152,11 +154,12 @@ def test_blocked_plan_families(ctx, family):
     g.release()
 
 
-def test_blocked_unfused_epilogue_matches_fused(ctx):
-    A = gg.erdos_renyi(384, 0.03, gg.rng_for("parity", 3000))
-    _, D1, _, g = check_against_oracle(ctx, A, -0.5, label="fused")
+@pytest.mark.parametrize("bw", [R.RDIST_BLOCK_128, R.RDIST_BLOCK_256])
+def test_blocked_unfused_epilogue_matches_fused(ctx, bw):
+    A = gg.erdos_renyi(768, 0.03, gg.rng_for("parity", 3000))
+    _, D1, _, g = check_against_oracle(ctx, A, -0.5, flags=bw, label="fused")
     g.release()
-    _, D2, _, g = check_against_oracle(ctx, A, -0.5, flags=R.RDIST_UNFUSED_EPILOGUE, label="unfused")
+    _, D2, _, g = check_against_oracle(ctx, A, -0.5, flags=bw | R.RDIST_UNFUSED_EPILOGUE, label="unfused")
     g.release()
     assert np.array_equal(D1, D2)
 
@@ -165,9 +168,10 @@ def test_blocked_refusal_fills_sentinel(ctx):
     check_against_oracle(ctx, gg.out_star(300), 0.25, keep=False, label="blocked not DD")
 
 
-@pytest.mark.parametrize("seed,fresh", [(0, False), (1, True)])
+@pytest.mark.parametrize("seed,fresh", [(0, False), (1, True), (2, False)])
 def test_c2_subsample_2048(ctx, seed, fresh):
-    """The n = 2048 graphs of the C2 density, solved with the same blocked kernels as n = 8192."""
+    """The n = 2048 graphs of the C2 density, solved with the same kernels and block width
+    (b = 256, lookahead) as n = 8192."""
     A = gg.c2_subsample(seed, fresh=fresh)
     _, _, _, g = check_against_oracle(ctx, A, -0.5, label=f"c2 subsample {seed} fresh={fresh}")
     g.release()
