@@ -102,6 +102,7 @@ def cpu_floyd_warshall_c2(A: np.ndarray, ksteps: int):
 
 def bench_c2(args, torch, R, gg):
     n = 8192
+    fl = R.RDIST_F64 | {0: 0, 128: R.RDIST_BLOCK_128, 256: R.RDIST_BLOCK_256}[args.block]
     A_np = gg.c2_graph(0)
     A = torch.from_numpy(A_np).cuda()
     D = torch.empty((n, n), dtype=torch.int16, device="cuda")
@@ -110,7 +111,7 @@ def bench_c2(args, torch, R, gg):
     info = R.PinnedInfo(1)
     log(f"[bench] c2 n={n}: warmup {args.warmup}")
     for _ in range(args.warmup):
-        ctx.solve_async(A, -0.5, R.RDIST_F64, D, info=info, stream=stream)
+        ctx.solve_async(A, -0.5, fl, D, info=info, stream=stream)
     torch.cuda.synchronize()
     st = info.get(0)
     assert st.status == 0, st.as_dict()
@@ -121,7 +122,7 @@ def bench_c2(args, torch, R, gg):
     t0 = time.perf_counter()
     for k in range(args.steps):
         evs[k][0].record(stream)
-        ctx.solve_async(A, -0.5, R.RDIST_F64, D, info=info, stream=stream)
+        ctx.solve_async(A, -0.5, fl, D, info=info, stream=stream)
         evs[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -134,7 +135,7 @@ def bench_c2(args, torch, R, gg):
     ctx.set_timing(False)
     st = info.get(0).as_dict()
     # next-hop on a kept solve (not part of the step)
-    _, g = ctx.solve_async(A, -0.5, R.RDIST_F64, D, keep=True, info=info, stream=stream)
+    _, g = ctx.solve_async(A, -0.5, fl, D, keep=True, info=info, stream=stream)
     rng = gg.rng_for("bench", 5)
     pairs = torch.from_numpy(rng.integers(0, n, size=(64, 2)).astype(np.int32)).cuda()
     cur, goal = pairs[:, 0].contiguous(), pairs[:, 1].contiguous()
@@ -169,7 +170,8 @@ def bench_c2(args, torch, R, gg):
         "data": "synthetic",
         "config": {"workload": "C2: directed ER(n=8192, p=0.02), gamma=0.5/max_out_degree, FP64 blocked "
                                "Gauss-Jordan on FP64 MFMA + fused int16 D readout",
-                   "n": n, "p": 0.02, "gamma": st["gamma"], "delta": st["delta"], "seed": "c2/0"},
+                   "n": n, "p": 0.02, "gamma": st["gamma"], "delta": st["delta"], "seed": "c2/0",
+                   "block": args.block or "auto"},
         "eff_tflops": flops / (ms * 1e-3) / 1e12,
         "frac_fp64_peak_whole_solve": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
         "p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
@@ -240,6 +242,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
+    ap.add_argument("--block", type=int, default=0, choices=[0, 128, 256],
+                    help="force the blocked plan's block width (0: the engine's choice)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--cpu-gj-steps", type=int, default=256)
@@ -257,14 +261,18 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.calibrate_copy:
+        # reference for the HBM byte counters: a plain device copy of a known size
+        # whose source was pushed out of the caches by a larger scrub write first
         nb = args.calibrate_copy << 20
         src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
+        scrub = torch.empty(nb // 16, dtype=torch.float64, device="cuda")
+        scrub.fill_(2.0)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
-        del src, dst
+        del src, dst, scrub
     out = {"c2": bench_c2, "c1": bench_c1}[args.workload](args, torch, R, gg)
     print(json.dumps(out), flush=True)
 

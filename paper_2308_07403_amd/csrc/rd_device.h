@@ -47,6 +47,15 @@ __device__ __forceinline__ int16_t rd_encode(double y, double lg, Counts &c) {
     return (int16_t)(int)d;
 }
 
+// 1/p from the hardware reciprocal estimate and one Newton step on the
+// residual e = 1 - p*r (fused, so e is exact): |error| of order 1 ulp,
+// without the long dependent sequence of the IEEE division.
+__device__ __forceinline__ double recip(double p) {
+    const double r0 = __builtin_amdgcn_rcp(p);
+    const double e = fma(-p, r0, 1.0);
+    return fma(r0, e, r0);
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -88,57 +97,73 @@ struct RegGJ {
     static constexpr int NT = TY * TX;
     double m[RA][RC];
 
-    // LDS scratch: 4 * NP doubles (pivot row and column, double-buffered).
-    // Returns false (uniformly) if a pivot is not strictly positive.
+    // Rank-1 steps k in [k_begin, k_end).  LDS scratch: 4 * NP doubles (pivot
+    // row and column, double-buffered).  Returns false (uniformly) if a pivot
+    // is not strictly positive.
     // Step k = TY*ka + kt: the pivot row is register row ka of the lanes with
     // ty == kt, the pivot column register column ka of the lanes with
     // tx == kt (square thread grid).  The loop over ka is unrolled, so the
     // register indices are compile-time and the fix-ups of the pivot row and
     // column are a few lane selects; every entry costs one FMA per step.
-    __device__ __forceinline__ bool run(int nsteps, double *lds, int ty, int tx) {
+    __device__ __forceinline__ bool run(int k_begin, int k_end, double *lds, int ty, int tx) {
         static_assert(TY == TX && RA == RC, "square thread grid and register tile");
         bool ok = true;
-#pragma unroll
-        for (int ka = 0; ka < RA; ++ka) {
-            for (int kt = 0; kt < TY; ++kt) {
-                const int k = ka * TY + kt;
-                if (k >= nsteps) break;
-                double *rb = lds + (k & 1) * (2 * NP);
-                double *cb = rb + NP;
-                const bool rowk = ty == kt, colk = tx == kt;
-                if (rowk) {
-#pragma unroll
-                    for (int c = 0; c < RC; ++c) rb[tx + TX * c] = m[ka][c];
-                }
-                if (colk) {
-#pragma unroll
-                    for (int a = 0; a < RA; ++a) cb[ty + TY * a] = m[a][ka];
-                }
-                __syncthreads();
-                const double p = cb[k];
-                ok = ok && (p > 0.0);
-                const double rp = 1.0 / p;
-                double ci[RA], rj[RC];
-#pragma unroll
-                for (int a = 0; a < RA; ++a) ci[a] = cb[ty + TY * a];
-#pragma unroll
-                for (int c = 0; c < RC; ++c) rj[c] = rb[tx + TX * c] * rp;
-                // pivot row: old entries become 0 and c_k = -1, so M'[k][j] = r_j;
-                // pivot column: old entries become 0 and r_k = 1/p, so M'[i][k] = -M[i][k]/p
-                ci[ka] = rowk ? -1.0 : ci[ka];
-                rj[ka] = colk ? rp : rj[ka];
-#pragma unroll
-                for (int c = 0; c < RC; ++c) m[ka][c] = rowk ? 0.0 : m[ka][c];
-#pragma unroll
-                for (int a = 0; a < RA; ++a) m[a][ka] = colk ? 0.0 : m[a][ka];
-#pragma unroll
-                for (int a = 0; a < RA; ++a)
-#pragma unroll
-                    for (int c = 0; c < RC; ++c) m[a][c] = fma(-ci[a], rj[c], m[a][c]);
-            }
-        }
+        run_from<0>(k_begin, k_end, lds, ty, tx, ok);
         return ok;
     }
+
+    template <int KA>
+    __device__ __forceinline__ void run_from(int k_begin, int k_end, double *lds, int ty, int tx, bool &ok) {
+        if constexpr (KA < RA) {
+            rank1_steps<KA>(k_begin, k_end, lds, ty, tx, ok);
+            run_from<KA + 1>(k_begin, k_end, lds, ty, tx, ok);
+        }
+    }
+
+    template <int ka>
+    __device__ __forceinline__ void rank1_steps(int k_begin, int k_end, double *lds, int ty, int tx, bool &ok) {
+        const int kt0 = k_begin > ka * TY ? k_begin - ka * TY : 0;
+        const int kt1 = k_end < (ka + 1) * TY ? k_end - ka * TY : TY;
+        for (int kt = kt0; kt < kt1; ++kt) {
+            const int k = ka * TY + kt;
+            double *rb = lds + (k & 1) * (2 * NP);
+            double *cb = rb + NP;
+            const bool rowk = ty == kt, colk = tx == kt;
+            if (rowk) {
+#pragma unroll
+                for (int c = 0; c < RC; ++c) rb[tx + TX * c] = m[ka][c];
+            }
+            if (colk) {
+#pragma unroll
+                for (int a = 0; a < RA; ++a) cb[ty + TY * a] = m[a][ka];
+            }
+            __syncthreads();
+            const double p = cb[k];
+            ok = ok && (p > 0.0);
+            const double rp = recip(p);
+            double ci[RA], rj[RC];
+#pragma unroll
+            for (int a = 0; a < RA; ++a) ci[a] = cb[ty + TY * a];
+#pragma unroll
+            for (int c = 0; c < RC; ++c) rj[c] = rb[tx + TX * c] * rp;
+            // pivot row: old entries become 0 and c_k = -1, so M'[k][j] = r_j;
+            // pivot column: old entries become 0 and r_k = 1/p, so M'[i][k] = -M[i][k]/p
+            ci[ka] = rowk ? -1.0 : ci[ka];
+            rj[ka] = colk ? rp : rj[ka];
+#pragma unroll
+            for (int c = 0; c < RC; ++c) m[ka][c] = rowk ? 0.0 : m[ka][c];
+#pragma unroll
+            for (int a = 0; a < RA; ++a) m[a][ka] = colk ? 0.0 : m[a][ka];
+#pragma unroll
+            for (int a = 0; a < RA; ++a)
+#pragma unroll
+                for (int c = 0; c < RC; ++c) m[a][c] = fma(-ci[a], rj[c], m[a][c]);
+        }
+    }
+
+    // The whole inverse of the leading n x n block (rank-1 steps 0 .. n-1).
+    // LDS scratch: 4 * NP doubles.
+    __device__ __forceinline__ bool invert(int n, double *lds, int ty, int tx) { return run(0, n, lds, ty, tx); }
 };
 
 // ---------------------------------------------------------------------------
@@ -146,17 +171,23 @@ struct RegGJ {
 // 256 threads = 4 waves; wave w owns the 64 x 64 quadrant (w >> 1, w & 1) as
 // a 4 x 4 grid of 16 x 16 accumulators.  Operands are k-major in global
 // memory: A_k[k * lda + i] (i in the tile's 128 rows), B_k[k * ldb + j].
-// acc += sum_k A_k[k][i] * B_k[k][j].
+// acc += sum_k A_k[k][i] * B_k[k][j]; the caller initialises acc (with zero
+// or with the tile being updated, so that its load overlaps the first
+// operand chunk instead of trailing the contraction).
 //
 // MFMA operand layout (lane l of the wave): A element (row l%16, k l/16),
 // B element (k l/16, column l%16); accumulator element r in 0..3 of lane l is
 // row l/16 + 4*r, column l%16 of the 16 x 16 block (measured on gfx950).
+//
+// Operand chunks of kKC k-rows are copied global -> LDS by the load unit
+// (global_load_lds_dwordx4: each lane moves 16 bytes, one wave one 1 KiB row),
+// double-buffered, so no VGPRs are spent on staging.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 128;
 constexpr int kKC = 16;                       // k-chunk staged per LDS buffer
-constexpr int kLdsRow = kTile + 16;           // padded row: lanes 16..31 hit the other bank half
+constexpr int kLdsRow = kTile;                // one k-row of an operand
 constexpr int kLdsChunk = kKC * kLdsRow;      // doubles per operand per buffer
-constexpr int kTileLdsDoubles = 4 * kLdsChunk;  // A,B x double buffer (72 KiB)
+constexpr int kTileLdsDoubles = 4 * kLdsChunk;  // A,B x double buffer (64 KiB)
 
 struct TileAcc {
     d4 v[4][4];
@@ -168,28 +199,27 @@ struct TileAcc {
     }
 };
 
-__device__ __forceinline__ void tile_load_chunk(const double *__restrict__ Ak, int lda,
-                                                const double *__restrict__ Bk, int ldb, int k0,
-                                                double2 ra[4], double2 rb[4]) {
-    const int t = threadIdx.x;
-    const int r = t >> 4;            // 0..15: k row within the chunk
-    const int c = (t & 15) * 8;      // 8 consecutive doubles
-    const double2 *pa = reinterpret_cast<const double2 *>(Ak + (size_t)(k0 + r) * lda + c);
-    const double2 *pb = reinterpret_cast<const double2 *>(Bk + (size_t)(k0 + r) * ldb + c);
+typedef __attribute__((address_space(3))) void lds_void;
+typedef const __attribute__((address_space(1))) void global_cvoid;
+
+// Wave w copies k-rows 4w .. 4w+3 of both operands' chunk starting at k0.
+__device__ __forceinline__ void tile_dma_chunk(const double *__restrict__ Ak, int lda,
+                                               const double *__restrict__ Bk, int ldb, int k0,
+                                               double *As, double *Bs) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) { ra[q] = pa[q]; rb[q] = pb[q]; }
+    for (int q = 0; q < kKC / 4; ++q) {
+        const int r = w * (kKC / 4) + q;
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(Ak + (size_t)(k0 + r) * lda + 2 * lane),
+                                         (lds_void *)(As + r * kLdsRow), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(Bk + (size_t)(k0 + r) * ldb + 2 * lane),
+                                         (lds_void *)(Bs + r * kLdsRow), 16, 0, 0);
+    }
 }
 
-__device__ __forceinline__ void tile_store_chunk(double *As, double *Bs, const double2 ra[4],
-                                                 const double2 rb[4]) {
-    const int t = threadIdx.x;
-    const int r = t >> 4;
-    const int c = (t & 15) * 8;
-    double2 *pa = reinterpret_cast<double2 *>(As + r * kLdsRow + c);
-    double2 *pb = reinterpret_cast<double2 *>(Bs + r * kLdsRow + c);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) { pa[q] = ra[q]; pb[q] = rb[q]; }
-}
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left unconstrained): the chunk this
+// wave copied has landed in LDS; the barrier after it publishes all waves' rows.
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 __device__ __forceinline__ void tile_load_frags(const double *As, const double *Bs, int kk, int r0, int c0,
                                                 int kr, double a[4], double b[4]) {
@@ -225,34 +255,44 @@ __device__ __forceinline__ void tile_mma_chunk(const double *As, const double *B
 
 // acc += A_k^T B_k over k in [0, KDIM), KDIM a multiple of kKC (a template
 // parameter: with a run-time trip count the register allocator spills).
-// lds: kTileLdsDoubles doubles.  Ends with a barrier (LDS reusable afterwards).
+// lds: kTileLdsDoubles doubles (a __shared__ array).  Ends with a barrier.
 template <int KDIM>
 __device__ __forceinline__ void tile_mma(const double *__restrict__ Ak, int lda,
                                          const double *__restrict__ Bk, int ldb,
                                          double *lds, TileAcc &acc) {
     static_assert(KDIM % kKC == 0, "inner dimension");
     // buffer q: A at lds + 2q*chunk, B right after it
-    {
-        double2 ra[4], rb[4];
-        tile_load_chunk(Ak, lda, Bk, ldb, 0, ra, rb);
-        tile_store_chunk(lds, lds + kLdsChunk, ra, rb);
-    }
+    tile_dma_chunk(Ak, lda, Bk, ldb, 0, lds, lds + kLdsChunk);
+    wait_vm_all();
     __syncthreads();
     constexpr int nchunks = KDIM / kKC;
 #pragma unroll
     for (int ch = 0; ch < nchunks; ++ch) {
         double *cur = lds + (ch & 1) * (2 * kLdsChunk);
         double *nxt = lds + ((ch + 1) & 1) * (2 * kLdsChunk);
-        if (ch + 1 < nchunks) {
-            double2 ra[4], rb[4];
-            tile_load_chunk(Ak, lda, Bk, ldb, (ch + 1) * kKC, ra, rb);
-            tile_mma_chunk(cur, cur + kLdsChunk, acc);
-            tile_store_chunk(nxt, nxt + kLdsChunk, ra, rb);
-        } else {
-            tile_mma_chunk(cur, cur + kLdsChunk, acc);
-        }
+        if (ch + 1 < nchunks) tile_dma_chunk(Ak, lda, Bk, ldb, (ch + 1) * kKC, nxt, nxt + kLdsChunk);
+        tile_mma_chunk(cur, cur + kLdsChunk, acc);
+        wait_vm_all();
         __syncthreads();
     }
+}
+
+// Row and column (within the tile) of accumulator element (p, q, r) of this lane.
+__device__ __forceinline__ int tile_row(int p, int r) {
+    return ((threadIdx.x >> 6) >> 1) * 64 + ((threadIdx.x & 63) >> 4) + 16 * p + 4 * r;
+}
+__device__ __forceinline__ int tile_col(int q) {
+    return ((threadIdx.x >> 6) & 1) * 64 + (threadIdx.x & 15) + 16 * q;
+}
+
+// acc = tile of C (ld), the starting value of an update C - U V.
+__device__ __forceinline__ void tile_load_acc(TileAcc &acc, const double *C, int ld) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc.v[p][q][r] = C[(size_t)tile_row(p, r) * ld + tile_col(q)];
 }
 
 // Visits the accumulator entries: f(row_in_tile, col_in_tile, value).

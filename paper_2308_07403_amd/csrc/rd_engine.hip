@@ -49,12 +49,12 @@ struct Workspace {
     Buf M;               // np x np
     Buf Ut[2], V[2];     // 256 x np each (double-buffered by step parity)
     Buf Pt[2];           // 256 x 256
-    Buf S, Ut2, V2, Pt2; // scratch of the 256-block inverse (256^2, 128x256, 128x256, 128^2)
+    Buf Ut2, V2, Pt2;    // scratch of the 256-block inverse (128x256, 128x256, 128^2)
     Buf small;           // out-degrees (n_cap + 1), flag, device info
     int n_cap = 0;
     Buf tasks, infos, counter;   // batched plan
     hipStream_t aux = nullptr;   // lookahead stream (default priority)
-    hipEvent_t ev_edge = nullptr, ev_panel = nullptr;
+    hipEvent_t ev_er = nullptr, ev_rest = nullptr, ev_panel = nullptr;
     double *m() const { return (double *)M.p; }
     int32_t *outdeg() const { return (int32_t *)small.p; }
     int32_t *bad() const { return outdeg() + n_cap + 1; }
@@ -165,7 +165,6 @@ rdist_status ensure_big(rdist_ctx c, Workspace &w, int np) {
         if ((st = ensure(c, w.V[q], (size_t)256 * cap * 8))) return st;
         if ((st = ensure(c, w.Pt[q], (size_t)256 * 256 * 8))) return st;
     }
-    if ((st = ensure(c, w.S, (size_t)256 * 256 * 8))) return st;
     if ((st = ensure(c, w.Ut2, (size_t)128 * 256 * 8))) return st;
     if ((st = ensure(c, w.V2, (size_t)128 * 256 * 8))) return st;
     if ((st = ensure(c, w.Pt2, (size_t)128 * 128 * 8))) return st;
@@ -174,7 +173,8 @@ rdist_status ensure_big(rdist_ctx c, Workspace &w, int np) {
             w.aux = nullptr;
             return fail(RDIST_E_HIP, "hipStreamCreateWithFlags failed");
         }
-        if (hipEventCreateWithFlags(&w.ev_edge, hipEventDisableTiming) != hipSuccess ||
+        if (hipEventCreateWithFlags(&w.ev_er, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&w.ev_rest, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&w.ev_panel, hipEventDisableTiming) != hipSuccess)
             return fail(RDIST_E_HIP, "hipEventCreateWithFlags failed");
     }
@@ -294,42 +294,49 @@ int block_tiles(int n, uint32_t flags) {
 }
 
 // P = M_KK^{-1} for the block at tile K0 (m tiles wide) into Pt (P^T) and
-// V's block columns, then the block's V row tiles and Ut, all on stream st.
-void enqueue_panel(rdist_ctx c, Workspace &w, int ld, int nt, int K0, int m, int par, rdist_info *dinfo,
-                   hipStream_t st) {
+// V's block columns, on stream st.  For m = 2 the 256 x 256 block is
+// inverted in place inside M by two Gauss-Jordan steps of 128 (the step
+// update of this block overwrites the diagonal block with P anyway).
+void enqueue_inverse(rdist_ctx c, Workspace &w, int ld, int K0, int m, int par, rdist_info *dinfo,
+                     hipStream_t st) {
     double *M = w.m();
-    double *Pt = (double *)w.Pt[par].p, *Ut = (double *)w.Ut[par].p, *V = (double *)w.V[par].p;
+    double *Pt = (double *)w.Pt[par].p, *V = (double *)w.V[par].p;
     const double b = 128.0 * m;
-    {
-        Timer t(c, st, RDIST_K_PANEL, 2.0 * b * b * b, 16.0 * b * b);
-        if (m == 1) {
-            rd::launch_panel(M, ld, K0, Pt, V, ld, dinfo, st);
-        } else {
-            double *S = (double *)w.S.p, *Ut2 = (double *)w.Ut2.p, *V2 = (double *)w.V2.p, *Pt2 = (double *)w.Pt2.p;
-            rd::launch_copy_block(M, ld, K0, 256, S, dinfo, st);
-            for (int k2 = 0; k2 < 2; ++k2) {
-                rd::launch_panel(S, 256, k2, Pt2, V2, 256, dinfo, st);
-                rd::launch_rowcol(S, 256, 2, k2, 1, Pt2, Ut2, V2, 256, dinfo, st);
-                rd::launch_update(rd::kUpdateAll, S, 256, 2, k2, 1, 0, Ut2, V2, 256, false, 0, nullptr, 0, dinfo, st);
-            }
-            rd::launch_panel_finish(S, 256, K0, Pt, V, ld, dinfo, st);
-        }
+    Timer t(c, st, RDIST_K_PANEL, 2.0 * b * b * b, 16.0 * b * b);
+    if (m == 1) {
+        rd::launch_panel(M, ld, K0, Pt, V, ld, dinfo, st);
+        return;
     }
-    {
-        Timer t(c, st, RDIST_K_ROWCOL, 2.0 * b * b * (nt * 128.0 - b), 8.0 * 4 * b * nt * 128.0);
-        rd::launch_rowcol(M, ld, nt, K0, m, Pt, Ut, V, ld, dinfo, st);
+    double *S = M + (size_t)K0 * kB * ld + (size_t)K0 * kB;     // the diagonal block, leading dim ld
+    double *Ut2 = (double *)w.Ut2.p, *V2 = (double *)w.V2.p, *Pt2 = (double *)w.Pt2.p;
+    for (int k2 = 0; k2 < 2; ++k2) {
+        rd::launch_panel(S, ld, k2, Pt2, V2, 256, dinfo, st);
+        rd::launch_rowcol(S, ld, 2, k2, 1, Pt2, Ut2, V2, 256, dinfo, st);
+        rd::launch_update(rd::kUpdateAll, S, ld, 2, k2, 1, 0, Ut2, V2, 256, false, 0, nullptr, 0, dinfo, st);
     }
+    rd::launch_panel_finish(S, ld, 256, K0, Pt, V, ld, dinfo, st);
+}
+
+void enqueue_rowcol(rdist_ctx c, Workspace &w, int ld, int nt, int K0, int m, int par, rdist_info *dinfo,
+                    hipStream_t st) {
+    const double b = 128.0 * m;
+    Timer t(c, st, RDIST_K_ROWCOL, 2.0 * b * b * (nt * 128.0 - b), 8.0 * 4 * b * nt * 128.0);
+    rd::launch_rowcol(w.m(), ld, nt, K0, m, (double *)w.Pt[par].p, (double *)w.Ut[par].p, (double *)w.V[par].p,
+                      ld, dinfo, st);
 }
 
 // Blocked solve of one graph on stream s: blocks of b = 128*m columns.
-// Step K's update is split into the next block's tile rows and columns (EDGE)
-// and all other tiles (REST).  EDGE and the next block's inverse and
-// row/column preparation run on the auxiliary stream while REST runs on s:
-//   aux: EDGE(K) -> panel(K+1) -> rowcol(K+1) -> record ev_panel
-//   s  : REST(K) -> record ev_edge ; wait ev_panel
-//   aux: wait ev_edge (EDGE(K+1) needs all of step K)
-// U, V and P^T are double-buffered by step parity, so step K+1's preparation
-// never overwrites what step K's update still reads.
+// Step K's update is split by what the next block needs:
+//   DIAG      the next block's diagonal tiles (its inverse needs only these),
+//   EDGEREST  the rest of its tile rows and columns (its row/column prep),
+//   REST      everything else.
+// Schedule of step K (s = caller's stream, aux = auxiliary stream):
+//   s  : wait ev_panel; EDGEREST(K); record ev_er; REST(K); record ev_rest
+//   aux: DIAG(K); inverse(K+1); wait ev_er; rowcol(K+1); record ev_panel;
+//        wait ev_rest
+// so the next block's inverse runs beside the big update.  U, V and P^T are
+// double-buffered by step parity, so step K+1's preparation never
+// overwrites what step K's update still reads.
 rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
                            rdist_graph *keep, rdist_info *info, hipStream_t s) {
     Workspace &w = c->ws[s];
@@ -350,10 +357,11 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
         rd::launch_ingest(A, n, np, ld, gamma, M, w.outdeg(), w.bad(), dinfo, s);
     }
     RD_HIP(hipGetLastError());
-    enqueue_panel(c, w, ld, nt, 0, m, 0, dinfo, s);
+    enqueue_inverse(c, w, ld, 0, m, 0, dinfo, s);
+    enqueue_rowcol(c, w, ld, nt, 0, m, 0, dinfo, s);
     if (nbk > 1) {
-        RD_HIP(hipEventRecord(w.ev_edge, s));
-        RD_HIP(hipStreamWaitEvent(w.aux, w.ev_edge, 0));
+        RD_HIP(hipEventRecord(w.ev_rest, s));
+        RD_HIP(hipStreamWaitEvent(w.aux, w.ev_rest, 0));
     }
     const double tile_flops = 2.0 * kB * kB * bw;
     for (int K = 0; K < nbk; ++K) {
@@ -362,21 +370,31 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
         const double *Ut = (const double *)w.Ut[par].p, *V = (const double *)w.V[par].p;
         if (K + 1 < nbk) {
             const int L0 = K0 + m;
-            const int te = rd::update_tiles(rd::kUpdateEdge, nt, m), tr = rd::update_tiles(rd::kUpdateRest, nt, m);
+            const int td = rd::update_tiles(rd::kUpdateDiag, nt, m);
+            const int te = rd::update_tiles(rd::kUpdateEdgeRest, nt, m);
+            const int tr = rd::update_tiles(rd::kUpdateRest, nt, m);
+            if (K > 0) RD_HIP(hipStreamWaitEvent(s, w.ev_panel, 0));
             {
-                Timer t(c, w.aux, RDIST_K_UPDATE_EDGE, tile_flops * te, 16.0 * kB * kB * te);
-                rd::launch_update(rd::kUpdateEdge, M, ld, nt, K0, m, L0, Ut, V, ld, false, n, D, 0, dinfo, w.aux);
+                Timer t(c, s, RDIST_K_UPDATE_EDGE, tile_flops * te, 16.0 * kB * kB * te);
+                rd::launch_update(rd::kUpdateEdgeRest, M, ld, nt, K0, m, L0, Ut, V, ld, false, n, D, 0, dinfo, s);
             }
-            enqueue_panel(c, w, ld, nt, L0, m, par ^ 1, dinfo, w.aux);
-            RD_HIP(hipEventRecord(w.ev_panel, w.aux));
+            RD_HIP(hipEventRecord(w.ev_er, s));
             {
                 Timer t(c, s, RDIST_K_UPDATE, tile_flops * tr, 16.0 * kB * kB * tr);
                 rd::launch_update(rd::kUpdateRest, M, ld, nt, K0, m, L0, Ut, V, ld, false, n, D, 0, dinfo, s);
             }
-            RD_HIP(hipEventRecord(w.ev_edge, s));
-            RD_HIP(hipStreamWaitEvent(s, w.ev_panel, 0));
-            RD_HIP(hipStreamWaitEvent(w.aux, w.ev_edge, 0));
+            RD_HIP(hipEventRecord(w.ev_rest, s));
+            {
+                Timer t(c, w.aux, RDIST_K_UPDATE_EDGE, tile_flops * td, 16.0 * kB * kB * td);
+                rd::launch_update(rd::kUpdateDiag, M, ld, nt, K0, m, L0, Ut, V, ld, false, n, D, 0, dinfo, w.aux);
+            }
+            enqueue_inverse(c, w, ld, L0, m, par ^ 1, dinfo, w.aux);
+            RD_HIP(hipStreamWaitEvent(w.aux, w.ev_er, 0));
+            enqueue_rowcol(c, w, ld, nt, L0, m, par ^ 1, dinfo, w.aux);
+            RD_HIP(hipEventRecord(w.ev_panel, w.aux));
+            RD_HIP(hipStreamWaitEvent(w.aux, w.ev_rest, 0));
         } else {
+            if (K > 0) RD_HIP(hipStreamWaitEvent(s, w.ev_panel, 0));
             Timer t(c, s, RDIST_K_UPDATE_EDGE, tile_flops * nt * nt, 16.0 * kB * kB * nt * nt);
             rd::launch_update(rd::kUpdateAll, M, ld, nt, K0, m, 0, Ut, V, ld, fused, n, D, keep_y ? 1 : 0, dinfo, s);
         }
@@ -475,11 +493,11 @@ void rdist_destroy(rdist_ctx c) {
         for (auto *gr : gs) release_graph_locked(gr);
         for (auto &kv : c->ws) {
             Workspace &w = kv.second;
-            for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.S, &w.Ut2, &w.V2,
+            for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2,
                            &w.Pt2, &w.small, &w.tasks, &w.infos, &w.counter})
                 release(c, *b);
-            if (w.ev_edge) (void)hipEventDestroy(w.ev_edge);
-            if (w.ev_panel) (void)hipEventDestroy(w.ev_panel);
+            for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
+                if (e) (void)hipEventDestroy(e);
             if (w.aux) (void)hipStreamDestroy(w.aux);
         }
     }

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int
     for (int a = 0; a < 8; ++a)
 #pragma unroll
         for (int c = 0; c < 8; ++c) g.m[a][c] = base[(size_t)(ty + 16 * a) * ld + tx + 16 * c];
-    const bool ok = g.run(kTile, piv, ty, tx);
+    const bool ok = g.invert(kTile, piv, ty, tx);
     double *vk = V + (size_t)K * kTile;
 #pragma unroll
     for (int a = 0; a < 8; ++a)
@@ -156,8 +156,10 @@ __global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int
 // 128 x 128; nt tiles per side).  Pt is P^T (b x b, row-major, ld b).
 // Blocks [0, m*nt): V tile (r, J) = rows 128r.. of P times M_KJ (J outside
 // the block; the block's own V is P, written by the panel).
-// Blocks [m*nt, m*nt + nt): Ut_I = (M_IK)^T (b x 128) for I outside the
-// block, and -I for the block's own rows.  Ut and V are b x np, row-major.
+// Blocks [m*nt, m*nt + nt): the negated transposed column block,
+// Ut_I = -(M_IK)^T (b x 128) for I outside the block, and +I for the
+// block's own rows (U_K = -I).  The update then accumulates C + Ut^T V.
+// Ut and V are b x np, row-major.
 template <int MT>
 __global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, int ld, int nt, int K0,
                                                 const double *__restrict__ Pt, double *__restrict__ Ut,
@@ -184,11 +186,11 @@ __global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, in
         const int off = (I - K0) * kTile;
         for (int e = threadIdx.x; e < bdim * kTile; e += 256) {
             const int k = e >> 7, i = e & 127;
-            out[(size_t)k * ldv + i] = (k == off + i) ? -1.0 : 0.0;
+            out[(size_t)k * ldv + i] = (k == off + i) ? 1.0 : 0.0;
         }
         return;
     }
-    // transpose the 128 x b block M_IK through LDS, 64 x 64 at a time
+    // transpose (and negate) the 128 x b block M_IK through LDS, 64 x 64 at a time
     double (*t)[65] = reinterpret_cast<double (*)[65]>(lds);
     const double *src = M + (size_t)I * kTile * ld + (size_t)K0 * kTile;
     for (int bi = 0; bi < 2; ++bi)
@@ -200,28 +202,36 @@ __global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, in
             __syncthreads();
             for (int e = threadIdx.x; e < 64 * 64; e += 256) {
                 const int k = e >> 6, i = e & 63;
-                out[(size_t)(bk * 64 + k) * ldv + bi * 64 + i] = t[i][k];
+                out[(size_t)(bk * 64 + k) * ldv + bi * 64 + i] = -t[i][k];
             }
             __syncthreads();
         }
 }
 
-// Tile sets of one update: ALL tiles; EDGE = the tiles in the tile rows or
-// tile columns [L0, L0 + m) (the next block, updated first for lookahead);
-// REST = all other tiles.
-enum { kAll = 0, kEdge = 1, kRest = 2 };
+// Tile sets of one update, with [L0, L0 + m) the next block's tile range:
+//   ALL       every tile;
+//   REST      tiles outside the next block's tile rows and columns;
+//   DIAG      the next block's m x m diagonal tiles (all its inverse needs);
+//   EDGEREST  the next block's tile rows and columns minus DIAG (what its
+//             row/column preparation needs besides DIAG).
+enum { kAll = 0, kDiag = 1, kRest = 2, kEdgeRest = 3 };
 
 template <int MODE>
 __device__ __forceinline__ void update_tile_index(int b, int nt, int L0, int m, int &I, int &J) {
     if (MODE == kAll) {
         I = b / nt;
         J = b - I * nt;
-    } else if (MODE == kEdge) {
-        if (b < m * nt) {
-            I = L0 + b / nt;
-            J = b - (b / nt) * nt;
+    } else if (MODE == kDiag) {
+        I = L0 + b / m;
+        J = L0 + (b - (b / m) * m);
+    } else if (MODE == kEdgeRest) {
+        const int w = nt - m;
+        if (b < m * w) {
+            I = L0 + b / w;
+            const int Jp = b - (b / w) * w;
+            J = Jp < L0 ? Jp : Jp + m;
         } else {
-            const int q = b - m * nt;
+            const int q = b - m * w;
             const int Ip = q / m;
             J = L0 + (q - Ip * m);
             I = Ip < L0 ? Ip : Ip + m;
@@ -234,10 +244,11 @@ __device__ __forceinline__ void update_tile_index(int b, int nt, int L0, int m, 
     }
 }
 
-// M_IJ <- M~_IJ - U_I V_J (inner dimension kdim = b) over the tiles of MODE,
-// M~ = M with the current block's tile rows and columns [K0, K0 + m) zeroed.
-// With FUSED the tile's final value is read out into D (and stored to M only
-// if keep_y).
+// M_IJ <- M~_IJ - U_I V_J (inner dimension b = 128*MT) over the tiles of
+// MODE, M~ = M with the current block's tile rows and columns [K0, K0 + m)
+// zeroed.  The accumulators start from M~_IJ (loaded before the first operand
+// chunk lands) and add (-U)^T V, Ut holding -U^T.  With FUSED the tile's
+// final value is read out into D (and stored to M only if keep_y).
 template <int MODE, bool FUSED, int MT>
 __global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int ld, int nt, int K0, int L0,
                                                    const double *__restrict__ Ut, const double *__restrict__ V,
@@ -248,23 +259,19 @@ __global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int l
     __shared__ double lds[kTileLdsDoubles];
     int I, J;
     update_tile_index<MODE>(blockIdx.x, nt, L0, m, I, J);
-    TileAcc acc;
-    acc.zero();
-    tile_mma<MT * kTile>(Ut + (size_t)I * kTile, ldv, V + (size_t)J * kTile, ldv, lds, acc);
     const bool zero_in = (I >= K0 && I < K0 + m) || (J >= K0 && J < K0 + m);
     double *base = M + (size_t)I * kTile * ld + (size_t)J * kTile;
+    TileAcc acc;
+    if (zero_in) acc.zero();
+    else tile_load_acc(acc, base, ld);
+    tile_mma<MT * kTile>(Ut + (size_t)I * kTile, ldv, V + (size_t)J * kTile, ldv, lds, acc);
     if (!FUSED) {
-        tile_for_each(acc, [&](int r, int c, double v) {
-            double *p = base + (size_t)r * ld + c;
-            *p = (zero_in ? 0.0 : *p) - v;
-        });
+        tile_for_each(acc, [&](int r, int c, double v) { base[(size_t)r * ld + c] = v; });
     } else {
         const double lg = log(info->gamma);
         Counts cnt;
-        tile_for_each(acc, [&](int r, int c, double v) {
-            double *p = base + (size_t)r * ld + c;
-            const double y = (zero_in ? 0.0 : *p) - v;
-            if (keep_y) *p = y;
+        tile_for_each(acc, [&](int r, int c, double y) {
+            if (keep_y) base[(size_t)r * ld + c] = y;
             const int gi = I * kTile + r, gj = J * kTile + c;
             if (gi < n && gj < n) D[(size_t)gi * n + gj] = rd_encode(y, lg, cnt);
         });
@@ -272,19 +279,9 @@ __global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int l
     }
 }
 
-// S (b x b, ld b) = the diagonal block of M starting at tile K0.
-__global__ __launch_bounds__(256) void k_copy_block(const double *__restrict__ M, int ld, int K0, int b,
-                                                    double *__restrict__ S, const rdist_info *info) {
-    if (info->status != RDIST_OK) return;
-    const double *src = M + (size_t)K0 * kTile * ld + (size_t)K0 * kTile;
-    for (int e = blockIdx.x * 256 + threadIdx.x; e < b * b; e += gridDim.x * 256) {
-        const int r = e / b, c = e - (e / b) * b;
-        S[e] = src[(size_t)r * ld + c];
-    }
-}
-
-// From P (b x b in S): Pt = P^T (ld b) and V's block columns [K0, K0 + m).
-__global__ __launch_bounds__(256) void k_panel_finish(const double *__restrict__ S, int b, int K0,
+// From P (b x b, stored with leading dimension lds): Pt = P^T (ld b) and V's
+// block columns [K0, K0 + m).
+__global__ __launch_bounds__(256) void k_panel_finish(const double *__restrict__ S, int lds, int b, int K0,
                                                       double *__restrict__ Pt, double *__restrict__ V, int ldv,
                                                       const rdist_info *info) {
     if (info->status != RDIST_OK) return;
@@ -293,7 +290,7 @@ __global__ __launch_bounds__(256) void k_panel_finish(const double *__restrict__
     const int bi = blockIdx.x / nb64, bj = blockIdx.x - (blockIdx.x / nb64) * nb64;
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int r = e >> 6, c = e & 63;
-        const double v = S[(size_t)(bi * 64 + r) * b + bj * 64 + c];
+        const double v = S[(size_t)(bi * 64 + r) * lds + bj * 64 + c];
         t[r][c] = v;
         V[(size_t)(bi * 64 + r) * ldv + (size_t)K0 * kTile + bj * 64 + c] = v;
     }
@@ -385,7 +382,7 @@ __device__ __forceinline__ void solve_small(const SmallTask &t, double *lds_gj, 
                 const int i = ty + TY * a, j = tx + TX * c;
                 g.m[a][c] = (i == j ? 1.0 : 0.0) - gamma * (double)a8[a][c];
             }
-        const bool ok = g.run(n, lds_gj, ty, tx);
+        const bool ok = g.invert(n, lds_gj, ty, tx);
         if (!ok) st = RDIST_E_NOT_DD;
     }
     if (st == RDIST_OK) {
@@ -562,7 +559,8 @@ void launch_rowcol(const double *M, int ld, int nt, int K0, int m, const double 
 
 int update_tiles(int mode, int nt, int m) {
     if (mode == kAll) return nt * nt;
-    if (mode == kEdge) return 2 * m * nt - m * m;
+    if (mode == kDiag) return m * m;
+    if (mode == kEdgeRest) return 2 * m * (nt - m);
     return (nt - m) * (nt - m);
 }
 
@@ -577,8 +575,11 @@ static void launch_update_t(int mode, double *M, int ld, int nt, int K0, int L0,
     else if (mode == kAll)
         hipLaunchKernelGGL((k_update<kAll, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
                            info);
-    else if (mode == kEdge)
-        hipLaunchKernelGGL((k_update<kEdge, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
+    else if (mode == kDiag)
+        hipLaunchKernelGGL((k_update<kDiag, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
+                           info);
+    else if (mode == kEdgeRest)
+        hipLaunchKernelGGL((k_update<kEdgeRest, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
                            info);
     else
         hipLaunchKernelGGL((k_update<kRest, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
@@ -593,13 +594,9 @@ void launch_update(int mode, double *M, int ld, int nt, int K0, int m, int L0, c
         launch_update_t<2>(mode, M, ld, nt, K0, L0, Ut, V, ldv, fused, n, D, keep_y, info, s);
 }
 
-void launch_copy_block(const double *M, int ld, int K0, int b, double *S, const rdist_info *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_block, dim3(std::min(1024, b * b / 256)), dim3(256), 0, s, M, ld, K0, b, S, info);
-}
-
-void launch_panel_finish(const double *S, int b, int K0, double *Pt, double *V, int ldv, const rdist_info *info,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_panel_finish, dim3((b / 64) * (b / 64)), dim3(256), 0, s, S, b, K0, Pt, V, ldv, info);
+void launch_panel_finish(const double *S, int lds, int b, int K0, double *Pt, double *V, int ldv,
+                         const rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_panel_finish, dim3((b / 64) * (b / 64)), dim3(256), 0, s, S, lds, b, K0, Pt, V, ldv, info);
 }
 
 void launch_epilogue(const double *Y, int n, int ld, int16_t *D, rdist_info *info, hipStream_t s) {

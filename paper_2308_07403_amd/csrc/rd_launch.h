@@ -27,15 +27,14 @@ void launch_fill_sentinel(int16_t *D, int n, const rdist_info *info, hipStream_t
 void launch_panel(const double *M, int ld, int K, double *Pt, double *V, int ldv, rdist_info *info, hipStream_t s);
 // Blocked Gauss-Jordan pieces (tiles are 128 x 128; a block is m tiles wide,
 // starting at tile K0; nt tiles per side).
-enum UpdateMode { kUpdateAll = 0, kUpdateEdge = 1, kUpdateRest = 2 };
+enum UpdateMode { kUpdateAll = 0, kUpdateDiag = 1, kUpdateRest = 2, kUpdateEdgeRest = 3 };
 int update_tiles(int mode, int nt, int m);
 void launch_rowcol(const double *M, int ld, int nt, int K0, int m, const double *Pt, double *Ut, double *V,
                    int ldv, const rdist_info *info, hipStream_t s);
 void launch_update(int mode, double *M, int ld, int nt, int K0, int m, int L0, const double *Ut, const double *V,
                    int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info, hipStream_t s);
-void launch_copy_block(const double *M, int ld, int K0, int b, double *S, const rdist_info *info, hipStream_t s);
-void launch_panel_finish(const double *S, int b, int K0, double *Pt, double *V, int ldv, const rdist_info *info,
-                         hipStream_t s);
+void launch_panel_finish(const double *S, int lds, int b, int K0, double *Pt, double *V, int ldv,
+                         const rdist_info *info, hipStream_t s);
 void launch_epilogue(const double *Y, int n, int ld, int16_t *D, rdist_info *info, hipStream_t s);
 void launch_info_set(rdist_info *info, double gamma, hipStream_t s);
 void launch_small_one(const SmallTask &t, hipStream_t s);
