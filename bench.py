@@ -235,12 +235,81 @@ def bench_c1(args, torch, R, gg):
                              "kind": "oracle", "sample": "200 solves of the seed-0 graph"}}
 
 
+def bench_c3(args, torch, R, gg):
+    """1024 small graphs (n log-uniform in [32, 512], ER / lattice / RGG) per
+    step, solved by one persistent batched launch."""
+    import oracle
+    specs = gg.c3_specs(1024, batch_index=0)
+    A_np = [s.build() for s in specs]
+    As = [torch.from_numpy(A).cuda() for A in A_np]
+    Ds = [torch.empty((a.shape[0],) * 2, dtype=torch.int16, device="cuda") for a in As]
+    ns = np.array([a.shape[0] for a in A_np], dtype=np.float64)
+    flops = float(np.sum(2.0 * ns ** 3))
+    ctx = R.Context(0)
+    stream = torch.cuda.current_stream()
+    info = R.PinnedInfo(len(As))
+    log(f"[bench] c3 {len(As)} graphs: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        ctx.solve_batched(As, -0.5, Ds=Ds, info=info, stream=stream, sync=False)
+    torch.cuda.synchronize()
+    bad = [k for k in range(len(As)) if info.get(k).status != 0]
+    assert not bad, f"graphs {bad[:5]} refused"
+    ctx.set_timing(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    log(f"[bench] timed {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        ctx.solve_batched(As, -0.5, Ds=Ds, info=info, stream=stream, sync=False)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    bk = ctx.kernel_stats(R.RDIST_K_BATCHED)
+    ctx.set_timing(False)
+    ctx.close()
+    ms = wall * 1000.0 / args.steps
+    avg_ms = bk["total_ms"] / max(bk["launches"], 1)
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    out = {
+        "metric": "batched small-graph APSP graphs/s (1024 graphs, n in [32, 512])",
+        "value": len(As) * args.steps / wall, "unit": "graphs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "C3: 1024 graphs per step, n log-uniform in [32, 512], ER(p~U[0.05,0.2]) / "
+                               "torus lattice / RGG, gamma=0.5/max_out_degree, one persistent launch",
+                   "graphs": len(As), "sum_n3": float(np.sum(ns ** 3))},
+        "eff_tflops": flops / (ms * 1e-3) / 1e12,
+        "p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
+        "roofline": {"bound": "mfma", "kernel": "k_batched (persistent: one workgroup per graph)",
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "avg_launch_ms": avg_ms,
+                     "launches": bk["launches"], "flops_per_launch": flops},
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle sample)")
+        idx = list(range(0, len(A_np), 16))
+        t0 = time.perf_counter()
+        for k in idx:
+            oracle.solve(A_np[k], -0.5, keep_y=False)
+        t = time.perf_counter() - t0
+        frac = float(np.sum(ns[idx] ** 3) / np.sum(ns ** 3))
+        out["cpu_baseline"] = {"value": len(A_np) / (t / frac), "unit": "graphs/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{len(idx)} of the 1024 graphs (every 16th), scaled by their share "
+                                         f"of sum n^3 ({frac:.3f}); {t:.1f} s sampled"}
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--block", type=int, default=0, choices=[0, 128, 256],
                     help="force the blocked plan's block width (0: the engine's choice)")
@@ -273,7 +342,7 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
         del src, dst, scrub
-    out = {"c2": bench_c2, "c1": bench_c1}[args.workload](args, torch, R, gg)
+    out = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3}[args.workload](args, torch, R, gg)
     print(json.dumps(out), flush=True)
 
 

@@ -37,6 +37,7 @@ rdist_status fail(rdist_status s, const std::string &msg) {
     } while (0)
 
 constexpr int kB = 128;   // block size of the blocked solver = tile size
+constexpr int kBatchMaxN = 512;   // largest graph the persistent batched kernel solves
 
 // A device allocation with its size, so the budget can be returned exactly.
 struct Buf {
@@ -53,6 +54,7 @@ struct Workspace {
     Buf small;           // out-degrees (n_cap + 1), flag, device info
     int n_cap = 0;
     Buf tasks, infos, counter;   // batched plan
+    Buf bpool, bscratch;         // batched plan: medium graphs' matrices, per-workgroup scratch
     hipStream_t aux = nullptr;   // lookahead stream (default priority)
     hipEvent_t ev_er = nullptr, ev_rest = nullptr, ev_panel = nullptr;
     double *m() const { return (double *)M.p; }
@@ -494,7 +496,7 @@ void rdist_destroy(rdist_ctx c) {
         for (auto &kv : c->ws) {
             Workspace &w = kv.second;
             for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2,
-                           &w.Pt2, &w.small, &w.tasks, &w.infos, &w.counter})
+                           &w.Pt2, &w.small, &w.tasks, &w.infos, &w.counter, &w.bpool, &w.bscratch})
                 release(c, *b);
             for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
                 if (e) (void)hipEventDestroy(e);
@@ -543,44 +545,69 @@ rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const int32_t *n, c
     RD_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     Workspace &w = c->ws[s];
-    // small graphs: one persistent launch, longest first
-    std::vector<int> small_ids, big_ids;
-    for (int g = 0; g < count; ++g) (n[g] <= 128 ? small_ids : big_ids).push_back(g);
-    std::stable_sort(small_ids.begin(), small_ids.end(), [&](int a, int b) { return n[a] > n[b]; });
-    if (!small_ids.empty()) {
-        const int ns = (int)small_ids.size();
-        const int cap = std::max(ns, 256);
-        if ((st = ensure(c, w.tasks, sizeof(rd::SmallTask) * (size_t)cap))) return st;
+    // graphs with n <= 512: one persistent launch, longest first; larger ones
+    // one after another with the blocked plan
+    std::vector<int> ids, big_ids;
+    for (int g = 0; g < count; ++g) (n[g] <= kBatchMaxN ? ids : big_ids).push_back(g);
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return n[a] > n[b]; });
+    if (!ids.empty()) {
+        const int nb = (int)ids.size();
+        const int cap = std::max(nb, 256);
+        if ((st = ensure(c, w.tasks, sizeof(rd::BatchTask) * (size_t)cap))) return st;
         if ((st = ensure(c, w.infos, sizeof(rdist_info) * (size_t)cap))) return st;
         if ((st = ensure(c, w.counter, 256))) return st;
-        rd::SmallTask *dtasks = (rd::SmallTask *)w.tasks.p;
-        rdist_info *dinfos = (rdist_info *)w.infos.p;
-        std::vector<rd::SmallTask> tasks(ns);
-        std::vector<double *> ys(ns, nullptr);
+        auto np_of = [&](int g) { return ((n[g] + kB - 1) / kB) * kB; };
+        // matrices: each kept graph gets its own (it becomes the graph's Y);
+        // otherwise one pooled workspace for the medium graphs
+        size_t pool = 0;
+        if (!keep_y)
+            for (int g : ids)
+                if (n[g] > 128) pool += (size_t)np_of(g) * np_of(g);
+        if (pool && (st = ensure(c, w.bpool, pool * 8))) return st;
+        const int grid = std::min(nb, c->num_cu * rd::batched_blocks_per_cu());
+        bool medium = false;
+        for (int g : ids) medium |= n[g] > 128;
+        const int stride = 2 * kB * kBatchMaxN + kB * kB;      // Ut + V + Pt per workgroup
+        if (medium && (st = ensure(c, w.bscratch, (size_t)grid * stride * 8))) return st;
+        std::vector<rd::BatchTask> tasks(nb);
+        std::vector<Buf> ys(nb);
         double flops = 0.0, bytes = 0.0;
-        for (int q = 0; q < ns; ++q) {
-            const int g = small_ids[q];
-            double *Y = nullptr;
-            if (keep_y && (st = dalloc(c, (void **)&Y, (size_t)n[g] * n[g] * 8))) {
-                for (double *y : ys) if (y) (void)hipFree(y);
-                return st;
+        size_t off = 0;
+        rdist_info *dinfos = (rdist_info *)w.infos.p;
+        for (int q = 0; q < nb; ++q) {
+            const int g = ids[q];
+            const int np = np_of(g);
+            double *Mg = nullptr;
+            if (keep_y) {
+                const size_t yb = (size_t)np * np * 8;
+                if ((st = dalloc(c, &ys[q].p, yb))) {
+                    for (Buf &y : ys) release(c, y);
+                    return st;
+                }
+                ys[q].bytes = yb;
+                Mg = (double *)ys[q].p;
+            } else if (n[g] > 128) {
+                Mg = (double *)w.bpool.p + off;
+                off += (size_t)np * np;
             }
-            ys[q] = Y;
-            tasks[q] = rd::SmallTask{A_dev[g], D_dev[g], Y, n[g], n[g], gamma[g], dinfos + q};
+            tasks[q] = rd::BatchTask{A_dev[g], D_dev[g], Mg, nullptr, nullptr, nullptr, n[g], np,
+                                     keep_y ? 1 : 0, 0, gamma[g], dinfos + q};
             flops += 2.0 * n[g] * (double)n[g] * n[g];
             bytes += 3.0 * n[g] * (double)n[g];
         }
-        RD_HIP(hipMemcpyAsync(dtasks, tasks.data(), sizeof(rd::SmallTask) * (size_t)ns, hipMemcpyHostToDevice, s));
-        const int grid = std::min(ns, c->num_cu * 4);
+        RD_HIP(hipMemcpyAsync(w.tasks.p, tasks.data(), sizeof(rd::BatchTask) * (size_t)nb, hipMemcpyHostToDevice, s));
         {
             Timer tm(c, s, RDIST_K_BATCHED, flops, bytes);
-            rd::launch_small_persistent(dtasks, ns, (int *)w.counter.p, grid, s);
+            rd::launch_batched((const rd::BatchTask *)w.tasks.p, nb, (int *)w.counter.p, grid,
+                               (double *)w.bscratch.p, stride, s);
         }
         RD_HIP(hipGetLastError());
-        for (int q = 0; q < ns; ++q) {
-            const int g = small_ids[q];
-            if (keep_y && (st = make_graph(c, n[g], ys[q], n[g], (size_t)n[g] * n[g] * 8, A_dev[g], s, &keep[g])))
-                return st;
+        for (int q = 0; q < nb; ++q) {
+            const int g = ids[q];
+            if (keep_y) {
+                if ((st = make_graph(c, n[g], (double *)ys[q].p, np_of(g), ys[q].bytes, A_dev[g], s, &keep[g])))
+                    return st;
+            }
             if (info) RD_HIP(hipMemcpyAsync(info + g, dinfos + q, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
         }
     }

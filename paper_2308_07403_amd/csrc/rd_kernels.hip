@@ -152,6 +152,27 @@ __global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int
     if (!ok && threadIdx.x == 0) atomicCAS(&info->status, RDIST_OK, RDIST_E_NOT_DD);
 }
 
+// out[k][i] = -src[i][k] for the 128 x (64 * kb64) block src (leading dim ld),
+// 64 x 64 at a time through LDS (lds: at least 64 * 65 doubles).  Ends with a
+// barrier.
+__device__ __forceinline__ void transpose_neg(const double *__restrict__ src, int ld, int kb64,
+                                              double *__restrict__ out, int ldv, double *lds) {
+    double (*t)[65] = reinterpret_cast<double (*)[65]>(lds);
+    for (int bi = 0; bi < 2; ++bi)
+        for (int bk = 0; bk < kb64; ++bk) {
+            for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+                const int r = e >> 6, c = e & 63;     // r: row i, c: column k
+                t[r][c] = src[(size_t)(bi * 64 + r) * ld + bk * 64 + c];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+                const int k = e >> 6, i = e & 63;
+                out[(size_t)(bk * 64 + k) * ldv + bi * 64 + i] = -t[i][k];
+            }
+            __syncthreads();
+        }
+}
+
 // Step with block width b = 128*m whose block starts at tile K0 (tiles are
 // 128 x 128; nt tiles per side).  Pt is P^T (b x b, row-major, ld b).
 // Blocks [0, m*nt): V tile (r, J) = rows 128r.. of P times M_KJ (J outside
@@ -190,22 +211,7 @@ __global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, in
         }
         return;
     }
-    // transpose (and negate) the 128 x b block M_IK through LDS, 64 x 64 at a time
-    double (*t)[65] = reinterpret_cast<double (*)[65]>(lds);
-    const double *src = M + (size_t)I * kTile * ld + (size_t)K0 * kTile;
-    for (int bi = 0; bi < 2; ++bi)
-        for (int bk = 0; bk < 2 * m; ++bk) {
-            for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-                const int r = e >> 6, c = e & 63;     // r: row i, c: column k
-                t[r][c] = src[(size_t)(bi * 64 + r) * ld + bk * 64 + c];
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-                const int k = e >> 6, i = e & 63;
-                out[(size_t)(bk * 64 + k) * ldv + bi * 64 + i] = -t[i][k];
-            }
-            __syncthreads();
-        }
+    transpose_neg(M + (size_t)I * kTile * ld + (size_t)K0 * kTile, ld, 2 * m, out, ldv, lds);
 }
 
 // Tile sets of one update, with [L0, L0 + m) the next block's tile range:
@@ -454,11 +460,198 @@ __global__ __launch_bounds__(TY *TX) void k_small_one(SmallTask t) {
     solve_small<TY, TX, RA, RC>(t, lds_gj, lds_int);
 }
 
-// Persistent form: each workgroup pulls task indices from *counter.
-__global__ __launch_bounds__(256) void k_small_persistent(const SmallTask *__restrict__ tasks, int count,
-                                                          int *counter) {
-    __shared__ double lds_gj[4 * 128];
-    __shared__ int lds_int[128 + 2];
+// One graph with 128 < n <= 512 on one workgroup: blocked Gauss-Jordan with
+// b = 128 on the np x np matrix M in global memory (np = n rounded up to
+// 128; padded rows and columns are identity).  Per block K: the panel inverse
+// in registers, the row tiles V_J = P M_KJ and the negated transposed column
+// tiles on the matrix cores, then every tile updated in place; the readout
+// is fused into the last update.  The phases are separated by workgroup
+// barriers, which make this workgroup's global writes visible to itself.
+// Each phase is its own (not inlined) function so that each gets a register
+// allocation of its own; registers are saved only at the phase boundaries.
+
+// Panel: P = M_KK^{-1}; V_K = P, Pt = P^T.  Returns false on a bad pivot.
+__device__ __noinline__ bool medium_panel(double *M, int np, int K, double *V, double *Pt, double *piv) {
+    RegGJ<16, 16, 8, 8> g;
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    const double *base = M + (size_t)K * kTile * np + (size_t)K * kTile;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) g.m[a][c] = base[(size_t)(ty + 16 * a) * np + tx + 16 * c];
+    const bool ok = g.invert(kTile, piv, ty, tx);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int i = ty + 16 * a, k = tx + 16 * c;
+            V[(size_t)i * np + (size_t)K * kTile + k] = g.m[a][c];
+            Pt[(size_t)k * kTile + i] = g.m[a][c];
+        }
+    __syncthreads();
+    return ok;
+}
+
+// Row tiles V_J = P M_KJ (J != K) and column tiles Ut_I = -(M_IK)^T (+I for I = K).
+__device__ __noinline__ void medium_rowcol(const double *M, int np, int K, const double *Pt, double *Ut, double *V,
+                                           double *lds) {
+    const int nt = np / kTile;
+    for (int J = 0; J < nt; ++J) {
+        if (J == K) continue;
+        TileAcc acc;
+        acc.zero();
+        tile_mma<kTile>(Pt, kTile, M + (size_t)K * kTile * np + (size_t)J * kTile, np, lds, acc);
+        double *out = V + (size_t)J * kTile;
+        tile_for_each(acc, [&](int r, int c, double v) { out[(size_t)r * np + c] = v; });
+    }
+    for (int I = 0; I < nt; ++I) {
+        double *out = Ut + (size_t)I * kTile;
+        if (I == K) {
+            for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+                const int k = e >> 7, i = e & 127;
+                out[(size_t)k * np + i] = (k == i) ? 1.0 : 0.0;
+            }
+        } else {
+            transpose_neg(M + (size_t)I * kTile * np + (size_t)K * kTile, np, 2, out, np, lds);
+        }
+    }
+    __syncthreads();
+}
+
+// Every tile M_IJ <- M~_IJ + Ut_I^T V_J (M~: block row and column K zeroed).
+__device__ __noinline__ void medium_update(double *M, int np, int K, const double *Ut, const double *V,
+                                           double *lds) {
+    const int nt = np / kTile;
+    for (int I = 0; I < nt; ++I)
+        for (int J = 0; J < nt; ++J) {
+            double *tb = M + (size_t)I * kTile * np + (size_t)J * kTile;
+            TileAcc acc;
+            if (I == K || J == K) acc.zero();
+            else tile_load_acc(acc, tb, np);
+            tile_mma<kTile>(Ut + (size_t)I * kTile, np, V + (size_t)J * kTile, np, lds, acc);
+            tile_for_each(acc, [&](int r, int c, double v) { tb[(size_t)r * np + c] = v; });
+        }
+    __syncthreads();
+}
+
+// The last update with the readout: D (n x n) from the final tiles; M keeps Y
+// only when keep is set.  Readout counters are added to red[0..4] (LDS).
+__device__ __noinline__ void medium_update_last(double *M, int np, int n, int K, const double *Ut, const double *V,
+                                                double *lds, int16_t *D, int keep, double lg,
+                                                unsigned long long *red) {
+    const int nt = np / kTile;
+    Counts cnt;
+    for (int I = 0; I < nt; ++I)
+        for (int J = 0; J < nt; ++J) {
+            double *tb = M + (size_t)I * kTile * np + (size_t)J * kTile;
+            TileAcc acc;
+            if (I == K || J == K) acc.zero();
+            else tile_load_acc(acc, tb, np);
+            tile_mma<kTile>(Ut + (size_t)I * kTile, np, V + (size_t)J * kTile, np, lds, acc);
+            tile_for_each(acc, [&](int r, int c, double y) {
+                if (keep) tb[(size_t)r * np + c] = y;
+                const int gi = I * kTile + r, gj = J * kTile + c;
+                if (gi < n && gj < n) D[(size_t)gi * n + gj] = rd_encode(y, lg, cnt);
+            });
+        }
+    unsigned long long v[5] = {wave_sum_u64(cnt.unreachable), wave_sum_u64(cnt.subnormal),
+                               wave_sum_u64(cnt.saturated), wave_sum_u64(cnt.ambiguous),
+                               wave_sum_u64(cnt.negative)};
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 5; ++q)
+            if (v[q]) atomicAdd(&red[q], v[q]);
+    __syncthreads();
+}
+
+// Ingest of one graph: out-degrees, validation, Delta, gain, gate; M = I - gamma A.
+__device__ __noinline__ int medium_ingest(const uint8_t *A, int n, int np, double gamma_arg, double *M, int *ints,
+                                          int *delta_out, double *gamma_out) {
+    int *colsum = ints;            // np
+    int *flags = ints + 512;       // [0] bad, [1] delta
+    for (int j = threadIdx.x; j < np; j += 256) colsum[j] = 0;
+    if (threadIdx.x == 0) { flags[0] = 0; flags[1] = 0; }
+    __syncthreads();
+    int bad = 0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        int sum = 0;
+        for (int i = 0; i < n; ++i) {
+            const int a = A[(size_t)i * n + j];
+            sum += a;
+            bad |= (a > 1) | ((i == j) & (a != 0));
+        }
+        colsum[j] = sum;
+    }
+    if (bad) atomicOr(&flags[0], 1);
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += 256) atomicMax(&flags[1], colsum[j]);
+    __syncthreads();
+    const int delta = flags[1];
+    const double gamma = gamma_arg > 0.0 ? gamma_arg : (delta > 0 ? (-gamma_arg) / (double)delta : -gamma_arg);
+    int st = RDIST_OK;
+    if (flags[0]) st = RDIST_E_ADJ;
+    else if (!(gamma > 0.0) || !(gamma < 1.0)) st = RDIST_E_ARG;
+    else if (!(gamma * (double)delta < 1.0)) st = RDIST_E_NOT_DD;
+    *delta_out = delta;
+    *gamma_out = gamma;
+    if (st == RDIST_OK) {
+        for (int e = threadIdx.x; e < np * np; e += 256) {
+            const int i = e / np, j = e - (e / np) * np;
+            double x = (i == j) ? 1.0 : 0.0;
+            if (i < n && j < n) x -= gamma * (double)A[(size_t)i * n + j];
+            M[e] = x;
+        }
+    }
+    __syncthreads();
+    return st;
+}
+
+__device__ __forceinline__ void solve_medium(const BatchTask &t, double *lds, double *piv, int *ints,
+                                             unsigned long long *red) {
+    const int n = t.n, np = t.np, nt = np / kTile;
+    int delta;
+    double gamma;
+    int st = medium_ingest(t.A, n, np, t.gamma_arg, t.M, ints, &delta, &gamma);
+    bool ok = st == RDIST_OK;
+    if (ok) {
+        if (threadIdx.x < 5) red[threadIdx.x] = 0;
+        __syncthreads();
+        for (int K = 0; K < nt && ok; ++K) {
+            ok = medium_panel(t.M, np, K, t.V, t.Pt, piv);
+            medium_rowcol(t.M, np, K, t.Pt, t.Ut, t.V, lds);
+            if (K + 1 < nt) medium_update(t.M, np, K, t.Ut, t.V, lds);
+            else medium_update_last(t.M, np, n, K, t.Ut, t.V, lds, t.D, t.keep, log(gamma), red);
+        }
+        if (!ok) st = RDIST_E_NOT_DD;
+    }
+    if (st != RDIST_OK)
+        for (int e = threadIdx.x; e < n * n; e += 256) t.D[e] = kUnreachable;
+    if (threadIdx.x == 0) {
+        rdist_info *info = t.info;
+        info->status = st;
+        info->delta = delta;
+        info->gamma = gamma;
+        info->n_unreachable = st == RDIST_OK ? (int64_t)red[0] : 0;
+        info->n_subnormal = st == RDIST_OK ? (int64_t)red[1] : 0;
+        info->n_saturated = st == RDIST_OK ? (int64_t)red[2] : 0;
+        info->n_ambiguous = st == RDIST_OK ? (int64_t)red[3] : 0;
+        info->n_negative = st == RDIST_OK ? (int64_t)red[4] : 0;
+        info->n_uncertified = 0;
+        info->fallback_fraction = 0.0;
+    }
+    __syncthreads();
+}
+
+// Persistent batched solve: each workgroup pulls task indices from *counter
+// (tasks are sorted by decreasing n, longest first) and solves the graph
+// alone: register-resident Gauss-Jordan for n <= 128, the in-workgroup
+// blocked solver for n <= 512.  Every workgroup exits once the counter
+// passes the task count.
+__global__ __launch_bounds__(256) void k_batched(const BatchTask *__restrict__ tasks, int count, int *counter,
+                                                 double *__restrict__ scratch, int scratch_stride) {
+    __shared__ double lds[kTileLdsDoubles];
+    __shared__ double piv[4 * kTile];
+    __shared__ int ints[512 + 2];
+    __shared__ unsigned long long red[8];
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -466,9 +659,20 @@ __global__ __launch_bounds__(256) void k_small_persistent(const SmallTask *__res
         const int idx = next;
         __syncthreads();
         if (idx >= count) break;
-        const SmallTask t = tasks[idx];
-        if (t.n <= 64) solve_small<16, 16, 4, 4>(t, lds_gj, lds_int);
-        else solve_small<16, 16, 8, 8>(t, lds_gj, lds_int);
+        BatchTask t = tasks[idx];
+        if (t.n <= 64) {
+            SmallTask s{t.A, t.D, t.keep ? t.M : nullptr, t.n, t.np, t.gamma_arg, t.info};
+            solve_small<16, 16, 4, 4>(s, piv, ints);
+        } else if (t.n <= 128) {
+            SmallTask s{t.A, t.D, t.keep ? t.M : nullptr, t.n, t.np, t.gamma_arg, t.info};
+            solve_small<16, 16, 8, 8>(s, piv, ints);
+        } else {
+            double *sc = scratch + (size_t)blockIdx.x * scratch_stride;
+            t.Ut = sc;
+            t.V = sc + (size_t)kTile * t.np;
+            t.Pt = sc + (size_t)2 * kTile * t.np;
+            solve_medium(t, lds, piv, ints, red);
+        }
     }
 }
 
@@ -635,9 +839,19 @@ void launch_small_one(const SmallTask &t, hipStream_t s) {
         hipLaunchKernelGGL((k_small_one<16, 16, 8, 8>), dim3(1), dim3(256), 0, s, t);
 }
 
-void launch_small_persistent(const SmallTask *tasks, int count, int *counter, int grid, hipStream_t s) {
+void launch_batched(const BatchTask *tasks, int count, int *counter, int grid, double *scratch, int scratch_stride,
+                    hipStream_t s) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, counter, 1);
-    hipLaunchKernelGGL(k_small_persistent, dim3(grid), dim3(256), 0, s, tasks, count, counter);
+    hipLaunchKernelGGL(k_batched, dim3(grid), dim3(256), 0, s, tasks, count, counter, scratch, scratch_stride);
+}
+
+int batched_blocks_per_cu() {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)k_batched, 256, 0) != hipSuccess || b < 1) {
+        (void)hipGetLastError();
+        b = 1;
+    }
+    return b;
 }
 
 void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s) {

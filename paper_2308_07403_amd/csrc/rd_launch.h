@@ -21,6 +21,22 @@ struct SmallTask {
     rdist_info *info;      // device
 };
 
+// One graph of a batched solve (n <= 512).  M: np x np workspace (np = n
+// rounded up to 128; for n <= 128 it receives Y with ld np when keep is set).
+// Ut, V, Pt: the solving workgroup's scratch, filled in by the kernel.
+struct BatchTask {
+    const uint8_t *A;
+    int16_t *D;
+    double *M;
+    double *Ut, *V, *Pt;
+    int32_t n;
+    int32_t np;
+    int32_t keep;
+    int32_t pad;
+    double gamma_arg;
+    rdist_info *info;
+};
+
 void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
                    int32_t *bad, rdist_info *info, hipStream_t s);
 void launch_fill_sentinel(int16_t *D, int n, const rdist_info *info, hipStream_t s);
@@ -38,7 +54,9 @@ void launch_panel_finish(const double *S, int lds, int b, int K0, double *Pt, do
 void launch_epilogue(const double *Y, int n, int ld, int16_t *D, rdist_info *info, hipStream_t s);
 void launch_info_set(rdist_info *info, double gamma, hipStream_t s);
 void launch_small_one(const SmallTask &t, hipStream_t s);
-void launch_small_persistent(const SmallTask *tasks, int count, int *counter, int grid, hipStream_t s);
+void launch_batched(const BatchTask *tasks, int count, int *counter, int grid, double *scratch, int scratch_stride,
+                    hipStream_t s);
+int batched_blocks_per_cu();
 void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s);
 void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
                      const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s);

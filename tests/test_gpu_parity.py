@@ -289,6 +289,94 @@ def test_batched_mixed_sizes_and_refusal(ctx):
         assert np.array_equal(Ds[k].cpu().numpy(), sol.D)
 
 
+def check_batch(As, gam, Ds, info, graphs=None, label="batched"):
+    for k, A in enumerate(As):
+        g = gam[k] if isinstance(gam, (list, tuple)) else gam
+        sol = oracle.solve(A, g)
+        inf = info.get(k)
+        assert inf.status == sol.status, f"{label} graph {k} n={A.shape[0]}"
+        Dh = Ds[k].cpu().numpy()
+        if sol.status != oracle.OK:
+            assert np.all(Dh == R.RDIST_UNREACHABLE)
+            continue
+        assert inf.delta == sol.delta and inf.gamma == sol.gamma
+        bad = Dh != sol.D
+        assert not bad.any(), f"{label} graph {k} n={A.shape[0]}: {int(bad.sum())} D mismatches"
+        assert inf.n_unreachable == sol.unreachable and inf.n_saturated == sol.saturated
+        assert inf.n_subnormal == sol.subnormal and inf.n_negative == 0
+        if graphs is not None and graphs[k] is not None:
+            Yh = graphs[k].y().cpu().numpy()
+            assert np.array_equal(Yh == 0.0, sol.Y == 0.0)
+            nz = sol.Y >= DBL_MIN
+            if nz.any():
+                assert np.max(np.abs(Yh[nz] - sol.Y[nz]) / sol.Y[nz]) <= Y_TOL
+
+
+def test_batched_medium_graphs(ctx):
+    """128 < n <= 512: the blocked solver inside one workgroup per graph."""
+    specs = [s for s in gg.c3_specs(512, batch_index=3) if s.n > 128][:40]
+    As = [s.build() for s in specs]
+    note(f"[parity] batched medium count={len(As)} n={[A.shape[0] for A in As]}")
+    Ds, info, graphs = ctx.solve_batched([dev(A) for A in As], -0.5, keep=True)
+    check_batch(As, -0.5, Ds, info, graphs, "medium")
+    for g in graphs:
+        g.release()
+
+
+@pytest.mark.parametrize("n", [129, 255, 256, 257, 383, 384, 511, 512])
+def test_batched_medium_tile_edges(ctx, n):
+    A = gg.erdos_renyi(n, 6.0 / n, gg.rng_for("parity", 8000 + n))
+    note(f"[parity] batched medium edge n={n}")
+    Ds, info, graphs = ctx.solve_batched([dev(A)], -0.5, keep=True)
+    check_batch([A], -0.5, Ds, info, graphs, f"n={n}")
+    graphs[0].release()
+
+
+def test_batched_medium_refusals(ctx):
+    good = gg.erdos_renyi(300, 0.03, gg.rng_for("parity", 8100))
+    bad_adj = good.copy()
+    bad_adj[5, 7] = 2
+    loop = good.copy()
+    loop[9, 9] = 1
+    As = [good, bad_adj, loop, good, gg.out_star(400)]
+    gam = [-0.5, -0.5, -0.5, 0.999, 0.25]
+    Ds, info, _ = ctx.solve_batched([dev(A) for A in As], gam)
+    assert [info.get(k).status for k in range(5)] == [oracle.solve(A, g).status for A, g in zip(As, gam)]
+    check_batch(As, gam, Ds, info, None, "refusals")
+
+
+def test_batched_c3_full_batch_sampled(ctx):
+    """The 1024-graph batch in one launch; every 16th graph against the oracle."""
+    specs = gg.c3_specs(1024, batch_index=0)
+    As = [s.build() for s in specs]
+    note(f"[parity] C3 batch count={len(As)}")
+    Ds, info, _ = ctx.solve_batched([dev(A) for A in As], -0.5)
+    idx = list(range(0, 1024, 16))
+    check_batch([As[k] for k in idx], -0.5, [Ds[k] for k in idx], _Sub(info, idx), None, "c3")
+
+
+class _Sub:
+    def __init__(self, info, idx):
+        self.info, self.idx = info, idx
+
+    def get(self, k):
+        return self.info.get(self.idx[k])
+
+
+def test_batched_deterministic_and_order_free(ctx):
+    """The same graph gives the same bits alone, in a batch, and in another batch order."""
+    specs = gg.c3_specs(64, batch_index=11)
+    As = [s.build() for s in specs]
+    Ds1, _, _ = ctx.solve_batched([dev(A) for A in As], -0.5)
+    perm = list(reversed(range(len(As))))
+    Ds2, _, _ = ctx.solve_batched([dev(As[k]) for k in perm], -0.5)
+    for k, A in enumerate(As):
+        alone, _, _ = ctx.solve_batched([dev(A)], -0.5)
+        a = Ds1[k].cpu().numpy()
+        assert np.array_equal(a, Ds2[perm.index(k)].cpu().numpy())
+        assert np.array_equal(a, alone[0].cpu().numpy())
+
+
 # ---------------------------------------------------------------------------
 # Synchronous errors and the budget
 # ---------------------------------------------------------------------------
