@@ -245,12 +245,19 @@ def bench_c3(args, torch, R, gg):
     Ds = [torch.empty((a.shape[0],) * 2, dtype=torch.int16, device="cuda") for a in As]
     ns = np.array([a.shape[0] for a in A_np], dtype=np.float64)
     flops = float(np.sum(2.0 * ns ** 3))
-    ctx = R.Context(0)
+    import tempfile
+    tile_cache = os.path.join(tempfile.mkdtemp(prefix="rdist_"), "tiles.json")
+    ctx = R.Context(0, tile_cache=tile_cache)
     stream = torch.cuda.current_stream()
     info = R.PinnedInfo(len(As))
-    log(f"[bench] c3 {len(As)} graphs: warmup {args.warmup}")
+    batch = R.Batch(As, -0.5, Ds)
+    log(f"[bench] c3 {len(As)} graphs: autotune + warmup {args.warmup}")
+    t0 = time.perf_counter()
+    ctx.solve_batched(batch, info=info, stream=stream)        # tunes, then builds and captures the plan
+    tune_s = time.perf_counter() - t0
+    tuned = json.load(open(tile_cache))["batched"]
     for _ in range(args.warmup):
-        ctx.solve_batched(As, -0.5, Ds=Ds, info=info, stream=stream, sync=False)
+        ctx.solve_batched(batch, info=info, stream=stream, sync=False)
     torch.cuda.synchronize()
     bad = [k for k in range(len(As)) if info.get(k).status != 0]
     assert not bad, f"graphs {bad[:5]} refused"
@@ -261,13 +268,22 @@ def bench_c3(args, torch, R, gg):
     t0 = time.perf_counter()
     for k in range(args.steps):
         evs[k][0].record(stream)
-        ctx.solve_batched(As, -0.5, Ds=Ds, info=info, stream=stream, sync=False)
+        ctx.solve_batched(batch, info=info, stream=stream, sync=False)
         evs[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = [a.elapsed_time(b) for a, b in evs]
     bk = ctx.kernel_stats(R.RDIST_K_BATCHED)
     ctx.set_timing(False)
+    # eager launches of the same plan (no HIP graph), for comparison
+    for _ in range(2):
+        ctx.solve_batched(batch, flags=R.RDIST_NO_GRAPH, info=info, stream=stream, sync=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.solve_batched(batch, flags=R.RDIST_NO_GRAPH, info=info, stream=stream, sync=False)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     ctx.close()
     ms = wall * 1000.0 / args.steps
     avg_ms = bk["total_ms"] / max(bk["launches"], 1)
@@ -279,7 +295,9 @@ def bench_c3(args, torch, R, gg):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "C3: 1024 graphs per step, n log-uniform in [32, 512], ER(p~U[0.05,0.2]) / "
                                "torus lattice / RGG, gamma=0.5/max_out_degree, one persistent launch",
-                   "graphs": len(As), "sum_n3": float(np.sum(ns ** 3))},
+                   "graphs": len(As), "sum_n3": float(np.sum(ns ** 3)), "tuning": tuned[0],
+                   "autotune_s": tune_s},
+        "eager_ms_per_step": eager_ms,
         "eff_tflops": flops / (ms * 1e-3) / 1e12,
         "p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
         "roofline": {"bound": "mfma", "kernel": "k_batched (persistent: one workgroup per graph)",

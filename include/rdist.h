@@ -81,6 +81,7 @@ typedef enum rdist_status {
 #define RDIST_UNFUSED_EPILOGUE 0x400u /* run the readout as a standalone pass over Y */
 #define RDIST_BLOCK_128 0x800u      /* blocked plan: force block width b = 128 */
 #define RDIST_BLOCK_256 0x1000u     /* blocked plan: force block width b = 256 (default for n > 1024) */
+#define RDIST_NO_GRAPH 0x2000u      /* rdist_solve_batched: launch eagerly, no HIP graph capture or replay */
 
 /* ---- flags for rdist_create ---- */
 #define RDIST_THREADSAFE 0x1u
@@ -131,13 +132,23 @@ rdist_status rdist_solve(rdist_ctx ctx, const uint8_t *A_dev, int32_t n, double 
                          rdist_info *info, void *stream);
 
 /*
- * Many independent graphs in one persistent launch (graphs with n <= 512;
- * larger ones are solved one after another with the blocked plan).
+ * Many independent graphs per call (Sec. 3, Eq. of the inverse, applied to
+ * each graph on its own).  Graphs with n <= T (T = 128 unless tuned) go to
+ * one persistent launch in which each workgroup solves whole graphs, longest
+ * first; graphs with T < n <= 512 take the blocked steps together, one
+ * launch per step phase for the whole set; larger graphs are solved one after
+ * another with the blocked plan.
  * Host arrays of length `count`: n[g], A_dev[g], gamma[g], D_dev[g]
- * (device pointers), info[g] (nullable array).  flags as rdist_solve
- * (RDIST_KEEP_Y fills keep[g]).  Each graph's status is in info[g].status.
- * The launch is captured into a HIP graph keyed by the batch's pointer and
- * size lists and replayed on later identical calls.
+ * (device pointers), info[g] (nullable array, preferably pinned).  flags as
+ * rdist_solve plus RDIST_NO_GRAPH (RDIST_KEEP_Y fills keep[g]).  Each
+ * graph's status is in info[g].status.
+ * Without RDIST_KEEP_Y / RDIST_NO_GRAPH the launch sequence is captured into
+ * a HIP graph keyed by (stream, flags, n[], A_dev[], gamma[], D_dev[]) and
+ * replayed on later identical calls; the context keeps the last 4 such plans
+ * and their device buffers (about n^2 + 256 n doubles per graph).  With a
+ * tile cache file (rdist_create), the first batch of each size class is
+ * first timed under every candidate T and persistent grid (the call then
+ * blocks until those trial runs end) and the fastest is recorded in the file.
  */
 rdist_status rdist_solve_batched(rdist_ctx ctx, int32_t count, const int32_t *n,
                                  const uint8_t *const *A_dev, const double *gamma,

@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 import sys
 import time
 
@@ -14,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librdist.so")
-SOURCES = ["rd_engine.hip", "rd_kernels.hip"]
+SOURCES = ["rd_engine.hip", "rd_batch.hip", "rd_kernels.hip"]
+OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -32,15 +34,33 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = True) -> str:
-    t0 = time.time()
-    tmp = LIB + f".tmp{os.getpid()}"
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *srcs, "-o", tmp]
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed to build librdist.so")
+        sys.stderr.write(" ".join(cmd) + "\n" + res.stdout + res.stderr)
+    return res.returncode
+
+
+def build(verbose: bool = True) -> str:
+    """Compiles every source to an object (in parallel), then links the library."""
+    t0 = time.time()
+    os.makedirs(OBJDIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include")]
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    objs, cmds = [], []
+    for s in SOURCES:
+        obj = os.path.join(OBJDIR, s + f".{os.getpid()}.o")
+        objs.append(obj)
+        cmds.append([hipcc(), *flags, *inc, "-c", os.path.join(CSRC, s), "-o", obj])
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        rcs = list(ex.map(_run, cmds))
+    if any(rcs):
+        raise RuntimeError("hipcc failed to compile the engine")
+    tmp = LIB + f".tmp{os.getpid()}"
+    if _run([hipcc(), *HIPCC_FLAGS, *objs, "-o", tmp]):
+        raise RuntimeError("hipcc failed to link librdist.so")
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, LIB)
     if verbose:
         print(f"[build] {LIB} ({time.time() - t0:.1f}s)")

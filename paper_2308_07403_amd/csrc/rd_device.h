@@ -34,18 +34,22 @@ struct Counts {
     unsigned long long unreachable = 0, subnormal = 0, saturated = 0, ambiguous = 0, negative = 0;
 };
 
-// D for one entry.  lg = log(gamma) < 0.
-__device__ __forceinline__ int16_t rd_encode(double y, double lg, Counts &c) {
+// D for one entry.  il = 1 / log(gamma) < 0: R = log(Y) / log(gamma) is
+// formed as a product with the reciprocal (within an ulp or two of the
+// quotient; the eta shift keeps exact integers R on the right side).
+__device__ __forceinline__ int16_t rd_encode(double y, double il, Counts &c) {
     if (y == 0.0) { ++c.unreachable; return kUnreachable; }
     if (!(y > 0.0)) { ++c.negative; return kUnreachable; }
     if (y < kDblMin) ++c.subnormal;
-    double t = log(y) / lg - kEta;
+    double t = log(y) * il - kEta;
     double d = ceil(t);
     if (fabs(t - rint(t)) < kBeta) ++c.ambiguous;
     if (d > kDMax) { d = kDMax; ++c.saturated; }
     if (d < kDMin) { d = kDMin; ++c.saturated; }
     return (int16_t)(int)d;
 }
+
+__device__ __forceinline__ double rd_inv_log(double gamma) { return 1.0 / log(gamma); }
 
 // 1/p from the hardware reciprocal estimate and one Newton step on the
 // residual e = 1 - p*r (fused, so e is exact): |error| of order 1 ulp,

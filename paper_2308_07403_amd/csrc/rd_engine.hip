@@ -19,88 +19,13 @@
 #include <vector>
 
 #include "../../include/rdist.h"
+#include "rd_engine.h"
 #include "rd_launch.h"
 
-namespace {
+namespace rd {
+namespace eng {
 
 thread_local std::string g_last_error;
-
-rdist_status fail(rdist_status s, const std::string &msg) {
-    g_last_error = msg;
-    return s;
-}
-
-#define RD_HIP(expr)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return fail(RDIST_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr int kB = 128;   // block size of the blocked solver = tile size
-constexpr int kBatchMaxN = 512;   // largest graph the persistent batched kernel solves
-
-// A device allocation with its size, so the budget can be returned exactly.
-struct Buf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-struct Workspace {
-    int np_cap = 0;      // blocked plan: padded order the buffers below hold
-    Buf M;               // np x np
-    Buf Ut[2], V[2];     // 256 x np each (double-buffered by step parity)
-    Buf Pt[2];           // 256 x 256
-    Buf Ut2, V2, Pt2;    // scratch of the 256-block inverse (128x256, 128x256, 128^2)
-    Buf small;           // out-degrees (n_cap + 1), flag, device info
-    int n_cap = 0;
-    Buf tasks, infos, counter;   // batched plan
-    Buf bpool, bscratch;         // batched plan: medium graphs' matrices, per-workgroup scratch
-    hipStream_t aux = nullptr;   // lookahead stream (default priority)
-    hipEvent_t ev_er = nullptr, ev_rest = nullptr, ev_panel = nullptr;
-    double *m() const { return (double *)M.p; }
-    int32_t *outdeg() const { return (int32_t *)small.p; }
-    int32_t *bad() const { return outdeg() + n_cap + 1; }
-    rdist_info *dinfo() const { return (rdist_info *)((char *)small.p + 256 * ((sizeof(int32_t) * (n_cap + 2) + 255) / 256)); }
-};
-
-struct TimedLaunch {
-    hipEvent_t a, b;
-    int which;
-    double flops, bytes;
-};
-
-}  // namespace
-
-struct rdist_graph_s {
-    rdist_ctx ctx = nullptr;
-    double *Y = nullptr;
-    int n = 0, ld = 0;
-    unsigned long long *succ = nullptr;
-    size_t bytes = 0;
-};
-
-struct rdist_ctx_s {
-    int device = 0;
-    size_t budget = 0;
-    size_t in_use = 0;
-    bool threadsafe = false;
-    std::recursive_mutex mu;
-    std::map<hipStream_t, Workspace> ws;
-    std::set<rdist_graph_s *> graphs;
-    bool timing = false;
-    std::vector<TimedLaunch> pending;
-    std::vector<hipEvent_t> event_pool;
-    rdist_kernel_stats stats[RDIST_K_COUNT];
-    int num_cu = 256;
-};
-
-namespace {
-
-struct Guard {
-    rdist_ctx c;
-    explicit Guard(rdist_ctx c_) : c(c_) { if (c->threadsafe) c->mu.lock(); }
-    ~Guard() { if (c->threadsafe) c->mu.unlock(); }
-};
 
 rdist_status dalloc(rdist_ctx c, void **p, size_t bytes) {
     *p = nullptr;
@@ -170,9 +95,18 @@ rdist_status ensure_big(rdist_ctx c, Workspace &w, int np) {
     if ((st = ensure(c, w.Ut2, (size_t)128 * 256 * 8))) return st;
     if ((st = ensure(c, w.V2, (size_t)128 * 256 * 8))) return st;
     if ((st = ensure(c, w.Pt2, (size_t)128 * 128 * 8))) return st;
+    return ensure_aux(w);
+}
+
+// The workspace's auxiliary stream (default priority) and its events.
+rdist_status ensure_aux(Workspace &w) {
     if (!w.aux) {
         if (hipStreamCreateWithFlags(&w.aux, hipStreamNonBlocking) != hipSuccess) {
             w.aux = nullptr;
+            return fail(RDIST_E_HIP, "hipStreamCreateWithFlags failed");
+        }
+        if (hipStreamCreateWithFlags(&w.aux2, hipStreamNonBlocking) != hipSuccess) {
+            w.aux2 = nullptr;
             return fail(RDIST_E_HIP, "hipStreamCreateWithFlags failed");
         }
         if (hipEventCreateWithFlags(&w.ev_er, hipEventDisableTiming) != hipSuccess ||
@@ -194,27 +128,6 @@ hipEvent_t take_event(rdist_ctx c) {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
-
-struct Timer {
-    rdist_ctx c;
-    hipStream_t s;
-    int which;
-    double flops, bytes;
-    hipEvent_t a = nullptr;
-    Timer(rdist_ctx c_, hipStream_t s_, int w, double f, double b) : c(c_), s(s_), which(w), flops(f), bytes(b) {
-        if (c->timing) {
-            a = take_event(c);
-            if (a) (void)hipEventRecord(a, s);
-        }
-    }
-    ~Timer() {
-        if (!a) return;
-        hipEvent_t b2 = take_event(c);
-        if (!b2) return;
-        (void)hipEventRecord(b2, s);
-        c->pending.push_back(TimedLaunch{a, b2, which, flops, bytes});
-    }
-};
 
 void drain_timing(rdist_ctx c) {
     for (auto &t : c->pending) {
@@ -271,7 +184,7 @@ void release_graph_locked(rdist_graph g) {
 
 rdist_status check_flags(uint32_t flags) {
     const uint32_t known = RDIST_MIXED_F32 | RDIST_KEEP_Y | RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED |
-                           RDIST_UNFUSED_EPILOGUE | RDIST_BLOCK_128 | RDIST_BLOCK_256;
+                           RDIST_UNFUSED_EPILOGUE | RDIST_BLOCK_128 | RDIST_BLOCK_256 | RDIST_NO_GRAPH;
     if (flags & ~known) return fail(RDIST_E_ARG, "unknown flag bits");
     if ((flags & RDIST_BLOCK_128) && (flags & RDIST_BLOCK_256)) return fail(RDIST_E_ARG, "two block widths");
     if ((flags & RDIST_PLAN_SMALL) && (flags & RDIST_PLAN_BLOCKED)) return fail(RDIST_E_ARG, "two plan flags");
@@ -442,7 +355,10 @@ rdist_status solve_small(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
     return copy_info(info, w.dinfo(), 1, s);
 }
 
-}  // namespace
+}  // namespace eng
+}  // namespace rd
+
+using namespace rd::eng;
 
 extern "C" {
 
@@ -464,7 +380,6 @@ const char *rdist_status_string(rdist_status s) {
 
 rdist_status rdist_create(rdist_ctx *out, int device, size_t hbm_budget_bytes, const char *tile_cache_path,
                           uint32_t flags) {
-    (void)tile_cache_path;
     if (!out) return fail(RDIST_E_ARG, "out is NULL");
     *out = nullptr;
     if (flags & ~RDIST_THREADSAFE) return fail(RDIST_E_ARG, "unknown create flags");
@@ -479,6 +394,10 @@ rdist_status rdist_create(rdist_ctx *out, int device, size_t hbm_budget_bytes, c
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
     std::memset(c->stats, 0, sizeof(c->stats));
+    if (tile_cache_path && *tile_cache_path) {
+        c->tile_cache_path = tile_cache_path;
+        load_tile_cache(c);
+    }
     *out = c;
     g_last_error.clear();
     return RDIST_OK;
@@ -490,17 +409,20 @@ void rdist_destroy(rdist_ctx c) {
         Guard g(c);
         (void)hipSetDevice(c->device);
         drain_timing(c);
+        destroy_plans(c);
+        if (c->tuned_dirty) save_tile_cache(c);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
         std::vector<rdist_graph_s *> gs(c->graphs.begin(), c->graphs.end());
         for (auto *gr : gs) release_graph_locked(gr);
         for (auto &kv : c->ws) {
             Workspace &w = kv.second;
             for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2,
-                           &w.Pt2, &w.small, &w.tasks, &w.infos, &w.counter, &w.bpool, &w.bscratch})
+                           &w.Pt2, &w.small})
                 release(c, *b);
             for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
                 if (e) (void)hipEventDestroy(e);
             if (w.aux) (void)hipStreamDestroy(w.aux);
+            if (w.aux2) (void)hipStreamDestroy(w.aux2);
         }
     }
     delete c;
@@ -522,101 +444,6 @@ rdist_status rdist_solve(rdist_ctx c, const uint8_t *A_dev, int32_t n, double ga
     const bool small = !(flags & RDIST_PLAN_BLOCKED) && n <= 128;
     if (small) return solve_small(c, A_dev, n, gamma, flags, D_dev, keep, info, s);
     return solve_blocked(c, A_dev, n, gamma, flags, D_dev, keep, info, s);
-}
-
-rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const int32_t *n, const uint8_t *const *A_dev,
-                                 const double *gamma, uint32_t flags, int16_t *const *D_dev, rdist_graph *keep,
-                                 rdist_info *info, void *stream) {
-    if (!c) return fail(RDIST_E_ARG, "ctx is NULL");
-    if (count < 0) return fail(RDIST_E_ARG, "count < 0");
-    if (count == 0) return RDIST_OK;
-    if (!n || !A_dev || !gamma || !D_dev) return fail(RDIST_E_ARG, "NULL array");
-    rdist_status st;
-    if ((st = check_flags(flags))) return st;
-    if (flags & (RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED)) return fail(RDIST_E_ARG, "plan flags are per solve");
-    for (int g = 0; g < count; ++g) {
-        if (n[g] < 1 || n[g] > 65536) return fail(RDIST_E_ARG, "n out of range");
-        if (!A_dev[g] || !D_dev[g]) return fail(RDIST_E_ARG, "NULL graph pointer");
-        if ((st = check_gamma(gamma[g]))) return st;
-    }
-    const bool keep_y = (flags & RDIST_KEEP_Y) && keep;
-    if (keep) for (int g = 0; g < count; ++g) keep[g] = nullptr;
-    Guard gd(c);
-    RD_HIP(hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
-    Workspace &w = c->ws[s];
-    // graphs with n <= 512: one persistent launch, longest first; larger ones
-    // one after another with the blocked plan
-    std::vector<int> ids, big_ids;
-    for (int g = 0; g < count; ++g) (n[g] <= kBatchMaxN ? ids : big_ids).push_back(g);
-    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return n[a] > n[b]; });
-    if (!ids.empty()) {
-        const int nb = (int)ids.size();
-        const int cap = std::max(nb, 256);
-        if ((st = ensure(c, w.tasks, sizeof(rd::BatchTask) * (size_t)cap))) return st;
-        if ((st = ensure(c, w.infos, sizeof(rdist_info) * (size_t)cap))) return st;
-        if ((st = ensure(c, w.counter, 256))) return st;
-        auto np_of = [&](int g) { return ((n[g] + kB - 1) / kB) * kB; };
-        // matrices: each kept graph gets its own (it becomes the graph's Y);
-        // otherwise one pooled workspace for the medium graphs
-        size_t pool = 0;
-        if (!keep_y)
-            for (int g : ids)
-                if (n[g] > 128) pool += (size_t)np_of(g) * np_of(g);
-        if (pool && (st = ensure(c, w.bpool, pool * 8))) return st;
-        const int grid = std::min(nb, c->num_cu * rd::batched_blocks_per_cu());
-        bool medium = false;
-        for (int g : ids) medium |= n[g] > 128;
-        const int stride = 2 * kB * kBatchMaxN + kB * kB;      // Ut + V + Pt per workgroup
-        if (medium && (st = ensure(c, w.bscratch, (size_t)grid * stride * 8))) return st;
-        std::vector<rd::BatchTask> tasks(nb);
-        std::vector<Buf> ys(nb);
-        double flops = 0.0, bytes = 0.0;
-        size_t off = 0;
-        rdist_info *dinfos = (rdist_info *)w.infos.p;
-        for (int q = 0; q < nb; ++q) {
-            const int g = ids[q];
-            const int np = np_of(g);
-            double *Mg = nullptr;
-            if (keep_y) {
-                const size_t yb = (size_t)np * np * 8;
-                if ((st = dalloc(c, &ys[q].p, yb))) {
-                    for (Buf &y : ys) release(c, y);
-                    return st;
-                }
-                ys[q].bytes = yb;
-                Mg = (double *)ys[q].p;
-            } else if (n[g] > 128) {
-                Mg = (double *)w.bpool.p + off;
-                off += (size_t)np * np;
-            }
-            tasks[q] = rd::BatchTask{A_dev[g], D_dev[g], Mg, nullptr, nullptr, nullptr, n[g], np,
-                                     keep_y ? 1 : 0, 0, gamma[g], dinfos + q};
-            flops += 2.0 * n[g] * (double)n[g] * n[g];
-            bytes += 3.0 * n[g] * (double)n[g];
-        }
-        RD_HIP(hipMemcpyAsync(w.tasks.p, tasks.data(), sizeof(rd::BatchTask) * (size_t)nb, hipMemcpyHostToDevice, s));
-        {
-            Timer tm(c, s, RDIST_K_BATCHED, flops, bytes);
-            rd::launch_batched((const rd::BatchTask *)w.tasks.p, nb, (int *)w.counter.p, grid,
-                               (double *)w.bscratch.p, stride, s);
-        }
-        RD_HIP(hipGetLastError());
-        for (int q = 0; q < nb; ++q) {
-            const int g = ids[q];
-            if (keep_y) {
-                if ((st = make_graph(c, n[g], (double *)ys[q].p, np_of(g), ys[q].bytes, A_dev[g], s, &keep[g])))
-                    return st;
-            }
-            if (info) RD_HIP(hipMemcpyAsync(info + g, dinfos + q, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
-        }
-    }
-    for (int g : big_ids) {
-        st = solve_blocked(c, A_dev[g], n[g], gamma[g], flags, D_dev[g], keep ? &keep[g] : nullptr,
-                           info ? info + g : nullptr, s);
-        if (st) return st;
-    }
-    return RDIST_OK;
 }
 
 rdist_status rdist_next_hop(rdist_ctx c, rdist_graph gr, const int32_t *cur_dev, const int32_t *goal_dev, int32_t q,

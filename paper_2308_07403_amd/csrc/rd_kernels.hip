@@ -114,12 +114,9 @@ __global__ __launch_bounds__(256) void k_fill_sentinel(int16_t *D, size_t count,
 // consecutive tx hold consecutive columns); P^T goes through a 64 x 65 LDS
 // quadrant.  About 37 KiB of LDS and under 192 VGPRs, so the kernel fits in
 // the slot of one update workgroup and can run beside the update kernels.
-__global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int ld, int K,
-                                               double *__restrict__ Pt, double *__restrict__ V, int ldv,
-                                               rdist_info *info) {
-    if (info->status != RDIST_OK) return;
-    __shared__ double piv[4 * kTile];
-    __shared__ double tq[64][65];
+__device__ __forceinline__ void panel_core(const double *__restrict__ M, int ld, int K, double *__restrict__ Pt,
+                                           double *__restrict__ V, int ldv, rdist_info *info, double *piv,
+                                           double (*tq)[65]) {
     const double *base = M + (size_t)K * kTile * ld + (size_t)K * kTile;
     RegGJ<16, 16, 8, 8> g;
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
@@ -150,6 +147,15 @@ __global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int
             }
         }
     if (!ok && threadIdx.x == 0) atomicCAS(&info->status, RDIST_OK, RDIST_E_NOT_DD);
+}
+
+__global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int ld, int K,
+                                               double *__restrict__ Pt, double *__restrict__ V, int ldv,
+                                               rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ double piv[4 * kTile];
+    __shared__ double tq[64][65];
+    panel_core(M, ld, K, Pt, V, ldv, info, piv, tq);
 }
 
 // out[k][i] = -src[i][k] for the 128 x (64 * kb64) block src (leading dim ld),
@@ -291,7 +297,7 @@ __global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int l
     if (!FUSED) {
         tile_for_each(acc, [&](int r, int c, double v) { base[(size_t)r * ld + c] = v; });
     } else {
-        const double lg = log(info->gamma);
+        const double lg = rd_inv_log(info->gamma);
         Counts cnt;
         tile_for_each(acc, [&](int r, int c, double y) {
             if (keep_y) base[(size_t)r * ld + c] = y;
@@ -328,7 +334,7 @@ __global__ __launch_bounds__(256) void k_panel_finish(const double *__restrict__
 __global__ __launch_bounds__(256) void k_epilogue(const double *__restrict__ Y, int n, int ld,
                                                   int16_t *__restrict__ D, rdist_info *info) {
     if (info->status != RDIST_OK) return;
-    const double lg = log(info->gamma);
+    const double lg = rd_inv_log(info->gamma);
     Counts cnt;
     const size_t total = (size_t)n * n;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
@@ -409,7 +415,7 @@ __device__ __forceinline__ void solve_small(const SmallTask &t, double *lds_gj, 
         if (!ok) st = RDIST_E_NOT_DD;
     }
     if (st == RDIST_OK) {
-        const double lg = log(gamma);
+        const double lg = rd_inv_log(gamma);
 #pragma unroll
         for (int a = 0; a < RA; ++a)
 #pragma unroll
@@ -563,6 +569,60 @@ __device__ __noinline__ void medium_update_last(double *M, int np, int n, int K,
     __syncthreads();
 }
 
+// Column sums (out-degrees) of the n x n byte matrix A (n <= 512) added into
+// colsum (LDS, zeroed by the caller), and *bad set when an entry is not 0/1
+// or the diagonal is not zero.  A is scanned flat, four bytes per load and
+// four loads in flight per thread; only nonzero bytes cost more (sparse
+// graphs: most words are zero).
+__device__ __forceinline__ void adj_colsum(const uint8_t *__restrict__ A, int n, int *colsum, int *bad_flag) {
+    const unsigned total = (unsigned)n * (unsigned)n;
+    const unsigned un = (unsigned)n;
+    int bad = 0;
+    // bytes e0 .. e0+3 of the word v; (i, j) of byte e0 advanced without a
+    // division per byte
+    auto add_word = [&](unsigned e0, uint32_t v) {
+        unsigned i = e0 / un, j = e0 - i * un;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const unsigned byte = (v >> (8 * b)) & 0xFFu;
+            if (byte) {
+                bad |= (byte > 1u) | (i == j);
+                atomicAdd(&colsum[j], (int)byte);
+            }
+            if (++j == un) { j = 0; ++i; }
+        }
+    };
+    unsigned done = 0;
+    if ((reinterpret_cast<uintptr_t>(A) & 15) == 0) {
+        // 16 bytes per load, 4 loads in flight per thread
+        const uint4 *W = reinterpret_cast<const uint4 *>(A);
+        const unsigned nq = total >> 4;
+        for (unsigned q0 = threadIdx.x; q0 < nq; q0 += 4 * 256) {
+            uint4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = q0 + u * 256 < nq ? W[q0 + u * 256] : uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const unsigned e0 = 16u * (q0 + u * 256);
+                if (v[u].x) add_word(e0, v[u].x);
+                if (v[u].y) add_word(e0 + 4, v[u].y);
+                if (v[u].z) add_word(e0 + 8, v[u].z);
+                if (v[u].w) add_word(e0 + 12, v[u].w);
+            }
+        }
+        done = nq << 4;
+    }
+    for (unsigned e = done + threadIdx.x; e < total; e += 256) {
+        const unsigned byte = A[e];
+        if (byte) {
+            const unsigned i = e / un, j = e - i * un;
+            bad |= (byte > 1u) | (i == j);
+            atomicAdd(&colsum[j], (int)byte);
+        }
+    }
+    if (bad) atomicOr(bad_flag, 1);
+}
+
 // Ingest of one graph: out-degrees, validation, Delta, gain, gate; M = I - gamma A.
 __device__ __noinline__ int medium_ingest(const uint8_t *A, int n, int np, double gamma_arg, double *M, int *ints,
                                           int *delta_out, double *gamma_out) {
@@ -571,19 +631,11 @@ __device__ __noinline__ int medium_ingest(const uint8_t *A, int n, int np, doubl
     for (int j = threadIdx.x; j < np; j += 256) colsum[j] = 0;
     if (threadIdx.x == 0) { flags[0] = 0; flags[1] = 0; }
     __syncthreads();
-    int bad = 0;
-    for (int j = threadIdx.x; j < n; j += 256) {
-        int sum = 0;
-        for (int i = 0; i < n; ++i) {
-            const int a = A[(size_t)i * n + j];
-            sum += a;
-            bad |= (a > 1) | ((i == j) & (a != 0));
-        }
-        colsum[j] = sum;
-    }
-    if (bad) atomicOr(&flags[0], 1);
+    adj_colsum(A, n, colsum, &flags[0]);
     __syncthreads();
-    for (int j = threadIdx.x; j < n; j += 256) atomicMax(&flags[1], colsum[j]);
+    int m = 0;
+    for (int j = threadIdx.x; j < n; j += 256) m = max(m, colsum[j]);
+    atomicMax(&flags[1], m);
     __syncthreads();
     const int delta = flags[1];
     const double gamma = gamma_arg > 0.0 ? gamma_arg : (delta > 0 ? (-gamma_arg) / (double)delta : -gamma_arg);
@@ -594,11 +646,17 @@ __device__ __noinline__ int medium_ingest(const uint8_t *A, int n, int np, doubl
     *delta_out = delta;
     *gamma_out = gamma;
     if (st == RDIST_OK) {
-        for (int e = threadIdx.x; e < np * np; e += 256) {
-            const int i = e / np, j = e - (e / np) * np;
-            double x = (i == j) ? 1.0 : 0.0;
-            if (i < n && j < n) x -= gamma * (double)A[(size_t)i * n + j];
-            M[e] = x;
+        const int half = np >> 1;
+        for (int e = threadIdx.x; e < np * half; e += 256) {
+            const int i = e / half, j = (e - (e / half) * half) * 2;
+            double v[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                double x = (i == j + q) ? 1.0 : 0.0;
+                if (i < n && j + q < n) x -= gamma * (double)A[(size_t)i * n + j + q];
+                v[q] = x;
+            }
+            *reinterpret_cast<double2 *>(M + (size_t)i * np + j) = double2{v[0], v[1]};
         }
     }
     __syncthreads();
@@ -619,7 +677,7 @@ __device__ __forceinline__ void solve_medium(const BatchTask &t, double *lds, do
             ok = medium_panel(t.M, np, K, t.V, t.Pt, piv);
             medium_rowcol(t.M, np, K, t.Pt, t.Ut, t.V, lds);
             if (K + 1 < nt) medium_update(t.M, np, K, t.Ut, t.V, lds);
-            else medium_update_last(t.M, np, n, K, t.Ut, t.V, lds, t.D, t.keep, log(gamma), red);
+            else medium_update_last(t.M, np, n, K, t.Ut, t.V, lds, t.D, t.keep, rd_inv_log(gamma), red);
         }
         if (!ok) st = RDIST_E_NOT_DD;
     }
@@ -646,7 +704,7 @@ __device__ __forceinline__ void solve_medium(const BatchTask &t, double *lds, do
 // alone: register-resident Gauss-Jordan for n <= 128, the in-workgroup
 // blocked solver for n <= 512.  Every workgroup exits once the counter
 // passes the task count.
-__global__ __launch_bounds__(256) void k_batched(const BatchTask *__restrict__ tasks, int count, int *counter,
+__global__ __launch_bounds__(256, 2) void k_batched(const BatchTask *__restrict__ tasks, int count, int *counter,
                                                  double *__restrict__ scratch, int scratch_stride) {
     __shared__ double lds[kTileLdsDoubles];
     __shared__ double piv[4 * kTile];
@@ -673,6 +731,223 @@ __global__ __launch_bounds__(256) void k_batched(const BatchTask *__restrict__ t
             t.Pt = sc + (size_t)2 * kTile * t.np;
             solve_medium(t, lds, piv, ints, red);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level-synchronous batched blocked Gauss-Jordan for 128 < n <= 512: every
+// graph of the batch takes step K in the same launches (panel, row and
+// column tiles, trailing update), so one graph's tiles run on many compute
+// units at once.  Each launch reads its work from a unit list built on the
+// host: unit u = (graph << kLvShift) | item, or -1 for an idle slot.  The
+// host spreads each graph's units over the workgroups of one XCD
+// (workgroup b runs on XCD b % 8) so that its operand slabs share one L2.
+// Step K uses the step buffers of parity K & 1, so step K+1's panel and
+// row/column tiles (on a second stream) never overwrite what step K's update
+// still reads.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool lv_unit(const int *units, int &g, int &item) {
+    const int u = units[blockIdx.x];
+    if (u < 0) return false;
+    g = u >> kLvShift;
+    item = u & ((1 << kLvShift) - 1);
+    return true;
+}
+
+// Ingest and gate, one workgroup per graph: out-degrees from a flat scan of
+// A, then info (status, delta, gamma, zeroed counters).
+__global__ __launch_bounds__(256) void k_lv_ingest(const LevelGraph *__restrict__ gs) {
+    __shared__ int colsum[512];
+    __shared__ int flags[2];
+    const LevelGraph g = gs[blockIdx.x];
+    for (int j = threadIdx.x; j < 512; j += 256) colsum[j] = 0;
+    if (threadIdx.x == 0) { flags[0] = 0; flags[1] = 0; }
+    __syncthreads();
+    adj_colsum(g.A, g.n, colsum, &flags[0]);
+    __syncthreads();
+    int m = 0;
+    for (int j = threadIdx.x; j < g.n; j += 256) m = max(m, colsum[j]);
+    atomicMax(&flags[1], m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int delta = flags[1];
+        const double gamma = g.gamma_arg > 0.0 ? g.gamma_arg
+                                               : (delta > 0 ? (-g.gamma_arg) / (double)delta : -g.gamma_arg);
+        int st = RDIST_OK;
+        if (flags[0]) st = RDIST_E_ADJ;
+        else if (!(gamma > 0.0) || !(gamma < 1.0)) st = RDIST_E_ARG;
+        else if (!(gamma * (double)delta < 1.0)) st = RDIST_E_NOT_DD;
+        rdist_info *info = g.info;
+        info->status = st;
+        info->delta = delta;
+        info->gamma = gamma;
+        info->n_unreachable = info->n_subnormal = info->n_saturated = 0;
+        info->n_ambiguous = info->n_negative = info->n_uncertified = 0;
+        info->fallback_fraction = 0.0;
+    }
+}
+
+// Step 0's inputs from the adjacency: items [0, nt) are the M tiles (0, J)
+// of block row 0 (I - gamma A, identity on the padding), read by the panel
+// and the row tiles; items [nt, 2nt-1) are the column operand blocks
+// Ut_I = -(M_I0)^T for I >= 1, i.e. Ut[k][128 I + i] = gamma A[128 I + i][k]
+// (these entries are off the diagonal).  Step 0's update forms its other
+// starting tiles straight from A.
+__global__ __launch_bounds__(256) void k_lv_build(const LevelGraph *__restrict__ gs, const int *__restrict__ units) {
+    int gi, item;
+    if (!lv_unit(units, gi, item)) return;
+    const LevelGraph g = gs[gi];
+    if (g.info->status != RDIST_OK) return;
+    const double gamma = g.info->gamma;
+    const int nt = g.nt, n = g.n, np = g.np;
+    if (item < nt) {
+        const int J = item;
+        for (int e = threadIdx.x; e < kTile * kTile / 2; e += 256) {
+            const int i = e >> 6, j = J * kTile + (e & 63) * 2;
+            double v[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                double x = (i == j + q) ? 1.0 : 0.0;
+                if (i < n && j + q < n) x -= gamma * (double)g.A[(size_t)i * n + j + q];
+                v[q] = x;
+            }
+            *reinterpret_cast<double2 *>(g.M + (size_t)i * np + j) = double2{v[0], v[1]};
+        }
+        return;
+    }
+    // the 128 x 128 byte block A[128 I + i][k] staged in LDS (rows read
+    // coalesced, padded to 132 bytes), then written transposed
+    __shared__ uint8_t blk[kTile * 132];
+    const int I = item - nt + 1;
+    for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+        const int ii = e >> 7, k = e & 127;
+        const int i = I * kTile + ii;
+        blk[ii * 132 + k] = (i < n && k < n) ? g.A[(size_t)i * n + k] : (uint8_t)0;
+    }
+    __syncthreads();
+    double *out = g.Ut[0] + (size_t)I * kTile;
+    for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+        const int k = e >> 7, ii = e & 127;
+        out[(size_t)k * np + ii] = gamma * (double)blk[ii * 132 + k];
+    }
+}
+
+// Panel of step K (item unused).
+__global__ __launch_bounds__(256) void k_lv_panel(const LevelGraph *__restrict__ gs, const int *__restrict__ units,
+                                                  int K) {
+    int gi, item;
+    if (!lv_unit(units, gi, item)) return;
+    const LevelGraph g = gs[gi];
+    if (g.info->status != RDIST_OK) return;
+    __shared__ double piv[4 * kTile];
+    __shared__ double tq[64][65];
+    const int par = K & 1;
+    panel_core(g.M, g.np, K, g.Pt[par], g.V[par], g.np, g.info, piv, tq);
+}
+
+// Row tiles of step K: items [0, nt-1) are V_J = P M_KJ for the tile
+// columns J != K (the column operand Ut of step K is written by the build for
+// K = 0 and by the edge update of step K-1 otherwise).
+__global__ __launch_bounds__(256) void k_lv_rowcol(const LevelGraph *__restrict__ gs, const int *__restrict__ units,
+                                                   int K) {
+    int gi, item;
+    if (!lv_unit(units, gi, item)) return;
+    const LevelGraph g = gs[gi];
+    if (g.info->status != RDIST_OK) return;
+    __shared__ double lds[kTileLdsDoubles];
+    const int np = g.np, par = K & 1;
+    const int J = item < K ? item : item + 1;
+    TileAcc acc;
+    acc.zero();
+    tile_mma<kTile>(g.Pt[par], kTile, g.M + (size_t)K * kTile * np + (size_t)J * kTile, np, lds, acc);
+    double *out = g.V[par] + (size_t)J * kTile;
+    tile_for_each(acc, [&](int r, int c, double v) { out[(size_t)r * np + c] = v; });
+}
+
+// acc = tile (I, J) of I - gamma A (identity on the padding), in the
+// accumulator layout: step 0's starting value for tiles outside block row
+// and column 0, read from the adjacency bytes instead of a built M.
+__device__ __forceinline__ void tile_acc_from_adj(TileAcc &acc, const uint8_t *__restrict__ A, int n, int I, int J,
+                                                  double gamma) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I * kTile + tile_row(p, r), j = J * kTile + tile_col(q);
+                double x = (i == j) ? 1.0 : 0.0;
+                if (i < n && j < n) x -= gamma * (double)A[(size_t)i * n + j];
+                acc.v[p][q][r] = x;
+            }
+}
+
+// Trailing update of step K over the tiles of `kind`:
+//   kLvEdge  tile row and column L = K + 1 (what step K+1's panel and
+//            row tiles read): items [0, nt) are (L, j), items [nt, 2nt-1)
+//            are (i, L), i != L.  A column tile is not stored to M: it is
+//            written straight into step L's column operand as -(M'_iL)^T;
+//   kLvRest  the other tiles: (nt-1)^2 items skipping row and column L when
+//            L < nt, all nt^2 tiles (item = I nt + J) on the graph's last step.
+// Block row K is V itself (U_K = -I), copied without a product.  On a
+// graph's last step the tile's final value is read out into D (stored to M
+// only with keep); a refused graph gets the sentinel there instead.
+__global__ __launch_bounds__(256, 2) void k_lv_update(const LevelGraph *__restrict__ gs,
+                                                      const int *__restrict__ units, int K, int kind) {
+    int gi, item;
+    if (!lv_unit(units, gi, item)) return;
+    const LevelGraph g = gs[gi];
+    const int np = g.np, nt = g.nt, n = g.n, par = K & 1;
+    const int L = K + 1;
+    const bool last = L == nt;
+    int I, J;
+    if (kind == kLvEdge) {
+        if (item < nt) { I = L; J = item; }
+        else { const int ip = item - nt; I = ip < L ? ip : ip + 1; J = L; }
+    } else if (last) {
+        I = item / nt;
+        J = item - (item / nt) * nt;
+    } else {
+        const int w = nt - 1;
+        const int ip = item / w, jp = item - (item / w) * w;
+        I = ip < L ? ip : ip + 1;
+        J = jp < L ? jp : jp + 1;
+    }
+    if (g.info->status != RDIST_OK) {
+        if (last)
+            for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+                const int gi2 = I * kTile + (e >> 7), gj = J * kTile + (e & 127);
+                if (gi2 < n && gj < n) g.D[(size_t)gi2 * n + gj] = kUnreachable;
+            }
+        return;
+    }
+    __shared__ double lds[kTileLdsDoubles];
+    double *base = g.M + (size_t)I * kTile * np + (size_t)J * kTile;
+    TileAcc acc;
+    if (I == K) {
+        tile_load_acc(acc, g.V[par] + (size_t)J * kTile, np);
+    } else {
+        if (J == K) acc.zero();
+        else if (K == 0) tile_acc_from_adj(acc, g.A, n, I, J, g.info->gamma);
+        else tile_load_acc(acc, base, np);
+        tile_mma<kTile>(g.Ut[par] + (size_t)I * kTile, np, g.V[par] + (size_t)J * kTile, np, lds, acc);
+    }
+    if (kind == kLvEdge && J == L && I != L) {
+        double *out = g.Ut[par ^ 1] + (size_t)I * kTile;     // -(M'_IL)^T, k-major
+        tile_for_each(acc, [&](int r, int c, double v) { out[(size_t)c * np + r] = -v; });
+    } else if (!last) {
+        tile_for_each(acc, [&](int r, int c, double v) { base[(size_t)r * np + c] = v; });
+    } else {
+        const double il = rd_inv_log(g.info->gamma);
+        const int keep = g.keep;
+        Counts cnt;
+        tile_for_each(acc, [&](int r, int c, double y) {
+            if (keep) base[(size_t)r * np + c] = y;
+            const int gi2 = I * kTile + r, gj = J * kTile + c;
+            if (gi2 < n && gj < n) g.D[(size_t)gi2 * n + gj] = rd_encode(y, il, cnt);
+        });
+        flush_counts(g.info, cnt);
     }
 }
 
@@ -852,6 +1127,19 @@ int batched_blocks_per_cu() {
         b = 1;
     }
     return b;
+}
+
+void launch_lv_ingest(const LevelGraph *gs, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_lv_ingest, dim3(count), dim3(256), 0, s, gs);
+}
+
+void launch_lv(int phase, const LevelGraph *gs, const int *units, int grid, int K, hipStream_t s) {
+    switch (phase) {
+        case kLvBuild: hipLaunchKernelGGL(k_lv_build, dim3(grid), dim3(256), 0, s, gs, units); break;
+        case kLvPanel: hipLaunchKernelGGL(k_lv_panel, dim3(grid), dim3(256), 0, s, gs, units, K); break;
+        case kLvRowcol: hipLaunchKernelGGL(k_lv_rowcol, dim3(grid), dim3(256), 0, s, gs, units, K); break;
+        default: hipLaunchKernelGGL(k_lv_update, dim3(grid), dim3(256), 0, s, gs, units, K, phase); break;
+    }
 }
 
 void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s) {

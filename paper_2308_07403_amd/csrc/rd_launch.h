@@ -37,6 +37,23 @@ struct BatchTask {
     rdist_info *info;
 };
 
+// One graph of the level-synchronous batched solver (128 < n <= 512).
+// M: np x np (np = n rounded up to 128, nt = np / 128 tiles per side).
+// Step buffers by step parity: Ut, V 128 x np; Pt 128 x 128.
+// gamma_arg explicit (> 0) or AUTO (< 0).
+struct LevelGraph {
+    const uint8_t *A;
+    int16_t *D;
+    double *M;
+    double *Ut[2], *V[2], *Pt[2];
+    rdist_info *info;
+    int32_t n, np, nt, keep;
+    double gamma_arg;
+};
+constexpr int kLvShift = 6;   // unit = (graph << 6) | item, item < 64
+// Launch phases of the level plan (the last two are update tile sets).
+enum LevelPhase { kLvBuild = 0, kLvPanel = 1, kLvRowcol = 2, kLvEdge = 3, kLvRest = 4 };
+
 void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
                    int32_t *bad, rdist_info *info, hipStream_t s);
 void launch_fill_sentinel(int16_t *D, int n, const rdist_info *info, hipStream_t s);
@@ -57,6 +74,8 @@ void launch_small_one(const SmallTask &t, hipStream_t s);
 void launch_batched(const BatchTask *tasks, int count, int *counter, int grid, double *scratch, int scratch_stride,
                     hipStream_t s);
 int batched_blocks_per_cu();
+void launch_lv_ingest(const LevelGraph *gs, int count, hipStream_t s);
+void launch_lv(int phase, const LevelGraph *gs, const int *units, int grid, int K, hipStream_t s);
 void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s);
 void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
                      const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s);

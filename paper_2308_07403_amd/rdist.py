@@ -40,6 +40,7 @@ RDIST_PLAN_BLOCKED = 0x200
 RDIST_UNFUSED_EPILOGUE = 0x400
 RDIST_BLOCK_128 = 0x800
 RDIST_BLOCK_256 = 0x1000
+RDIST_NO_GRAPH = 0x2000
 RDIST_THREADSAFE = 0x1
 (RDIST_K_UPDATE, RDIST_K_PANEL, RDIST_K_ROWCOL, RDIST_K_INGEST, RDIST_K_EPILOGUE, RDIST_K_SMALL,
  RDIST_K_BATCHED, RDIST_K_NEXTHOP, RDIST_K_CERTIFY, RDIST_K_UPDATE_EDGE, RDIST_K_COUNT) = range(11)
@@ -182,6 +183,28 @@ class Graph:
             self.handle = 0
 
 
+class Batch:
+    """Argument arrays of one batch (sizes, adjacency and output pointers,
+    gains) marshalled once, for repeated rdist_solve_batched calls."""
+
+    def __init__(self, As, gamma, Ds=None):
+        self.As = list(As)
+        self.count = len(self.As)
+        for a in self.As:
+            assert a.is_cuda and a.dtype == torch.uint8 and a.dim() == 2 and a.shape[0] == a.shape[1]
+            assert a.is_contiguous()
+        if Ds is None:
+            Ds = [torch.empty((int(a.shape[0]),) * 2, dtype=torch.int16, device=a.device) for a in self.As]
+        self.Ds = list(Ds)
+        for a, d in zip(self.As, self.Ds):
+            assert d.is_cuda and d.dtype == torch.int16 and d.is_contiguous() and d.numel() == a.shape[0] ** 2
+        gam = gamma if hasattr(gamma, "__len__") else [gamma] * self.count
+        self.ns = (ctypes.c_int32 * self.count)(*[int(a.shape[0]) for a in self.As])
+        self.aptr = (ctypes.c_void_p * self.count)(*[a.data_ptr() for a in self.As])
+        self.dptr = (ctypes.c_void_p * self.count)(*[d.data_ptr() for d in self.Ds])
+        self.gptr = (ctypes.c_double * self.count)(*[float(x) for x in gam])
+
+
 class Context:
     """One engine context on a device (owns workspaces, budget, kept graphs)."""
 
@@ -234,27 +257,22 @@ class Context:
         (stream or torch.cuda.current_stream()).synchronize()
         return D, self.info.get(0).as_dict(), graph
 
-    def solve_batched(self, As, gamma, flags: int = RDIST_F64, Ds=None, keep: bool = False, stream=None,
+    def solve_batched(self, As, gamma=None, flags: int = RDIST_F64, Ds=None, keep: bool = False, stream=None,
                       info: PinnedInfo | None = None, sync: bool = True):
-        count = len(As)
-        ns = (ctypes.c_int32 * count)(*[int(a.shape[0]) for a in As])
-        aptr = (ctypes.c_void_p * count)(*[a.data_ptr() for a in As])
-        if Ds is None:
-            Ds = [torch.empty((int(a.shape[0]),) * 2, dtype=torch.int16, device=a.device) for a in As]
-        dptr = (ctypes.c_void_p * count)(*[d.data_ptr() for d in Ds])
-        gam = gamma if hasattr(gamma, "__len__") else [gamma] * count
-        gptr = (ctypes.c_double * count)(*[float(x) for x in gam])
-        info = info or PinnedInfo(count)
-        keeps = (ctypes.c_void_p * count)() if keep else None
+        """Solves many graphs in one call.  As: list of uint8 adjacency tensors,
+        or a Batch (its argument arrays are reused as they are)."""
+        b = As if isinstance(As, Batch) else Batch(As, gamma, Ds)
+        info = info or PinnedInfo(b.count)
+        keeps = (ctypes.c_void_p * b.count)() if keep else None
         if keep:
             flags |= RDIST_KEEP_Y
-        st = rdist_solve_batched(self.handle, count, ns, aptr, gptr, flags, dptr, keeps, info.ptr,
+        st = rdist_solve_batched(self.handle, b.count, b.ns, b.aptr, b.gptr, flags, b.dptr, keeps, info.ptr,
                                  _stream_ptr(stream))
         _check(st, "rdist_solve_batched")
-        graphs = [Graph(self, keeps[i], int(As[i].shape[0])) for i in range(count)] if keep else None
+        graphs = [Graph(self, keeps[i], int(b.ns[i])) for i in range(b.count)] if keep else None
         if sync:
             (stream or torch.cuda.current_stream()).synchronize()
-        return Ds, info, graphs
+        return b.Ds, info, graphs
 
     def next_hop(self, graph: Graph, cur: torch.Tensor, goal: torch.Tensor, max_hops: int = 1,
                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

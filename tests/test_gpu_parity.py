@@ -377,6 +377,69 @@ def test_batched_deterministic_and_order_free(ctx):
         assert np.array_equal(a, alone[0].cpu().numpy())
 
 
+def test_batched_graph_replay_matches_eager(ctx):
+    """The captured HIP graph, replayed with other work and synchronisations
+    in between, gives the eager launches' bits every time."""
+    specs = gg.c3_specs(96, batch_index=21)
+    As = [dev(s.build()) for s in specs]
+    eager, einfo, _ = ctx.solve_batched(As, -0.5, flags=R.RDIST_NO_GRAPH)
+    ref = [d.cpu().numpy().copy() for d in eager]
+    ref_status = [einfo.get(k).status for k in range(len(As))]
+    b = R.Batch(As, -0.5)
+    other = dev(gg.erdos_renyi(300, 0.05, gg.rng_for("parity", 8200)))
+    for rep in range(4):
+        for d in b.Ds:
+            d.fill_(0x1234)
+        Ds, info, _ = ctx.solve_batched(b)
+        note(f"[parity] graph replay {rep}")
+        for k in range(len(As)):
+            assert info.get(k).status == ref_status[k]
+            assert np.array_equal(Ds[k].cpu().numpy(), ref[k]), f"replay {rep} graph {k}"
+        ctx.solve(other, -0.5)          # eager work between replays
+        torch.cuda.synchronize()
+    # and the eager result is the oracle's
+    idx = list(range(0, len(As), 6))
+    check_batch([specs[k].build() for k in idx], -0.5, [eager[k] for k in idx], _Sub(einfo, idx), None, "eager")
+
+
+def test_batched_autotuner_and_tile_cache(tmp_path):
+    """The autotuner writes the tile cache on the first batch of a class; a
+    context that loads the file uses its entry (here edited to put every graph
+    up to 512 into the persistent kernel) and still matches the oracle."""
+    import json
+    path = str(tmp_path / "tiles.json")
+    specs = gg.c3_specs(64, batch_index=22)
+    A_np = [s.build() for s in specs]
+    As = [dev(A) for A in A_np]
+    c1 = R.Context(0, tile_cache=path)
+    Ds, info, _ = c1.solve_batched(As, -0.5)
+    check_batch(A_np, -0.5, Ds, info, None, "tuned")
+    c1.close()
+    entries = json.load(open(path))["batched"]
+    assert len(entries) == 1 and entries[0]["persist_max_n"] in (128, 256, 512)
+    note(f"[parity] tuned {entries[0]}")
+    for T, grid in ((512, 64), (256, 512), (128, 0)):
+        entries[0]["persist_max_n"], entries[0]["persist_grid"] = T, grid
+        json.dump({"batched": entries}, open(path, "w"))
+        c2 = R.Context(0, tile_cache=path)
+        for flags in (0, R.RDIST_NO_GRAPH):
+            Ds, info, _ = c2.solve_batched(As, -0.5, flags=flags)
+            check_batch(A_np, -0.5, Ds, info, None, f"T={T} grid={grid} flags={flags:#x}")
+        c2.close()
+
+
+def test_batched_with_large_graphs(ctx):
+    """n > 512 graphs in a batch go through the blocked plan after the batch."""
+    A_np = [gg.erdos_renyi(n, 8.0 / n, gg.rng_for("parity", 8300 + n)) for n in (600, 40, 300, 1030, 128)]
+    As = [dev(A) for A in A_np]
+    for flags in (0, R.RDIST_NO_GRAPH):
+        Ds, info, graphs = ctx.solve_batched(As, -0.5, flags=flags, keep=bool(flags))
+        check_batch(A_np, -0.5, Ds, info, graphs, f"large flags={flags:#x}")
+        if graphs:
+            for g in graphs:
+                g.release()
+
+
 # ---------------------------------------------------------------------------
 # Synchronous errors and the budget
 # ---------------------------------------------------------------------------
