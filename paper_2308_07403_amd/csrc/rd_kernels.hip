@@ -623,6 +623,54 @@ __device__ __forceinline__ void adj_colsum(const uint8_t *__restrict__ A, int n,
     if (bad) atomicOr(bad_flag, 1);
 }
 
+// Column sums of the n x n byte matrix A (n <= 512) into colsum[j] (LDS) and
+// *bad as adj_colsum, one workgroup: rows are staged through LDS (stage:
+// kStageBytes) in chunks copied flat, 16 bytes per load and all of a chunk in
+// flight, then each thread adds up its columns (j = t, t + 256) from LDS: no
+// atomics, no divisions.
+constexpr int kStageBytes = 65536;
+__device__ __forceinline__ void adj_colsum_staged(const uint8_t *__restrict__ A, int n, int *colsum, int *bad_flag,
+                                                  uint8_t *stage) {
+    const int rows_per = kStageBytes / n - 1;      // leaves room for the alignment shift
+    const int j0 = threadIdx.x, j1 = threadIdx.x + 256;
+    int s0 = 0, s1 = 0, bad = 0;
+    for (int r0 = 0; r0 < n; r0 += rows_per) {
+        const int rows = min(rows_per, n - r0);
+        const size_t gs = (size_t)r0 * n, ge = (size_t)(r0 + rows) * n;
+        const size_t as = gs & ~(size_t)15;
+        const size_t full = (ge - as) >> 4;          // whole 16-byte words inside [as, ge)
+        const uint4 *W = reinterpret_cast<const uint4 *>(A + as);
+        const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+        if (aligned) {
+            for (size_t q = threadIdx.x; q < full; q += 256)
+                *reinterpret_cast<uint4 *>(stage + 16 * q) = W[q];
+            for (size_t e = as + 16 * full + threadIdx.x; e < ge; e += 256) stage[e - as] = A[e];
+        } else {
+            for (size_t e = gs + threadIdx.x; e < ge; e += 256) stage[e - as] = A[e];
+        }
+        __syncthreads();
+        const int off = (int)(gs - as);
+        for (int r = 0; r < rows; ++r) {
+            const int i = r0 + r;
+            const uint8_t *row = stage + off + r * n;
+            if (j0 < n) {
+                const int a = row[j0];
+                s0 += a;
+                bad |= (a > 1) | ((i == j0) & (a != 0));
+            }
+            if (j1 < n) {
+                const int a = row[j1];
+                s1 += a;
+                bad |= (a > 1) | ((i == j1) & (a != 0));
+            }
+        }
+        __syncthreads();
+    }
+    if (j0 < n) colsum[j0] = s0;
+    if (j1 < n) colsum[j1] = s1;
+    if (bad) atomicOr(bad_flag, 1);
+}
+
 // Ingest of one graph: out-degrees, validation, Delta, gain, gate; M = I - gamma A.
 __device__ __noinline__ int medium_ingest(const uint8_t *A, int n, int np, double gamma_arg, double *M, int *ints,
                                           int *delta_out, double *gamma_out) {
@@ -760,11 +808,11 @@ __device__ __forceinline__ bool lv_unit(const int *units, int &g, int &item) {
 __global__ __launch_bounds__(256) void k_lv_ingest(const LevelGraph *__restrict__ gs) {
     __shared__ int colsum[512];
     __shared__ int flags[2];
+    __shared__ __attribute__((aligned(16))) uint8_t stage[kStageBytes];
     const LevelGraph g = gs[blockIdx.x];
-    for (int j = threadIdx.x; j < 512; j += 256) colsum[j] = 0;
     if (threadIdx.x == 0) { flags[0] = 0; flags[1] = 0; }
     __syncthreads();
-    adj_colsum(g.A, g.n, colsum, &flags[0]);
+    adj_colsum_staged(g.A, g.n, colsum, &flags[0], stage);
     __syncthreads();
     int m = 0;
     for (int j = threadIdx.x; j < g.n; j += 256) m = max(m, colsum[j]);
@@ -801,6 +849,8 @@ __global__ __launch_bounds__(256) void k_lv_build(const LevelGraph *__restrict__
     if (g.info->status != RDIST_OK) return;
     const double gamma = g.info->gamma;
     const int nt = g.nt, n = g.n, np = g.np;
+    const uint8_t *__restrict__ A = g.A;
+    double *__restrict__ M = g.M;
     if (item < nt) {
         const int J = item;
         for (int e = threadIdx.x; e < kTile * kTile / 2; e += 256) {
@@ -809,10 +859,10 @@ __global__ __launch_bounds__(256) void k_lv_build(const LevelGraph *__restrict__
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 double x = (i == j + q) ? 1.0 : 0.0;
-                if (i < n && j + q < n) x -= gamma * (double)g.A[(size_t)i * n + j + q];
+                if (i < n && j + q < n) x -= gamma * (double)A[(size_t)i * n + j + q];
                 v[q] = x;
             }
-            *reinterpret_cast<double2 *>(g.M + (size_t)i * np + j) = double2{v[0], v[1]};
+            *reinterpret_cast<double2 *>(M + (size_t)i * np + j) = double2{v[0], v[1]};
         }
         return;
     }
@@ -823,7 +873,7 @@ __global__ __launch_bounds__(256) void k_lv_build(const LevelGraph *__restrict__
     for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
         const int ii = e >> 7, k = e & 127;
         const int i = I * kTile + ii;
-        blk[ii * 132 + k] = (i < n && k < n) ? g.A[(size_t)i * n + k] : (uint8_t)0;
+        blk[ii * 132 + k] = (i < n && k < n) ? A[(size_t)i * n + k] : (uint8_t)0;
     }
     __syncthreads();
     double *out = g.Ut[0] + (size_t)I * kTile;
