@@ -209,7 +209,9 @@ typedef struct rdist_kernel_stats {
 #define RDIST_K_CERTIFY 8     /* mixed precision: certification + recompute */
 #define RDIST_K_UPDATE_EDGE 9 /* update of the next block's row and column (lookahead) and the
                                  last, readout-fused update */
-#define RDIST_K_COUNT 10
+#define RDIST_K_MIXED_GEMM 10  /* mixed precision: FP32 row products and trailing updates */
+#define RDIST_K_REFINE 11     /* mixed precision: residual, correction product and recompute */
+#define RDIST_K_COUNT 12
 
 /* Enables (1) or disables (0) per-kernel event timing; enabling resets the counters. */
 rdist_status rdist_set_timing(rdist_ctx ctx, int enable);

@@ -15,7 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librdist.so")
-SOURCES = ["rd_engine.hip", "rd_batch.hip", "rd_kernels.hip"]
+SOURCES = ["rd_engine.hip", "rd_batch.hip", "rd_mixed.hip", "rd_kernels.hip"]
+# rocBLAS provides the plain FP32 GEMMs of the mixed-precision plan
+LINK = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
@@ -57,7 +59,7 @@ def build(verbose: bool = True) -> str:
     if any(rcs):
         raise RuntimeError("hipcc failed to compile the engine")
     tmp = LIB + f".tmp{os.getpid()}"
-    if _run([hipcc(), *HIPCC_FLAGS, *objs, "-o", tmp]):
+    if _run([hipcc(), *HIPCC_FLAGS, *objs, *LINK, "-o", tmp]):
         raise RuntimeError("hipcc failed to link librdist.so")
     for o in objs:
         os.remove(o)

@@ -55,6 +55,10 @@ struct Workspace {
     hipStream_t aux2 = nullptr;   // batched plans: the persistent kernel's stream
     hipEvent_t ev_er = nullptr, ev_rest = nullptr, ev_panel = nullptr;
     BatchPlan *transient = nullptr;   // batched plan rebuilt per call (not captured)
+    // mixed precision: FP32 matrix, row product, column copy, FP64 diagonal
+    // block, FP32 P, certification counters + slab flags, sparse rows of A,
+    // residual and correction slabs
+    Buf m32, v32, u32, s64, p32, cert, csr_cnt, csr_off, csr_col, r32, c32;
     double *m() const { return (double *)M.p; }
     int32_t *outdeg() const { return (int32_t *)small.p; }
     int32_t *bad() const { return outdeg() + n_cap + 1; }
@@ -106,6 +110,7 @@ struct rdist_ctx_s {
     std::string tile_cache_path;
     std::vector<std::pair<std::string, rd::eng::BatchTuning>> tuned;   // batch class -> tuning
     bool tuned_dirty = false;
+    void *blas = nullptr;   // rocBLAS handle of the mixed-precision path (created on first use)
 };
 
 namespace rd {
@@ -158,6 +163,11 @@ rdist_status check_flags(uint32_t flags);
 rdist_status check_gamma(double gamma);
 rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
                            rdist_graph *keep, rdist_info *info, hipStream_t s);
+
+// rd_mixed.hip
+rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
+                         rdist_info *info, hipStream_t s);
+void destroy_blas(rdist_ctx c);
 
 // rd_batch.hip
 void destroy_plans(rdist_ctx c);

@@ -188,7 +188,8 @@ rdist_status check_flags(uint32_t flags) {
     if (flags & ~known) return fail(RDIST_E_ARG, "unknown flag bits");
     if ((flags & RDIST_BLOCK_128) && (flags & RDIST_BLOCK_256)) return fail(RDIST_E_ARG, "two block widths");
     if ((flags & RDIST_PLAN_SMALL) && (flags & RDIST_PLAN_BLOCKED)) return fail(RDIST_E_ARG, "two plan flags");
-    if (flags & RDIST_MIXED_F32) return fail(RDIST_E_ARG, "RDIST_MIXED_F32 is not available in this build");
+    if ((flags & RDIST_MIXED_F32) && (flags & (RDIST_KEEP_Y | RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED)))
+        return fail(RDIST_E_ARG, "RDIST_MIXED_F32 takes no KEEP_Y or plan flag");
     return RDIST_OK;
 }
 
@@ -410,6 +411,7 @@ void rdist_destroy(rdist_ctx c) {
         (void)hipSetDevice(c->device);
         drain_timing(c);
         destroy_plans(c);
+        destroy_blas(c);
         if (c->tuned_dirty) save_tile_cache(c);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
         std::vector<rdist_graph_s *> gs(c->graphs.begin(), c->graphs.end());
@@ -417,7 +419,8 @@ void rdist_destroy(rdist_ctx c) {
         for (auto &kv : c->ws) {
             Workspace &w = kv.second;
             for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2,
-                           &w.Pt2, &w.small})
+                           &w.Pt2, &w.small, &w.m32, &w.v32, &w.u32, &w.s64, &w.p32, &w.cert, &w.csr_cnt,
+                           &w.csr_off, &w.csr_col, &w.r32, &w.c32})
                 release(c, *b);
             for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
                 if (e) (void)hipEventDestroy(e);
@@ -441,6 +444,7 @@ rdist_status rdist_solve(rdist_ctx c, const uint8_t *A_dev, int32_t n, double ga
     Guard g(c);
     RD_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
+    if (flags & RDIST_MIXED_F32) return solve_mixed(c, A_dev, n, gamma, flags, D_dev, info, s);
     const bool small = !(flags & RDIST_PLAN_BLOCKED) && n <= 128;
     if (small) return solve_small(c, A_dev, n, gamma, flags, D_dev, keep, info, s);
     return solve_blocked(c, A_dev, n, gamma, flags, D_dev, keep, info, s);

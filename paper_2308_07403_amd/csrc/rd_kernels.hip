@@ -1072,14 +1072,19 @@ __global__ __launch_bounds__(256) void k_next_hop(const double *__restrict__ Y, 
 // Launchers
 // ---------------------------------------------------------------------------
 
-void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
-                   int32_t *bad, rdist_info *info, hipStream_t s) {
+void launch_gate(const uint8_t *A, int n, double gamma_arg, int32_t *outdeg, int32_t *bad, rdist_info *info,
+                 hipStream_t s) {
     hipLaunchKernelGGL(k_zero_i32, dim3((n + 1 + 255) / 256), dim3(256), 0, s, outdeg, n);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, bad, 1);
     const int rows = 256;
     hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256, (n + rows - 1) / rows), dim3(256), 0, s, A, n, rows,
                        outdeg, bad);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, outdeg, bad, n, gamma_arg, info);
+}
+
+void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
+                   int32_t *bad, rdist_info *info, hipStream_t s) {
+    launch_gate(A, n, gamma_arg, outdeg, bad, info, s);
     const size_t pairs = (size_t)np * np / 2;
     const int blocks = (int)std::min<size_t>((pairs + 255) / 256, 8192);
     hipLaunchKernelGGL(k_build_m, dim3(blocks), dim3(256), 0, s, A, n, np, ld, M, info);

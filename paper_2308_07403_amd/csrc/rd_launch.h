@@ -54,6 +54,9 @@ constexpr int kLvShift = 6;   // unit = (graph << 6) | item, item < 64
 // Launch phases of the level plan (the last two are update tile sets).
 enum LevelPhase { kLvBuild = 0, kLvPanel = 1, kLvRowcol = 2, kLvEdge = 3, kLvRest = 4 };
 
+// Out-degrees, validation and the gate: info (status, delta, gamma, zeroed counters).
+void launch_gate(const uint8_t *A, int n, double gamma_arg, int32_t *outdeg, int32_t *bad, rdist_info *info,
+                 hipStream_t s);
 void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
                    int32_t *bad, rdist_info *info, hipStream_t s);
 void launch_fill_sentinel(int16_t *D, int n, const rdist_info *info, hipStream_t s);
@@ -76,6 +79,20 @@ void launch_batched(const BatchTask *tasks, int count, int *counter, int grid, d
 int batched_blocks_per_cu();
 void launch_lv_ingest(const LevelGraph *gs, int count, hipStream_t s);
 void launch_lv(int phase, const LevelGraph *gs, const int *units, int grid, int K, hipStream_t s);
+// Mixed precision (rd_mixed.hip).
+void launch_m32_build(const uint8_t *A, int n, int np, float *M, const rdist_info *info, hipStream_t s);
+void launch_diag_to_f64(const float *M, int np, int K0, double *S, hipStream_t s);
+void launch_p_to_f32(const double *S, float *P, float *V, int np, int K0, hipStream_t s);
+void launch_ucopy_zero(float *M, int np, int K0, float *U, hipStream_t s);
+void launch_certify(const float *X, int np, int n, double margin, int16_t *D, int32_t *slab_flag,
+                    unsigned long long *cnt, rdist_info *info, hipStream_t s);
+void launch_row_count(const uint8_t *A, int n, int32_t *cnt, hipStream_t s);
+void launch_row_fill(const uint8_t *A, int n, const int64_t *off, int32_t *cols, hipStream_t s);
+void launch_residual(const float *X, int np, int n, const int64_t *off, const int32_t *cols, const int32_t *slabs,
+                     int nslab, float *R, const rdist_info *info, hipStream_t s);
+void launch_fix(const float *X, int np, int n, const float *C, const int32_t *slabs, int nslab, double margin,
+                int16_t *D, rdist_info *info, hipStream_t s);
+void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s);
 void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s);
 void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
                      const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s);

@@ -1,0 +1,416 @@
+// rd_mixed.hip -- mixed-precision solve (RDIST_MIXED_F32).
+//
+// Y is first formed in FP32: blocked Gauss-Jordan with b = 256, the 256 x 256
+// diagonal block inverted in FP64 (the FP64 register / MFMA kernels, in
+// place on a converted copy), and the row product V = P M_K,: and the
+// trailing update M <- M~ - U V as FP32 GEMMs (rocBLAS, FP32 matrix cores).
+// Every entry of the FP32 result X0 is then certified or not (Sec. 5, the
+// FP64 precision limit, restated for FP32):
+//   uncertified  iff  X0 < FLT_MIN (zero included: FP32 cannot tell an
+//                underflowed entry from an unreachable one), or
+//                |R32 - round(R32)| < margin, R32 = log(X0) / log(gamma);
+// a certified entry's D = ceil(R32 - eta) is the FP64 answer, because the
+// FP32 error in R is far below the margin.  Uncertified entries are
+// recomputed to FP64 accuracy:
+//   * no underflow: one refinement step Y = X0 + X0 (I - M X0) on the
+//     128-column slabs that hold them.  The residual is formed in FP64 from
+//     the sparse adjacency (it is of order eps32 * Y entrywise, M being an
+//     M-matrix with Y >= 0), so the FP32 product X0 R adds an error of order
+//     eps32^2 * Y;
+//   * some underflow: the whole graph goes through the FP64 blocked plan.
+// The call synchronises the stream once (after certification), because the
+// size of the recompute is data-dependent.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/rdist.h"
+#include "rd_device.h"
+#include "rd_engine.h"
+#include "rd_launch.h"
+
+namespace rd {
+
+namespace {
+
+constexpr int kMB = 256;      // block width of the FP32 Gauss-Jordan
+constexpr int kSlab = 128;    // column slab of the refinement
+
+// M32 = I - gamma A (n x n), identity on the padding (np x np).
+__global__ __launch_bounds__(256) void k_m32_build(const uint8_t *__restrict__ A, int n, int np,
+                                                   float *__restrict__ M, const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    const double gamma = info->gamma;
+    const size_t total = (size_t)np * np;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const int i = (int)(e / np), j = (int)(e - (size_t)i * np);
+        double x = (i == j) ? 1.0 : 0.0;
+        if (i < n && j < n) x -= gamma * (double)A[(size_t)i * n + j];
+        M[e] = (float)x;
+    }
+}
+
+// S (256 x 256 FP64) = the diagonal block at K0 of M.
+__global__ __launch_bounds__(256) void k_diag_to_f64(const float *__restrict__ M, int np, int K0,
+                                                     double *__restrict__ S) {
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < kMB * kMB; e += gridDim.x * 256) {
+        const int r = e >> 8, c = e & 255;
+        S[e] = (double)M[(size_t)(K0 + r) * np + K0 + c];
+    }
+}
+
+// P (FP64, in S) rounded to FP32 into P (V == nullptr), or P copied into
+// V's block columns at K0.
+__global__ __launch_bounds__(256) void k_p_to_f32(const double *__restrict__ S, float *__restrict__ P,
+                                                  float *__restrict__ V, int np, int K0) {
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < kMB * kMB; e += gridDim.x * 256) {
+        const int r = e >> 8, c = e & 255;
+        if (V) V[(size_t)r * np + K0 + c] = P[e];
+        else P[e] = (float)S[e];
+    }
+}
+
+// U (np x 256) = the column block K of M with its own rows replaced by -I;
+// then block row and block column K of M are zeroed (M~).
+__global__ __launch_bounds__(256) void k_ucopy_zero(float *__restrict__ M, int np, int K0, float *__restrict__ U) {
+    const size_t total = (size_t)np * kMB;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const int i = (int)(e >> 8), c = (int)(e & 255);
+        float u;
+        if (i >= K0 && i < K0 + kMB) {
+            u = (i - K0 == c) ? -1.0f : 0.0f;
+        } else {
+            u = M[(size_t)i * np + K0 + c];
+            M[(size_t)i * np + K0 + c] = 0.0f;
+        }
+        U[e] = u;
+    }
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const int r = (int)(e / np), j = (int)(e - (size_t)r * np);
+        M[(size_t)(K0 + r) * np + j] = 0.0f;
+    }
+}
+
+__device__ __forceinline__ bool uncertified(float y, double il, double margin) {
+    if (!(y >= FLT_MIN)) return true;
+    const double r = log((double)y) * il;
+    return fabs(r - rint(r)) < margin;
+}
+
+// Certification of X (FP32, n x n inside np x np): certified entries get D;
+// uncertified ones are counted (cnt[0]; cnt[1] those below FLT_MIN) and
+// their 128-column slab flagged.
+__global__ __launch_bounds__(256) void k_certify(const float *__restrict__ X, int np, int n, double margin,
+                                                 int16_t *__restrict__ D, int32_t *__restrict__ slab_flag,
+                                                 unsigned long long *cnt, rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    const double il = rd_inv_log(info->gamma);
+    Counts c;
+    unsigned long long unc = 0, under = 0;
+    const size_t total = (size_t)n * n;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const int i = (int)(e / n), j = (int)(e - (size_t)i * n);
+        const float y = X[(size_t)i * np + j];
+        if (uncertified(y, il, margin)) {
+            ++unc;
+            under += !(y >= FLT_MIN);
+            slab_flag[j / kSlab] = 1;
+        } else {
+            D[e] = rd_encode((double)y, il, c);
+        }
+    }
+    flush_counts(info, c);
+    unc = wave_sum_u64(unc);
+    under = wave_sum_u64(under);
+    if ((threadIdx.x & 63) == 0) {
+        if (unc) atomicAdd(&cnt[0], unc);
+        if (under) atomicAdd(&cnt[1], under);
+    }
+}
+
+// Nonzeros per row of A (row i lists the in-neighbours of i).
+__global__ __launch_bounds__(256) void k_row_count(const uint8_t *__restrict__ A, int n, int32_t *cnt) {
+    __shared__ int tot;
+    if (threadIdx.x == 0) tot = 0;
+    __syncthreads();
+    const uint8_t *row = A + (size_t)blockIdx.x * n;
+    int c = 0;
+    for (int j = threadIdx.x; j < n; j += 256) c += row[j] != 0;
+    atomicAdd(&tot, c);
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+}
+
+// Column indices of row i's nonzeros, in increasing order: thread t scans a
+// contiguous stretch of the row; an exclusive scan over the threads' counts
+// gives each its output position.
+__global__ __launch_bounds__(256) void k_row_fill(const uint8_t *__restrict__ A, int n,
+                                                  const int64_t *__restrict__ off, int32_t *__restrict__ cols) {
+    __shared__ int pos[257];
+    const uint8_t *row = A + (size_t)blockIdx.x * n;
+    const int per = (n + 255) / 256;
+    const int j0 = min(n, threadIdx.x * per), j1 = min(n, j0 + per);
+    int c = 0;
+    for (int j = j0; j < j1; ++j) c += row[j] != 0;
+    pos[threadIdx.x + 1] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pos[0] = 0;
+        for (int t = 1; t <= 256; ++t) pos[t] += pos[t - 1];
+    }
+    __syncthreads();
+    int32_t *out = cols + off[blockIdx.x] + pos[threadIdx.x];
+    for (int j = j0; j < j1; ++j)
+        if (row[j]) *out++ = j;
+}
+
+// R (np x w, w = 128 nslab) = I - M X on the slabs: for row k and column
+// j of slab s, R = [k == j] - X[k][j] + gamma * sum over nonzeros l of
+// A's row k of X[l][j], accumulated in FP64, stored in FP32.
+__global__ __launch_bounds__(256) void k_residual(const float *__restrict__ X, int np, int n,
+                                                  const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
+                                                  const int32_t *__restrict__ slabs, int nslab, float *__restrict__ R,
+                                                  const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    const double gamma = info->gamma;
+    const int k = blockIdx.x * 2 + (threadIdx.x >> 7), c = threadIdx.x & 127;
+    const int s = blockIdx.y;
+    const int j = slabs[s] * kSlab + c;
+    double acc = 0.0;
+    if (k < n) {
+        const int64_t e1 = off[k + 1];
+        for (int64_t e = off[k]; e < e1; ++e) acc += (double)X[(size_t)cols[e] * np + j];
+    }
+    const double r = ((k == j) ? 1.0 : 0.0) - (double)X[(size_t)k * np + j] + gamma * acc;
+    R[(size_t)k * ((size_t)nslab * kSlab) + (size_t)s * kSlab + c] = (float)r;
+}
+
+// Uncertified entries of the slabs: Y = X + (X R), the correction C = X R
+// (np x w) from the FP32 GEMM; D from Y in FP64.
+__global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np, int n, const float *__restrict__ C,
+                                             const int32_t *__restrict__ slabs, int nslab, double margin,
+                                             int16_t *__restrict__ D, rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    const double il = rd_inv_log(info->gamma);
+    const int i = blockIdx.x * 2 + (threadIdx.x >> 7), c = threadIdx.x & 127;
+    const int s = blockIdx.y;
+    const int j = slabs[s] * kSlab + c;
+    Counts cnt;
+    if (i < n && j < n) {
+        const float x = X[(size_t)i * np + j];
+        if (uncertified(x, il, margin)) {
+            const double y = (double)x + (double)C[(size_t)i * ((size_t)nslab * kSlab) + (size_t)s * kSlab + c];
+            D[(size_t)i * n + j] = rd_encode(y, il, cnt);
+        }
+    }
+    flush_counts(info, cnt);
+}
+
+__global__ void k_set_mixed_info(rdist_info *info, long long uncertified, double fraction) {
+    info->n_uncertified = uncertified;
+    info->fallback_fraction = fraction;
+}
+
+int grid_for(size_t total) { return (int)std::min<size_t>((total + 255) / 256, 16384); }
+
+}  // namespace
+
+void launch_m32_build(const uint8_t *A, int n, int np, float *M, const rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_m32_build, dim3(grid_for((size_t)np * np)), dim3(256), 0, s, A, n, np, M, info);
+}
+void launch_diag_to_f64(const float *M, int np, int K0, double *S, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_to_f64, dim3(256), dim3(256), 0, s, M, np, K0, S);
+}
+void launch_p_to_f32(const double *S, float *P, float *V, int np, int K0, hipStream_t s) {
+    hipLaunchKernelGGL(k_p_to_f32, dim3(256), dim3(256), 0, s, S, P, V, np, K0);
+}
+void launch_ucopy_zero(float *M, int np, int K0, float *U, hipStream_t s) {
+    hipLaunchKernelGGL(k_ucopy_zero, dim3(grid_for((size_t)np * kMB)), dim3(256), 0, s, M, np, K0, U);
+}
+void launch_certify(const float *X, int np, int n, double margin, int16_t *D, int32_t *slab_flag,
+                    unsigned long long *cnt, rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_certify, dim3(grid_for((size_t)n * n)), dim3(256), 0, s, X, np, n, margin, D, slab_flag,
+                       cnt, info);
+}
+void launch_row_count(const uint8_t *A, int n, int32_t *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_count, dim3(n), dim3(256), 0, s, A, n, cnt);
+}
+void launch_row_fill(const uint8_t *A, int n, const int64_t *off, int32_t *cols, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_fill, dim3(n), dim3(256), 0, s, A, n, off, cols);
+}
+void launch_residual(const float *X, int np, int n, const int64_t *off, const int32_t *cols, const int32_t *slabs,
+                     int nslab, float *R, const rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_residual, dim3(np / 2, nslab), dim3(256), 0, s, X, np, n, off, cols, slabs, nslab, R, info);
+}
+void launch_fix(const float *X, int np, int n, const float *C, const int32_t *slabs, int nslab, double margin,
+                int16_t *D, rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_fix, dim3(np / 2, nslab), dim3(256), 0, s, X, np, n, C, slabs, nslab, margin, D, info);
+}
+void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_mixed_info, dim3(1), dim3(1), 0, s, info, uncertified, fraction);
+}
+
+namespace eng {
+
+namespace {
+
+// Certification margin on R = log_gamma Y: an FP32 entry whose R lies
+// within this of an integer is recomputed.
+constexpr double kCertMargin = 0.05;
+
+const char *blas_status_name(rocblas_status st) { return rocblas_status_to_string(st); }
+
+#define RD_BLAS(expr)                                                                              \
+    do {                                                                                           \
+        rocblas_status b_ = (expr);                                                                \
+        if (b_ != rocblas_status_success) return fail(RDIST_E_HIP, std::string(#expr) + ": " + blas_status_name(b_)); \
+    } while (0)
+
+rdist_status ensure_blas(rdist_ctx c, hipStream_t s) {
+    if (!c->blas) {
+        rocblas_handle h = nullptr;
+        RD_BLAS(rocblas_create_handle(&h));
+        c->blas = h;
+    }
+    RD_BLAS(rocblas_set_stream((rocblas_handle)c->blas, s));
+    return RDIST_OK;
+}
+
+}  // namespace
+
+void destroy_blas(rdist_ctx c) {
+    if (c->blas) (void)rocblas_destroy_handle((rocblas_handle)c->blas);
+    c->blas = nullptr;
+}
+
+rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
+                         rdist_info *info, hipStream_t s) {
+    Workspace &w = c->ws[s];
+    const int np = ((n + kMB - 1) / kMB) * kMB;
+    const int nb = np / kMB;
+    const double margin = kCertMargin;
+    rdist_status st;
+    if ((st = ensure_small(c, w, n))) return st;
+    if ((st = ensure(c, w.m32, (size_t)np * np * 4))) return st;
+    if ((st = ensure(c, w.v32, (size_t)kMB * np * 4))) return st;
+    if ((st = ensure(c, w.u32, (size_t)kMB * np * 4))) return st;
+    if ((st = ensure(c, w.s64, (size_t)kMB * kMB * 8))) return st;
+    if ((st = ensure(c, w.p32, (size_t)kMB * kMB * 4))) return st;
+    if ((st = ensure(c, w.Ut2, (size_t)128 * 256 * 8))) return st;
+    if ((st = ensure(c, w.V2, (size_t)128 * 256 * 8))) return st;
+    if ((st = ensure(c, w.Pt2, (size_t)128 * 128 * 8))) return st;
+    const int nslab_all = np / kSlab;
+    if ((st = ensure(c, w.cert, 256 + (size_t)nslab_all * 4))) return st;
+    if ((st = ensure_blas(c, s))) return st;
+    rocblas_handle h = (rocblas_handle)c->blas;
+    rdist_info *dinfo = w.dinfo();
+    float *M = (float *)w.m32.p, *V = (float *)w.v32.p, *U = (float *)w.u32.p, *P = (float *)w.p32.p;
+    double *S = (double *)w.s64.p;
+    {
+        Timer t(c, s, RDIST_K_INGEST, 0.0, (double)n * n + 4.0 * np * np);
+        rd::launch_gate(A, n, gamma, w.outdeg(), w.bad(), dinfo, s);
+        rd::launch_m32_build(A, n, np, M, dinfo, s);
+    }
+    RD_HIP(hipGetLastError());
+    const float one = 1.0f, zero = 0.0f, minus_one = -1.0f;
+    for (int K = 0; K < nb; ++K) {
+        const int K0 = K * kMB;
+        {
+            Timer t(c, s, RDIST_K_PANEL, 2.0 * kMB * kMB * kMB, 16.0 * kMB * kMB);
+            rd::launch_diag_to_f64(M, np, K0, S, s);
+            for (int k2 = 0; k2 < 2; ++k2) {
+                rd::launch_panel(S, kMB, k2, (double *)w.Pt2.p, (double *)w.V2.p, kMB, dinfo, s);
+                rd::launch_rowcol(S, kMB, 2, k2, 1, (const double *)w.Pt2.p, (double *)w.Ut2.p, (double *)w.V2.p,
+                                  kMB, dinfo, s);
+                rd::launch_update(rd::kUpdateAll, S, kMB, 2, k2, 1, 0, (const double *)w.Ut2.p,
+                                  (const double *)w.V2.p, kMB, false, 0, nullptr, 0, dinfo, s);
+            }
+        }
+        RD_HIP(hipGetLastError());
+        {
+            Timer t(c, s, RDIST_K_MIXED_GEMM, 2.0 * np * (double)np * kMB + 2.0 * kMB * (double)kMB * np,
+                    4.0 * (3.0 * np * (double)np + 4.0 * kMB * np));
+            rd::launch_p_to_f32(S, P, nullptr, np, K0, s);   // P rounded to FP32
+            // V = P M_K,: (row-major), i.e. column-major V^T = M_K,:^T P^T; then V_K = P
+            RD_BLAS(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, np, kMB, kMB, &one,
+                                  M + (size_t)K0 * np, np, P, kMB, &zero, V, np));
+            rd::launch_p_to_f32(S, P, V, np, K0, s);
+            rd::launch_ucopy_zero(M, np, K0, U, s);
+            // M <- M~ - U V, i.e. column-major M^T <- M^T - V^T U^T
+            RD_BLAS(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, np, np, kMB, &minus_one, V, np,
+                                  U, kMB, &one, M, np));
+        }
+        RD_HIP(hipGetLastError());
+    }
+    // certification
+    int32_t *slab_flag = (int32_t *)((char *)w.cert.p + 256);
+    unsigned long long *cnt = (unsigned long long *)w.cert.p;
+    RD_HIP(hipMemsetAsync(w.cert.p, 0, 256 + (size_t)nslab_all * 4, s));
+    {
+        Timer t(c, s, RDIST_K_CERTIFY, 0.0, 6.0 * n * (double)n);
+        rd::launch_certify(M, np, n, margin, D, slab_flag, cnt, dinfo, s);
+    }
+    RD_HIP(hipGetLastError());
+    std::vector<int32_t> flags_h(nslab_all);
+    unsigned long long cnt_h[2] = {0, 0};
+    rdist_info info_h;
+    RD_HIP(hipMemcpyAsync(cnt_h, cnt, sizeof(cnt_h), hipMemcpyDeviceToHost, s));
+    RD_HIP(hipMemcpyAsync(flags_h.data(), slab_flag, (size_t)nslab_all * 4, hipMemcpyDeviceToHost, s));
+    RD_HIP(hipMemcpyAsync(&info_h, dinfo, sizeof(info_h), hipMemcpyDeviceToHost, s));
+    RD_HIP(hipStreamSynchronize(s));
+    const long long unc = (long long)cnt_h[0];
+    const double frac = (double)unc / ((double)n * n);
+    if (info_h.status == RDIST_OK && cnt_h[1] > 0) {
+        // below the FP32 range: the FP64 plan decides every entry
+        st = solve_blocked(c, A, n, gamma, flags & ~RDIST_MIXED_F32, D, nullptr, nullptr, s);
+        if (st) return st;
+        rd::launch_set_mixed_info(dinfo, unc, 1.0, s);
+        return copy_info(info, dinfo, 1, s);
+    }
+    if (info_h.status == RDIST_OK && unc > 0) {
+        std::vector<int32_t> slabs;
+        for (int q = 0; q < nslab_all; ++q)
+            if (flags_h[q]) slabs.push_back(q);
+        const int ns = (int)slabs.size();
+        const size_t wcols = (size_t)ns * kSlab;
+        Timer t(c, s, RDIST_K_REFINE, 2.0 * np * (double)np * wcols, 4.0 * np * (double)np);
+        // sparse rows of A (the residual's M X0 term)
+        if ((st = ensure(c, w.csr_cnt, (size_t)(n + 1) * 8))) return st;
+        rd::launch_row_count(A, n, (int32_t *)w.csr_cnt.p, s);
+        std::vector<int32_t> rc(n);
+        RD_HIP(hipMemcpyAsync(rc.data(), w.csr_cnt.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        RD_HIP(hipStreamSynchronize(s));
+        std::vector<int64_t> off(n + 1, 0);
+        for (int i = 0; i < n; ++i) off[i + 1] = off[i] + rc[i];
+        if ((st = ensure(c, w.csr_off, (size_t)(n + 1) * 8 + (size_t)ns * 4))) return st;
+        if ((st = ensure(c, w.csr_col, std::max<size_t>(4, (size_t)off[n] * 4)))) return st;
+        if ((st = ensure(c, w.r32, (size_t)np * wcols * 4))) return st;
+        if ((st = ensure(c, w.c32, (size_t)np * wcols * 4))) return st;
+        int64_t *doff = (int64_t *)w.csr_off.p;
+        int32_t *dslabs = (int32_t *)((char *)w.csr_off.p + (size_t)(n + 1) * 8);
+        RD_HIP(hipMemcpyAsync(doff, off.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
+        RD_HIP(hipMemcpyAsync(dslabs, slabs.data(), (size_t)ns * 4, hipMemcpyHostToDevice, s));
+        rd::launch_row_fill(A, n, doff, (int32_t *)w.csr_col.p, s);
+        rd::launch_residual(M, np, n, doff, (const int32_t *)w.csr_col.p, dslabs, ns, (float *)w.r32.p, dinfo, s);
+        RD_HIP(hipGetLastError());
+        // C = X0 R (row-major np x w), i.e. column-major C^T = R^T X0^T
+        RD_BLAS(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, (int)wcols, np, np, &one,
+                              (const float *)w.r32.p, (int)wcols, M, np, &zero, (float *)w.c32.p, (int)wcols));
+        rd::launch_fix(M, np, n, (const float *)w.c32.p, dslabs, ns, margin, D, dinfo, s);
+        RD_HIP(hipGetLastError());
+        // keep the host vectors alive until the copies above have run
+        RD_HIP(hipStreamSynchronize(s));
+    }
+    rd::launch_set_mixed_info(dinfo, unc, frac, s);
+    rd::launch_fill_sentinel(D, n, dinfo, s);
+    RD_HIP(hipGetLastError());
+    return copy_info(info, dinfo, 1, s);
+}
+
+}  // namespace eng
+}  // namespace rd

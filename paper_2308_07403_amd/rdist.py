@@ -43,7 +43,8 @@ RDIST_BLOCK_256 = 0x1000
 RDIST_NO_GRAPH = 0x2000
 RDIST_THREADSAFE = 0x1
 (RDIST_K_UPDATE, RDIST_K_PANEL, RDIST_K_ROWCOL, RDIST_K_INGEST, RDIST_K_EPILOGUE, RDIST_K_SMALL,
- RDIST_K_BATCHED, RDIST_K_NEXTHOP, RDIST_K_CERTIFY, RDIST_K_UPDATE_EDGE, RDIST_K_COUNT) = range(11)
+ RDIST_K_BATCHED, RDIST_K_NEXTHOP, RDIST_K_CERTIFY, RDIST_K_UPDATE_EDGE, RDIST_K_MIXED_GEMM, RDIST_K_REFINE,
+ RDIST_K_COUNT) = range(13)
 
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_ADJ", 3: "E_NOT_DD", 4: "E_NOMEM", 5: "E_AGAIN",
                 6: "E_HIP", 7: "E_STATE"}

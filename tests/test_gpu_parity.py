@@ -441,6 +441,75 @@ def test_batched_with_large_graphs(ctx):
 
 
 # ---------------------------------------------------------------------------
+# Mixed precision (FP32 inversion, certification, FP64 recompute)
+# ---------------------------------------------------------------------------
+
+def check_mixed(ctx, A, gamma, label):
+    note(f"[parity] mixed {label} n={A.shape[0]}")
+    sol = oracle.solve(A, gamma, keep_y=False)
+    D, info, _ = ctx.solve(dev(A), gamma, flags=R.RDIST_MIXED_F32)
+    Dh = D.cpu().numpy()
+    assert info["status"] == sol.status
+    if sol.status != oracle.OK:
+        assert np.all(Dh == R.RDIST_UNREACHABLE)
+        return info
+    bad = Dh != sol.D
+    assert not bad.any(), f"{label}: {int(bad.sum())} D mismatches at {np.argwhere(bad)[:5].tolist()}"
+    assert info["n_unreachable"] == sol.unreachable
+    assert 0.0 <= info["fallback_fraction"] <= 1.0
+    note(f"[parity] mixed {label}: uncertified {info['n_uncertified']} ({info['fallback_fraction']:.4f})")
+    return info
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_mixed_c4_subsample(ctx, seed):
+    info = check_mixed(ctx, gg.c4_subsample(seed), -0.5, f"c4 subsample {seed}")
+    assert info["n_uncertified"] > 0          # edges and the diagonal sit near integers
+
+
+def test_mixed_c2_subsample(ctx):
+    check_mixed(ctx, gg.c2_subsample(0), -0.5, "c2 subsample 0")
+
+
+@pytest.mark.parametrize("family,n", [("er", 300), ("rgg", 700), ("lattice", 500), ("tree", 257)])
+def test_mixed_families(ctx, family, n):
+    rng = gg.rng_for("parity", 8400 + n)
+    A = {"er": lambda: gg.erdos_renyi(n, 0.05, rng),
+         "rgg": lambda: gg.random_geometric(n, rng),
+         "lattice": lambda: gg.grid_lattice_deleted(n, rng),
+         "tree": lambda: gg.random_tree(n, rng)}[family]()
+    check_mixed(ctx, A, -0.5, family)
+
+
+def test_mixed_underflow_takes_fp64(ctx):
+    """gamma^d below the FP32 range: every entry is decided by the FP64 plan."""
+    info = check_mixed(ctx, gg.directed_path(300), 0.003, "path gamma=0.003")
+    assert info["fallback_fraction"] == 1.0
+
+
+def test_mixed_matches_fp64_at_c2_size(ctx):
+    A = dev(gg.c2_graph(0))
+    D64, i64, _ = ctx.solve(A, -0.5)
+    D64 = D64.cpu().numpy()
+    D32, i32, _ = ctx.solve(A, -0.5, flags=R.RDIST_MIXED_F32)
+    note(f"[parity] mixed c2 full: uncertified {i32['n_uncertified']} ({i32['fallback_fraction']:.4f})")
+    assert np.array_equal(D32.cpu().numpy(), D64)
+    assert i32["n_unreachable"] == i64["n_unreachable"]
+
+
+def test_mixed_refusals(ctx):
+    A = gg.out_star(300)
+    check_mixed(ctx, A, 0.25, "not DD")
+    Ad = dev(gg.c1_graph(0))
+    D = torch.empty((64, 64), dtype=torch.int16, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    assert R.rdist_solve(ctx.handle, Ad.data_ptr(), 64, 0.05, R.RDIST_MIXED_F32 | R.RDIST_KEEP_Y, D.data_ptr(),
+                         None, None, s) == R.RDIST_E_ARG
+    with pytest.raises(R.RdistError):
+        ctx.solve_batched([Ad], 0.05, flags=R.RDIST_MIXED_F32)
+
+
+# ---------------------------------------------------------------------------
 # Synchronous errors and the budget
 # ---------------------------------------------------------------------------
 
