@@ -100,6 +100,35 @@ def cpu_floyd_warshall_c2(A: np.ndarray, ksteps: int):
             "sample": f"{ksteps} of {n} Floyd-Warshall relaxation rounds, scaled to all {n}"}
 
 
+def measure_mixed(ctx, R, torch, A, D_ref, steps, stream):
+    """The mixed-precision solve of the same graph: time per solve, its split,
+    the fallback fraction and D against the FP64 result."""
+    n = A.shape[0]
+    D = torch.empty((n, n), dtype=torch.int16, device="cuda")
+    info = R.PinnedInfo(1)
+    ctx.solve_async(A, -0.5, R.RDIST_MIXED_F32, D, info=info, stream=stream)    # warm-up
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.solve_async(A, -0.5, R.RDIST_MIXED_F32, D, info=info, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    split = {name: ctx.kernel_stats(k)["total_ms"] / steps for name, k in
+             (("ingest", R.RDIST_K_INGEST), ("panel_fp64", R.RDIST_K_PANEL), ("fp32_gemm", R.RDIST_K_MIXED_GEMM),
+              ("certify", R.RDIST_K_CERTIFY), ("refine", R.RDIST_K_REFINE))}
+    gemm = ctx.kernel_stats(R.RDIST_K_MIXED_GEMM)
+    ctx.set_timing(False)
+    st = info.get(0).as_dict()
+    mism = int((D != D_ref).sum().item())
+    gemm_tf = gemm["flops"] / max(gemm["total_ms"], 1e-9) / 1e9
+    return {"ms_per_solve": ms, "graphs_per_s": 1e3 / ms, "eff_tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
+            "fallback_fraction": st["fallback_fraction"], "n_uncertified": st["n_uncertified"],
+            "certification_margin": 0.05, "split_ms": split,
+            "fp32_gemm_tflops": gemm_tf, "fp32_gemm_frac_of_peak": gemm_tf / FP32_PEAK_TFLOPS,
+            "d_mismatches_vs_fp64": mism}
+
+
 def bench_c2(args, torch, R, gg):
     n = 8192
     fl = R.RDIST_F64 | {0: 0, 128: R.RDIST_BLOCK_128, 256: R.RDIST_BLOCK_256}[args.block]
@@ -148,6 +177,11 @@ def bench_c2(args, torch, R, gg):
     torch.cuda.synchronize()
     nh_ms = e0.elapsed_time(e1)
     g.release()
+    mixed = None
+    if not args.no_mixed:
+        log("[bench] mixed precision on the same graph")
+        mixed = measure_mixed(ctx, R, torch, A, D, max(2, args.steps // 3), stream)
+        mixed["speed_vs_fp64"] = mixed["graphs_per_s"] / (args.steps / wall)
     ctx.close()
 
     flops = 2.0 * n ** 3
@@ -185,7 +219,7 @@ def bench_c2(args, torch, R, gg):
                                (("update_rest", upd), ("update_edge_and_last", edge), ("panel", panel),
                                 ("rowcol", rowcol), ("ingest", ingest))},
         "next_hop_64_paths_ms": nh_ms,
-        "mixed": None,
+        "mixed": mixed,
         "solve_info": {k: st[k] for k in ("status", "n_unreachable", "n_subnormal", "n_ambiguous")},
     }
     if not args.no_cpu:
@@ -195,6 +229,159 @@ def bench_c2(args, torch, R, gg):
     else:
         out["cpu_baseline"] = None
     return out
+
+
+def bench_c4(args, torch, R, gg):
+    """ER(16384, 0.01): the mixed-precision solve (value) against the FP64
+    solve of the same graph on the same GPU, D compared entry by entry."""
+    import oracle
+    n = 16384
+    A_np = gg.c4_graph(0)
+    A = torch.from_numpy(A_np).cuda()
+    D = torch.empty((n, n), dtype=torch.int16, device="cuda")
+    ctx = R.Context(0)
+    stream = torch.cuda.current_stream()
+    info = R.PinnedInfo(1)
+    log("[bench] c4 FP64 reference solve")
+    ctx.solve_async(A, -0.5, 0, D, info=info, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps64 = max(1, args.steps // 3)
+    for _ in range(steps64):
+        ctx.solve_async(A, -0.5, 0, D, info=info, stream=stream)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / steps64
+    st64 = info.get(0).as_dict()
+    log(f"[bench] c4 mixed: {args.steps} steps")
+    mixed = measure_mixed(ctx, R, torch, A, D, args.steps, stream)
+    ctx.close()
+    out = {
+        "metric": "mixed-precision APSP graphs/s at n=16384 vs FP64, fallback fraction, D exactness",
+        "value": mixed["graphs_per_s"], "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": mixed["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "C4: directed ER(n=16384, p=0.01), gamma=0.5/max_out_degree, FP32 inversion "
+                               "(FP64 panels) + certification (margin 0.05, FP32 underflow) + FP64-accurate "
+                               "recompute", "n": n, "p": 0.01, "gamma": st64["gamma"], "delta": st64["delta"],
+                   "seed": "c4/0"},
+        "mixed": mixed,
+        "fp64": {"ms_per_solve": ms64, "graphs_per_s": 1e3 / ms64, "eff_tflops": 2.0 * n ** 3 / (ms64 * 1e-3) / 1e12},
+        "roofline": {"bound": "mfma", "kernel": "FP32 trailing-update GEMM (rocBLAS sgemm, rank-256)",
+                     "achieved": mixed["fp32_gemm_tflops"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": mixed["fp32_gemm_frac_of_peak"], "traffic": None},
+    }
+    if not args.no_cpu:
+        sub = gg.c4_subsample(0)
+        t0 = time.perf_counter()
+        oracle.solve(sub, -0.5, keep_y=False)
+        t = time.perf_counter() - t0
+        t_full = t * (n / sub.shape[0]) ** 3
+        out["cpu_baseline"] = {"value": 1.0 / t_full, "unit": "graphs/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"one n=2048 C4-density solve ({t:.1f} s), scaled by (16384/2048)^3"}
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
+def bench_c5(args, torch, R, gg):
+    """Serving: Poisson arrivals of full-D and 64-pair path requests on graphs
+    with n log-uniform in [64, 4096] (ER or torus lattice, mean degree 6-20),
+    through the engine's request loop (continuous batching, HBM-footprint
+    admission).  Graphs come from a pool of pre-built graphs resident in HBM
+    (request k uses pool entry k mod P); latency runs from the scheduled
+    arrival to the poll that reports the result in host memory."""
+    pool_n = args.c5_pool
+    pool_reqs = gg.c5_requests(pool_n, qps=1.0, stream_index=0)
+    log(f"[bench] c5: building a pool of {pool_n} graphs")
+    pool = []
+    for r in pool_reqs:
+        A = r.spec.build()
+        n = A.shape[0]
+        it = {"A": torch.from_numpy(A).cuda(), "n": n,
+              "kind": R.RDIST_QUERY_D if r.query == "D" else R.RDIST_QUERY_PATHS}
+        if it["kind"] == R.RDIST_QUERY_D:
+            it["D"] = torch.empty((n, n), dtype=torch.int16, pin_memory=True)
+        else:
+            it["cur"] = torch.from_numpy(r.pairs[:, 0].copy()).pin_memory()
+            it["goal"] = torch.from_numpy(r.pairs[:, 1].copy()).pin_memory()
+            it["paths"] = torch.empty((len(r.pairs), 65), dtype=torch.int32, pin_memory=True)
+        pool.append(it)
+    flops_pool = [2.0 * it["n"] ** 3 for it in pool]
+    ctx = R.Context(0)
+    budget = args.c5_budget_gib << 30
+
+    def run(arrivals):
+        """Submits request k at arrivals[k] (seconds from start); returns latencies (s), wall, stats."""
+        srv = R.Server(ctx, slots=args.c5_slots, hbm_budget=budget, max_batch=64)
+        N = len(arrivals)
+        lat = np.zeros(N)
+        conc = []
+        t0 = time.perf_counter()
+        k = 0
+        done = 0
+        while done < N:
+            now = time.perf_counter() - t0
+            while k < N and arrivals[k] <= now:
+                it = pool[k % pool_n]
+                if it["kind"] == R.RDIST_QUERY_D:
+                    st = srv.submit(k, it["A"], -0.5, R.RDIST_QUERY_D, D_host=it["D"])
+                else:
+                    st = srv.submit(k, it["A"], -0.5, R.RDIST_QUERY_PATHS, cur_host=it["cur"], goal_host=it["goal"],
+                                    max_hops=64, paths_host=it["paths"])
+                assert st == R.RDIST_OK, R.rdist_last_error()
+                k += 1
+            ids = srv.poll()
+            if ids:
+                t = time.perf_counter() - t0
+                for i in ids:
+                    lat[i] = t - arrivals[i]
+                done += len(ids)
+                conc.append(srv.stats()["in_flight"])
+            else:
+                time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return lat, wall, st, conc
+
+    # saturated throughput: everything arrives at once
+    n_sat = args.c5_sat
+    log(f"[bench] c5: saturation run with {n_sat} requests")
+    run(np.zeros(min(n_sat, 200)))                    # warm-up (workspaces, kernels)
+    lat, wall, st_sat, _ = run(np.zeros(n_sat))
+    sat = n_sat / wall
+    levels = []
+    for frac in (0.5, 0.8):
+        qps = frac * sat
+        reqs = gg.c5_requests(args.c5_requests, qps=qps, stream_index=1)
+        arrivals = np.array([r.arrival_s for r in reqs])
+        log(f"[bench] c5: {args.c5_requests} requests at {qps:.0f} QPS")
+        lat, wall, st, conc = run(arrivals)
+        fl = sum(flops_pool[k % pool_n] for k in range(len(arrivals)))
+        hist = np.bincount(np.asarray(conc, dtype=np.int64), minlength=1).tolist() if conc else []
+        levels.append({"qps": qps, "fraction_of_saturated": frac, "requests": len(arrivals),
+                       "graphs_per_s": len(arrivals) / wall, "eff_tflops": fl / wall / 1e12,
+                       "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                       "mean_ms": float(lat.mean() * 1e3), "batches": st["batches"],
+                       "batched_requests": st["batched_requests"], "max_in_flight": st["max_in_flight"],
+                       "max_footprint_in_flight_gib": st["max_footprint_in_flight"] / 2 ** 30,
+                       "in_flight_histogram": hist})
+    ctx.close()
+    return {
+        "metric": "serving: graphs/s and p50/p99 latency under Poisson arrivals (n in [64, 4096])",
+        "value": sat, "unit": "graphs/s", "n_gpus": 1, "steps": n_sat, "warmup": 200,
+        "ms_per_step": 1e3 / sat, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "C5: Poisson stream, n log-uniform [64, 4096], ER p=k/(n-1) k~U[6,20] or torus "
+                               "lattice (6/8/12/18 neighbours), 50/50 full D or 64 greedy paths, gamma=0.5/Delta; "
+                               f"pool of {pool_n} graphs resident in HBM",
+                   "slots": args.c5_slots, "hbm_budget_gib": args.c5_budget_gib, "max_batch": 64},
+        "saturated": {"graphs_per_s": sat, "requests": n_sat, "batches": st_sat["batches"],
+                      "max_in_flight": st_sat["max_in_flight"]},
+        "levels": levels,
+        "cpu_baseline": None,
+    }
 
 
 def bench_c1(args, torch, R, gg):
@@ -327,12 +514,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--block", type=int, default=0, choices=[0, 128, 256],
                     help="force the blocked plan's block width (0: the engine's choice)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (reference for HBM counters)")
+    ap.add_argument("--c5-pool", type=int, default=96, help="C5: distinct graphs in the pool")
+    ap.add_argument("--c5-requests", type=int, default=20000, help="C5: requests per QPS level")
+    ap.add_argument("--c5-sat", type=int, default=3000, help="C5: requests of the saturation run")
+    ap.add_argument("--c5-slots", type=int, default=8)
+    ap.add_argument("--c5-budget-gib", type=int, default=16)
     ap.add_argument("--cpu-gj-steps", type=int, default=256)
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--cpu-fw-steps", type=int, default=128)
@@ -360,7 +553,7 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
         del src, dst, scrub
-    out = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3}[args.workload](args, torch, R, gg)
+    out = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args, torch, R, gg)
     print(json.dumps(out), flush=True)
 
 

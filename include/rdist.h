@@ -189,6 +189,74 @@ rdist_status rdist_graph_y(rdist_graph g, const double **Y_dev, int32_t *n, int3
 rdist_status rdist_epilogue(rdist_ctx ctx, const double *Y_dev, int32_t n, int32_t ld,
                             double gamma, int16_t *D_dev, rdist_info *info, void *stream);
 
+/*
+ * ---- Serving: a request loop with continuous batching ----
+ *
+ * A server owns `slots` HIP streams of its context (each with its own
+ * workspace) and a queue.  rdist_server_submit only queues a request;
+ * rdist_server_poll (non-blocking) collects finished requests and then
+ * dispatches queued ones, oldest first, while a slot is free and the HBM
+ * footprint of the requests in flight stays within the server's budget:
+ * full-D requests with n <= 512 that are waiting are solved together in
+ * one batched call (rdist_solve_batched) on one slot, up to max_batch of
+ * them; every other request takes a slot of its own (path requests keep Y
+ * for rdist_next_hop and release it when done).  Requests on different
+ * slots run concurrently on the device.  Results are bit-for-bit those of
+ * the same request solved alone: every slot has its own workspace and no
+ * kernel's arithmetic depends on what else runs.  For the paper's query
+ * modes see Sec. 4.1 (full distance matrix) and Sec. 4.2 (greedy routing).
+ */
+typedef struct rdist_server_s *rdist_server;
+
+#define RDIST_QUERY_D 0       /* full n x n D */
+#define RDIST_QUERY_PATHS 1   /* greedy paths for q (start, goal) pairs */
+
+typedef struct rdist_request {
+    int64_t id;                /* caller's tag, reported by rdist_server_poll */
+    const uint8_t *A_dev;      /* n x n adjacency (device); kept alive by the caller until done */
+    int32_t n;
+    int32_t kind;              /* RDIST_QUERY_D or RDIST_QUERY_PATHS */
+    double gamma;              /* explicit or AUTO (< 0), as rdist_solve */
+    int16_t *D_host;           /* RDIST_QUERY_D: n*n int16 host buffer (pinned) receiving D */
+    const int32_t *cur_host;   /* RDIST_QUERY_PATHS: q start nodes (host) */
+    const int32_t *goal_host;  /* RDIST_QUERY_PATHS: q goal nodes (host) */
+    int32_t q;                 /* RDIST_QUERY_PATHS: pairs, 0 <= q <= 4096 */
+    int32_t max_hops;          /* RDIST_QUERY_PATHS: 1 .. 65535 */
+    int32_t *paths_host;       /* RDIST_QUERY_PATHS: q*(max_hops+1) int32 host buffer (pinned), layout as
+                                  rdist_next_hop's out */
+    rdist_info *info_host;     /* nullable: the solve's info, valid once the request is reported done */
+} rdist_request;
+
+/* Creates a server on ctx with `slots` streams (1..64), an HBM budget for
+ * the footprint of requests in flight (0: unbounded) and a batch limit
+ * (1..1024).  A request's footprint is 8 np^2 + 4096 np bytes (np = n
+ * rounded up to 128), twice that for path requests (the kept Y). */
+rdist_status rdist_server_create(rdist_ctx ctx, int32_t slots, size_t hbm_budget_bytes, int32_t max_batch,
+                                 rdist_server *out);
+
+/* Queues a copy of *req.  RDIST_E_ARG for bad fields; RDIST_E_NOMEM when
+ * its footprint alone exceeds the budget (it could never be admitted). */
+rdist_status rdist_server_submit(rdist_server s, const rdist_request *req);
+
+/* Finished requests since the last call: their ids into done_ids (up to
+ * max), their count into *n_done; then dispatches what fits.  Never blocks
+ * on the device.  A request whose solve failed to launch is reported done
+ * with info_host->status set (when given) and counted in rdist_server_stats. */
+rdist_status rdist_server_poll(rdist_server s, int64_t *done_ids, int32_t max, int32_t *n_done);
+
+typedef struct rdist_server_stats {
+    int64_t submitted, completed, failed;
+    int64_t queued, in_flight;         /* now */
+    int64_t batches, batched_requests; /* batched dispatches and the requests they carried */
+    int64_t max_in_flight;             /* most requests in flight at once */
+    size_t footprint_in_flight, max_footprint_in_flight;
+} rdist_server_stats;
+
+rdist_status rdist_server_stats_get(rdist_server s, rdist_server_stats *out);
+
+/* Waits for everything in flight, then frees the server (not the context). */
+void rdist_server_destroy(rdist_server s);
+
 /* Per-kernel timing collected with HIP events on the launching stream. */
 typedef struct rdist_kernel_stats {
     int64_t launches;        /* timed launches since the last reset */

@@ -434,13 +434,15 @@ BatchPlan *lookup_plan(rdist_ctx c, hipStream_t s, uint32_t flags, int count, co
 
 }  // namespace
 
+void free_transient_plan(rdist_ctx c, Workspace &w) {
+    free_plan(c, w.transient);
+    w.transient = nullptr;
+}
+
 void destroy_plans(rdist_ctx c) {
     for (BatchPlan *p : c->plans) free_plan(c, p);
     c->plans.clear();
-    for (auto &kv : c->ws) {
-        free_plan(c, kv.second.transient);
-        kv.second.transient = nullptr;
-    }
+    for (auto &kv : c->ws) free_transient_plan(c, kv.second);
     if (c->capture) (void)hipStreamDestroy(c->capture);
     if (c->capture_aux) (void)hipStreamDestroy(c->capture_aux);
     if (c->capture_aux2) (void)hipStreamDestroy(c->capture_aux2);

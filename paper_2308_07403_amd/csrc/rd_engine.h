@@ -169,8 +169,12 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
                          rdist_info *info, hipStream_t s);
 void destroy_blas(rdist_ctx c);
 
+void free_workspace(rdist_ctx c, Workspace &w);
+void release_stream_workspace(rdist_ctx c, hipStream_t s);
+
 // rd_batch.hip
 void destroy_plans(rdist_ctx c);
+void free_transient_plan(rdist_ctx c, Workspace &w);
 void load_tile_cache(rdist_ctx c);
 void save_tile_cache(rdist_ctx c);
 

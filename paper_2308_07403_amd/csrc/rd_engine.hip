@@ -356,6 +356,31 @@ rdist_status solve_small(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
     return copy_info(info, w.dinfo(), 1, s);
 }
 
+// Frees everything a workspace holds (its buffers, lookahead streams and
+// events, its transient batched plan).
+void free_workspace(rdist_ctx c, Workspace &w) {
+    free_transient_plan(c, w);
+    for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2, &w.Pt2, &w.small,
+                   &w.m32, &w.v32, &w.u32, &w.s64, &w.p32, &w.cert, &w.csr_cnt, &w.csr_off, &w.csr_col, &w.r32,
+                   &w.c32})
+        release(c, *b);
+    for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
+        if (e) (void)hipEventDestroy(e);
+    if (w.aux) (void)hipStreamDestroy(w.aux);
+    if (w.aux2) (void)hipStreamDestroy(w.aux2);
+    w = Workspace{};
+}
+
+// Drops the workspace of a stream that is about to be destroyed (its work
+// must have finished), so that a later stream with the same handle starts
+// afresh and the memory returns to the budget.
+void release_stream_workspace(rdist_ctx c, hipStream_t s) {
+    auto it = c->ws.find(s);
+    if (it == c->ws.end()) return;
+    free_workspace(c, it->second);
+    c->ws.erase(it);
+}
+
 }  // namespace eng
 }  // namespace rd
 
@@ -416,17 +441,8 @@ void rdist_destroy(rdist_ctx c) {
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
         std::vector<rdist_graph_s *> gs(c->graphs.begin(), c->graphs.end());
         for (auto *gr : gs) release_graph_locked(gr);
-        for (auto &kv : c->ws) {
-            Workspace &w = kv.second;
-            for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2,
-                           &w.Pt2, &w.small, &w.m32, &w.v32, &w.u32, &w.s64, &w.p32, &w.cert, &w.csr_cnt,
-                           &w.csr_off, &w.csr_col, &w.r32, &w.c32})
-                release(c, *b);
-            for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
-                if (e) (void)hipEventDestroy(e);
-            if (w.aux) (void)hipStreamDestroy(w.aux);
-            if (w.aux2) (void)hipStreamDestroy(w.aux2);
-        }
+        for (auto &kv : c->ws) free_workspace(c, kv.second);
+        c->ws.clear();
     }
     delete c;
 }

@@ -68,6 +68,24 @@ class rdist_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class rdist_request(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("A_dev", ctypes.c_void_p), ("n", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("D_host", ctypes.c_void_p), ("cur_host", ctypes.c_void_p),
+                ("goal_host", ctypes.c_void_p),
+                ("q", ctypes.c_int32), ("max_hops", ctypes.c_int32), ("paths_host", ctypes.c_void_p),
+                ("info_host", ctypes.c_void_p)]
+
+
+class rdist_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("batched_requests", ctypes.c_int64), ("max_in_flight", ctypes.c_int64),
+                ("footprint_in_flight", ctypes.c_size_t), ("max_footprint_in_flight", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class rdist_kernel_stats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -104,6 +122,17 @@ _lib.rdist_last_error.argtypes = []
 _lib.rdist_last_error.restype = ctypes.c_char_p
 _lib.rdist_status_string.argtypes = [ctypes.c_int]
 _lib.rdist_status_string.restype = ctypes.c_char_p
+_lib.rdist_server_create.argtypes = [_P, ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(_P)]
+_lib.rdist_server_create.restype = ctypes.c_int
+_lib.rdist_server_submit.argtypes = [_P, ctypes.POINTER(rdist_request)]
+_lib.rdist_server_submit.restype = ctypes.c_int
+_lib.rdist_server_poll.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)]
+_lib.rdist_server_poll.restype = ctypes.c_int
+_lib.rdist_server_stats_get.argtypes = [_P, ctypes.POINTER(rdist_server_stats)]
+_lib.rdist_server_stats_get.restype = ctypes.c_int
+_lib.rdist_server_destroy.argtypes = [_P]
+_lib.rdist_server_destroy.restype = None
 
 # Raw C entry points under their C names.
 rdist_create = _lib.rdist_create
@@ -119,10 +148,19 @@ rdist_kernel_stats_get = _lib.rdist_kernel_stats_get
 rdist_hbm_in_use = _lib.rdist_hbm_in_use
 rdist_last_error = _lib.rdist_last_error
 rdist_status_string = _lib.rdist_status_string
+rdist_server_create = _lib.rdist_server_create
+rdist_server_submit = _lib.rdist_server_submit
+rdist_server_poll = _lib.rdist_server_poll
+rdist_server_stats_get = _lib.rdist_server_stats_get
+rdist_server_destroy = _lib.rdist_server_destroy
 
 EXPORTS = ("rdist_create", "rdist_destroy", "rdist_solve", "rdist_solve_batched", "rdist_next_hop",
            "rdist_graph_release", "rdist_graph_y", "rdist_epilogue", "rdist_set_timing",
-           "rdist_kernel_stats_get", "rdist_hbm_in_use", "rdist_last_error", "rdist_status_string")
+           "rdist_kernel_stats_get", "rdist_hbm_in_use", "rdist_last_error", "rdist_status_string",
+           "rdist_server_create", "rdist_server_submit", "rdist_server_poll", "rdist_server_stats_get",
+           "rdist_server_destroy")
+RDIST_QUERY_D = 0
+RDIST_QUERY_PATHS = 1
 
 
 class RdistError(RuntimeError):
@@ -309,3 +347,58 @@ class Context:
 
     def hbm_in_use(self) -> int:
         return int(rdist_hbm_in_use(self.handle))
+
+
+class Server:
+    """The engine's request loop (continuous batching, HBM-footprint admission).
+
+    submit() queues a request (A on the device, results into pinned host
+    buffers the caller keeps alive until the request is reported done);
+    poll() returns the ids finished since the last call and dispatches more.
+    """
+
+    def __init__(self, ctx: Context, slots: int = 8, hbm_budget: int = 0, max_batch: int = 64):
+        self.ctx = ctx
+        h = _P()
+        _check(rdist_server_create(ctx.handle, slots, hbm_budget, max_batch, ctypes.byref(h)), "rdist_server_create")
+        self.handle = h.value
+        self._ids = (ctypes.c_int64 * 4096)()
+        self._req = rdist_request()
+
+    def submit(self, rid: int, A: torch.Tensor, gamma: float, kind: int = RDIST_QUERY_D, D_host=None,
+               cur_host=None, goal_host=None, max_hops: int = 64, paths_host=None, info_ptr: int = 0):
+        r = self._req
+        r.id = rid
+        r.A_dev = A.data_ptr()
+        r.n = int(A.shape[0])
+        r.kind = kind
+        r.gamma = float(gamma)
+        r.D_host = D_host.data_ptr() if D_host is not None else None
+        r.cur_host = cur_host.data_ptr() if cur_host is not None else None
+        r.goal_host = goal_host.data_ptr() if goal_host is not None else None
+        r.q = int(cur_host.numel()) if cur_host is not None else 0
+        r.max_hops = max_hops
+        r.paths_host = paths_host.data_ptr() if paths_host is not None else None
+        r.info_host = info_ptr or None
+        return rdist_server_submit(self.handle, ctypes.byref(r))
+
+    def poll(self) -> list:
+        n = ctypes.c_int32()
+        _check(rdist_server_poll(self.handle, self._ids, 4096, ctypes.byref(n)), "rdist_server_poll")
+        return [self._ids[i] for i in range(n.value)]
+
+    def stats(self) -> dict:
+        s = rdist_server_stats()
+        _check(rdist_server_stats_get(self.handle, ctypes.byref(s)), "rdist_server_stats_get")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            rdist_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,125 @@
+"""GPU: the request loop (rdist_server_*): continuous batching, admission by
+HBM footprint, and results that are bit-for-bit those of the same request
+solved alone; spot checks against the oracle."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2308_07403_amd import rdist as R  # noqa: E402
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def footprint(n, kind):
+    np_ = (n + 127) // 128 * 128
+    f = 8 * np_ * np_ + 4096 * np_
+    return 2 * f if kind == R.RDIST_QUERY_PATHS else f
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def make_requests(count, stream_index, n_hi):
+    reqs = gg.c5_requests(count, qps=100.0, stream_index=stream_index, n_lo=32, n_hi=n_hi, pairs_per_request=16)
+    out = []
+    for r in reqs:
+        A = r.spec.build()
+        kind = R.RDIST_QUERY_D if r.query == "D" else R.RDIST_QUERY_PATHS
+        n = A.shape[0]
+        item = {"id": r.rid, "A_np": A, "A": torch.from_numpy(A).cuda(), "kind": kind, "n": n,
+                "info": R.PinnedInfo(1)}
+        if kind == R.RDIST_QUERY_D:
+            item["D"] = torch.empty((n, n), dtype=torch.int16, pin_memory=True)
+        else:
+            item["cur"] = torch.from_numpy(r.pairs[:, 0].copy()).pin_memory()
+            item["goal"] = torch.from_numpy(r.pairs[:, 1].copy()).pin_memory()
+            item["paths"] = torch.empty((len(r.pairs), 33), dtype=torch.int32, pin_memory=True)
+        out.append(item)
+    return out
+
+
+def run_server(srv, items, timeout_s=120.0):
+    for it in items:
+        if it["kind"] == R.RDIST_QUERY_D:
+            st = srv.submit(it["id"], it["A"], -0.5, R.RDIST_QUERY_D, D_host=it["D"], info_ptr=it["info"].at(0))
+        else:
+            st = srv.submit(it["id"], it["A"], -0.5, R.RDIST_QUERY_PATHS, cur_host=it["cur"], goal_host=it["goal"],
+                            max_hops=32, paths_host=it["paths"], info_ptr=it["info"].at(0))
+        assert st == R.RDIST_OK, R.rdist_last_error()
+    done = set()
+    t0 = time.time()
+    while len(done) < len(items):
+        done.update(srv.poll())
+        assert time.time() - t0 < timeout_s, f"only {len(done)} of {len(items)} finished"
+        time.sleep(0.0005)
+    return done
+
+
+def test_server_mix_is_bitwise_alone(ctx):
+    items = make_requests(40, stream_index=7, n_hi=900)
+    budget = 3 * footprint(900, R.RDIST_QUERY_PATHS)
+    srv = R.Server(ctx, slots=4, hbm_budget=budget, max_batch=8)
+    note(f"[server] {len(items)} requests, budget {budget >> 20} MiB")
+    done = run_server(srv, items)
+    st = srv.stats()
+    note(f"[server] stats {st}")
+    srv.close()
+    assert done == {it["id"] for it in items}
+    assert st["completed"] == len(items) and st["failed"] == 0
+    assert st["max_footprint_in_flight"] <= budget
+    assert st["batches"] >= 1 and st["max_in_flight"] >= 2
+    # each result equals the same request solved alone
+    for it in items:
+        info = it["info"].get(0)
+        A = it["A"]
+        if it["kind"] == R.RDIST_QUERY_D:
+            D, ainfo, _ = ctx.solve(A, -0.5)
+            assert info.status == ainfo["status"]
+            assert np.array_equal(it["D"].numpy(), D.cpu().numpy()), f"request {it['id']} n={it['n']}"
+        else:
+            _, ainfo, g = ctx.solve(A, -0.5, keep=True)
+            alone = ctx.next_hop(g, it["cur"].cuda(), it["goal"].cuda(), max_hops=32)
+            torch.cuda.synchronize()
+            g.release()
+            assert info.status == ainfo["status"]
+            assert np.array_equal(it["paths"].numpy(), alone.cpu().numpy()), f"request {it['id']} paths"
+
+
+def test_server_oracle_spot_checks(ctx):
+    items = make_requests(12, stream_index=8, n_hi=400)
+    srv = R.Server(ctx, slots=3, hbm_budget=0, max_batch=4)
+    run_server(srv, items)
+    srv.close()
+    for it in items[::3]:
+        if it["kind"] != R.RDIST_QUERY_D:
+            continue
+        sol = oracle.solve(it["A_np"], -0.5, keep_y=False)
+        assert it["info"].get(0).status == sol.status
+        assert np.array_equal(it["D"].numpy(), sol.D)
+
+
+def test_server_refuses_what_never_fits(ctx):
+    srv = R.Server(ctx, slots=2, hbm_budget=footprint(256, R.RDIST_QUERY_D), max_batch=4)
+    A = torch.from_numpy(gg.erdos_renyi(600, 0.02, gg.rng_for("parity", 9100))).cuda()
+    D = torch.empty((600, 600), dtype=torch.int16, pin_memory=True)
+    assert srv.submit(1, A, -0.5, R.RDIST_QUERY_D, D_host=D) == R.RDIST_E_NOMEM
+    assert srv.submit(2, A, 1.5, R.RDIST_QUERY_D, D_host=D) == R.RDIST_E_ARG
+    srv.close()
