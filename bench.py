@@ -176,6 +176,25 @@ def bench_c2(args, torch, R, gg):
     e1.record(stream)
     torch.cuda.synchronize()
     nh_ms = e0.elapsed_time(e1)
+    # the readout as its own pass over the kept Y (the unfused epilogue): HBM-bound, 10 B per entry
+    import ctypes
+    yp, nn, ld = ctypes.c_void_p(), ctypes.c_int32(), ctypes.c_int32()
+    R.rdist_graph_y(g.handle, ctypes.byref(yp), ctypes.byref(nn), ctypes.byref(ld))
+    D_unf = torch.empty_like(D)
+    sp = stream.cuda_stream
+    R.rdist_epilogue(ctx.handle, yp, n, ld.value, st["gamma"], D_unf.data_ptr(), info.at(0), sp)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for _ in range(5):
+        R.rdist_epilogue(ctx.handle, yp, n, ld.value, st["gamma"], D_unf.data_ptr(), info.at(0), sp)
+    torch.cuda.synchronize()
+    ep = ctx.kernel_stats(R.RDIST_K_EPILOGUE)
+    ctx.set_timing(False)
+    ep_ms = ep["total_ms"] / max(ep["launches"], 1)
+    epilogue = {"kernel": "k_epilogue (standalone readout over Y, ld = padded n)", "ms": ep_ms,
+                "bytes_per_launch": 10.0 * n * n, "achieved_gbs": 10.0 * n * n / (ep_ms * 1e-3) / 1e9,
+                "frac_hbm_peak": 10.0 * n * n / (ep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "d_equals_fused": bool(torch.equal(D_unf, D))}
     g.release()
     mixed = None
     if not args.no_mixed:
@@ -219,6 +238,7 @@ def bench_c2(args, torch, R, gg):
                                (("update_rest", upd), ("update_edge_and_last", edge), ("panel", panel),
                                 ("rowcol", rowcol), ("ingest", ingest))},
         "next_hop_64_paths_ms": nh_ms,
+        "epilogue_unfused": epilogue,
         "mixed": mixed,
         "solve_info": {k: st[k] for k in ("status", "n_unreachable", "n_subnormal", "n_ambiguous")},
     }

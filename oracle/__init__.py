@@ -148,6 +148,17 @@ def readout(Y, gamma: float, eta: float = ETA, beta: float = BETA) -> Readout:
     return Readout(D, *[int(x) for x in c])
 
 
+def readout_entries(y, gamma: float, eta: float = ETA, beta: float = BETA) -> np.ndarray:
+    """The readout of orc_readout applied to a vector of Y entries (e.g. one
+    column from the series): the entries are laid into a square block (the
+    rest filled with 1.0) and read out by the same routine."""
+    y = np.asarray(y, dtype=np.float64).ravel()
+    m = max(1, int(np.ceil(np.sqrt(y.size))))
+    blk = np.ones(m * m, dtype=np.float64)
+    blk[: y.size] = y
+    return readout(blk.reshape(m, m), gamma, eta, beta).D.ravel()[: y.size]
+
+
 @dataclass
 class Solution:
     status: int

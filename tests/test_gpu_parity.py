@@ -345,14 +345,14 @@ def test_batched_medium_refusals(ctx):
     check_batch(As, gam, Ds, info, None, "refusals")
 
 
-def test_batched_c3_full_batch_sampled(ctx):
-    """The 1024-graph batch in one launch; every 16th graph against the oracle."""
+def test_batched_c3_full_batch(ctx):
+    """The 1024-graph batch (the bench's batch, through the captured plan): D of
+    every graph against the oracle."""
     specs = gg.c3_specs(1024, batch_index=0)
     As = [s.build() for s in specs]
     note(f"[parity] C3 batch count={len(As)}")
     Ds, info, _ = ctx.solve_batched([dev(A) for A in As], -0.5)
-    idx = list(range(0, 1024, 16))
-    check_batch([As[k] for k in idx], -0.5, [Ds[k] for k in idx], _Sub(info, idx), None, "c3")
+    check_batch(As, -0.5, Ds, info, None, "c3")
 
 
 class _Sub:
@@ -438,6 +438,76 @@ def test_batched_with_large_graphs(ctx):
         if graphs:
             for g in graphs:
                 g.release()
+
+
+# ---------------------------------------------------------------------------
+# Full sizes (the bench's launch configuration): sampled rows and columns of Y
+# from the oracle's series, one by one; closed forms at any size
+# ---------------------------------------------------------------------------
+
+def check_sampled(A_np, Yg, Dg, gamma, cols, rows, label):
+    Yh = None
+    for j in cols:
+        y = oracle.y_column(A_np, gamma, j)
+        yg = Yg[:, j].cpu().numpy()
+        dg = Dg[:, j].cpu().numpy()
+        assert np.array_equal(yg == 0.0, y == 0.0), f"{label} col {j} zero pattern"
+        nz = y >= DBL_MIN
+        assert np.max(np.abs(yg[nz] - y[nz]) / y[nz]) <= Y_TOL, f"{label} col {j}"
+        assert np.array_equal(dg, oracle.readout_entries(y, gamma)), f"{label} col {j} D"
+    for i in rows:
+        y = oracle.y_row(A_np, gamma, i)
+        yg = Yg[i, :].cpu().numpy()
+        dg = Dg[i, :].cpu().numpy()
+        assert np.array_equal(yg == 0.0, y == 0.0), f"{label} row {i} zero pattern"
+        nz = y >= DBL_MIN
+        assert np.max(np.abs(yg[nz] - y[nz]) / y[nz]) <= Y_TOL, f"{label} row {i}"
+        assert np.array_equal(dg, oracle.readout_entries(y, gamma)), f"{label} row {i} D"
+    return Yh
+
+
+def test_c2_full_size_sampled_rows_and_columns(ctx):
+    A_np = gg.c2_graph(0)
+    note("[parity] C2 n=8192 full size")
+    prep = oracle.prepare(A_np, -0.5)
+    D, info, g = ctx.solve(dev(A_np), -0.5, keep=True)
+    assert info["status"] == 0 and info["delta"] == prep.delta and info["gamma"] == prep.gamma
+    Yg = g.y()
+    check_sampled(A_np, Yg, D, prep.gamma, cols=[0, 1234, 4097, 8191], rows=[7, 2048, 6000], label="c2")
+    del Yg
+    g.release()
+
+
+def test_c4_full_size_fp64_sampled(ctx):
+    A_np = gg.c4_graph(0)
+    note("[parity] C4 n=16384 full size (FP64)")
+    prep = oracle.prepare(A_np, -0.5)
+    D, info, g = ctx.solve(dev(A_np), -0.5, keep=True)
+    assert info["status"] == 0 and info["gamma"] == prep.gamma
+    Yg = g.y()
+    check_sampled(A_np, Yg, D, prep.gamma, cols=[3, 16383], rows=[9000], label="c4")
+    del Yg
+    g.release()
+
+
+def test_complete_digraph_full_size_closed_form(ctx):
+    """K_n at n = 8192: Y = [I + gamma J / (1 - (n-1) gamma)] / (1 + gamma)
+    (Sherman-Morrison), so D = 1 off the diagonal and 0 on it."""
+    n = 8192
+    A = torch.ones((n, n), dtype=torch.uint8, device="cuda")
+    A.fill_diagonal_(0)
+    D, info, g = ctx.solve(A, -0.5, keep=True)
+    gam = info["gamma"]
+    assert info["delta"] == n - 1 and gam == 0.5 / (n - 1)
+    off = gam / ((1.0 + gam) * (1.0 - (n - 1) * gam))
+    diag = (1.0 + gam / (1.0 - (n - 1) * gam)) / (1.0 + gam)
+    Y = g.y()
+    eye = torch.eye(n, dtype=torch.bool, device="cuda")
+    assert torch.max(torch.abs(Y[~eye] - off)).item() / off <= Y_TOL
+    assert torch.max(torch.abs(Y[eye] - diag)).item() / diag <= Y_TOL
+    assert bool((D[~eye] == 1).all()) and bool((D[eye] == 0).all())
+    del Y
+    g.release()
 
 
 # ---------------------------------------------------------------------------

@@ -451,3 +451,14 @@ def test_series_directed_path_exact_powers():
     col = oracle.y_column(A, 0.5, 3)
     assert np.array_equal(col[3:], 0.5 ** np.arange(27))
     assert np.all(col[:3] == 0.0)
+
+
+def test_readout_entries_is_the_matrix_readout():
+    """The vector form used for full-size spot checks agrees with the matrix readout."""
+    rng = np.random.default_rng(5)
+    Y = np.exp(-rng.uniform(0, 40, size=(37, 37)))
+    Y[3, 4] = 0.0
+    g = 0.05
+    full = oracle.readout(Y, g).D
+    assert np.array_equal(oracle.readout_entries(Y[:, 4], g), full[:, 4])
+    assert np.array_equal(oracle.readout_entries(Y[10], g), full[10])
