@@ -395,6 +395,7 @@ rdist_status autotune(rdist_ctx c, hipStream_t s, uint32_t flags, int count, con
     Workspace &w = c->ws[s];
     rdist_status st;
     if ((st = ensure_aux(w))) return st;
+    if ((st = ensure_aux2(w))) return st;
     if (!w.transient) w.transient = new BatchPlan();
     BatchPlan &p = *w.transient;
     hipEvent_t e0 = take_event(c), e1 = take_event(c);
@@ -523,6 +524,7 @@ extern "C" rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const in
     hipStream_t s = (hipStream_t)stream;
     Workspace &w = c->ws[s];
     if ((st = ensure_aux(w))) return st;
+    if ((st = ensure_aux2(w))) return st;
 
     BatchTuning tune;
     {

@@ -128,6 +128,7 @@ rdist_status ensure(rdist_ctx c, Buf &b, size_t bytes);
 void release(rdist_ctx c, Buf &b);
 rdist_status ensure_small(rdist_ctx c, Workspace &w, int n);
 rdist_status ensure_aux(Workspace &w);
+rdist_status ensure_aux2(Workspace &w);
 
 hipEvent_t take_event(rdist_ctx c);
 

@@ -98,15 +98,21 @@ rdist_status ensure_big(rdist_ctx c, Workspace &w, int np) {
     return ensure_aux(w);
 }
 
+// The workspace's second auxiliary stream (the batched plans' persistent
+// kernel), created on first use.
+rdist_status ensure_aux2(Workspace &w) {
+    if (!w.aux2 && hipStreamCreateWithFlags(&w.aux2, hipStreamNonBlocking) != hipSuccess) {
+        w.aux2 = nullptr;
+        return fail(RDIST_E_HIP, "hipStreamCreateWithFlags failed");
+    }
+    return RDIST_OK;
+}
+
 // The workspace's auxiliary stream (default priority) and its events.
 rdist_status ensure_aux(Workspace &w) {
     if (!w.aux) {
         if (hipStreamCreateWithFlags(&w.aux, hipStreamNonBlocking) != hipSuccess) {
             w.aux = nullptr;
-            return fail(RDIST_E_HIP, "hipStreamCreateWithFlags failed");
-        }
-        if (hipStreamCreateWithFlags(&w.aux2, hipStreamNonBlocking) != hipSuccess) {
-            w.aux2 = nullptr;
             return fail(RDIST_E_HIP, "hipStreamCreateWithFlags failed");
         }
         if (hipEventCreateWithFlags(&w.ev_er, hipEventDisableTiming) != hipSuccess ||
@@ -228,7 +234,7 @@ void enqueue_inverse(rdist_ctx c, Workspace &w, int ld, int K0, int m, int par, 
     for (int k2 = 0; k2 < 2; ++k2) {
         rd::launch_panel(S, ld, k2, Pt2, V2, 256, dinfo, st);
         rd::launch_rowcol(S, ld, 2, k2, 1, Pt2, Ut2, V2, 256, dinfo, st);
-        rd::launch_update(rd::kUpdateAll, S, ld, 2, k2, 1, 0, Ut2, V2, 256, false, 0, nullptr, 0, dinfo, st);
+        rd::launch_update(rd::kUpdateAll, S, ld, 2, k2, 1, 0, 1, Ut2, V2, 256, false, 0, nullptr, 0, dinfo, st);
     }
     rd::launch_panel_finish(S, ld, 256, K0, Pt, V, ld, dinfo, st);
 }
@@ -242,17 +248,20 @@ void enqueue_rowcol(rdist_ctx c, Workspace &w, int ld, int nt, int K0, int m, in
 }
 
 // Blocked solve of one graph on stream s: blocks of b = 128*m columns.
-// Step K's update is split by what the next block needs:
+// Step K's update is split by what the lookahead needs (lookahead depth 2):
 //   DIAG      the next block's diagonal tiles (its inverse needs only these),
-//   EDGEREST  the rest of its tile rows and columns (its row/column prep),
+//   EDGEREST  the rest of the next two blocks' tile rows and columns,
 //   REST      everything else.
-// Schedule of step K (s = caller's stream, aux = auxiliary stream):
-//   s  : wait ev_panel; EDGEREST(K); record ev_er; REST(K); record ev_rest
-//   aux: DIAG(K); inverse(K+1); wait ev_er; rowcol(K+1); record ev_panel;
-//        wait ev_rest
-// so the next block's inverse runs beside the big update.  U, V and P^T are
-// double-buffered by step parity, so step K+1's preparation never
-// overwrites what step K's update still reads.
+// Schedule of step K (s = caller's stream, aux = lookahead stream):
+//   s  : wait ev_panel (step K's row/column tiles); EDGEREST(K);
+//        record ev_er; REST(K)
+//   aux: DIAG(K); inverse(K+1); wait ev_er; row/column tiles (K+1);
+//        record ev_panel
+// DIAG(K) reads the next-next block's tiles as EDGEREST(K-1) left them, so the
+// lookahead chain never waits for a REST update: the next block's inverse
+// runs beside the big update.  U, V and P^T are double-buffered by step
+// parity; a step's buffers are rewritten only after the main stream has
+// passed the EDGEREST that follows the REST reading them.
 rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
                            rdist_graph *keep, rdist_info *info, hipStream_t s) {
     Workspace &w = c->ws[s];
@@ -275,9 +284,11 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
     RD_HIP(hipGetLastError());
     enqueue_inverse(c, w, ld, 0, m, 0, dinfo, s);
     enqueue_rowcol(c, w, ld, nt, 0, m, 0, dinfo, s);
+    // streams of the step loop: the caller's stream and the lookahead stream
+    hipStream_t ms = s, as = w.aux;
     if (nbk > 1) {
-        RD_HIP(hipEventRecord(w.ev_rest, s));
-        RD_HIP(hipStreamWaitEvent(w.aux, w.ev_rest, 0));
+        RD_HIP(hipEventRecord(w.ev_panel, ms));          // block 0's row/column tiles are ready
+        RD_HIP(hipStreamWaitEvent(as, w.ev_panel, 0));
     }
     const double tile_flops = 2.0 * kB * kB * bw;
     for (int K = 0; K < nbk; ++K) {
@@ -286,33 +297,34 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
         const double *Ut = (const double *)w.Ut[par].p, *V = (const double *)w.V[par].p;
         if (K + 1 < nbk) {
             const int L0 = K0 + m;
-            const int td = rd::update_tiles(rd::kUpdateDiag, nt, m);
-            const int te = rd::update_tiles(rd::kUpdateEdgeRest, nt, m);
-            const int tr = rd::update_tiles(rd::kUpdateRest, nt, m);
-            if (K > 0) RD_HIP(hipStreamWaitEvent(s, w.ev_panel, 0));
+            const int wt = std::min(2 * m, nt - L0);      // the next two blocks' tile rows and columns
+            const int td = rd::update_tiles(rd::kUpdateDiag, nt, m, wt);
+            const int te = rd::update_tiles(rd::kUpdateEdgeRest, nt, m, wt);
+            const int tr = rd::update_tiles(rd::kUpdateRest, nt, m, wt);
+            if (K > 0) RD_HIP(hipStreamWaitEvent(ms, w.ev_panel, 0));
             {
-                Timer t(c, s, RDIST_K_UPDATE_EDGE, tile_flops * te, 16.0 * kB * kB * te);
-                rd::launch_update(rd::kUpdateEdgeRest, M, ld, nt, K0, m, L0, Ut, V, ld, false, n, D, 0, dinfo, s);
+                Timer t(c, ms, RDIST_K_UPDATE_EDGE, tile_flops * te, 16.0 * kB * kB * te);
+                rd::launch_update(rd::kUpdateEdgeRest, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo,
+                                  ms);
             }
-            RD_HIP(hipEventRecord(w.ev_er, s));
+            RD_HIP(hipEventRecord(w.ev_er, ms));
             {
-                Timer t(c, s, RDIST_K_UPDATE, tile_flops * tr, 16.0 * kB * kB * tr);
-                rd::launch_update(rd::kUpdateRest, M, ld, nt, K0, m, L0, Ut, V, ld, false, n, D, 0, dinfo, s);
+                Timer t(c, ms, RDIST_K_UPDATE, tile_flops * tr, 16.0 * kB * kB * tr);
+                rd::launch_update(rd::kUpdateRest, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo, ms);
             }
-            RD_HIP(hipEventRecord(w.ev_rest, s));
             {
-                Timer t(c, w.aux, RDIST_K_UPDATE_EDGE, tile_flops * td, 16.0 * kB * kB * td);
-                rd::launch_update(rd::kUpdateDiag, M, ld, nt, K0, m, L0, Ut, V, ld, false, n, D, 0, dinfo, w.aux);
+                Timer t(c, as, RDIST_K_UPDATE_EDGE, tile_flops * td, 16.0 * kB * kB * td);
+                rd::launch_update(rd::kUpdateDiag, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo, as);
             }
-            enqueue_inverse(c, w, ld, L0, m, par ^ 1, dinfo, w.aux);
-            RD_HIP(hipStreamWaitEvent(w.aux, w.ev_er, 0));
-            enqueue_rowcol(c, w, ld, nt, L0, m, par ^ 1, dinfo, w.aux);
-            RD_HIP(hipEventRecord(w.ev_panel, w.aux));
-            RD_HIP(hipStreamWaitEvent(w.aux, w.ev_rest, 0));
+            enqueue_inverse(c, w, ld, L0, m, par ^ 1, dinfo, as);
+            RD_HIP(hipStreamWaitEvent(as, w.ev_er, 0));
+            enqueue_rowcol(c, w, ld, nt, L0, m, par ^ 1, dinfo, as);
+            RD_HIP(hipEventRecord(w.ev_panel, as));
         } else {
-            if (K > 0) RD_HIP(hipStreamWaitEvent(s, w.ev_panel, 0));
-            Timer t(c, s, RDIST_K_UPDATE_EDGE, tile_flops * nt * nt, 16.0 * kB * kB * nt * nt);
-            rd::launch_update(rd::kUpdateAll, M, ld, nt, K0, m, 0, Ut, V, ld, fused, n, D, keep_y ? 1 : 0, dinfo, s);
+            if (K > 0) RD_HIP(hipStreamWaitEvent(ms, w.ev_panel, 0));
+            Timer t(c, ms, RDIST_K_UPDATE_EDGE, tile_flops * nt * nt, 16.0 * kB * kB * nt * nt);
+            rd::launch_update(rd::kUpdateAll, M, ld, nt, K0, m, 0, m, Ut, V, ld, fused, n, D, keep_y ? 1 : 0, dinfo,
+                              ms);
         }
         RD_HIP(hipGetLastError());
     }

@@ -220,12 +220,13 @@ __global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, in
     transpose_neg(M + (size_t)I * kTile * ld + (size_t)K0 * kTile, ld, 2 * m, out, ldv, lds);
 }
 
-// Tile sets of one update, with [L0, L0 + m) the next block's tile range:
+// Tile sets of one update, with [L0, L0 + m) the next block's tile range and
+// [L0, L0 + wt) the band of tile rows and columns the lookahead needs early
+// (the next block's, or the next two blocks'):
 //   ALL       every tile;
-//   REST      tiles outside the next block's tile rows and columns;
+//   REST      tiles outside the band's rows and columns;
 //   DIAG      the next block's m x m diagonal tiles (all its inverse needs);
-//   EDGEREST  the next block's tile rows and columns minus DIAG (what its
-//             row/column preparation needs besides DIAG).
+//   EDGEREST  the band's tile rows and columns minus DIAG.
 enum { kAll = 0, kDiag = 1, kRest = 2, kEdgeRest = 3 };
 
 // Order of the tiles of an nr x nr grid for a big launch.  Workgroups are
@@ -247,29 +248,35 @@ __device__ __forceinline__ void xcd_strip_order(int b, int nr, int &i, int &j) {
 }
 
 template <int MODE>
-__device__ __forceinline__ void update_tile_index(int b, int nt, int L0, int m, int &I, int &J) {
+__device__ __forceinline__ void update_tile_index(int b, int nt, int L0, int m, int wt, int &I, int &J) {
     if (MODE == kAll) {
         xcd_strip_order(b, nt, I, J);
     } else if (MODE == kDiag) {
         I = L0 + b / m;
         J = L0 + (b - (b / m) * m);
     } else if (MODE == kEdgeRest) {
-        const int w = nt - m;
-        if (b < m * w) {
-            I = L0 + b / w;
-            const int Jp = b - (b / w) * w;
+        // tile rows [L0, L0 + wt) (minus the m x m diagonal block at L0),
+        // then tile columns [L0, L0 + wt) outside those rows
+        const int r1 = m * (nt - m), r2 = r1 + (wt - m) * nt;
+        if (b < r1) {
+            I = L0 + b / (nt - m);
+            const int Jp = b - (b / (nt - m)) * (nt - m);
             J = Jp < L0 ? Jp : Jp + m;
+        } else if (b < r2) {
+            const int q = b - r1;
+            I = L0 + m + q / nt;
+            J = q - (q / nt) * nt;
         } else {
-            const int q = b - m * w;
-            const int Ip = q / m;
-            J = L0 + (q - Ip * m);
-            I = Ip < L0 ? Ip : Ip + m;
+            const int q = b - r2;
+            const int Ip = q / wt;
+            J = L0 + (q - Ip * wt);
+            I = Ip < L0 ? Ip : Ip + wt;
         }
     } else {
         int Ip, Jp;
-        xcd_strip_order(b, nt - m, Ip, Jp);
-        I = Ip < L0 ? Ip : Ip + m;
-        J = Jp < L0 ? Jp : Jp + m;
+        xcd_strip_order(b, nt - wt, Ip, Jp);
+        I = Ip < L0 ? Ip : Ip + wt;
+        J = Jp < L0 ? Jp : Jp + wt;
     }
 }
 
@@ -279,7 +286,7 @@ __device__ __forceinline__ void update_tile_index(int b, int nt, int L0, int m, 
 // chunk lands) and add (-U)^T V, Ut holding -U^T.  With FUSED the tile's
 // final value is read out into D (and stored to M only if keep_y).
 template <int MODE, bool FUSED, int MT>
-__global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int ld, int nt, int K0, int L0,
+__global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int ld, int nt, int K0, int L0, int wt,
                                                    const double *__restrict__ Ut, const double *__restrict__ V,
                                                    int ldv, int n, int16_t *__restrict__ D, int keep_y,
                                                    rdist_info *info) {
@@ -287,7 +294,7 @@ __global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int l
     if (info->status != RDIST_OK) return;
     __shared__ double lds[kTileLdsDoubles];
     int I, J;
-    update_tile_index<MODE>(blockIdx.x, nt, L0, m, I, J);
+    update_tile_index<MODE>(blockIdx.x, nt, L0, m, wt, I, J);
     const bool zero_in = (I >= K0 && I < K0 + m) || (J >= K0 && J < K0 + m);
     double *base = M + (size_t)I * kTile * ld + (size_t)J * kTile;
     TileAcc acc;
@@ -1108,41 +1115,37 @@ void launch_rowcol(const double *M, int ld, int nt, int K0, int m, const double 
         hipLaunchKernelGGL(k_rowcol<2>, dim3(3 * nt), dim3(256), 0, s, M, ld, nt, K0, Pt, Ut, V, ldv, info);
 }
 
-int update_tiles(int mode, int nt, int m) {
+int update_tiles(int mode, int nt, int m, int wt) {
     if (mode == kAll) return nt * nt;
     if (mode == kDiag) return m * m;
-    if (mode == kEdgeRest) return 2 * m * (nt - m);
-    return (nt - m) * (nt - m);
+    if (mode == kEdgeRest) return m * (nt - m) + (wt - m) * nt + (nt - wt) * wt;
+    return (nt - wt) * (nt - wt);
 }
 
 template <int MT>
-static void launch_update_t(int mode, double *M, int ld, int nt, int K0, int L0, const double *Ut, const double *V,
-                            int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info, hipStream_t s) {
-    const int tiles = update_tiles(mode, nt, MT);
+static void launch_update_t(int mode, double *M, int ld, int nt, int K0, int L0, int wt, const double *Ut,
+                            const double *V, int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info,
+                            hipStream_t s) {
+    const int tiles = update_tiles(mode, nt, MT, wt);
     if (tiles <= 0) return;
     const dim3 g(tiles), bl(256);
-    if (fused)
-        hipLaunchKernelGGL((k_update<kAll, true, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y, info);
-    else if (mode == kAll)
-        hipLaunchKernelGGL((k_update<kAll, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
-                           info);
-    else if (mode == kDiag)
-        hipLaunchKernelGGL((k_update<kDiag, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
-                           info);
-    else if (mode == kEdgeRest)
-        hipLaunchKernelGGL((k_update<kEdgeRest, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
-                           info);
-    else
-        hipLaunchKernelGGL((k_update<kRest, false, MT>), g, bl, 0, s, M, ld, nt, K0, L0, Ut, V, ldv, n, D, keep_y,
-                           info);
+#define RD_UPD(MODE_, FUSED_) \
+    hipLaunchKernelGGL((k_update<MODE_, FUSED_, MT>), g, bl, 0, s, M, ld, nt, K0, L0, wt, Ut, V, ldv, n, D, keep_y, info)
+    if (fused) RD_UPD(kAll, true);
+    else if (mode == kAll) RD_UPD(kAll, false);
+    else if (mode == kDiag) RD_UPD(kDiag, false);
+    else if (mode == kEdgeRest) RD_UPD(kEdgeRest, false);
+    else RD_UPD(kRest, false);
+#undef RD_UPD
 }
 
-void launch_update(int mode, double *M, int ld, int nt, int K0, int m, int L0, const double *Ut, const double *V,
-                   int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info, hipStream_t s) {
+void launch_update(int mode, double *M, int ld, int nt, int K0, int m, int L0, int wt, const double *Ut,
+                   const double *V, int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info,
+                   hipStream_t s) {
     if (m == 1)
-        launch_update_t<1>(mode, M, ld, nt, K0, L0, Ut, V, ldv, fused, n, D, keep_y, info, s);
+        launch_update_t<1>(mode, M, ld, nt, K0, L0, wt, Ut, V, ldv, fused, n, D, keep_y, info, s);
     else
-        launch_update_t<2>(mode, M, ld, nt, K0, L0, Ut, V, ldv, fused, n, D, keep_y, info, s);
+        launch_update_t<2>(mode, M, ld, nt, K0, L0, wt, Ut, V, ldv, fused, n, D, keep_y, info, s);
 }
 
 void launch_panel_finish(const double *S, int lds, int b, int K0, double *Pt, double *V, int ldv,

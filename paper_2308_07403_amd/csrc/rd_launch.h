@@ -64,11 +64,13 @@ void launch_panel(const double *M, int ld, int K, double *Pt, double *V, int ldv
 // Blocked Gauss-Jordan pieces (tiles are 128 x 128; a block is m tiles wide,
 // starting at tile K0; nt tiles per side).
 enum UpdateMode { kUpdateAll = 0, kUpdateDiag = 1, kUpdateRest = 2, kUpdateEdgeRest = 3 };
-int update_tiles(int mode, int nt, int m);
+int update_tiles(int mode, int nt, int m, int wt);
 void launch_rowcol(const double *M, int ld, int nt, int K0, int m, const double *Pt, double *Ut, double *V,
                    int ldv, const rdist_info *info, hipStream_t s);
-void launch_update(int mode, double *M, int ld, int nt, int K0, int m, int L0, const double *Ut, const double *V,
-                   int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info, hipStream_t s);
+// wt: width in tiles of the band [L0, L0 + wt) of EDGEREST / REST (>= m).
+void launch_update(int mode, double *M, int ld, int nt, int K0, int m, int L0, int wt, const double *Ut,
+                   const double *V, int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info,
+                   hipStream_t s);
 void launch_panel_finish(const double *S, int lds, int b, int K0, double *Pt, double *V, int ldv,
                          const rdist_info *info, hipStream_t s);
 void launch_epilogue(const double *Y, int n, int ld, int16_t *D, rdist_info *info, hipStream_t s);

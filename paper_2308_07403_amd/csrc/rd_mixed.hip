@@ -327,7 +327,7 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
                 rd::launch_panel(S, kMB, k2, (double *)w.Pt2.p, (double *)w.V2.p, kMB, dinfo, s);
                 rd::launch_rowcol(S, kMB, 2, k2, 1, (const double *)w.Pt2.p, (double *)w.Ut2.p, (double *)w.V2.p,
                                   kMB, dinfo, s);
-                rd::launch_update(rd::kUpdateAll, S, kMB, 2, k2, 1, 0, (const double *)w.Ut2.p,
+                rd::launch_update(rd::kUpdateAll, S, kMB, 2, k2, 1, 0, 1, (const double *)w.Ut2.p,
                                   (const double *)w.V2.p, kMB, false, 0, nullptr, 0, dinfo, s);
             }
         }
