@@ -372,7 +372,7 @@ def bench_c5(args, torch, R, gg):
     lat, wall, st_sat, _ = run(np.zeros(n_sat))
     sat = n_sat / wall
     levels = []
-    for frac in (0.5, 0.8):
+    for frac in [float(x) for x in args.c5_levels.split(",") if x.strip()]:
         qps = frac * sat
         reqs = gg.c5_requests(args.c5_requests, qps=qps, stream_index=1)
         arrivals = np.array([r.arrival_s for r in reqs])
@@ -544,8 +544,10 @@ def main():
     ap.add_argument("--c5-pool", type=int, default=96, help="C5: distinct graphs in the pool")
     ap.add_argument("--c5-requests", type=int, default=20000, help="C5: requests per QPS level")
     ap.add_argument("--c5-sat", type=int, default=3000, help="C5: requests of the saturation run")
-    ap.add_argument("--c5-slots", type=int, default=8)
+    ap.add_argument("--c5-slots", type=int, default=2)
     ap.add_argument("--c5-budget-gib", type=int, default=16)
+    ap.add_argument("--c5-levels", default="0.5,0.8",
+                    help="C5: Poisson rates as fractions of the saturated rate (comma list; empty for none)")
     ap.add_argument("--cpu-gj-steps", type=int, default=256)
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--cpu-fw-steps", type=int, default=128)

@@ -135,10 +135,12 @@ rdist_status rdist_solve(rdist_ctx ctx, const uint8_t *A_dev, int32_t n, double 
  * Many independent graphs per call (Sec. 3, Eq. of the inverse, applied to
  * each graph on its own).  Graphs with n <= T (T = 128 unless tuned) go to
  * one persistent launch in which each workgroup solves whole graphs, longest
- * first; graphs with T < n <= 512 take the blocked steps together, one
- * launch per step phase for the whole set; larger graphs are solved one after
- * another with the blocked plan.
- * Host arrays of length `count`: n[g], A_dev[g], gamma[g], D_dev[g]
+ * first; graphs with T < n <= 4096 take the blocked steps together, one
+ * launch per step phase for the whole set (128-wide blocks; a large graph's
+ * tiles spread over the whole device); larger graphs are solved one after
+ * another with the blocked plan.  A graph's arithmetic does not depend on the
+ * rest of the batch, only on T.
+ * Host arrays of length `count` (0 .. 2^20): n[g], A_dev[g], gamma[g], D_dev[g]
  * (device pointers), info[g] (nullable array, preferably pinned).  flags as
  * rdist_solve plus RDIST_NO_GRAPH (RDIST_KEEP_Y fills keep[g]).  Each
  * graph's status is in info[g].status.
@@ -197,14 +199,19 @@ rdist_status rdist_epilogue(rdist_ctx ctx, const double *Y_dev, int32_t n, int32
  * rdist_server_poll (non-blocking) collects finished requests and then
  * dispatches queued ones, oldest first, while a slot is free and the HBM
  * footprint of the requests in flight stays within the server's budget:
- * full-D requests with n <= 512 that are waiting are solved together in
- * one batched call (rdist_solve_batched) on one slot, up to max_batch of
- * them; every other request takes a slot of its own (path requests keep Y
- * for rdist_next_hop and release it when done).  Requests on different
- * slots run concurrently on the device.  Results are bit-for-bit those of
- * the same request solved alone: every slot has its own workspace and no
- * kernel's arithmetic depends on what else runs.  For the paper's query
- * modes see Sec. 4.1 (full distance matrix) and Sec. 4.2 (greedy routing).
+ * the requests with n <= 4096 that are waiting, both kinds, are solved
+ * together in one batched solve on one slot (as rdist_solve_batched with
+ * T = 128, eager launches), up to max_batch of them; a path request keeps
+ * its Y in the slot's buffers and its greedy paths (as rdist_next_hop) run
+ * on the slot right after the batch.  A larger request takes a slot of its
+ * own (rdist_solve, rdist_next_hop on its kept Y).  Requests on different
+ * slots run concurrently on the device.  A slot's device buffers grow with
+ * headroom and are kept until rdist_server_destroy.  Results are
+ * bit-for-bit those of the same request solved alone (rdist_solve_batched
+ * with count 1 and no tile cache for n <= 4096, rdist_solve above): every
+ * slot has its own workspace and no kernel's arithmetic depends on what
+ * else runs.  For the paper's query modes see Sec. 4.1 (full distance
+ * matrix) and Sec. 4.2 (greedy routing).
  */
 typedef struct rdist_server_s *rdist_server;
 

@@ -5,11 +5,11 @@
 //                     from a counter, longest first (register-resident
 //                     Gauss-Jordan for n <= 128, an in-workgroup blocked solver
 //                     up to 512);
-//   T < n <= 512      the level-synchronous plan: every such graph takes
+//   T < n <= 4096     the level-synchronous plan: every such graph takes
 //                     blocked step K in the same panel / row-column / update
 //                     launches, so one graph's tiles spread over many compute
 //                     units;
-//   n > 512           the single-graph blocked plan, one graph after another.
+//   n > 4096          the single-graph blocked plan, one graph after another.
 // The first two run concurrently (the persistent kernel on a forked stream).
 // Their launch sequence is built once per distinct batch (sizes, pointers,
 // gains, flags, stream), captured into a HIP graph and replayed on identical
@@ -105,21 +105,28 @@ void free_plan(rdist_ctx c, BatchPlan *p) {
     delete p;
 }
 
-// Assigns the items of one launch to workgroups: each graph's items go to
-// one XCD (graphs placed largest first on the least loaded XCD), and the
-// XCD lists are interleaved so that workgroup b takes an item of XCD b % 8.
+// Assigns the items of one launch to workgroups.  A graph's items are cut
+// into contiguous runs of at most kRunItems (items are numbered tile-row
+// major, so a run shares its rows' operand slab); runs are placed longest
+// first on the least loaded XCD, and the XCD lists are interleaved so that
+// workgroup b takes an item of XCD b % 8.  A small graph is one run on one
+// XCD; a large one spreads over all of them.
+constexpr int kRunItems = 64;
 int build_units(const std::vector<std::pair<int, int>> &graph_items, std::vector<int> &units) {
+    struct Run { int g, first, count; };
+    std::vector<Run> runs;
+    for (const auto &gi : graph_items) {
+        const int items = gi.second, parts = (items + kRunItems - 1) / kRunItems;
+        const int per = (items + parts - 1) / parts;
+        for (int f = 0; f < items; f += per) runs.push_back(Run{gi.first, f, std::min(per, items - f)});
+    }
+    std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &b) { return a.count > b.count; });
     std::vector<std::vector<int>> lists(kXcds);
     std::vector<size_t> load(kXcds, 0);
-    std::vector<int> order(graph_items.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return graph_items[a].second > graph_items[b].second; });
-    for (int i : order) {
+    for (const Run &r : runs) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        const int g = graph_items[i].first, items = graph_items[i].second;
-        for (int it = 0; it < items; ++it) lists[x].push_back((g << rd::kLvShift) | it);
-        load[x] += items;
+        for (int it = r.first; it < r.first + r.count; ++it) lists[x].push_back((r.g << rd::kLvShift) | it);
+        load[x] += r.count;
     }
     size_t slots = 0;
     for (auto &l : lists) slots = std::max(slots, l.size());
@@ -128,12 +135,18 @@ int build_units(const std::vector<std::pair<int, int>> &graph_items, std::vector
     return (int)(slots * kXcds);
 }
 
+// Row-chunk height of the level plan's column sums: about 256 KB of A per
+// workgroup.
+int colsum_rows(int n) { return std::max(1, (262144 + n - 1) / n); }
+
 // Builds the plan's tables and buffers for the batch.  ys (keep_y only):
 // per-graph Y buffers, allocated here and handed to the graph handles after
-// the launch; the persistent graphs' Y has leading dimension np.
+// the launch; the persistent graphs' Y has leading dimension np.  ext_y
+// (nullable): caller-owned Y buffers (np x np, ld np) instead, for the
+// graphs whose entry is non-null; nothing is allocated for them.
 rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags, int count, const int32_t *n,
                         const uint8_t *const *A, const double *gamma, int16_t *const *D, const BatchTuning &tune,
-                        bool keep_y, std::vector<Buf> &ys) {
+                        bool keep_y, std::vector<Buf> &ys, double *const *ext_y = nullptr) {
     rdist_status st;
     p.stream = s;
     p.flags = flags;
@@ -156,27 +169,33 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     std::stable_sort(p.level_ids.begin(), p.level_ids.end(), by_n);
     const int np_ = (int)p.persist_ids.size(), nl = (int)p.level_ids.size();
 
-    if ((st = ensure(c, p.infos, sizeof(rdist_info) * (size_t)count))) return st;
+    if ((st = ensure_grow(c, p.infos, sizeof(rdist_info) * (size_t)count))) return st;
     rdist_info *dinfo = (rdist_info *)p.infos.p;
 
-    // device memory: matrices (unless kept), level step buffers, scratch
+    // device memory: matrices (unless kept), level step buffers and column
+    // sums, scratch
+    auto kept = [&](int g) { return keep_y || (ext_y && ext_y[g]); };
+    auto colpart_doubles = [&](int g) {
+        const size_t nc = (n[g] + colsum_rows(n[g]) - 1) / colsum_rows(n[g]);
+        return (nc * n[g] + nc + 1) / 2;
+    };
     size_t pool = 0;
     for (int g : p.persist_ids)
-        if (!keep_y && n[g] > 128) pool += (size_t)np_of(n[g]) * np_of(n[g]);
+        if (!kept(g) && n[g] > 128) pool += (size_t)np_of(n[g]) * np_of(n[g]);
     for (int g : p.level_ids) {
         const size_t q = np_of(n[g]);
-        pool += (keep_y ? 0 : q * q) + 2 * (2 * (size_t)kB * q + (size_t)kB * kB);
+        pool += (kept(g) ? 0 : q * q) + 2 * (2 * (size_t)kB * q + (size_t)kB * kB) + colpart_doubles(g);
     }
-    if (pool && (st = ensure(c, p.pool, pool * 8))) return st;
+    if (pool && (st = ensure_grow(c, p.pool, pool * 8))) return st;
     bool persist_medium = false;
     for (int g : p.persist_ids) persist_medium |= n[g] > 128;
     // default grid: half the compute units, so that the level plan's
     // launches keep most of the device while it runs
     const int grid_default = std::max(1, c->num_cu / 2);
     p.persist_grid = std::max(1, std::min(np_, tune.persist_grid > 0 ? tune.persist_grid : grid_default));
-    p.persist_stride = 2 * kB * kBatchMaxN + kB * kB;
+    p.persist_stride = 2 * kB * kPersistMaxN + kB * kB;
     if (np_ && persist_medium &&
-        (st = ensure(c, p.scratch, (size_t)p.persist_grid * p.persist_stride * 8)))
+        (st = ensure_grow(c, p.scratch, (size_t)p.persist_grid * p.persist_stride * 8)))
         return st;
     if (keep_y) {
         ys.assign(count, Buf{});
@@ -202,15 +221,17 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     for (int q = 0; q < np_; ++q) {
         const int g = p.persist_ids[q], npg = np_of(n[g]);
         double *M = nullptr;
-        if (keep_y) M = (double *)ys[g].p;
+        if (ext_y && ext_y[g]) M = ext_y[g];
+        else if (keep_y) M = (double *)ys[g].p;
         else if (n[g] > 128) { M = cur; cur += (size_t)npg * npg; }
-        tasks[q] = rd::BatchTask{A[g], D[g], M, nullptr, nullptr, nullptr, n[g], npg, keep_y ? 1 : 0, 0, gamma[g],
+        tasks[q] = rd::BatchTask{A[g], D[g], M, nullptr, nullptr, nullptr, n[g], npg, kept(g) ? 1 : 0, 0, gamma[g],
                                  dinfo + g};
     }
     for (int q = 0; q < nl; ++q) {
         const int g = p.level_ids[q], npg = np_of(n[g]);
         rd::LevelGraph &L = lgs[q];
-        if (keep_y) L.M = (double *)ys[g].p;
+        if (ext_y && ext_y[g]) L.M = ext_y[g];
+        else if (keep_y) L.M = (double *)ys[g].p;
         else { L.M = cur; cur += (size_t)npg * npg; }
         for (int par = 0; par < 2; ++par) {
             L.Ut[par] = cur;
@@ -218,13 +239,17 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
             L.Pt[par] = cur + 2 * (size_t)kB * npg;
             cur += 2 * (size_t)kB * npg + (size_t)kB * kB;
         }
+        L.colpart = (int32_t *)cur;
+        cur += colpart_doubles(g);
+        L.rows_per = colsum_rows(n[g]);
+        L.nchunk = (n[g] + L.rows_per - 1) / L.rows_per;
         L.A = A[g];
         L.D = D[g];
         L.info = dinfo + g;
         L.n = n[g];
         L.np = npg;
         L.nt = npg / kB;
-        L.keep = keep_y ? 1 : 0;
+        L.keep = kept(g) ? 1 : 0;
         L.gamma_arg = gamma[g];
     }
     for (int g : p.persist_ids) {
@@ -242,7 +267,7 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     auto launch = [&](int stream, int phase, int K, auto items_of) {
         std::vector<std::pair<int, int>> gi;
         for (int q = 0; q < nl; ++q) {
-            const int it = items_of(lgs[q].nt);
+            const int it = items_of(lgs[q]);
             if (it > 0) gi.emplace_back(q, it);
         }
         const int off = (int)units.size();
@@ -253,9 +278,11 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     auto wait = [&](int stream, int ev) { p.ops.push_back(Op{BatchPlan::kWait, stream, 0, 0, 0, 0, ev}); };
     // the persistent kernel forks off after the level plan's ingest and
     // build (which use the whole device) and fills the narrow launches after
+    using LG = rd::LevelGraph;
     if (nl) {
-        p.ops.push_back(Op{BatchPlan::kIngest, 0, 0, 0, 0, nl, 0});
-        launch(0, rd::kLvBuild, 0, [](int nt) { return 2 * nt - 1; });
+        launch(0, rd::kLvColsum, 0, [](const LG &L) { return L.nchunk; });
+        p.ops.push_back(Op{BatchPlan::kIngest, 0, 0, 0, 0, nl, 0});   // the gate
+        launch(0, rd::kLvBuild, 0, [](const LG &L) { return 2 * L.nt - 1; });
     }
     if (np_ && nl) {
         record(0, 0);
@@ -264,21 +291,23 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     if (np_) p.ops.push_back(Op{BatchPlan::kPersist, nl ? 2 : 0, 0, 0, 0, p.persist_grid, 0});
     if (np_ && nl) record(2, 1);
     if (nl) {
-        launch(0, rd::kLvPanel, 0, [](int) { return 1; });
-        launch(0, rd::kLvRowcol, 0, [](int nt) { return nt - 1; });
+        launch(0, rd::kLvPanel, 0, [](const LG &) { return 1; });
+        launch(0, rd::kLvRowcol, 0, [](const LG &L) { return L.nt - 1; });
         const int max_nt = lgs[0].nt;
         for (int K = 0; K < max_nt; ++K) {
             if (K > 0) wait(0, 3);                       // step K's row/column tiles are ready
             const bool next = max_nt > K + 1;
             if (next) {
-                launch(0, rd::kLvEdge, K, [K](int nt) { return nt > K + 1 ? 2 * nt - 1 : 0; });
+                launch(0, rd::kLvEdge, K, [K](const LG &L) { return L.nt > K + 1 ? 2 * L.nt - 1 : 0; });
                 record(0, 2);
             }
-            launch(0, rd::kLvRest, K, [K](int nt) { return nt > K + 1 ? (nt - 1) * (nt - 1) : nt == K + 1 ? nt * nt : 0; });
+            launch(0, rd::kLvRest, K, [K](const LG &L) {
+                return L.nt > K + 1 ? (L.nt - 1) * (L.nt - 1) : L.nt == K + 1 ? L.nt * L.nt : 0;
+            });
             if (next) {
                 wait(1, 2);
-                launch(1, rd::kLvPanel, K + 1, [K](int nt) { return nt > K + 1 ? 1 : 0; });
-                launch(1, rd::kLvRowcol, K + 1, [K](int nt) { return nt > K + 1 ? nt - 1 : 0; });
+                launch(1, rd::kLvPanel, K + 1, [K](const LG &L) { return L.nt > K + 1 ? 1 : 0; });
+                launch(1, rd::kLvRowcol, K + 1, [K](const LG &L) { return L.nt > K + 1 ? L.nt - 1 : 0; });
                 record(1, 3);
             }
         }
@@ -291,7 +320,7 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     p.off_units = p.off_level + align(sizeof(rd::LevelGraph) * lgs.size());
     p.off_counter = p.off_units + align(sizeof(int) * units.size());
     const size_t tbytes = p.off_counter + 256;
-    if ((st = ensure(c, p.table, tbytes))) return st;
+    if ((st = ensure_grow(c, p.table, tbytes))) return st;
     if (!p.ev_upload) RD_HIP(hipEventCreateWithFlags(&p.ev_upload, hipEventDisableTiming));
     else RD_HIP(hipEventSynchronize(p.ev_upload));   // the previous upload has left the staging buffer
     if (p.staging_bytes < tbytes) {
@@ -323,7 +352,7 @@ rdist_status enqueue_plan(BatchPlan &p, const hipStream_t st[3]) {
         hipStream_t s = st[o.stream];
         switch (o.kind) {
             case BatchPlan::kLaunch: rd::launch_lv(o.phase, lgs, units + o.offset, o.grid, o.K, s); break;
-            case BatchPlan::kIngest: rd::launch_lv_ingest(lgs, o.grid, s); break;
+            case BatchPlan::kIngest: rd::launch_lv_gate(lgs, o.grid, s); break;
             case BatchPlan::kPersist:
                 rd::launch_batched((const rd::BatchTask *)t, (int)p.persist_ids.size(), (int *)(t + p.off_counter),
                                    o.grid, (double *)p.scratch.p, p.persist_stride, s);
@@ -494,6 +523,31 @@ void save_tile_cache(rdist_ctx c) {
     c->tuned_dirty = false;
 }
 
+rdist_status solve_batch_into(rdist_ctx c, hipStream_t s, int count, const int32_t *n, const uint8_t *const *A,
+                              const double *gamma, int16_t *const *D, double *const *ext_y, rdist_info *info_host) {
+    for (int g = 0; g < count; ++g)
+        if (n[g] < 1 || n[g] > kBatchMaxN) return fail(RDIST_E_ARG, "n out of the batched range");
+    Workspace &w = c->ws[s];
+    rdist_status st;
+    if ((st = ensure_aux(w))) return st;
+    if ((st = ensure_aux2(w))) return st;
+    // the default threshold T = 128 whatever the batch, so that a graph's
+    // arithmetic never depends on what it is batched with
+    const BatchTuning tune;
+    if (!w.transient) w.transient = new BatchPlan();
+    BatchPlan &p = *w.transient;
+    std::vector<Buf> none;
+    if ((st = build_plan(c, p, s, RDIST_F64, count, n, A, gamma, D, tune, false, none, ext_y))) return st;
+    {
+        Timer tm(c, s, RDIST_K_BATCHED, p.flops, p.bytes);
+        const hipStream_t sts[3] = {s, w.aux, w.aux2};
+        if ((st = enqueue_plan(p, sts))) return st;
+    }
+    if (info_host)
+        RD_HIP(hipMemcpyAsync(info_host, p.infos.p, sizeof(rdist_info) * (size_t)count, hipMemcpyDeviceToHost, s));
+    return RDIST_OK;
+}
+
 }  // namespace eng
 }  // namespace rd
 
@@ -511,7 +565,7 @@ extern "C" rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const in
     if ((st = check_flags(flags))) return st;
     if (flags & (RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED)) return fail(RDIST_E_ARG, "plan flags are per solve");
     if (flags & RDIST_MIXED_F32) return fail(RDIST_E_ARG, "RDIST_MIXED_F32 is a single-graph plan");
-    if (count > (1 << 24)) return fail(RDIST_E_ARG, "count too large");
+    if (count > (1 << 20)) return fail(RDIST_E_ARG, "count too large (at most 2^20 graphs per call)");
     for (int g = 0; g < count; ++g) {
         if (n[g] < 1 || n[g] > 65536) return fail(RDIST_E_ARG, "n out of range");
         if (!A_dev[g] || !D_dev[g]) return fail(RDIST_E_ARG, "NULL graph pointer");

@@ -33,7 +33,8 @@ inline rdist_status fail(rdist_status s, const std::string &msg) {
     } while (0)
 
 constexpr int kB = 128;           // block size of the blocked solver = tile size
-constexpr int kBatchMaxN = 512;   // largest graph the batched plans solve (larger: blocked plan)
+constexpr int kBatchMaxN = rd::kLvMaxN;   // largest graph the batched plans solve (larger: blocked plan)
+constexpr int kPersistMaxN = 512;        // largest graph of the persistent kernel's in-workgroup solver
 
 struct BatchPlan;   // rd_batch.hip
 
@@ -125,6 +126,9 @@ struct Guard {
 rdist_status dalloc(rdist_ctx c, void **p, size_t bytes);
 void dfree(rdist_ctx c, void *p, size_t bytes);
 rdist_status ensure(rdist_ctx c, Buf &b, size_t bytes);
+// ensure with headroom: a buffer that has to grow takes 1.5x its old size
+// (or the request, if larger), falling back to the exact size.
+rdist_status ensure_grow(rdist_ctx c, Buf &b, size_t bytes);
 void release(rdist_ctx c, Buf &b);
 rdist_status ensure_small(rdist_ctx c, Workspace &w, int n);
 rdist_status ensure_aux(Workspace &w);
@@ -176,6 +180,12 @@ void release_stream_workspace(rdist_ctx c, hipStream_t s);
 // rd_batch.hip
 void destroy_plans(rdist_ctx c);
 void free_transient_plan(rdist_ctx c, Workspace &w);
+// Eager batched solve on stream s for the request loop: every n <= kBatchMaxN;
+// ext_y[g] (nullable array, nullable entries): caller-owned Y of graph g
+// (np x np, ld np = n rounded up to 128); info_host (pinned, count entries)
+// receives the infos when the stream gets there.
+rdist_status solve_batch_into(rdist_ctx c, hipStream_t s, int count, const int32_t *n, const uint8_t *const *A,
+                              const double *gamma, int16_t *const *D, double *const *ext_y, rdist_info *info_host);
 void load_tile_cache(rdist_ctx c);
 void save_tile_cache(rdist_ctx c);
 

@@ -60,6 +60,13 @@ rdist_status ensure(rdist_ctx c, Buf &b, size_t bytes) {
     return st;
 }
 
+rdist_status ensure_grow(rdist_ctx c, Buf &b, size_t bytes) {
+    if (b.p && b.bytes >= bytes) return RDIST_OK;
+    const size_t want = std::max(bytes, b.bytes + b.bytes / 2);
+    if (want > bytes && ensure(c, b, want) == RDIST_OK) return RDIST_OK;
+    return ensure(c, b, bytes);
+}
+
 void release(rdist_ctx c, Buf &b) {
     dfree(c, b.p, b.bytes);
     b.p = nullptr;

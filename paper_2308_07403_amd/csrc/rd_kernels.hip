@@ -630,51 +630,61 @@ __device__ __forceinline__ void adj_colsum(const uint8_t *__restrict__ A, int n,
     if (bad) atomicOr(bad_flag, 1);
 }
 
-// Column sums of the n x n byte matrix A (n <= 512) into colsum[j] (LDS) and
-// *bad as adj_colsum, one workgroup: rows are staged through LDS (stage:
-// kStageBytes) in chunks copied flat, 16 bytes per load and all of a chunk in
-// flight, then each thread adds up its columns (j = t, t + 256) from LDS: no
-// atomics, no divisions.
-constexpr int kStageBytes = 65536;
-__device__ __forceinline__ void adj_colsum_staged(const uint8_t *__restrict__ A, int n, int *colsum, int *bad_flag,
-                                                  uint8_t *stage) {
-    const int rows_per = kStageBytes / n - 1;      // leaves room for the alignment shift
-    const int j0 = threadIdx.x, j1 = threadIdx.x + 256;
-    int s0 = 0, s1 = 0, bad = 0;
-    for (int r0 = 0; r0 < n; r0 += rows_per) {
-        const int rows = min(rows_per, n - r0);
-        const size_t gs = (size_t)r0 * n, ge = (size_t)(r0 + rows) * n;
-        const size_t as = gs & ~(size_t)15;
-        const size_t full = (ge - as) >> 4;          // whole 16-byte words inside [as, ge)
-        const uint4 *W = reinterpret_cast<const uint4 *>(A + as);
-        const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0;
-        if (aligned) {
-            for (size_t q = threadIdx.x; q < full; q += 256)
-                *reinterpret_cast<uint4 *>(stage + 16 * q) = W[q];
-            for (size_t e = as + 16 * full + threadIdx.x; e < ge; e += 256) stage[e - as] = A[e];
-        } else {
-            for (size_t e = gs + threadIdx.x; e < ge; e += 256) stage[e - as] = A[e];
-        }
-        __syncthreads();
-        const int off = (int)(gs - as);
-        for (int r = 0; r < rows; ++r) {
-            const int i = r0 + r;
-            const uint8_t *row = stage + off + r * n;
-            if (j0 < n) {
-                const int a = row[j0];
-                s0 += a;
-                bad |= (a > 1) | ((i == j0) & (a != 0));
+// Column sums of the bytes [b0, b1) of the n x n byte matrix A (flat,
+// row-major) added into colsum[j] (LDS, zeroed by the caller), and *bad set
+// as adj_colsum.  The 16-byte words inside the range are read 4 per thread
+// in flight when A is 16-byte aligned; the bytes before the first and after
+// the last whole word one at a time.  One division per nonzero word.
+__device__ __forceinline__ void adj_colsum_range(const uint8_t *__restrict__ A, unsigned n, unsigned b0, unsigned b1,
+                                                 int *colsum, int *bad_flag) {
+    int bad = 0;
+    auto add_byte = [&](unsigned e, unsigned byte) {
+        const unsigned i = e / n, j = e - i * n;
+        bad |= (byte > 1u) | (i == j);
+        atomicAdd(&colsum[j], (int)byte);
+    };
+    auto add_word = [&](unsigned e0, uint32_t v) {
+        unsigned i = e0 / n, j = e0 - i * n;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const unsigned byte = (v >> (8 * b)) & 0xFFu;
+            if (byte) {
+                bad |= (byte > 1u) | (i == j);
+                atomicAdd(&colsum[j], (int)byte);
             }
-            if (j1 < n) {
-                const int a = row[j1];
-                s1 += a;
-                bad |= (a > 1) | ((i == j1) & (a != 0));
+            if (++j == n) { j = 0; ++i; }
+        }
+    };
+    unsigned w0 = b1, w1 = b1;   // [w0, w1): the bytes covered by whole words
+    if ((reinterpret_cast<uintptr_t>(A) & 15) == 0) {
+        const unsigned q0 = (b0 + 15) >> 4, q1 = b1 >> 4;
+        if (q1 > q0) {
+            w0 = q0 << 4;
+            w1 = q1 << 4;
+            const uint4 *W = reinterpret_cast<const uint4 *>(A);
+            for (unsigned q = q0 + threadIdx.x; q < q1; q += 4 * 256) {
+                uint4 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = q + u * 256 < q1 ? W[q + u * 256] : uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const unsigned e0 = 16u * (q + u * 256);
+                    if (v[u].x) add_word(e0, v[u].x);
+                    if (v[u].y) add_word(e0 + 4, v[u].y);
+                    if (v[u].z) add_word(e0 + 8, v[u].z);
+                    if (v[u].w) add_word(e0 + 12, v[u].w);
+                }
             }
         }
-        __syncthreads();
     }
-    if (j0 < n) colsum[j0] = s0;
-    if (j1 < n) colsum[j1] = s1;
+    for (unsigned e = b0 + threadIdx.x; e < w0; e += 256) {
+        const unsigned byte = A[e];
+        if (byte) add_byte(e, byte);
+    }
+    for (unsigned e = w1 + threadIdx.x; e < b1; e += 256) {
+        const unsigned byte = A[e];
+        if (byte) add_byte(e, byte);
+    }
     if (bad) atomicOr(bad_flag, 1);
 }
 
@@ -790,13 +800,14 @@ __global__ __launch_bounds__(256, 2) void k_batched(const BatchTask *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Level-synchronous batched blocked Gauss-Jordan for 128 < n <= 512: every
+// Level-synchronous batched blocked Gauss-Jordan for 128 < n <= 4096: every
 // graph of the batch takes step K in the same launches (panel, row and
 // column tiles, trailing update), so one graph's tiles run on many compute
 // units at once.  Each launch reads its work from a unit list built on the
 // host: unit u = (graph << kLvShift) | item, or -1 for an idle slot.  The
-// host spreads each graph's units over the workgroups of one XCD
-// (workgroup b runs on XCD b % 8) so that its operand slabs share one L2.
+// host keeps a small graph's units on the workgroups of one XCD (workgroup
+// b runs on XCD b % 8) so that its operand slabs share one L2, and splits a
+// large graph's units into contiguous runs of tile rows, one run per XCD.
 // Step K uses the step buffers of parity K & 1, so step K+1's panel and
 // row/column tiles (on a second stream) never overwrite what step K's update
 // still reads.
@@ -810,20 +821,45 @@ __device__ __forceinline__ bool lv_unit(const int *units, int &g, int &item) {
     return true;
 }
 
-// Ingest and gate, one workgroup per graph: out-degrees from a flat scan of
-// A, then info (status, delta, gamma, zeroed counters).
-__global__ __launch_bounds__(256) void k_lv_ingest(const LevelGraph *__restrict__ gs) {
-    __shared__ int colsum[512];
+// Column sums of one row chunk (item): rows [item * rows_per, + rows_per)
+// of A summed per column in LDS, written to the graph's partial sums, with
+// the chunk's validation flag.
+__global__ __launch_bounds__(256) void k_lv_colsum(const LevelGraph *__restrict__ gs, const int *__restrict__ units) {
+    int gi, item;
+    if (!lv_unit(units, gi, item)) return;
+    const LevelGraph g = gs[gi];
+    __shared__ int colsum[kLvMaxN];
+    __shared__ int bad;
+    const int n = g.n;
+    for (int j = threadIdx.x; j < n; j += 256) colsum[j] = 0;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const int r0 = item * g.rows_per, r1 = min(n, r0 + g.rows_per);
+    adj_colsum_range(g.A, (unsigned)n, (unsigned)r0 * (unsigned)n, (unsigned)r1 * (unsigned)n, colsum, &bad);
+    __syncthreads();
+    int32_t *out = g.colpart + (size_t)item * n;
+    for (int j = threadIdx.x; j < n; j += 256) out[j] = colsum[j];
+    if (threadIdx.x == 0) g.colpart[(size_t)g.nchunk * n + item] = bad;
+}
+
+// Gate, one workgroup per graph: out-degrees (the chunks' partial sums
+// added up), Delta, the gain and the diagonal-dominance test, then info
+// (status, delta, gamma, zeroed counters).
+__global__ __launch_bounds__(256) void k_lv_gate(const LevelGraph *__restrict__ gs) {
     __shared__ int flags[2];
-    __shared__ __attribute__((aligned(16))) uint8_t stage[kStageBytes];
     const LevelGraph g = gs[blockIdx.x];
     if (threadIdx.x == 0) { flags[0] = 0; flags[1] = 0; }
     __syncthreads();
-    adj_colsum_staged(g.A, g.n, colsum, &flags[0], stage);
-    __syncthreads();
-    int m = 0;
-    for (int j = threadIdx.x; j < g.n; j += 256) m = max(m, colsum[j]);
-    atomicMax(&flags[1], m);
+    const int n = g.n, nc = g.nchunk;
+    int m = 0, bad = 0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        int sum = 0;
+        for (int c = 0; c < nc; ++c) sum += g.colpart[(size_t)c * n + j];
+        m = max(m, sum);
+    }
+    for (int c = threadIdx.x; c < nc; c += 256) bad |= g.colpart[(size_t)nc * n + c];
+    if (m) atomicMax(&flags[1], m);
+    if (bad) atomicOr(&flags[0], 1);
     __syncthreads();
     if (threadIdx.x == 0) {
         const int delta = flags[1];
@@ -1187,12 +1223,13 @@ int batched_blocks_per_cu() {
     return b;
 }
 
-void launch_lv_ingest(const LevelGraph *gs, int count, hipStream_t s) {
-    hipLaunchKernelGGL(k_lv_ingest, dim3(count), dim3(256), 0, s, gs);
+void launch_lv_gate(const LevelGraph *gs, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_lv_gate, dim3(count), dim3(256), 0, s, gs);
 }
 
 void launch_lv(int phase, const LevelGraph *gs, const int *units, int grid, int K, hipStream_t s) {
     switch (phase) {
+        case kLvColsum: hipLaunchKernelGGL(k_lv_colsum, dim3(grid), dim3(256), 0, s, gs, units); break;
         case kLvBuild: hipLaunchKernelGGL(k_lv_build, dim3(grid), dim3(256), 0, s, gs, units); break;
         case kLvPanel: hipLaunchKernelGGL(k_lv_panel, dim3(grid), dim3(256), 0, s, gs, units, K); break;
         case kLvRowcol: hipLaunchKernelGGL(k_lv_rowcol, dim3(grid), dim3(256), 0, s, gs, units, K); break;

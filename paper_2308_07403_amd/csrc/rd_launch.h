@@ -37,9 +37,11 @@ struct BatchTask {
     rdist_info *info;
 };
 
-// One graph of the level-synchronous batched solver (128 < n <= 512).
+// One graph of the level-synchronous batched solver (n <= kLvMaxN).
 // M: np x np (np = n rounded up to 128, nt = np / 128 tiles per side).
 // Step buffers by step parity: Ut, V 128 x np; Pt 128 x 128.
+// colpart: int32 [nchunk][n] partial column sums of A over row chunks of
+// rows_per rows, then nchunk flags (an entry not 0/1, or a self-loop).
 // gamma_arg explicit (> 0) or AUTO (< 0).
 struct LevelGraph {
     const uint8_t *A;
@@ -47,12 +49,15 @@ struct LevelGraph {
     double *M;
     double *Ut[2], *V[2], *Pt[2];
     rdist_info *info;
+    int32_t *colpart;
     int32_t n, np, nt, keep;
+    int32_t rows_per, nchunk;
     double gamma_arg;
 };
-constexpr int kLvShift = 6;   // unit = (graph << 6) | item, item < 64
-// Launch phases of the level plan (the last two are update tile sets).
-enum LevelPhase { kLvBuild = 0, kLvPanel = 1, kLvRowcol = 2, kLvEdge = 3, kLvRest = 4 };
+constexpr int kLvMaxN = 4096;  // largest graph of the level plan
+constexpr int kLvShift = 10;   // unit = (graph << 10) | item, item < 1024 (nt^2 <= 1024)
+// Launch phases of the level plan (Edge and Rest are update tile sets).
+enum LevelPhase { kLvBuild = 0, kLvPanel = 1, kLvRowcol = 2, kLvEdge = 3, kLvRest = 4, kLvColsum = 5 };
 
 // Out-degrees, validation and the gate: info (status, delta, gamma, zeroed counters).
 void launch_gate(const uint8_t *A, int n, double gamma_arg, int32_t *outdeg, int32_t *bad, rdist_info *info,
@@ -79,7 +84,7 @@ void launch_small_one(const SmallTask &t, hipStream_t s);
 void launch_batched(const BatchTask *tasks, int count, int *counter, int grid, double *scratch, int scratch_stride,
                     hipStream_t s);
 int batched_blocks_per_cu();
-void launch_lv_ingest(const LevelGraph *gs, int count, hipStream_t s);
+void launch_lv_gate(const LevelGraph *gs, int count, hipStream_t s);
 void launch_lv(int phase, const LevelGraph *gs, const int *units, int grid, int K, hipStream_t s);
 // Mixed precision (rd_mixed.hip).
 void launch_m32_build(const uint8_t *A, int n, int np, float *M, const rdist_info *info, hipStream_t s);

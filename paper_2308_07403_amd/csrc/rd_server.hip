@@ -1,7 +1,11 @@
 // rd_server.hip -- the request loop (rdist_server_*): a queue, slots (HIP
 // streams with their own workspaces), admission by HBM footprint and
-// continuous batching of small full-D requests.  Driven by the caller's
-// polls; no thread of its own, and the device is never waited on except in
+// continuous batching: every request with n <= 4096, full D or paths, joins
+// the next batch of a free slot (one level-synchronous batched solve; a path
+// request keeps Y in the slot's own buffer and its next hops run right after
+// the batch).  Slot buffers grow with headroom and are kept, so a warmed-up
+// server allocates nothing per request.  Driven by the caller's polls; no
+// thread of its own, and the device is never waited on except in
 // rdist_server_destroy.
 #include <hip/hip_runtime.h>
 
@@ -18,7 +22,6 @@ namespace rd {
 namespace eng {
 namespace {
 
-constexpr int kBatchN = 512;      // full-D requests up to this n are batched together
 constexpr int kMaxPairs = 4096;
 
 struct Pending {
@@ -31,10 +34,10 @@ struct Slot {
     hipEvent_t done = nullptr;
     bool busy = false;
     std::vector<Pending> reqs;           // in flight on this slot
-    rdist_graph graph = nullptr;         // path request: the kept Y
-    Buf D, paths, pairs;                 // device buffers, grown as needed
+    rdist_graph graph = nullptr;         // a path request above the batched range: its kept Y
+    Buf D, Y, bits, paths, pairs;        // device buffers, grown with headroom and kept
     rdist_info *info_h = nullptr;        // pinned, one per batched request
-    int32_t *pairs_h = nullptr;          // pinned staging of (cur, goal)
+    int32_t *pairs_h = nullptr;          // pinned staging of (cur, goal), max_batch * kMaxPairs pairs
     size_t footprint = 0;
 };
 
@@ -44,7 +47,8 @@ size_t footprint_of(const rdist_request &r) {
     return r.kind == RDIST_QUERY_PATHS ? 2 * f : f;
 }
 
-bool batchable(const rdist_request &r) { return r.kind == RDIST_QUERY_D && r.n <= kBatchN; }
+bool batchable(const rdist_request &r) { return r.n <= kBatchMaxN; }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 }  // namespace eng
@@ -64,7 +68,7 @@ struct rdist_server_s {
 
 namespace {
 
-rdist_status grow(rdist_ctx c, Buf &b, size_t bytes) { return ensure(c, b, std::max<size_t>(bytes, 256)); }
+rdist_status grow(rdist_ctx c, Buf &b, size_t bytes) { return ensure_grow(c, b, std::max<size_t>(bytes, 256)); }
 
 void fail_request(rdist_server s, const Pending &p, rdist_status why) {
     if (p.r.info_host) {
@@ -110,25 +114,72 @@ rdist_status dispatch(rdist_server s, int k, std::vector<Pending> &batch) {
             }
         }
     } else {
+        // one batched solve; path requests keep Y in the slot's buffer
         const int cnt = (int)batch.size();
-        std::vector<size_t> off(cnt + 1, 0);
-        for (int i = 0; i < cnt; ++i) off[i + 1] = off[i] + ((size_t)batch[i].r.n * batch[i].r.n * 2 + 255) / 256 * 256;
-        if ((e = grow(c, sl.D, off[cnt]))) return e;
+        std::vector<size_t> offD(cnt), offY(cnt), offB(cnt), offQ(cnt), offP(cnt);
+        size_t tD = 0, tY = 0, tB = 0, tQ = 0, tP = 0;
+        for (int i = 0; i < cnt; ++i) {
+            const rdist_request &r = batch[i].r;
+            offD[i] = tD;
+            tD += align256((size_t)r.n * r.n * 2);
+            if (r.kind != RDIST_QUERY_PATHS) continue;
+            const size_t np = ((size_t)r.n + kB - 1) / kB * kB, nw = ((size_t)r.n + 63) / 64;
+            offY[i] = tY;
+            tY += np * np * 8;
+            offB[i] = tB;
+            tB += align256((size_t)r.n * nw * 8);
+            offQ[i] = tQ;
+            tQ += (size_t)r.q;
+            offP[i] = tP;
+            tP += align256((size_t)r.q * (r.max_hops + 1) * 4);
+        }
+        if ((e = grow(c, sl.D, tD))) return e;
+        if (tY && ((e = grow(c, sl.Y, tY)) || (e = grow(c, sl.bits, tB)))) return e;
+        if (tQ && ((e = grow(c, sl.pairs, 2 * tQ * 4)) || (e = grow(c, sl.paths, tP)))) return e;
         std::vector<int32_t> ns(cnt);
         std::vector<const uint8_t *> As(cnt);
         std::vector<double> gs(cnt);
         std::vector<int16_t *> Ds(cnt);
+        std::vector<double *> Ys(cnt, nullptr);
         for (int i = 0; i < cnt; ++i) {
-            ns[i] = batch[i].r.n;
-            As[i] = batch[i].r.A_dev;
-            gs[i] = batch[i].r.gamma;
-            Ds[i] = (int16_t *)((char *)sl.D.p + off[i]);
+            const rdist_request &r = batch[i].r;
+            ns[i] = r.n;
+            As[i] = r.A_dev;
+            gs[i] = r.gamma;
+            Ds[i] = (int16_t *)((char *)sl.D.p + offD[i]);
+            if (r.kind == RDIST_QUERY_PATHS) Ys[i] = (double *)((char *)sl.Y.p + offY[i]);
         }
-        e = rdist_solve_batched(c, cnt, ns.data(), As.data(), gs.data(), RDIST_F64 | RDIST_NO_GRAPH, Ds.data(),
-                                nullptr, sl.info_h, st);
+        e = solve_batch_into(c, st, cnt, ns.data(), As.data(), gs.data(), Ds.data(), Ys.data(), sl.info_h);
         if (e) return e;
-        for (int i = 0; i < cnt; ++i)
-            RD_HIP(hipMemcpyAsync(batch[i].r.D_host, Ds[i], (size_t)ns[i] * ns[i] * 2, hipMemcpyDeviceToHost, st));
+        int32_t *cur_d = (int32_t *)sl.pairs.p, *goal_d = cur_d + tQ;
+        if (tQ) {
+            for (int i = 0; i < cnt; ++i) {
+                const rdist_request &r = batch[i].r;
+                if (r.kind != RDIST_QUERY_PATHS || r.q == 0) continue;
+                std::memcpy(sl.pairs_h + offQ[i], r.cur_host, (size_t)r.q * 4);
+                std::memcpy(sl.pairs_h + tQ + offQ[i], r.goal_host, (size_t)r.q * 4);
+            }
+            RD_HIP(hipMemcpyAsync(cur_d, sl.pairs_h, 2 * tQ * 4, hipMemcpyHostToDevice, st));
+        }
+        for (int i = 0; i < cnt; ++i) {
+            const rdist_request &r = batch[i].r;
+            if (r.kind == RDIST_QUERY_D) {
+                RD_HIP(hipMemcpyAsync(r.D_host, Ds[i], (size_t)r.n * r.n * 2, hipMemcpyDeviceToHost, st));
+            } else if (r.q > 0) {
+                const int np = (r.n + kB - 1) / kB * kB;
+                auto *bits = (unsigned long long *)((char *)sl.bits.p + offB[i]);
+                auto *paths = (int32_t *)((char *)sl.paths.p + offP[i]);
+                {
+                    Timer tm(c, st, RDIST_K_NEXTHOP, 0.0, 0.0);
+                    rd::launch_succ_bitmap(r.A_dev, r.n, bits, st);
+                    rd::launch_next_hop(Ys[i], np, r.n, bits, cur_d + offQ[i], goal_d + offQ[i], r.q, r.max_hops,
+                                        paths, st);
+                }
+                RD_HIP(hipGetLastError());
+                RD_HIP(hipMemcpyAsync(r.paths_host, paths, (size_t)r.q * (r.max_hops + 1) * 4,
+                                      hipMemcpyDeviceToHost, st));
+            }
+        }
         s->st.batches += 1;
         s->st.batched_requests += cnt;
     }
@@ -236,7 +287,8 @@ rdist_status rdist_server_create(rdist_ctx ctx, int32_t slots, size_t hbm_budget
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc((void **)&sl.info_h, sizeof(rdist_info) * (size_t)max_batch, hipHostMallocDefault) !=
                 hipSuccess ||
-            hipHostMalloc((void **)&sl.pairs_h, (size_t)2 * kMaxPairs * 4, hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc((void **)&sl.pairs_h, (size_t)2 * kMaxPairs * 4 * max_batch, hipHostMallocDefault) !=
+                hipSuccess) {
             rdist_server_destroy(s);
             return fail(RDIST_E_HIP, "server stream, event or pinned buffer creation failed");
         }
@@ -309,7 +361,7 @@ void rdist_server_destroy(rdist_server s) {
         for (Slot &sl : s->slots) {
             if (sl.stream) (void)hipStreamSynchronize(sl.stream);
             if (sl.graph) rdist_graph_release(sl.graph);
-            for (Buf *b : {&sl.D, &sl.paths, &sl.pairs}) release(s->ctx, *b);
+            for (Buf *b : {&sl.D, &sl.Y, &sl.bits, &sl.paths, &sl.pairs}) release(s->ctx, *b);
             if (sl.info_h) (void)hipHostFree(sl.info_h);
             if (sl.pairs_h) (void)hipHostFree(sl.pairs_h);
             if (sl.done) (void)hipEventDestroy(sl.done);

@@ -429,7 +429,7 @@ def test_batched_autotuner_and_tile_cache(tmp_path):
 
 
 def test_batched_with_large_graphs(ctx):
-    """n > 512 graphs in a batch go through the blocked plan after the batch."""
+    """Graphs up to 4096 take the level-synchronous plan beside the small ones."""
     A_np = [gg.erdos_renyi(n, 8.0 / n, gg.rng_for("parity", 8300 + n)) for n in (600, 40, 300, 1030, 128)]
     As = [dev(A) for A in A_np]
     for flags in (0, R.RDIST_NO_GRAPH):
@@ -438,6 +438,95 @@ def test_batched_with_large_graphs(ctx):
         if graphs:
             for g in graphs:
                 g.release()
+
+
+@pytest.mark.parametrize("n", [513, 640, 767, 1000, 1153])
+def test_batched_level_sizes_above_512(ctx, n):
+    """Level plan above 512: tile-count edges, row chunks of the column sums
+    that do not divide n, rows that do not start on a 16-byte boundary."""
+    A = gg.erdos_renyi(n, 7.0 / n, gg.rng_for("parity", 8400 + n))
+    small = gg.erdos_renyi(90, 0.06, gg.rng_for("parity", 8400))
+    note(f"[parity] level n={n}")
+    Ds, info, graphs = ctx.solve_batched([dev(A), dev(small)], -0.5, keep=True)
+    check_batch([A, small], -0.5, Ds, info, graphs, f"level n={n}")
+    for g in graphs:
+        g.release()
+
+
+def test_batched_level_unaligned_adjacency(ctx):
+    """An adjacency that starts one byte past a 16-byte boundary (the column
+    sums then read it byte by byte) gives the same D as an aligned copy."""
+    n = 700
+    A = gg.torus_lattice(n, "moore")
+    buf = torch.zeros(n * n + 64, dtype=torch.uint8, device="cuda")
+    buf[1:1 + n * n] = dev(A).reshape(-1)
+    Au = buf[1:1 + n * n].view(n, n)
+    assert Au.data_ptr() % 16 == 1
+    Ds, info, _ = ctx.solve_batched([Au, dev(A)], -0.5)
+    check_batch([A, A], -0.5, Ds, info, None, "unaligned")
+
+
+def test_batched_level_refusals_large(ctx):
+    """Refusals found in any row chunk of a large graph: a 2 in the last
+    chunk, a self-loop in the first, a gate failure; the good graphs of the
+    batch are unaffected."""
+    n = 1500
+    good = gg.erdos_renyi(n, 5.0 / n, gg.rng_for("parity", 8500))
+    bad_adj = good.copy()
+    bad_adj[n - 1, 3] = 2
+    loop = good.copy()
+    loop[2, 2] = 1
+    small = gg.erdos_renyi(300, 0.03, gg.rng_for("parity", 8501))
+    As = [bad_adj, loop, good, small]
+    gam = [-0.5, -0.5, 0.9, -0.5]
+    Ds, info, _ = ctx.solve_batched([dev(A) for A in As], gam)
+    assert [info.get(k).status for k in range(4)] == [R.RDIST_E_ADJ, R.RDIST_E_ADJ, R.RDIST_E_NOT_DD, R.RDIST_OK]
+    for k in range(3):
+        assert bool((Ds[k] == R.RDIST_UNREACHABLE).all())
+    check_batch([small], -0.5, [Ds[3]], _Sub(info, [3]), None, "beside refusals")
+
+
+@pytest.mark.parametrize("family", ["er", "torus"])
+def test_batched_level_max_size_sampled(ctx, family):
+    """n = 4096 (the level plan's largest) and 4160 (just above: the blocked
+    plan after the batch) with small graphs: sampled rows and columns of Y and
+    D from the oracle's series; the small graphs against the oracle."""
+    big = [gg.erdos_renyi(n, 10.0 / n, gg.rng_for("parity", 8600 + n)) if family == "er"
+           else gg.torus_lattice(n, "manhattan2") for n in (4096, 4160)]
+    small = [gg.erdos_renyi(n, 8.0 / n, gg.rng_for("parity", 8610 + n)) for n in (70, 200, 900)]
+    A_np = big + small
+    note(f"[parity] level max size {family}")
+    Ds, info, graphs = ctx.solve_batched([dev(A) for A in A_np], -0.5, flags=R.RDIST_NO_GRAPH, keep=True)
+    for k, A in enumerate(big):
+        prep = oracle.prepare(A, -0.5)
+        inf = info.get(k)
+        assert inf.status == 0 and inf.delta == prep.delta and inf.gamma == prep.gamma
+        n = A.shape[0]
+        check_sampled(A, graphs[k].y(), Ds[k], prep.gamma, cols=[0, 127, 128, n - 1], rows=[1, 2047, n - 1],
+                      label=f"{family} n={n}")
+    check_batch(small, -0.5, Ds[2:], _Sub(info, [2, 3, 4]), graphs[2:], f"{family} small")
+    for g in graphs:
+        g.release()
+
+
+def test_batched_level_matches_single_blocked_d(ctx):
+    """A mid-size batch (ER and torus, 900 .. 2600) gives the D and, within the
+    Y tolerance, the Y of the single-graph blocked plan (itself checked against
+    the oracle above)."""
+    A_np = [gg.erdos_renyi(2600, 9.0 / 2600, gg.rng_for("parity", 8700)), gg.torus_lattice(1800, "tri"),
+            gg.erdos_renyi(900, 15.0 / 900, gg.rng_for("parity", 8701)), gg.torus_lattice(2100, "cubic18")]
+    Ds, info, graphs = ctx.solve_batched([dev(A) for A in A_np], -0.5, keep=True)
+    for k, A in enumerate(A_np):
+        D1, inf1, g1 = ctx.solve(dev(A), -0.5, keep=True)
+        assert info.get(k).status == inf1["status"] == 0
+        assert torch.equal(Ds[k], D1), f"graph {k} n={A.shape[0]}"
+        Yb, Y1 = graphs[k].y(), g1.y()
+        assert torch.equal(Yb == 0, Y1 == 0)
+        nz = Y1 >= DBL_MIN
+        assert (torch.abs(Yb[nz] - Y1[nz]) / Y1[nz]).max().item() <= 2 * Y_TOL
+        del Yb, Y1
+        g1.release()
+        graphs[k].release()
 
 
 # ---------------------------------------------------------------------------

@@ -73,11 +73,30 @@ def run_server(srv, items, timeout_s=120.0):
     return done
 
 
+def alone(ctx, it):
+    """The request solved by itself: a batch of one (no tile cache) up to
+    n = 4096, the single-graph plan above; paths from its kept Y."""
+    A = it["A"]
+    if it["n"] <= 4096:
+        keep = it["kind"] == R.RDIST_QUERY_PATHS
+        Ds, info, graphs = ctx.solve_batched([A], -0.5, flags=R.RDIST_NO_GRAPH, keep=keep)
+        D, status, g = Ds[0], info.get(0).status, graphs[0] if keep else None
+    else:
+        D, inf, g = ctx.solve(A, -0.5, keep=it["kind"] == R.RDIST_QUERY_PATHS)
+        status = inf["status"]
+    paths = None
+    if g is not None:
+        paths = ctx.next_hop(g, it["cur"].cuda(), it["goal"].cuda(), max_hops=32)
+        torch.cuda.synchronize()
+        g.release()
+    return D, status, paths
+
+
 def test_server_mix_is_bitwise_alone(ctx):
-    items = make_requests(40, stream_index=7, n_hi=900)
-    budget = 3 * footprint(900, R.RDIST_QUERY_PATHS)
-    srv = R.Server(ctx, slots=4, hbm_budget=budget, max_batch=8)
-    note(f"[server] {len(items)} requests, budget {budget >> 20} MiB")
+    items = make_requests(40, stream_index=7, n_hi=1500)
+    budget = 3 * footprint(1500, R.RDIST_QUERY_PATHS)
+    srv = R.Server(ctx, slots=2, hbm_budget=budget, max_batch=8)
+    note(f"[server] {len(items)} requests n={sorted(it['n'] for it in items)}, budget {budget >> 20} MiB")
     done = run_server(srv, items)
     st = srv.stats()
     note(f"[server] stats {st}")
@@ -85,22 +104,46 @@ def test_server_mix_is_bitwise_alone(ctx):
     assert done == {it["id"] for it in items}
     assert st["completed"] == len(items) and st["failed"] == 0
     assert st["max_footprint_in_flight"] <= budget
-    assert st["batches"] >= 1 and st["max_in_flight"] >= 2
+    assert st["batches"] >= 2 and st["batched_requests"] == len(items) and st["max_in_flight"] >= 2
     # each result equals the same request solved alone
     for it in items:
         info = it["info"].get(0)
-        A = it["A"]
+        D, status, paths = alone(ctx, it)
+        assert info.status == status
         if it["kind"] == R.RDIST_QUERY_D:
-            D, ainfo, _ = ctx.solve(A, -0.5)
-            assert info.status == ainfo["status"]
             assert np.array_equal(it["D"].numpy(), D.cpu().numpy()), f"request {it['id']} n={it['n']}"
         else:
-            _, ainfo, g = ctx.solve(A, -0.5, keep=True)
-            alone = ctx.next_hop(g, it["cur"].cuda(), it["goal"].cuda(), max_hops=32)
-            torch.cuda.synchronize()
-            g.release()
-            assert info.status == ainfo["status"]
-            assert np.array_equal(it["paths"].numpy(), alone.cpu().numpy()), f"request {it['id']} paths"
+            assert np.array_equal(it["paths"].numpy(), paths.cpu().numpy()), f"request {it['id']} paths"
+
+
+def test_server_large_request_takes_own_slot(ctx):
+    """A request above the batched range (n = 4200) runs on a slot of its own
+    beside batches; both kinds; results as alone."""
+    items = make_requests(6, stream_index=9, n_hi=300)
+    for kind, rid in ((R.RDIST_QUERY_D, 900001), (R.RDIST_QUERY_PATHS, 900002)):
+        n = 4200
+        A = gg.erdos_renyi(n, 8.0 / n, gg.rng_for("parity", 9200 + kind))
+        it = {"id": rid, "A_np": A, "A": torch.from_numpy(A).cuda(), "kind": kind, "n": n, "info": R.PinnedInfo(1)}
+        if kind == R.RDIST_QUERY_D:
+            it["D"] = torch.empty((n, n), dtype=torch.int16, pin_memory=True)
+        else:
+            pairs = gg.rng_for("parity", 9210).integers(0, n, size=(64, 2)).astype(np.int32)
+            it["cur"] = torch.from_numpy(pairs[:, 0].copy()).pin_memory()
+            it["goal"] = torch.from_numpy(pairs[:, 1].copy()).pin_memory()
+            it["paths"] = torch.empty((64, 33), dtype=torch.int32, pin_memory=True)
+        items.insert(2, it)
+    srv = R.Server(ctx, slots=3, hbm_budget=0, max_batch=8)
+    run_server(srv, items)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(items) and st["batched_requests"] == len(items) - 2
+    for it in items:
+        D, status, paths = alone(ctx, it)
+        assert it["info"].get(0).status == status == 0
+        if it["kind"] == R.RDIST_QUERY_D:
+            assert np.array_equal(it["D"].numpy(), D.cpu().numpy()), f"request {it['id']} n={it['n']}"
+        else:
+            assert np.array_equal(it["paths"].numpy(), paths.cpu().numpy()), f"request {it['id']} paths"
 
 
 def test_server_oracle_spot_checks(ctx):
