@@ -60,11 +60,12 @@ struct BatchPlan {
     Buf pool;       // matrices and step buffers (when Y is not kept)
     Buf scratch;    // per-workgroup scratch of the persistent kernel's blocked solver
     size_t off_level = 0, off_units = 0, off_counter = 0;
+    size_t colsum_ints = 0;   // the level graphs' column sums at the start of the pool (zeroed by kFill)
     int persist_grid = 0;
     int persist_stride = 0;
     // launch program: kernel launches, event records and waits on three
     // streams (0: the caller's, 1: lookahead, 2: persistent kernel)
-    enum OpKind { kLaunch = 0, kIngest = 1, kPersist = 2, kRecord = 3, kWait = 4 };
+    enum OpKind { kLaunch = 0, kIngest = 1, kPersist = 2, kRecord = 3, kWait = 4, kFill = 5 };
     struct Op {
         int kind, stream, phase, K, offset, grid, event;
     };
@@ -135,9 +136,9 @@ int build_units(const std::vector<std::pair<int, int>> &graph_items, std::vector
     return (int)(slots * kXcds);
 }
 
-// Row-chunk height of the level plan's column sums: about 256 KB of A per
+// Row-chunk height of the level plan's column sums: about 64 KB of A per
 // workgroup.
-int colsum_rows(int n) { return std::max(1, (262144 + n - 1) / n); }
+int colsum_rows(int n) { return std::max(1, (65536 + n - 1) / n); }
 
 // Builds the plan's tables and buffers for the batch.  ys (keep_y only):
 // per-graph Y buffers, allocated here and handed to the graph handles after
@@ -175,16 +176,16 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     // device memory: matrices (unless kept), level step buffers and column
     // sums, scratch
     auto kept = [&](int g) { return keep_y || (ext_y && ext_y[g]); };
-    auto colpart_doubles = [&](int g) {
-        const size_t nc = (n[g] + colsum_rows(n[g]) - 1) / colsum_rows(n[g]);
-        return (nc * n[g] + nc + 1) / 2;
-    };
-    size_t pool = 0;
+    p.colsum_ints = 0;
+    for (int g : p.level_ids) p.colsum_ints += (size_t)n[g] + 1;
+    if (p.colsum_ints > (size_t)INT32_MAX) return fail(RDIST_E_NOMEM, "batch too large for one plan");
+    const size_t colsum_doubles = ((p.colsum_ints + 1) / 2 + 31) / 32 * 32;
+    size_t pool = colsum_doubles;
     for (int g : p.persist_ids)
         if (!kept(g) && n[g] > 128) pool += (size_t)np_of(n[g]) * np_of(n[g]);
     for (int g : p.level_ids) {
         const size_t q = np_of(n[g]);
-        pool += (kept(g) ? 0 : q * q) + 2 * (2 * (size_t)kB * q + (size_t)kB * kB) + colpart_doubles(g);
+        pool += (kept(g) ? 0 : q * q) + 2 * (2 * (size_t)kB * q + (size_t)kB * kB);
     }
     if (pool && (st = ensure_grow(c, p.pool, pool * 8))) return st;
     bool persist_medium = false;
@@ -216,7 +217,8 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     // host tables
     std::vector<rd::BatchTask> tasks(np_);
     std::vector<rd::LevelGraph> lgs(nl);
-    double *cur = (double *)p.pool.p;
+    int32_t *cs = (int32_t *)p.pool.p;
+    double *cur = (double *)p.pool.p + colsum_doubles;
     p.flops = p.bytes = 0.0;
     for (int q = 0; q < np_; ++q) {
         const int g = p.persist_ids[q], npg = np_of(n[g]);
@@ -239,8 +241,8 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
             L.Pt[par] = cur + 2 * (size_t)kB * npg;
             cur += 2 * (size_t)kB * npg + (size_t)kB * kB;
         }
-        L.colpart = (int32_t *)cur;
-        cur += colpart_doubles(g);
+        L.colsum = cs;
+        cs += n[g] + 1;
         L.rows_per = colsum_rows(n[g]);
         L.nchunk = (n[g] + L.rows_per - 1) / L.rows_per;
         L.A = A[g];
@@ -280,6 +282,7 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     // build (which use the whole device) and fills the narrow launches after
     using LG = rd::LevelGraph;
     if (nl) {
+        p.ops.push_back(Op{BatchPlan::kFill, 0, 0, 0, 0, 0, 0});       // zero the column sums
         launch(0, rd::kLvColsum, 0, [](const LG &L) { return L.nchunk; });
         p.ops.push_back(Op{BatchPlan::kIngest, 0, 0, 0, 0, nl, 0});   // the gate
         launch(0, rd::kLvBuild, 0, [](const LG &L) { return 2 * L.nt - 1; });
@@ -353,6 +356,7 @@ rdist_status enqueue_plan(BatchPlan &p, const hipStream_t st[3]) {
         switch (o.kind) {
             case BatchPlan::kLaunch: rd::launch_lv(o.phase, lgs, units + o.offset, o.grid, o.K, s); break;
             case BatchPlan::kIngest: rd::launch_lv_gate(lgs, o.grid, s); break;
+            case BatchPlan::kFill: rd::launch_fill_i32((int32_t *)p.pool.p, p.colsum_ints, s); break;
             case BatchPlan::kPersist:
                 rd::launch_batched((const rd::BatchTask *)t, (int)p.persist_ids.size(), (int *)(t + p.off_counter),
                                    o.grid, (double *)p.scratch.p, p.persist_stride, s);

@@ -40,8 +40,9 @@ struct BatchTask {
 // One graph of the level-synchronous batched solver (n <= kLvMaxN).
 // M: np x np (np = n rounded up to 128, nt = np / 128 tiles per side).
 // Step buffers by step parity: Ut, V 128 x np; Pt 128 x 128.
-// colpart: int32 [nchunk][n] partial column sums of A over row chunks of
-// rows_per rows, then nchunk flags (an entry not 0/1, or a self-loop).
+// colsum: int32 [n + 1], zeroed before the plan: the column sums of A
+// (out-degrees), then the validation flag (an entry not 0/1, or a
+// self-loop); the column sums are taken over nchunk row chunks of rows_per.
 // gamma_arg explicit (> 0) or AUTO (< 0).
 struct LevelGraph {
     const uint8_t *A;
@@ -49,7 +50,7 @@ struct LevelGraph {
     double *M;
     double *Ut[2], *V[2], *Pt[2];
     rdist_info *info;
-    int32_t *colpart;
+    int32_t *colsum;
     int32_t n, np, nt, keep;
     int32_t rows_per, nchunk;
     double gamma_arg;
@@ -84,6 +85,7 @@ void launch_small_one(const SmallTask &t, hipStream_t s);
 void launch_batched(const BatchTask *tasks, int count, int *counter, int grid, double *scratch, int scratch_stride,
                     hipStream_t s);
 int batched_blocks_per_cu();
+void launch_fill_i32(int32_t *p, size_t count, hipStream_t s);   // p[0, count) = 0
 void launch_lv_gate(const LevelGraph *gs, int count, hipStream_t s);
 void launch_lv(int phase, const LevelGraph *gs, const int *units, int grid, int K, hipStream_t s);
 // Mixed precision (rd_mixed.hip).
@@ -100,6 +102,21 @@ void launch_residual(const float *X, int np, int n, const int64_t *off, const in
 void launch_fix(const float *X, int np, int n, const float *C, const int32_t *slabs, int nslab, double margin,
                 int16_t *D, rdist_info *info, hipStream_t s);
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s);
+// Path requests of a batch (the request loop), one task per graph with q > 0
+// queries; blk0 and q0 are the prefix sums of path_task_blocks(n) and of q
+// over the tasks before it.
+struct PathTask {
+    const uint8_t *A;            // n x n adjacency (device)
+    const double *Y;             // Y with leading dimension ld (device)
+    unsigned long long *bits;    // n x ceil(n/64) successor bitmap, written by launch_paths_multi
+    const int32_t *cur, *goal;   // q start and goal nodes (device)
+    int32_t *out;                // q x (max_hops + 1), as rdist_next_hop's out
+    int32_t n, ld, q, max_hops;
+    int32_t blk0, q0;
+};
+int path_task_blocks(int n);
+// Bitmaps then paths of every task (tasks: device copy of the table).
+void launch_paths_multi(const PathTask *tasks, int ntasks, int total_blocks, int total_q, hipStream_t s);
 void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s);
 void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
                      const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s);

@@ -35,9 +35,10 @@ struct Slot {
     bool busy = false;
     std::vector<Pending> reqs;           // in flight on this slot
     rdist_graph graph = nullptr;         // a path request above the batched range: its kept Y
-    Buf D, Y, bits, paths, pairs;        // device buffers, grown with headroom and kept
+    Buf D, Y, bits, paths, pairs, tasks; // device buffers, grown with headroom and kept
     rdist_info *info_h = nullptr;        // pinned, one per batched request
     int32_t *pairs_h = nullptr;          // pinned staging of (cur, goal), max_batch * kMaxPairs pairs
+    rd::PathTask *tasks_h = nullptr;     // pinned staging of a batch's path tasks, max_batch entries
     size_t footprint = 0;
 };
 
@@ -161,24 +162,45 @@ rdist_status dispatch(rdist_server s, int k, std::vector<Pending> &batch) {
             }
             RD_HIP(hipMemcpyAsync(cur_d, sl.pairs_h, 2 * tQ * 4, hipMemcpyHostToDevice, st));
         }
+        // every path request of the batch: one task table, one bitmap launch
+        // and one path launch
+        int ntask = 0, tblk = 0, tq = 0;
         for (int i = 0; i < cnt; ++i) {
             const rdist_request &r = batch[i].r;
-            if (r.kind == RDIST_QUERY_D) {
-                RD_HIP(hipMemcpyAsync(r.D_host, Ds[i], (size_t)r.n * r.n * 2, hipMemcpyDeviceToHost, st));
-            } else if (r.q > 0) {
-                const int np = (r.n + kB - 1) / kB * kB;
-                auto *bits = (unsigned long long *)((char *)sl.bits.p + offB[i]);
-                auto *paths = (int32_t *)((char *)sl.paths.p + offP[i]);
-                {
-                    Timer tm(c, st, RDIST_K_NEXTHOP, 0.0, 0.0);
-                    rd::launch_succ_bitmap(r.A_dev, r.n, bits, st);
-                    rd::launch_next_hop(Ys[i], np, r.n, bits, cur_d + offQ[i], goal_d + offQ[i], r.q, r.max_hops,
-                                        paths, st);
-                }
-                RD_HIP(hipGetLastError());
-                RD_HIP(hipMemcpyAsync(r.paths_host, paths, (size_t)r.q * (r.max_hops + 1) * 4,
-                                      hipMemcpyDeviceToHost, st));
+            if (r.kind != RDIST_QUERY_PATHS || r.q == 0) continue;
+            rd::PathTask &t = sl.tasks_h[ntask++];
+            t.A = r.A_dev;
+            t.Y = Ys[i];
+            t.bits = (unsigned long long *)((char *)sl.bits.p + offB[i]);
+            t.cur = cur_d + offQ[i];
+            t.goal = goal_d + offQ[i];
+            t.out = (int32_t *)((char *)sl.paths.p + offP[i]);
+            t.n = r.n;
+            t.ld = (r.n + kB - 1) / kB * kB;
+            t.q = r.q;
+            t.max_hops = r.max_hops;
+            t.blk0 = tblk;
+            t.q0 = tq;
+            tblk += rd::path_task_blocks(r.n);
+            tq += r.q;
+        }
+        if (ntask) {
+            if ((e = grow(c, sl.tasks, sizeof(rd::PathTask) * (size_t)ntask))) return e;
+            RD_HIP(hipMemcpyAsync(sl.tasks.p, sl.tasks_h, sizeof(rd::PathTask) * (size_t)ntask,
+                                  hipMemcpyHostToDevice, st));
+            {
+                Timer tm(c, st, RDIST_K_NEXTHOP, 0.0, 0.0);
+                rd::launch_paths_multi((const rd::PathTask *)sl.tasks.p, ntask, tblk, tq, st);
             }
+            RD_HIP(hipGetLastError());
+        }
+        for (int i = 0; i < cnt; ++i) {
+            const rdist_request &r = batch[i].r;
+            if (r.kind == RDIST_QUERY_D)
+                RD_HIP(hipMemcpyAsync(r.D_host, Ds[i], (size_t)r.n * r.n * 2, hipMemcpyDeviceToHost, st));
+            else if (r.q > 0)
+                RD_HIP(hipMemcpyAsync(r.paths_host, (char *)sl.paths.p + offP[i], (size_t)r.q * (r.max_hops + 1) * 4,
+                                      hipMemcpyDeviceToHost, st));
         }
         s->st.batches += 1;
         s->st.batched_requests += cnt;
@@ -288,6 +310,8 @@ rdist_status rdist_server_create(rdist_ctx ctx, int32_t slots, size_t hbm_budget
             hipHostMalloc((void **)&sl.info_h, sizeof(rdist_info) * (size_t)max_batch, hipHostMallocDefault) !=
                 hipSuccess ||
             hipHostMalloc((void **)&sl.pairs_h, (size_t)2 * kMaxPairs * 4 * max_batch, hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc((void **)&sl.tasks_h, sizeof(rd::PathTask) * (size_t)max_batch, hipHostMallocDefault) !=
                 hipSuccess) {
             rdist_server_destroy(s);
             return fail(RDIST_E_HIP, "server stream, event or pinned buffer creation failed");
@@ -361,9 +385,10 @@ void rdist_server_destroy(rdist_server s) {
         for (Slot &sl : s->slots) {
             if (sl.stream) (void)hipStreamSynchronize(sl.stream);
             if (sl.graph) rdist_graph_release(sl.graph);
-            for (Buf *b : {&sl.D, &sl.Y, &sl.bits, &sl.paths, &sl.pairs}) release(s->ctx, *b);
+            for (Buf *b : {&sl.D, &sl.Y, &sl.bits, &sl.paths, &sl.pairs, &sl.tasks}) release(s->ctx, *b);
             if (sl.info_h) (void)hipHostFree(sl.info_h);
             if (sl.pairs_h) (void)hipHostFree(sl.pairs_h);
+            if (sl.tasks_h) (void)hipHostFree(sl.tasks_h);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.stream) {
                 release_stream_workspace(s->ctx, sl.stream);
