@@ -65,7 +65,10 @@ struct BatchPlan {
     int persist_stride = 0;
     // launch program: kernel launches, event records and waits on three
     // streams (0: the caller's, 1: lookahead, 2: persistent kernel)
-    enum OpKind { kLaunch = 0, kIngest = 1, kPersist = 2, kRecord = 3, kWait = 4, kFill = 5 };
+    // kMark (eager launches with marks only): records marks[K] on the op's
+    // stream once the graphs of completion group K are final (group 0: the
+    // persistent kernel's graphs; group t >= 1: the level graphs with nt = t)
+    enum OpKind { kLaunch = 0, kIngest = 1, kPersist = 2, kRecord = 3, kWait = 4, kFill = 5, kMark = 6 };
     struct Op {
         int kind, stream, phase, K, offset, grid, event;
     };
@@ -292,6 +295,7 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
         wait(2, 0);
     }
     if (np_) p.ops.push_back(Op{BatchPlan::kPersist, nl ? 2 : 0, 0, 0, 0, p.persist_grid, 0});
+    if (np_) p.ops.push_back(Op{BatchPlan::kMark, nl ? 2 : 0, 0, 0, 0, 0, 0});
     if (np_ && nl) record(2, 1);
     if (nl) {
         launch(0, rd::kLvPanel, 0, [](const LG &) { return 1; });
@@ -307,6 +311,7 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
             launch(0, rd::kLvRest, K, [K](const LG &L) {
                 return L.nt > K + 1 ? (L.nt - 1) * (L.nt - 1) : L.nt == K + 1 ? L.nt * L.nt : 0;
             });
+            p.ops.push_back(Op{BatchPlan::kMark, 0, 0, K + 1, 0, 0, 0});   // graphs with nt = K + 1 are final
             if (next) {
                 wait(1, 2);
                 launch(1, rd::kLvPanel, K + 1, [K](const LG &L) { return L.nt > K + 1 ? 1 : 0; });
@@ -347,7 +352,7 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
 
 // Runs the plan's launch program on the streams st[0] (the caller's),
 // st[1] (lookahead) and st[2] (persistent kernel).
-rdist_status enqueue_plan(BatchPlan &p, const hipStream_t st[3]) {
+rdist_status enqueue_plan(BatchPlan &p, const hipStream_t st[3], hipEvent_t *marks = nullptr) {
     char *t = (char *)p.table.p;
     const rd::LevelGraph *lgs = (const rd::LevelGraph *)(t + p.off_level);
     const int *units = (const int *)(t + p.off_units);
@@ -362,6 +367,9 @@ rdist_status enqueue_plan(BatchPlan &p, const hipStream_t st[3]) {
                                    o.grid, (double *)p.scratch.p, p.persist_stride, s);
                 break;
             case BatchPlan::kRecord: RD_HIP(hipEventRecord(p.ev[o.event], s)); break;
+            case BatchPlan::kMark:
+                if (marks) RD_HIP(hipEventRecord(marks[o.K], s));
+                break;
             case BatchPlan::kWait: RD_HIP(hipStreamWaitEvent(s, p.ev[o.event], 0)); break;
         }
     }
@@ -528,7 +536,8 @@ void save_tile_cache(rdist_ctx c) {
 }
 
 rdist_status solve_batch_into(rdist_ctx c, hipStream_t s, int count, const int32_t *n, const uint8_t *const *A,
-                              const double *gamma, int16_t *const *D, double *const *ext_y, rdist_info *info_host) {
+                              const double *gamma, int16_t *const *D, double *const *ext_y, rdist_info *info_host,
+                              hipEvent_t *marks, hipStream_t *tail, const rdist_info **info_dev) {
     for (int g = 0; g < count; ++g)
         if (n[g] < 1 || n[g] > kBatchMaxN) return fail(RDIST_E_ARG, "n out of the batched range");
     Workspace &w = c->ws[s];
@@ -545,8 +554,10 @@ rdist_status solve_batch_into(rdist_ctx c, hipStream_t s, int count, const int32
     {
         Timer tm(c, s, RDIST_K_BATCHED, p.flops, p.bytes);
         const hipStream_t sts[3] = {s, w.aux, w.aux2};
-        if ((st = enqueue_plan(p, sts))) return st;
+        if ((st = enqueue_plan(p, sts, marks))) return st;
     }
+    if (tail) *tail = w.aux2;
+    if (info_dev) *info_dev = (const rdist_info *)p.infos.p;
     if (info_host)
         RD_HIP(hipMemcpyAsync(info_host, p.infos.p, sizeof(rdist_info) * (size_t)count, hipMemcpyDeviceToHost, s));
     return RDIST_OK;

@@ -180,12 +180,20 @@ void release_stream_workspace(rdist_ctx c, hipStream_t s);
 // rd_batch.hip
 void destroy_plans(rdist_ctx c);
 void free_transient_plan(rdist_ctx c, Workspace &w);
-// Eager batched solve on stream s for the request loop: every n <= kBatchMaxN;
-// ext_y[g] (nullable array, nullable entries): caller-owned Y of graph g
-// (np x np, ld np = n rounded up to 128); info_host (pinned, count entries)
-// receives the infos when the stream gets there.
+// Eager batched solve on stream s for the request loop: every n <= kBatchMaxN,
+// threshold T = 128 whatever the batch.  ext_y[g] (nullable array, nullable
+// entries): caller-owned Y of graph g (np x np, ld np = n rounded up to 128);
+// info_host (nullable, pinned, count entries) receives the infos at the end of
+// stream s.  marks (nullable, kBatchMarks events): marks[0] is recorded once
+// the graphs with n <= 128 are final, marks[t] once those with
+// ceil(n / 128) = t are (each only if such graphs exist); *tail (nullable)
+// receives the stream the graphs with n <= 128 finish on (work queued there
+// after the call runs after them), *info_dev the device infos (valid until
+// the next batched call on s).
+constexpr int kBatchMarks = kBatchMaxN / kB + 1;
 rdist_status solve_batch_into(rdist_ctx c, hipStream_t s, int count, const int32_t *n, const uint8_t *const *A,
-                              const double *gamma, int16_t *const *D, double *const *ext_y, rdist_info *info_host);
+                              const double *gamma, int16_t *const *D, double *const *ext_y, rdist_info *info_host,
+                              hipEvent_t *marks, hipStream_t *tail, const rdist_info **info_dev);
 void load_tile_cache(rdist_ctx c);
 void save_tile_cache(rdist_ctx c);
 

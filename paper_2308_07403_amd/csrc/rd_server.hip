@@ -2,10 +2,14 @@
 // streams with their own workspaces), admission by HBM footprint and
 // continuous batching: every request with n <= 4096, full D or paths, joins
 // the next batch of a free slot (one level-synchronous batched solve; a path
-// request keeps Y in the slot's own buffer and its next hops run right after
-// the batch).  Slot buffers grow with headroom and are kept, so a warmed-up
-// server allocates nothing per request.  Driven by the caller's polls; no
-// thread of its own, and the device is never waited on except in
+// request keeps Y in the slot's own buffer).  A batch completes in groups:
+// the graphs with n <= 128 when the persistent kernel ends, those with
+// ceil(n / 128) = t after blocked step t - 1; each group's results (D, infos,
+// and the greedy paths of its path requests) are copied out as soon as the
+// group is final and its requests are reported then, while the batch's
+// larger graphs still run.  Slot buffers grow with headroom and are kept, so
+// a warmed-up server allocates nothing per request.  Driven by the caller's
+// polls; no thread of its own, and the device is never waited on except in
 // rdist_server_destroy.
 #include <hip/hip_runtime.h>
 
@@ -29,16 +33,26 @@ struct Pending {
     size_t footprint;
 };
 
+// Requests of a slot that complete together, and the event after their copies.
+struct Group {
+    int index = 0;             // completion group (its info block in info_h and its events)
+    std::vector<int> reqs;     // indices into Slot::reqs
+    bool done = false;
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
     bool busy = false;
     std::vector<Pending> reqs;           // in flight on this slot
+    std::vector<Group> groups;           // their completion groups
+    int groups_left = 0;
     rdist_graph graph = nullptr;         // a path request above the batched range: its kept Y
     Buf D, Y, bits, paths, pairs, tasks; // device buffers, grown with headroom and kept
-    rdist_info *info_h = nullptr;        // pinned, one per batched request
+    rdist_info *info_h = nullptr;        // pinned, kBatchMarks blocks of max_batch infos
     int32_t *pairs_h = nullptr;          // pinned staging of (cur, goal), max_batch * kMaxPairs pairs
     rd::PathTask *tasks_h = nullptr;     // pinned staging of a batch's path tasks, max_batch entries
+    hipEvent_t marks[kBatchMarks] = {};  // group t's results are final (recorded by the plan)
+    hipEvent_t gdone[kBatchMarks] = {};  // group t's results are in host memory
     size_t footprint = 0;
 };
 
@@ -50,6 +64,8 @@ size_t footprint_of(const rdist_request &r) {
 
 bool batchable(const rdist_request &r) { return r.n <= kBatchMaxN; }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+// Completion group of a batched graph (the batched plan's threshold T = 128).
+int group_of(int n) { return n <= kB ? 0 : (n + kB - 1) / kB; }
 
 }  // namespace
 }  // namespace eng
@@ -80,92 +96,105 @@ void fail_request(rdist_server s, const Pending &p, rdist_status why) {
     s->st.failed += 1;
 }
 
-// Launches the requests of `batch` on slot k.  Returns RDIST_E_AGAIN when the
-// context's own budget is in use (the caller puts them back in the queue).
-rdist_status dispatch(rdist_server s, int k, std::vector<Pending> &batch) {
+// A request above the batched range, alone on the slot's stream: the
+// single-graph plan, its D or its paths on a kept Y; one group.
+rdist_status dispatch_single(rdist_server s, Slot &sl, const rdist_request &r0) {
     rdist_ctx c = s->ctx;
-    Slot &sl = s->slots[k];
     hipStream_t st = sl.stream;
-    rdist_status e = RDIST_OK;
-    const rdist_request &r0 = batch[0].r;
-    if (batch.size() == 1 && !batchable(r0)) {
-        const size_t n2 = (size_t)r0.n * r0.n;
-        if ((e = grow(c, sl.D, n2 * 2))) return e;
-        if (r0.kind == RDIST_QUERY_D) {
-            e = rdist_solve(c, r0.A_dev, r0.n, r0.gamma, RDIST_F64, (int16_t *)sl.D.p, nullptr, sl.info_h, st);
-            if (e) return e;
-            RD_HIP(hipMemcpyAsync(r0.D_host, sl.D.p, n2 * 2, hipMemcpyDeviceToHost, st));
-        } else {
-            const size_t pb = (size_t)r0.q * (r0.max_hops + 1) * 4;
-            if ((e = grow(c, sl.paths, pb))) return e;
-            if ((e = grow(c, sl.pairs, (size_t)2 * kMaxPairs * 4))) return e;
-            rdist_graph g = nullptr;
-            e = rdist_solve(c, r0.A_dev, r0.n, r0.gamma, RDIST_F64 | RDIST_KEEP_Y, (int16_t *)sl.D.p, &g, sl.info_h,
-                            st);
-            if (e) return e;
-            sl.graph = g;
-            if (r0.q > 0) {
-                std::memcpy(sl.pairs_h, r0.cur_host, (size_t)r0.q * 4);
-                std::memcpy(sl.pairs_h + kMaxPairs, r0.goal_host, (size_t)r0.q * 4);
-                int32_t *cur = (int32_t *)sl.pairs.p, *goal = cur + kMaxPairs;
-                RD_HIP(hipMemcpyAsync(cur, sl.pairs_h, (size_t)2 * kMaxPairs * 4, hipMemcpyHostToDevice, st));
-                e = rdist_next_hop(c, g, cur, goal, r0.q, r0.max_hops, (int32_t *)sl.paths.p, st);
-                if (e) return e;
-                RD_HIP(hipMemcpyAsync(r0.paths_host, sl.paths.p, pb, hipMemcpyDeviceToHost, st));
-            }
-        }
-    } else {
-        // one batched solve; path requests keep Y in the slot's buffer
-        const int cnt = (int)batch.size();
-        std::vector<size_t> offD(cnt), offY(cnt), offB(cnt), offQ(cnt), offP(cnt);
-        size_t tD = 0, tY = 0, tB = 0, tQ = 0, tP = 0;
-        for (int i = 0; i < cnt; ++i) {
-            const rdist_request &r = batch[i].r;
-            offD[i] = tD;
-            tD += align256((size_t)r.n * r.n * 2);
-            if (r.kind != RDIST_QUERY_PATHS) continue;
-            const size_t np = ((size_t)r.n + kB - 1) / kB * kB, nw = ((size_t)r.n + 63) / 64;
-            offY[i] = tY;
-            tY += np * np * 8;
-            offB[i] = tB;
-            tB += align256((size_t)r.n * nw * 8);
-            offQ[i] = tQ;
-            tQ += (size_t)r.q;
-            offP[i] = tP;
-            tP += align256((size_t)r.q * (r.max_hops + 1) * 4);
-        }
-        if ((e = grow(c, sl.D, tD))) return e;
-        if (tY && ((e = grow(c, sl.Y, tY)) || (e = grow(c, sl.bits, tB)))) return e;
-        if (tQ && ((e = grow(c, sl.pairs, 2 * tQ * 4)) || (e = grow(c, sl.paths, tP)))) return e;
-        std::vector<int32_t> ns(cnt);
-        std::vector<const uint8_t *> As(cnt);
-        std::vector<double> gs(cnt);
-        std::vector<int16_t *> Ds(cnt);
-        std::vector<double *> Ys(cnt, nullptr);
-        for (int i = 0; i < cnt; ++i) {
-            const rdist_request &r = batch[i].r;
-            ns[i] = r.n;
-            As[i] = r.A_dev;
-            gs[i] = r.gamma;
-            Ds[i] = (int16_t *)((char *)sl.D.p + offD[i]);
-            if (r.kind == RDIST_QUERY_PATHS) Ys[i] = (double *)((char *)sl.Y.p + offY[i]);
-        }
-        e = solve_batch_into(c, st, cnt, ns.data(), As.data(), gs.data(), Ds.data(), Ys.data(), sl.info_h);
+    rdist_status e;
+    const size_t n2 = (size_t)r0.n * r0.n;
+    if ((e = grow(c, sl.D, n2 * 2))) return e;
+    if (r0.kind == RDIST_QUERY_D) {
+        e = rdist_solve(c, r0.A_dev, r0.n, r0.gamma, RDIST_F64, (int16_t *)sl.D.p, nullptr, sl.info_h, st);
         if (e) return e;
-        int32_t *cur_d = (int32_t *)sl.pairs.p, *goal_d = cur_d + tQ;
-        if (tQ) {
-            for (int i = 0; i < cnt; ++i) {
-                const rdist_request &r = batch[i].r;
-                if (r.kind != RDIST_QUERY_PATHS || r.q == 0) continue;
-                std::memcpy(sl.pairs_h + offQ[i], r.cur_host, (size_t)r.q * 4);
-                std::memcpy(sl.pairs_h + tQ + offQ[i], r.goal_host, (size_t)r.q * 4);
-            }
-            RD_HIP(hipMemcpyAsync(cur_d, sl.pairs_h, 2 * tQ * 4, hipMemcpyHostToDevice, st));
+        RD_HIP(hipMemcpyAsync(r0.D_host, sl.D.p, n2 * 2, hipMemcpyDeviceToHost, st));
+    } else {
+        const size_t pb = (size_t)r0.q * (r0.max_hops + 1) * 4;
+        if ((e = grow(c, sl.paths, pb))) return e;
+        if ((e = grow(c, sl.pairs, (size_t)2 * kMaxPairs * 4))) return e;
+        rdist_graph g = nullptr;
+        e = rdist_solve(c, r0.A_dev, r0.n, r0.gamma, RDIST_F64 | RDIST_KEEP_Y, (int16_t *)sl.D.p, &g, sl.info_h, st);
+        if (e) return e;
+        sl.graph = g;
+        if (r0.q > 0) {
+            std::memcpy(sl.pairs_h, r0.cur_host, (size_t)r0.q * 4);
+            std::memcpy(sl.pairs_h + kMaxPairs, r0.goal_host, (size_t)r0.q * 4);
+            int32_t *cur = (int32_t *)sl.pairs.p, *goal = cur + kMaxPairs;
+            RD_HIP(hipMemcpyAsync(cur, sl.pairs_h, (size_t)2 * kMaxPairs * 4, hipMemcpyHostToDevice, st));
+            e = rdist_next_hop(c, g, cur, goal, r0.q, r0.max_hops, (int32_t *)sl.paths.p, st);
+            if (e) return e;
+            RD_HIP(hipMemcpyAsync(r0.paths_host, sl.paths.p, pb, hipMemcpyDeviceToHost, st));
         }
-        // every path request of the batch: one task table, one bitmap launch
-        // and one path launch
-        int ntask = 0, tblk = 0, tq = 0;
-        for (int i = 0; i < cnt; ++i) {
+    }
+    RD_HIP(hipEventRecord(sl.gdone[0], st));
+    sl.groups.assign(1, Group{0, {0}, false});
+    return RDIST_OK;
+}
+
+// Requests with n <= kBatchMaxN: one batched solve on the slot's stream,
+// then per completion group (on the plan's tail stream, after the group's
+// mark): the infos, the group's greedy paths (one bitmap and one path launch
+// for all its path requests), the copies to host memory, and its event.
+rdist_status dispatch_batch(rdist_server s, Slot &sl, const std::vector<Pending> &batch) {
+    rdist_ctx c = s->ctx;
+    hipStream_t st = sl.stream;
+    rdist_status e;
+    const int cnt = (int)batch.size();
+    std::vector<size_t> offD(cnt), offY(cnt), offB(cnt), offQ(cnt), offP(cnt);
+    std::vector<int> grp(cnt);
+    size_t tD = 0, tY = 0, tB = 0, tQ = 0, tP = 0;
+    for (int i = 0; i < cnt; ++i) {
+        const rdist_request &r = batch[i].r;
+        grp[i] = group_of(r.n);
+        offD[i] = tD;
+        tD += align256((size_t)r.n * r.n * 2);
+        if (r.kind != RDIST_QUERY_PATHS) continue;
+        const size_t np = ((size_t)r.n + kB - 1) / kB * kB, nw = ((size_t)r.n + 63) / 64;
+        offY[i] = tY;
+        tY += np * np * 8;
+        offB[i] = tB;
+        tB += align256((size_t)r.n * nw * 8);
+        offQ[i] = tQ;
+        tQ += (size_t)r.q;
+        offP[i] = tP;
+        tP += align256((size_t)r.q * (r.max_hops + 1) * 4);
+    }
+    if ((e = grow(c, sl.D, tD))) return e;
+    if (tY && ((e = grow(c, sl.Y, tY)) || (e = grow(c, sl.bits, tB)))) return e;
+    if (tQ && ((e = grow(c, sl.pairs, 2 * tQ * 4)) || (e = grow(c, sl.paths, tP)))) return e;
+    std::vector<int32_t> ns(cnt);
+    std::vector<const uint8_t *> As(cnt);
+    std::vector<double> gs(cnt);
+    std::vector<int16_t *> Ds(cnt);
+    std::vector<double *> Ys(cnt, nullptr);
+    for (int i = 0; i < cnt; ++i) {
+        const rdist_request &r = batch[i].r;
+        ns[i] = r.n;
+        As[i] = r.A_dev;
+        gs[i] = r.gamma;
+        Ds[i] = (int16_t *)((char *)sl.D.p + offD[i]);
+        if (r.kind == RDIST_QUERY_PATHS) Ys[i] = (double *)((char *)sl.Y.p + offY[i]);
+    }
+    // groups present, in completion order, with their requests
+    std::vector<Group> groups;
+    for (int g = 0; g < kBatchMarks; ++g) {
+        Group G;
+        G.index = g;
+        for (int i = 0; i < cnt; ++i)
+            if (grp[i] == g) G.reqs.push_back(i);
+        if (!G.reqs.empty()) groups.push_back(std::move(G));
+    }
+    // path tasks group by group (each group's tasks contiguous, prefix sums
+    // within the group) and the (cur, goal) pairs, uploaded on st before the
+    // plan, so that every group's work (which waits for a mark of the plan)
+    // sees them
+    const size_t ng = groups.size();
+    int32_t *cur_d = (int32_t *)sl.pairs.p, *goal_d = cur_d + tQ;
+    std::vector<int> task0(ng + 1, 0), tblk(ng, 0), tq(ng, 0);
+    int ntask = 0;
+    for (size_t gi = 0; gi < ng; ++gi) {
+        task0[gi] = ntask;
+        for (int i : groups[gi].reqs) {
             const rdist_request &r = batch[i].r;
             if (r.kind != RDIST_QUERY_PATHS || r.q == 0) continue;
             rd::PathTask &t = sl.tasks_h[ntask++];
@@ -179,35 +208,64 @@ rdist_status dispatch(rdist_server s, int k, std::vector<Pending> &batch) {
             t.ld = (r.n + kB - 1) / kB * kB;
             t.q = r.q;
             t.max_hops = r.max_hops;
-            t.blk0 = tblk;
-            t.q0 = tq;
-            tblk += rd::path_task_blocks(r.n);
-            tq += r.q;
+            t.blk0 = tblk[gi];
+            t.q0 = tq[gi];
+            tblk[gi] += rd::path_task_blocks(r.n);
+            tq[gi] += r.q;
+            std::memcpy(sl.pairs_h + offQ[i], r.cur_host, (size_t)r.q * 4);
+            std::memcpy(sl.pairs_h + tQ + offQ[i], r.goal_host, (size_t)r.q * 4);
         }
-        if (ntask) {
-            if ((e = grow(c, sl.tasks, sizeof(rd::PathTask) * (size_t)ntask))) return e;
-            RD_HIP(hipMemcpyAsync(sl.tasks.p, sl.tasks_h, sizeof(rd::PathTask) * (size_t)ntask,
-                                  hipMemcpyHostToDevice, st));
-            {
-                Timer tm(c, st, RDIST_K_NEXTHOP, 0.0, 0.0);
-                rd::launch_paths_multi((const rd::PathTask *)sl.tasks.p, ntask, tblk, tq, st);
-            }
-            RD_HIP(hipGetLastError());
+    }
+    task0[ng] = ntask;
+    if (ntask) {
+        if ((e = grow(c, sl.tasks, sizeof(rd::PathTask) * (size_t)ntask))) return e;
+        RD_HIP(hipMemcpyAsync(cur_d, sl.pairs_h, 2 * tQ * 4, hipMemcpyHostToDevice, st));
+        RD_HIP(hipMemcpyAsync(sl.tasks.p, sl.tasks_h, sizeof(rd::PathTask) * (size_t)ntask, hipMemcpyHostToDevice,
+                              st));
+    }
+    hipStream_t tail = nullptr;
+    const rdist_info *info_dev = nullptr;
+    e = solve_batch_into(c, st, cnt, ns.data(), As.data(), gs.data(), Ds.data(), Ys.data(), nullptr, sl.marks, &tail,
+                         &info_dev);
+    if (e) return e;
+    const rd::PathTask *tasks_d = (const rd::PathTask *)sl.tasks.p;
+    for (size_t gi = 0; gi < ng; ++gi) {
+        const Group &G = groups[gi];
+        RD_HIP(hipStreamWaitEvent(tail, sl.marks[G.index], 0));
+        RD_HIP(hipMemcpyAsync(sl.info_h + (size_t)G.index * s->max_batch, info_dev, sizeof(rdist_info) * (size_t)cnt,
+                              hipMemcpyDeviceToHost, tail));
+        const int nt = task0[gi + 1] - task0[gi];
+        if (nt) {
+            Timer tm(c, tail, RDIST_K_NEXTHOP, 0.0, 0.0);
+            rd::launch_paths_multi(tasks_d + task0[gi], nt, tblk[gi], tq[gi], tail);
         }
-        for (int i = 0; i < cnt; ++i) {
+        RD_HIP(hipGetLastError());
+        for (int i : G.reqs) {
             const rdist_request &r = batch[i].r;
             if (r.kind == RDIST_QUERY_D)
-                RD_HIP(hipMemcpyAsync(r.D_host, Ds[i], (size_t)r.n * r.n * 2, hipMemcpyDeviceToHost, st));
+                RD_HIP(hipMemcpyAsync(r.D_host, Ds[i], (size_t)r.n * r.n * 2, hipMemcpyDeviceToHost, tail));
             else if (r.q > 0)
                 RD_HIP(hipMemcpyAsync(r.paths_host, (char *)sl.paths.p + offP[i], (size_t)r.q * (r.max_hops + 1) * 4,
-                                      hipMemcpyDeviceToHost, st));
+                                      hipMemcpyDeviceToHost, tail));
         }
-        s->st.batches += 1;
-        s->st.batched_requests += cnt;
+        RD_HIP(hipEventRecord(sl.gdone[G.index], tail));
     }
-    RD_HIP(hipEventRecord(sl.done, st));
+    sl.groups = std::move(groups);
+    s->st.batches += 1;
+    s->st.batched_requests += cnt;
+    return RDIST_OK;
+}
+
+// Launches the requests of `batch` on slot k.  Returns RDIST_E_AGAIN when the
+// context's own budget is in use (the caller puts them back in the queue).
+rdist_status dispatch(rdist_server s, int k, std::vector<Pending> &batch) {
+    Slot &sl = s->slots[k];
+    const rdist_status e = batch.size() == 1 && !batchable(batch[0].r) ? dispatch_single(s, sl, batch[0].r)
+                                                                        : dispatch_batch(s, sl, batch);
+    if (e) return e;
     sl.busy = true;
     sl.reqs = batch;
+    sl.groups_left = (int)sl.groups.size();
     sl.footprint = 0;
     for (auto &p : batch) sl.footprint += p.footprint;
     s->st.footprint_in_flight += sl.footprint;
@@ -254,35 +312,46 @@ void pump(rdist_server s) {
         const rdist_status e = dispatch(s, k, batch);
         if (e == RDIST_E_AGAIN && s->st.in_flight > 0) {
             // the context's budget is in use: retry after something finishes
+            (void)hipDeviceSynchronize();   // whatever the failed dispatch enqueued
             for (auto it = batch.rbegin(); it != batch.rend(); ++it) s->queue.push_front(*it);
             s->st.queued = (int64_t)s->queue.size();
             Slot &sl = s->slots[k];
             if (sl.graph) { rdist_graph_release(sl.graph); sl.graph = nullptr; }
+            sl.groups.clear();
             return;
         }
         if (e) {
             Slot &sl = s->slots[k];
-            (void)hipStreamSynchronize(sl.stream);
+            (void)hipDeviceSynchronize();   // the slot's stream and the plan's other streams
             if (sl.graph) { rdist_graph_release(sl.graph); sl.graph = nullptr; }
+            sl.groups.clear();
             for (auto &p : batch) fail_request(s, p, e);
         }
     }
 }
 
-void complete(rdist_server s, Slot &sl) {
-    for (size_t i = 0; i < sl.reqs.size(); ++i) {
+// Reports the requests of a finished group of slot sl.
+void complete_group(rdist_server s, Slot &sl, Group &G, bool single) {
+    for (int i : G.reqs) {
         const rdist_request &r = sl.reqs[i].r;
-        if (r.info_host) *r.info_host = sl.info_h[i];
+        if (r.info_host) *r.info_host = single ? sl.info_h[0] : sl.info_h[(size_t)G.index * s->max_batch + i];
         s->finished.push_back(r.id);
         s->st.completed += 1;
+        s->st.in_flight -= 1;
     }
+    G.done = true;
+    sl.groups_left -= 1;
+}
+
+void release_slot(rdist_server s, Slot &sl) {
     if (sl.graph) {
         rdist_graph_release(sl.graph);
         sl.graph = nullptr;
     }
-    s->st.in_flight -= (int64_t)sl.reqs.size();
     s->st.footprint_in_flight -= sl.footprint;
     sl.reqs.clear();
+    sl.groups.clear();
+    sl.groups_left = 0;
     sl.footprint = 0;
     sl.busy = false;
 }
@@ -305,14 +374,17 @@ rdist_status rdist_server_create(rdist_ctx ctx, int32_t slots, size_t hbm_budget
     s->max_batch = max_batch;
     s->slots.resize(slots);
     for (Slot &sl : s->slots) {
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc((void **)&sl.info_h, sizeof(rdist_info) * (size_t)max_batch, hipHostMallocDefault) !=
-                hipSuccess ||
-            hipHostMalloc((void **)&sl.pairs_h, (size_t)2 * kMaxPairs * 4 * max_batch, hipHostMallocDefault) !=
-                hipSuccess ||
-            hipHostMalloc((void **)&sl.tasks_h, sizeof(rd::PathTask) * (size_t)max_batch, hipHostMallocDefault) !=
-                hipSuccess) {
+        bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+                  hipHostMalloc((void **)&sl.info_h, sizeof(rdist_info) * (size_t)max_batch * kBatchMarks,
+                                hipHostMallocDefault) == hipSuccess &&
+                  hipHostMalloc((void **)&sl.pairs_h, (size_t)2 * kMaxPairs * 4 * max_batch, hipHostMallocDefault) ==
+                      hipSuccess &&
+                  hipHostMalloc((void **)&sl.tasks_h, sizeof(rd::PathTask) * (size_t)max_batch,
+                                hipHostMallocDefault) == hipSuccess;
+        for (int g = 0; ok && g < kBatchMarks; ++g)
+            ok = hipEventCreateWithFlags(&sl.marks[g], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&sl.gdone[g], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
             rdist_server_destroy(s);
             return fail(RDIST_E_HIP, "server stream, event or pinned buffer creation failed");
         }
@@ -351,17 +423,29 @@ rdist_status rdist_server_poll(rdist_server s, int64_t *done_ids, int32_t max, i
     RD_HIP(hipSetDevice(s->ctx->device));
     for (Slot &sl : s->slots) {
         if (!sl.busy) continue;
-        const hipError_t q = hipEventQuery(sl.done);
-        if (q == hipSuccess) {
-            complete(s, sl);
-        } else if (q != hipErrorNotReady) {
-            (void)hipGetLastError();
-            for (auto &p : sl.reqs) fail_request(s, p, RDIST_E_HIP);
-            s->st.in_flight -= (int64_t)sl.reqs.size();
-            s->st.footprint_in_flight -= sl.footprint;
-            sl.reqs.clear();
-            sl.busy = false;
+        const bool single = sl.reqs.size() == 1 && !batchable(sl.reqs[0].r);
+        bool failed = false;
+        for (Group &G : sl.groups) {
+            if (G.done) continue;
+            const hipError_t q = hipEventQuery(sl.gdone[G.index]);
+            if (q == hipSuccess) {
+                complete_group(s, sl, G, single);
+            } else if (q != hipErrorNotReady) {
+                failed = true;
+                break;
+            }
         }
+        if (failed) {
+            (void)hipGetLastError();
+            for (Group &G : sl.groups) {
+                if (G.done) continue;
+                for (int i : G.reqs) fail_request(s, sl.reqs[i], RDIST_E_HIP);
+                s->st.in_flight -= (int64_t)G.reqs.size();
+                G.done = true;
+            }
+            sl.groups_left = 0;
+        }
+        if (sl.groups_left == 0) release_slot(s, sl);
     }
     pump(s);
     const int32_t k = (int32_t)std::min<size_t>((size_t)max, s->finished.size());
@@ -382,14 +466,17 @@ void rdist_server_destroy(rdist_server s) {
     {
         Guard g(s->ctx);
         (void)hipSetDevice(s->ctx->device);
+        (void)hipDeviceSynchronize();   // every slot's streams, the plans' tail streams included
         for (Slot &sl : s->slots) {
-            if (sl.stream) (void)hipStreamSynchronize(sl.stream);
             if (sl.graph) rdist_graph_release(sl.graph);
             for (Buf *b : {&sl.D, &sl.Y, &sl.bits, &sl.paths, &sl.pairs, &sl.tasks}) release(s->ctx, *b);
             if (sl.info_h) (void)hipHostFree(sl.info_h);
             if (sl.pairs_h) (void)hipHostFree(sl.pairs_h);
             if (sl.tasks_h) (void)hipHostFree(sl.tasks_h);
-            if (sl.done) (void)hipEventDestroy(sl.done);
+            for (int g = 0; g < kBatchMarks; ++g) {
+                if (sl.marks[g]) (void)hipEventDestroy(sl.marks[g]);
+                if (sl.gdone[g]) (void)hipEventDestroy(sl.gdone[g]);
+            }
             if (sl.stream) {
                 release_stream_workspace(s->ctx, sl.stream);
                 (void)hipStreamDestroy(sl.stream);

@@ -146,6 +146,56 @@ def test_server_large_request_takes_own_slot(ctx):
             assert np.array_equal(it["paths"].numpy(), paths.cpu().numpy()), f"request {it['id']} paths"
 
 
+def test_server_reports_small_requests_of_a_batch_first(ctx):
+    """One batch holding a large graph and small ones: requests are reported
+    group by group (n <= 128 first, then by ceil(n / 128)), and every result
+    still equals the request solved alone."""
+    items = []
+    sizes = [4000, 70, 300, 1000, 100, 2000, 64]
+    for k, n in enumerate(sizes):
+        A = gg.erdos_renyi(n, min(1.0, 8.0 / n), gg.rng_for("parity", 9300 + k))
+        kind = R.RDIST_QUERY_PATHS if k % 2 else R.RDIST_QUERY_D
+        it = {"id": 500 + k, "A_np": A, "A": torch.from_numpy(A).cuda(), "kind": kind, "n": n,
+              "info": R.PinnedInfo(1)}
+        if kind == R.RDIST_QUERY_D:
+            it["D"] = torch.empty((n, n), dtype=torch.int16, pin_memory=True)
+        else:
+            pairs = gg.rng_for("parity", 9310 + k).integers(0, n, size=(16, 2)).astype(np.int32)
+            it["cur"] = torch.from_numpy(pairs[:, 0].copy()).pin_memory()
+            it["goal"] = torch.from_numpy(pairs[:, 1].copy()).pin_memory()
+            it["paths"] = torch.empty((16, 33), dtype=torch.int32, pin_memory=True)
+        items.append(it)
+    srv = R.Server(ctx, slots=1, hbm_budget=0, max_batch=16)
+    for it in items:
+        if it["kind"] == R.RDIST_QUERY_D:
+            assert srv.submit(it["id"], it["A"], -0.5, R.RDIST_QUERY_D, D_host=it["D"],
+                              info_ptr=it["info"].at(0)) == R.RDIST_OK
+        else:
+            assert srv.submit(it["id"], it["A"], -0.5, R.RDIST_QUERY_PATHS, cur_host=it["cur"],
+                              goal_host=it["goal"], max_hops=32, paths_host=it["paths"],
+                              info_ptr=it["info"].at(0)) == R.RDIST_OK
+    order = []
+    t0 = time.time()
+    while len(order) < len(items):
+        order.extend(srv.poll())
+        assert time.time() - t0 < 60
+        time.sleep(0.0002)
+    st = srv.stats()
+    srv.close()
+    assert st["batches"] == 1 and st["completed"] == len(items)
+    group = {it["id"]: (0 if it["n"] <= 128 else (it["n"] + 127) // 128) for it in items}
+    note(f"[server] report order {[(i, group[i]) for i in order]}")
+    gs = [group[i] for i in order]
+    assert gs == sorted(gs)
+    for it in items:
+        D, status, paths = alone(ctx, it)
+        assert it["info"].get(0).status == status == 0
+        if it["kind"] == R.RDIST_QUERY_D:
+            assert np.array_equal(it["D"].numpy(), D.cpu().numpy()), f"request {it['id']} n={it['n']}"
+        else:
+            assert np.array_equal(it["paths"].numpy(), paths.cpu().numpy()), f"request {it['id']} paths"
+
+
 def test_server_oracle_spot_checks(ctx):
     items = make_requests(12, stream_index=8, n_hi=400)
     srv = R.Server(ctx, slots=3, hbm_budget=0, max_batch=4)
