@@ -374,9 +374,11 @@ def bench_c5(args, torch, R, gg):
     levels = []
     for frac in [float(x) for x in args.c5_levels.split(",") if x.strip()]:
         qps = frac * sat
-        reqs = gg.c5_requests(args.c5_requests, qps=qps, stream_index=1)
+        # args.c5_requests per level, fewer at low rates (at most about 10 s of arrivals)
+        count = max(1000, min(args.c5_requests, int(qps * 10.0)))
+        reqs = gg.c5_requests(count, qps=qps, stream_index=1)
         arrivals = np.array([r.arrival_s for r in reqs])
-        log(f"[bench] c5: {args.c5_requests} requests at {qps:.0f} QPS")
+        log(f"[bench] c5: {count} requests at {qps:.0f} QPS")
         lat, wall, st, conc = run(arrivals)
         fl = sum(flops_pool[k % pool_n] for k in range(len(arrivals)))
         hist = np.bincount(np.asarray(conc, dtype=np.int64), minlength=1).tolist() if conc else []
@@ -546,7 +548,7 @@ def main():
     ap.add_argument("--c5-sat", type=int, default=3000, help="C5: requests of the saturation run")
     ap.add_argument("--c5-slots", type=int, default=2)
     ap.add_argument("--c5-budget-gib", type=int, default=16)
-    ap.add_argument("--c5-levels", default="0.5,0.8",
+    ap.add_argument("--c5-levels", default="0.1,0.5,0.8",
                     help="C5: Poisson rates as fractions of the saturated rate (comma list; empty for none)")
     ap.add_argument("--cpu-gj-steps", type=int, default=256)
     ap.add_argument("--cpu-rows", type=int, default=2048)
