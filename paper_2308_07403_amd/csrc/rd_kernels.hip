@@ -277,16 +277,32 @@ __global__ __launch_bounds__(256) void k_panel_finish(const double *__restrict__
     }
 }
 
-// Standalone readout over Y (ld) into D (n x n).
+// Standalone readout over Y (ld) into D (n x n).  A workgroup takes chunks
+// of 1024 columns of one row, four entries per thread; with VEC (Y 16-byte
+// aligned, ld even) the four are read as two 16-byte loads.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_epilogue(const double *__restrict__ Y, int n, int ld,
                                                   int16_t *__restrict__ D, rdist_info *info) {
     if (info->status != RDIST_OK) return;
     const double lg = rd_inv_log(info->gamma);
     Counts cnt;
-    const size_t total = (size_t)n * n;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
-        const size_t i = e / n, j = e - i * n;
-        D[e] = rd_encode(Y[i * ld + j], lg, cnt);
+    const int cpr = (n + 1023) / 1024;
+    const long long units = (long long)n * cpr;
+    for (long long u = blockIdx.x; u < units; u += gridDim.x) {
+        const int i = (int)(u / cpr), ch = (int)(u - (long long)i * cpr);
+        const int j0 = ch * 1024 + threadIdx.x * 4;
+        const double *__restrict__ yr = Y + (size_t)i * ld;
+        int16_t *__restrict__ dr = D + (size_t)i * n;
+        if (VEC && j0 + 3 < n) {
+            const double2 a = *reinterpret_cast<const double2 *>(yr + j0);
+            const double2 b = *reinterpret_cast<const double2 *>(yr + j0 + 2);
+            dr[j0] = rd_encode(a.x, lg, cnt);
+            dr[j0 + 1] = rd_encode(a.y, lg, cnt);
+            dr[j0 + 2] = rd_encode(b.x, lg, cnt);
+            dr[j0 + 3] = rd_encode(b.y, lg, cnt);
+        } else {
+            for (int j = j0; j < min(n, j0 + 4); ++j) dr[j] = rd_encode(yr[j], lg, cnt);
+        }
     }
     flush_counts(info, cnt);
 }
@@ -394,9 +410,12 @@ void launch_panel_finish(const double *S, int lds, int b, int K0, double *Pt, do
 }
 
 void launch_epilogue(const double *Y, int n, int ld, int16_t *D, rdist_info *info, hipStream_t s) {
-    const size_t total = (size_t)n * n;
-    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((total + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_epilogue, dim3(blocks), dim3(256), 0, s, Y, n, ld, D, info);
+    const long long units = (long long)n * ((n + 1023) / 1024);
+    const int blocks = (int)std::max<long long>(1, std::min<long long>(units, 8192));
+    if ((reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (ld & 1) == 0)
+        hipLaunchKernelGGL(k_epilogue<true>, dim3(blocks), dim3(256), 0, s, Y, n, ld, D, info);
+    else
+        hipLaunchKernelGGL(k_epilogue<false>, dim3(blocks), dim3(256), 0, s, Y, n, ld, D, info);
 }
 
 void launch_info_set(rdist_info *info, double gamma, hipStream_t s) {

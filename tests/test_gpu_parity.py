@@ -197,6 +197,61 @@ def test_epilogue_on_oracle_y(ctx):
     assert info["n_unreachable"] == r.unreachable and info["n_subnormal"] == r.subnormal
 
 
+@pytest.mark.parametrize("gamma", [0.999, 0.5, 0.05, 1e-3])
+def test_epilogue_near_integer_distances(ctx, gamma):
+    """Entries Y = gamma^(k + delta) for many distances k and offsets delta
+    from far inside to just outside the band around each integer where the
+    readout falls back to the full logarithm (the band widens as gamma -> 1),
+    the eta boundary included; zeros, subnormals and saturating distances
+    too.  Read out from an aligned Y with even leading dimension (16-byte
+    loads) and from a shifted Y with odd leading dimension (scalar loads):
+    D and every counter but the ambiguity count equal the oracle's readout.
+    Entries whose t = R - eta lies within the ambiguity band of an integer
+    (here planted on purpose) are decided by the last bits of log(Y) /
+    log(gamma), which the engine forms as a product with the reciprocal and
+    the oracle as a quotient; there D may differ by one, and nowhere else."""
+    n = 301
+    rng = gg.rng_for("parity", 4100 + int(1e4 * gamma))
+    kmax = min(30000.0, 700.0 / -np.log(gamma))
+    # offsets around eta = 1e-9: on it, well inside the ambiguity band (5e-11) and well outside it (2e-10),
+    # never on the band's edge, where last-bit differences of log would decide the count
+    deltas = np.array([0.0, 1e-12, -1e-12, 1e-10, -1e-10, 0.8e-9, 0.95e-9, 1e-9, 1.05e-9, 1.2e-9, -1e-9, 1e-7,
+                       -1e-7, 1e-6, -1e-6, 5e-5, -5e-5, 1e-4, -1e-4, 2e-4, -2e-4, 1e-3, -1e-3, 0.01, -0.01, 0.5,
+                       -0.5])
+    k = rng.integers(0, int(kmax), size=n * n).astype(np.float64)
+    d = np.where(rng.random(n * n) < 0.7, deltas[rng.integers(0, deltas.size, size=n * n)],
+                 rng.uniform(-0.5, 0.5, size=n * n))
+    Y = (gamma ** (k + d)).reshape(n, n)
+    Y.flat[:5] = [0.0, 5e-320, 1e-310, 1.0, 3.0]
+    r = oracle.readout(Y, gamma)
+    assert r.ambiguous > 0 or gamma == 1e-3
+    for aligned in (True, False):
+        if aligned:
+            buf = torch.zeros((n, n + 1), dtype=torch.float64, device="cuda")
+            Yd = buf[:, :n]
+        else:
+            buf = torch.zeros(n * (n + 2) + 1, dtype=torch.float64, device="cuda")
+            Yd = buf[1:1 + n * (n + 2)].view(n, n + 2)[:, :n]
+        Yd.copy_(torch.from_numpy(Y))
+        assert (Yd.stride(0) % 2 == 0) == aligned and (Yd.data_ptr() % 16 == 0) == aligned
+        D = ctx.epilogue(Yd, gamma)
+        torch.cuda.synchronize()
+        info = ctx.info.get(0).as_dict()
+        Dg = D.cpu().numpy()
+        bad = Dg != r.D
+        note(f"[parity] readout gamma={gamma} aligned={aligned} ambiguous={r.ambiguous} "
+             f"(engine {info['n_ambiguous']}), D differences {int(bad.sum())}")
+        if bad.any():
+            yb = Y[bad]
+            tb = np.log(yb) / np.log(gamma) - oracle.ETA
+            assert np.all(np.abs(tb - np.rint(tb)) < oracle.BETA), (yb[:4], tb[:4])
+            assert np.all(np.abs(Dg[bad].astype(int) - r.D[bad].astype(int)) == 1)
+            assert bad.sum() <= r.ambiguous
+        assert (info["n_unreachable"], info["n_subnormal"], info["n_saturated"], info["n_negative"]) == \
+            (r.unreachable, r.subnormal, r.saturated, r.negative)
+        assert abs(info["n_ambiguous"] - r.ambiguous) <= max(2, r.ambiguous // 100)
+
+
 # ---------------------------------------------------------------------------
 # Next hop
 # ---------------------------------------------------------------------------
