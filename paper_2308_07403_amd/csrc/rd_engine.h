@@ -60,6 +60,7 @@ struct Workspace {
     // block, FP32 P, certification counters + slab flags, sparse rows of A,
     // residual and correction slabs
     Buf m32, v32, u32, s64, p32, cert, csr_cnt, csr_off, csr_col, r32, c32;
+    Buf xh, xl, rh, rl;   // bf16 hi/lo parts of the FP32 inverse and of the scaled residual
     double *m() const { return (double *)M.p; }
     int32_t *outdeg() const { return (int32_t *)small.p; }
     int32_t *bad() const { return outdeg() + n_cap + 1; }

@@ -381,7 +381,7 @@ void free_workspace(rdist_ctx c, Workspace &w) {
     free_transient_plan(c, w);
     for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2, &w.Pt2, &w.small,
                    &w.m32, &w.v32, &w.u32, &w.s64, &w.p32, &w.cert, &w.csr_cnt, &w.csr_off, &w.csr_col, &w.r32,
-                   &w.c32})
+                   &w.c32, &w.xh, &w.xl, &w.rh, &w.rl})
         release(c, *b);
     for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
         if (e) (void)hipEventDestroy(e);

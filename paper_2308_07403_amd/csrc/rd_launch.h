@@ -97,10 +97,17 @@ void launch_certify(const float *X, int np, int n, double margin, int16_t *D, in
                     unsigned long long *cnt, rdist_info *info, hipStream_t s);
 void launch_row_count(const uint8_t *A, int n, int32_t *cnt, hipStream_t s);
 void launch_row_fill(const uint8_t *A, int n, const int64_t *off, int32_t *cols, hipStream_t s);
+// rmax: device unsigned, zeroed by the caller; receives the bits of max |R|.
 void launch_residual(const float *X, int np, int n, const int64_t *off, const int32_t *cols, const int32_t *slabs,
-                     int nslab, float *R, const rdist_info *info, hipStream_t s);
+                     int nslab, float *R, unsigned *rmax, const rdist_info *info, hipStream_t s);
+// rmax: as written by launch_residual when C was formed from the scaled
+// residual (launch_split_bf16 with rmax), else nullptr.
 void launch_fix(const float *X, int np, int n, const float *C, const int32_t *slabs, int nslab, double margin,
-                int16_t *D, rdist_info *info, hipStream_t s);
+                const unsigned *rmax, int16_t *D, rdist_info *info, hipStream_t s);
+// hi/lo bf16 parts (16-bit patterns) of 2^s src, s = 0 or the residual's
+// scale (rmax given).
+void launch_split_bf16(const float *src, size_t count, uint16_t *hi, uint16_t *lo, const unsigned *rmax,
+                       hipStream_t s);
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s);
 // Path requests of a batch (the request loop), one task per graph with q > 0
 // queries; blk0 and q0 are the prefix sums of path_task_blocks(n) and of q

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_row_fill(const uint8_t *__restrict__ A,
 __global__ __launch_bounds__(256) void k_residual(const float *__restrict__ X, int np, int n,
                                                   const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
                                                   const int32_t *__restrict__ slabs, int nslab, float *__restrict__ R,
-                                                  const rdist_info *info) {
+                                                  unsigned *__restrict__ rmax, const rdist_info *info) {
     if (info->status != RDIST_OK) return;
     const double gamma = info->gamma;
     const int k = blockIdx.x * 8 + (threadIdx.x >> 5), c = (threadIdx.x & 31) * 4;
@@ -215,15 +215,50 @@ __global__ __launch_bounds__(256) void k_residual(const float *__restrict__ X, i
     r.z = (float)(((k == j + 2) ? 1.0 : 0.0) - (double)xk.z + gamma * a2);
     r.w = (float)(((k == j + 3) ? 1.0 : 0.0) - (double)xk.w + gamma * a3);
     *reinterpret_cast<float4 *>(R + (size_t)k * ((size_t)nslab * kSlab) + (size_t)s * kSlab + c) = r;
+    // largest |R| (the bits of a nonnegative float order like its value)
+    unsigned m = max(max(__float_as_uint(fabsf(r.x)), __float_as_uint(fabsf(r.y))),
+                     max(__float_as_uint(fabsf(r.z)), __float_as_uint(fabsf(r.w))));
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(rmax, m);
+}
+
+// Power-of-two exponent s with 2^s max|R| in [0.5, 1) (0 when R is zero).
+__device__ __forceinline__ int residual_scale(unsigned rmax_bits) {
+    if (rmax_bits == 0) return 0;
+    const int e = (int)((rmax_bits >> 23) & 0xFF) - 127;   // max|R| in [2^e, 2^(e+1))
+    return -(e + 1);
+}
+
+// bf16 with round to nearest even of a finite float (as its 16 high bits).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// hi = bf16(2^s x), lo = bf16(2^s x - hi) (the difference is exact in FP32)
+// for count floats; s = 0, or the residual's scale when rmax is given.
+__global__ __launch_bounds__(256) void k_split_bf16(const float *__restrict__ src, size_t count,
+                                                    uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+                                                    const unsigned *__restrict__ rmax) {
+    const float sc = rmax ? ldexpf(1.0f, residual_scale(*rmax)) : 1.0f;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
+        const float x = src[e] * sc;
+        const uint16_t h = bf16_rne(x);
+        hi[e] = h;
+        lo[e] = bf16_rne(x - __uint_as_float((unsigned)h << 16));
+    }
 }
 
 // Uncertified entries of the slabs: Y = X + (X R), the correction C = X R
-// (np x w) from the FP32 GEMM; D from Y in FP64.
+// (np x w) from the GEMMs on the residual scaled by 2^s (undone here
+// exactly); D from Y in FP64.
 __global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np, int n, const float *__restrict__ C,
                                              const int32_t *__restrict__ slabs, int nslab, double margin,
-                                             int16_t *__restrict__ D, rdist_info *info) {
+                                             const unsigned *__restrict__ rmax, int16_t *__restrict__ D,
+                                             rdist_info *info) {
     if (info->status != RDIST_OK) return;
     const double il = rd_inv_log(info->gamma);
+    const double unscale = rmax ? ldexp(1.0, -residual_scale(*rmax)) : 1.0;
     const int i = blockIdx.x * 2 + (threadIdx.x >> 7), c = threadIdx.x & 127;
     const int s = blockIdx.y;
     const int j = slabs[s] * kSlab + c;
@@ -231,7 +266,7 @@ __global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np
     if (i < n && j < n) {
         const float x = X[(size_t)i * np + j];
         if (uncertified(x, il, margin)) {
-            const double y = (double)x + (double)C[(size_t)i * ((size_t)nslab * kSlab) + (size_t)s * kSlab + c];
+            const double y = (double)x + unscale * (double)C[(size_t)i * ((size_t)nslab * kSlab) + (size_t)s * kSlab + c];
             D[(size_t)i * n + j] = rd_encode(y, il, cnt);
         }
     }
@@ -271,12 +306,17 @@ void launch_row_fill(const uint8_t *A, int n, const int64_t *off, int32_t *cols,
     hipLaunchKernelGGL(k_row_fill, dim3(n), dim3(256), 0, s, A, n, off, cols);
 }
 void launch_residual(const float *X, int np, int n, const int64_t *off, const int32_t *cols, const int32_t *slabs,
-                     int nslab, float *R, const rdist_info *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual, dim3(np / 8, nslab), dim3(256), 0, s, X, np, n, off, cols, slabs, nslab, R, info);
+                     int nslab, float *R, unsigned *rmax, const rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_residual, dim3(np / 8, nslab), dim3(256), 0, s, X, np, n, off, cols, slabs, nslab, R, rmax,
+                       info);
 }
 void launch_fix(const float *X, int np, int n, const float *C, const int32_t *slabs, int nslab, double margin,
-                int16_t *D, rdist_info *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_fix, dim3(np / 2, nslab), dim3(256), 0, s, X, np, n, C, slabs, nslab, margin, D, info);
+                const unsigned *rmax, int16_t *D, rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_fix, dim3(np / 2, nslab), dim3(256), 0, s, X, np, n, C, slabs, nslab, margin, rmax, D, info);
+}
+void launch_split_bf16(const float *src, size_t count, uint16_t *hi, uint16_t *lo, const unsigned *rmax,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_split_bf16, dim3(grid_for(count)), dim3(256), 0, s, src, count, hi, lo, rmax);
 }
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s) {
     hipLaunchKernelGGL(k_set_mixed_info, dim3(1), dim3(1), 0, s, info, uncertified, fraction);
@@ -423,12 +463,42 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
         RD_HIP(hipMemcpyAsync(doff, off.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
         RD_HIP(hipMemcpyAsync(dslabs, slabs.data(), (size_t)ns * 4, hipMemcpyHostToDevice, s));
         rd::launch_row_fill(A, n, doff, (int32_t *)w.csr_col.p, s);
-        rd::launch_residual(M, np, n, doff, (const int32_t *)w.csr_col.p, dslabs, ns, (float *)w.r32.p, dinfo, s);
+        unsigned *rmax = (unsigned *)((char *)w.cert.p + 64);     // inside the 256 B header, unused by certify
+        RD_HIP(hipMemsetAsync(rmax, 0, sizeof(unsigned), s));
+        rd::launch_residual(M, np, n, doff, (const int32_t *)w.csr_col.p, dslabs, ns, (float *)w.r32.p, rmax, dinfo,
+                            s);
         RD_HIP(hipGetLastError());
-        // C = X0 R (row-major np x w), i.e. column-major C^T = R^T X0^T
-        RD_BLAS(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, (int)wcols, np, np, &one,
-                              (const float *)w.r32.p, (int)wcols, M, np, &zero, (float *)w.c32.p, (int)wcols));
-        rd::launch_fix(M, np, n, (const float *)w.c32.p, dslabs, ns, margin, D, dinfo, s);
+        // C = X0 R (row-major np x w), i.e. column-major C^T = R^T X0^T, from
+        // the bf16 hi/lo parts of X0 and of 2^s R: Rh Xh + Rl Xh + Rh Xl with
+        // FP32 accumulation (the dropped parts are about 2^-16 of C, and C is
+        // about eps32 Y); FP32 GEMM if the bf16 GEMM is not available
+        const size_t nx = (size_t)np * np, nr = (size_t)np * wcols;
+        bool bf16 = false;
+        if (!ensure(c, w.xh, nx * 2) && !ensure(c, w.xl, nx * 2) && !ensure(c, w.rh, nr * 2) &&
+            !ensure(c, w.rl, nr * 2)) {
+            rd::launch_split_bf16(M, nx, (uint16_t *)w.xh.p, (uint16_t *)w.xl.p, nullptr, s);
+            rd::launch_split_bf16((const float *)w.r32.p, nr, (uint16_t *)w.rh.p, (uint16_t *)w.rl.p, rmax, s);
+            RD_HIP(hipGetLastError());
+            const void *ra[3] = {w.rh.p, w.rl.p, w.rh.p}, *xb[3] = {w.xh.p, w.xh.p, w.xl.p};
+            bf16 = true;
+            for (int t3 = 0; t3 < 3 && bf16; ++t3) {
+                const rocblas_status bs = rocblas_gemm_ex(
+                    h, rocblas_operation_none, rocblas_operation_none, (int)wcols, np, np, &one, ra[t3],
+                    rocblas_datatype_bf16_r, (int)wcols, xb[t3], rocblas_datatype_bf16_r, np, t3 ? &one : &zero,
+                    w.c32.p, rocblas_datatype_f32_r, (int)wcols, w.c32.p, rocblas_datatype_f32_r, (int)wcols,
+                    rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0);
+                if (bs == rocblas_status_not_implemented && t3 == 0) bf16 = false;
+                else if (bs != rocblas_status_success) RD_BLAS(bs);
+            }
+        }
+        if (!bf16) {
+            (void)hipGetLastError();
+            g_last_error.clear();
+            RD_HIP(hipMemsetAsync(rmax, 0, sizeof(unsigned), s));   // C from the unscaled residual
+            RD_BLAS(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, (int)wcols, np, np, &one,
+                                  (const float *)w.r32.p, (int)wcols, M, np, &zero, (float *)w.c32.p, (int)wcols));
+        }
+        rd::launch_fix(M, np, n, (const float *)w.c32.p, dslabs, ns, margin, rmax, D, dinfo, s);
         RD_HIP(hipGetLastError());
         // keep the host vectors alive until the copies above have run
         RD_HIP(hipStreamSynchronize(s));
