@@ -110,10 +110,17 @@ __global__ __launch_bounds__(256) void k_fill_sentinel(int16_t *D, size_t count,
 // Blocked Gauss-Jordan
 // ---------------------------------------------------------------------------
 
+// The kernels of the lookahead chain (the next block's diagonal update, its
+// inverse and its row and column tiles) run beside the big update and are
+// on the critical path: their waves take the highest issue priority on the
+// SIMDs they share with the update's waves.
+__device__ __forceinline__ void lookahead_priority() { __builtin_amdgcn_s_setprio(3); }
+
 __global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int ld, int K,
                                                double *__restrict__ Pt, double *__restrict__ V, int ldv,
                                                rdist_info *info) {
     if (info->status != RDIST_OK) return;
+    lookahead_priority();
     __shared__ double piv[4 * kTile];
     __shared__ double tq[64][65];
     panel_core(M, ld, K, Pt, V, ldv, info, piv, tq);
@@ -133,6 +140,7 @@ __global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, in
                                                 double *__restrict__ V, int ldv, const rdist_info *info) {
     constexpr int m = MT;
     if (info->status != RDIST_OK) return;
+    lookahead_priority();
     __shared__ double lds[kTileLdsDoubles];
     const int bdim = m * kTile;
     const int blk = blockIdx.x;
@@ -232,6 +240,7 @@ __global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int l
                                                    rdist_info *info) {
     constexpr int m = MT;
     if (info->status != RDIST_OK) return;
+    if (MODE == kDiag || (MODE == kAll && !FUSED && MT == 1)) lookahead_priority();
     __shared__ double lds[kTileLdsDoubles];
     int I, J;
     update_tile_index<MODE>(blockIdx.x, nt, L0, m, wt, I, J);
@@ -261,6 +270,7 @@ __global__ __launch_bounds__(256) void k_panel_finish(const double *__restrict__
                                                       double *__restrict__ Pt, double *__restrict__ V, int ldv,
                                                       const rdist_info *info) {
     if (info->status != RDIST_OK) return;
+    lookahead_priority();
     __shared__ double t[64][65];
     const int nb64 = b / 64;
     const int bi = blockIdx.x / nb64, bj = blockIdx.x - (blockIdx.x / nb64) * nb64;

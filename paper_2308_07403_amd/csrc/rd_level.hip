@@ -479,6 +479,7 @@ __global__ __launch_bounds__(256) void k_lv_panel(const LevelGraph *__restrict__
     if (!lv_unit(units, gi, item)) return;
     const LevelGraph g = gs[gi];
     if (g.info->status != RDIST_OK) return;
+    __builtin_amdgcn_s_setprio(3);   // lookahead chain: ahead of the update's waves on shared SIMDs
     __shared__ double piv[4 * kTile];
     __shared__ double tq[64][65];
     const int par = K & 1;
@@ -494,6 +495,7 @@ __global__ __launch_bounds__(256) void k_lv_rowcol(const LevelGraph *__restrict_
     if (!lv_unit(units, gi, item)) return;
     const LevelGraph g = gs[gi];
     if (g.info->status != RDIST_OK) return;
+    __builtin_amdgcn_s_setprio(3);   // lookahead chain: ahead of the update's waves on shared SIMDs
     __shared__ double lds[kTileLdsDoubles];
     const int np = g.np, par = K & 1;
     const int J = item < K ? item : item + 1;
