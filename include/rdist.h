@@ -288,7 +288,11 @@ typedef struct rdist_kernel_stats {
 #define RDIST_K_REFINE 11     /* mixed precision: residual, correction product and recompute */
 #define RDIST_K_COUNT 12
 
-/* Enables (1) or disables (0) per-kernel event timing; enabling resets the counters. */
+/* Per-kernel event timing: 0 off, 1 every kernel class, or a mask of
+ * RDIST_TIMING_CLASS(k) bits timing only those classes (each timed launch
+ * records two events on its stream, so a narrow mask disturbs a timed run
+ * less).  Enabling resets the counters; RDIST_E_ARG for a negative value. */
+#define RDIST_TIMING_CLASS(k) (2 << (k))
 rdist_status rdist_set_timing(rdist_ctx ctx, int enable);
 /* Reads the counters of kernel class `which` (RDIST_K_*); synchronises the
  * streams the timed launches ran on. */

@@ -542,8 +542,9 @@ rdist_status rdist_epilogue(rdist_ctx c, const double *Y_dev, int32_t n, int32_t
 rdist_status rdist_set_timing(rdist_ctx c, int enable) {
     if (!c) return fail(RDIST_E_ARG, "ctx is NULL");
     Guard g(c);
+    if (enable < 0) return fail(RDIST_E_ARG, "negative timing mask");
     drain_timing(c);
-    c->timing = enable != 0;
+    c->timing_mask = enable == 1 ? (1u << RDIST_K_COUNT) - 1 : ((uint32_t)enable >> 1) & ((1u << RDIST_K_COUNT) - 1);
     if (enable) std::memset(c->stats, 0, sizeof(c->stats));
     return RDIST_OK;
 }

@@ -36,7 +36,33 @@ __global__ void k_zero_i32(int32_t *p, int count) {
     if (i < count) p[i] = 0;
 }
 
-// Column sums of A (out-degrees) and validation, over a block of rows.
+// Column sums of A (out-degrees) and validation, over a block of rows:
+// with 16 | n and A 16-byte aligned, thread t of workgroup (x, y) reads 16
+// bytes (columns 16 (256 x + t) ..) of each row of block y.
+__global__ __launch_bounds__(256) void k_colsum16(const uint8_t *__restrict__ A, int n, int rows_per_block,
+                                                  int32_t *outdeg, int32_t *bad) {
+    const int j0 = (blockIdx.x * 256 + threadIdx.x) * 16;
+    if (j0 >= n) return;
+    const int i0 = blockIdx.y * rows_per_block;
+    const int i1 = min(n, i0 + rows_per_block);
+    int s[16] = {};
+    int b = 0;
+    for (int i = i0; i < i1; ++i) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(A + (size_t)i * n + j0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int a = (int)((w[q >> 2] >> (8 * (q & 3))) & 0xFFu);
+            s[q] += a;
+            b |= (a > 1) | ((i == j0 + q) & (a != 0));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        if (s[q]) atomicAdd(&outdeg[j0 + q], s[q]);
+    if (b) atomicOr(bad, 1);
+}
+
 __global__ __launch_bounds__(256) void k_colsum(const uint8_t *__restrict__ A, int n, int rows_per_block,
                                                 int32_t *outdeg, int32_t *bad) {
     const int j = blockIdx.x * 256 + threadIdx.x;
@@ -79,23 +105,26 @@ __global__ __launch_bounds__(1024) void k_finalize(const int32_t *outdeg, const 
     }
 }
 
-// M = I - gamma*A on the n x n block, identity on the padding (np x np, ld).
+// M = I - gamma*A on the n x n block, identity on the padding (np x np, ld):
+// a workgroup per row (grid-stride over rows), two entries per thread and
+// 16-byte stores.
 __global__ __launch_bounds__(256) void k_build_m(const uint8_t *__restrict__ A, int n, int np, int ld,
                                                  double *__restrict__ M, const rdist_info *info) {
     const double gamma = info->gamma;
-    const size_t pairs = (size_t)np * np / 2;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < pairs; e += (size_t)gridDim.x * 256) {
-        const int i = (int)((2 * e) / np);
-        const int j = (int)((2 * e) % np);     // even; np is even
-        double v[2];
+    for (int i = blockIdx.x; i < np; i += gridDim.x) {
+        const uint8_t *__restrict__ ar = A + (size_t)i * n;
+        double *__restrict__ mr = M + (size_t)i * ld;
+        for (int j = 2 * threadIdx.x; j < np; j += 512) {   // even; np is even
+            double v[2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int jj = j + q;
-            double x = (i == jj) ? 1.0 : 0.0;
-            if (i < n && jj < n) x -= gamma * (double)A[(size_t)i * n + jj];
-            v[q] = x;
+            for (int q = 0; q < 2; ++q) {
+                const int jj = j + q;
+                double x = (i == jj) ? 1.0 : 0.0;
+                if (i < n && jj < n) x -= gamma * (double)ar[jj];
+                v[q] = x;
+            }
+            *reinterpret_cast<double2 *>(mr + j) = double2{v[0], v[1]};
         }
-        *reinterpret_cast<double2 *>(M + (size_t)i * ld + j) = double2{v[0], v[1]};
     }
 }
 
@@ -349,18 +378,22 @@ void launch_gate(const uint8_t *A, int n, double gamma_arg, int32_t *outdeg, int
                  hipStream_t s) {
     hipLaunchKernelGGL(k_zero_i32, dim3((n + 1 + 255) / 256), dim3(256), 0, s, outdeg, n);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, bad, 1);
-    const int rows = 256;
-    hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256, (n + rows - 1) / rows), dim3(256), 0, s, A, n, rows,
-                       outdeg, bad);
+    if (n % 16 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0) {
+        const int rows = 64;
+        hipLaunchKernelGGL(k_colsum16, dim3((n / 16 + 255) / 256, (n + rows - 1) / rows), dim3(256), 0, s, A, n,
+                           rows, outdeg, bad);
+    } else {
+        const int rows = 256;
+        hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256, (n + rows - 1) / rows), dim3(256), 0, s, A, n, rows,
+                           outdeg, bad);
+    }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, outdeg, bad, n, gamma_arg, info);
 }
 
 void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
                    int32_t *bad, rdist_info *info, hipStream_t s) {
     launch_gate(A, n, gamma_arg, outdeg, bad, info, s);
-    const size_t pairs = (size_t)np * np / 2;
-    const int blocks = (int)std::min<size_t>((pairs + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_build_m, dim3(blocks), dim3(256), 0, s, A, n, np, ld, M, info);
+    hipLaunchKernelGGL(k_build_m, dim3(std::min(np, 8192)), dim3(256), 0, s, A, n, np, ld, M, info);
 }
 
 void launch_fill_sentinel(int16_t *D, int n, const rdist_info *info, hipStream_t s) {

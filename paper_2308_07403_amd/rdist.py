@@ -46,6 +46,10 @@ RDIST_THREADSAFE = 0x1
  RDIST_K_BATCHED, RDIST_K_NEXTHOP, RDIST_K_CERTIFY, RDIST_K_UPDATE_EDGE, RDIST_K_MIXED_GEMM, RDIST_K_REFINE,
  RDIST_K_COUNT) = range(13)
 
+def RDIST_TIMING_CLASS(k: int) -> int:
+    return 2 << k
+
+
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_ADJ", 3: "E_NOT_DD", 4: "E_NOMEM", 5: "E_AGAIN",
                 6: "E_HIP", 7: "E_STATE"}
 
@@ -337,8 +341,10 @@ class Context:
         return D
 
     # ---- timing ----
-    def set_timing(self, on: bool):
-        _check(rdist_set_timing(self.handle, 1 if on else 0), "rdist_set_timing")
+    def set_timing(self, on: bool, classes=None):
+        """Event timing of every kernel class, or of the RDIST_K_* classes listed."""
+        mask = (1 if on else 0) if classes is None else sum(RDIST_TIMING_CLASS(k) for k in classes)
+        _check(rdist_set_timing(self.handle, mask), "rdist_set_timing")
 
     def kernel_stats(self, which: int) -> dict:
         s = rdist_kernel_stats()

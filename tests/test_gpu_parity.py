@@ -740,6 +740,21 @@ def test_argument_errors(ctx):
     assert R.rdist_solve(ctx.handle, A.data_ptr(), 64, 0.1, 0x8000, D.data_ptr(), None, None, s) == R.RDIST_E_ARG
 
 
+def test_timing_mask(ctx):
+    """rdist_set_timing with a class mask times only those classes; 1 times all; negative is refused."""
+    A = dev(gg.erdos_renyi(1500, 0.01, gg.rng_for("parity", 9500)))
+    ctx.set_timing(True, classes=[R.RDIST_K_UPDATE])
+    ctx.solve(A, -0.5)
+    assert ctx.kernel_stats(R.RDIST_K_UPDATE)["launches"] > 0
+    assert ctx.kernel_stats(R.RDIST_K_PANEL)["launches"] == 0
+    ctx.set_timing(True)
+    ctx.solve(A, -0.5)
+    assert ctx.kernel_stats(R.RDIST_K_PANEL)["launches"] > 0
+    assert ctx.kernel_stats(R.RDIST_K_UPDATE)["launches"] > 0
+    ctx.set_timing(False)
+    assert R.rdist_set_timing(ctx.handle, -1) == R.RDIST_E_ARG
+
+
 def test_budget_refusal():
     c = R.Context(0, hbm_budget=1 << 20)
     A = dev(gg.erdos_renyi(1024, 0.01, gg.rng_for("parity", 7000)))
