@@ -178,21 +178,23 @@ def bench_c2(args, torch, R, gg):
     ctx.set_timing(False)
     # throughput with three independent solves in flight on three streams
     # (each stream has its own workspace); reported beside the value
-    streams = [torch.cuda.Stream() for _ in range(3)]
-    Dc = [torch.empty((n, n), dtype=torch.int16, device="cuda") for _ in range(3)]
-    infc = R.PinnedInfo(3)
-    for k in range(3):
-        ctx.solve_async(A, -0.5, fl, Dc[k], info=infc, info_index=k, stream=streams[k])
-    torch.cuda.synchronize()
-    nconc = max(6, 3 * (args.steps // 3))
-    t1 = time.perf_counter()
-    for k in range(nconc):
-        ctx.solve_async(A, -0.5, fl, Dc[k % 3], info=infc, info_index=k % 3, stream=streams[k % 3])
-    torch.cuda.synchronize()
-    conc_s = (time.perf_counter() - t1) / nconc
-    conc = {"streams": 3, "solves": nconc, "graphs_per_s": 1.0 / conc_s,
-            "eff_tflops": 2.0 * n ** 3 / conc_s / 1e12,
-            "d_equal_single": all(bool(torch.equal(Dc[k], D)) for k in range(3))}
+    conc = None
+    streams = [torch.cuda.Stream() for _ in range(3)] if not args.no_concurrent else []
+    if streams:
+        Dc = [torch.empty((n, n), dtype=torch.int16, device="cuda") for _ in range(3)]
+        infc = R.PinnedInfo(3)
+        for k in range(3):
+            ctx.solve_async(A, -0.5, fl, Dc[k], info=infc, info_index=k, stream=streams[k])
+        torch.cuda.synchronize()
+        nconc = max(6, 3 * (args.steps // 3))
+        t1 = time.perf_counter()
+        for k in range(nconc):
+            ctx.solve_async(A, -0.5, fl, Dc[k % 3], info=infc, info_index=k % 3, stream=streams[k % 3])
+        torch.cuda.synchronize()
+        conc_s = (time.perf_counter() - t1) / nconc
+        conc = {"streams": 3, "solves": nconc, "graphs_per_s": 1.0 / conc_s,
+                "eff_tflops": 2.0 * n ** 3 / conc_s / 1e12,
+                "d_equal_single": all(bool(torch.equal(Dc[k], D)) for k in range(3))}
     st = info.get(0).as_dict()
     # next-hop on a kept solve (not part of the step)
     _, g = ctx.solve_async(A, -0.5, fl, D, keep=True, info=info, stream=stream)
@@ -570,6 +572,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="C2: skip the three-stream throughput (profiling runs, one solve at a time)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--block", type=int, default=0, choices=[0, 128, 256],
                     help="force the blocked plan's block width (0: the engine's choice)")
