@@ -74,6 +74,18 @@ def erdos_renyi(n: int, p: float, rng: np.random.Generator, chunk: int = 1024) -
     return A
 
 
+def weighted(A: np.ndarray, rng: np.random.Generator, w_lo: int = 1, w_hi: int = 100) -> np.ndarray:
+    """Integer weights on the edges of A (W[i, j] = weight of edge j -> i, 0 = no
+    edge), log-uniform in [w_lo, w_hi] (w_hi <= 255, uint8)."""
+    assert 1 <= w_lo <= w_hi <= 255
+    W = np.zeros_like(A)
+    e = A != 0
+    k = int(e.sum())
+    w = np.exp(rng.uniform(np.log(w_lo), np.log(w_hi + 1.0), size=k)).astype(np.int64)
+    W[e] = np.clip(w, w_lo, w_hi).astype(np.uint8)
+    return W
+
+
 def induced_subgraph(A: np.ndarray, nodes) -> np.ndarray:
     """Subgraph induced by ``nodes`` (order kept), same convention."""
     nodes = np.asarray(nodes, dtype=np.int64)
@@ -199,6 +211,26 @@ def directed_path(n: int) -> np.ndarray:
     """0 -> 1 -> ... -> n-1."""
     i = np.arange(n - 1)
     return from_edges(n, i, i + 1)
+
+
+def weighted_path(weights) -> np.ndarray:
+    """0 -> 1 -> ... -> n-1 with the given edge weights (weights[k] on k -> k+1)."""
+    w = np.asarray(weights, dtype=np.uint8)
+    n = w.size + 1
+    W = _empty(n)
+    i = np.arange(n - 1)
+    W[i + 1, i] = w
+    return W
+
+
+def weighted_cycle(weights) -> np.ndarray:
+    """0 -> 1 -> ... -> n-1 -> 0 with weights[k] on k -> (k+1) mod n."""
+    w = np.asarray(weights, dtype=np.uint8)
+    n = w.size
+    W = _empty(n)
+    i = np.arange(n)
+    W[(i + 1) % n, i] = w
+    return W
 
 
 def directed_cycle(n: int) -> np.ndarray:

@@ -62,6 +62,11 @@ def lib():
         L.orc_readout.argtypes = [P, i32, f64, f64, f64, P, P]
         L.orc_solve.argtypes = [P, i32, f64, f64, f64, P, P, P, P, P, P]
         L.orc_solve.restype = i32
+        L.orc_prepare_weighted.argtypes = [P, i32, f64, P, P, P]
+        L.orc_prepare_weighted.restype = i32
+        L.orc_build_m_weighted.argtypes = [P, i32, f64, P]
+        L.orc_solve_weighted.argtypes = [P, i32, f64, f64, f64, P, P, P, P, P, P]
+        L.orc_solve_weighted.restype = i32
         L.orc_next_hop.argtypes = [P, P, i32, i32, i32]
         L.orc_next_hop.restype = i32
         L.orc_path.argtypes = [P, P, i32, i32, i32, i32, P]
@@ -186,6 +191,43 @@ def solve(A, gamma_arg: float, keep_y: bool = True, eta: float = ETA, beta: floa
     sw = np.zeros(1, dtype=np.int64)
     st = lib().orc_solve(_p(A), n, float(gamma_arg), float(eta), float(beta), _p(D),
                          _p(Y) if keep_y else None, _p(delta), _p(gamma), _p(c), _p(sw))
+    return Solution(int(st), int(delta[0]), float(gamma[0]), D, Y if st == OK else None,
+                    *[int(x) for x in c], int(sw[0]))
+
+
+def prepare_weighted(W, gamma_arg: float) -> Prep:
+    """Sec. 3.2 weights (W[i, j] = weight of edge j -> i, 0 = no edge): no
+    self-loops, out-edge counts, Delta, gain and the gate gamma * Delta < 1."""
+    W = _adj(W)
+    n = W.shape[0]
+    outdeg = np.zeros(max(n, 1), dtype=np.int32)
+    delta = np.zeros(1, dtype=np.int32)
+    gamma = np.zeros(1, dtype=np.float64)
+    st = lib().orc_prepare_weighted(_p(W), n, float(gamma_arg), _p(outdeg), _p(delta), _p(gamma))
+    return Prep(int(st), int(delta[0]), float(gamma[0]), outdeg[:n])
+
+
+def build_m_weighted(W, gamma: float) -> np.ndarray:
+    """M = I - gamma^W elementwise (0 where there is no edge)."""
+    W = _adj(W)
+    n = W.shape[0]
+    M = np.empty((n, n), dtype=np.float64)
+    lib().orc_build_m_weighted(_p(W), n, float(gamma), _p(M))
+    return M
+
+
+def solve_weighted(W, gamma_arg: float, keep_y: bool = True, eta: float = ETA, beta: float = BETA) -> Solution:
+    """Weighted pipeline (Sec. 3.2): gate, M = I - gamma^W, Gauss-Jordan inverse, readout."""
+    W = _adj(W)
+    n = W.shape[0]
+    D = np.empty((n, n), dtype=np.int16)
+    Y = np.empty((n, n), dtype=np.float64) if keep_y else None
+    delta = np.zeros(1, dtype=np.int32)
+    gamma = np.zeros(1, dtype=np.float64)
+    c = np.zeros(5, dtype=np.int64)
+    sw = np.zeros(1, dtype=np.int64)
+    st = lib().orc_solve_weighted(_p(W), n, float(gamma_arg), float(eta), float(beta), _p(D),
+                                  _p(Y) if keep_y else None, _p(delta), _p(gamma), _p(c), _p(sw))
     return Solution(int(st), int(delta[0]), float(gamma[0]), D, Y if st == OK else None,
                     *[int(x) for x in c], int(sw[0]))
 

@@ -103,6 +103,53 @@ void orc_build_m(const uint8_t *A, int n, double gamma, double *M) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Positive integer weights (Sec. 3.2, extension to weighted graphs).        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * W[i*n + j] = weight of the edge j -> i (1 .. 255), 0 = no edge (weight
+ * infinity, gamma^inf = 0).  Validation: no self-loops.  The out-degree of j
+ * counts its out-edges; Delta, the gain and the gate are those of
+ * orc_prepare.  The gate gamma * Delta < 1 bounds every column sum of
+ * X = gamma^W (each entry is at most gamma), so I - X is column-wise strictly
+ * diagonally dominant as in the unweighted case.
+ */
+int orc_prepare_weighted(const uint8_t *W, int n, double gamma_arg, int32_t *outdeg,
+                         int32_t *delta_out, double *gamma_out) {
+    if (n < 1 || !(gamma_arg == gamma_arg) || gamma_arg == 0.0) return ORC_E_ARG;
+    for (int i = 0; i < n; ++i)
+        if (W[(size_t)i * n + i] != 0) return ORC_E_ADJ;
+    int32_t delta = 0;
+    for (int j = 0; j < n; ++j) {
+        int32_t s = 0;
+        for (int i = 0; i < n; ++i) s += W[(size_t)i * n + j] != 0;
+        if (outdeg) outdeg[j] = s;
+        if (s > delta) delta = s;
+    }
+    double gamma;
+    if (gamma_arg > 0.0) {
+        gamma = gamma_arg;
+    } else {
+        double c = -gamma_arg;
+        gamma = delta > 0 ? c / (double)delta : c;
+    }
+    if (delta_out) *delta_out = delta;
+    if (gamma_out) *gamma_out = gamma;
+    if (!(gamma > 0.0) || !(gamma < 1.0)) return ORC_E_ARG;
+    if (!(gamma * (double)delta < 1.0)) return ORC_E_NOT_DD;
+    return ORC_OK;
+}
+
+/* M = I - X with X_ij = gamma^W_ij (Eq. Y-taylor-series-integer), 0 where W_ij = 0. */
+void orc_build_m_weighted(const uint8_t *W, int n, double gamma, double *M) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const uint8_t w = W[(size_t)i * n + j];
+            M[(size_t)i * n + j] = (i == j ? 1.0 : 0.0) - (w ? pow(gamma, (double)w) : 0.0);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Inversion: unblocked in-place Gauss-Jordan, natural order, no pivoting.   */
 /* ------------------------------------------------------------------------ */
 
@@ -215,6 +262,35 @@ int orc_solve(const uint8_t *A, int n, double gamma_arg, double eta, double beta
     return st;
 }
 
+/*
+ * orc_solve for a weighted graph (Sec. 3.2): gate of orc_prepare_weighted,
+ * Y = (I - gamma^W)^{-1}, the same readout (Eq. distance-function-integer).
+ */
+int orc_solve_weighted(const uint8_t *W, int n, double gamma_arg, double eta, double beta,
+                       int16_t *D, double *Y, int32_t *delta_out, double *gamma_out,
+                       int64_t *counts, int64_t *would_swap) {
+    int32_t delta = 0;
+    double gamma = 0.0;
+    int st = orc_prepare_weighted(W, n, gamma_arg, NULL, &delta, &gamma);
+    if (delta_out) *delta_out = delta;
+    if (gamma_out) *gamma_out = gamma;
+    if (st != ORC_OK) {
+        if (n > 0 && D)
+            for (size_t idx = 0; idx < (size_t)n * n; ++idx) D[idx] = ORC_UNREACHABLE;
+        return st;
+    }
+    double *M = Y;
+    if (!M) {
+        M = (double *)malloc(sizeof(double) * (size_t)n * n);
+        if (!M) return ORC_E_NOMEM;
+    }
+    orc_build_m_weighted(W, n, gamma, M);
+    st = orc_gj_invert(M, n, would_swap);
+    if (st == ORC_OK) orc_readout(M, n, gamma, eta, beta, D, counts);
+    if (M != Y) free(M);
+    return st;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Local pursuit (Eq. descent; Theorem 4 and its corollary).                 */
 /* ------------------------------------------------------------------------ */
@@ -226,7 +302,7 @@ int orc_next_hop(const uint8_t *A, const double *Y, int n, int cur, int goal) {
     int best = -1;
     double bestv = 0.0;
     for (int j = 0; j < n; ++j) {
-        if (A[(size_t)j * n + cur] != 1) continue;   /* successor j: edge cur -> j */
+        if (A[(size_t)j * n + cur] == 0) continue;   /* successor j: edge cur -> j (any weight) */
         if (yg[j] > bestv) { bestv = yg[j]; best = j; }
     }
     return best;

@@ -462,3 +462,130 @@ def test_readout_entries_is_the_matrix_readout():
     full = oracle.readout(Y, g).D
     assert np.array_equal(oracle.readout_entries(Y[:, 4], g), full[:, 4])
     assert np.array_equal(oracle.readout_entries(Y[10], g), full[10])
+
+
+# ---------------------------------------------------------------------------
+# Positive integer weights (Sec. 3.2): X = gamma^W, Y = (I - X)^{-1},
+# R = log_gamma Y -> weighted distance as gamma -> 0 (Eq. distance-function-integer)
+# ---------------------------------------------------------------------------
+
+def test_weighted_path_closed_form():
+    """Weighted directed path: Y[i, j] = gamma^(w_j + ... + w_{i-1}) for i >= j
+    (the one walk from j to i), 0 above the diagonal; D is that weight sum."""
+    rng = np.random.default_rng(11)
+    w = rng.integers(1, 10, size=11)
+    W = gg.weighted_path(w)
+    g = Fraction(1, 20)
+    sol = oracle.solve_weighted(W, float(g))
+    assert sol.status == oracle.OK and sol.delta == 1
+    n = W.shape[0]
+    for i in range(n):
+        for j in range(n):
+            if i < j:
+                assert sol.Y[i, j] == 0.0 and sol.D[i, j] == oracle.UNREACHABLE
+            else:
+                s = int(w[j:i].sum())
+                exact = float(g ** s)
+                # a product of i - j rounded factors gamma^w
+                assert abs(sol.Y[i, j] - exact) <= 4 * (i - j + 2) * EPS * exact
+                assert sol.D[i, j] == s
+
+
+def test_weighted_cycle_closed_form():
+    """Weighted directed cycle of total weight L: Y[i, j] = gamma^d / (1 - gamma^L)
+    with d the weight of the arc from j to i; D = d."""
+    w = np.array([3, 1, 4, 1, 5, 9, 2, 6])
+    W = gg.weighted_cycle(w)
+    n = w.size
+    g = Fraction(1, 7)
+    L = int(w.sum())
+    sol = oracle.solve_weighted(W, float(g))
+    assert sol.status == oracle.OK
+    for i in range(n):
+        for j in range(n):
+            d = int(sum(w[(j + k) % n] for k in range((i - j) % n)))
+            exact = float(g ** d / (1 - g ** L))
+            assert abs(sol.Y[i, j] - exact) <= 4 * (n + 4) * EPS * exact
+            assert sol.D[i, j] == d
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weighted_small_gamma_is_dijkstra(seed):
+    """At small gamma the weighted R-distance rounds to the weighted shortest
+    distance (Eq. distance-function-integer): against scipy's Dijkstra."""
+    rng = np.random.default_rng(200 + seed)
+    n = int(rng.integers(5, 13))
+    A = gg.erdos_renyi(n, 0.3, rng)
+    W = gg.weighted(A, rng, 1, 6)
+    sol = oracle.solve_weighted(W, 1e-7)
+    assert sol.status == oracle.OK
+    d = csg.dijkstra(np.ascontiguousarray(W.T, dtype=np.float64), directed=True).T   # [i, j]: from j to i
+    reach = ~np.isinf(d)
+    assert np.array_equal(sol.D[reach], d[reach].astype(np.int64))
+    assert np.all(sol.D[~reach] == oracle.UNREACHABLE)
+    assert np.array_equal(sol.Y == 0.0, ~reach)
+
+
+def test_weighted_unit_weights_are_the_unweighted_method():
+    """All weights 1: X = gamma A, so the weighted pipeline gives the unweighted
+    result bit for bit (Sec. 3.2, the special case)."""
+    rng = np.random.default_rng(31)
+    A = gg.erdos_renyi(60, 0.08, rng)
+    a = oracle.solve(A, -0.5)
+    b = oracle.solve_weighted(A, -0.5)
+    assert a.status == b.status == oracle.OK and a.gamma == b.gamma and a.delta == b.delta
+    assert np.array_equal(a.Y, b.Y) and np.array_equal(a.D, b.D)
+
+
+def test_weighted_inverse_against_lapack():
+    """The Gauss-Jordan inverse of I - gamma^W against LAPACK (numpy) on a
+    weighted graph with weights up to 100."""
+    rng = np.random.default_rng(41)
+    W = gg.weighted(gg.erdos_renyi(120, 0.1, rng), rng, 1, 100)
+    sol = oracle.solve_weighted(W, -0.5)
+    assert sol.status == oracle.OK
+    M = oracle.build_m_weighted(W, sol.gamma)
+    ref = np.linalg.inv(M)
+    nz = np.abs(ref) > 1e-300
+    assert np.max(np.abs(sol.Y[nz] - ref[nz]) / np.abs(ref[nz])) < 1e-11
+    # structure of M: identity diagonal, -gamma^w on the edges, 0 elsewhere
+    e = W != 0
+    assert np.all(np.diag(M) == 1.0) and np.all(M[~e & ~np.eye(120, dtype=bool)] == 0.0)
+    assert np.all(M[e] < 0.0) and np.all(-M[e] <= sol.gamma)
+
+
+def test_weighted_gate_and_validation():
+    """Delta counts out-edges (not weights); AUTO gamma = c / Delta; the gate
+    gamma * Delta < 1; a self-loop of any weight is refused; weight 255 allowed."""
+    W = gg.weighted_path([255, 7, 1])
+    W[3, 0] = 2                                  # 0 -> 3: node 0 has two out-edges
+    p = oracle.prepare_weighted(W, -0.5)
+    assert p.status == oracle.OK and p.delta == 2 and p.gamma == 0.25
+    assert list(p.outdeg) == [2, 1, 1, 0]
+    assert oracle.prepare_weighted(W, 0.5).status == oracle.E_NOT_DD
+    loop = W.copy()
+    loop[1, 1] = 3
+    assert oracle.prepare_weighted(loop, -0.5).status == oracle.E_ADJ
+    assert oracle.prepare_weighted(W, 1.0).status == oracle.E_ARG
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_weighted_greedy_reaches_goal(seed):
+    """Theorem 4's argument carries over (Y_gi = sum over successors j of
+    Y_gj gamma^W_ji, and those weights sum to less than 1 under the gate):
+    greedy ascent reaches the goal with Y strictly increasing."""
+    rng = np.random.default_rng(300 + seed)
+    n = 40
+    A = gg.erdos_renyi(n, 0.1, rng)
+    W = gg.weighted(A, rng, 1, 20)
+    sol = oracle.solve_weighted(W, -0.5)
+    assert sol.status == oracle.OK
+    for cur, goal in rng.integers(0, n, size=(30, 2)):
+        if sol.Y[goal, cur] == 0.0:
+            continue
+        out = oracle.path(W, sol.Y, int(cur), int(goal), n)
+        hops = [int(x) for x in out if x >= 0]
+        assert hops[-1] == goal
+        ys = [sol.Y[goal, h] for h in hops]
+        assert all(b > a for a, b in zip(ys, ys[1:]))
+        assert all(W[b, a] != 0 for a, b in zip(hops, hops[1:]))
