@@ -440,6 +440,84 @@ def bench_c5(args, torch, R, gg):
     }
 
 
+def bench_f1(args, torch, R, gg):
+    """Positive integer weights (Sec. 3.2): a weighted graph of the C2 shape,
+    ER(8192, 0.02) with weights log-uniform in [1, 100] and gamma = 0.5/Delta,
+    solved with RDIST_WEIGHTED (value, roofline of the same REST update); and
+    the paper's weighted-graph experiment size, n = 1000, p = 0.5, weights
+    log-uniform in [1, 100], gamma = 1e-7, beside the oracle on the host."""
+    import oracle
+    n = 8192
+    rng = gg.rng_for("f1", 0)
+    W_np = gg.weighted(gg.erdos_renyi(n, 0.02, rng), rng, 1, 100)
+    W = torch.from_numpy(W_np).cuda()
+    D = torch.empty((n, n), dtype=torch.int16, device="cuda")
+    ctx = R.Context(0)
+    stream = torch.cuda.current_stream()
+    info = R.PinnedInfo(1)
+    fl = R.RDIST_WEIGHTED
+    for _ in range(args.warmup):
+        ctx.solve_async(W, -0.5, fl, D, info=info, stream=stream)
+    torch.cuda.synchronize()
+    assert info.get(0).status == 0, info.get(0).as_dict()
+    ctx.set_timing(True, classes=[R.RDIST_K_UPDATE])
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.solve_async(W, -0.5, fl, D, info=info, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    upd = ctx.kernel_stats(R.RDIST_K_UPDATE)
+    ctx.set_timing(False)
+    st = info.get(0).as_dict()
+    # the paper's weighted experiment size
+    n2 = 1000
+    rng2 = gg.rng_for("f1", 1)
+    W2_np = gg.weighted(gg.erdos_renyi(n2, 0.5, rng2), rng2, 1, 100)
+    W2 = torch.from_numpy(W2_np).cuda()
+    D2 = torch.empty((n2, n2), dtype=torch.int16, device="cuda")
+    for _ in range(3):
+        ctx.solve_async(W2, 1e-7, fl, D2, info=info, stream=stream)
+    torch.cuda.synchronize()
+    reps = 50
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ctx.solve_async(W2, 1e-7, fl, D2, info=info, stream=stream)
+    torch.cuda.synchronize()
+    ms2 = (time.perf_counter() - t1) * 1e3 / reps
+    ctx.close()
+    ms = wall * 1e3 / args.steps
+    per_launch_flops = upd["flops"] / max(upd["launches"], 1)
+    avg_ms = upd["total_ms"] / max(upd["launches"], 1)
+    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
+    sha = source_sha(UPDATE_SOURCES)
+    out = {
+        "metric": "weighted APSP (integer weights) graphs/s at n=8192",
+        "value": args.steps / wall, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "f1: directed ER(n=8192, p=0.02), integer weights log-uniform in [1, 100], "
+                               "gamma=0.5/Delta, FP64 blocked Gauss-Jordan of I - gamma^W + fused readout",
+                   "n": n, "gamma": st["gamma"], "delta": st["delta"]},
+        "eff_tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
+        "roofline": {"bound": "mfma", "kernel": "k_update<kRest> (as C2)", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": read_traffic("k_update_c2_n8192_pmc.md", sha), "avg_launch_ms": avg_ms,
+                     "launches": upd["launches"], "flops_per_launch": per_launch_flops, "source_sha": sha},
+        "paper_size": {"n": n2, "p": 0.5, "gamma": 1e-7, "ms_per_solve": ms2, "graphs_per_s": 1e3 / ms2},
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle, n = 1000 weighted solve)")
+        t2 = time.perf_counter()
+        sol = oracle.solve_weighted(W2_np, 1e-7, keep_y=False)
+        tc = time.perf_counter() - t2
+        assert np.array_equal(sol.D, D2.cpu().numpy()), "paper-size weighted D differs from the oracle"
+        out["cpu_baseline"] = {"value": 1.0 / tc, "unit": "graphs/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"one full n = {n2} weighted solve ({tc:.3f} s)"}
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
 def bench_c1(args, torch, R, gg):
     import oracle
     As = [torch.from_numpy(gg.c1_graph(s)).cuda() for s in range(100)]
@@ -570,7 +648,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "f1"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-concurrent", action="store_true",
                     help="C2: skip the three-stream throughput (profiling runs, one solve at a time)")
@@ -613,7 +691,8 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
         del src, dst, scrub
-    out = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args, torch, R, gg)
+    out = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
+           "f1": bench_f1}[args.workload](args, torch, R, gg)
     print(json.dumps(out), flush=True)
 
 

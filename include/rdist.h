@@ -82,6 +82,7 @@ typedef enum rdist_status {
 #define RDIST_BLOCK_128 0x800u      /* blocked plan: force block width b = 128 */
 #define RDIST_BLOCK_256 0x1000u     /* blocked plan: force block width b = 256 (default for n > 1024) */
 #define RDIST_NO_GRAPH 0x2000u      /* rdist_solve_batched: launch eagerly, no HIP graph capture or replay */
+#define RDIST_WEIGHTED 0x4000u      /* rdist_solve: A_dev holds positive integer weights (Sec. 3.2) */
 
 /* ---- flags for rdist_create ---- */
 #define RDIST_THREADSAFE 0x1u
@@ -119,6 +120,15 @@ void rdist_destroy(rdist_ctx ctx);
  *   n     : 1 <= n <= 65536.
  *   gamma : explicit (0,1) or AUTO (< 0, |gamma| in (0, 1]).
  *   flags : RDIST_F64 or RDIST_MIXED_F32, optionally | RDIST_KEEP_Y and a plan flag.
+ *           With RDIST_WEIGHTED (Sec. 3.2, extension to weighted graphs),
+ *           A_dev[i*n + j] is the positive integer weight W_ij of the edge
+ *           j -> i (1 .. 255; 0: no edge, gamma^inf = 0), Y = (I - gamma^W)^{-1}
+ *           elementwise-powered, and D is the weighted distance (Eq.
+ *           distance-function-integer, same readout).  Delta counts out-edges
+ *           and the gate is gamma * Delta < 1 as for 0/1 graphs (every column
+ *           sum of gamma^W is then below 1); self-loops are refused
+ *           (RDIST_E_ADJ).  Always the blocked plan; not with
+ *           RDIST_MIXED_F32 or RDIST_PLAN_SMALL, nor in rdist_solve_batched.
  *   D_dev : n x n int16 output, written by the device.
  *   keep  : with RDIST_KEEP_Y, receives a graph handle owning Y and the
  *           out-neighbour lists (release with rdist_graph_release); else NULL.

@@ -580,6 +580,7 @@ extern "C" rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const in
     if ((st = check_flags(flags))) return st;
     if (flags & (RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED)) return fail(RDIST_E_ARG, "plan flags are per solve");
     if (flags & RDIST_MIXED_F32) return fail(RDIST_E_ARG, "RDIST_MIXED_F32 is a single-graph plan");
+    if (flags & RDIST_WEIGHTED) return fail(RDIST_E_ARG, "RDIST_WEIGHTED is a single-graph plan");
     if (count > (1 << 20)) return fail(RDIST_E_ARG, "count too large (at most 2^20 graphs per call)");
     for (int g = 0; g < count; ++g) {
         if (n[g] < 1 || n[g] > 65536) return fail(RDIST_E_ARG, "n out of range");

@@ -197,12 +197,15 @@ void release_graph_locked(rdist_graph g) {
 
 rdist_status check_flags(uint32_t flags) {
     const uint32_t known = RDIST_MIXED_F32 | RDIST_KEEP_Y | RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED |
-                           RDIST_UNFUSED_EPILOGUE | RDIST_BLOCK_128 | RDIST_BLOCK_256 | RDIST_NO_GRAPH;
+                           RDIST_UNFUSED_EPILOGUE | RDIST_BLOCK_128 | RDIST_BLOCK_256 | RDIST_NO_GRAPH |
+                           RDIST_WEIGHTED;
     if (flags & ~known) return fail(RDIST_E_ARG, "unknown flag bits");
     if ((flags & RDIST_BLOCK_128) && (flags & RDIST_BLOCK_256)) return fail(RDIST_E_ARG, "two block widths");
     if ((flags & RDIST_PLAN_SMALL) && (flags & RDIST_PLAN_BLOCKED)) return fail(RDIST_E_ARG, "two plan flags");
     if ((flags & RDIST_MIXED_F32) && (flags & (RDIST_KEEP_Y | RDIST_PLAN_SMALL | RDIST_PLAN_BLOCKED)))
         return fail(RDIST_E_ARG, "RDIST_MIXED_F32 takes no KEEP_Y or plan flag");
+    if ((flags & RDIST_WEIGHTED) && (flags & (RDIST_MIXED_F32 | RDIST_PLAN_SMALL)))
+        return fail(RDIST_E_ARG, "RDIST_WEIGHTED runs on the FP64 blocked plan only");
     return RDIST_OK;
 }
 
@@ -286,7 +289,7 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
     const bool fused = !(flags & RDIST_UNFUSED_EPILOGUE);
     {
         Timer t(c, s, RDIST_K_INGEST, 0.0, (double)n * n + 8.0 * np * np);
-        rd::launch_ingest(A, n, np, ld, gamma, M, w.outdeg(), w.bad(), dinfo, s);
+        rd::launch_ingest(A, n, np, ld, gamma, M, w.outdeg(), w.bad(), dinfo, s, (flags & RDIST_WEIGHTED) != 0);
     }
     RD_HIP(hipGetLastError());
     enqueue_inverse(c, w, ld, 0, m, 0, dinfo, s);
@@ -480,7 +483,7 @@ rdist_status rdist_solve(rdist_ctx c, const uint8_t *A_dev, int32_t n, double ga
     RD_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     if (flags & RDIST_MIXED_F32) return solve_mixed(c, A_dev, n, gamma, flags, D_dev, info, s);
-    const bool small = !(flags & RDIST_PLAN_BLOCKED) && n <= 128;
+    const bool small = !(flags & (RDIST_PLAN_BLOCKED | RDIST_WEIGHTED)) && n <= 128;
     if (small) return solve_small(c, A_dev, n, gamma, flags, D_dev, keep, info, s);
     return solve_blocked(c, A_dev, n, gamma, flags, D_dev, keep, info, s);
 }

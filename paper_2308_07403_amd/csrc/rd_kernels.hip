@@ -40,7 +40,7 @@ __global__ void k_zero_i32(int32_t *p, int count) {
 // with 16 | n and A 16-byte aligned, thread t of workgroup (x, y) reads 16
 // bytes (columns 16 (256 x + t) ..) of each row of block y.
 __global__ __launch_bounds__(256) void k_colsum16(const uint8_t *__restrict__ A, int n, int rows_per_block,
-                                                  int32_t *outdeg, int32_t *bad) {
+                                                  int32_t *outdeg, int32_t *bad, int weighted) {
     const int j0 = (blockIdx.x * 256 + threadIdx.x) * 16;
     if (j0 >= n) return;
     const int i0 = blockIdx.y * rows_per_block;
@@ -53,8 +53,8 @@ __global__ __launch_bounds__(256) void k_colsum16(const uint8_t *__restrict__ A,
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int a = (int)((w[q >> 2] >> (8 * (q & 3))) & 0xFFu);
-            s[q] += a;
-            b |= (a > 1) | ((i == j0 + q) & (a != 0));
+            s[q] += a != 0;
+            b |= (!weighted & (a > 1)) | ((i == j0 + q) & (a != 0));
         }
     }
 #pragma unroll
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_colsum16(const uint8_t *__restrict__ A,
 }
 
 __global__ __launch_bounds__(256) void k_colsum(const uint8_t *__restrict__ A, int n, int rows_per_block,
-                                                int32_t *outdeg, int32_t *bad) {
+                                                int32_t *outdeg, int32_t *bad, int weighted) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     const int i0 = blockIdx.y * rows_per_block;
@@ -72,8 +72,8 @@ __global__ __launch_bounds__(256) void k_colsum(const uint8_t *__restrict__ A, i
     int s = 0, b = 0;
     for (int i = i0; i < i1; ++i) {
         const int a = A[(size_t)i * n + j];
-        s += a;
-        b |= (a > 1) | ((i == j) & (a != 0));
+        s += a != 0;
+        b |= (!weighted & (a > 1)) | ((i == j) & (a != 0));
     }
     if (s) atomicAdd(&outdeg[j], s);
     if (b) atomicOr(bad, 1);
@@ -109,8 +109,14 @@ __global__ __launch_bounds__(1024) void k_finalize(const int32_t *outdeg, const 
 // a workgroup per row (grid-stride over rows), two entries per thread and
 // 16-byte stores.
 __global__ __launch_bounds__(256) void k_build_m(const uint8_t *__restrict__ A, int n, int np, int ld,
-                                                 double *__restrict__ M, const rdist_info *info) {
+                                                 double *__restrict__ M, const rdist_info *info, int weighted) {
     const double gamma = info->gamma;
+    // weighted (Sec. 3.2): entry -gamma^w for an edge of weight w, from a table
+    __shared__ double gpow[256];
+    if (weighted) {
+        gpow[threadIdx.x] = threadIdx.x ? pow(gamma, (double)threadIdx.x) : 0.0;
+        __syncthreads();
+    }
     for (int i = blockIdx.x; i < np; i += gridDim.x) {
         const uint8_t *__restrict__ ar = A + (size_t)i * n;
         double *__restrict__ mr = M + (size_t)i * ld;
@@ -120,7 +126,7 @@ __global__ __launch_bounds__(256) void k_build_m(const uint8_t *__restrict__ A, 
             for (int q = 0; q < 2; ++q) {
                 const int jj = j + q;
                 double x = (i == jj) ? 1.0 : 0.0;
-                if (i < n && jj < n) x -= gamma * (double)ar[jj];
+                if (i < n && jj < n) x -= weighted ? gpow[ar[jj]] : gamma * (double)ar[jj];
                 v[q] = x;
             }
             *reinterpret_cast<double2 *>(mr + j) = double2{v[0], v[1]};
@@ -375,25 +381,25 @@ __global__ __launch_bounds__(TY *TX) void k_small_one(SmallTask t) {
 // ---------------------------------------------------------------------------
 
 void launch_gate(const uint8_t *A, int n, double gamma_arg, int32_t *outdeg, int32_t *bad, rdist_info *info,
-                 hipStream_t s) {
+                 hipStream_t s, bool weighted) {
     hipLaunchKernelGGL(k_zero_i32, dim3((n + 1 + 255) / 256), dim3(256), 0, s, outdeg, n);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, bad, 1);
     if (n % 16 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0) {
         const int rows = 64;
         hipLaunchKernelGGL(k_colsum16, dim3((n / 16 + 255) / 256, (n + rows - 1) / rows), dim3(256), 0, s, A, n,
-                           rows, outdeg, bad);
+                           rows, outdeg, bad, (int)weighted);
     } else {
         const int rows = 256;
         hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256, (n + rows - 1) / rows), dim3(256), 0, s, A, n, rows,
-                           outdeg, bad);
+                           outdeg, bad, (int)weighted);
     }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, outdeg, bad, n, gamma_arg, info);
 }
 
 void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
-                   int32_t *bad, rdist_info *info, hipStream_t s) {
-    launch_gate(A, n, gamma_arg, outdeg, bad, info, s);
-    hipLaunchKernelGGL(k_build_m, dim3(std::min(np, 8192)), dim3(256), 0, s, A, n, np, ld, M, info);
+                   int32_t *bad, rdist_info *info, hipStream_t s, bool weighted) {
+    launch_gate(A, n, gamma_arg, outdeg, bad, info, s, weighted);
+    hipLaunchKernelGGL(k_build_m, dim3(std::min(np, 8192)), dim3(256), 0, s, A, n, np, ld, M, info, (int)weighted);
 }
 
 void launch_fill_sentinel(int16_t *D, int n, const rdist_info *info, hipStream_t s) {

@@ -61,10 +61,13 @@ constexpr int kLvShift = 10;   // unit = (graph << 10) | item, item < 1024 (nt^2
 enum LevelPhase { kLvBuild = 0, kLvPanel = 1, kLvRowcol = 2, kLvEdge = 3, kLvRest = 4, kLvColsum = 5 };
 
 // Out-degrees, validation and the gate: info (status, delta, gamma, zeroed counters).
+// weighted: A holds integer weights (0 = no edge); out-degrees count edges and
+// only self-loops are invalid.
 void launch_gate(const uint8_t *A, int n, double gamma_arg, int32_t *outdeg, int32_t *bad, rdist_info *info,
-                 hipStream_t s);
+                 hipStream_t s, bool weighted = false);
+// ... then M = I - gamma A (weighted: I - gamma^W elementwise).
 void launch_ingest(const uint8_t *A, int n, int np, int ld, double gamma_arg, double *M, int32_t *outdeg,
-                   int32_t *bad, rdist_info *info, hipStream_t s);
+                   int32_t *bad, rdist_info *info, hipStream_t s, bool weighted = false);
 void launch_fill_sentinel(int16_t *D, int n, const rdist_info *info, hipStream_t s);
 void launch_panel(const double *M, int ld, int K, double *Pt, double *V, int ldv, rdist_info *info, hipStream_t s);
 // Blocked Gauss-Jordan pieces (tiles are 128 x 128; a block is m tiles wide,

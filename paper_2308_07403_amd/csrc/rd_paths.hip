@@ -11,7 +11,7 @@
 namespace rd {
 
 // Successor bitmaps: bit b of word w in row i is set iff there is an edge
-// i -> 64w + b, i.e. A[(64w + b) * n + i] == 1.  Row i is nw = ceil(n/64)
+// i -> 64w + b, i.e. A[(64w + b) * n + i] != 0 (any weight).  Row i is nw = ceil(n/64)
 // 64-bit words; its size is known up front, so no host synchronisation is
 // needed to allocate it.  Thread i of the word-w pass reads column i of 64
 // rows (consecutive i read consecutive bytes of a row).
@@ -21,7 +21,7 @@ __device__ __forceinline__ void succ_word(const uint8_t *__restrict__ A, int n, 
     const int j0 = w * 64;
     const int j1 = min(n, j0 + 64);
     for (int j = j0; j < j1; ++j)
-        if (A[(size_t)j * n + i] == 1) word |= 1ull << (j - j0);
+        if (A[(size_t)j * n + i] != 0) word |= 1ull << (j - j0);
     bits[(size_t)i * nw + w] = word;
 }
 

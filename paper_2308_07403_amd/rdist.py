@@ -41,6 +41,7 @@ RDIST_UNFUSED_EPILOGUE = 0x400
 RDIST_BLOCK_128 = 0x800
 RDIST_BLOCK_256 = 0x1000
 RDIST_NO_GRAPH = 0x2000
+RDIST_WEIGHTED = 0x4000
 RDIST_THREADSAFE = 0x1
 (RDIST_K_UPDATE, RDIST_K_PANEL, RDIST_K_ROWCOL, RDIST_K_INGEST, RDIST_K_EPILOGUE, RDIST_K_SMALL,
  RDIST_K_BATCHED, RDIST_K_NEXTHOP, RDIST_K_CERTIFY, RDIST_K_UPDATE_EDGE, RDIST_K_MIXED_GEMM, RDIST_K_REFINE,

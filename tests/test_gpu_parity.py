@@ -253,6 +253,90 @@ def test_epilogue_near_integer_distances(ctx, gamma):
 
 
 # ---------------------------------------------------------------------------
+# Positive integer weights (Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,p,w_hi,gamma", [(40, 0.2, 5, -0.5), (129, 0.05, 100, -0.5), (300, 0.5, 100, 1e-7),
+                                            (700, 0.02, 255, -0.5), (1300, 0.01, 100, -0.5)])
+def test_weighted_against_oracle(ctx, n, p, w_hi, gamma):
+    """Weighted ER graphs (weights log-uniform in [1, w_hi], the dense p = 0.5
+    case at gamma = 1e-7 as in the paper's weighted experiment): D bit-exact,
+    Y within the tolerance, through the blocked plan at every size."""
+    rng = gg.rng_for("parity", 9600 + n)
+    W = gg.weighted(gg.erdos_renyi(n, p, rng), rng, 1, w_hi)
+    note(f"[parity] weighted n={n} p={p} w<={w_hi} gamma={gamma}")
+    sol = oracle.solve_weighted(W, gamma)
+    D, info, g = ctx.solve(dev(W), gamma, flags=R.RDIST_WEIGHTED, keep=True)
+    assert info["status"] == sol.status == 0
+    assert info["delta"] == sol.delta and info["gamma"] == sol.gamma
+    assert np.array_equal(D.cpu().numpy(), sol.D)
+    assert info["n_unreachable"] == sol.unreachable and info["n_saturated"] == sol.saturated
+    Yh = g.y().cpu().numpy()
+    g.release()
+    assert np.array_equal(Yh == 0.0, sol.Y == 0.0)
+    nz = sol.Y >= DBL_MIN
+    assert np.max(np.abs(Yh[nz] - sol.Y[nz]) / sol.Y[nz]) <= Y_TOL
+
+
+def test_weighted_unit_weights_equal_unweighted(ctx):
+    """All weights 1: the weighted solve is the unweighted one, bit for bit."""
+    A = dev(gg.erdos_renyi(900, 0.01, gg.rng_for("parity", 9700)))
+    D0, i0, g0 = ctx.solve(A, -0.5, flags=R.RDIST_PLAN_BLOCKED, keep=True)
+    D1, i1, g1 = ctx.solve(A, -0.5, flags=R.RDIST_WEIGHTED, keep=True)
+    assert i0["status"] == i1["status"] == 0 and i0["gamma"] == i1["gamma"]
+    assert torch.equal(D0, D1) and torch.equal(g0.y(), g1.y())
+    g0.release()
+    g1.release()
+
+
+def test_weighted_path_closed_form_large(ctx):
+    """Weighted directed path at n = 3000 (b = 256 blocks): Y[i, j] = gamma^(sum
+    of the weights from j to i), D that sum, checked on sampled columns."""
+    rng = gg.rng_for("parity", 9710)
+    w = rng.integers(1, 4, size=2999)
+    W = gg.weighted_path(w)
+    gamma = 0.9
+    D, info, g = ctx.solve(dev(W), gamma, flags=R.RDIST_WEIGHTED, keep=True)
+    assert info["status"] == 0
+    Y = g.y()
+    cs = np.concatenate([[0], np.cumsum(w)])
+    for j in (0, 1, 1500, 2998, 2999):
+        s = cs[j:] - cs[j]                        # weight from j to i = j ..
+        exact = gamma ** s.astype(np.float64)
+        y = Y[j:, j].cpu().numpy()
+        assert np.max(np.abs(y - exact) / exact) <= 1e-12, j
+        assert np.array_equal(D[j:, j].cpu().numpy(), s.astype(np.int64)), j
+        assert bool((Y[:j, j] == 0).all()) and bool((D[:j, j] == R.RDIST_UNREACHABLE).all())
+    del Y
+    g.release()
+
+
+def test_weighted_next_hop_and_refusals(ctx):
+    """Greedy paths on a weighted graph follow the oracle's (successors are
+    the nonzero weights); a weighted self-loop is refused; the batched and
+    mixed plans refuse the weighted flag."""
+    rng = gg.rng_for("parity", 9720)
+    n = 200
+    W = gg.weighted(gg.erdos_renyi(n, 0.04, rng), rng, 1, 30)
+    sol = oracle.solve_weighted(W, -0.5)
+    _, info, g = ctx.solve(dev(W), -0.5, flags=R.RDIST_WEIGHTED, keep=True)
+    assert info["status"] == 0
+    pairs = rng.integers(0, n, size=(64, 2)).astype(np.int32)
+    out = ctx.next_hop(g, torch.from_numpy(pairs[:, 0].copy()), torch.from_numpy(pairs[:, 1].copy()),
+                       max_hops=n).cpu().numpy()
+    g.release()
+    check_paths(W, sol.Y, pairs, out, n)
+    loop = W.copy()
+    loop[5, 5] = 7
+    _, info, _ = ctx.solve(dev(loop), -0.5, flags=R.RDIST_WEIGHTED)
+    assert info["status"] == R.RDIST_E_ADJ
+    with pytest.raises(R.RdistError):
+        ctx.solve_batched([dev(W)], -0.5, flags=R.RDIST_WEIGHTED)
+    with pytest.raises(R.RdistError):
+        ctx.solve(dev(W), -0.5, flags=R.RDIST_WEIGHTED | R.RDIST_MIXED_F32)
+
+
+# ---------------------------------------------------------------------------
 # Next hop
 # ---------------------------------------------------------------------------
 
