@@ -32,7 +32,7 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
-UPDATE_SOURCES = ["paper_2308_07403_amd/csrc/rd_kernels.hip", "paper_2308_07403_amd/csrc/rd_device.h"]
+UPDATE_SOURCES = ["paper_2308_07403_amd/csrc/rd_update.hip", "paper_2308_07403_amd/csrc/rd_device.h"]
 
 
 def log(msg):

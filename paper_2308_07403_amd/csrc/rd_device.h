@@ -87,6 +87,12 @@ __device__ __forceinline__ double recip(double p) {
     return fma(r0, e, r0);
 }
 
+// The kernels of the lookahead chain (the next block's diagonal update, its
+// inverse and its row and column tiles) run beside the big update and are
+// on the critical path: their waves take the highest issue priority on the
+// SIMDs they share with the update's waves.
+__device__ __forceinline__ void lookahead_priority() { __builtin_amdgcn_s_setprio(3); }
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;

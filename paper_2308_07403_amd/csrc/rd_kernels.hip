@@ -145,12 +145,6 @@ __global__ __launch_bounds__(256) void k_fill_sentinel(int16_t *D, size_t count,
 // Blocked Gauss-Jordan
 // ---------------------------------------------------------------------------
 
-// The kernels of the lookahead chain (the next block's diagonal update, its
-// inverse and its row and column tiles) run beside the big update and are
-// on the critical path: their waves take the highest issue priority on the
-// SIMDs they share with the update's waves.
-__device__ __forceinline__ void lookahead_priority() { __builtin_amdgcn_s_setprio(3); }
-
 __global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int ld, int K,
                                                double *__restrict__ Pt, double *__restrict__ V, int ldv,
                                                rdist_info *info) {
@@ -201,102 +195,6 @@ __global__ __launch_bounds__(256) void k_rowcol(const double *__restrict__ M, in
         return;
     }
     transpose_neg(M + (size_t)I * kTile * ld + (size_t)K0 * kTile, ld, 2 * m, out, ldv, lds);
-}
-
-// Tile sets of one update, with [L0, L0 + m) the next block's tile range and
-// [L0, L0 + wt) the band of tile rows and columns the lookahead needs early
-// (the next block's, or the next two blocks'):
-//   ALL       every tile;
-//   REST      tiles outside the band's rows and columns;
-//   DIAG      the next block's m x m diagonal tiles (all its inverse needs);
-//   EDGEREST  the band's tile rows and columns minus DIAG.
-enum { kAll = 0, kDiag = 1, kRest = 2, kEdgeRest = 3 };
-
-// Order of the tiles of an nr x nr grid for a big launch.  Workgroups are
-// handed to the 8 XCDs round-robin (workgroup b to XCD b % 8), and each XCD
-// has its own 4 MB L2.  Workgroup b = 8l + x is given position x*F + l of a
-// list that walks strips of 8 tile rows column by column (F = number of
-// workgroups per XCD), so the tiles an XCD holds at one time cover about 8
-// tile rows x 8 tile columns and share their U and V operand slabs in L2.
-// A bijection on [0, nr^2) whatever the hardware's actual assignment.
-__device__ __forceinline__ void xcd_strip_order(int b, int nr, int &i, int &j) {
-    const int total = nr * nr;
-    const int full = total & ~7;
-    const int idx = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
-    const int s = idx / (8 * nr);
-    const int w = idx - s * 8 * nr;
-    const int h = min(8, nr - 8 * s);
-    j = w / h;
-    i = 8 * s + (w - j * h);
-}
-
-template <int MODE>
-__device__ __forceinline__ void update_tile_index(int b, int nt, int L0, int m, int wt, int &I, int &J) {
-    if (MODE == kAll) {
-        xcd_strip_order(b, nt, I, J);
-    } else if (MODE == kDiag) {
-        I = L0 + b / m;
-        J = L0 + (b - (b / m) * m);
-    } else if (MODE == kEdgeRest) {
-        // tile rows [L0, L0 + wt) (minus the m x m diagonal block at L0),
-        // then tile columns [L0, L0 + wt) outside those rows
-        const int r1 = m * (nt - m), r2 = r1 + (wt - m) * nt;
-        if (b < r1) {
-            I = L0 + b / (nt - m);
-            const int Jp = b - (b / (nt - m)) * (nt - m);
-            J = Jp < L0 ? Jp : Jp + m;
-        } else if (b < r2) {
-            const int q = b - r1;
-            I = L0 + m + q / nt;
-            J = q - (q / nt) * nt;
-        } else {
-            const int q = b - r2;
-            const int Ip = q / wt;
-            J = L0 + (q - Ip * wt);
-            I = Ip < L0 ? Ip : Ip + wt;
-        }
-    } else {
-        int Ip, Jp;
-        xcd_strip_order(b, nt - wt, Ip, Jp);
-        I = Ip < L0 ? Ip : Ip + wt;
-        J = Jp < L0 ? Jp : Jp + wt;
-    }
-}
-
-// M_IJ <- M~_IJ - U_I V_J (inner dimension b = 128*MT) over the tiles of
-// MODE, M~ = M with the current block's tile rows and columns [K0, K0 + m)
-// zeroed.  The accumulators start from M~_IJ (loaded before the first operand
-// chunk lands) and add (-U)^T V, Ut holding -U^T.  With FUSED the tile's
-// final value is read out into D (and stored to M only if keep_y).
-template <int MODE, bool FUSED, int MT>
-__global__ __launch_bounds__(256, 2) void k_update(double *__restrict__ M, int ld, int nt, int K0, int L0, int wt,
-                                                   const double *__restrict__ Ut, const double *__restrict__ V,
-                                                   int ldv, int n, int16_t *__restrict__ D, int keep_y,
-                                                   rdist_info *info) {
-    constexpr int m = MT;
-    if (info->status != RDIST_OK) return;
-    if (MODE == kDiag || (MODE == kAll && !FUSED && MT == 1)) lookahead_priority();
-    __shared__ double lds[kTileLdsDoubles];
-    int I, J;
-    update_tile_index<MODE>(blockIdx.x, nt, L0, m, wt, I, J);
-    const bool zero_in = (I >= K0 && I < K0 + m) || (J >= K0 && J < K0 + m);
-    double *base = M + (size_t)I * kTile * ld + (size_t)J * kTile;
-    TileAcc acc;
-    if (zero_in) acc.zero();
-    else tile_load_acc(acc, base, ld);
-    tile_mma<MT * kTile>(Ut + (size_t)I * kTile, ldv, V + (size_t)J * kTile, ldv, lds, acc);
-    if (!FUSED) {
-        tile_for_each(acc, [&](int r, int c, double v) { base[(size_t)r * ld + c] = v; });
-    } else {
-        const double lg = rd_inv_log(info->gamma);
-        Counts cnt;
-        tile_for_each(acc, [&](int r, int c, double y) {
-            if (keep_y) base[(size_t)r * ld + c] = y;
-            const int gi = I * kTile + r, gj = J * kTile + c;
-            if (gi < n && gj < n) D[(size_t)gi * n + gj] = rd_encode(y, lg, cnt);
-        });
-        flush_counts(info, cnt);
-    }
 }
 
 // From P (b x b, stored with leading dimension lds): Pt = P^T (ld b) and V's
@@ -418,39 +316,6 @@ void launch_rowcol(const double *M, int ld, int nt, int K0, int m, const double 
         hipLaunchKernelGGL(k_rowcol<1>, dim3(2 * nt), dim3(256), 0, s, M, ld, nt, K0, Pt, Ut, V, ldv, info);
     else
         hipLaunchKernelGGL(k_rowcol<2>, dim3(3 * nt), dim3(256), 0, s, M, ld, nt, K0, Pt, Ut, V, ldv, info);
-}
-
-int update_tiles(int mode, int nt, int m, int wt) {
-    if (mode == kAll) return nt * nt;
-    if (mode == kDiag) return m * m;
-    if (mode == kEdgeRest) return m * (nt - m) + (wt - m) * nt + (nt - wt) * wt;
-    return (nt - wt) * (nt - wt);
-}
-
-template <int MT>
-static void launch_update_t(int mode, double *M, int ld, int nt, int K0, int L0, int wt, const double *Ut,
-                            const double *V, int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info,
-                            hipStream_t s) {
-    const int tiles = update_tiles(mode, nt, MT, wt);
-    if (tiles <= 0) return;
-    const dim3 g(tiles), bl(256);
-#define RD_UPD(MODE_, FUSED_) \
-    hipLaunchKernelGGL((k_update<MODE_, FUSED_, MT>), g, bl, 0, s, M, ld, nt, K0, L0, wt, Ut, V, ldv, n, D, keep_y, info)
-    if (fused) RD_UPD(kAll, true);
-    else if (mode == kAll) RD_UPD(kAll, false);
-    else if (mode == kDiag) RD_UPD(kDiag, false);
-    else if (mode == kEdgeRest) RD_UPD(kEdgeRest, false);
-    else RD_UPD(kRest, false);
-#undef RD_UPD
-}
-
-void launch_update(int mode, double *M, int ld, int nt, int K0, int m, int L0, int wt, const double *Ut,
-                   const double *V, int ldv, bool fused, int n, int16_t *D, int keep_y, rdist_info *info,
-                   hipStream_t s) {
-    if (m == 1)
-        launch_update_t<1>(mode, M, ld, nt, K0, L0, wt, Ut, V, ldv, fused, n, D, keep_y, info, s);
-    else
-        launch_update_t<2>(mode, M, ld, nt, K0, L0, wt, Ut, V, ldv, fused, n, D, keep_y, info, s);
 }
 
 void launch_panel_finish(const double *S, int lds, int b, int K0, double *Pt, double *V, int ldv,
