@@ -11,7 +11,7 @@ Prints ONE JSON line: graphs/s (whole job), ms per step, effective TFLOP/s
 trailing-update kernel, timed with HIP events on its launch stream inside
 the library), and the CPU oracle timed on a bounded sample of the same solve.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5|f1|f3]
 """
 from __future__ import annotations
 
@@ -518,6 +518,116 @@ def bench_f1(args, torch, R, gg):
     return out
 
 
+DYNAMIC_SOURCES = ["paper_2308_07403_amd/csrc/rd_dynamic.hip", "paper_2308_07403_amd/csrc/rd_device.h"]
+
+
+def plan_changes(rng, A, delta_cap, count):
+    """`count` edge changes applied to A in place, alternating removals of
+    existing edges and additions that keep every out-degree <= delta_cap."""
+    n = A.shape[0]
+    outdeg = (A != 0).sum(axis=0).astype(np.int64)
+    out = []
+    for k in range(count):
+        if k % 2 == 0:
+            while True:
+                src, dst = map(int, rng.integers(0, n, size=2))
+                if src != dst and A[dst, src]:
+                    break
+            A[dst, src] = 0
+            outdeg[src] -= 1
+            out.append((src, dst, 0))
+        else:
+            while True:
+                src, dst = map(int, rng.integers(0, n, size=2))
+                if src != dst and not A[dst, src] and outdeg[src] < delta_cap:
+                    break
+            A[dst, src] = 1
+            outdeg[src] += 1
+            out.append((src, dst, 1))
+    return out
+
+
+def bench_f3(args, torch, R, gg):
+    """Edge changes on a kept graph (rank-one update of Y, the dynamic
+    re-planning use of the Discussion): the C2 graph, ER(8192, 0.02) at
+    gamma = 0.5/Delta, solved once with KEEP_Y; one step = 32 changes
+    (alternating removals and additions), each rewriting Y, its error bounds
+    and D in one pass.  Re-inversions the bounds call for are inside the
+    timed region and counted."""
+    n, per_step = 8192, 32
+    rng = gg.rng_for("f3", 0)
+    A_np = gg.erdos_renyi(n, 0.02, rng)
+    A = torch.from_numpy(A_np).cuda()
+    D = torch.empty((n, n), dtype=torch.int16, device="cuda")
+    ctx = R.Context(0)
+    stream = torch.cuda.current_stream()
+    D0, info, g = ctx.solve(A, -0.5, keep=True)
+    assert info["status"] == 0
+    gamma, delta = info["gamma"], info["delta"]
+    # a full re-solve of the same graph on the GPU, for comparison
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.solve_async(A, -0.5, 0, D, stream=stream)
+    torch.cuda.synchronize()
+    resolve_ms = (time.perf_counter() - t0) * 1e3 / reps
+    A_host = A_np.copy()
+    warm = plan_changes(rng, A_host, delta, args.warmup * per_step)
+    timed = plan_changes(rng, A_host, delta, args.steps * per_step)
+    for src, dst, w in warm:
+        g.update_edge(src, dst, w, D=D)
+    torch.cuda.synchronize()
+    ctx.set_timing(True, classes=[R.RDIST_K_EDGE_UPDATE])
+    lost = refreshed = 0
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for src, dst, w in timed:
+        t1 = time.perf_counter()
+        inf = g.update_edge(src, dst, w, D=D)
+        lat.append((time.perf_counter() - t1) * 1e3)
+        lost += inf["n_uncertified"]
+        refreshed += inf["fallback_fraction"] == 1.0
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.kernel_stats(R.RDIST_K_EDGE_UPDATE)
+    ctx.set_timing(False)
+    assert inf["status"] == 0, inf
+    g.release()
+    ctx.close()
+    nch = len(timed)
+    per_launch_bytes = 22.0 * n * n
+    avg_ms = st["total_ms"] / max(st["launches"], 1)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    sha = source_sha(DYNAMIC_SOURCES)
+    out = {
+        "metric": "edge changes/s on a kept n=8192 graph (Y and D rewritten per change)",
+        "value": nch / wall, "unit": "changes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "f3: directed ER(n=8192, p=0.02), gamma=0.5/Delta, kept Y; one step = 32 edge "
+                               "changes (alternating removals and additions), each a rank-one update of Y with "
+                               "its error bounds and the int16 D readout in the same pass",
+                   "n": n, "gamma": gamma, "delta": delta, "changes_per_step": per_step},
+        "ms_per_change": wall * 1e3 / nch, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+        "resolve_ms": resolve_ms, "speedup_vs_resolve": resolve_ms / (wall * 1e3 / nch),
+        "lost_entries": int(lost), "reinversions": int(refreshed),
+        "roofline": {"bound": "hbm", "kernel": "k_sm_apply<4>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": read_traffic("k_sm_apply_f3_n8192_pmc.md", sha), "avg_launch_ms": avg_ms,
+                     "launches": st["launches"], "bytes_per_launch": per_launch_bytes, "source_sha": sha},
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle re-solve of the changed graph, sampled)")
+        cb = cpu_baseline_c2(A_host, args.cpu_gj_steps, args.cpu_rows)
+        cb["unit"] = "changes/s"
+        cb["sample"] = "one oracle re-solve per change; " + cb["sample"]
+        out["cpu_baseline"] = cb
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
 def bench_c1(args, torch, R, gg):
     import oracle
     As = [torch.from_numpy(gg.c1_graph(s)).cuda() for s in range(100)]
@@ -648,7 +758,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "f1"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "f1", "f3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-concurrent", action="store_true",
                     help="C2: skip the three-stream throughput (profiling runs, one solve at a time)")
@@ -692,7 +802,7 @@ def main():
         log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
         del src, dst, scrub
     out = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
-           "f1": bench_f1}[args.workload](args, torch, R, gg)
+           "f1": bench_f1, "f3": bench_f3}[args.workload](args, torch, R, gg)
     print(json.dumps(out), flush=True)
 
 

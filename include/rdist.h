@@ -96,8 +96,10 @@ typedef struct rdist_info {
     int64_t n_saturated;     /* entries clamped to the int16 range */
     int64_t n_ambiguous;     /* entries whose R - eta lies within 1e-10 of an integer */
     int64_t n_negative;      /* entries with Y < 0 (never expected under the gate) */
-    int64_t n_uncertified;   /* RDIST_MIXED_F32: entries recomputed in FP64 */
-    double fallback_fraction;/* RDIST_MIXED_F32: n_uncertified / n^2 */
+    int64_t n_uncertified;   /* RDIST_MIXED_F32: entries recomputed in FP64;
+                                edge change: entries its error bounds lost */
+    double fallback_fraction;/* RDIST_MIXED_F32: n_uncertified / n^2;
+                                edge change: 1 when it re-inverted the graph */
 } rdist_info;
 
 /*
@@ -192,6 +194,37 @@ void rdist_graph_release(rdist_graph g);
  * Y[i*ld + j] for 0 <= i, j < n.  Returns RDIST_E_ARG for a NULL handle.
  */
 rdist_status rdist_graph_y(rdist_graph g, const double **Y_dev, int32_t *n, int32_t *ld);
+
+/*
+ * Edge change on a kept graph without a new inversion (the dynamic
+ * re-planning of the Discussion, Applications): the edge src -> dst gets
+ * weight `weight` (0 removes it; 0/1 for graphs solved without
+ * RDIST_WEIGHTED, 0 .. 255 with it).  With delta the change of the entry
+ * gamma^w of X (Sec. 3.2), Y becomes
+ *   Y + f Y[:, dst] Y[src, :],  f = delta / (1 - delta Y[src, dst])
+ * (Sherman-Morrison), i.e. (I - X')^{-1} for the changed graph at the graph's
+ * gain, in one pass over Y; the graph's adjacency, out-degrees and successor
+ * lists follow.  D_dev (nullable, n x n int16) receives the changed graph's D.
+ *
+ * Every entry of Y carries a bound on its relative error (2 bytes per entry,
+ * allocated by the first change and counted in the budget), carried through
+ * each change.  Entries whose bound no longer vouches for them (a removal
+ * that cancels an entry to zero or to its rounding error; a D readout whose
+ * integer boundary lies within the bound) are counted in
+ * info->n_uncertified, and the call then re-inverts the changed graph from
+ * its kept adjacency (info->fallback_fraction = 1, info's counters those of
+ * the new inversion).  So D_dev equals, up to the readout's own ambiguity
+ * band, the D of a fresh rdist_solve of the changed graph at the same gain.
+ *
+ * The change is applied only if the changed graph passes the gate
+ * gamma * Delta' < 1; otherwise Y, D_dev and the graph stay as they were and
+ * info->status is RDIST_E_NOT_DD.  info (nullable, host) receives the call's
+ * status, Delta', gamma and D's counters.  RDIST_E_ARG for bad nodes or
+ * weight.  The call returns when the change is complete (it waits for the
+ * stream); changes to one graph must not overlap.
+ */
+rdist_status rdist_graph_update_edge(rdist_ctx ctx, rdist_graph g, int32_t src, int32_t dst, int32_t weight,
+                                     int16_t *D_dev, rdist_info *info, void *stream);
 
 /*
  * Standalone readout over a caller-provided Y (the unfused form of the
@@ -296,7 +329,8 @@ typedef struct rdist_kernel_stats {
                                  last, readout-fused update */
 #define RDIST_K_MIXED_GEMM 10  /* mixed precision: FP32 row products and trailing updates */
 #define RDIST_K_REFINE 11     /* mixed precision: residual, correction product and recompute */
-#define RDIST_K_COUNT 12
+#define RDIST_K_EDGE_UPDATE 12 /* rdist_graph_update_edge: the rank-1 pass over Y (and D) */
+#define RDIST_K_COUNT 13
 
 /* Per-kernel event timing: 0 off, 1 every kernel class, or a mask of
  * RDIST_TIMING_CLASS(k) bits timing only those classes (each timed launch

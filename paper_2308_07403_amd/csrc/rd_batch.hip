@@ -656,7 +656,8 @@ extern "C" rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const in
             if (!ys[g].p) continue;
             Buf y = ys[g];
             ys[g] = Buf{};
-            if ((st = make_graph(c, n[g], (double *)y.p, np_of(n[g]), y.bytes, A_dev[g], s, &keep[g]))) {
+            if ((st = make_graph(c, n[g], (double *)y.p, np_of(n[g]), y.bytes, A_dev[g], s, &keep[g],
+                                 (const rdist_info *)p->infos.p + g, false))) {
                 release(c, y);
                 for (Buf &b : ys) release(c, b);
                 return st;

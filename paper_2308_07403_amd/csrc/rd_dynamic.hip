@@ -1,0 +1,309 @@
+// rd_dynamic.hip -- edge changes on a kept graph without a new inversion.
+//
+// Adding, removing or re-weighting the edge src -> dst changes one entry of
+// M = I - X: M' = M - delta e_dst e_src^T with delta = X'_{dst,src} -
+// X_{dst,src} (gamma^w for an edge of weight w, 0 for none; Sec. 3.2).  The
+// Sherman-Morrison identity gives the new inverse from the old one,
+//   Y' = Y + f Y[:, dst] Y[src, :],   f = delta / (1 - delta Y[src, dst]),
+// one pass over Y instead of an O(n^3) solve (the dynamic re-planning of the
+// paper's Discussion, Applications).  The change is applied only if the new
+// graph still passes the gate gamma Delta' < 1 (then M' is a nonsingular
+// M-matrix, Y' >= 0 and the denominator is positive); otherwise the graph is
+// left as it was.
+//
+// Rounding.  A removal (delta < 0) subtracts: an entry whose walks mostly
+// used the removed edge keeps only the rounding error of the old value, and
+// an entry the removal disconnects comes out as a tiny residue instead of 0.
+// So every entry carries a bound beta on its relative error, propagated
+// through each update to first order,
+//   beta' Y' >= beta Y + (beta_f + beta_c + beta_r + u) |t| + u Y'
+// (t = f c r the update term, u = 2^-53), with a 2^-16 relative margin for
+// the second-order terms.  beta is kept as a 16-bit fixed-point -log2 with
+// 8 fraction bits (q = floor(-256 log2 beta), decoded upwards), one pass
+// of 2 bytes per entry beside Y's 8.  An entry is lost when its Y' is not
+// positive while the term was not zero, when beta' exceeds 2^-20, or when
+// D is asked for and the readout's integer boundary lies within beta' of it
+// (in log_gamma units): then D of the computed Y' might differ from D of
+// the exact one.  Lost entries are counted; the host re-inverts the changed
+// graph from its kept adjacency when there are any.  The starting bound of
+// an inversion is an assumption, max(2^-40, 8 n u / (1 - gamma Delta)).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rd_device.h"
+#include "rd_launch.h"
+
+namespace rd {
+
+namespace {
+
+constexpr double kU = 1.1102230246251565e-16;      // 2^-53
+constexpr double kBetaCap = 9.5367431640625e-07;   // 2^-20
+constexpr double kBetaFCap = 5.9604644775390625e-08;   // 2^-24: f itself too uncertain
+constexpr int kRows = 8;                          // rows per workgroup of the apply pass
+
+// beta <= 2^(-q/256), decoded upwards (the FP32 exp2 is within an ulp or two).
+__device__ __forceinline__ float beta_decode(uint16_t q) {
+    return __builtin_amdgcn_exp2f(-(float)q * (1.0f / 256.0f)) * 1.0000010f;
+}
+
+// The largest q with 2^(-q/256) >= beta (0 for beta >= 1).
+__device__ __forceinline__ uint16_t beta_encode(double beta) {
+    const float b = (float)(beta * 1.000001);
+    if (!(b < 1.0f)) return 0;
+    const float q = floorf(-__builtin_amdgcn_logf(b) * 256.0f - 0.01f);
+    return (uint16_t)fminf(fmaxf(q, 0.0f), 65535.0f);
+}
+
+// D for an entry with computed Y' = y > 0 and relative error bound beta:
+// the readout of rd_encode; `near` is raised when an integer boundary of
+// t = log_gamma Y' - eta lies within beta |il| (1 + 1%) of t.
+__device__ __forceinline__ int16_t encode_bounded(double y, double beta, double il, Counts &c, bool &near) {
+    const double w = -beta * il * 1.01;   // il < 0
+    if (y >= kDblMin) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(y);
+        const int e = (int)((bits >> 52) & 0x7FFull) - 1023;
+        const double m = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+        const double l2m = (double)__builtin_amdgcn_logf((float)m);
+        const double s = kLn2 * il;
+        const double te = ((double)e + l2m) * s - kEta;
+        const double band = 1e-4 - 4e-6 * s;
+        if (fabs(te - rint(te)) > band + w) return rd_clamp_d(ceil(te), c);
+    } else {
+        ++c.subnormal;
+    }
+    const double t = log(y) * il - kEta;
+    const double dt = fabs(t - rint(t));
+    near = dt <= w;
+    if (dt < kBeta) ++c.ambiguous;
+    return rd_clamp_d(ceil(t), c);
+}
+
+}  // namespace
+
+// Out-degree of node j = set bits of its successor row.
+__global__ __launch_bounds__(256) void k_outdeg_from_bits(const unsigned long long *__restrict__ bits, int n, int nw,
+                                                          int32_t *__restrict__ outdeg) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    int c = 0;
+    for (int w = 0; w < nw; ++w) c += __popcll(bits[(size_t)j * nw + w]);
+    outdeg[j] = c;
+}
+
+// Every entry's bound set to the starting bound of an inversion of this
+// graph (its gain and Delta from the graph's info).
+__global__ __launch_bounds__(256) void k_beta_fill(uint16_t *__restrict__ Q, size_t count,
+                                                   const rdist_info *__restrict__ ginfo, int n) {
+    const double gd = ginfo->gamma * (double)ginfo->delta;
+    const double b0 = fmax(9.094947017729282e-13, 8.0 * n * kU / fmax(1.0 - gd, 1e-300));   // 2^-40
+    const uint16_t q = beta_encode(b0);
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < count; k += (size_t)gridDim.x * 256) Q[k] = q;
+}
+
+// Gate and snapshots, one thread per node i.  Every workgroup evaluates the
+// gate on the new out-degrees itself (no grid-wide step); workgroup 0 writes
+// the call's info and f.  The graph's own adjacency, out-degrees and
+// successor bit are changed by the apply pass, after every read here.
+// sm: [0] f, [1] beta_f, [2, 11) the call's rdist_info, [15] 1 when f is too
+// uncertain to use, [16, 16 + n) Y's column dst, [16 + n, 16 + 2n) Y's row
+// src, then 2n floats: the bounds of that column and that row.
+__global__ __launch_bounds__(256) void k_sm_prep(const double *__restrict__ Y, int ld, int n,
+                                                 const uint8_t *__restrict__ A, const int32_t *__restrict__ outdeg,
+                                                 const uint16_t *__restrict__ Q, const rdist_info *__restrict__ ginfo,
+                                                 double *__restrict__ sm, int src, int dst, int w_new) {
+    __shared__ int smax;
+    rdist_info *ci = reinterpret_cast<rdist_info *>(sm + 2);
+    const double gamma = ginfo->gamma;
+    const int w_old = A[(size_t)dst * n + src];
+    const int cnt_src = outdeg[src] + (w_new != 0) - (w_old != 0);
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    int m = 0;
+    for (int j = threadIdx.x; j < n; j += 256) m = max(m, j == src ? cnt_src : outdeg[j]);
+    atomicMax(&smax, m);
+    __syncthreads();
+    const int delta_new = smax;
+    // the entries of X the inversion itself would build for these weights
+    const double xo = w_old ? pow(gamma, (double)w_old) : 0.0;
+    const double xn = w_new ? pow(gamma, (double)w_new) : 0.0;
+    const double d = xn - xo;
+    const double ysd = Y[(size_t)src * ld + dst];
+    const double den = fma(-d, ysd, 1.0);
+    const bool ok = ginfo->status == RDIST_OK && gamma * (double)delta_new < 1.0 && den > 0.0;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (ok && i < n) {
+        float *bc = reinterpret_cast<float *>(sm + 16 + 2 * (size_t)n);
+        sm[16 + i] = Y[(size_t)i * ld + dst];
+        sm[16 + n + i] = Y[(size_t)src * ld + i];
+        bc[i] = beta_decode(Q[(size_t)i * n + dst]);
+        bc[n + i] = beta_decode(Q[(size_t)src * n + i]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double bd = (xo != 0.0 && xn != 0.0) ? kU : 0.0;
+        const double bsd = beta_decode(Q[(size_t)src * n + dst]);
+        const double bden = fabs(d) * ysd * (bd + bsd) / den + kU;
+        const double bf = (bd + bden + kU) * (1.0 + 1.0 / 65536.0);
+        ci->status = ginfo->status != RDIST_OK ? ginfo->status : (ok ? RDIST_OK : RDIST_E_NOT_DD);
+        ci->delta = ok ? delta_new : ginfo->delta;
+        ci->gamma = gamma;
+        ci->n_unreachable = ci->n_subnormal = ci->n_saturated = 0;
+        ci->n_ambiguous = ci->n_negative = 0;
+        ci->n_uncertified = (ok && !(bf <= kBetaFCap)) ? (int64_t)n * n : 0;
+        ci->fallback_fraction = 0.0;
+        sm[0] = ok ? d / den : 0.0;
+        sm[1] = bf;
+        sm[15] = (ok && !(bf <= kBetaFCap)) ? 1.0 : 0.0;
+    }
+}
+
+// Y[i][j] += f c[i] r[j] with the bound update, and D[i][j] read out from
+// the new Y when D is given (counters and lost entries into the call's
+// info).  A workgroup takes kRows rows by 256 V columns: r and its bounds
+// are read once per kRows rows.  V = 4 needs n and ld multiples of 4 and
+// D (when given) 8-byte aligned.
+template <int V>
+__global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld, int n, uint16_t *__restrict__ Q,
+                                                  double *__restrict__ sm, int16_t *__restrict__ D,
+                                                  uint8_t *__restrict__ A, int32_t *__restrict__ outdeg,
+                                                  unsigned long long *__restrict__ bits, rdist_info *__restrict__ ginfo,
+                                                  int src, int dst, int w_new) {
+    rdist_info *ci = reinterpret_cast<rdist_info *>(sm + 2);
+    if (ci->status != RDIST_OK) return;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        // the graph follows the change (the prep pass has read it already)
+        const int w_old = A[(size_t)dst * n + src];
+        A[(size_t)dst * n + src] = (uint8_t)w_new;
+        outdeg[src] += (w_new != 0) - (w_old != 0);
+        unsigned long long *word = bits + (size_t)src * ((n + 63) / 64) + (dst >> 6);
+        const unsigned long long bit = 1ull << (dst & 63);
+        *word = w_new ? (*word | bit) : (*word & ~bit);
+        ginfo->delta = ci->delta;
+    }
+    if (sm[15] != 0.0) return;   // f too uncertain: the host re-inverts
+    const double f = sm[0], bf = sm[1];
+    const double *__restrict__ c = sm + 16;
+    const double *__restrict__ r = sm + 16 + n;
+    const float *__restrict__ bc = reinterpret_cast<const float *>(sm + 16 + 2 * (size_t)n);
+    const float *__restrict__ br = bc + n;
+    const double il = rd_inv_log(ci->gamma);
+    const int j0 = (blockIdx.x * 256 + threadIdx.x) * V;
+    const bool active = j0 < n;
+    Counts cnt;
+    unsigned lost = 0;
+    double rv[V], brv[V];
+    if (active) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const bool in = V == 1 || j0 + v < n;
+            rv[v] = in ? r[j0 + v] : 0.0;
+            brv[v] = in ? (double)br[j0 + v] : 0.0;
+        }
+    }
+    const int i0 = blockIdx.y * kRows;
+    for (int ii = 0; ii < kRows && active; ++ii) {
+        const int i = i0 + ii;
+        if (i >= n) break;
+        const double fc = f * c[i];
+        const double bci = (double)bc[i] + bf + kU;
+        double *__restrict__ yr = Y + (size_t)i * ld + j0;
+        uint16_t *__restrict__ qr = Q + (size_t)i * n + j0;
+        double y[V];
+        uint16_t q[V];
+        if constexpr (V == 4) {
+            const d4 y4 = *reinterpret_cast<const d4 *>(yr);
+            const ushort4 q4 = *reinterpret_cast<const ushort4 *>(qr);
+            y[0] = y4.x; y[1] = y4.y; y[2] = y4.z; y[3] = y4.w;
+            q[0] = q4.x; q[1] = q4.y; q[2] = q4.z; q[3] = q4.w;
+        } else {
+            y[0] = yr[0];
+            q[0] = qr[0];
+        }
+        int16_t dv[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const double t = fc * rv[v];
+            const double yo = y[v];
+            const double yn = fma(fc, rv[v], yo);
+            y[v] = yn;
+            // entries the term leaves alone keep their value, bound and D
+            bool bad = false;
+            double beta = 0.0;
+            if (t != 0.0) {
+                if (yn >= kDblMin) {
+                    double inv = __builtin_amdgcn_rcp(yn);
+                    inv = fma(fma(-yn, inv, 1.0), inv, inv);
+                    beta = ((double)beta_decode(q[v]) * yo + (bci + brv[v]) * fabs(t)) * inv *
+                               (1.0 + 1.0 / 65536.0) + 2.0 * kU;
+                    bad = !(beta <= kBetaCap);
+                } else {
+                    bad = true;   // cancelled to zero or below, or no relative bound (subnormal)
+                    beta = 1.0;
+                }
+                q[v] = beta_encode(beta);
+            }
+            if (D) {
+                if (yn > 0.0) {
+                    bool near = false;
+                    dv[v] = encode_bounded(yn, beta, il, cnt, near);
+                    bad |= t != 0.0 && near;
+                } else {
+                    dv[v] = kUnreachable;
+                    if (t == 0.0) {
+                        if (yn == 0.0) ++cnt.unreachable;
+                        else ++cnt.negative;
+                    }
+                }
+            }
+            lost += bad ? 1u : 0u;
+        }
+        if constexpr (V == 4) {
+            d4 o;
+            o.x = y[0]; o.y = y[1]; o.z = y[2]; o.w = y[3];
+            *reinterpret_cast<d4 *>(yr) = o;
+            *reinterpret_cast<ushort4 *>(qr) = make_ushort4(q[0], q[1], q[2], q[3]);
+            if (D) {
+                short4 s4 = make_short4(dv[0], dv[1], dv[2], dv[3]);
+                *reinterpret_cast<short4 *>(D + (size_t)i * n + j0) = s4;
+            }
+        } else {
+            yr[0] = y[0];
+            qr[0] = q[0];
+            if (D) D[(size_t)i * n + j0] = dv[0];
+        }
+    }
+    if (D) flush_counts(ci, cnt);
+    unsigned long long l = wave_sum_u64(lost);
+    if ((threadIdx.x & 63) == 0 && l) atomicAdd((unsigned long long *)&ci->n_uncertified, l);
+}
+
+void launch_outdeg_from_bits(const unsigned long long *bits, int n, int32_t *outdeg, hipStream_t s) {
+    const int nw = (n + 63) / 64;
+    hipLaunchKernelGGL(k_outdeg_from_bits, dim3((n + 255) / 256), dim3(256), 0, s, bits, n, nw, outdeg);
+}
+
+void launch_beta_fill(uint16_t *Q, int n, const rdist_info *ginfo, hipStream_t s) {
+    const size_t count = (size_t)n * n;
+    const int blocks = (int)std::min<size_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_beta_fill, dim3(blocks), dim3(256), 0, s, Q, count, ginfo, n);
+}
+
+void launch_edge_prep(const double *Y, int ld, int n, const uint8_t *A, const int32_t *outdeg, const uint16_t *Q,
+                      const rdist_info *ginfo, double *sm, int src, int dst, int weight, hipStream_t s) {
+    hipLaunchKernelGGL(k_sm_prep, dim3((n + 255) / 256), dim3(256), 0, s, Y, ld, n, A, outdeg, Q, ginfo, sm, src,
+                       dst, weight);
+}
+
+void launch_edge_apply(double *Y, int ld, int n, uint16_t *Q, double *sm, int16_t *D, uint8_t *A, int32_t *outdeg,
+                       unsigned long long *bits, rdist_info *ginfo, int src, int dst, int weight, hipStream_t s) {
+    const dim3 rows((n + kRows - 1) / kRows);
+    if (n % 4 == 0 && ld % 4 == 0 && ((uintptr_t)D & 7) == 0) {
+        hipLaunchKernelGGL(k_sm_apply<4>, dim3((n / 4 + 255) / 256, rows.x), dim3(256), 0, s, Y, ld, n, Q, sm, D, A,
+                           outdeg, bits, ginfo, src, dst, weight);
+    } else {
+        hipLaunchKernelGGL(k_sm_apply<1>, dim3((n + 255) / 256, rows.x), dim3(256), 0, s, Y, ld, n, Q, sm, D, A,
+                           outdeg, bits, ginfo, src, dst, weight);
+    }
+}
+
+}  // namespace rd

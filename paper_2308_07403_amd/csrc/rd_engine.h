@@ -88,8 +88,18 @@ struct rdist_graph_s {
     rdist_ctx ctx = nullptr;
     double *Y = nullptr;
     int n = 0, ld = 0;
-    unsigned long long *succ = nullptr;
-    size_t bytes = 0;
+    unsigned long long *succ = nullptr;   // successor bitmaps (n x ceil(n/64))
+    // for edge changes: the graph's own adjacency or weights (n x n), its
+    // out-degrees, its info (gain, status), scratch of an update
+    uint8_t *A = nullptr;
+    int32_t *outdeg = nullptr;
+    rdist_info *ginfo = nullptr;
+    double *sm = nullptr;
+    uint16_t *beta = nullptr;             // per-entry error bounds, made by the first change
+    int weighted = 0;
+    void *aux = nullptr;                  // one allocation holding succ .. sm
+    size_t ybytes = 0, aux_bytes = 0, beta_bytes = 0;
+    size_t bytes = 0;                     // their sum, counted in the context's budget
 };
 
 struct rdist_ctx_s {
@@ -162,8 +172,11 @@ struct Timer {
 
 void drain_timing(rdist_ctx c);
 rdist_status copy_info(rdist_info *host, const rdist_info *dev, int count, hipStream_t s);
+// A graph handle owning Y (ld) and ybytes of it; copies A, builds the
+// successor bitmaps and out-degrees and keeps a copy of the solve's info
+// (dinfo, device), all on stream s.
 rdist_status make_graph(rdist_ctx c, int n, double *Y, int ld, size_t ybytes, const uint8_t *A, hipStream_t s,
-                        rdist_graph *out);
+                        rdist_graph *out, const rdist_info *dinfo, bool weighted);
 void release_graph_locked(rdist_graph g);
 rdist_status check_flags(uint32_t flags);
 rdist_status check_gamma(double gamma);

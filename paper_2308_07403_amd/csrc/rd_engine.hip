@@ -166,21 +166,41 @@ rdist_status copy_info(rdist_info *host, const rdist_info *dev, int count, hipSt
 }
 
 rdist_status make_graph(rdist_ctx c, int n, double *Y, int ld, size_t ybytes, const uint8_t *A, hipStream_t s,
-                        rdist_graph *out) {
+                        rdist_graph *out, const rdist_info *dinfo, bool weighted) {
     const int nw = (n + 63) / 64;
-    const size_t bb = (size_t)n * nw * 8;
-    unsigned long long *bits = nullptr;
-    rdist_status st = dalloc(c, (void **)&bits, bb);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t b_succ = al((size_t)n * nw * 8), b_a = al((size_t)n * n), b_deg = al((size_t)n * 4),
+                 b_info = al(sizeof(rdist_info)), b_sm = al(((size_t)3 * n + 16) * 8);
+    const size_t bytes = b_succ + b_a + b_deg + b_info + b_sm;
+    void *aux = nullptr;
+    rdist_status st = dalloc(c, &aux, bytes);
     if (st) return st;
-    rd::launch_succ_bitmap(A, n, bits, s);
-    RD_HIP(hipGetLastError());
+    char *p = (char *)aux;
     auto *g = new rdist_graph_s();
     g->ctx = c;
     g->Y = Y;
     g->n = n;
     g->ld = ld;
-    g->succ = bits;
-    g->bytes = ybytes + bb;
+    g->succ = (unsigned long long *)p;
+    g->A = (uint8_t *)(p + b_succ);
+    g->outdeg = (int32_t *)(p + b_succ + b_a);
+    g->ginfo = (rdist_info *)(p + b_succ + b_a + b_deg);
+    g->sm = (double *)(p + b_succ + b_a + b_deg + b_info);
+    g->weighted = weighted ? 1 : 0;
+    g->aux = aux;
+    g->ybytes = ybytes;
+    g->aux_bytes = bytes;
+    g->bytes = ybytes + bytes;
+    rd::launch_succ_bitmap(A, n, g->succ, s);
+    rd::launch_outdeg_from_bits(g->succ, n, g->outdeg, s);
+    hipError_t e = hipMemcpyAsync(g->A, A, (size_t)n * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->ginfo, dinfo, sizeof(rdist_info), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        dfree(c, aux, bytes);
+        delete g;
+        return fail(RDIST_E_HIP, std::string("graph handle: ") + hipGetErrorString(e));
+    }
     c->graphs.insert(g);
     *out = g;
     return RDIST_OK;
@@ -189,7 +209,8 @@ rdist_status make_graph(rdist_ctx c, int n, double *Y, int ld, size_t ybytes, co
 void release_graph_locked(rdist_graph g) {
     rdist_ctx c = g->ctx;
     (void)hipFree(g->Y);
-    (void)hipFree(g->succ);
+    (void)hipFree(g->aux);
+    if (g->beta) (void)hipFree(g->beta);
     c->in_use -= std::min(g->bytes, c->in_use);
     c->graphs.erase(g);
     delete g;
@@ -347,7 +368,7 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
     if (keep_y && keep) {
         Buf y = w.M;          // the graph takes M over (its bytes stay counted)
         w.M = Buf{};
-        st = make_graph(c, n, (double *)y.p, ld, y.bytes, A, s, keep);
+        st = make_graph(c, n, (double *)y.p, ld, y.bytes, A, s, keep, dinfo, (flags & RDIST_WEIGHTED) != 0);
         if (st) {
             release(c, y);
             return st;
@@ -372,7 +393,7 @@ rdist_status solve_small(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
     }
     RD_HIP(hipGetLastError());
     if (keep_y) {
-        st = make_graph(c, n, Y, n, yb, A, s, keep);
+        st = make_graph(c, n, Y, n, yb, A, s, keep, w.dinfo(), false);
         if (st) { dfree(c, Y, yb); return st; }
     }
     return copy_info(info, w.dinfo(), 1, s);
@@ -519,6 +540,85 @@ rdist_status rdist_graph_y(rdist_graph g, const double **Y_dev, int32_t *n, int3
     if (Y_dev) *Y_dev = g->Y;
     if (n) *n = g->n;
     if (ld) *ld = g->ld;
+    return RDIST_OK;
+}
+
+// Re-inverts a kept graph from its own (already changed) adjacency at its
+// gain and takes the new Y over; the error bounds restart.  D gets the new
+// graph's D (a temporary when the caller passed none); *out the solve's info.
+static rdist_status refresh_graph(rdist_ctx c, rdist_graph g, double gamma, int16_t *D, rdist_info *out,
+                                  hipStream_t s) {
+    void *tmp = nullptr;
+    const size_t db = (size_t)g->n * g->n * 2;
+    rdist_status st;
+    if (!D) {
+        if ((st = dalloc(c, &tmp, db))) return st;
+        D = (int16_t *)tmp;
+    }
+    const uint32_t flags = RDIST_KEEP_Y | (g->weighted ? RDIST_WEIGHTED : 0u);
+    rdist_graph fresh = nullptr;
+    st = (!g->weighted && g->n <= 128) ? solve_small(c, g->A, g->n, gamma, flags, D, &fresh, nullptr, s)
+                                       : solve_blocked(c, g->A, g->n, gamma, flags, D, &fresh, nullptr, s);
+    if (!st && !fresh) st = fail(RDIST_E_STATE, "re-inversion kept no graph");
+    if (!st) {
+        std::swap(g->Y, fresh->Y);
+        std::swap(g->ld, fresh->ld);
+        std::swap(g->ybytes, fresh->ybytes);
+        g->bytes = g->ybytes + g->aux_bytes + g->beta_bytes;
+        fresh->bytes = fresh->ybytes + fresh->aux_bytes + fresh->beta_bytes;
+        hipError_t e = hipMemcpyAsync(g->ginfo, fresh->ginfo, sizeof(rdist_info), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(out, fresh->ginfo, sizeof(rdist_info), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) {
+            rd::launch_beta_fill(g->beta, g->n, g->ginfo, s);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(RDIST_E_HIP, std::string("re-inversion: ") + hipGetErrorString(e));
+        release_graph_locked(fresh);   // frees the old Y
+    }
+    if (tmp) dfree(c, tmp, db);
+    return st;
+}
+
+rdist_status rdist_graph_update_edge(rdist_ctx c, rdist_graph g, int32_t src, int32_t dst, int32_t weight,
+                                     int16_t *D_dev, rdist_info *info, void *stream) {
+    if (!c || !g) return fail(RDIST_E_ARG, "NULL handle");
+    if (g->ctx != c) return fail(RDIST_E_STATE, "graph belongs to another context");
+    if (src < 0 || src >= g->n || dst < 0 || dst >= g->n || src == dst)
+        return fail(RDIST_E_ARG, "src and dst must be distinct nodes of the graph");
+    if (weight < 0 || weight > (g->weighted ? 255 : 1))
+        return fail(RDIST_E_ARG, g->weighted ? "weight must lie in [0, 255]" : "weight must be 0 or 1");
+    Guard gd(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int n = g->n;
+    rdist_status st;
+    if (!g->beta) {
+        const size_t bb = (size_t)n * n * 2;
+        if ((st = dalloc(c, (void **)&g->beta, bb))) return st;
+        g->beta_bytes = bb;
+        g->bytes += bb;
+        rd::launch_beta_fill(g->beta, n, g->ginfo, s);
+    }
+    rdist_info *ci = reinterpret_cast<rdist_info *>(g->sm + 2);
+    rd::launch_edge_prep(g->Y, g->ld, n, g->A, g->outdeg, g->beta, g->ginfo, g->sm, src, dst, weight, s);
+    {
+        const double n2 = (double)n * n;
+        Timer t(c, s, RDIST_K_EDGE_UPDATE, 2.0 * n2, (D_dev ? 22.0 : 20.0) * n2);
+        rd::launch_edge_apply(g->Y, g->ld, n, g->beta, g->sm, D_dev, g->A, g->outdeg, g->succ, g->ginfo, src, dst,
+                              weight, s);
+    }
+    RD_HIP(hipGetLastError());
+    rdist_info hi;
+    RD_HIP(hipMemcpyAsync(&hi, ci, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
+    RD_HIP(hipStreamSynchronize(s));
+    if (hi.status == RDIST_OK && hi.n_uncertified > 0) {
+        const int64_t lost = hi.n_uncertified;
+        if ((st = refresh_graph(c, g, hi.gamma, D_dev, &hi, s))) return st;
+        hi.n_uncertified = lost;
+        hi.fallback_fraction = 1.0;
+    }
+    if (info) *info = hi;
     return RDIST_OK;
 }
 

@@ -128,6 +128,15 @@ int path_task_blocks(int n);
 // Bitmaps then paths of every task (tasks: device copy of the table).
 void launch_paths_multi(const PathTask *tasks, int ntasks, int total_blocks, int total_q, hipStream_t s);
 void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s);
+// Edge changes of a kept graph (rd_dynamic.hip).
+void launch_outdeg_from_bits(const unsigned long long *bits, int n, int32_t *outdeg, hipStream_t s);
+// Q: per-entry error bounds (n x n, 16-bit -log2 in 1/256 steps); sm: the
+// update's scratch (16 + 3n doubles) holding the call's info at sm + 2.
+void launch_beta_fill(uint16_t *Q, int n, const rdist_info *ginfo, hipStream_t s);
+void launch_edge_prep(const double *Y, int ld, int n, const uint8_t *A, const int32_t *outdeg, const uint16_t *Q,
+                      const rdist_info *ginfo, double *sm, int src, int dst, int weight, hipStream_t s);
+void launch_edge_apply(double *Y, int ld, int n, uint16_t *Q, double *sm, int16_t *D, uint8_t *A, int32_t *outdeg,
+                       unsigned long long *bits, rdist_info *ginfo, int src, int dst, int weight, hipStream_t s);
 void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
                      const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s);
 

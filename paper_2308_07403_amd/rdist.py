@@ -45,7 +45,7 @@ RDIST_WEIGHTED = 0x4000
 RDIST_THREADSAFE = 0x1
 (RDIST_K_UPDATE, RDIST_K_PANEL, RDIST_K_ROWCOL, RDIST_K_INGEST, RDIST_K_EPILOGUE, RDIST_K_SMALL,
  RDIST_K_BATCHED, RDIST_K_NEXTHOP, RDIST_K_CERTIFY, RDIST_K_UPDATE_EDGE, RDIST_K_MIXED_GEMM, RDIST_K_REFINE,
- RDIST_K_COUNT) = range(13)
+ RDIST_K_EDGE_UPDATE, RDIST_K_COUNT) = range(14)
 
 def RDIST_TIMING_CLASS(k: int) -> int:
     return 2 << k
@@ -115,6 +115,8 @@ _lib.rdist_graph_release.argtypes = [_P]
 _lib.rdist_graph_release.restype = None
 _lib.rdist_graph_y.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
 _lib.rdist_graph_y.restype = ctypes.c_int
+_lib.rdist_graph_update_edge.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
+_lib.rdist_graph_update_edge.restype = ctypes.c_int
 _lib.rdist_epilogue.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P, _P, _P]
 _lib.rdist_epilogue.restype = ctypes.c_int
 _lib.rdist_set_timing.argtypes = [_P, ctypes.c_int]
@@ -147,6 +149,7 @@ rdist_solve_batched = _lib.rdist_solve_batched
 rdist_next_hop = _lib.rdist_next_hop
 rdist_graph_release = _lib.rdist_graph_release
 rdist_graph_y = _lib.rdist_graph_y
+rdist_graph_update_edge = _lib.rdist_graph_update_edge
 rdist_epilogue = _lib.rdist_epilogue
 rdist_set_timing = _lib.rdist_set_timing
 rdist_kernel_stats_get = _lib.rdist_kernel_stats_get
@@ -160,7 +163,7 @@ rdist_server_stats_get = _lib.rdist_server_stats_get
 rdist_server_destroy = _lib.rdist_server_destroy
 
 EXPORTS = ("rdist_create", "rdist_destroy", "rdist_solve", "rdist_solve_batched", "rdist_next_hop",
-           "rdist_graph_release", "rdist_graph_y", "rdist_epilogue", "rdist_set_timing",
+           "rdist_graph_release", "rdist_graph_y", "rdist_graph_update_edge", "rdist_epilogue", "rdist_set_timing",
            "rdist_kernel_stats_get", "rdist_hbm_in_use", "rdist_last_error", "rdist_status_string",
            "rdist_server_create", "rdist_server_submit", "rdist_server_poll", "rdist_server_stats_get",
            "rdist_server_destroy")
@@ -207,6 +210,19 @@ class Graph:
     ctx: "Context"
     handle: int
     n: int
+
+    def update_edge(self, src: int, dst: int, weight: int, D: torch.Tensor | None = None, stream=None,
+                    info: "PinnedInfo | None" = None) -> dict:
+        """Sets the weight of edge src -> dst (0 removes it) by a rank-1 update of Y;
+        D (optional, n x n int16) receives the new D.  Returns the call's info."""
+        info = info or PinnedInfo(1)
+        if D is not None:
+            assert D.is_cuda and D.dtype == torch.int16 and D.numel() == self.n * self.n
+        _check(rdist_graph_update_edge(self.ctx.handle, self.handle, int(src), int(dst), int(weight),
+                                       D.data_ptr() if D is not None else None, info.at(0), _stream_ptr(stream)),
+               "rdist_graph_update_edge")
+        (stream or torch.cuda.current_stream()).synchronize()
+        return info.get(0).as_dict()
 
     def y(self) -> torch.Tensor:
         """Copy of Y (n x n float64) on the device."""

@@ -1,0 +1,284 @@
+"""GPU parity of edge changes on a kept graph (rank-one update of Y) against
+the oracle's inversion of the changed graph at the same gain.
+
+Bars: D bit-exact, except entries whose oracle R - eta lies within 1e-10 of
+an integer (the readout's own ambiguity band), which may differ by one; Y
+within 2^-20 relative (the largest error bound an update keeps before it
+re-inverts; in practice far smaller, printed), zeros exactly where the
+oracle has zeros.  Sampled columns at n = 8192 come from the oracle's series
+for one column, or from closed forms.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2308_07403_amd import rdist as R  # noqa: E402
+
+DBL_MIN = np.finfo(np.float64).tiny
+Y_TOL = 2.0 ** -20
+AMBIG = 1e-10
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def dev(A):
+    return torch.from_numpy(np.ascontiguousarray(A)).cuda()
+
+
+def near_boundary(Yo, gamma):
+    """Entries whose oracle R - eta lies within AMBIG of an integer."""
+    with np.errstate(divide="ignore"):
+        t = np.log(np.where(Yo > 0, Yo, 1.0)) / np.log(gamma) - oracle.ETA
+    return (Yo > 0) & (np.abs(t - np.rint(t)) < AMBIG)
+
+
+def check_d(Dg, Do, Yo, gamma, label):
+    bad = Dg != Do
+    if not bad.any():
+        return
+    amb = near_boundary(Yo, gamma)
+    hard = bad & ~amb
+    assert not hard.any(), (label, int(hard.sum()), np.argwhere(hard)[:5].tolist())
+    assert np.all(np.abs(Dg[bad].astype(np.int32) - Do[bad].astype(np.int32)) == 1), label
+
+
+def check_y(Yg, Yo, label):
+    assert np.array_equal(Yg == 0.0, Yo == 0.0), label
+    nz = Yo >= DBL_MIN
+    rel = np.abs(Yg[nz] - Yo[nz]) / Yo[nz] if nz.any() else np.zeros(1)
+    assert rel.max() <= Y_TOL, (label, rel.max())
+    return float(rel.max())
+
+
+def check_full(ctx, g, A, gamma, D, info, weighted, label):
+    sol = (oracle.solve_weighted if weighted else oracle.solve)(A, gamma)
+    assert sol.status == oracle.OK
+    assert info["status"] == 0, (label, info)
+    assert info["delta"] == sol.delta, (label, info["delta"], sol.delta)
+    assert info["gamma"] == gamma
+    Dg = D.cpu().numpy()
+    check_d(Dg, sol.D, sol.Y, gamma, label)
+    assert info["n_unreachable"] == sol.unreachable, label
+    rel = check_y(g.y().cpu().numpy(), sol.Y, label)
+    note(f"[update] {label}: ok, Y max rel {rel:.2e}, lost {info['n_uncertified']}, "
+         f"re-inverted {info['fallback_fraction'] == 1.0}")
+    return sol
+
+
+def pick_change(rng, A, delta_cap, weighted):
+    """A removal, an addition (keeping every out-degree <= delta_cap) or, on
+    weighted graphs, a re-weighting; returns (src, dst, weight)."""
+    n = A.shape[0]
+    outdeg = (A != 0).sum(axis=0)
+    kind = rng.integers(0, 3 if weighted else 2)
+    if kind == 0:                                   # remove an edge
+        dst, src = map(int, np.argwhere(A != 0)[rng.integers(0, int((A != 0).sum()))])
+        return src, dst, 0
+    if kind == 2:                                   # re-weight an edge
+        dst, src = map(int, np.argwhere(A != 0)[rng.integers(0, int((A != 0).sum()))])
+        return src, dst, int(rng.integers(1, 31))
+    while True:                                     # add an edge
+        src, dst = map(int, rng.integers(0, n, size=2))
+        if src != dst and A[dst, src] == 0 and outdeg[src] < delta_cap:
+            return src, dst, int(rng.integers(1, 31)) if weighted else 1
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_change_sequence(ctx, weighted):
+    """Sixteen changes on a kept n = 600 graph, D and Y against the oracle's
+    inversion of each changed graph."""
+    rng = gg.rng_for("update", 600 + weighted)
+    n = 600
+    A = gg.erdos_renyi(n, 0.02, rng)
+    if weighted:
+        A = gg.weighted(A, rng, 1, 30)
+    flags = R.RDIST_WEIGHTED if weighted else 0
+    D, info, g = ctx.solve(dev(A), -0.5, flags=flags, keep=True)
+    assert info["status"] == 0
+    gamma = info["gamma"]
+    delta0 = info["delta"]
+    for step in range(16):
+        src, dst, w = pick_change(rng, A, delta0, weighted)
+        note(f"[update] weighted={weighted} step {step}: {src} -> {dst} weight {w}")
+        inf = g.update_edge(src, dst, w, D=D)
+        A[dst, src] = w
+        if step % 4 == 3 or inf["fallback_fraction"] == 1.0:
+            check_full(ctx, g, A, gamma, D, inf, weighted, f"step {step}")
+        else:
+            assert inf["status"] == 0
+    g.release()
+
+
+def test_removal_that_disconnects_reinverts(ctx):
+    """Cutting a directed path: the entries it disconnects cancel to their
+    rounding residue, so the call re-inverts; adding the edge back is exact."""
+    n = 200
+    A = gg.directed_path(n)
+    D, info, g = ctx.solve(dev(A), 0.5, keep=True)
+    inf = g.update_edge(99, 100, 0, D=D)     # edge 99 -> 100 is A[100, 99]
+    A[100, 99] = 0
+    assert inf["n_uncertified"] > 0 and inf["fallback_fraction"] == 1.0
+    sol = check_full(ctx, g, A, 0.5, D, inf, False, "cut path")
+    assert sol.unreachable == n * n - 2 * (100 * 101 // 2)
+    inf = g.update_edge(99, 100, 1, D=D)
+    A[100, 99] = 1
+    assert inf["n_uncertified"] == 0 and inf["fallback_fraction"] == 0.0
+    check_full(ctx, g, A, 0.5, D, inf, False, "path restored")
+    i, j = np.indices(A.shape)
+    Dh = D.cpu().numpy()
+    assert np.array_equal(Dh[i >= j], (i - j)[i >= j])
+    g.release()
+
+
+def test_refused_change_leaves_graph(ctx):
+    """A change that breaks the gate gamma * Delta' < 1 is refused and leaves
+    Y, D and the graph as they were; the next change applies."""
+    n = 50
+    A = gg.directed_cycle(n)
+    D, info, g = ctx.solve(dev(A), 0.6, keep=True)
+    Y0 = g.y().cpu().numpy()
+    D0 = D.cpu().numpy().copy()
+    inf = g.update_edge(3, 10, 1, D=D)          # node 3 would get 2 out-edges: 1.2 >= 1
+    assert inf["status"] == R.RDIST_E_NOT_DD and inf["delta"] == 1
+    assert np.array_equal(g.y().cpu().numpy(), Y0)
+    assert np.array_equal(D.cpu().numpy(), D0)
+    inf = g.update_edge(3, 4, 0, D=D)           # cut the cycle: a path
+    A[4, 3] = 0
+    check_full(ctx, g, A, 0.6, D, inf, False, "cycle cut")
+    inf = g.update_edge(3, 10, 1, D=D)          # node 3 has no out-edge now
+    A[10, 3] = 1
+    check_full(ctx, g, A, 0.6, D, inf, False, "chord")
+    g.release()
+
+
+def test_next_hop_follows_changes(ctx):
+    from test_gpu_parity import check_paths
+    rng = gg.rng_for("update", 300)
+    n = 300
+    A = gg.erdos_renyi(n, 0.03, rng)
+    D, info, g = ctx.solve(dev(A), -0.5, keep=True)
+    gamma = info["gamma"]
+    for _ in range(6):
+        src, dst, w = pick_change(rng, A, info["delta"], False)
+        g.update_edge(src, dst, w)
+        A[dst, src] = w
+    sol = oracle.solve(A, gamma)
+    pairs = rng.integers(0, n, size=(64, 2)).astype(np.int32)
+    out = ctx.next_hop(g, torch.from_numpy(pairs[:, 0].copy()), torch.from_numpy(pairs[:, 1].copy()),
+                       max_hops=n).cpu().numpy()
+    check_paths(A, sol.Y, pairs, out, n)
+    g.release()
+
+
+def test_noop_and_bad_arguments(ctx):
+    rng = gg.rng_for("update", 77)
+    A = gg.erdos_renyi(150, 0.05, rng)
+    D, info, g = ctx.solve(dev(A), -0.5, keep=True)
+    Y0 = g.y().cpu().numpy()
+    D0 = D.cpu().numpy().copy()
+    dst, src = map(int, np.argwhere(A != 0)[0])
+    inf = g.update_edge(src, dst, 1, D=D)        # weight unchanged: f = 0
+    assert inf["status"] == 0 and inf["n_uncertified"] == 0
+    assert np.array_equal(g.y().cpu().numpy(), Y0)
+    assert np.array_equal(D.cpu().numpy(), D0)
+    for a in [(src, src, 1), (-1, 3, 1), (3, 150, 1), (src, dst, 2), (src, dst, -1)]:
+        with pytest.raises(R.RdistError):
+            g.update_edge(*a)
+    g.release()
+    W = gg.weighted(gg.erdos_renyi(100, 0.05, rng), rng, 1, 30)
+    _, _, gw = ctx.solve(dev(W), -0.5, flags=R.RDIST_WEIGHTED, keep=True)
+    with pytest.raises(R.RdistError):
+        gw.update_edge(1, 2, 256)
+    gw.release()
+
+
+# ---------------------------------------------------------------------------
+# Full size (n = 8192), sampled
+# ---------------------------------------------------------------------------
+
+def test_full_size_path_chord_closed_form(ctx):
+    """A chord a -> b on a directed path of 8192 nodes, then its removal.
+    With the chord, Y[i, j] = gamma^(i-j) + gamma^((i-j) - (b-a) + 1) for
+    j <= a, b <= i, gamma^(i-j) elsewhere below the diagonal, 0 above."""
+    n, gamma, a, b = 8192, 0.45, 1000, 1040
+    A = gg.directed_path(n)
+    D, info, g = ctx.solve(dev(A), gamma, keep=True)
+    assert info["status"] == 0
+    inf = g.update_edge(a, b, 1, D=D)
+    assert inf["status"] == 0 and inf["delta"] == 2
+    Y = g.y()
+    i = np.arange(n)
+
+    def expect(j, chord):
+        d = np.maximum(i - j, 0).astype(np.float64)
+        exact = np.where(i >= j, gamma ** d, 0.0)        # underflows to 0 far down the path
+        if chord:
+            via = (j <= a) & (i >= b)
+            exact[via] += gamma ** (d[via] - (b - a) + 1)
+        Do = np.full(n, R.RDIST_UNREACHABLE, dtype=np.int16)
+        Do[exact > 0] = oracle.readout_entries(exact[exact > 0], gamma)
+        return exact, Do
+
+    for j in (0, 500, 999, 1000, 1001, 1039, 5000, 8191):
+        exact, Do = expect(j, True)
+        check_y(Y[:, j].cpu().numpy()[None, :], exact[None, :], f"chord column {j}")
+        check_d(D[:, j].cpu().numpy(), Do, exact, gamma, f"chord column {j}")
+    del Y
+    inf = g.update_edge(a, b, 0, D=D)           # cancels: re-inverted
+    assert inf["status"] == 0 and inf["fallback_fraction"] == 1.0 and inf["n_uncertified"] > 0
+    Y = g.y()
+    for j in (0, 999, 1000, 1040, 8191):
+        exact, Do = expect(j, False)
+        check_y(Y[:, j].cpu().numpy()[None, :], exact[None, :], f"path column {j}")
+        check_d(D[:, j].cpu().numpy(), Do, exact, gamma, f"path column {j}")
+    del Y
+    g.release()
+
+
+def test_full_size_er_sampled_columns(ctx):
+    """Changes on ER(8192, 0.02) at gamma = 0.5 / Delta, the size and launch
+    the benchmark times: sampled columns against the oracle's series."""
+    rng = gg.rng_for("update", 8192)
+    n = 8192
+    A = gg.erdos_renyi(n, 0.02, rng)
+    D, info, g = ctx.solve(dev(A), -0.5, keep=True)
+    assert info["status"] == 0
+    gamma = info["gamma"]
+    changes = []
+    for _ in range(4):
+        src, dst, w = pick_change(rng, A, info["delta"], False)
+        inf = g.update_edge(src, dst, w, D=D)
+        assert inf["status"] == 0
+        A[dst, src] = w
+        changes.append((src, dst, w, inf["n_uncertified"], inf["fallback_fraction"]))
+    note(f"[update] n=8192 changes {changes}")
+    Y = g.y()
+    cols = sorted({c[0] for c in changes} | {c[1] for c in changes} | {0, 4095, 8191})
+    for j in cols:
+        yo = oracle.y_column(A, gamma, j)
+        check_y(Y[:, j].cpu().numpy()[None, :], yo[None, :], f"column {j}")
+        Do = np.full(n, R.RDIST_UNREACHABLE, dtype=np.int16)
+        Do[yo > 0] = oracle.readout_entries(yo[yo > 0], gamma)
+        check_d(D[:, j].cpu().numpy(), Do, yo, gamma, f"column {j}")
+    del Y
+    g.release()

@@ -589,3 +589,31 @@ def test_weighted_greedy_reaches_goal(seed):
         ys = [sol.Y[goal, h] for h in hops]
         assert all(b > a for a, b in zip(ys, ys[1:]))
         assert all(W[b, a] != 0 for a, b in zip(hops, hops[1:]))
+
+
+def test_rank_one_edge_change_identity():
+    """An edge change src -> dst alters entry (dst, src) of X; Y of the changed
+    graph is Y + f Y[:, dst] Y[src, :] with f = delta / (1 - delta Y[src, dst])
+    (Sherman-Morrison on M' = M - delta e_dst e_src^T), checked against the
+    oracle's inversion of the changed graph, for an addition, a removal and a
+    weight change."""
+    rng = gg.rng_for("pins", 4242)
+    A = gg.erdos_renyi(80, 0.05, rng)
+    W = gg.weighted(A, rng, 1, 9)
+    sol = oracle.solve_weighted(W, -0.5)
+    gamma, Y = sol.gamma, sol.Y
+    dst, src = map(int, np.argwhere(W != 0)[3])
+    add_dst, add_src = map(int, np.argwhere((W == 0) & ~np.eye(80, dtype=bool))[5])
+    for s, d, w in [(src, dst, 0), (src, dst, int(W[dst, src]) % 9 + 1), (add_src, add_dst, 2)]:
+        W2 = W.copy()
+        W2[d, s] = w
+        x_old = gamma ** float(W[d, s]) if W[d, s] else 0.0
+        delta = (gamma ** float(w) if w else 0.0) - x_old
+        f = delta / (1.0 - delta * Y[s, d])
+        Y2 = Y + f * np.outer(Y[:, d], Y[s, :])
+        ref = oracle.solve_weighted(W2, gamma)
+        assert ref.status == oracle.OK
+        np.testing.assert_allclose(Y2, ref.Y, rtol=1e-9, atol=1e-15)
+        # a transposed orientation is not the changed graph's inverse
+        wrong = Y + f * np.outer(Y[:, s], Y[d, :])
+        assert np.abs(wrong - ref.Y).max() > 1e-6 * np.abs(ref.Y).max()
