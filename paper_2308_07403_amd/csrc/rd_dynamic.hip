@@ -40,7 +40,8 @@ namespace {
 constexpr double kU = 1.1102230246251565e-16;      // 2^-53
 constexpr double kBetaCap = 9.5367431640625e-07;   // 2^-20
 constexpr double kBetaFCap = 5.9604644775390625e-08;   // 2^-24: f itself too uncertain
-constexpr int kRows = 8;                          // rows per workgroup of the apply pass
+constexpr int kRows = 2;                          // rows per step of the apply pass
+constexpr int kApplyGroups = 8192;                // workgroups of the apply pass (grid-stride)
 
 // beta <= 2^(-q/256), decoded upwards (the FP32 exp2 is within an ulp or two).
 __device__ __forceinline__ float beta_decode(uint16_t q) {
@@ -91,6 +92,12 @@ __global__ __launch_bounds__(256) void k_outdeg_from_bits(const unsigned long lo
     outdeg[j] = c;
 }
 
+// hist[d] = number of nodes of out-degree d (hist zeroed beforehand, n + 1 entries).
+__global__ __launch_bounds__(256) void k_deg_hist(const int32_t *__restrict__ outdeg, int n, int32_t *__restrict__ hist) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n) atomicAdd(&hist[outdeg[j]], 1);
+}
+
 // Every entry's bound set to the starting bound of an inversion of this
 // graph (its gain and Delta from the graph's info).
 __global__ __launch_bounds__(256) void k_beta_fill(uint16_t *__restrict__ Q, size_t count,
@@ -101,29 +108,29 @@ __global__ __launch_bounds__(256) void k_beta_fill(uint16_t *__restrict__ Q, siz
     for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < count; k += (size_t)gridDim.x * 256) Q[k] = q;
 }
 
-// Gate and snapshots, one thread per node i.  Every workgroup evaluates the
-// gate on the new out-degrees itself (no grid-wide step); workgroup 0 writes
-// the call's info and f.  The graph's own adjacency, out-degrees and
-// successor bit are changed by the apply pass, after every read here.
-// sm: [0] f, [1] beta_f, [2, 11) the call's rdist_info, [15] 1 when f is too
-// uncertain to use, [16, 16 + n) Y's column dst, [16 + n, 16 + 2n) Y's row
-// src, then 2n floats: the bounds of that column and that row.
+// Gate and snapshots, one thread per node i.  The gate needs Delta' only:
+// with hist[d] = number of nodes of out-degree d, an added out-edge of src
+// (degree k -> k + 1) gives max(Delta, k + 1); a removed one (k -> k - 1)
+// lowers Delta to k - 1 only when src was the one node of degree Delta.
+// Workgroup 0 writes the call's info and f.  The graph's own adjacency,
+// out-degrees, histogram and successor bit are changed by the apply pass,
+// after every read here.
+// sm: [0] f, [1] beta_f, [2, 11) the call's rdist_info, [12] 1 / log gamma,
+// [15] 1 when f is too uncertain to use, [16, 16 + n) Y's column dst,
+// [16 + n, 16 + 2n) Y's row src, then 2n floats: the bounds of that column
+// and that row.
 __global__ __launch_bounds__(256) void k_sm_prep(const double *__restrict__ Y, int ld, int n,
                                                  const uint8_t *__restrict__ A, const int32_t *__restrict__ outdeg,
-                                                 const uint16_t *__restrict__ Q, const rdist_info *__restrict__ ginfo,
-                                                 double *__restrict__ sm, int src, int dst, int w_new) {
-    __shared__ int smax;
+                                                 const int32_t *__restrict__ hist, const uint16_t *__restrict__ Q,
+                                                 const rdist_info *__restrict__ ginfo, double *__restrict__ sm, int src,
+                                                 int dst, int w_new) {
     rdist_info *ci = reinterpret_cast<rdist_info *>(sm + 2);
     const double gamma = ginfo->gamma;
+    const int delta = ginfo->delta;
     const int w_old = A[(size_t)dst * n + src];
-    const int cnt_src = outdeg[src] + (w_new != 0) - (w_old != 0);
-    if (threadIdx.x == 0) smax = 0;
-    __syncthreads();
-    int m = 0;
-    for (int j = threadIdx.x; j < n; j += 256) m = max(m, j == src ? cnt_src : outdeg[j]);
-    atomicMax(&smax, m);
-    __syncthreads();
-    const int delta_new = smax;
+    const int k = outdeg[src];
+    const int k_new = k + (w_new != 0) - (w_old != 0);
+    const int delta_new = k_new > k ? max(delta, k_new) : (k_new < k && k == delta && hist[k] == 1 ? k_new : delta);
     // the entries of X the inversion itself would build for these weights
     const double xo = w_old ? pow(gamma, (double)w_old) : 0.0;
     const double xn = w_new ? pow(gamma, (double)w_new) : 0.0;
@@ -145,7 +152,7 @@ __global__ __launch_bounds__(256) void k_sm_prep(const double *__restrict__ Y, i
         const double bden = fabs(d) * ysd * (bd + bsd) / den + kU;
         const double bf = (bd + bden + kU) * (1.0 + 1.0 / 65536.0);
         ci->status = ginfo->status != RDIST_OK ? ginfo->status : (ok ? RDIST_OK : RDIST_E_NOT_DD);
-        ci->delta = ok ? delta_new : ginfo->delta;
+        ci->delta = ok ? delta_new : delta;
         ci->gamma = gamma;
         ci->n_unreachable = ci->n_subnormal = ci->n_saturated = 0;
         ci->n_ambiguous = ci->n_negative = 0;
@@ -153,20 +160,23 @@ __global__ __launch_bounds__(256) void k_sm_prep(const double *__restrict__ Y, i
         ci->fallback_fraction = 0.0;
         sm[0] = ok ? d / den : 0.0;
         sm[1] = bf;
+        sm[12] = rd_inv_log(gamma);
         sm[15] = (ok && !(bf <= kBetaFCap)) ? 1.0 : 0.0;
     }
 }
 
 // Y[i][j] += f c[i] r[j] with the bound update, and D[i][j] read out from
 // the new Y when D is given (counters and lost entries into the call's
-// info).  A workgroup takes kRows rows by 256 V columns: r and its bounds
-// are read once per kRows rows.  V = 4 needs n and ld multiples of 4 and
+// info).  A workgroup takes 256 V columns and steps over the rows kRows at
+// a time, grid-stride (a fixed grid of about kApplyGroups workgroups: fewer
+// per-workgroup starts and counter flushes); r and its bounds are read once.  V = 4 needs n and ld multiples of 4 and
 // D (when given) 8-byte aligned.
 template <int V>
 __global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld, int n, uint16_t *__restrict__ Q,
                                                   double *__restrict__ sm, int16_t *__restrict__ D,
                                                   uint8_t *__restrict__ A, int32_t *__restrict__ outdeg,
-                                                  unsigned long long *__restrict__ bits, rdist_info *__restrict__ ginfo,
+                                                  int32_t *__restrict__ hist, unsigned long long *__restrict__ bits,
+                                                  rdist_info *__restrict__ ginfo,
                                                   int src, int dst, int w_new) {
     rdist_info *ci = reinterpret_cast<rdist_info *>(sm + 2);
     if (ci->status != RDIST_OK) return;
@@ -174,7 +184,10 @@ __global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld
         // the graph follows the change (the prep pass has read it already)
         const int w_old = A[(size_t)dst * n + src];
         A[(size_t)dst * n + src] = (uint8_t)w_new;
-        outdeg[src] += (w_new != 0) - (w_old != 0);
+        const int k = outdeg[src], k_new = k + (w_new != 0) - (w_old != 0);
+        outdeg[src] = k_new;
+        hist[k] -= 1;
+        hist[k_new] += 1;
         unsigned long long *word = bits + (size_t)src * ((n + 63) / 64) + (dst >> 6);
         const unsigned long long bit = 1ull << (dst & 63);
         *word = w_new ? (*word | bit) : (*word & ~bit);
@@ -186,7 +199,7 @@ __global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld
     const double *__restrict__ r = sm + 16 + n;
     const float *__restrict__ bc = reinterpret_cast<const float *>(sm + 16 + 2 * (size_t)n);
     const float *__restrict__ br = bc + n;
-    const double il = rd_inv_log(ci->gamma);
+    const double il = sm[12];
     const int j0 = (blockIdx.x * 256 + threadIdx.x) * V;
     const bool active = j0 < n;
     Counts cnt;
@@ -200,8 +213,9 @@ __global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld
             brv[v] = in ? (double)br[j0 + v] : 0.0;
         }
     }
-    const int i0 = blockIdx.y * kRows;
-    for (int ii = 0; ii < kRows && active; ++ii) {
+    for (int i0 = blockIdx.y * kRows; i0 < n && active; i0 += gridDim.y * kRows)
+#pragma unroll
+    for (int ii = 0; ii < kRows; ++ii) {
         const int i = i0 + ii;
         if (i >= n) break;
         const double fc = f * c[i];
@@ -288,21 +302,30 @@ void launch_beta_fill(uint16_t *Q, int n, const rdist_info *ginfo, hipStream_t s
     hipLaunchKernelGGL(k_beta_fill, dim3(blocks), dim3(256), 0, s, Q, count, ginfo, n);
 }
 
-void launch_edge_prep(const double *Y, int ld, int n, const uint8_t *A, const int32_t *outdeg, const uint16_t *Q,
-                      const rdist_info *ginfo, double *sm, int src, int dst, int weight, hipStream_t s) {
-    hipLaunchKernelGGL(k_sm_prep, dim3((n + 255) / 256), dim3(256), 0, s, Y, ld, n, A, outdeg, Q, ginfo, sm, src,
-                       dst, weight);
+void launch_deg_hist(const int32_t *outdeg, int n, int32_t *hist, hipStream_t s) {
+    launch_fill_i32(hist, (size_t)n + 1, s);
+    hipLaunchKernelGGL(k_deg_hist, dim3((n + 255) / 256), dim3(256), 0, s, outdeg, n, hist);
+}
+
+void launch_edge_prep(const double *Y, int ld, int n, const uint8_t *A, const int32_t *outdeg, const int32_t *hist,
+                      const uint16_t *Q, const rdist_info *ginfo, double *sm, int src, int dst, int weight,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_sm_prep, dim3((n + 255) / 256), dim3(256), 0, s, Y, ld, n, A, outdeg, hist, Q, ginfo, sm,
+                       src, dst, weight);
 }
 
 void launch_edge_apply(double *Y, int ld, int n, uint16_t *Q, double *sm, int16_t *D, uint8_t *A, int32_t *outdeg,
-                       unsigned long long *bits, rdist_info *ginfo, int src, int dst, int weight, hipStream_t s) {
-    const dim3 rows((n + kRows - 1) / kRows);
-    if (n % 4 == 0 && ld % 4 == 0 && ((uintptr_t)D & 7) == 0) {
-        hipLaunchKernelGGL(k_sm_apply<4>, dim3((n / 4 + 255) / 256, rows.x), dim3(256), 0, s, Y, ld, n, Q, sm, D, A,
-                           outdeg, bits, ginfo, src, dst, weight);
+                       int32_t *hist, unsigned long long *bits, rdist_info *ginfo, int src, int dst, int weight,
+                       hipStream_t s) {
+    const bool v4 = n % 4 == 0 && ld % 4 == 0 && ((uintptr_t)D & 7) == 0;
+    const int gx = v4 ? (n / 4 + 255) / 256 : (n + 255) / 256;
+    const int gy = std::max(1, std::min((n + kRows - 1) / kRows, kApplyGroups / gx));
+    if (v4) {
+        hipLaunchKernelGGL(k_sm_apply<4>, dim3(gx, gy), dim3(256), 0, s, Y, ld, n, Q, sm, D, A, outdeg, hist, bits,
+                           ginfo, src, dst, weight);
     } else {
-        hipLaunchKernelGGL(k_sm_apply<1>, dim3((n + 255) / 256, rows.x), dim3(256), 0, s, Y, ld, n, Q, sm, D, A,
-                           outdeg, bits, ginfo, src, dst, weight);
+        hipLaunchKernelGGL(k_sm_apply<1>, dim3(gx, gy), dim3(256), 0, s, Y, ld, n, Q, sm, D, A, outdeg, hist, bits,
+                           ginfo, src, dst, weight);
     }
 }
 

@@ -95,7 +95,9 @@ struct rdist_graph_s {
     int32_t *outdeg = nullptr;
     rdist_info *ginfo = nullptr;
     double *sm = nullptr;
-    uint16_t *beta = nullptr;             // per-entry error bounds, made by the first change
+    uint16_t *beta = nullptr;             // per-entry error bounds, made by the first change,
+    int32_t *hist = nullptr;              // and in the same allocation the out-degree histogram
+    rdist_info *hinfo = nullptr;          // pinned host copy of a change's info
     int weighted = 0;
     void *aux = nullptr;                  // one allocation holding succ .. sm
     size_t ybytes = 0, aux_bytes = 0, beta_bytes = 0;

@@ -211,6 +211,7 @@ void release_graph_locked(rdist_graph g) {
     (void)hipFree(g->Y);
     (void)hipFree(g->aux);
     if (g->beta) (void)hipFree(g->beta);
+    if (g->hinfo) (void)hipHostFree(g->hinfo);
     c->in_use -= std::min(g->bytes, c->in_use);
     c->graphs.erase(g);
     delete g;
@@ -593,25 +594,29 @@ rdist_status rdist_graph_update_edge(rdist_ctx c, rdist_graph g, int32_t src, in
     hipStream_t s = (hipStream_t)stream;
     const int n = g->n;
     rdist_status st;
+    if (!g->hinfo) RD_HIP(hipHostMalloc((void **)&g->hinfo, sizeof(rdist_info), hipHostMallocDefault));
     if (!g->beta) {
-        const size_t bb = (size_t)n * n * 2;
+        const size_t qb = ((size_t)n * n * 2 + 255) & ~(size_t)255;
+        const size_t bb = qb + (size_t)(n + 1) * 4;
         if ((st = dalloc(c, (void **)&g->beta, bb))) return st;
+        g->hist = (int32_t *)((char *)g->beta + qb);
         g->beta_bytes = bb;
         g->bytes += bb;
         rd::launch_beta_fill(g->beta, n, g->ginfo, s);
+        rd::launch_deg_hist(g->outdeg, n, g->hist, s);
     }
     rdist_info *ci = reinterpret_cast<rdist_info *>(g->sm + 2);
-    rd::launch_edge_prep(g->Y, g->ld, n, g->A, g->outdeg, g->beta, g->ginfo, g->sm, src, dst, weight, s);
+    rd::launch_edge_prep(g->Y, g->ld, n, g->A, g->outdeg, g->hist, g->beta, g->ginfo, g->sm, src, dst, weight, s);
     {
         const double n2 = (double)n * n;
         Timer t(c, s, RDIST_K_EDGE_UPDATE, 2.0 * n2, (D_dev ? 22.0 : 20.0) * n2);
-        rd::launch_edge_apply(g->Y, g->ld, n, g->beta, g->sm, D_dev, g->A, g->outdeg, g->succ, g->ginfo, src, dst,
-                              weight, s);
+        rd::launch_edge_apply(g->Y, g->ld, n, g->beta, g->sm, D_dev, g->A, g->outdeg, g->hist, g->succ, g->ginfo,
+                              src, dst, weight, s);
     }
     RD_HIP(hipGetLastError());
-    rdist_info hi;
-    RD_HIP(hipMemcpyAsync(&hi, ci, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
+    RD_HIP(hipMemcpyAsync(g->hinfo, ci, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
     RD_HIP(hipStreamSynchronize(s));
+    rdist_info hi = *g->hinfo;
     if (hi.status == RDIST_OK && hi.n_uncertified > 0) {
         const int64_t lost = hi.n_uncertified;
         if ((st = refresh_graph(c, g, hi.gamma, D_dev, &hi, s))) return st;

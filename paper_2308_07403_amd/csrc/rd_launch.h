@@ -132,11 +132,15 @@ void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipSt
 void launch_outdeg_from_bits(const unsigned long long *bits, int n, int32_t *outdeg, hipStream_t s);
 // Q: per-entry error bounds (n x n, 16-bit -log2 in 1/256 steps); sm: the
 // update's scratch (16 + 3n doubles) holding the call's info at sm + 2.
+// hist: n + 1 counts of nodes per out-degree.
 void launch_beta_fill(uint16_t *Q, int n, const rdist_info *ginfo, hipStream_t s);
-void launch_edge_prep(const double *Y, int ld, int n, const uint8_t *A, const int32_t *outdeg, const uint16_t *Q,
-                      const rdist_info *ginfo, double *sm, int src, int dst, int weight, hipStream_t s);
+void launch_deg_hist(const int32_t *outdeg, int n, int32_t *hist, hipStream_t s);
+void launch_edge_prep(const double *Y, int ld, int n, const uint8_t *A, const int32_t *outdeg, const int32_t *hist,
+                      const uint16_t *Q, const rdist_info *ginfo, double *sm, int src, int dst, int weight,
+                      hipStream_t s);
 void launch_edge_apply(double *Y, int ld, int n, uint16_t *Q, double *sm, int16_t *D, uint8_t *A, int32_t *outdeg,
-                       unsigned long long *bits, rdist_info *ginfo, int src, int dst, int weight, hipStream_t s);
+                       int32_t *hist, unsigned long long *bits, rdist_info *ginfo, int src, int dst, int weight,
+                       hipStream_t s);
 void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
                      const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s);
 

@@ -211,18 +211,18 @@ class Graph:
     handle: int
     n: int
 
-    def update_edge(self, src: int, dst: int, weight: int, D: torch.Tensor | None = None, stream=None,
-                    info: "PinnedInfo | None" = None) -> dict:
-        """Sets the weight of edge src -> dst (0 removes it) by a rank-1 update of Y;
-        D (optional, n x n int16) receives the new D.  Returns the call's info."""
-        info = info or PinnedInfo(1)
+    def update_edge(self, src: int, dst: int, weight: int, D: torch.Tensor | None = None, stream=None) -> dict:
+        """Sets the weight of edge src -> dst (0 removes it) by a rank-one update of Y;
+        D (optional, n x n int16) receives the new D.  Blocks until the change is
+        complete; returns the call's info."""
         if D is not None:
             assert D.is_cuda and D.dtype == torch.int16 and D.numel() == self.n * self.n
+        out = rdist_info()
         _check(rdist_graph_update_edge(self.ctx.handle, self.handle, int(src), int(dst), int(weight),
-                                       D.data_ptr() if D is not None else None, info.at(0), _stream_ptr(stream)),
+                                       D.data_ptr() if D is not None else None, ctypes.byref(out),
+                                       _stream_ptr(stream)),
                "rdist_graph_update_edge")
-        (stream or torch.cuda.current_stream()).synchronize()
-        return info.get(0).as_dict()
+        return out.as_dict()
 
     def y(self) -> torch.Tensor:
         """Copy of Y (n x n float64) on the device."""

@@ -171,6 +171,41 @@ def test_refused_change_leaves_graph(ctx):
     g.release()
 
 
+def test_delta_follows_changes(ctx):
+    """Delta' after each change (the gate's input) is the changed graph's
+    largest out-degree: removals from the single node of largest degree
+    lower it, removals elsewhere and additions below it keep it, an
+    addition above it raises it."""
+    rng = gg.rng_for("update", 201)
+    n = 200
+    A = gg.erdos_renyi(n, 0.03, rng)
+    hub = 7
+    free = [i for i in range(n) if i != hub and not A[i, hub]]
+    A[free[:20], hub] = 1                      # node 7: the one node of largest out-degree
+    D, info, g = ctx.solve(dev(A), 0.02, keep=True)
+    assert info["status"] == 0 and info["delta"] == int(A.sum(axis=0).max())
+    outs = list(np.nonzero(A[:, hub])[0])
+    for step in range(12):
+        if step % 3 == 2:                      # an addition at a low-degree node
+            src = int(np.argmin(A.sum(axis=0)))
+            dst = next(i for i in range(n) if i != src and not A[i, src])
+            w = 1
+        else:                                   # a removal from the hub
+            src, dst, w = hub, int(outs.pop()), 0
+        inf = g.update_edge(src, dst, w, D=D)
+        A[dst, src] = w
+        assert inf["status"] == 0
+        assert inf["delta"] == int(A.sum(axis=0).max()), (step, inf["delta"], int(A.sum(axis=0).max()))
+    src = int(np.argmin(A.sum(axis=0)))
+    top = int(A.sum(axis=0).max())
+    for dst in [i for i in range(n) if i != src and not A[i, src]][: top + 1 - int(A[:, src].sum())]:
+        inf = g.update_edge(src, dst, 1, D=D)
+        A[dst, src] = 1
+    assert inf["delta"] == top + 1 == int(A.sum(axis=0).max())
+    check_full(ctx, g, A, 0.02, D, inf, False, "degree changes")
+    g.release()
+
+
 def test_next_hop_follows_changes(ctx):
     from test_gpu_parity import check_paths
     rng = gg.rng_for("update", 300)
