@@ -11,7 +11,7 @@ Prints ONE JSON line: graphs/s (whole job), ms per step, effective TFLOP/s
 trailing-update kernel, timed with HIP events on its launch stream inside
 the library), and the CPU oracle timed on a bounded sample of the same solve.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5|f1|f3]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5|f1|f3|f4]
 """
 from __future__ import annotations
 
@@ -628,6 +628,94 @@ def bench_f3(args, torch, R, gg):
     return out
 
 
+ROWS_SOURCES = ["paper_2308_07403_amd/csrc/rd_rows.hip", "paper_2308_07403_amd/csrc/rd_device.h"]
+
+
+def bench_f4(args, torch, R, gg):
+    """Goal rows without an inversion (the network's fixed point, Sec. 2): a
+    1024 x 1024 lattice with 10% of its directed edges deleted (n = 1048576,
+    successor lists), gamma = 0.5/Delta; one step = the rows (and D rows) of
+    64 random goals.  Beside it: 64 goal rows of the C2 graph against one
+    full C2 solve."""
+    import oracle
+    n = 1024 * 1024
+    rng = gg.rng_for("f4", 0)
+    ptr_np, idx_np = gg.grid_lattice_csr(n, rng)
+    ptr, idx = torch.from_numpy(ptr_np).cuda(), torch.from_numpy(idx_np).cuda()
+    goal_sets = [torch.from_numpy(rng.integers(0, n, size=64).astype(np.int32)) for _ in range(args.warmup + args.steps)]
+    ctx = R.Context(0)
+    for k in range(args.warmup):
+        ctx.goal_rows(ptr, idx, goal_sets[k], -0.5)
+    torch.cuda.synchronize()
+    ctx.set_timing(True, classes=[R.RDIST_K_ROWS_STEP])
+    steps_run = []
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        Y, D, info, steps = ctx.goal_rows(ptr, idx, goal_sets[k], -0.5)
+        steps_run.append(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.kernel_stats(R.RDIST_K_ROWS_STEP)
+    ctx.set_timing(False)
+    assert info["status"] == 0, info
+    gamma, delta = info["gamma"], info["delta"]
+    del Y, D
+    # the C2 graph: 64 goal rows against the full solve
+    A_np = gg.erdos_renyi(8192, 0.02, gg.rng_for("f4", 1))
+    p2, i2, _ = gg.csr_from_dense(A_np)
+    p2t, i2t = torch.from_numpy(p2).cuda(), torch.from_numpy(i2).cuda()
+    g2 = torch.from_numpy(np.arange(0, 8192, 128, dtype=np.int32))
+    ctx.goal_rows(p2t, i2t, g2, -0.5)
+    reps = 5
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        _, _, inf2, steps2 = ctx.goal_rows(p2t, i2t, g2, -0.5)
+    torch.cuda.synchronize()
+    c2_rows_ms = (time.perf_counter() - t1) * 1e3 / reps
+    A2 = torch.from_numpy(A_np).cuda()
+    D2 = torch.empty((8192, 8192), dtype=torch.int16, device="cuda")
+    ctx.solve_async(A2, -0.5, 0, D2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ctx.solve_async(A2, -0.5, 0, D2)
+    torch.cuda.synchronize()
+    c2_solve_ms = (time.perf_counter() - t1) * 1e3 / reps
+    ctx.close()
+    q = 64
+    nnz = int(idx_np.shape[0])
+    per_launch_bytes = 2.0 * n * q * 8 + 8.0 * (n + 1) + 4.0 * nnz
+    avg_ms = st["total_ms"] / max(st["launches"], 1)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    sha = source_sha(ROWS_SOURCES)
+    out = {
+        "metric": "goal rows/s on a 1M-node lattice (no inversion)", "value": q * args.steps / wall,
+        "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "f4: 1024x1024 4-neighbour lattice, 10% of directed edges deleted (n=1048576), "
+                               "gamma=0.5/Delta, successor lists; one step = Y and D rows of 64 random goals by "
+                               "the fixed-point iteration",
+                   "n": n, "nnz": nnz, "gamma": gamma, "delta": delta, "goals_per_step": q},
+        "iterations_per_step": float(np.mean(steps_run)),
+        "roofline": {"bound": "hbm", "kernel": "k_rows_step<64, 1>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": read_traffic("k_rows_step_f4_lattice1m_pmc.md", sha), "avg_launch_ms": avg_ms,
+                     "launches": st["launches"], "bytes_per_launch": per_launch_bytes, "source_sha": sha},
+        "c2_graph": {"rows": 64, "ms": c2_rows_ms, "iterations": steps2, "full_solve_ms": c2_solve_ms},
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle series row on the lattice)")
+        t2 = time.perf_counter()
+        oracle.y_row_csr(ptr_np, idx_np, gamma, int(goal_sets[-1][0]))
+        tc = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": 1.0 / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one goal row of the same lattice by the oracle's series ({tc:.1f} s)"}
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
 def bench_c1(args, torch, R, gg):
     import oracle
     As = [torch.from_numpy(gg.c1_graph(s)).cuda() for s in range(100)]
@@ -758,7 +846,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "f1", "f3"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "f1", "f3", "f4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-concurrent", action="store_true",
                     help="C2: skip the three-stream throughput (profiling runs, one solve at a time)")
@@ -802,7 +890,7 @@ def main():
         log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
         del src, dst, scrub
     out = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
-           "f1": bench_f1, "f3": bench_f3}[args.workload](args, torch, R, gg)
+           "f1": bench_f1, "f3": bench_f3, "f4": bench_f4}[args.workload](args, torch, R, gg)
     print(json.dumps(out), flush=True)
 
 

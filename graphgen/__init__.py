@@ -409,3 +409,84 @@ def c5_requests(count: int, qps: float, stream_index: int = 0, n_lo: int = 64,
             pairs = rng.integers(0, n, size=(pairs_per_request, 2)).astype(np.int32)
         out.append(Request(rid, t, spec, query, pairs))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Successor lists (CSR) for graphs too large for a dense adjacency
+# ---------------------------------------------------------------------------
+
+def csr_from_edges(n: int, src, dst, weights=None):
+    """Successor lists from directed edges ``src[k] -> dst[k]`` (self-loops and
+    repeated edges dropped, the first weight kept): ``ptr`` (n + 1, int64),
+    ``idx`` (int32, increasing within a node) and the weights (uint8, or None)."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    w = None if weights is None else np.asarray(weights, dtype=np.uint8)[keep]
+    key = src * n + dst
+    key, first = np.unique(key, return_index=True)
+    s2, d2 = key // n, key % n
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(s2, minlength=n), out=ptr[1:])
+    return ptr, d2.astype(np.int32), (None if w is None else w[first])
+
+
+def csr_from_dense(A: np.ndarray):
+    """Successor lists of a dense adjacency (``A[i, j] != 0`` iff edge j -> i);
+    the nonzero values become the weights (uint8)."""
+    At = np.ascontiguousarray(A.T)
+    nz = At != 0
+    ptr = np.zeros(A.shape[0] + 1, dtype=np.int64)
+    np.cumsum(nz.sum(axis=1), out=ptr[1:])
+    rows, cols = np.nonzero(nz)
+    return ptr, cols.astype(np.int32), At[rows, cols].astype(np.uint8)
+
+
+def dense_from_csr(n: int, ptr, idx, weights=None) -> np.ndarray:
+    """The dense adjacency (or weight matrix) of successor lists."""
+    A = _empty(n)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(np.asarray(ptr, dtype=np.int64)))
+    A[np.asarray(idx, dtype=np.int64), src] = 1 if weights is None else np.asarray(weights, dtype=np.uint8)
+    return A
+
+
+def grid_lattice_csr(n: int, rng: np.random.Generator, p_delete: float = 0.1):
+    """``grid_lattice_deleted`` as successor lists: the same grid, the same
+    deletions for the same generator state."""
+    a = max(1, int(math.isqrt(n)))
+    w = -(-n // a)
+    ids = np.arange(n)
+    r, c = ids // w, ids % w
+    src, dst = [], []
+    for dr, dc in ((0, 1), (1, 0), (0, -1), (-1, 0)):
+        rr, cc = r + dr, c + dc
+        tgt = rr * w + cc
+        ok = (rr >= 0) & (rr < a) & (cc >= 0) & (cc < w) & (tgt < n)
+        src.append(ids[ok])
+        dst.append(tgt[ok])
+    src = np.concatenate(src)
+    dst = np.concatenate(dst)
+    keep = rng.random(src.shape[0]) >= p_delete
+    ptr, idx, _ = csr_from_edges(n, src[keep], dst[keep])
+    return ptr, idx
+
+
+def erdos_renyi_csr(n: int, mean_degree: float, rng: np.random.Generator):
+    """Sparse random directed graph with the given mean out-degree: the number
+    of edges m ~ Binomial(n (n - 1), p) with p = mean_degree / (n - 1), drawn
+    as uniform ordered pairs (self-loops redrawn, repeats dropped)."""
+    p = mean_degree / max(n - 1, 1)
+    m = int(rng.binomial(n * (n - 1), p))
+    src = rng.integers(0, n, size=m)
+    off = rng.integers(1, n, size=m)          # dst != src
+    dst = (src + off) % n
+    ptr, idx, _ = csr_from_edges(n, src, dst)
+    return ptr, idx
+
+
+def weights_for(count: int, rng: np.random.Generator, w_lo: int = 1, w_hi: int = 100) -> np.ndarray:
+    """``count`` integer edge weights, log-uniform in [w_lo, w_hi] (as ``weighted``)."""
+    w = np.exp(rng.uniform(np.log(w_lo), np.log(w_hi + 1.0), size=count)).astype(np.int64)
+    return np.clip(w, w_lo, w_hi).astype(np.uint8)
+

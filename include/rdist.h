@@ -227,6 +227,50 @@ rdist_status rdist_graph_update_edge(rdist_ctx ctx, rdist_graph g, int32_t src, 
                                      int16_t *D_dev, rdist_info *info, void *stream);
 
 /*
+ * Goal rows without an inversion (the recurrent network of Sec. 2 and its
+ * walk series, Eq. Y-series): for each of q goals g = goals[k], row k of the
+ * output is row g of Y = (I - X)^{-1}, the fixed point of
+ *   y_j = [j == g] + sum over successors i of j of x y_i,  x = gamma^w of edge j -> i
+ * (the network on the reversed edges, driven at the goal), found by
+ * iterating from y = 0 until a step changes no entry (the iterates never
+ * decrease, so this takes finitely many steps).  Row g is what the next hop
+ * toward g reads (Sec. 4.2), so greedy paths need only these rows.
+ *
+ * Graph: successor lists in CSR, on the device: the successors of node j
+ * are succ_idx[succ_ptr[j] .. succ_ptr[j+1]) (int64 offsets, int32 ids,
+ * strictly increasing, no self-loop; succ_ptr[0] = 0, succ_ptr[n] = nnz).
+ * weights (nullable, device, nnz bytes in 1..255): integer edge weights
+ * (Sec. 3.2); NULL means weight 1.  gamma: explicit in (0, 1), or < 0 for
+ * AUTO = |gamma| / Delta (Delta = the largest out-degree).  Malformed lists
+ * give info->status RDIST_E_ADJ, a failed gate RDIST_E_NOT_DD; then Y rows
+ * are 0 and D rows the sentinel.  goals (device, q ids; an id outside
+ * [0, n) gives a row of zeros).
+ *
+ * Y_dev (nullable, device, q x n doubles, row k at Y_dev + k*n) and D_dev
+ * (nullable, device, q x n int16: the readout of rdist_solve) receive the
+ * rows; steps (nullable, host) the number of iteration steps.  Needs 2 n q'
+ * doubles of workspace (q' = q rounded up to a power of two up to 64, then
+ * to a multiple of 64).  1 <= q <= 65535.  The call waits for its stream
+ * (it reads back, every 16 steps, whether the rows have settled).
+ */
+rdist_status rdist_goal_rows(rdist_ctx ctx, int32_t n, const int64_t *succ_ptr, const int32_t *succ_idx,
+                             int64_t nnz, const uint8_t *weights, double gamma, const int32_t *goals,
+                             int32_t q, double *Y_dev, int16_t *D_dev, int32_t *steps, rdist_info *info,
+                             void *stream);
+
+/*
+ * Greedy paths over goal rows (Sec. 4.2): query k walks from starts[k]
+ * toward goals[k], each hop to the successor j (CSR as above) with the
+ * largest Y_rows[k*n + j], the lowest j on exact ties; out_dev layout and
+ * ending as rdist_next_hop (q x (max_hops+1) int32).  Y_rows as written by
+ * rdist_goal_rows for the same goals (successor offsets are clamped to
+ * [0, nnz), ids outside [0, n) skipped).  Asynchronous on the stream.
+ */
+rdist_status rdist_goal_paths(rdist_ctx ctx, int32_t n, const int64_t *succ_ptr, const int32_t *succ_idx,
+                              int64_t nnz, const double *Y_rows, const int32_t *goals, const int32_t *starts, int32_t q,
+                              int32_t max_hops, int32_t *out_dev, void *stream);
+
+/*
  * Standalone readout over a caller-provided Y (the unfused form of the
  * epilogue): D[i*n + j] from Y_dev[i*ld + j] for 0 <= i, j < n with the
  * given gain (0 < gamma < 1).  info (nullable) receives the counters.
@@ -330,7 +374,8 @@ typedef struct rdist_kernel_stats {
 #define RDIST_K_MIXED_GEMM 10  /* mixed precision: FP32 row products and trailing updates */
 #define RDIST_K_REFINE 11     /* mixed precision: residual, correction product and recompute */
 #define RDIST_K_EDGE_UPDATE 12 /* rdist_graph_update_edge: the rank-1 pass over Y (and D) */
-#define RDIST_K_COUNT 13
+#define RDIST_K_ROWS_STEP 13   /* rdist_goal_rows: one iteration step */
+#define RDIST_K_COUNT 14
 
 /* Per-kernel event timing: 0 off, 1 every kernel class, or a mask of
  * RDIST_TIMING_CLASS(k) bits timing only those classes (each timed launch

@@ -77,6 +77,8 @@ def lib():
         L.orc_y_column_series.restype = i32
         L.orc_y_row_series.argtypes = [P, i32, f64, i32, f64, i32, P]
         L.orc_y_row_series.restype = i32
+        L.orc_y_row_series_csr.argtypes = [P, P, P, i32, f64, i32, f64, i32, P]
+        L.orc_y_row_series_csr.restype = i32
         _lib = L
     return _lib
 
@@ -286,6 +288,22 @@ def y_row(A, gamma: float, g: int, rel_tol: float = 1e-17, max_terms: int = 1000
     A = _adj(A)
     y = np.empty(A.shape[0], dtype=np.float64)
     k = lib().orc_y_row_series(_p(A), A.shape[0], float(gamma), int(g), float(rel_tol), int(max_terms), _p(y))
+    if k < 0:
+        raise ValueError("bad row index")
+    return y
+
+
+def y_row_csr(ptr, idx, gamma: float, g: int, weights=None, rel_tol: float = 1e-17,
+              max_terms: int = 1000000) -> np.ndarray:
+    """Row g of Y from the series, for a graph given as successor lists
+    (successors of c: idx[ptr[c]:ptr[c+1]], optional integer weights)."""
+    ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    n = ptr.shape[0] - 1
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint8)
+    y = np.empty(n, dtype=np.float64)
+    k = lib().orc_y_row_series_csr(_p(ptr), _p(idx), _p(w) if w is not None else None, n, float(gamma), int(g),
+                                   float(rel_tol), int(max_terms), _p(y))
     if k < 0:
         raise ValueError("bad row index")
     return y

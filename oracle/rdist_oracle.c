@@ -442,6 +442,57 @@ int orc_y_row_series(const uint8_t *A, int n, double gamma, int g, double rel_to
     return k;
 }
 
+/*
+ * Row g of Y for a graph given as successor lists (the same series as
+ * orc_y_row_series, Eq. Y-series, for graphs too large for a dense A):
+ * the successors of node c are idx[ptr[c] .. ptr[c+1]), w (nullable) their
+ * integer weights, so the entry of X for the edge c -> i is gamma^w (Sec. 3.2;
+ * gamma itself without weights).  Term k+1 of the row is
+ *   t2[c] = sum over successors i of c of x(c -> i) * t[i],
+ * and the terms are summed until, with the support settled, the bound
+ * |tail| <= max(t) q / (1 - q) (q = gamma * largest out-degree) is below
+ * rel_tol times the smallest positive entry, or a term vanishes.
+ * Returns the number of terms, or -1 for a bad g.
+ */
+int orc_y_row_series_csr(const int64_t *ptr, const int32_t *idx, const uint8_t *w, int n, double gamma, int g,
+                         double rel_tol, int max_terms, double *y) {
+    if (g < 0 || g >= n) return -1;
+    int64_t delta = 0;
+    for (int c = 0; c < n; ++c)
+        if (ptr[c + 1] - ptr[c] > delta) delta = ptr[c + 1] - ptr[c];
+    double *t = (double *)calloc((size_t)n, sizeof(double));
+    double *t2 = (double *)calloc((size_t)n, sizeof(double));
+    for (int i = 0; i < n; ++i) y[i] = 0.0;
+    y[g] = 1.0; t[g] = 1.0;
+    double q = gamma * (double)delta;
+    long support = 1, prev_support = 0;
+    int k;
+    for (k = 1; k <= max_terms; ++k) {
+        for (int c = 0; c < n; ++c) {
+            double acc = 0.0;
+            for (int64_t e = ptr[c]; e < ptr[c + 1]; ++e) {
+                double x = w ? pow(gamma, (double)w[e]) : gamma;
+                acc += x * t[idx[e]];
+            }
+            t2[c] = acc;
+        }
+        double ninf = 0.0, ymin = 1.0e308;
+        support = 0;
+        for (int i = 0; i < n; ++i) {
+            y[i] += t2[i];
+            if (t2[i] > ninf) ninf = t2[i];
+            if (y[i] > 0.0) { ++support; if (y[i] < ymin) ymin = y[i]; }
+        }
+        double *sw = t; t = t2; t2 = sw;
+        if (ninf == 0.0) break;
+        int settled = support == prev_support;
+        prev_support = support;
+        if (settled && q < 1.0 && ninf * q / (1.0 - q) < rel_tol * ymin) break;
+    }
+    free(t); free(t2);
+    return k;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Brute-force companions: BFS distances and shortest-path counts, and the   */
 /* Floyd-Warshall CPU baseline.                                              */

@@ -61,6 +61,9 @@ struct Workspace {
     // residual and correction slabs
     Buf m32, v32, u32, s64, p32, cert, csr_cnt, csr_off, csr_col, r32, c32;
     Buf xh, xl, rh, rl;   // bf16 hi/lo parts of the FP32 inverse and of the scaled residual
+    // goal rows: the two iteration states, and [info | bad flag | change flag | gamma^w table]
+    Buf rv, rmisc;
+    int32_t *rflag_h = nullptr;   // pinned host copy of the change flag
     double *m() const { return (double *)M.p; }
     int32_t *outdeg() const { return (int32_t *)small.p; }
     int32_t *bad() const { return outdeg() + n_cap + 1; }

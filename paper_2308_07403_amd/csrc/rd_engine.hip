@@ -406,8 +406,9 @@ void free_workspace(rdist_ctx c, Workspace &w) {
     free_transient_plan(c, w);
     for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2, &w.Pt2, &w.small,
                    &w.m32, &w.v32, &w.u32, &w.s64, &w.p32, &w.cert, &w.csr_cnt, &w.csr_off, &w.csr_col, &w.r32,
-                   &w.c32, &w.xh, &w.xl, &w.rh, &w.rl})
+                   &w.c32, &w.xh, &w.xl, &w.rh, &w.rl, &w.rv, &w.rmisc})
         release(c, *b);
+    if (w.rflag_h) (void)hipHostFree(w.rflag_h);
     for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
         if (e) (void)hipEventDestroy(e);
     if (w.aux) (void)hipStreamDestroy(w.aux);
@@ -624,6 +625,81 @@ rdist_status rdist_graph_update_edge(rdist_ctx c, rdist_graph g, int32_t src, in
         hi.fallback_fraction = 1.0;
     }
     if (info) *info = hi;
+    return RDIST_OK;
+}
+
+// Layout of the goal-rows scratch: info, bad-input flag, change flag, then
+// the 256-entry table of gamma^w.
+static constexpr size_t kRowsInfo = 0, kRowsBad = 256, kRowsFlag = 512, kRowsPow = 768;
+static constexpr size_t kRowsMisc = kRowsPow + 256 * 8;
+static constexpr int kRowsCheckEvery = 16;
+static constexpr int64_t kRowsMaxSteps = 1 << 22;
+
+rdist_status rdist_goal_rows(rdist_ctx c, int32_t n, const int64_t *succ_ptr, const int32_t *succ_idx, int64_t nnz,
+                             const uint8_t *weights, double gamma, const int32_t *goals, int32_t q, double *Y_dev,
+                             int16_t *D_dev, int32_t *steps, rdist_info *info, void *stream) {
+    if (!c) return fail(RDIST_E_ARG, "ctx is NULL");
+    if (n < 1 || q < 1 || q > 65535 || nnz < 0) return fail(RDIST_E_ARG, "need n >= 1, 1 <= q <= 65535, nnz >= 0");
+    if (!succ_ptr || !goals || (nnz > 0 && !succ_idx)) return fail(RDIST_E_ARG, "NULL graph or goal array");
+    rdist_status st;
+    if ((st = check_gamma(gamma))) return st;
+    Guard gd(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &w = c->ws[s];
+    const size_t G = (size_t)rd::rows_group(q);
+    const size_t vbytes = (size_t)n * G * (size_t)((q + G - 1) / G) * 8;
+    if ((st = ensure_grow(c, w.rv, 2 * vbytes))) return st;
+    if ((st = ensure_grow(c, w.rmisc, kRowsMisc))) return st;
+    if (!w.rflag_h) RD_HIP(hipHostMalloc((void **)&w.rflag_h, sizeof(int32_t), hipHostMallocDefault));
+    char *misc = (char *)w.rmisc.p;
+    rdist_info *dinfo = (rdist_info *)(misc + kRowsInfo);
+    int32_t *bad = (int32_t *)(misc + kRowsBad), *flag = (int32_t *)(misc + kRowsFlag);
+    double *gpow = (double *)(misc + kRowsPow);
+    double *V[2] = {(double *)w.rv.p, (double *)((char *)w.rv.p + vbytes)};
+    rd::launch_info_set(dinfo, gamma, s);
+    rd::launch_fill_i32(bad, 1, s);
+    rd::launch_rows_check(succ_ptr, succ_idx, weights, n, nnz, gamma, dinfo, bad, gpow, s);
+    rd::launch_fill_i32((int32_t *)V[0], vbytes / 4, s);
+    rd::RowsLaunch L{succ_ptr, succ_idx, weights, gpow, n, nnz, goals, q, dinfo};
+    int64_t k = 0;
+    int cur = 0;
+    for (;;) {
+        // kRowsCheckEvery steps, the last of which reports whether any entry changed
+        for (int t = 0; t < kRowsCheckEvery; ++t, ++k) {
+            const bool check = t == kRowsCheckEvery - 1;
+            if (check) rd::launch_fill_i32(flag, 1, s);
+            Timer tm(c, s, RDIST_K_ROWS_STEP, 0.0, 16.0 * (double)vbytes / 8.0 + 8.0 * n + (weights ? 5.0 : 4.0) * (double)nnz);
+            rd::launch_rows_step(L, V[cur], V[cur ^ 1], check ? flag : nullptr, s);
+            cur ^= 1;
+        }
+        RD_HIP(hipGetLastError());
+        RD_HIP(hipMemcpyAsync(w.rflag_h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        RD_HIP(hipStreamSynchronize(s));
+        if (*w.rflag_h == 0) break;
+        if (k >= kRowsMaxSteps) return fail(RDIST_E_STATE, "goal rows did not settle");
+    }
+    rd::launch_rows_out(V[cur], n, q, Y_dev, D_dev, dinfo, s);
+    RD_HIP(hipGetLastError());
+    if (steps) *steps = (int32_t)std::min<int64_t>(k, 0x7FFFFFFF);
+    return copy_info(info, dinfo, 1, s);
+}
+
+rdist_status rdist_goal_paths(rdist_ctx c, int32_t n, const int64_t *succ_ptr, const int32_t *succ_idx, int64_t nnz,
+                              const double *Y_rows, const int32_t *goals, const int32_t *starts, int32_t q,
+                              int32_t max_hops, int32_t *out_dev, void *stream) {
+    if (!c) return fail(RDIST_E_ARG, "ctx is NULL");
+    if (n < 1 || q < 0 || nnz < 0 || max_hops < 1 || max_hops > 65535) return fail(RDIST_E_ARG, "bad n, nnz, q or max_hops");
+    if (q == 0) return RDIST_OK;
+    if (!succ_ptr || (nnz > 0 && !succ_idx) || !Y_rows || !goals || !starts || !out_dev) return fail(RDIST_E_ARG, "NULL argument");
+    Guard gd(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    {
+        Timer tm(c, s, RDIST_K_NEXTHOP, 0.0, 0.0);
+        rd::launch_rows_paths(succ_ptr, succ_idx, n, nnz, Y_rows, goals, starts, q, max_hops, out_dev, s);
+    }
+    RD_HIP(hipGetLastError());
     return RDIST_OK;
 }
 

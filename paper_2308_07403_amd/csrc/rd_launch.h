@@ -141,6 +141,26 @@ void launch_edge_prep(const double *Y, int ld, int n, const uint8_t *A, const in
 void launch_edge_apply(double *Y, int ld, int n, uint16_t *Q, double *sm, int16_t *D, uint8_t *A, int32_t *outdeg,
                        int32_t *hist, unsigned long long *bits, rdist_info *ginfo, int src, int dst, int weight,
                        hipStream_t s);
+// Goal rows without an inversion (rd_rows.hip): successor lists in CSR,
+// optional per-edge weights, q goals.
+struct RowsLaunch {
+    const int64_t *ptr;
+    const int32_t *idx;
+    const uint8_t *wts;      // nullable: unit weights
+    const double *gpow;      // gamma^w table (256 entries)
+    int n;
+    int64_t nnz;
+    const int32_t *goals;
+    int q;
+    const rdist_info *info;
+};
+int rows_group(int q);   // goals per chunk: the power of two >= q, at most 64
+void launch_rows_check(const int64_t *ptr, const int32_t *idx, const uint8_t *wts, int n, int64_t nnz,
+                       double gamma, rdist_info *info, int32_t *bad, double *gpow, hipStream_t s);
+void launch_rows_step(const RowsLaunch &L, const double *Vo, double *Vn, int32_t *flag, hipStream_t s);
+void launch_rows_out(const double *V, int n, int q, double *Y, int16_t *D, rdist_info *info, hipStream_t s);
+void launch_rows_paths(const int64_t *ptr, const int32_t *idx, int n, int64_t nnz, const double *Y,
+                       const int32_t *goals, const int32_t *starts, int q, int max_hops, int32_t *out, hipStream_t s);
 void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
                      const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s);
 

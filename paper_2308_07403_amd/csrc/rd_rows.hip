@@ -1,0 +1,254 @@
+// rd_rows.hip -- goal rows of Y without an inversion.
+//
+// Row g of Y = (I - X)^{-1} is the fixed point of
+//   y_j = [j == g] + sum_{i in succ(j)} x_ij y_i        (x_ij = gamma^w of edge j -> i)
+// i.e. y^T (I - X) = e_g^T: the recurrent network of Sec. 2 run on the
+// reversed edges with the drive at the goal (each node adds its successors'
+// outputs).  The walk series (Eq. Y-series) is its Jacobi iteration from
+// y = 0: after k steps y holds every walk of length < k.  The gate
+// gamma Delta < 1 makes the step a contraction in the max norm.
+//
+// Every coefficient is non-negative and rounding is monotone, so the
+// iterates never decrease, also in floating point, and reach a floating-point
+// fixed point after finitely many steps; the iteration stops at the first
+// checked step that changes no entry.
+//
+// Layout: q goals in chunks of G (one chunk per grid row); the state of a
+// chunk is node-major, V[j][g] (G doubles per node), so a successor's values
+// for all G goals are one contiguous read.  A wavefront's 64 lanes are
+// (N nodes) x (S successor slots) x (G goals), N = 64 / (G S); the S partial
+// sums of a node are combined by lane shuffles.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rd_device.h"
+#include "rd_launch.h"
+
+namespace rd {
+
+namespace {
+
+// One block per 256 nodes: successor lists checked (ids in range, no
+// self-loop, strictly increasing, weights non-zero), out-degree maxima into
+// info->delta, bad input into *bad.
+__global__ __launch_bounds__(256) void k_rows_check(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                    const uint8_t *__restrict__ wts, int n, int64_t nnz,
+                                                    rdist_info *__restrict__ info, int32_t *__restrict__ bad) {
+    __shared__ int smax;
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    int deg = 0;
+    bool ok = true;
+    if (j < n) {
+        const int64_t e0 = ptr[j], e1 = ptr[j + 1];
+        ok = e0 >= 0 && e1 >= e0 && e1 <= nnz && (j > 0 || e0 == 0) && (j < n - 1 || e1 == nnz);
+        if (ok) {
+            deg = (int)min<int64_t>(e1 - e0, 0x7FFFFFFF);
+            int prev = -1;
+            for (int64_t e = e0; e < e1; ++e) {
+                const int i = idx[e];
+                ok = ok && i >= 0 && i < n && i != j && i > prev && (!wts || wts[e] != 0);
+                prev = i;
+            }
+        }
+        atomicMax(&smax, deg);
+    }
+    if (!ok) atomicOr(bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&info->delta, smax);
+}
+
+// Gain, gate and the table of gamma^w (weighted graphs).
+__global__ void k_rows_gate(double gamma_arg, const int32_t *__restrict__ bad, rdist_info *__restrict__ info,
+                            double *__restrict__ gpow) {
+    const int d = info->delta;
+    const double gamma = gamma_arg > 0.0 ? gamma_arg : (d > 0 ? -gamma_arg / (double)d : -gamma_arg);
+    if (threadIdx.x == 0) {
+        info->gamma = gamma;
+        info->status = *bad ? RDIST_E_ADJ : (gamma * (double)d < 1.0 ? RDIST_OK : RDIST_E_NOT_DD);
+    }
+    gpow[threadIdx.x] = threadIdx.x ? pow(gamma, (double)threadIdx.x) : 0.0;
+}
+
+// One Jacobi step for every node and goal.  flag (nullable): set when any
+// entry changed.
+template <int G, int S>
+__global__ __launch_bounds__(256) void k_rows_step(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                   const uint8_t *__restrict__ wts, const double *__restrict__ gpow,
+                                                   int n, const int32_t *__restrict__ goals, int q,
+                                                   const double *__restrict__ Vold, double *__restrict__ Vnew,
+                                                   const rdist_info *__restrict__ info, int32_t *__restrict__ flag) {
+    constexpr int N = 64 / (G * S);
+    if (info->status != RDIST_OK) return;
+    const double gamma = info->gamma;
+    const int lane = threadIdx.x & 63;
+    const int g = lane % G;
+    const int s = (lane / G) % S;
+    const int nd = lane / (G * S);
+    const int j = ((blockIdx.x * 256 + threadIdx.x) >> 6) * N + nd;
+    const size_t base = (size_t)blockIdx.y * n * G;
+    const double *__restrict__ Vo = Vold + base;
+    double acc = 0.0;
+    if (j < n) {
+        const int64_t e1 = ptr[j + 1];
+        if (wts) {
+            for (int64_t e = ptr[j] + s; e < e1; e += S) acc = fma(gpow[wts[e]], Vo[(size_t)idx[e] * G + g], acc);
+        } else {
+            for (int64_t e = ptr[j] + s; e < e1; e += S) acc += Vo[(size_t)idx[e] * G + g];
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < S; m <<= 1) acc += __shfl_xor(acc, G * m);
+    bool changed = false;
+    if (j < n && s == 0) {
+        const int k = blockIdx.y * G + g;
+        const double seed = (k < q && goals[k] == j) ? 1.0 : 0.0;
+        const double v = wts ? seed + acc : fma(gamma, acc, seed);
+        Vnew[base + (size_t)j * G + g] = v;
+        changed = v != Vo[(size_t)j * G + g];
+    }
+    if (flag && __any(changed) && lane == 0) *flag = 1;
+}
+
+// Rows out: Y[k * n + j] and the readout D[k * n + j] (either nullable);
+// status not OK: Y = 0 and D = the sentinel.
+template <int G>
+__global__ __launch_bounds__(256) void k_rows_out(const double *__restrict__ V, int n, int q, double *__restrict__ Y,
+                                                  int16_t *__restrict__ D, rdist_info *__restrict__ info) {
+    const bool ok = info->status == RDIST_OK;
+    const double il = ok ? rd_inv_log(info->gamma) : 0.0;
+    Counts cnt;
+    const int k = blockIdx.y;
+    const int c = k / G, g = k % G;
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
+        const double v = ok ? V[((size_t)c * n + j) * G + g] : 0.0;
+        if (Y) Y[(size_t)k * n + j] = v;
+        if (D) D[(size_t)k * n + j] = ok ? rd_encode(v, il, cnt) : kUnreachable;
+    }
+    if (ok && D) flush_counts(info, cnt);
+}
+
+// Greedy paths over the rows: query k walks from start[k] toward goals[k]
+// on row k, each hop to the successor with the largest row value (lowest
+// id on ties); layout and ending as rdist_next_hop.  One wavefront per query;
+// offsets are clamped to [0, nnz) and ids outside [0, n) skipped.
+__global__ __launch_bounds__(256) void k_rows_paths(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                    int n, int64_t nnz, const double *__restrict__ Y,
+                                                    const int32_t *__restrict__ goals,
+                                                    const int32_t *__restrict__ starts, int q, int max_hops,
+                                                    int32_t *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int k = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (k >= q) return;
+    int32_t *o = out + (size_t)k * (max_hops + 1);
+    const int goal = goals[k];
+    int cur = starts[k];
+    const bool valid = cur >= 0 && cur < n && goal >= 0 && goal < n;
+    if (lane == 0) o[0] = valid ? cur : -1;
+    const double *__restrict__ row = Y + (size_t)k * n;
+    for (int h = 1; h <= max_hops; ++h) {
+        if (!valid || cur < 0 || cur == goal) {
+            for (int t = h + lane; t <= max_hops; t += 64) o[t] = -1;
+            break;
+        }
+        double best = 0.0;
+        int bj = 0x7FFFFFFF;
+        const int64_t e0 = max<int64_t>(ptr[cur], 0), e1 = min<int64_t>(ptr[cur + 1], nnz);
+        for (int64_t e = e0 + lane; e < e1; e += 64) {
+            const int i = idx[e];
+            if (i < 0 || i >= n) continue;
+            const double v = row[i];
+            if (v > best || (v == best && v > 0.0 && i < bj)) { best = v; bj = i; }
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            const double ob = __shfl_xor(best, m);
+            const int oj = __shfl_xor(bj, m);
+            if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+        }
+        cur = best > 0.0 ? bj : -1;
+        if (lane == 0) o[h] = cur;
+    }
+}
+
+template <int G, int S>
+void step_gs(const RowsLaunch &L, const double *Vo, double *Vn, int32_t *flag, hipStream_t s) {
+    constexpr int N = 64 / (G * S);
+    const int waves = (L.n + N - 1) / N;
+    const dim3 grid((waves + 3) / 4, (L.q + G - 1) / G);
+    hipLaunchKernelGGL((k_rows_step<G, S>), grid, dim3(256), 0, s, L.ptr, L.idx, L.wts, L.wts ? L.gpow : nullptr,
+                       L.n, L.goals, L.q, Vo, Vn, L.info, flag);
+}
+
+template <int G>
+void step_g(int log_s, const RowsLaunch &L, const double *Vo, double *Vn, int32_t *flag, hipStream_t s) {
+    switch (log_s) {
+        case 0: step_gs<G, 1>(L, Vo, Vn, flag, s); break;
+        case 1: if constexpr (G <= 32) step_gs<G, 2>(L, Vo, Vn, flag, s); break;
+        case 2: if constexpr (G <= 16) step_gs<G, 4>(L, Vo, Vn, flag, s); break;
+        case 3: if constexpr (G <= 8) step_gs<G, 8>(L, Vo, Vn, flag, s); break;
+        case 4: if constexpr (G <= 4) step_gs<G, 16>(L, Vo, Vn, flag, s); break;
+        case 5: if constexpr (G <= 2) step_gs<G, 32>(L, Vo, Vn, flag, s); break;
+        default: if constexpr (G <= 1) step_gs<G, 64>(L, Vo, Vn, flag, s); break;
+    }
+}
+
+int ilog2(int x) {
+    int l = 0;
+    while ((1 << (l + 1)) <= x) ++l;
+    return l;
+}
+
+}  // namespace
+
+int rows_group(int q) {
+    int g = 1;
+    while (g < q && g < 64) g <<= 1;
+    return g;
+}
+
+void launch_rows_check(const int64_t *ptr, const int32_t *idx, const uint8_t *wts, int n, int64_t nnz,
+                       double gamma, rdist_info *info, int32_t *bad, double *gpow, hipStream_t s) {
+    hipLaunchKernelGGL(k_rows_check, dim3((n + 255) / 256), dim3(256), 0, s, ptr, idx, wts, n, nnz, info, bad);
+    hipLaunchKernelGGL(k_rows_gate, dim3(1), dim3(256), 0, s, gamma, bad, info, gpow);
+}
+
+void launch_rows_step(const RowsLaunch &L, const double *Vo, double *Vn, int32_t *flag, hipStream_t s) {
+    const int G = rows_group(L.q);
+    const int deg = (int)std::max<int64_t>(1, (L.nnz + L.n - 1) / std::max(L.n, 1));
+    int S = 1;
+    while (S < deg && G * S < 64) S <<= 1;
+    const int ls = ilog2(S);
+    switch (ilog2(G)) {
+        case 0: step_g<1>(ls, L, Vo, Vn, flag, s); break;
+        case 1: step_g<2>(ls, L, Vo, Vn, flag, s); break;
+        case 2: step_g<4>(ls, L, Vo, Vn, flag, s); break;
+        case 3: step_g<8>(ls, L, Vo, Vn, flag, s); break;
+        case 4: step_g<16>(ls, L, Vo, Vn, flag, s); break;
+        case 5: step_g<32>(ls, L, Vo, Vn, flag, s); break;
+        default: step_g<64>(ls, L, Vo, Vn, flag, s); break;
+    }
+}
+
+void launch_rows_out(const double *V, int n, int q, double *Y, int16_t *D, rdist_info *info, hipStream_t s) {
+    const int G = rows_group(q);
+    const dim3 grid((unsigned)std::min((n + 255) / 256, 64), (unsigned)q);
+    switch (ilog2(G)) {
+        case 0: hipLaunchKernelGGL(k_rows_out<1>, grid, dim3(256), 0, s, V, n, q, Y, D, info); break;
+        case 1: hipLaunchKernelGGL(k_rows_out<2>, grid, dim3(256), 0, s, V, n, q, Y, D, info); break;
+        case 2: hipLaunchKernelGGL(k_rows_out<4>, grid, dim3(256), 0, s, V, n, q, Y, D, info); break;
+        case 3: hipLaunchKernelGGL(k_rows_out<8>, grid, dim3(256), 0, s, V, n, q, Y, D, info); break;
+        case 4: hipLaunchKernelGGL(k_rows_out<16>, grid, dim3(256), 0, s, V, n, q, Y, D, info); break;
+        case 5: hipLaunchKernelGGL(k_rows_out<32>, grid, dim3(256), 0, s, V, n, q, Y, D, info); break;
+        default: hipLaunchKernelGGL(k_rows_out<64>, grid, dim3(256), 0, s, V, n, q, Y, D, info); break;
+    }
+}
+
+void launch_rows_paths(const int64_t *ptr, const int32_t *idx, int n, int64_t nnz, const double *Y,
+                       const int32_t *goals, const int32_t *starts, int q, int max_hops, int32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_rows_paths, dim3((q + 3) / 4), dim3(256), 0, s, ptr, idx, n, nnz, Y, goals, starts, q,
+                       max_hops, out);
+}
+
+}  // namespace rd

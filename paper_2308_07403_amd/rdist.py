@@ -45,7 +45,7 @@ RDIST_WEIGHTED = 0x4000
 RDIST_THREADSAFE = 0x1
 (RDIST_K_UPDATE, RDIST_K_PANEL, RDIST_K_ROWCOL, RDIST_K_INGEST, RDIST_K_EPILOGUE, RDIST_K_SMALL,
  RDIST_K_BATCHED, RDIST_K_NEXTHOP, RDIST_K_CERTIFY, RDIST_K_UPDATE_EDGE, RDIST_K_MIXED_GEMM, RDIST_K_REFINE,
- RDIST_K_EDGE_UPDATE, RDIST_K_COUNT) = range(14)
+ RDIST_K_EDGE_UPDATE, RDIST_K_ROWS_STEP, RDIST_K_COUNT) = range(15)
 
 def RDIST_TIMING_CLASS(k: int) -> int:
     return 2 << k
@@ -111,6 +111,12 @@ _lib.rdist_solve_batched.argtypes = [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_ui
 _lib.rdist_solve_batched.restype = ctypes.c_int
 _lib.rdist_next_hop.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]
 _lib.rdist_next_hop.restype = ctypes.c_int
+_lib.rdist_goal_rows.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.c_int64, _P, ctypes.c_double, _P, ctypes.c_int32,
+                                 _P, _P, _P, _P, _P]
+_lib.rdist_goal_rows.restype = ctypes.c_int
+_lib.rdist_goal_paths.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_int32,
+                                  ctypes.c_int32, _P, _P]
+_lib.rdist_goal_paths.restype = ctypes.c_int
 _lib.rdist_graph_release.argtypes = [_P]
 _lib.rdist_graph_release.restype = None
 _lib.rdist_graph_y.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -148,6 +154,8 @@ rdist_solve = _lib.rdist_solve
 rdist_solve_batched = _lib.rdist_solve_batched
 rdist_next_hop = _lib.rdist_next_hop
 rdist_graph_release = _lib.rdist_graph_release
+rdist_goal_rows = _lib.rdist_goal_rows
+rdist_goal_paths = _lib.rdist_goal_paths
 rdist_graph_y = _lib.rdist_graph_y
 rdist_graph_update_edge = _lib.rdist_graph_update_edge
 rdist_epilogue = _lib.rdist_epilogue
@@ -163,7 +171,8 @@ rdist_server_stats_get = _lib.rdist_server_stats_get
 rdist_server_destroy = _lib.rdist_server_destroy
 
 EXPORTS = ("rdist_create", "rdist_destroy", "rdist_solve", "rdist_solve_batched", "rdist_next_hop",
-           "rdist_graph_release", "rdist_graph_y", "rdist_graph_update_edge", "rdist_epilogue", "rdist_set_timing",
+           "rdist_graph_release", "rdist_graph_y", "rdist_graph_update_edge", "rdist_goal_rows", "rdist_goal_paths",
+           "rdist_epilogue", "rdist_set_timing",
            "rdist_kernel_stats_get", "rdist_hbm_in_use", "rdist_last_error", "rdist_status_string",
            "rdist_server_create", "rdist_server_submit", "rdist_server_poll", "rdist_server_stats_get",
            "rdist_server_destroy")
@@ -344,6 +353,42 @@ class Context:
         st = rdist_next_hop(self.handle, graph.handle, cur.data_ptr(), goal.data_ptr(), q, max_hops,
                             out.data_ptr(), _stream_ptr(stream))
         _check(st, "rdist_next_hop")
+        return out
+
+    def goal_rows(self, ptr: torch.Tensor, idx: torch.Tensor, goals: torch.Tensor, gamma: float,
+                  weights: torch.Tensor | None = None, want_y: bool = True, want_d: bool = True, stream=None):
+        """Rows Y[g, :] (and their D) for the goals of a graph given as successor lists
+        (device tensors: ptr int64 (n + 1), idx int32); returns (Y or None, D or None, info, steps)."""
+        assert ptr.is_cuda and ptr.dtype == torch.int64 and idx.is_cuda and idx.dtype == torch.int32
+        n = int(ptr.numel()) - 1
+        goals = goals.to(device=self.device, dtype=torch.int32).contiguous()
+        q = int(goals.numel())
+        Y = torch.empty((q, n), dtype=torch.float64, device=self.device) if want_y else None
+        D = torch.empty((q, n), dtype=torch.int16, device=self.device) if want_d else None
+        if weights is not None:
+            assert weights.is_cuda and weights.dtype == torch.uint8 and weights.numel() == idx.numel()
+        steps = ctypes.c_int32(0)
+        st = rdist_goal_rows(self.handle, n, ptr.data_ptr(), idx.data_ptr() if idx.numel() else None,
+                             int(idx.numel()), weights.data_ptr() if weights is not None else None, float(gamma),
+                             goals.data_ptr(), q, Y.data_ptr() if Y is not None else None,
+                             D.data_ptr() if D is not None else None, ctypes.byref(steps), self.info.at(0),
+                             _stream_ptr(stream))
+        _check(st, "rdist_goal_rows")
+        (stream or torch.cuda.current_stream()).synchronize()
+        return Y, D, self.info.get(0).as_dict(), int(steps.value)
+
+    def goal_paths(self, ptr: torch.Tensor, idx: torch.Tensor, Y_rows: torch.Tensor, goals: torch.Tensor,
+                   starts: torch.Tensor, max_hops: int, stream=None) -> torch.Tensor:
+        """Greedy paths over goal rows (query k: row k, goals[k], starts[k])."""
+        n = int(ptr.numel()) - 1
+        goals = goals.to(device=self.device, dtype=torch.int32).contiguous()
+        starts = starts.to(device=self.device, dtype=torch.int32).contiguous()
+        q = int(goals.numel())
+        out = torch.empty((q, max_hops + 1), dtype=torch.int32, device=self.device)
+        st = rdist_goal_paths(self.handle, n, ptr.data_ptr(), idx.data_ptr(), int(idx.numel()), Y_rows.data_ptr(),
+                              goals.data_ptr(),
+                              starts.data_ptr(), q, max_hops, out.data_ptr(), _stream_ptr(stream))
+        _check(st, "rdist_goal_paths")
         return out
 
     def epilogue(self, Y: torch.Tensor, gamma: float, n: int | None = None, D: torch.Tensor | None = None,

@@ -617,3 +617,40 @@ def test_rank_one_edge_change_identity():
         # a transposed orientation is not the changed graph's inverse
         wrong = Y + f * np.outer(Y[:, s], Y[d, :])
         assert np.abs(wrong - ref.Y).max() > 1e-6 * np.abs(ref.Y).max()
+
+
+def test_row_series_on_successor_lists():
+    """The series row for successor lists equals the (pinned) inversion's row
+    on ER, lattice and tree graphs and on a weighted graph, and the directed
+    path's closed form Y[g, j] = gamma^(g - j) at n = 3000; the lattice
+    generator's lists equal those of its dense form."""
+    rng = gg.rng_for("pins", 777)
+    for A, gam in [(gg.erdos_renyi(90, 0.05, rng), -0.5), (gg.grid_lattice_deleted(100, rng), -0.5),
+                   (gg.random_tree(70, rng), -0.6)]:
+        sol = oracle.solve(A, gam)
+        ptr, idx, _ = gg.csr_from_dense(A)
+        for g in (0, 17, A.shape[0] - 1):
+            row = oracle.y_row_csr(ptr, idx, sol.gamma, g)
+            assert np.array_equal(row == 0, sol.Y[g] == 0)
+            nz = sol.Y[g] > 0
+            assert np.max(np.abs(row[nz] - sol.Y[g][nz]) / sol.Y[g][nz]) < 1e-13
+    W = gg.weighted(gg.erdos_renyi(80, 0.06, rng), rng, 1, 9)
+    sol = oracle.solve_weighted(W, -0.5)
+    ptr, idx, w = gg.csr_from_dense(W)
+    row = oracle.y_row_csr(ptr, idx, sol.gamma, 5, weights=w)
+    nz = sol.Y[5] > 0
+    assert np.array_equal(row == 0, sol.Y[5] == 0)
+    assert np.max(np.abs(row[nz] - sol.Y[5][nz]) / sol.Y[5][nz]) < 1e-13
+    n, gamma, g = 3000, 0.7, 1500                      # 0.7^1500 ~ 1e-232: no underflow
+    ptr, idx = np.arange(n + 1, dtype=np.int64), np.arange(1, n + 1, dtype=np.int32)
+    ptr[-1] = n - 1
+    idx = idx[: n - 1]                                  # edge j -> j + 1
+    row = oracle.y_row_csr(ptr, idx, gamma, g)
+    j = np.arange(n)
+    exact = np.where(j <= g, gamma ** np.maximum(g - j, 0).astype(np.float64), 0.0)
+    nz = exact > 0
+    assert np.array_equal(row == 0, exact == 0)
+    assert np.max(np.abs(row[nz] - exact[nz]) / exact[nz]) < 1e-12
+    p1, i1 = gg.grid_lattice_csr(500, gg.rng_for("pins", 778))
+    p2, i2, _ = gg.csr_from_dense(gg.grid_lattice_deleted(500, gg.rng_for("pins", 778)))
+    assert np.array_equal(p1, p2) and np.array_equal(i1, i2)
