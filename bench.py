@@ -698,7 +698,7 @@ def bench_f4(args, torch, R, gg):
                                "the fixed-point iteration",
                    "n": n, "nnz": nnz, "gamma": gamma, "delta": delta, "goals_per_step": q},
         "iterations_per_step": float(np.mean(steps_run)),
-        "roofline": {"bound": "hbm", "kernel": "k_rows_step<64, 1>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "k_rows_step64<16>", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": read_traffic("k_rows_step_f4_lattice1m_pmc.md", sha), "avg_launch_ms": avg_ms,
                      "launches": st["launches"], "bytes_per_launch": per_launch_bytes, "source_sha": sha},

@@ -86,7 +86,11 @@ __global__ __launch_bounds__(256) void k_rows_step(const int64_t *__restrict__ p
     const int g = lane % G;
     const int s = (lane / G) % S;
     const int nd = lane / (G * S);
-    const int j = ((blockIdx.x * 256 + threadIdx.x) >> 6) * N + nd;
+    // workgroup b runs on XCD b % 8: each XCD takes a contiguous range of
+    // nodes, so neighbouring nodes' states stay in that XCD's L2
+    const int per = gridDim.x / 8;
+    const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int j = ((blk * 256 + (int)threadIdx.x) >> 6) * N + nd;
     const size_t base = (size_t)blockIdx.y * n * G;
     const double *__restrict__ Vo = Vold + base;
     double acc = 0.0;
@@ -108,6 +112,70 @@ __global__ __launch_bounds__(256) void k_rows_step(const int64_t *__restrict__ p
         Vnew[base + (size_t)j * G + g] = v;
         changed = v != Vo[(size_t)j * G + g];
     }
+    if (flag && __any(changed) && lane == 0) *flag = 1;
+}
+
+// The step for chunks of 64 goals, NB consecutive nodes per wavefront
+// (lane = goal): one load brings the batch's successor offsets, one the
+// successor ids of up to 64 of its edges, and the gathers of eight edges are
+// in flight together, so the wavefront waits for three memory latencies per
+// batch rather than per node.  Sums run in edge order, as in k_rows_step.
+template <int NB>
+__global__ __launch_bounds__(256) void k_rows_step64(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                     const uint8_t *__restrict__ wts, const double *__restrict__ gpow,
+                                                     int n, const int32_t *__restrict__ goals, int q,
+                                                     const double *__restrict__ Vold, double *__restrict__ Vnew,
+                                                     const rdist_info *__restrict__ info, int32_t *__restrict__ flag) {
+    if (info->status != RDIST_OK) return;
+    const double gamma = info->gamma;
+    const int lane = threadIdx.x & 63;
+    const int per = gridDim.x / 8;
+    const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;   // contiguous node ranges per XCD
+    const int j0 = (blk * 4 + (int)(threadIdx.x >> 6)) * NB;
+    if (j0 >= n) return;                                       // whole wavefront
+    const int nb = min(NB, n - j0);
+    const size_t base = (size_t)blockIdx.y * n * 64;
+    const double *__restrict__ Vo = Vold + base;
+    double *__restrict__ Vn = Vnew + base;
+    const int k = blockIdx.y * 64 + lane;
+    const int goal = k < q ? goals[k] : -1;
+    const long long pl = lane <= nb ? (long long)ptr[j0 + lane] : 0;
+    const long long E0 = __shfl(pl, 0), E1 = __shfl(pl, nb);
+    int node = 0;
+    long long bound = __shfl(pl, 1);
+    double acc = 0.0;
+    bool changed = false;
+    auto finish = [&]() {
+        const int j = j0 + node;
+        const double seed = goal == j ? 1.0 : 0.0;
+        const double v = wts ? seed + acc : fma(gamma, acc, seed);
+        Vn[(size_t)j * 64 + lane] = v;
+        if (flag) changed |= v != Vo[(size_t)j * 64 + lane];
+        ++node;
+        acc = 0.0;
+        bound = __shfl(pl, min(node + 1, nb));
+    };
+    for (long long c0 = E0; c0 < E1; c0 += 64) {
+        const int cnt = (int)min<long long>(64, E1 - c0);
+        const int myi = lane < cnt ? idx[c0 + lane] : 0;
+        const double myx = (wts && lane < cnt) ? gpow[wts[c0 + lane]] : 1.0;
+        for (int k0 = 0; k0 < cnt; k0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = __shfl(myi, min(k0 + u, 63));
+                v[u] = k0 + u < cnt ? Vo[(size_t)i * 64 + lane] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (k0 + u >= cnt) break;
+                while (c0 + k0 + u >= bound) finish();
+                if (wts) acc = fma(__shfl(myx, k0 + u), v[u], acc);
+                else acc += v[u];
+            }
+        }
+    }
+    while (node < nb) finish();
     if (flag && __any(changed) && lane == 0) *flag = 1;
 }
 
@@ -176,7 +244,8 @@ template <int G, int S>
 void step_gs(const RowsLaunch &L, const double *Vo, double *Vn, int32_t *flag, hipStream_t s) {
     constexpr int N = 64 / (G * S);
     const int waves = (L.n + N - 1) / N;
-    const dim3 grid((waves + 3) / 4, (L.q + G - 1) / G);
+    const int blocks = (waves + 3) / 4;
+    const dim3 grid(((blocks + 7) / 8) * 8, (L.q + G - 1) / G);   // a multiple of the 8 XCDs
     hipLaunchKernelGGL((k_rows_step<G, S>), grid, dim3(256), 0, s, L.ptr, L.idx, L.wts, L.wts ? L.gpow : nullptr,
                        L.n, L.goals, L.q, Vo, Vn, L.info, flag);
 }
@@ -214,9 +283,28 @@ void launch_rows_check(const int64_t *ptr, const int32_t *idx, const uint8_t *wt
     hipLaunchKernelGGL(k_rows_gate, dim3(1), dim3(256), 0, s, gamma, bad, info, gpow);
 }
 
+template <int NB>
+void step64(const RowsLaunch &L, const double *Vo, double *Vn, int32_t *flag, hipStream_t s) {
+    const int waves = (L.n + NB - 1) / NB;
+    const int blocks = (waves + 3) / 4;
+    const dim3 grid(((blocks + 7) / 8) * 8, (L.q + 63) / 64);
+    hipLaunchKernelGGL((k_rows_step64<NB>), grid, dim3(256), 0, s, L.ptr, L.idx, L.wts, L.wts ? L.gpow : nullptr,
+                       L.n, L.goals, L.q, Vo, Vn, L.info, flag);
+}
+
 void launch_rows_step(const RowsLaunch &L, const double *Vo, double *Vn, int32_t *flag, hipStream_t s) {
     const int G = rows_group(L.q);
     const int deg = (int)std::max<int64_t>(1, (L.nnz + L.n - 1) / std::max(L.n, 1));
+    if (G == 64) {
+        // nodes per wavefront: about 64 edges' worth, at most 16
+        const int nb = std::max(1, std::min(16, 64 / deg));
+        if (nb >= 16) step64<16>(L, Vo, Vn, flag, s);
+        else if (nb >= 8) step64<8>(L, Vo, Vn, flag, s);
+        else if (nb >= 4) step64<4>(L, Vo, Vn, flag, s);
+        else if (nb >= 2) step64<2>(L, Vo, Vn, flag, s);
+        else step64<1>(L, Vo, Vn, flag, s);
+        return;
+    }
     int S = 1;
     while (S < deg && G * S < 64) S <<= 1;
     const int ls = ilog2(S);
