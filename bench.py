@@ -11,7 +11,7 @@ Prints ONE JSON line: graphs/s (whole job), ms per step, effective TFLOP/s
 trailing-update kernel, timed with HIP events on its launch stream inside
 the library), and the CPU oracle timed on a bounded sample of the same solve.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5|f1|f3|f4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5|f1|f2|f3|f4]
 """
 from __future__ import annotations
 
@@ -716,6 +716,107 @@ def bench_f4(args, torch, R, gg):
     return out
 
 
+GAMMA_SOURCES = ["paper_2308_07403_amd/csrc/rd_gamma.hip", "paper_2308_07403_amd/csrc/rd_device.h"]
+
+
+def bench_f2(args, torch, R, gg):
+    """Gain selection and the per-entry certificate (Sec. 4.1, 4.2, 5.1):
+    the certificate pass and the spectral-radius bracket on the C2 graph
+    (value: certified-entry checks per second), and the accuracy sweep of the
+    paper's Fig. 2 families (Towers of Hanoi, square grid, binary tree, dense
+    random p = 0.5, preferential attachment): global, local and certified
+    fractions against BFS over gains up to the gate gamma Delta < 1."""
+    import oracle
+    n = 8192
+    A_np = gg.erdos_renyi(n, 0.02, gg.rng_for("f2", 0))
+    A = torch.from_numpy(A_np).cuda()
+    ctx = R.Context(0)
+    D, info, g = ctx.solve(A, -0.5, keep=True)
+    t0 = time.perf_counter()
+    gb = ctx.gain_bounds(A)
+    gain_ms = (time.perf_counter() - t0) * 1e3
+    for _ in range(args.warmup):
+        ctx.certify(g)
+    ctx.set_timing(True, classes=[R.RDIST_K_CERTIFY])
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cnt, _ = ctx.certify(g)
+    wall = time.perf_counter() - t0
+    st = ctx.kernel_stats(R.RDIST_K_CERTIFY)
+    ctx.set_timing(False)
+    g.release()
+    # the accuracy sweep
+    rng = gg.rng_for("f2", 1)
+    fams = [("hanoi", 5, gg.hanoi(5)), ("hanoi", 6, gg.hanoi(6)), ("grid", 10, gg.square_grid(10)),
+            ("grid", 20, gg.square_grid(20)), ("binary_tree", 7, gg.binary_tree(7)),
+            ("binary_tree", 9, gg.binary_tree(9)), ("dense_p0.5", 100, gg.erdos_renyi(100, 0.5, rng)),
+            ("dense_p0.5", 400, gg.erdos_renyi(400, 0.5, rng)),
+            ("power_law", 200, gg.barabasi_albert(200, 2, rng)), ("power_law", 800, gg.barabasi_albert(800, 2, rng))]
+    fracs = [1e-6, 1e-5, 1e-4, 1e-3, 0.01, 0.03, 0.1, 0.3, 0.5, 0.7, 0.9, 0.99]
+    sweep = []
+    for fam, size, G_np in fams:
+        m = G_np.shape[0]
+        dist, _ = oracle.bfs(G_np)
+        G = torch.from_numpy(G_np).cuda()
+        r = ctx.gain_bounds(G, diameter=int(dist.max()))
+        delta = r["delta"]
+        pairs = np.argwhere(dist > 0)                     # [goal, cur] with the goal reachable from cur
+        goal_t = torch.from_numpy(pairs[:, 0].astype(np.int32))
+        cur_t = torch.from_numpy(pairs[:, 1].astype(np.int32))
+        pts = []
+        for f in fracs:
+            gamma = f / delta
+            Dg, inf, gr = ctx.solve(G, gamma, keep=True)
+            c, _ = ctx.certify(gr)
+            hop = ctx.next_hop(gr, cur_t, goal_t, 1).cpu().numpy()[:, 1]
+            gr.release()
+            Dh = Dg.cpu().numpy()
+            ok = np.where(dist >= 0, Dh == dist, Dh == R.RDIST_UNREACHABLE)
+            np.fill_diagonal(ok, False)
+            good = (hop >= 0) & (dist[pairs[:, 0], np.maximum(hop, 0)] == dist[pairs[:, 0], pairs[:, 1]] - 1)
+            pts.append({"gamma": gamma, "gamma_delta": f, "global": float(ok.sum()) / (m * (m - 1)),
+                        "local": float(good.mean()) if len(good) else 1.0, "certified": c / (m * m)})
+        sweep.append({"family": fam, "size": size, "n": m, "delta": delta, "diameter": int(dist.max()),
+                      "rho": [r["rho_lo"], r["rho_hi"]], "gamma_c_lo": r["gamma_c_lo"],
+                      "gamma_global": r["gamma_global"], "gamma_precision": r["gamma_precision"], "points": pts})
+        log(f"[bench] sweep {fam} n={m}: global {[round(p['global'], 3) for p in pts]}")
+    ctx.close()
+    avg_ms = st["total_ms"] / max(st["launches"], 1)
+    per_launch_bytes = 8.0 * n * n
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    sha = source_sha(GAMMA_SOURCES)
+    out = {
+        "metric": "certified-entry checks/s on a kept n=8192 graph", "value": args.steps * n * n / wall,
+        "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "f2: per-entry certificate of D on the kept C2 graph (ER(8192, 0.02), "
+                               "gamma = 0.5/Delta) and the spectral-radius bracket; plus the Fig. 2 accuracy sweep",
+                   "n": n, "gamma": info["gamma"], "delta": info["delta"]},
+        "certified_fraction": cnt / (n * n),
+        "gain_bounds": {"ms": gain_ms, "rho": [gb["rho_lo"], gb["rho_hi"]], "steps": gb["steps"],
+                        "gamma_c_lo": gb["gamma_c_lo"], "gamma_gate": gb["gamma_gate"]},
+        "roofline": {"bound": "hbm", "kernel": "k_certify", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms,
+                     "launches": st["launches"], "bytes_per_launch": per_launch_bytes, "source_sha": sha},
+        "sweep": sweep,
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle certificate on a 2048 x 2048 sample)")
+        m = 2048
+        rs = np.random.default_rng(7)
+        Ys = np.exp(rs.uniform(-40.0, 0.0, size=(m, m)))
+        Ds = oracle.readout(Ys, info["gamma"]).D
+        t2 = time.perf_counter()
+        oracle.certify(Ys, Ds, info["gamma"], info["delta"])
+        tc = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": m * m / tc, "unit": "entries/s", "cores": 1, "kind": "oracle",
+                               "sample": f"oracle.certify on a synthetic {m}x{m} Y ({tc:.2f} s)"}
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
 def bench_c1(args, torch, R, gg):
     import oracle
     As = [torch.from_numpy(gg.c1_graph(s)).cuda() for s in range(100)]
@@ -846,7 +947,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "f1", "f3", "f4"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "f1", "f2", "f3", "f4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-concurrent", action="store_true",
                     help="C2: skip the three-stream throughput (profiling runs, one solve at a time)")
@@ -890,7 +991,7 @@ def main():
         log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
         del src, dst, scrub
     out = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
-           "f1": bench_f1, "f3": bench_f3, "f4": bench_f4}[args.workload](args, torch, R, gg)
+           "f1": bench_f1, "f2": bench_f2, "f3": bench_f3, "f4": bench_f4}[args.workload](args, torch, R, gg)
     print(json.dumps(out), flush=True)
 
 

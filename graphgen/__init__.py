@@ -490,3 +490,45 @@ def weights_for(count: int, rng: np.random.Generator, w_lo: int = 1, w_hi: int =
     w = np.exp(rng.uniform(np.log(w_lo), np.log(w_hi + 1.0), size=count)).astype(np.int64)
     return np.clip(w, w_lo, w_hi).astype(np.uint8)
 
+
+def hanoi(disks: int) -> np.ndarray:
+    """State graph of the Towers of Hanoi with ``disks`` disks on 3 pegs (paper
+    Fig. 2 A): 3^disks states (peg of each disk, digit k = disk k, disk 0 the
+    smallest); an undirected edge for every legal move of one top disk."""
+    n = 3 ** disks
+    src, dst = [], []
+    for s in range(n):
+        pegs = [(s // 3 ** k) % 3 for k in range(disks)]
+        top = {}
+        for k in range(disks):                     # smallest disk on each peg
+            top.setdefault(pegs[k], k)
+        for a, k in top.items():
+            for b in range(3):
+                if b != a and (b not in top or top[b] > k):
+                    src.append(s)
+                    dst.append(s + (b - a) * 3 ** k)
+    return from_edges(n, src, dst)
+
+
+def barabasi_albert(n: int, m: int, rng: np.random.Generator) -> np.ndarray:
+    """Undirected preferential-attachment graph (degree distribution with a
+    power-law tail of exponent 3, paper Fig. 2 E): start from a clique of
+    m + 1 nodes; each new node joins m distinct earlier nodes chosen with
+    probability proportional to their degree."""
+    src, dst = [], []
+    ends = []
+    for a in range(m + 1):
+        for b in range(a + 1, m + 1):
+            src += [a, b]
+            dst += [b, a]
+            ends += [a, b]
+    for v in range(m + 1, n):
+        chosen = set()
+        while len(chosen) < m:
+            chosen.add(int(ends[int(rng.integers(0, len(ends)))]))
+        for u in chosen:
+            src += [v, u]
+            dst += [u, v]
+            ends += [v, u]
+    return from_edges(n, src, dst)
+

@@ -271,6 +271,54 @@ rdist_status rdist_goal_paths(rdist_ctx ctx, int32_t n, const int64_t *succ_ptr,
                               int32_t max_hops, int32_t *out_dev, void *stream);
 
 /*
+ * Bounds on the gain for one graph (Sec. 4.1: the critical gain
+ * Eq. critical-gain, Theorem 2's sufficient bound, Theorem 3's bound for
+ * trees; Sec. 5.1: the machine-precision bound Eq. gamma-precision), to
+ * choose gamma before a solve.  rho(A) is bracketed by power iteration on
+ * A + I with Collatz-Wielandt ratios, which bound the spectral radius for
+ * any positive vector: rho_lo <= rho(A) <= rho_hi rigorously (rounding
+ * included); on graphs that are not strongly connected the lower bound may
+ * stay loose.
+ */
+typedef struct rdist_gain_report {
+    int32_t status;          /* RDIST_OK, or RDIST_E_ADJ (entries other than 0/1, or a self-loop) */
+    int32_t delta;           /* largest out-degree Delta */
+    int32_t steps;           /* power-iteration steps taken */
+    int32_t diameter;        /* d used below: the caller's, else n - 1 (a bound) */
+    double rho_lo, rho_hi;   /* bracket of the spectral radius of A (0 <= rho <= Delta) */
+    double gamma_c_lo, gamma_c_hi; /* 1 / rho_hi and 1 / rho_lo: the critical gain (HUGE_VAL for 0) */
+    double gamma_gate;       /* 1 / Delta: gains below it pass this library's gate gamma Delta < 1 */
+    double gamma_global;     /* Theorem 2: below 1 / (Delta + Delta^(d-1)) D is globally correct */
+    double gamma_tree;       /* Theorem 3 (undirected trees): (-1 + sqrt(1 + 4 Delta (d+2))) / (2 Delta (d+2)) */
+    double gamma_precision;  /* Eq. gamma-precision: gamma^d stays above the smallest double above this */
+} rdist_gain_report;
+
+/*
+ * A_dev: n x n adjacency as for rdist_solve (0/1).  diameter: the graph's
+ * diameter if the caller knows it, else 0 (then n - 1 is used).  Iterates
+ * at most max_steps steps, stopping once rho_hi - rho_lo <= rel_tol rho_hi.
+ * Synchronous (reads the bounds back every 16 steps).
+ */
+rdist_status rdist_gain_bounds(rdist_ctx ctx, const uint8_t *A_dev, int32_t n, int32_t diameter,
+                               int32_t max_steps, double rel_tol, rdist_gain_report *out, void *stream);
+
+/*
+ * Per-entry certificate of a kept graph's D (Sec. 3.1, Eq. Y-series-trunc
+ * with the walk-count bound Eq. Nijk-limit, as in the proof of Theorem 2):
+ * with k = D_ij the readout of Y_ij, the true distance is at least k, and a
+ * true distance of k + 1 or more would give
+ *   Y_ij <= gamma^(k+1) Delta^k / (1 - gamma Delta)           (Eq. Y-bracket).
+ * An entry with Y_ij above that bound (by a 2^-30 relative margin for
+ * rounding) has D_ij equal to the graph distance; Y_ij = 0 certifies
+ * "unreachable" when e gamma^(n-1) > DBL_MIN (then no reachable entry can
+ * underflow); entries below DBL_MIN are not certified.  mask_dev
+ * (nullable, device, n x n bytes) receives 1 for certified entries;
+ * *n_certified (host) their count.  Unweighted graphs only (RDIST_E_ARG
+ * otherwise).  Synchronous.
+ */
+rdist_status rdist_certify(rdist_ctx ctx, rdist_graph g, uint8_t *mask_dev, int64_t *n_certified, void *stream);
+
+/*
  * Standalone readout over a caller-provided Y (the unfused form of the
  * epilogue): D[i*n + j] from Y_dev[i*ld + j] for 0 <= i, j < n with the
  * given gain (0 < gamma < 1).  info (nullable) receives the counters.
@@ -368,7 +416,7 @@ typedef struct rdist_kernel_stats {
 #define RDIST_K_SMALL 5       /* single-workgroup solve */
 #define RDIST_K_BATCHED 6     /* persistent batched solve */
 #define RDIST_K_NEXTHOP 7     /* next-hop queries */
-#define RDIST_K_CERTIFY 8     /* mixed precision: certification + recompute */
+#define RDIST_K_CERTIFY 8     /* mixed precision: certification + recompute; rdist_certify */
 #define RDIST_K_UPDATE_EDGE 9 /* update of the next block's row and column (lookahead) and the
                                  last, readout-fused update */
 #define RDIST_K_MIXED_GEMM 10  /* mixed precision: FP32 row products and trailing updates */

@@ -18,6 +18,8 @@ import os
 import subprocess
 from dataclasses import dataclass
 
+import math
+
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -307,6 +309,81 @@ def y_row_csr(ptr, idx, gamma: float, g: int, weights=None, rel_tol: float = 1e-
     if k < 0:
         raise ValueError("bad row index")
     return y
+
+
+def spectral_radius(A) -> float:
+    """rho(A), the largest modulus of A's eigenvalues (numpy's eigenvalue routine);
+    the critical gain is 1 / rho(A) (Eq. critical-gain)."""
+    A = np.asarray(A, dtype=np.float64)
+    if A.shape[0] == 0:
+        return 0.0
+    return float(np.max(np.abs(np.linalg.eigvals(A))))
+
+
+def certify(Y, D, gamma: float, delta: int) -> np.ndarray:
+    """Per-entry certificate (Eq. Y-bracket of Theorem 2's proof, from
+    Eq. Y-series-trunc and Eq. Nijk-limit): with k = D, a true distance of
+    k + 1 or more would give Y <= gamma^(k+1) Delta^k / (1 - gamma Delta); Y
+    above that proves D exact.  Y == 0 certifies unreachable when
+    e gamma^(n-1) > DBL_MIN (no reachable entry can underflow); Y below
+    DBL_MIN is not certified.  Returns a boolean mask."""
+    Y = np.asarray(Y, dtype=np.float64)
+    k = np.asarray(D, dtype=np.float64)
+    dl = float(max(delta, 1))
+    tiny = np.finfo(np.float64).tiny
+    # a zero proves "no walk" only if no reachable entry (>= gamma^(n-1)) can underflow
+    zero_ok = (Y.shape[0] - 1) * math.log(gamma) > math.log(tiny) + 1.0
+    out = (Y == 0.0) & zero_ok
+    pos = Y >= np.finfo(np.float64).tiny
+    lb = (k + 1.0) * math.log(gamma * dl) - math.log(dl * (1.0 - gamma * dl))
+    out[pos] = np.log(Y[pos]) > lb[pos]
+    return out
+
+
+def gain_bounds(delta: int, d: int) -> dict:
+    """The paper's gain bounds for largest out-degree Delta and diameter d:
+    Theorem 2 (1 / (Delta + Delta^(d-1))), Theorem 3 for trees, and the
+    machine-precision bound Eq. gamma-precision (smallest double)^(1/d)."""
+    x = delta * (d + 2)
+    return {"gamma_gate": 1.0 / delta if delta else math.inf,
+            "gamma_global": 1.0 / (delta + float(delta) ** (d - 1)) if delta else math.inf,
+            "gamma_tree": (-1.0 + math.sqrt(1.0 + 4.0 * x)) / (2.0 * x) if delta else math.inf,
+            "gamma_precision": math.exp(math.log(5e-324) / d)}
+
+
+def global_fraction(D, dist) -> float:
+    """Fraction of ordered pairs i != j whose D is the graph distance
+    (Sec. 4.1's global performance; unreachable pairs count when D says so)."""
+    D = np.asarray(D)
+    dist = np.asarray(dist)
+    n = D.shape[0]
+    if n < 2:
+        return 1.0
+    ok = np.where(dist >= 0, D == dist, D == UNREACHABLE)
+    np.fill_diagonal(ok, False)
+    return float(ok.sum()) / (n * (n - 1))
+
+
+def local_fraction(A, Y, dist) -> float:
+    """Fraction of (current, goal) pairs, current != goal and the goal
+    reachable, whose greedy successor (Eq. descent read as ascent on Y:
+    the successor with the largest Y[goal, j], the lowest j on ties) lies one
+    step closer to the goal (Sec. 4.2's local performance)."""
+    A = np.asarray(A)
+    Y = np.asarray(Y, dtype=np.float64)
+    dist = np.asarray(dist)
+    n = A.shape[0]
+    succ = A.T != 0                                   # succ[c, j]: edge c -> j
+    good = total = 0
+    for g in range(n):
+        vals = np.where(succ, Y[g][None, :], -np.inf)     # [cur, j]
+        best = np.argmax(vals, axis=1)                    # first maximum: the lowest j on ties
+        has = np.isfinite(vals.max(axis=1)) & (vals.max(axis=1) > 0)
+        want = (dist[g] > 0)                              # cur != g, goal reachable from cur
+        ok = has & (dist[g, best] == dist[g] - 1)
+        good += int((ok & want).sum())
+        total += int(want.sum())
+    return good / total if total else 1.0
 
 
 def num_threads() -> int:

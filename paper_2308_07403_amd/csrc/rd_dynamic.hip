@@ -286,9 +286,22 @@ __global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld
             if (D) D[(size_t)i * n + j0] = dv[0];
         }
     }
-    if (D) flush_counts(ci, cnt);
-    unsigned long long l = wave_sum_u64(lost);
-    if ((threadIdx.x & 63) == 0 && l) atomicAdd((unsigned long long *)&ci->n_uncertified, l);
+    // one atomic per counter and workgroup: every workgroup adds into the same info
+    __shared__ unsigned long long part[6][4];
+    const unsigned long long v[6] = {wave_sum_u64(cnt.unreachable), wave_sum_u64(cnt.subnormal),
+                                     wave_sum_u64(cnt.saturated),   wave_sum_u64(cnt.ambiguous),
+                                     wave_sum_u64(cnt.negative),    wave_sum_u64(lost)};
+    if ((threadIdx.x & 63) == 0)
+        for (int t = 0; t < 6; ++t) part[t][threadIdx.x >> 6] = v[t];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const unsigned long long sum = part[threadIdx.x][0] + part[threadIdx.x][1] + part[threadIdx.x][2] +
+                                       part[threadIdx.x][3];
+        unsigned long long *dst[6] = {(unsigned long long *)&ci->n_unreachable, (unsigned long long *)&ci->n_subnormal,
+                                      (unsigned long long *)&ci->n_saturated, (unsigned long long *)&ci->n_ambiguous,
+                                      (unsigned long long *)&ci->n_negative, (unsigned long long *)&ci->n_uncertified};
+        if (sum) atomicAdd(dst[threadIdx.x], sum);
+    }
 }
 
 void launch_outdeg_from_bits(const unsigned long long *bits, int n, int32_t *outdeg, hipStream_t s) {

@@ -63,6 +63,7 @@ struct Workspace {
     Buf xh, xl, rh, rl;   // bf16 hi/lo parts of the FP32 inverse and of the scaled residual
     // goal rows: the two iteration states, and [info | bad flag | change flag | gamma^w table]
     Buf rv, rmisc;
+    Buf gb;               // gain bounds: two vectors of n doubles and the iteration's scratch
     int32_t *rflag_h = nullptr;   // pinned host copy of the change flag
     double *m() const { return (double *)M.p; }
     int32_t *outdeg() const { return (int32_t *)small.p; }

@@ -406,7 +406,7 @@ void free_workspace(rdist_ctx c, Workspace &w) {
     free_transient_plan(c, w);
     for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2, &w.Pt2, &w.small,
                    &w.m32, &w.v32, &w.u32, &w.s64, &w.p32, &w.cert, &w.csr_cnt, &w.csr_off, &w.csr_col, &w.r32,
-                   &w.c32, &w.xh, &w.xl, &w.rh, &w.rl, &w.rv, &w.rmisc})
+                   &w.c32, &w.xh, &w.xl, &w.rh, &w.rl, &w.rv, &w.rmisc, &w.gb})
         release(c, *b);
     if (w.rflag_h) (void)hipHostFree(w.rflag_h);
     for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
@@ -700,6 +700,83 @@ rdist_status rdist_goal_paths(rdist_ctx c, int32_t n, const int64_t *succ_ptr, c
         rd::launch_rows_paths(succ_ptr, succ_idx, n, nnz, Y_rows, goals, starts, q, max_hops, out_dev, s);
     }
     RD_HIP(hipGetLastError());
+    return RDIST_OK;
+}
+
+rdist_status rdist_gain_bounds(rdist_ctx c, const uint8_t *A_dev, int32_t n, int32_t diameter, int32_t max_steps,
+                               double rel_tol, rdist_gain_report *out, void *stream) {
+    if (!c || !A_dev || !out) return fail(RDIST_E_ARG, "NULL argument");
+    if (n < 1 || n > 65536 || diameter < 0 || diameter >= n || max_steps < 1 || !(rel_tol >= 0.0))
+        return fail(RDIST_E_ARG, "need 1 <= n <= 65536, 0 <= diameter < n, max_steps >= 1, rel_tol >= 0");
+    Guard gd(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &w = c->ws[s];
+    const size_t vb = (((size_t)n * 8 + 255) / 256) * 256, sb = rd::power_scratch_bytes();
+    rdist_status st;
+    if ((st = ensure_grow(c, w.gb, 2 * vb + sb))) return st;
+    double *x[2] = {(double *)w.gb.p, (double *)((char *)w.gb.p + vb)};
+    void *scratch = (char *)w.gb.p + 2 * vb;
+    std::vector<char> host(sb);
+    rd::launch_gamma_check(A_dev, n, scratch, s);
+    const double u = 0x1p-53;
+    double lo = 1.0, hi = HUGE_VAL;
+    int delta = 0, bad = 0, k = 0;
+    while (k < max_steps) {
+        const int chunk = std::min(16, max_steps - k);
+        for (int t = 0; t < chunk; ++t, ++k) rd::launch_power_step(A_dev, n, x[k & 1], x[(k & 1) ^ 1], scratch, k, s);
+        rd::launch_power_fold(scratch, k - 1, s);
+        RD_HIP(hipGetLastError());
+        RD_HIP(hipMemcpyAsync(host.data(), scratch, sb, hipMemcpyDeviceToHost, s));
+        RD_HIP(hipStreamSynchronize(s));
+        double lr, hr;
+        rd::power_read(host.data(), &lr, &hr, &delta, &bad);
+        // each ratio carries the rounding of a sum of at most Delta + 1 terms and a quotient
+        const double m = (delta + 3) * u;
+        lo = std::max(0.0, lr * (1.0 - m) - 1.0);
+        hi = std::min((double)delta, hr * (1.0 + m) - 1.0);
+        if (bad || hi - lo <= rel_tol * hi) break;
+    }
+    rdist_gain_report r{};
+    r.status = bad ? RDIST_E_ADJ : RDIST_OK;
+    r.delta = delta;
+    r.steps = k;
+    const int d = diameter > 0 ? diameter : std::max(n - 1, 1);
+    r.diameter = d;
+    r.rho_lo = lo;
+    r.rho_hi = std::max(lo, hi);
+    r.gamma_c_lo = r.rho_hi > 0.0 ? 1.0 / r.rho_hi : HUGE_VAL;
+    r.gamma_c_hi = r.rho_lo > 0.0 ? 1.0 / r.rho_lo : HUGE_VAL;
+    r.gamma_gate = delta > 0 ? 1.0 / delta : HUGE_VAL;
+    const double dd = (double)delta;
+    r.gamma_global = delta > 0 ? 1.0 / (dd + std::pow(dd, (double)(d - 1))) : HUGE_VAL;
+    r.gamma_tree = delta > 0 ? (-1.0 + std::sqrt(1.0 + 4.0 * dd * (d + 2))) / (2.0 * dd * (d + 2)) : HUGE_VAL;
+    r.gamma_precision = std::exp(std::log(4.9406564584124654e-324) / (double)d);
+    *out = r;
+    return RDIST_OK;
+}
+
+rdist_status rdist_certify(rdist_ctx c, rdist_graph g, uint8_t *mask_dev, int64_t *n_certified, void *stream) {
+    if (!c || !g || !n_certified) return fail(RDIST_E_ARG, "NULL argument");
+    if (g->ctx != c) return fail(RDIST_E_STATE, "graph belongs to another context");
+    if (g->weighted) return fail(RDIST_E_ARG, "the certificate covers unweighted graphs");
+    Guard gd(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &w = c->ws[s];
+    rdist_status st;
+    if ((st = ensure_grow(c, w.rmisc, kRowsMisc))) return st;
+    unsigned long long *cnt = (unsigned long long *)((char *)w.rmisc.p + kRowsFlag);
+    rd::launch_fill_i32((int32_t *)cnt, 2, s);
+    {
+        Timer tm(c, s, RDIST_K_CERTIFY, 0.0, (8.0 + (mask_dev ? 1.0 : 0.0)) * (double)g->n * g->n);
+        rd::launch_certify(g->Y, g->ld, g->n, g->ginfo, mask_dev, cnt, s);
+    }
+    RD_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    RD_HIP(hipMemcpyAsync(&h, cnt, 8, hipMemcpyDeviceToHost, s));
+    RD_HIP(hipStreamSynchronize(s));
+    *n_certified = (int64_t)h;
     return RDIST_OK;
 }
 

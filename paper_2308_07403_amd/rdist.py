@@ -117,6 +117,21 @@ _lib.rdist_goal_rows.restype = ctypes.c_int
 _lib.rdist_goal_paths.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_int32,
                                   ctypes.c_int32, _P, _P]
 _lib.rdist_goal_paths.restype = ctypes.c_int
+class rdist_gain_report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("delta", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("diameter", ctypes.c_int32), ("rho_lo", ctypes.c_double), ("rho_hi", ctypes.c_double),
+                ("gamma_c_lo", ctypes.c_double), ("gamma_c_hi", ctypes.c_double), ("gamma_gate", ctypes.c_double),
+                ("gamma_global", ctypes.c_double), ("gamma_tree", ctypes.c_double),
+                ("gamma_precision", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib.rdist_gain_bounds.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P, _P]
+_lib.rdist_gain_bounds.restype = ctypes.c_int
+_lib.rdist_certify.argtypes = [_P, _P, _P, _P, _P]
+_lib.rdist_certify.restype = ctypes.c_int
 _lib.rdist_graph_release.argtypes = [_P]
 _lib.rdist_graph_release.restype = None
 _lib.rdist_graph_y.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -155,6 +170,8 @@ rdist_solve_batched = _lib.rdist_solve_batched
 rdist_next_hop = _lib.rdist_next_hop
 rdist_graph_release = _lib.rdist_graph_release
 rdist_goal_rows = _lib.rdist_goal_rows
+rdist_gain_bounds = _lib.rdist_gain_bounds
+rdist_certify = _lib.rdist_certify
 rdist_goal_paths = _lib.rdist_goal_paths
 rdist_graph_y = _lib.rdist_graph_y
 rdist_graph_update_edge = _lib.rdist_graph_update_edge
@@ -172,6 +189,7 @@ rdist_server_destroy = _lib.rdist_server_destroy
 
 EXPORTS = ("rdist_create", "rdist_destroy", "rdist_solve", "rdist_solve_batched", "rdist_next_hop",
            "rdist_graph_release", "rdist_graph_y", "rdist_graph_update_edge", "rdist_goal_rows", "rdist_goal_paths",
+           "rdist_gain_bounds", "rdist_certify",
            "rdist_epilogue", "rdist_set_timing",
            "rdist_kernel_stats_get", "rdist_hbm_in_use", "rdist_last_error", "rdist_status_string",
            "rdist_server_create", "rdist_server_submit", "rdist_server_poll", "rdist_server_stats_get",
@@ -376,6 +394,24 @@ class Context:
         _check(st, "rdist_goal_rows")
         (stream or torch.cuda.current_stream()).synchronize()
         return Y, D, self.info.get(0).as_dict(), int(steps.value)
+
+    def gain_bounds(self, A: torch.Tensor, diameter: int = 0, max_steps: int = 4000, rel_tol: float = 1e-10,
+                    stream=None) -> dict:
+        """Bracket of rho(A), the critical gain and the paper's bounds on gamma (a dict)."""
+        assert A.is_cuda and A.dtype == torch.uint8 and A.dim() == 2 and A.shape[0] == A.shape[1]
+        A = A.contiguous()
+        r = rdist_gain_report()
+        _check(rdist_gain_bounds(self.handle, A.data_ptr(), A.shape[0], int(diameter), int(max_steps),
+                                 float(rel_tol), ctypes.byref(r), _stream_ptr(stream)), "rdist_gain_bounds")
+        return r.as_dict()
+
+    def certify(self, graph: "Graph", want_mask: bool = False, stream=None):
+        """Per-entry certificate of a kept graph's D: (count, n x n uint8 mask or None)."""
+        mask = torch.empty((graph.n, graph.n), dtype=torch.uint8, device=self.device) if want_mask else None
+        cnt = ctypes.c_int64(0)
+        _check(rdist_certify(self.handle, graph.handle, mask.data_ptr() if mask is not None else None,
+                             ctypes.byref(cnt), _stream_ptr(stream)), "rdist_certify")
+        return int(cnt.value), mask
 
     def goal_paths(self, ptr: torch.Tensor, idx: torch.Tensor, Y_rows: torch.Tensor, goals: torch.Tensor,
                    starts: torch.Tensor, max_hops: int, stream=None) -> torch.Tensor:

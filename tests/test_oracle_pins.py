@@ -654,3 +654,101 @@ def test_row_series_on_successor_lists():
     p1, i1 = gg.grid_lattice_csr(500, gg.rng_for("pins", 778))
     p2, i2, _ = gg.csr_from_dense(gg.grid_lattice_deleted(500, gg.rng_for("pins", 778)))
     assert np.array_equal(p1, p2) and np.array_equal(i1, i2)
+
+
+# ---------------------------------------------------------------------------
+# Gain selection and the per-entry certificate
+# ---------------------------------------------------------------------------
+
+def test_spectral_radius_closed_forms():
+    """rho(A) of the paper's three-vertex path (sqrt 2, its Example), a
+    directed cycle (1), the complete digraph (n - 1) and an M x M grid
+    (4 cos(pi / (M + 1)))."""
+    assert abs(oracle.spectral_radius(gg.undirected_path3()) - math.sqrt(2.0)) < 1e-14
+    assert abs(oracle.spectral_radius(gg.directed_cycle(40)) - 1.0) < 1e-12
+    assert abs(oracle.spectral_radius(gg.complete_digraph(30)) - 29.0) < 1e-11
+    for M in (3, 7, 12):
+        assert abs(oracle.spectral_radius(gg.square_grid(M)) - 4.0 * math.cos(math.pi / (M + 1))) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_certificate_implies_bfs_distance(seed):
+    """Every entry the certificate accepts has D equal to the BFS distance, at
+    gains from tiny to the gate; below 1 / (Delta + Delta^d) every entry is
+    accepted; the certificate is not vacuous at AUTO gain on trees."""
+    rng = gg.rng_for("pin", 900 + seed)
+    n = int(rng.integers(20, 60))
+    for A in (gg.erdos_renyi(n, 0.08, rng), gg.random_tree(n, rng), gg.square_grid(5), gg.hanoi(3)):
+        dist = bfs_scipy(A)
+        delta = int(A.sum(axis=0).max())
+        d = diameter(dist)
+        for gamma in (1e-6, 0.05 / delta, 0.5 / delta, 0.95 / delta):
+            sol = oracle.solve(A, gamma)
+            ok = oracle.certify(sol.Y, sol.D, sol.gamma, delta)
+            reach = dist >= 0
+            assert np.all(sol.D[ok & reach] == dist[ok & reach])
+            assert np.all(sol.D[ok & ~reach] == oracle.UNREACHABLE)
+        g_all = 0.99 / (delta + float(delta) ** d)
+        sol = oracle.solve(A, g_all)
+        assert oracle.certify(sol.Y, sol.D, sol.gamma, delta).all()
+
+
+def test_gain_bound_functions_against_bfs():
+    """oracle.gain_bounds: below Theorem 2's bound D equals BFS on random
+    graphs, below Theorem 3's on trees; the precision bound keeps gamma^d
+    representable."""
+    rng = gg.rng_for("pin", 950)
+    for _ in range(6):
+        A = gg.erdos_renyi(int(rng.integers(4, 10)), 0.4, rng)
+        dist = bfs_scipy(A)
+        delta = int(A.sum(axis=0).max())
+        if delta == 0:
+            continue
+        b = oracle.gain_bounds(delta, diameter(dist))
+        sol = oracle.solve(A, 0.999 * b["gamma_global"])
+        assert oracle.global_fraction(sol.D, dist) == 1.0
+        T = gg.random_tree(int(rng.integers(5, 25)), rng)
+        dist = bfs_scipy(T)
+        b = oracle.gain_bounds(int(T.sum(axis=0).max()), diameter(dist))
+        _, D = rdist_ungated(T, 0.999 * b["gamma_tree"])
+        assert oracle.global_fraction(D, dist) == 1.0
+    b = oracle.gain_bounds(4, 300)
+    assert b["gamma_precision"] ** 300 > 0.0 and (0.99 * b["gamma_precision"]) ** 300 == 0.0
+
+
+def test_global_and_local_fractions():
+    """global_fraction and local_fraction against direct counts on small
+    graphs: the three-vertex path above gamma = 1/2 (the Example) is not
+    globally correct but locally correct; a direct loop over oracle.next_hop
+    gives the same local fraction on a grid at a large gain."""
+    A = gg.undirected_path3()
+    dist = bfs_scipy(A)
+    Y, D = rdist_ungated(A, 0.6)
+    assert oracle.global_fraction(D, dist) < 1.0
+    assert oracle.local_fraction(A, Y, dist) == 1.0
+    G = gg.square_grid(6)
+    dist = bfs_scipy(G)
+    sol = oracle.solve(G, 0.24)
+    good = total = 0
+    for g in range(G.shape[0]):
+        for c in range(G.shape[0]):
+            if dist[g, c] > 0:
+                total += 1
+                j = oracle.next_hop(G, sol.Y, c, g)
+                good += int(j >= 0 and dist[g, j] == dist[g, c] - 1)
+    assert oracle.local_fraction(G, sol.Y, dist) == good / total
+    ok = np.where(dist >= 0, sol.D == dist, sol.D == oracle.UNREACHABLE)
+    np.fill_diagonal(ok, False)
+    assert oracle.global_fraction(sol.D, dist) == ok.sum() / (36 * 35)
+
+
+def test_hanoi_and_power_law_generators():
+    """Towers of Hanoi: 3^k states, 3 (3^k - 1) / 2 moves, diameter 2^k - 1,
+    degree at most 3; preferential attachment: m edges per new node."""
+    for k in (2, 3, 4):
+        H = gg.hanoi(k)
+        assert H.shape[0] == 3 ** k and int(H.sum()) == 3 * (3 ** k - 1)
+        assert np.array_equal(H, H.T) and int(H.sum(axis=0).max()) == 3
+        assert diameter(bfs_scipy(H)) == 2 ** k - 1
+    B = gg.barabasi_albert(200, 2, gg.rng_for("pin", 960))
+    assert np.array_equal(B, B.T) and int(B.sum()) == 2 * (3 + 2 * (200 - 3))
