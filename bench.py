@@ -797,7 +797,8 @@ def bench_f2(args, torch, R, gg):
         "gain_bounds": {"ms": gain_ms, "rho": [gb["rho_lo"], gb["rho_hi"]], "steps": gb["steps"],
                         "gamma_c_lo": gb["gamma_c_lo"], "gamma_gate": gb["gamma_gate"]},
         "roofline": {"bound": "hbm", "kernel": "k_certify", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": read_traffic("k_certify_f2_n8192_pmc.md", sha), "avg_launch_ms": avg_ms,
                      "launches": st["launches"], "bytes_per_launch": per_launch_bytes, "source_sha": sha},
         "sweep": sweep,
     }
