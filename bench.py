@@ -593,6 +593,21 @@ def bench_f3(args, torch, R, gg):
     st = ctx.kernel_stats(R.RDIST_K_EDGE_UPDATE)
     ctx.set_timing(False)
     assert inf["status"] == 0, inf
+    # the same kind of changes in batches: one call per step of 32 (4 passes of 8)
+    batches = [plan_changes(rng, A_host, delta, per_step) for _ in range(args.steps + 1)]
+    g.update_edges(batches[0], D=D)
+    torch.cuda.synchronize()
+    ctx.set_timing(True, classes=[R.RDIST_K_EDGE_UPDATE])
+    t0 = time.perf_counter()
+    for b in batches[1:]:
+        binf = g.update_edges(b, D=D)
+        lost += binf["n_uncertified"]
+        refreshed += binf["fallback_fraction"] == 1.0
+    torch.cuda.synchronize()
+    bwall = time.perf_counter() - t0
+    bst = ctx.kernel_stats(R.RDIST_K_EDGE_UPDATE)
+    ctx.set_timing(False)
+    assert binf["status"] == 0, binf
     g.release()
     ctx.close()
     nch = len(timed)
@@ -612,6 +627,10 @@ def bench_f3(args, torch, R, gg):
         "ms_per_change": wall * 1e3 / nch, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
         "resolve_ms": resolve_ms, "speedup_vs_resolve": resolve_ms / (wall * 1e3 / nch),
         "lost_entries": int(lost), "reinversions": int(refreshed),
+        "batched": {"changes_per_s": per_step * args.steps / bwall, "ms_per_step": bwall * 1e3 / args.steps,
+                    "passes_per_step": (per_step + 7) // 8,
+                    "apply_ms": bst["total_ms"] / max(bst["launches"], 1),
+                    "apply_gbs": 22.0 * n * n / (bst["total_ms"] / max(bst["launches"], 1) * 1e-3) / 1e9},
         "roofline": {"bound": "hbm", "kernel": "k_sm_apply<4>", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": read_traffic("k_sm_apply_f3_n8192_pmc.md", sha), "avg_launch_ms": avg_ms,

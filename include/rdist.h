@@ -227,6 +227,26 @@ rdist_status rdist_graph_update_edge(rdist_ctx ctx, rdist_graph g, int32_t src, 
                                      int16_t *D_dev, rdist_info *info, void *stream);
 
 /*
+ * Several edge changes, applied in order (a later change to the same edge
+ * wins): src[e] -> dst[e] gets weight[e] (host arrays of count entries,
+ * rules as rdist_graph_update_edge).  Changes go in chunks of up to 8 per
+ * pass over Y: change a of a chunk is the rank-one step of the graph left by
+ * changes 0 .. a-1 (its column and row of Y are built from Y and the earlier
+ * terms), and one pass adds all of a chunk's terms to Y, carrying each
+ * entry's error bound through every term; re-inversion as for one change.
+ * A chunk is applied only if every intermediate graph passes the gate (a
+ * bound on its Delta: the largest of Delta and every out-degree a change of
+ * the chunk passes through); otherwise info->status is RDIST_E_NOT_DD, that
+ * chunk and the rest are not applied, the chunks before it stay applied, and
+ * D_dev is left as it was.  D_dev (nullable) receives the final graph's D.
+ * info->n_uncertified sums the lost entries of all chunks,
+ * info->fallback_fraction is 1 if any chunk re-inverted.  Synchronous.
+ */
+rdist_status rdist_graph_update_edges(rdist_ctx ctx, rdist_graph g, int32_t count, const int32_t *src,
+                                      const int32_t *dst, const int32_t *weight, int16_t *D_dev,
+                                      rdist_info *info, void *stream);
+
+/*
  * Goal rows without an inversion (the recurrent network of Sec. 2 and its
  * walk series, Eq. Y-series): for each of q goals g = goals[k], row k of the
  * output is row g of Y = (I - X)^{-1}, the fixed point of

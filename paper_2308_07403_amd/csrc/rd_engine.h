@@ -102,9 +102,10 @@ struct rdist_graph_s {
     uint16_t *beta = nullptr;             // per-entry error bounds, made by the first change,
     int32_t *hist = nullptr;              // and in the same allocation the out-degree histogram
     rdist_info *hinfo = nullptr;          // pinned host copy of a change's info
+    double *bs = nullptr;                 // scratch of batched changes, made by the first batch
     int weighted = 0;
     void *aux = nullptr;                  // one allocation holding succ .. sm
-    size_t ybytes = 0, aux_bytes = 0, beta_bytes = 0;
+    size_t ybytes = 0, aux_bytes = 0, beta_bytes = 0, bs_bytes = 0;
     size_t bytes = 0;                     // their sum, counted in the context's budget
 };
 

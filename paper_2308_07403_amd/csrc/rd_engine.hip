@@ -212,6 +212,7 @@ void release_graph_locked(rdist_graph g) {
     (void)hipFree(g->aux);
     if (g->beta) (void)hipFree(g->beta);
     if (g->hinfo) (void)hipHostFree(g->hinfo);
+    if (g->bs) (void)hipFree(g->bs);
     c->in_use -= std::min(g->bytes, c->in_use);
     c->graphs.erase(g);
     delete g;
@@ -566,8 +567,8 @@ static rdist_status refresh_graph(rdist_ctx c, rdist_graph g, double gamma, int1
         std::swap(g->Y, fresh->Y);
         std::swap(g->ld, fresh->ld);
         std::swap(g->ybytes, fresh->ybytes);
-        g->bytes = g->ybytes + g->aux_bytes + g->beta_bytes;
-        fresh->bytes = fresh->ybytes + fresh->aux_bytes + fresh->beta_bytes;
+        g->bytes = g->ybytes + g->aux_bytes + g->beta_bytes + g->bs_bytes;
+        fresh->bytes = fresh->ybytes + fresh->aux_bytes + fresh->beta_bytes + fresh->bs_bytes;
         hipError_t e = hipMemcpyAsync(g->ginfo, fresh->ginfo, sizeof(rdist_info), hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(out, fresh->ginfo, sizeof(rdist_info), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) {
@@ -582,17 +583,9 @@ static rdist_status refresh_graph(rdist_ctx c, rdist_graph g, double gamma, int1
     return st;
 }
 
-rdist_status rdist_graph_update_edge(rdist_ctx c, rdist_graph g, int32_t src, int32_t dst, int32_t weight,
-                                     int16_t *D_dev, rdist_info *info, void *stream) {
-    if (!c || !g) return fail(RDIST_E_ARG, "NULL handle");
-    if (g->ctx != c) return fail(RDIST_E_STATE, "graph belongs to another context");
-    if (src < 0 || src >= g->n || dst < 0 || dst >= g->n || src == dst)
-        return fail(RDIST_E_ARG, "src and dst must be distinct nodes of the graph");
-    if (weight < 0 || weight > (g->weighted ? 255 : 1))
-        return fail(RDIST_E_ARG, g->weighted ? "weight must lie in [0, 255]" : "weight must be 0 or 1");
-    Guard gd(c);
-    RD_HIP(hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
+// What edge changes keep beside Y, made by the first change: the pinned
+// info copy, the per-entry error bounds and the out-degree histogram.
+static rdist_status ensure_change_state(rdist_ctx c, rdist_graph g, hipStream_t s) {
     const int n = g->n;
     rdist_status st;
     if (!g->hinfo) RD_HIP(hipHostMalloc((void **)&g->hinfo, sizeof(rdist_info), hipHostMallocDefault));
@@ -606,6 +599,89 @@ rdist_status rdist_graph_update_edge(rdist_ctx c, rdist_graph g, int32_t src, in
         rd::launch_beta_fill(g->beta, n, g->ginfo, s);
         rd::launch_deg_hist(g->outdeg, n, g->hist, s);
     }
+    return RDIST_OK;
+}
+
+static rdist_status check_change(rdist_graph g, int32_t src, int32_t dst, int32_t weight) {
+    if (src < 0 || src >= g->n || dst < 0 || dst >= g->n || src == dst)
+        return fail(RDIST_E_ARG, "src and dst must be distinct nodes of the graph");
+    if (weight < 0 || weight > (g->weighted ? 255 : 1))
+        return fail(RDIST_E_ARG, g->weighted ? "weight must lie in [0, 255]" : "weight must be 0 or 1");
+    return RDIST_OK;
+}
+
+rdist_status rdist_graph_update_edges(rdist_ctx c, rdist_graph g, int32_t count, const int32_t *src,
+                                      const int32_t *dst, const int32_t *weight, int16_t *D_dev, rdist_info *info,
+                                      void *stream) {
+    if (!c || !g) return fail(RDIST_E_ARG, "NULL handle");
+    if (g->ctx != c) return fail(RDIST_E_STATE, "graph belongs to another context");
+    if (count < 0 || (count > 0 && (!src || !dst || !weight))) return fail(RDIST_E_ARG, "bad count or NULL arrays");
+    rdist_status st;
+    for (int32_t e = 0; e < count; ++e)
+        if ((st = check_change(g, src[e], dst[e], weight[e]))) return st;
+    Guard gd(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int n = g->n;
+    if ((st = ensure_change_state(c, g, s))) return st;
+    if (!g->bs) {
+        const size_t b = rd::batch_scratch_doubles(n) * 8;
+        if ((st = dalloc(c, (void **)&g->bs, b))) return st;
+        g->bs_bytes = b;
+        g->bytes += b;
+    }
+    rdist_info *ci = reinterpret_cast<rdist_info *>(g->sm + 2);
+    rdist_info hi{};
+    hi.status = RDIST_OK;
+    int64_t lost_total = 0;
+    bool reinverted = false;
+    for (int32_t off = 0; off < count; off += rd::kMaxBatch) {
+        rd::EdgeBatch B{};
+        B.k = std::min(rd::kMaxBatch, count - off);
+        for (int a = 0; a < B.k; ++a) {
+            B.src[a] = src[off + a];
+            B.dst[a] = dst[off + a];
+            B.w[a] = weight[off + a];
+        }
+        const bool last = off + B.k >= count;
+        int16_t *D = last ? D_dev : nullptr;
+        rd::launch_edge_batch_prep(g->Y, g->ld, n, g->beta, g->sm, g->bs, g->A, g->outdeg, g->ginfo, B, s);
+        {
+            const double n2 = (double)n * n;
+            Timer t(c, s, RDIST_K_EDGE_UPDATE, 2.0 * B.k * n2, (D ? 22.0 : 20.0) * n2);
+            rd::launch_edge_batch_apply(g->Y, g->ld, n, g->beta, g->sm, g->bs, D, g->A, g->outdeg, g->hist, g->succ,
+                                        g->ginfo, B, s);
+        }
+        RD_HIP(hipGetLastError());
+        RD_HIP(hipMemcpyAsync(g->hinfo, ci, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
+        RD_HIP(hipStreamSynchronize(s));
+        hi = *g->hinfo;
+        if (hi.status != RDIST_OK) break;
+        if (hi.n_uncertified > 0) {
+            lost_total += hi.n_uncertified;
+            if ((st = refresh_graph(c, g, hi.gamma, D, &hi, s))) return st;
+            reinverted = true;
+        }
+    }
+    if (count > 0) {
+        hi.n_uncertified = lost_total;
+        hi.fallback_fraction = reinverted ? 1.0 : 0.0;
+    }
+    if (info) *info = hi;
+    return RDIST_OK;
+}
+
+rdist_status rdist_graph_update_edge(rdist_ctx c, rdist_graph g, int32_t src, int32_t dst, int32_t weight,
+                                     int16_t *D_dev, rdist_info *info, void *stream) {
+    if (!c || !g) return fail(RDIST_E_ARG, "NULL handle");
+    if (g->ctx != c) return fail(RDIST_E_STATE, "graph belongs to another context");
+    rdist_status st;
+    if ((st = check_change(g, src, dst, weight))) return st;
+    Guard gd(c);
+    RD_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int n = g->n;
+    if ((st = ensure_change_state(c, g, s))) return st;
     rdist_info *ci = reinterpret_cast<rdist_info *>(g->sm + 2);
     rd::launch_edge_prep(g->Y, g->ld, n, g->A, g->outdeg, g->hist, g->beta, g->ginfo, g->sm, src, dst, weight, s);
     {

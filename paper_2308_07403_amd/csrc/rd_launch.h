@@ -130,6 +130,19 @@ void launch_paths_multi(const PathTask *tasks, int ntasks, int total_blocks, int
 void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s);
 // Edge changes of a kept graph (rd_dynamic.hip).
 void launch_outdeg_from_bits(const unsigned long long *bits, int n, int32_t *outdeg, hipStream_t s);
+// Up to kMaxBatch edge changes applied in one pass (rd_dynamic.hip).
+constexpr int kMaxBatch = 8;
+struct EdgeBatch {
+    int k;
+    int src[kMaxBatch], dst[kMaxBatch], w[kMaxBatch];
+};
+size_t batch_scratch_doubles(int n);
+void launch_edge_batch_prep(const double *Y, int ld, int n, const uint16_t *Q, double *sm, double *bs,
+                            const uint8_t *A, const int32_t *outdeg, const rdist_info *ginfo, const EdgeBatch &B,
+                            hipStream_t s);
+void launch_edge_batch_apply(double *Y, int ld, int n, uint16_t *Q, double *sm, const double *bs, int16_t *D,
+                             uint8_t *A, int32_t *outdeg, int32_t *hist, unsigned long long *bits, rdist_info *ginfo,
+                             const EdgeBatch &B, hipStream_t s);
 // Q: per-entry error bounds (n x n, 16-bit -log2 in 1/256 steps); sm: the
 // update's scratch (16 + 3n doubles) holding the call's info at sm + 2.
 // hist: n + 1 counts of nodes per out-degree.

@@ -14,6 +14,8 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
+
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -138,6 +140,8 @@ _lib.rdist_graph_y.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_i
 _lib.rdist_graph_y.restype = ctypes.c_int
 _lib.rdist_graph_update_edge.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
 _lib.rdist_graph_update_edge.restype = ctypes.c_int
+_lib.rdist_graph_update_edges.argtypes = [_P, _P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]
+_lib.rdist_graph_update_edges.restype = ctypes.c_int
 _lib.rdist_epilogue.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P, _P, _P]
 _lib.rdist_epilogue.restype = ctypes.c_int
 _lib.rdist_set_timing.argtypes = [_P, ctypes.c_int]
@@ -175,6 +179,7 @@ rdist_certify = _lib.rdist_certify
 rdist_goal_paths = _lib.rdist_goal_paths
 rdist_graph_y = _lib.rdist_graph_y
 rdist_graph_update_edge = _lib.rdist_graph_update_edge
+rdist_graph_update_edges = _lib.rdist_graph_update_edges
 rdist_epilogue = _lib.rdist_epilogue
 rdist_set_timing = _lib.rdist_set_timing
 rdist_kernel_stats_get = _lib.rdist_kernel_stats_get
@@ -188,7 +193,7 @@ rdist_server_stats_get = _lib.rdist_server_stats_get
 rdist_server_destroy = _lib.rdist_server_destroy
 
 EXPORTS = ("rdist_create", "rdist_destroy", "rdist_solve", "rdist_solve_batched", "rdist_next_hop",
-           "rdist_graph_release", "rdist_graph_y", "rdist_graph_update_edge", "rdist_goal_rows", "rdist_goal_paths",
+           "rdist_graph_release", "rdist_graph_y", "rdist_graph_update_edge", "rdist_graph_update_edges", "rdist_goal_rows", "rdist_goal_paths",
            "rdist_gain_bounds", "rdist_certify",
            "rdist_epilogue", "rdist_set_timing",
            "rdist_kernel_stats_get", "rdist_hbm_in_use", "rdist_last_error", "rdist_status_string",
@@ -249,6 +254,21 @@ class Graph:
                                        D.data_ptr() if D is not None else None, ctypes.byref(out),
                                        _stream_ptr(stream)),
                "rdist_graph_update_edge")
+        return out.as_dict()
+
+    def update_edges(self, changes, D: torch.Tensor | None = None, stream=None) -> dict:
+        """Applies [(src, dst, weight), ...] in order (chunks of up to 8 per pass over Y);
+        D (optional) receives the final D.  Blocks; returns the call's info."""
+        ch = np.asarray(changes, dtype=np.int32).reshape(-1, 3)
+        if D is not None:
+            assert D.is_cuda and D.dtype == torch.int16 and D.numel() == self.n * self.n
+        srcs = np.ascontiguousarray(ch[:, 0])
+        dsts = np.ascontiguousarray(ch[:, 1])
+        ws = np.ascontiguousarray(ch[:, 2])
+        out = rdist_info()
+        _check(rdist_graph_update_edges(self.ctx.handle, self.handle, int(ch.shape[0]), srcs.ctypes.data,
+                                        dsts.ctypes.data, ws.ctypes.data, D.data_ptr() if D is not None else None,
+                                        ctypes.byref(out), _stream_ptr(stream)), "rdist_graph_update_edges")
         return out.as_dict()
 
     def y(self) -> torch.Tensor:

@@ -317,3 +317,117 @@ def test_full_size_er_sampled_columns(ctx):
         check_d(D[:, j].cpu().numpy(), Do, yo, gamma, f"column {j}")
     del Y
     g.release()
+
+
+# ---------------------------------------------------------------------------
+# Batched changes (up to 8 per pass over Y)
+# ---------------------------------------------------------------------------
+
+def plan_batch(rng, A, count, delta_cap, weighted):
+    """count changes in order, applied to a copy of A as they are drawn (so
+    repeated edges see the earlier change); a repeat of an earlier edge is
+    planted every fifth change."""
+    A = A.copy()
+    out = []
+    for t in range(count):
+        if t % 5 == 4 and out:
+            s, d, _ = out[int(rng.integers(0, len(out)))]
+            w = 0 if A[d, s] else (int(rng.integers(1, 31)) if weighted else 1)
+            outdeg = (A != 0).sum(axis=0)
+            if w and outdeg[s] >= delta_cap:
+                w = 0
+        else:
+            s, d, w = pick_change(rng, A, delta_cap, weighted)
+        A[d, s] = w
+        out.append((s, d, w))
+    return out, A
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_batch_sequence(ctx, weighted):
+    """Three batches of 13 changes (a chunk of 8 and one of 5, repeated edges
+    inside a chunk) on a kept n = 600 graph against the oracle's inversion of
+    each changed graph."""
+    rng = gg.rng_for("update", 1600 + weighted)
+    n = 600
+    A = gg.erdos_renyi(n, 0.02, rng)
+    if weighted:
+        A = gg.weighted(A, rng, 1, 30)
+    flags = R.RDIST_WEIGHTED if weighted else 0
+    D, info, g = ctx.solve(dev(A), -0.5, flags=flags, keep=True)
+    gamma, delta0 = info["gamma"], info["delta"]
+    for step in range(3):
+        changes, A = plan_batch(rng, A, 13, delta0, weighted)
+        inf = g.update_edges(changes, D=D)
+        check_full(ctx, g, A, gamma, D, inf, weighted, f"batch {step}")
+    g.release()
+
+
+def test_batch_equals_single_changes(ctx):
+    """The same 16 changes as two batches and one by one give the same D
+    (both checked against the oracle) and Y within the bounds."""
+    rng = gg.rng_for("update", 1700)
+    A = gg.erdos_renyi(500, 0.03, rng)
+    changes, A2 = plan_batch(rng, A, 16, int((A != 0).sum(axis=0).max()), False)
+    D1, info, g1 = ctx.solve(dev(A), -0.5, keep=True)
+    D2, _, g2 = ctx.solve(dev(A), -0.5, keep=True)
+    g1.update_edges(changes, D=D1)
+    for s, d, w in changes:
+        g2.update_edge(s, d, w, D=D2)
+    Yo = oracle.solve(A2, info["gamma"])
+    check_d(D1.cpu().numpy(), Yo.D, Yo.Y, info["gamma"], "batched")
+    check_d(D2.cpu().numpy(), Yo.D, Yo.Y, info["gamma"], "one by one")
+    check_y(g1.y().cpu().numpy(), Yo.Y, "batched")
+    check_y(g2.y().cpu().numpy(), Yo.Y, "one by one")
+    g1.release()
+    g2.release()
+
+
+def test_batch_refusal(ctx):
+    """A chunk whose intermediate graph breaks the gate is refused with the
+    rest of the list; earlier chunks stay applied."""
+    n = 50
+    A = gg.directed_cycle(n)
+    D, info, g = ctx.solve(dev(A), 0.6, keep=True)
+    Y0 = g.y().cpu().numpy()
+    D0 = D.cpu().numpy().copy()
+    inf = g.update_edges([(3, 10, 1), (3, 4, 0)], D=D)      # node 3 first gets 2 out-edges: 1.2 >= 1
+    assert inf["status"] == R.RDIST_E_NOT_DD
+    assert np.array_equal(g.y().cpu().numpy(), Y0) and np.array_equal(D.cpu().numpy(), D0)
+    inf = g.update_edges([(3, 4, 0), (3, 10, 1)], D=D)      # the other order passes
+    A[4, 3] = 0
+    A[10, 3] = 1
+    check_full(ctx, g, A, 0.6, D, inf, False, "cycle cut and chord")
+    first = [(k, k + 1, 0) for k in range(20, 28)]          # a chunk of 8 removals: applied
+    inf = g.update_edges(first + [(30, 35, 1), (30, 36, 1)], D=D)   # node 30 would get 2 out-edges
+    assert inf["status"] == R.RDIST_E_NOT_DD
+    for s, d, w in first:
+        A[d, s] = w
+    sol = oracle.solve(A, 0.6)
+    check_y(g.y().cpu().numpy(), sol.Y, "first chunk kept")
+    g.release()
+
+
+def test_batch_full_size(ctx):
+    """A batch of 8 changes on ER(8192, 0.02) at gamma = 0.5 / Delta (the
+    benchmark's graph and launch): sampled columns against the oracle's
+    series."""
+    rng = gg.rng_for("update", 18192)
+    n = 8192
+    A = gg.erdos_renyi(n, 0.02, rng)
+    D, info, g = ctx.solve(dev(A), -0.5, keep=True)
+    gamma = info["gamma"]
+    changes, A = plan_batch(rng, A, 8, info["delta"], False)
+    inf = g.update_edges(changes, D=D)
+    note(f"[update] batch n=8192: lost {inf['n_uncertified']}, re-inverted {inf['fallback_fraction']}")
+    assert inf["status"] == 0
+    Y = g.y()
+    cols = sorted({c[0] for c in changes} | {c[1] for c in changes} | {1, 8190})
+    for j in cols:
+        yo = oracle.y_column(A, gamma, j)
+        check_y(Y[:, j].cpu().numpy()[None, :], yo[None, :], f"column {j}")
+        Do = np.full(n, R.RDIST_UNREACHABLE, dtype=np.int16)
+        Do[yo > 0] = oracle.readout_entries(yo[yo > 0], gamma)
+        check_d(D[:, j].cpu().numpy(), Do, yo, gamma, f"column {j}")
+    del Y
+    g.release()
