@@ -679,6 +679,12 @@ def bench_f4(args, torch, R, gg):
     assert info["status"] == 0, info
     gamma, delta = info["gamma"], info["delta"]
     del Y, D
+    # one goal at a time on the same lattice (latency of a single row)
+    one = []
+    for k in range(3):
+        t1 = time.perf_counter()
+        _, _, inf1, steps1 = ctx.goal_rows(ptr, idx, goal_sets[k][:1], -0.5)
+        one.append((time.perf_counter() - t1) * 1e3)
     # the C2 graph: 64 goal rows against the full solve
     A_np = gg.erdos_renyi(8192, 0.02, gg.rng_for("f4", 1))
     p2, i2, _ = gg.csr_from_dense(A_np)
@@ -722,6 +728,7 @@ def bench_f4(args, torch, R, gg):
                      "traffic": read_traffic("k_rows_step_f4_lattice1m_pmc.md", sha), "avg_launch_ms": avg_ms,
                      "launches": st["launches"], "bytes_per_launch": per_launch_bytes, "source_sha": sha},
         "c2_graph": {"rows": 64, "ms": c2_rows_ms, "iterations": steps2, "full_solve_ms": c2_solve_ms},
+        "single_goal": {"ms": float(np.median(one)), "iterations": steps1},
     }
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle series row on the lattice)")
