@@ -92,6 +92,13 @@ struct BatchPlan {
     }
 };
 
+rdist_status ensure_capture_streams(rdist_ctx c) {
+    if (!c->capture) RD_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+    if (!c->capture_aux) RD_HIP(hipStreamCreateWithFlags(&c->capture_aux, hipStreamNonBlocking));
+    if (!c->capture_aux2) RD_HIP(hipStreamCreateWithFlags(&c->capture_aux2, hipStreamNonBlocking));
+    return RDIST_OK;
+}
+
 namespace {
 
 void free_plan(rdist_ctx c, BatchPlan *p) {
@@ -374,13 +381,6 @@ rdist_status enqueue_plan(BatchPlan &p, const hipStream_t st[3], hipEvent_t *mar
         }
     }
     RD_HIP(hipGetLastError());
-    return RDIST_OK;
-}
-
-rdist_status ensure_capture_streams(rdist_ctx c) {
-    if (!c->capture) RD_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
-    if (!c->capture_aux) RD_HIP(hipStreamCreateWithFlags(&c->capture_aux, hipStreamNonBlocking));
-    if (!c->capture_aux2) RD_HIP(hipStreamCreateWithFlags(&c->capture_aux2, hipStreamNonBlocking));
     return RDIST_OK;
 }
 

@@ -62,9 +62,14 @@ struct Workspace {
     Buf m32, v32, u32, s64, p32, cert, csr_cnt, csr_off, csr_col, r32, c32;
     Buf xh, xl, rh, rl;   // bf16 hi/lo parts of the FP32 inverse and of the scaled residual
     // goal rows: the two iteration states, and [info | bad flag | change flag | gamma^w table]
-    Buf rv, rmisc;
+    Buf rv, rmisc, rgoals;
     Buf gb;               // gain bounds: two vectors of n doubles and the iteration's scratch
     int32_t *rflag_h = nullptr;   // pinned host copy of the change flag
+    // a captured chunk of goal-row steps, replayed while its inputs stay the same
+    hipGraph_t rows_graph = nullptr;
+    hipGraphExec_t rows_exec = nullptr;
+    const void *rows_key[6] = {};
+    int64_t rows_key_n[3] = {};
     double *m() const { return (double *)M.p; }
     int32_t *outdeg() const { return (int32_t *)small.p; }
     int32_t *bad() const { return outdeg() + n_cap + 1; }
@@ -149,6 +154,7 @@ rdist_status ensure(rdist_ctx c, Buf &b, size_t bytes);
 rdist_status ensure_grow(rdist_ctx c, Buf &b, size_t bytes);
 void release(rdist_ctx c, Buf &b);
 rdist_status ensure_small(rdist_ctx c, Workspace &w, int n);
+rdist_status ensure_capture_streams(rdist_ctx c);   // the context's streams for graph capture (rd_batch.hip)
 rdist_status ensure_aux(Workspace &w);
 rdist_status ensure_aux2(Workspace &w);
 

@@ -407,8 +407,10 @@ void free_workspace(rdist_ctx c, Workspace &w) {
     free_transient_plan(c, w);
     for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2, &w.Pt2, &w.small,
                    &w.m32, &w.v32, &w.u32, &w.s64, &w.p32, &w.cert, &w.csr_cnt, &w.csr_off, &w.csr_col, &w.r32,
-                   &w.c32, &w.xh, &w.xl, &w.rh, &w.rl, &w.rv, &w.rmisc, &w.gb})
+                   &w.c32, &w.xh, &w.xl, &w.rh, &w.rl, &w.rv, &w.rmisc, &w.rgoals, &w.gb})
         release(c, *b);
+    if (w.rows_exec) (void)hipGraphExecDestroy(w.rows_exec);
+    if (w.rows_graph) (void)hipGraphDestroy(w.rows_graph);
     if (w.rflag_h) (void)hipHostFree(w.rflag_h);
     for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
         if (e) (void)hipEventDestroy(e);
@@ -733,28 +735,81 @@ rdist_status rdist_goal_rows(rdist_ctx c, int32_t n, const int64_t *succ_ptr, co
     int32_t *bad = (int32_t *)(misc + kRowsBad), *flag = (int32_t *)(misc + kRowsFlag);
     double *gpow = (double *)(misc + kRowsPow);
     double *V[2] = {(double *)w.rv.p, (double *)((char *)w.rv.p + vbytes)};
+    // the goals in workspace memory, so that a captured chunk serves any goal set
+    if ((st = ensure_grow(c, w.rgoals, (size_t)q * 4))) return st;
+    int32_t *wgoals = (int32_t *)w.rgoals.p;
+    RD_HIP(hipMemcpyAsync(wgoals, goals, (size_t)q * 4, hipMemcpyDeviceToDevice, s));
     rd::launch_info_set(dinfo, gamma, s);
     rd::launch_fill_i32(bad, 1, s);
     rd::launch_rows_check(succ_ptr, succ_idx, weights, n, nnz, gamma, dinfo, bad, gpow, s);
     rd::launch_fill_i32((int32_t *)V[0], vbytes / 4, s);
-    rd::RowsLaunch L{succ_ptr, succ_idx, weights, gpow, n, nnz, goals, q, dinfo};
-    int64_t k = 0;
-    int cur = 0;
-    for (;;) {
-        // kRowsCheckEvery steps, the last of which reports whether any entry changed
-        for (int t = 0; t < kRowsCheckEvery; ++t, ++k) {
+    rd::RowsLaunch L{succ_ptr, succ_idx, weights, gpow, n, nnz, wgoals, q, dinfo};
+    const double step_bytes = 16.0 * (double)vbytes / 8.0 + 8.0 * n + (weights ? 5.0 : 4.0) * (double)nnz;
+    // One chunk: kRowsCheckEvery steps (an even count, so the state ends in
+    // V[0] again), the last of which reports whether any entry changed, and
+    // the report's copy to the host.
+    auto enqueue_chunk = [&](hipStream_t cs, bool timed) {
+        int cur = 0;
+        for (int t = 0; t < kRowsCheckEvery; ++t) {
             const bool check = t == kRowsCheckEvery - 1;
-            if (check) rd::launch_fill_i32(flag, 1, s);
-            Timer tm(c, s, RDIST_K_ROWS_STEP, 0.0, 16.0 * (double)vbytes / 8.0 + 8.0 * n + (weights ? 5.0 : 4.0) * (double)nnz);
-            rd::launch_rows_step(L, V[cur], V[cur ^ 1], check ? flag : nullptr, s);
+            if (check) rd::launch_fill_i32(flag, 1, cs);
+            if (timed) {
+                Timer tm(c, cs, RDIST_K_ROWS_STEP, 0.0, step_bytes);
+                rd::launch_rows_step(L, V[cur], V[cur ^ 1], check ? flag : nullptr, cs);
+            } else {
+                rd::launch_rows_step(L, V[cur], V[cur ^ 1], check ? flag : nullptr, cs);
+            }
             cur ^= 1;
         }
+        return hipMemcpyAsync(w.rflag_h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, cs);
+    };
+    // per-step timing asks for the eager launches; otherwise the chunk is a
+    // HIP graph, captured once per (lists, weights, sizes, buffers)
+    const bool eager = (c->timing_mask & (1u << RDIST_K_ROWS_STEP)) != 0;
+    if (!eager) {
+        const void *key[6] = {succ_ptr, succ_idx, weights, w.rv.p, w.rmisc.p, wgoals};
+        const int64_t key_n[3] = {n, nnz, q};
+        bool same = w.rows_exec != nullptr;
+        for (int t = 0; t < 6 && same; ++t) same = key[t] == w.rows_key[t];
+        for (int t = 0; t < 3 && same; ++t) same = key_n[t] == w.rows_key_n[t];
+        if (!same) {
+            if (w.rows_exec) (void)hipGraphExecDestroy(w.rows_exec);
+            if (w.rows_graph) (void)hipGraphDestroy(w.rows_graph);
+            w.rows_exec = nullptr;
+            w.rows_graph = nullptr;
+            if ((st = ensure_capture_streams(c))) return st;
+            // the capture stream must see the set-up above
+            hipEvent_t ev = nullptr;
+            RD_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            RD_HIP(hipEventRecord(ev, s));
+            RD_HIP(hipStreamWaitEvent(c->capture, ev, 0));
+            (void)hipEventDestroy(ev);
+            RD_HIP(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+            const hipError_t ce = enqueue_chunk(c->capture, false);
+            hipGraph_t gr = nullptr;
+            const hipError_t ee = hipStreamEndCapture(c->capture, &gr);
+            if (ce != hipSuccess || ee != hipSuccess) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return fail(RDIST_E_HIP, std::string("goal rows capture: ") +
+                                             hipGetErrorString(ce != hipSuccess ? ce : ee));
+            }
+            w.rows_graph = gr;
+            RD_HIP(hipGraphInstantiate(&w.rows_exec, w.rows_graph, nullptr, nullptr, 0));
+            for (int t = 0; t < 6; ++t) w.rows_key[t] = key[t];
+            for (int t = 0; t < 3; ++t) w.rows_key_n[t] = key_n[t];
+        }
+    }
+    int64_t k = 0;
+    for (;;) {
+        if (eager) RD_HIP(enqueue_chunk(s, true));
+        else RD_HIP(hipGraphLaunch(w.rows_exec, s));
+        k += kRowsCheckEvery;
         RD_HIP(hipGetLastError());
-        RD_HIP(hipMemcpyAsync(w.rflag_h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         RD_HIP(hipStreamSynchronize(s));
         if (*w.rflag_h == 0) break;
         if (k >= kRowsMaxSteps) return fail(RDIST_E_STATE, "goal rows did not settle");
     }
+    const int cur = 0;
     rd::launch_rows_out(V[cur], n, q, Y_dev, D_dev, dinfo, s);
     RD_HIP(hipGetLastError());
     if (steps) *steps = (int32_t)std::min<int64_t>(k, 0x7FFFFFFF);

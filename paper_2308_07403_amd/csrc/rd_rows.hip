@@ -99,6 +99,7 @@ __global__ __launch_bounds__(256) void k_rows_step(const int64_t *__restrict__ p
         if (wts) {
             for (int64_t e = ptr[j] + s; e < e1; e += S) acc = fma(gpow[wts[e]], Vo[(size_t)idx[e] * G + g], acc);
         } else {
+#pragma unroll 4
             for (int64_t e = ptr[j] + s; e < e1; e += S) acc += Vo[(size_t)idx[e] * G + g];
         }
     }
@@ -305,8 +306,11 @@ void launch_rows_step(const RowsLaunch &L, const double *Vo, double *Vn, int32_t
         else step64<1>(L, Vo, Vn, flag, s);
         return;
     }
+    // successor slots per node: a quarter of the mean degree (each lane then
+    // walks a few successors, four loads in flight), so more nodes share a
+    // wavefront
     int S = 1;
-    while (S < deg && G * S < 64) S <<= 1;
+    while (S < deg / 4 && G * S < 64) S <<= 1;
     const int ls = ilog2(S);
     switch (ilog2(G)) {
         case 0: step_g<1>(ls, L, Vo, Vn, flag, s); break;

@@ -185,3 +185,31 @@ def test_rows_c2_graph(ctx):
     for k, g in enumerate(goals):
         yo = oracle.y_row_csr(ptr, idx, gamma, int(g))
         check_rows(Yg[k][None, :], Dg[k][None, :], yo[None, :], gamma, info["delta"], f"ER goal {g}")
+
+
+def test_captured_chunks_replay(ctx):
+    """The iteration's captured chunk is replayed across calls with other
+    goal sets and other work in between; every call matches the eager
+    launches (per-step timing on) bitwise, and the oracle."""
+    rng = gg.rng_for("rows", 900)
+    A = gg.grid_lattice_deleted(900, rng)
+    ptr, idx, _ = gg.csr_from_dense(A)
+    P, I = dev(ptr), dev(idx)
+    sol = oracle.solve(A, -0.5)
+    sets = [rng.integers(0, 900, size=q).astype(np.int32) for q in (5, 5, 64, 5)]
+    graph_out = []
+    for k, goals in enumerate(sets):
+        Y, D, info, steps = ctx.goal_rows(P, I, torch.from_numpy(goals), -0.5)
+        graph_out.append((Y.cpu().numpy(), D.cpu().numpy()))
+        ctx.solve(dev(gg.erdos_renyi(200, 0.05, rng)), -0.5)          # other work between replays
+        torch.cuda.synchronize()
+        check_rows(graph_out[-1][0], graph_out[-1][1], sol.Y[goals], sol.gamma, sol.delta, f"replay {k}",
+                   Do=sol.D[goals])
+    ctx.set_timing(True, classes=[R.RDIST_K_ROWS_STEP])
+    try:
+        for k, goals in enumerate(sets):
+            Y, D, info, steps = ctx.goal_rows(P, I, torch.from_numpy(goals), -0.5)
+            assert np.array_equal(Y.cpu().numpy(), graph_out[k][0]), k
+            assert np.array_equal(D.cpu().numpy(), graph_out[k][1]), k
+    finally:
+        ctx.set_timing(False)
