@@ -15,9 +15,11 @@
 //
 // Layout: q goals in chunks of G (one chunk per grid row); the state of a
 // chunk is node-major, V[j][g] (G doubles per node), so a successor's values
-// for all G goals are one contiguous read.  A wavefront's 64 lanes are
-// (N nodes) x (S successor slots) x (G goals), N = 64 / (G S); the S partial
-// sums of a node are combined by lane shuffles.
+// for all G goals are one contiguous read.  Three step kernels: 64 goals
+// with a batch of nodes per wavefront (lane = goal); 2 .. 32 goals on sparse
+// graphs with one node per lane; otherwise a wavefront's 64 lanes as
+// (N nodes) x (S successor slots) x (G goals), N = 64 / (G S), the S partial
+// sums of a node combined by lane shuffles.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -180,6 +182,69 @@ __global__ __launch_bounds__(256) void k_rows_step64(const int64_t *__restrict__
     if (flag && __any(changed) && lane == 0) *flag = 1;
 }
 
+// The step for chunks of 2 .. 32 goals, one node per lane: the lane keeps its
+// node's G sums in registers and reads each successor's G values as one
+// contiguous G x 8 bytes (whole cache lines from G = 16 on); 64 consecutive
+// nodes per wavefront, contiguous node ranges per XCD.  Sums run in edge
+// order.
+template <int G>
+__global__ __launch_bounds__(256) void k_rows_step_lane(const int64_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ idx,
+                                                        const uint8_t *__restrict__ wts,
+                                                        const double *__restrict__ gpow, int n,
+                                                        const int32_t *__restrict__ goals, int q,
+                                                        const double *__restrict__ Vold, double *__restrict__ Vnew,
+                                                        const rdist_info *__restrict__ info,
+                                                        int32_t *__restrict__ flag) {
+    if (info->status != RDIST_OK) return;
+    const double gamma = info->gamma;
+    const int per = gridDim.x / 8;
+    const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int j = blk * 256 + (int)threadIdx.x;
+    const size_t base = (size_t)blockIdx.y * n * G;
+    const double *__restrict__ Vo = Vold + base;
+    bool changed = false;
+    if (j < n) {
+        double acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = 0.0;
+        const int64_t e1 = ptr[j + 1];
+        for (int64_t e = ptr[j]; e < e1; ++e) {
+            const double *__restrict__ src = Vo + (size_t)idx[e] * G;
+            const double x = wts ? gpow[wts[e]] : 1.0;
+#pragma unroll
+            for (int g = 0; g < G; g += 2) {
+                const double2 v = *reinterpret_cast<const double2 *>(src + g);
+                if (wts) {
+                    acc[g] = fma(x, v.x, acc[g]);
+                    acc[g + 1] = fma(x, v.y, acc[g + 1]);
+                } else {
+                    acc[g] += v.x;
+                    acc[g + 1] += v.y;
+                }
+            }
+        }
+        const double *__restrict__ own = Vo + (size_t)j * G;
+        double *__restrict__ out = Vnew + base + (size_t)j * G;
+#pragma unroll
+        for (int g = 0; g < G; g += 2) {
+            double v2[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = blockIdx.y * G + g + h;
+                const double seed = (k < q && goals[k] == j) ? 1.0 : 0.0;
+                v2[h] = wts ? seed + acc[g + h] : fma(gamma, acc[g + h], seed);
+            }
+            if (flag) {
+                const double2 o = *reinterpret_cast<const double2 *>(own + g);
+                changed = changed || v2[0] != o.x || v2[1] != o.y;
+            }
+            *reinterpret_cast<double2 *>(out + g) = make_double2(v2[0], v2[1]);
+        }
+    }
+    if (flag && __any(changed) && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
 // Rows out: Y[k * n + j] and the readout D[k * n + j] (either nullable);
 // status not OK: Y = 0 and D = the sentinel.
 template <int G>
@@ -296,6 +361,22 @@ void step64(const RowsLaunch &L, const double *Vo, double *Vn, int32_t *flag, hi
 void launch_rows_step(const RowsLaunch &L, const double *Vo, double *Vn, int32_t *flag, hipStream_t s) {
     const int G = rows_group(L.q);
     const int deg = (int)std::max<int64_t>(1, (L.nnz + L.n - 1) / std::max(L.n, 1));
+    if (G >= 2 && G <= 32 && deg <= 16) {   // sparse graphs: a lane walks its node's few successors
+        const int blocks = (L.n + 255) / 256;
+        const dim3 grid(((blocks + 7) / 8) * 8, (L.q + G - 1) / G);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, L.ptr, L.idx, L.wts, L.wts ? L.gpow : nullptr, L.n,
+                               L.goals, L.q, Vo, Vn, L.info, flag);
+        };
+        switch (ilog2(G)) {
+            case 1: go(k_rows_step_lane<2>); break;
+            case 2: go(k_rows_step_lane<4>); break;
+            case 3: go(k_rows_step_lane<8>); break;
+            case 4: go(k_rows_step_lane<16>); break;
+            default: go(k_rows_step_lane<32>); break;
+        }
+        return;
+    }
     if (G == 64) {
         // nodes per wavefront: about 64 edges' worth, at most 16
         const int nb = std::max(1, std::min(16, 64 / deg));
