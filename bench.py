@@ -683,7 +683,7 @@ def bench_f4(args, torch, R, gg):
     one = []
     for k in range(3):
         t1 = time.perf_counter()
-        _, _, inf1, steps1 = ctx.goal_rows(ptr, idx, goal_sets[k][:1], -0.5)
+        _, _, inf1, steps1 = ctx.goal_rows(ptr, idx, goal_sets[k % len(goal_sets)][:1], -0.5)
         one.append((time.perf_counter() - t1) * 1e3)
     # the C2 graph: 64 goal rows against the full solve
     A_np = gg.erdos_renyi(8192, 0.02, gg.rng_for("f4", 1))
