@@ -56,6 +56,13 @@ def test_synchronous_argument_errors_without_device(lib):
     assert R.rdist_epilogue(None, None, 4, 4, 0.5, None, None, None) == R.RDIST_E_ARG
     assert R.rdist_create(None, 0, 0, None, 0) == R.RDIST_E_ARG
     assert R.rdist_hbm_in_use(None) == 0
+    # the widened entry points refuse NULL handles the same way
+    assert R.rdist_graph_update_edge(None, None, 0, 1, 1, None, None, None) == R.RDIST_E_ARG
+    assert R.rdist_graph_update_edges(None, None, 1, None, None, None, None, None, None) == R.RDIST_E_ARG
+    assert R.rdist_goal_rows(None, 4, None, None, 0, None, 0.1, None, 1, None, None, None, None, None) == R.RDIST_E_ARG
+    assert R.rdist_goal_paths(None, 4, None, None, 0, None, None, None, 1, 1, None, None) == R.RDIST_E_ARG
+    assert R.rdist_gain_bounds(None, None, 4, 0, 16, 0.0, None, None) == R.RDIST_E_ARG
+    assert R.rdist_certify(None, None, None, None, None) == R.RDIST_E_ARG
     R.rdist_graph_release(None)
     R.rdist_destroy(None)
 
@@ -72,3 +79,12 @@ def test_oracle_and_engine_share_nothing():
             assert "import oracle" not in open(p).read()
     otext = open(os.path.join(ROOT, "oracle", "rdist_oracle.c")).read()
     assert "rdist.h" not in otext and "rd_device" not in otext
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with a message before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
