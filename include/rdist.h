@@ -333,8 +333,13 @@ rdist_status rdist_gain_bounds(rdist_ctx ctx, const uint8_t *A_dev, int32_t n, i
  * "unreachable" when e gamma^(n-1) > DBL_MIN (then no reachable entry can
  * underflow); entries below DBL_MIN are not certified.  mask_dev
  * (nullable, device, n x n bytes) receives 1 for certified entries;
- * *n_certified (host) their count.  Unweighted graphs only (RDIST_E_ARG
- * otherwise).  Synchronous.
+ * *n_certified (host) their count.  For graphs solved with RDIST_WEIGHTED
+ * the bound covers positive integer weights: a true distance of k + 1 or
+ * more makes every walk of l edges weigh at least max(l, k + 1), so
+ *   Y_ij <= gamma^(k+1) (Delta^(k+1) - 1) / (Delta - 1)
+ *           + (gamma Delta)^(k+2) / (Delta (1 - gamma Delta))
+ * ((k + 1) gamma^(k+1) + gamma^(k+2) / (1 - gamma) for Delta = 1), with
+ * Delta the largest number of out-edges.  Synchronous.
  */
 rdist_status rdist_certify(rdist_ctx ctx, rdist_graph g, uint8_t *mask_dev, int64_t *n_certified, void *stream);
 

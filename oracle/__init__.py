@@ -340,6 +340,35 @@ def certify(Y, D, gamma: float, delta: int) -> np.ndarray:
     return out
 
 
+def certify_weighted(Y, D, gamma: float, delta: int) -> np.ndarray:
+    """Per-entry certificate for positive integer weights (Sec. 3.2 with the
+    walk-count bound Eq. Nijk-limit): with k = D, a true distance of k + 1 or
+    more makes every walk of l edges weigh at least max(l, k + 1), so
+    Y <= sum_l Delta^(l-1) gamma^max(l, k+1)
+      = gamma^(k+1) (Delta^(k+1) - 1) / (Delta - 1) + (gamma Delta)^(k+2) / (Delta (1 - gamma Delta))
+    ((k + 1) gamma^(k+1) + gamma^(k+2) / (1 - gamma) for Delta = 1); Y above
+    that proves D exact.  Zeros and entries below DBL_MIN as in certify."""
+    Y = np.asarray(Y, dtype=np.float64)
+    k = np.asarray(D, dtype=np.float64)
+    dl = float(max(delta, 1))
+    tiny = np.finfo(np.float64).tiny
+    zero_ok = (Y.shape[0] - 1) * math.log(gamma) > math.log(tiny) + 1.0
+    out = (Y == 0.0) & zero_ok
+    pos = Y >= tiny
+    kp = k[pos]
+    if dl == 1.0:
+        first = np.log(kp + 1.0) + (kp + 1.0) * math.log(gamma)
+        second = (kp + 2.0) * math.log(gamma) - math.log(1.0 - gamma)
+    else:
+        # ln((Delta^(k+1) - 1) / (Delta - 1)) = (k+1) ln Delta + ln(1 - Delta^-(k+1)) - ln(Delta - 1)
+        first = ((kp + 1.0) * math.log(gamma) + (kp + 1.0) * math.log(dl) + np.log1p(-dl ** (-(kp + 1.0)))
+                 - math.log(dl - 1.0))
+        second = (kp + 2.0) * math.log(gamma * dl) - math.log(dl * (1.0 - gamma * dl))
+    lb = np.logaddexp(first, second)
+    out[pos] = np.log(Y[pos]) > lb
+    return out
+
+
 def gain_bounds(delta: int, d: int) -> dict:
     """The paper's gain bounds for largest out-degree Delta and diameter d:
     Theorem 2 (1 / (Delta + Delta^(d-1))), Theorem 3 for trees, and the

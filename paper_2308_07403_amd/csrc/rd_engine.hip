@@ -890,7 +890,6 @@ rdist_status rdist_gain_bounds(rdist_ctx c, const uint8_t *A_dev, int32_t n, int
 rdist_status rdist_certify(rdist_ctx c, rdist_graph g, uint8_t *mask_dev, int64_t *n_certified, void *stream) {
     if (!c || !g || !n_certified) return fail(RDIST_E_ARG, "NULL argument");
     if (g->ctx != c) return fail(RDIST_E_STATE, "graph belongs to another context");
-    if (g->weighted) return fail(RDIST_E_ARG, "the certificate covers unweighted graphs");
     Guard gd(c);
     RD_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
@@ -901,7 +900,7 @@ rdist_status rdist_certify(rdist_ctx c, rdist_graph g, uint8_t *mask_dev, int64_
     rd::launch_fill_i32((int32_t *)cnt, 2, s);
     {
         Timer tm(c, s, RDIST_K_CERTIFY, 0.0, (8.0 + (mask_dev ? 1.0 : 0.0)) * (double)g->n * g->n);
-        rd::launch_certify(g->Y, g->ld, g->n, g->ginfo, mask_dev, cnt, s);
+        rd::launch_certify(g->Y, g->ld, g->n, g->ginfo, g->weighted != 0, mask_dev, cnt, s);
     }
     RD_HIP(hipGetLastError());
     unsigned long long h = 0;

@@ -14,6 +14,7 @@
 // would give Y <= gamma^(k+1) Delta^k / (1 - gamma Delta) (Eq. Y-bracket).
 // So Y above that bound proves D_ij exact; Y = 0 proves "unreachable" when
 // gamma^(n-1) (the smallest value of a reachable entry) is well above DBL_MIN.
+// With integer weights the bound sums over walk lengths (weighted_bound_ln).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -145,6 +146,24 @@ __global__ void k_power_fold(PowerScratch *sc, int last_step) {
     atomicMin(&sc->best_hi, sc->slot[s][1]);
 }
 
+// ln of the weighted bound for readout k (positive integer weights, Sec. 3.2):
+// a true distance of k + 1 or more makes every walk of l edges weigh at least
+// max(l, k + 1), so Y <= gamma^(k+1) (Delta^(k+1) - 1) / (Delta - 1)
+// + (gamma Delta)^(k+2) / (Delta (1 - gamma Delta)); Delta = 1:
+// (k + 1) gamma^(k+1) + gamma^(k+2) / (1 - gamma).
+__device__ __forceinline__ double weighted_bound_ln(double k, double lg, double ld, double delta, double gamma) {
+    double first, second;
+    if (delta == 1.0) {
+        first = log(k + 1.0) + (k + 1.0) * lg;
+        second = (k + 2.0) * lg - log1p(-gamma);
+    } else {
+        first = (k + 1.0) * (lg + ld) + log1p(-exp(-(k + 1.0) * ld)) - log(delta - 1.0);
+        second = (k + 2.0) * (lg + ld) - ld - log1p(-gamma * delta);
+    }
+    const double m = fmax(first, second);
+    return m + log1p(exp(fmin(first, second) - m));
+}
+
 constexpr int kCertChunk = 2048;   // columns per step of the certificate pass (8 per thread)
 
 // Per-entry certificate over a kept graph's Y: mask (nullable, n x n bytes,
@@ -160,6 +179,7 @@ constexpr int kCertChunk = 2048;   // columns per step of the certificate pass (
 // wavefronts diverge into it.  At most 1024 workgroups stride over rows
 // (one count atomic each); each thread loads its 8 columns of a chunk before
 // working on them.
+template <bool W>
 __global__ __launch_bounds__(256) void k_certify(const double *__restrict__ Y, int ld, int n,
                                                  const rdist_info *__restrict__ ginfo, uint8_t *__restrict__ mask,
                                                  unsigned long long *__restrict__ count) {
@@ -168,7 +188,13 @@ __global__ __launch_bounds__(256) void k_certify(const double *__restrict__ Y, i
     const double gamma = ginfo->gamma;
     const double delta = (double)max(ginfo->delta, 1);
     const double lgd = log(gamma * delta);
-    const double l0 = -log(delta * (1.0 - gamma * delta)) + log1p(0x1p-30) - log1p(-0x1p-30);
+    const double margin = log1p(0x1p-30) - log1p(-0x1p-30);
+    const double l0 = -log(delta * (1.0 - gamma * delta)) + margin;
+    const double lg = log(gamma), lde = log(delta);
+    // ln of the bound for readout k, the margins included
+    auto bound_ln = [&](double k) {
+        return W ? weighted_bound_ln(k, lg, lde, delta, gamma) + margin : (k + 1.0) * lgd + l0;
+    };
     const double il = rd_inv_log(gamma);
     const double s2 = kLn2 * il;                   // log2 units to R units (< 0)
     const double band = 1e-4 - 4e-6 * s2;          // the readout's short-path band
@@ -208,7 +234,7 @@ __global__ __launch_bounds__(256) void k_certify(const double *__restrict__ Y, i
                     ok = -1;
                     if (fabs(te - rint(te)) > band) {
                         const double k = fmin(fmax(ceil(te), kDMin), kDMax);
-                        const double diff = l2 * kLn2 - ((k + 1.0) * lgd + l0);
+                        const double diff = l2 * kLn2 - bound_ln(k);
                         if (fabs(diff) > 1e-5) ok = diff > 0.0;
                     }
                 }
@@ -225,7 +251,7 @@ __global__ __launch_bounds__(256) void k_certify(const double *__restrict__ Y, i
                 const int j = queue[t];
                 const double y = yr[j];
                 const int k = rd_encode(y, il, dummy);
-                const bool ok = log(y) > (double)(k + 1) * lgd + l0;
+                const bool ok = log(y) > bound_ln((double)k);
                 if (mask) mask[(size_t)i * n + j] = ok ? 1 : 0;
                 c += ok ? 1 : 0;
             }
@@ -275,10 +301,13 @@ void power_read(const void *host_copy, double *lo_ratio, double *hi_ratio, int *
     *bad = sc->bad;
 }
 
-void launch_certify(const double *Y, int ld, int n, const rdist_info *ginfo, uint8_t *mask,
+void launch_certify(const double *Y, int ld, int n, const rdist_info *ginfo, bool weighted, uint8_t *mask,
                     unsigned long long *count, hipStream_t s) {
     const int blocks = std::min(n, 1024);
-    hipLaunchKernelGGL(k_certify, dim3(blocks), dim3(256), 0, s, Y, ld, n, ginfo, mask, count);
+    if (weighted)
+        hipLaunchKernelGGL(k_certify<true>, dim3(blocks), dim3(256), 0, s, Y, ld, n, ginfo, mask, count);
+    else
+        hipLaunchKernelGGL(k_certify<false>, dim3(blocks), dim3(256), 0, s, Y, ld, n, ginfo, mask, count);
 }
 
 }  // namespace rd

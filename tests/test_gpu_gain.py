@@ -7,7 +7,8 @@ than 1e-6 relative on strongly connected graphs; Delta exact; the gain
 bounds equal the oracle's formulas to 1e-15 relative.  Certificate: the
 mask equals the oracle's on the oracle's Y except entries within 1e-8 of the
 bound in log space (Y differs by rounding and the kernel keeps a 2^-30
-margin); every certified GPU entry has D equal to the BFS distance.
+margin); every certified GPU entry has D equal to the BFS (or, with
+weights, Dijkstra) distance.
 """
 import math
 import sys
@@ -113,12 +114,37 @@ def test_certificate_matches_oracle(ctx):
             g.release()
 
 
-def test_certificate_refuses_weighted(ctx):
-    W = gg.weighted(gg.erdos_renyi(60, 0.1, gg.rng_for("gain", 4)), gg.rng_for("gain", 5), 1, 9)
-    _, _, g = ctx.solve(dev(W), -0.5, flags=R.RDIST_WEIGHTED, keep=True)
-    with pytest.raises(R.RdistError):
-        ctx.certify(g)
-    g.release()
+def test_certificate_weighted(ctx):
+    """Weighted graphs: the mask equals the oracle's weighted certificate
+    (except within 1e-8 of the bound in log space) and every certified GPU
+    entry is the Dijkstra distance."""
+    import scipy.sparse.csgraph as csg
+    rng = gg.rng_for("gain", 4)
+    for n, p, hi in ((150, 0.05, 9), (300, 0.02, 30)):
+        W = gg.weighted(gg.erdos_renyi(n, p, rng), rng, 1, hi)
+        dist = csg.shortest_path(np.ascontiguousarray(W.T, dtype=np.float64), directed=True).T
+        reach = np.isfinite(dist)
+        delta = int((W != 0).sum(axis=0).max())
+        for gamma in (1e-9, 1e-5, 0.1 / delta, 0.6 / delta):
+            sol = oracle.solve_weighted(W, gamma)
+            D, info, g = ctx.solve(dev(W), gamma, flags=R.RDIST_WEIGHTED, keep=True)
+            cnt, mask = ctx.certify(g, want_mask=True)
+            m = mask.cpu().numpy().astype(bool)
+            want = oracle.certify_weighted(sol.Y, sol.D, sol.gamma, delta)
+            assert cnt == int(m.sum())
+            diff = m != want
+            if diff.any():
+                k = sol.D[diff].astype(np.float64)
+                d = float(max(delta, 1))
+                first = (k + 1) * math.log(gamma) + (k + 1) * math.log(d) + np.log1p(-d ** (-(k + 1))) - math.log(d - 1)
+                second = (k + 2) * math.log(gamma * d) - math.log(d * (1 - gamma * d))
+                lb = np.logaddexp(first, second)
+                assert np.all(np.abs(np.log(sol.Y[diff]) - lb) < 1e-8), (n, gamma, int(diff.sum()))
+            Dg = D.cpu().numpy()
+            assert np.all(Dg[m & reach] == dist[m & reach].astype(np.int64)), (n, gamma)
+            assert np.all(Dg[m & ~reach] == R.RDIST_UNREACHABLE)
+            note(f"[cert] weighted n={n} gamma={gamma:.3g}: {cnt} of {n * n} certified")
+            g.release()
 
 
 def test_gain_bounds_c2_size(ctx):

@@ -752,3 +752,36 @@ def test_hanoi_and_power_law_generators():
         assert diameter(bfs_scipy(H)) == 2 ** k - 1
     B = gg.barabasi_albert(200, 2, gg.rng_for("pin", 960))
     assert np.array_equal(B, B.T) and int(B.sum()) == 2 * (3 + 2 * (200 - 3))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weighted_certificate_implies_dijkstra(seed):
+    """The weighted certificate accepts only entries whose D is the weighted
+    graph distance (Dijkstra, scipy), at gains from tiny to the gate, and
+    accepts every entry above DBL_MIN once gamma (Delta^(d+1) - 1) / (Delta - 1)
+    is small;
+    on unit weights it accepts a subset of what the unweighted certificate
+    accepts (its bound is at least as large)."""
+    rng = gg.rng_for("pin", 980 + seed)
+    n = int(rng.integers(15, 40))
+    A = gg.erdos_renyi(n, 0.12, rng)
+    W = gg.weighted(A, rng, 1, 9)
+    dist = csg.shortest_path(np.ascontiguousarray(W.T, dtype=np.float64), directed=True).T
+    delta = int((W != 0).sum(axis=0).max())
+    if delta == 0:
+        return
+    reach = np.isfinite(dist)
+    for gamma in (1e-9, 1e-4, 0.05 / delta, 0.5 / delta, 0.95 / delta):
+        sol = oracle.solve_weighted(W, gamma)
+        ok = oracle.certify_weighted(sol.Y, sol.D, sol.gamma, delta)
+        assert np.all(sol.D[ok & reach] == dist[ok & reach].astype(np.int64))
+        assert np.all(sol.D[ok & ~reach] == oracle.UNREACHABLE)
+    dmax = int(dist[reach].max())
+    g_all = 0.5 * (delta - 1) / (delta ** (dmax + 1) - 1) if delta > 1 else 0.5 / (dmax + 2)
+    sol = oracle.solve_weighted(W, g_all)
+    normal = sol.Y >= np.finfo(np.float64).tiny          # long weighted distances underflow at such gains
+    assert normal[reach].any()
+    assert oracle.certify_weighted(sol.Y, sol.D, sol.gamma, delta)[reach & normal].all()
+    sol = oracle.solve(A, 0.3 / delta)
+    assert not np.any(oracle.certify_weighted(sol.Y, sol.D, sol.gamma, delta)
+                      & ~oracle.certify(sol.Y, sol.D, sol.gamma, delta))
