@@ -843,30 +843,40 @@ rdist_status rdist_gain_bounds(rdist_ctx c, const uint8_t *A_dev, int32_t n, int
     RD_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     Workspace &w = c->ws[s];
-    const size_t vb = (((size_t)n * 8 + 255) / 256) * 256, sb = rd::power_scratch_bytes();
+    const size_t vb = (((size_t)n * 8 + 255) / 256) * 256, sb = (rd::power_scratch_bytes() + 255) & ~(size_t)255;
+    const size_t db = (((size_t)n + 2) * 4 + 255) & ~(size_t)255;
     rdist_status st;
-    if ((st = ensure_grow(c, w.gb, 2 * vb + sb))) return st;
-    double *x[2] = {(double *)w.gb.p, (double *)((char *)w.gb.p + vb)};
-    void *scratch = (char *)w.gb.p + 2 * vb;
-    std::vector<char> host(sb);
-    rd::launch_gamma_check(A_dev, n, scratch, s);
+    if ((st = ensure_grow(c, w.gb, 2 * vb + sb + db + 256))) return st;
+    char *base = (char *)w.gb.p;
+    double *x[2] = {(double *)base, (double *)(base + vb)};
+    void *scratch = base + 2 * vb;
+    int32_t *outdeg = (int32_t *)(base + 2 * vb + sb), *badp = outdeg + n + 1;
+    rdist_info *ginf = (rdist_info *)(base + 2 * vb + sb + db);
+    std::vector<char> host(rd::power_scratch_bytes());
+    // Delta and the input check (0/1 entries, no self-loop): the solve's gate
+    rd::launch_gate(A_dev, n, -0.5, outdeg, badp, ginf, s);
+    rd::launch_power_init(scratch, s);
+    rdist_info gi{};
+    RD_HIP(hipMemcpyAsync(&gi, ginf, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
+    RD_HIP(hipStreamSynchronize(s));
+    const int delta = gi.delta, bad = gi.status == RDIST_E_ADJ;
     const double u = 0x1p-53;
     double lo = 1.0, hi = HUGE_VAL;
-    int delta = 0, bad = 0, k = 0;
-    while (k < max_steps) {
+    int k = 0;
+    while (!bad && k < max_steps) {
         const int chunk = std::min(16, max_steps - k);
         for (int t = 0; t < chunk; ++t, ++k) rd::launch_power_step(A_dev, n, x[k & 1], x[(k & 1) ^ 1], scratch, k, s);
         rd::launch_power_fold(scratch, k - 1, s);
         RD_HIP(hipGetLastError());
-        RD_HIP(hipMemcpyAsync(host.data(), scratch, sb, hipMemcpyDeviceToHost, s));
+        RD_HIP(hipMemcpyAsync(host.data(), scratch, host.size(), hipMemcpyDeviceToHost, s));
         RD_HIP(hipStreamSynchronize(s));
         double lr, hr;
-        rd::power_read(host.data(), &lr, &hr, &delta, &bad);
+        rd::power_read(host.data(), &lr, &hr);
         // each ratio carries the rounding of a sum of at most Delta + 1 terms and a quotient
         const double m = (delta + 3) * u;
         lo = std::max(0.0, lr * (1.0 - m) - 1.0);
         hi = std::min((double)delta, hr * (1.0 + m) - 1.0);
-        if (bad || hi - lo <= rel_tol * hi) break;
+        if (hi - lo <= rel_tol * hi) break;
     }
     rdist_gain_report r{};
     r.status = bad ? RDIST_E_ADJ : RDIST_OK;

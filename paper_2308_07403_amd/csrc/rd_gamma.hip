@@ -29,32 +29,15 @@ namespace {
 constexpr double kXFloor = 0x1p-900;
 
 // Slots of the power iteration's scratch (doubles as bit patterns where
-// atomics need them): per step parity-of-three a triple {min ratio, max
-// ratio, max of Bx}; then the best bounds and Delta / status.
+// atomics need them): per step, in a rotation of three, {min ratio, max
+// ratio, max of Bx}; then the best bounds over all steps.
 struct PowerScratch {
     unsigned long long slot[3][4];     // [0] min ratio, [1] max ratio, [2] max Bx (bits of positive doubles)
     unsigned long long best_lo, best_hi;
-    int32_t delta, bad;
 };
 
 __device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
-
-// Delta (largest out-degree = column count of A) and input check (entries
-// 0/1, zero diagonal), one thread per column.
-__global__ __launch_bounds__(256) void k_gamma_check(const uint8_t *__restrict__ A, int n, PowerScratch *sc) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    int c = 0;
-    bool ok = A[(size_t)j * n + j] == 0;
-    for (int i = 0; i < n; ++i) {
-        const int a = A[(size_t)i * n + j];
-        c += a;
-        ok = ok && a <= 1;
-    }
-    atomicMax(&sc->delta, c);
-    if (!ok) atomicOr(&sc->bad, 1);
-}
 
 __global__ void k_gamma_init(PowerScratch *sc) {
     for (int s = 0; s < 3; ++s) {
@@ -64,8 +47,6 @@ __global__ void k_gamma_init(PowerScratch *sc) {
     }
     sc->best_lo = dbits(1.0);
     sc->best_hi = dbits(__builtin_huge_val());
-    sc->delta = 0;
-    sc->bad = 0;
 }
 
 // One step: y = (A + I) x with x = xin * scale (scale = 1 / max of the last
@@ -275,10 +256,8 @@ __global__ __launch_bounds__(256) void k_certify(const double *__restrict__ Y, i
 
 size_t power_scratch_bytes() { return sizeof(PowerScratch); }
 
-void launch_gamma_check(const uint8_t *A, int n, void *scratch, hipStream_t s) {
-    PowerScratch *sc = (PowerScratch *)scratch;
-    hipLaunchKernelGGL(k_gamma_init, dim3(1), dim3(1), 0, s, sc);
-    hipLaunchKernelGGL(k_gamma_check, dim3((n + 255) / 256), dim3(256), 0, s, A, n, sc);
+void launch_power_init(void *scratch, hipStream_t s) {
+    hipLaunchKernelGGL(k_gamma_init, dim3(1), dim3(1), 0, s, (PowerScratch *)scratch);
 }
 
 void launch_power_step(const uint8_t *A, int n, const double *x, double *y, void *scratch, int step, hipStream_t s) {
@@ -290,15 +269,13 @@ void launch_power_fold(void *scratch, int last_step, hipStream_t s) {
     hipLaunchKernelGGL(k_power_fold, dim3(1), dim3(1), 0, s, (PowerScratch *)scratch, last_step);
 }
 
-void power_read(const void *host_copy, double *lo_ratio, double *hi_ratio, int *delta, int *bad) {
+void power_read(const void *host_copy, double *lo_ratio, double *hi_ratio) {
     const PowerScratch *sc = (const PowerScratch *)host_copy;
     double lo, hi;
     memcpy(&lo, &sc->best_lo, 8);
     memcpy(&hi, &sc->best_hi, 8);
     *lo_ratio = lo;
     *hi_ratio = hi;
-    *delta = sc->delta;
-    *bad = sc->bad;
 }
 
 void launch_certify(const double *Y, int ld, int n, const rdist_info *ginfo, bool weighted, uint8_t *mask,

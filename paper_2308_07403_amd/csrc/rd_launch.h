@@ -176,10 +176,10 @@ void launch_rows_paths(const int64_t *ptr, const int32_t *idx, int n, int64_t nn
                        const int32_t *goals, const int32_t *starts, int q, int max_hops, int32_t *out, hipStream_t s);
 // Gain bounds and the per-entry certificate (rd_gamma.hip).
 size_t power_scratch_bytes();
-void launch_gamma_check(const uint8_t *A, int n, void *scratch, hipStream_t s);
+void launch_power_init(void *scratch, hipStream_t s);
 void launch_power_step(const uint8_t *A, int n, const double *x, double *y, void *scratch, int step, hipStream_t s);
 void launch_power_fold(void *scratch, int last_step, hipStream_t s);
-void power_read(const void *host_copy, double *lo_ratio, double *hi_ratio, int *delta, int *bad);
+void power_read(const void *host_copy, double *lo_ratio, double *hi_ratio);
 void launch_certify(const double *Y, int ld, int n, const rdist_info *ginfo, bool weighted, uint8_t *mask,
                     unsigned long long *count, hipStream_t s);
 void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
