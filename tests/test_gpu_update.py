@@ -431,3 +431,53 @@ def test_batch_full_size(ctx):
         check_d(D[:, j].cpu().numpy(), Do, yo, gamma, f"column {j}")
     del Y
     g.release()
+
+
+def test_long_change_sequence_full_size(ctx):
+    """256 changes (alternating removals and additions, one at a time and in
+    batches) on ER(8192, 0.02): the bounds carried through every change keep
+    D exact; sampled columns against the oracle's series at the end."""
+    rng = gg.rng_for("update", 28192)
+    n = 8192
+    A = gg.erdos_renyi(n, 0.02, rng)
+    D, info, g = ctx.solve(dev(A), -0.5, keep=True)
+    gamma, delta = info["gamma"], info["delta"]
+    outdeg = (A != 0).sum(axis=0).astype(np.int64)
+    changes = []
+    for k in range(256):
+        while True:
+            s, d = map(int, rng.integers(0, n, size=2))
+            if s == d:
+                continue
+            if k % 2 == 0 and A[d, s]:
+                w = 0
+                break
+            if k % 2 == 1 and not A[d, s] and outdeg[s] < delta:
+                w = 1
+                break
+        outdeg[s] += 1 if w else -1
+        A[d, s] = w
+        changes.append((s, d, w))
+    lost = reinv = 0
+    for s, d, w in changes[:128]:
+        inf = g.update_edge(s, d, w)
+        assert inf["status"] == 0
+        lost += inf["n_uncertified"]
+        reinv += inf["fallback_fraction"] == 1.0
+    for k in range(128, 256, 32):
+        inf = g.update_edges(changes[k:k + 32], D=D if k == 224 else None)
+        assert inf["status"] == 0
+        lost += inf["n_uncertified"]
+        reinv += inf["fallback_fraction"] == 1.0
+    note(f"[update] 256 changes at n=8192: lost {lost}, re-inversions {reinv}")
+    Y = g.y()
+    touched = sorted({c[0] for c in changes[-8:]} | {c[1] for c in changes[-8:]} | {0, 8191})
+    for j in touched:
+        yo = oracle.y_column(A, gamma, j)
+        rel = check_y(Y[:, j].cpu().numpy()[None, :], yo[None, :], f"column {j}")
+        Do = np.full(n, R.RDIST_UNREACHABLE, dtype=np.int16)
+        Do[yo > 0] = oracle.readout_entries(yo[yo > 0], gamma)
+        check_d(D[:, j].cpu().numpy(), Do, yo, gamma, f"column {j}")
+    note(f"[update] last column max rel {rel:.2e}")
+    del Y
+    g.release()
