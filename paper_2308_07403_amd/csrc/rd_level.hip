@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "rd_device.h"
 #include "rd_gj.h"
 #include "rd_launch.h"
@@ -18,6 +20,12 @@ namespace rd {
 __global__ void k_counter_zero(int32_t *p, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0;
+}
+
+// p[0, count) = 0 for any count (grid-stride, 64-bit offsets).
+__global__ void k_zero_words(int32_t *p, size_t count) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 // One graph with 128 < n <= 512 on one workgroup: blocked Gauss-Jordan with
@@ -613,7 +621,8 @@ int batched_blocks_per_cu() {
 
 void launch_fill_i32(int32_t *p, size_t count, hipStream_t s) {
     if (!count) return;
-    hipLaunchKernelGGL(k_counter_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, (int)count);
+    const size_t blocks = std::min<size_t>((count + 255) / 256, (size_t)1 << 16);
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, s, p, count);
 }
 
 void launch_lv_gate(const LevelGraph *gs, int count, hipStream_t s) {

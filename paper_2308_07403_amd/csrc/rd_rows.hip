@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_rows_step(const int64_t *__restrict__ p
     // nodes, so neighbouring nodes' states stay in that XCD's L2
     const int per = gridDim.x / 8;
     const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
-    const int j = ((blk * 256 + (int)threadIdx.x) >> 6) * N + nd;
+    const int j = (blk * 4 + (int)(threadIdx.x >> 6)) * N + nd;
     const size_t base = (size_t)blockIdx.y * n * G;
     const double *__restrict__ Vo = Vold + base;
     double acc = 0.0;

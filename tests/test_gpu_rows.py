@@ -213,3 +213,36 @@ def test_captured_chunks_replay(ctx):
             assert np.array_equal(D.cpu().numpy(), graph_out[k][1]), k
     finally:
         ctx.set_timing(False)
+
+
+def test_rows_state_over_2_31_words():
+    """1088 goals on the 1024 x 1024 lattice (n = 2^20): the iteration state
+    is two buffers of 8.5 GiB, more 32-bit words than an int counts, so its
+    zeroing needs 64-bit counts.  Two calls with different goals (the second
+    starts from the state buffers the first left at its fixed point); sampled
+    rows of each equal, bitwise, the same goals' rows from a call with five
+    goals (the same sums in edge order, another kernel), and one row equals
+    the oracle's series row."""
+    n = 1024 * 1024
+    rng = gg.rng_for("rows", 1000)
+    ptr, idx = gg.grid_lattice_csr(n, rng)
+    P, I = dev(ptr), dev(idx)
+    c = R.Context(0)
+    try:
+        for call in range(2):
+            goals = rng.integers(0, n, size=17 * 64).astype(np.int32)
+            Y, _, info, steps = c.goal_rows(P, I, torch.from_numpy(goals), -0.5, want_d=False)
+            note(f"[rows] lattice n={n} q={goals.size} call {call}: {steps} steps")
+            assert info["status"] == 0
+            ks = np.array([0, 63, 64, 700, goals.size - 1])
+            Ys, Ds, _, _ = c.goal_rows(P, I, torch.from_numpy(goals[ks].copy()), -0.5)
+            for t, k in enumerate(ks):
+                assert torch.equal(Y[int(k)], Ys[t]), (call, int(k))
+            if call == 0:
+                yo = oracle.y_row_csr(ptr, idx, info["gamma"], int(goals[700]))
+                check_rows(Ys[3:4].cpu().numpy(), Ds[3:4].cpu().numpy(), yo[None, :], info["gamma"], info["delta"],
+                           "lattice 2^20 goal row")
+            del Y, Ys, Ds
+            torch.cuda.empty_cache()
+    finally:
+        c.close()
