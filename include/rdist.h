@@ -240,7 +240,10 @@ rdist_status rdist_graph_update_edge(rdist_ctx ctx, rdist_graph g, int32_t src, 
  * chunk and the rest are not applied, the chunks before it stay applied, and
  * D_dev is left as it was.  D_dev (nullable) receives the final graph's D.
  * info->n_uncertified sums the lost entries of all chunks,
- * info->fallback_fraction is 1 if any chunk re-inverted.  Synchronous.
+ * info->fallback_fraction is 1 if any chunk re-inverted.  count = 0 changes
+ * nothing: D_dev is not written and info receives the graph's status,
+ * Delta and gamma (its counters zero).
+ * Synchronous.
  */
 rdist_status rdist_graph_update_edges(rdist_ctx ctx, rdist_graph g, int32_t count, const int32_t *src,
                                       const int32_t *dst, const int32_t *weight, int16_t *D_dev,
@@ -328,8 +331,11 @@ rdist_status rdist_gain_bounds(rdist_ctx ctx, const uint8_t *A_dev, int32_t n, i
  * with k = D_ij the readout of Y_ij, the true distance is at least k, and a
  * true distance of k + 1 or more would give
  *   Y_ij <= gamma^(k+1) Delta^k / (1 - gamma Delta)           (Eq. Y-bracket).
- * An entry with Y_ij above that bound (by a 2^-30 relative margin for
- * rounding) has D_ij equal to the graph distance; Y_ij = 0 certifies
+ * An entry with Y_ij above that bound by a relative margin for Y's error
+ * has D_ij equal to the graph distance.  The margin is the largest of
+ * 2^-30, the inversion's error bound 8 n u / (1 - gamma Delta) (u = 2^-53)
+ * and, when Y carries edge changes made since its last inversion, the cap
+ * 2^-20 on the error bounds of changed entries.  Y_ij = 0 certifies
  * "unreachable" when e gamma^(n-1) > DBL_MIN (then no reachable entry can
  * underflow); entries below DBL_MIN are not certified.  mask_dev
  * (nullable, device, n x n bytes) receives 1 for certified entries;

@@ -38,7 +38,6 @@ namespace rd {
 namespace {
 
 constexpr double kU = 1.1102230246251565e-16;      // 2^-53
-constexpr double kBetaCap = 9.5367431640625e-07;   // 2^-20
 constexpr double kBetaFCap = 5.9604644775390625e-08;   // 2^-24: f itself too uncertain
 constexpr int kRows = 2;                          // rows per step of the apply pass
 constexpr int kApplyGroups = 8192;                // workgroups of the apply pass (grid-stride)

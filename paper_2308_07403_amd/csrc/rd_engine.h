@@ -109,6 +109,7 @@ struct rdist_graph_s {
     rdist_info *hinfo = nullptr;          // pinned host copy of a change's info
     double *bs = nullptr;                 // scratch of batched changes, made by the first batch
     int weighted = 0;
+    bool changed = false;                 // Y carries edge changes made since its inversion
     void *aux = nullptr;                  // one allocation holding succ .. sm
     size_t ybytes = 0, aux_bytes = 0, beta_bytes = 0, bs_bytes = 0;
     size_t bytes = 0;                     // their sum, counted in the context's budget

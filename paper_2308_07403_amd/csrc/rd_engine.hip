@@ -569,6 +569,7 @@ static rdist_status refresh_graph(rdist_ctx c, rdist_graph g, double gamma, int1
         std::swap(g->Y, fresh->Y);
         std::swap(g->ld, fresh->ld);
         std::swap(g->ybytes, fresh->ybytes);
+        g->changed = false;
         g->bytes = g->ybytes + g->aux_bytes + g->beta_bytes + g->bs_bytes;
         fresh->bytes = fresh->ybytes + fresh->aux_bytes + fresh->beta_bytes + fresh->bs_bytes;
         hipError_t e = hipMemcpyAsync(g->ginfo, fresh->ginfo, sizeof(rdist_info), hipMemcpyDeviceToDevice, s);
@@ -624,6 +625,18 @@ rdist_status rdist_graph_update_edges(rdist_ctx c, rdist_graph g, int32_t count,
     Guard gd(c);
     RD_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
+    if (count == 0) {   // nothing to change: the graph's status, Delta and gain
+        if (info) {
+            rdist_info cur{};
+            RD_HIP(hipMemcpyAsync(&cur, g->ginfo, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
+            RD_HIP(hipStreamSynchronize(s));
+            *info = rdist_info{};
+            info->status = cur.status;
+            info->delta = cur.delta;
+            info->gamma = cur.gamma;
+        }
+        return RDIST_OK;
+    }
     const int n = g->n;
     if ((st = ensure_change_state(c, g, s))) return st;
     if (!g->bs) {
@@ -659,16 +672,15 @@ rdist_status rdist_graph_update_edges(rdist_ctx c, rdist_graph g, int32_t count,
         RD_HIP(hipStreamSynchronize(s));
         hi = *g->hinfo;
         if (hi.status != RDIST_OK) break;
+        g->changed = true;
         if (hi.n_uncertified > 0) {
             lost_total += hi.n_uncertified;
             if ((st = refresh_graph(c, g, hi.gamma, D, &hi, s))) return st;
             reinverted = true;
         }
     }
-    if (count > 0) {
-        hi.n_uncertified = lost_total;
-        hi.fallback_fraction = reinverted ? 1.0 : 0.0;
-    }
+    hi.n_uncertified = lost_total;
+    hi.fallback_fraction = reinverted ? 1.0 : 0.0;
     if (info) *info = hi;
     return RDIST_OK;
 }
@@ -696,6 +708,7 @@ rdist_status rdist_graph_update_edge(rdist_ctx c, rdist_graph g, int32_t src, in
     RD_HIP(hipMemcpyAsync(g->hinfo, ci, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
     RD_HIP(hipStreamSynchronize(s));
     rdist_info hi = *g->hinfo;
+    if (hi.status == RDIST_OK) g->changed = true;
     if (hi.status == RDIST_OK && hi.n_uncertified > 0) {
         const int64_t lost = hi.n_uncertified;
         if ((st = refresh_graph(c, g, hi.gamma, D_dev, &hi, s))) return st;
@@ -910,7 +923,8 @@ rdist_status rdist_certify(rdist_ctx c, rdist_graph g, uint8_t *mask_dev, int64_
     rd::launch_fill_i32((int32_t *)cnt, 2, s);
     {
         Timer tm(c, s, RDIST_K_CERTIFY, 0.0, (8.0 + (mask_dev ? 1.0 : 0.0)) * (double)g->n * g->n);
-        rd::launch_certify(g->Y, g->ld, g->n, g->ginfo, g->weighted != 0, mask_dev, cnt, s);
+        rd::launch_certify(g->Y, g->ld, g->n, g->ginfo, g->weighted != 0, g->changed ? rd::kBetaCap : 0.0, mask_dev,
+                           cnt, s);
     }
     RD_HIP(hipGetLastError());
     unsigned long long h = 0;

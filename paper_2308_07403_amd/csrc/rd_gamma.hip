@@ -150,8 +150,10 @@ constexpr int kCertChunk = 2048;   // columns per step of the certificate pass (
 // Per-entry certificate over a kept graph's Y: mask (nullable, n x n bytes,
 // 1 = certified) and the certified count into *count.  Entries below
 // DBL_MIN, and zeros where gamma^(n-1) could underflow, are not certified
-// (their rounding has no relative bound); Y is taken 2^-30 relative below,
-// the bound 2^-30 above, to cover Y's rounding.
+// (their rounding has no relative bound).  Y is taken rel below and the
+// bound rel above, rel the larger of 2^-30, the inversion's error bound
+// 8 n u / (1 - gamma Delta) and err_floor (the cap on the error bounds of a
+// Y changed by edge updates, else 0), to cover Y's rounding.
 // First pass over a row: ln Y from the exponent bits and the FP32 logarithm
 // of the mantissa (within 1e-6 of ln Y, as in the readout's short path)
 // gives k and the decision for almost every entry; entries whose readout or
@@ -162,14 +164,16 @@ constexpr int kCertChunk = 2048;   // columns per step of the certificate pass (
 // working on them.
 template <bool W>
 __global__ __launch_bounds__(256) void k_certify(const double *__restrict__ Y, int ld, int n,
-                                                 const rdist_info *__restrict__ ginfo, uint8_t *__restrict__ mask,
-                                                 unsigned long long *__restrict__ count) {
+                                                 const rdist_info *__restrict__ ginfo, double err_floor,
+                                                 uint8_t *__restrict__ mask, unsigned long long *__restrict__ count) {
     __shared__ int queue[kCertChunk];
     __shared__ int qn;
     const double gamma = ginfo->gamma;
     const double delta = (double)max(ginfo->delta, 1);
     const double lgd = log(gamma * delta);
-    const double margin = log1p(0x1p-30) - log1p(-0x1p-30);
+    const double gd = gamma * (double)ginfo->delta;
+    const double rel = fmin(0.5, fmax(fmax(0x1p-30, err_floor), 8.0 * (double)n * 0x1p-53 / fmax(1.0 - gd, 1e-300)));
+    const double margin = log1p(rel) - log1p(-rel);
     const double l0 = -log(delta * (1.0 - gamma * delta)) + margin;
     const double lg = log(gamma), lde = log(delta);
     // ln of the bound for readout k, the margins included
@@ -278,13 +282,13 @@ void power_read(const void *host_copy, double *lo_ratio, double *hi_ratio) {
     *hi_ratio = hi;
 }
 
-void launch_certify(const double *Y, int ld, int n, const rdist_info *ginfo, bool weighted, uint8_t *mask,
-                    unsigned long long *count, hipStream_t s) {
+void launch_certify(const double *Y, int ld, int n, const rdist_info *ginfo, bool weighted, double err_floor,
+                    uint8_t *mask, unsigned long long *count, hipStream_t s) {
     const int blocks = std::min(n, 1024);
     if (weighted)
-        hipLaunchKernelGGL(k_certify<true>, dim3(blocks), dim3(256), 0, s, Y, ld, n, ginfo, mask, count);
+        hipLaunchKernelGGL(k_certify<true>, dim3(blocks), dim3(256), 0, s, Y, ld, n, ginfo, err_floor, mask, count);
     else
-        hipLaunchKernelGGL(k_certify<false>, dim3(blocks), dim3(256), 0, s, Y, ld, n, ginfo, mask, count);
+        hipLaunchKernelGGL(k_certify<false>, dim3(blocks), dim3(256), 0, s, Y, ld, n, ginfo, err_floor, mask, count);
 }
 
 }  // namespace rd

@@ -132,6 +132,9 @@ void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipSt
 void launch_outdeg_from_bits(const unsigned long long *bits, int n, int32_t *outdeg, hipStream_t s);
 // Up to kMaxBatch edge changes applied in one pass (rd_dynamic.hip).
 constexpr int kMaxBatch = 8;
+// The largest relative error bound an entry of a changed Y keeps: an entry
+// whose bound grows beyond it counts as lost and the graph is re-inverted.
+constexpr double kBetaCap = 0x1p-20;
 struct EdgeBatch {
     int k;
     int src[kMaxBatch], dst[kMaxBatch], w[kMaxBatch];
@@ -180,8 +183,8 @@ void launch_power_init(void *scratch, hipStream_t s);
 void launch_power_step(const uint8_t *A, int n, const double *x, double *y, void *scratch, int step, hipStream_t s);
 void launch_power_fold(void *scratch, int last_step, hipStream_t s);
 void power_read(const void *host_copy, double *lo_ratio, double *hi_ratio);
-void launch_certify(const double *Y, int ld, int n, const rdist_info *ginfo, bool weighted, uint8_t *mask,
-                    unsigned long long *count, hipStream_t s);
+void launch_certify(const double *Y, int ld, int n, const rdist_info *ginfo, bool weighted, double err_floor,
+                    uint8_t *mask, unsigned long long *count, hipStream_t s);
 void launch_next_hop(const double *Y, int ld, int n, const unsigned long long *bits, const int32_t *cur,
                      const int32_t *goal, int q, int max_hops, int32_t *out, hipStream_t s);
 

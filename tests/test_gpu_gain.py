@@ -156,3 +156,43 @@ def test_gain_bounds_c2_size(ctx):
     assert r["status"] == 0 and r["rho_hi"] - r["rho_lo"] <= 1e-6 * r["rho_hi"]
     assert abs(r["rho_hi"] - 8191 * 0.02) < 0.02 * 8191 * 0.02
     assert r["rho_hi"] < r["delta"]
+
+
+def test_certificate_after_changes(ctx):
+    """A kept graph changed by edge additions (no re-inversion): the
+    certificate allows for the 2^-20 relative error a changed Y may carry.
+    The mask equals the oracle's certificate of the changed graph except
+    entries within 4e-6 of the bound in log space (twice the margin), and
+    every certified entry's D is the changed graph's BFS distance."""
+    rng = gg.rng_for("gain", 5)
+    n = 300
+    A = gg.erdos_renyi(n, 0.03, rng)
+    D, info, g = ctx.solve(dev(A), -0.5, keep=True)
+    gamma = info["gamma"]
+    outdeg = A.sum(axis=0)
+    changes = []
+    for src in np.argsort(outdeg, kind="stable")[:12]:       # low out-degree nodes gain an edge
+        cand = np.flatnonzero((A[:, src] == 0) & (np.arange(n) != src))
+        dst = int(rng.choice(cand))
+        changes.append((int(src), dst, 1))
+        A[dst, src] = 1
+    inf = g.update_edges(changes, D=D)
+    delta = int(A.sum(axis=0).max())
+    assert inf["status"] == 0 and inf["fallback_fraction"] == 0.0 and inf["delta"] == delta
+    cnt, mask = ctx.certify(g, want_mask=True)
+    m = mask.cpu().numpy().astype(bool)
+    assert cnt == int(m.sum())
+    sol = oracle.solve(A, gamma)
+    want = oracle.certify(sol.Y, sol.D, gamma, delta)
+    diff = m != want
+    if diff.any():
+        k = sol.D[diff].astype(np.float64)
+        lb = (k + 1) * math.log(gamma * delta) - math.log(delta * (1 - gamma * delta))
+        assert np.all(np.abs(np.log(sol.Y[diff]) - lb) < 4e-6), int(diff.sum())
+    dist, _ = oracle.bfs(A)
+    Dg = D.cpu().numpy()
+    reach = dist >= 0
+    assert np.all(Dg[m & reach] == dist[m & reach])
+    assert np.all(Dg[m & ~reach] == R.RDIST_UNREACHABLE)
+    note(f"[cert] changed ER n={n}: {cnt} of {n * n} certified, {int(diff.sum())} differ from the oracle")
+    g.release()

@@ -236,6 +236,11 @@ def test_noop_and_bad_arguments(ctx):
     assert inf["status"] == 0 and inf["n_uncertified"] == 0
     assert np.array_equal(g.y().cpu().numpy(), Y0)
     assert np.array_equal(D.cpu().numpy(), D0)
+    inf = g.update_edges([], D=D)                # empty batch: nothing changes
+    assert inf["status"] == 0 and inf["delta"] == info["delta"] and inf["gamma"] == info["gamma"]
+    assert inf["n_uncertified"] == 0 and inf["n_unreachable"] == 0
+    assert np.array_equal(g.y().cpu().numpy(), Y0)
+    assert np.array_equal(D.cpu().numpy(), D0)
     for a in [(src, src, 1), (-1, 3, 1), (3, 150, 1), (src, dst, 2), (src, dst, -1)]:
         with pytest.raises(R.RdistError):
             g.update_edge(*a)
