@@ -120,8 +120,9 @@ __global__ __launch_bounds__(256) void k_rows_step(const int64_t *__restrict__ p
 
 // The step for chunks of 64 goals, NB consecutive nodes per wavefront
 // (lane = goal): one load brings the batch's successor offsets, one the
-// successor ids of up to 64 of its edges, and the gathers of eight edges are
-// in flight together, so the wavefront waits for three memory latencies per
+// successor ids of up to 64 of its edges, and the gathers of 16 edges (8
+// for batches under 8 nodes, which keep more wavefronts resident) are in
+// flight together, so the wavefront waits for three memory latencies per
 // batch rather than per node.  Sums run in edge order, as in k_rows_step.
 template <int NB>
 __global__ __launch_bounds__(256) void k_rows_step64(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
@@ -129,6 +130,7 @@ __global__ __launch_bounds__(256) void k_rows_step64(const int64_t *__restrict__
                                                      int n, const int32_t *__restrict__ goals, int q,
                                                      const double *__restrict__ Vold, double *__restrict__ Vnew,
                                                      const rdist_info *__restrict__ info, int32_t *__restrict__ flag) {
+    constexpr int kInFlight = NB >= 8 ? 16 : 8;
     if (info->status != RDIST_OK) return;
     const double gamma = info->gamma;
     const int lane = threadIdx.x & 63;
@@ -162,15 +164,15 @@ __global__ __launch_bounds__(256) void k_rows_step64(const int64_t *__restrict__
         const int cnt = (int)min<long long>(64, E1 - c0);
         const int myi = lane < cnt ? idx[c0 + lane] : 0;
         const double myx = (wts && lane < cnt) ? gpow[wts[c0 + lane]] : 1.0;
-        for (int k0 = 0; k0 < cnt; k0 += 8) {
-            double v[8];
+        for (int k0 = 0; k0 < cnt; k0 += kInFlight) {
+            double v[kInFlight];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kInFlight; ++u) {
                 const int i = __shfl(myi, min(k0 + u, 63));
                 v[u] = k0 + u < cnt ? Vo[(size_t)i * 64 + lane] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kInFlight; ++u) {
                 if (k0 + u >= cnt) break;
                 while (c0 + k0 + u >= bound) finish();
                 if (wts) acc = fma(__shfl(myx, k0 + u), v[u], acc);
