@@ -39,7 +39,7 @@ namespace {
 
 constexpr double kU = 1.1102230246251565e-16;      // 2^-53
 constexpr double kBetaFCap = 5.9604644775390625e-08;   // 2^-24: f itself too uncertain
-constexpr int kRows = 2;                          // rows per step of the apply pass
+constexpr int kRows = 4;                          // rows per step of the apply pass
 constexpr int kApplyGroups = 8192;                // workgroups of the apply pass (grid-stride)
 
 // beta <= 2^(-q/256), decoded upwards (the FP32 exp2 is within an ulp or two).
@@ -168,8 +168,9 @@ __global__ __launch_bounds__(256) void k_sm_prep(const double *__restrict__ Y, i
 // the new Y when D is given (counters and lost entries into the call's
 // info).  A workgroup takes 256 V columns and steps over the rows kRows at
 // a time, grid-stride (a fixed grid of about kApplyGroups workgroups: fewer
-// per-workgroup starts and counter flushes); r and its bounds are read once.  V = 4 needs n and ld multiples of 4 and
-// D (when given) 8-byte aligned.
+// per-workgroup starts and counter flushes), loading a step's rows before
+// working on any of them; r and its bounds are read once.  V = 4 needs n and
+// ld multiples of 4 and D (when given) 8-byte aligned.
 template <int V>
 __global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld, int n, uint16_t *__restrict__ Q,
                                                   double *__restrict__ sm, int16_t *__restrict__ D,
@@ -212,7 +213,25 @@ __global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld
             brv[v] = in ? (double)br[j0 + v] : 0.0;
         }
     }
-    for (int i0 = blockIdx.y * kRows; i0 < n && active; i0 += gridDim.y * kRows)
+    for (int i0 = blockIdx.y * kRows; i0 < n && active; i0 += gridDim.y * kRows) {
+    // all rows' loads first, so that they are in flight together
+    double ya[kRows][V];
+    uint16_t qa[kRows][V];
+#pragma unroll
+    for (int ii = 0; ii < kRows; ++ii) {
+        const int i = min(i0 + ii, n - 1);
+        const double *__restrict__ yr = Y + (size_t)i * ld + j0;
+        const uint16_t *__restrict__ qr = Q + (size_t)i * n + j0;
+        if constexpr (V == 4) {
+            const d4 y4 = *reinterpret_cast<const d4 *>(yr);
+            const ushort4 q4 = *reinterpret_cast<const ushort4 *>(qr);
+            ya[ii][0] = y4.x; ya[ii][1] = y4.y; ya[ii][2] = y4.z; ya[ii][3] = y4.w;
+            qa[ii][0] = q4.x; qa[ii][1] = q4.y; qa[ii][2] = q4.z; qa[ii][3] = q4.w;
+        } else {
+            ya[ii][0] = yr[0];
+            qa[ii][0] = qr[0];
+        }
+    }
 #pragma unroll
     for (int ii = 0; ii < kRows; ++ii) {
         const int i = i0 + ii;
@@ -221,17 +240,8 @@ __global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld
         const double bci = (double)bc[i] + bf + kU;
         double *__restrict__ yr = Y + (size_t)i * ld + j0;
         uint16_t *__restrict__ qr = Q + (size_t)i * n + j0;
-        double y[V];
-        uint16_t q[V];
-        if constexpr (V == 4) {
-            const d4 y4 = *reinterpret_cast<const d4 *>(yr);
-            const ushort4 q4 = *reinterpret_cast<const ushort4 *>(qr);
-            y[0] = y4.x; y[1] = y4.y; y[2] = y4.z; y[3] = y4.w;
-            q[0] = q4.x; q[1] = q4.y; q[2] = q4.z; q[3] = q4.w;
-        } else {
-            y[0] = yr[0];
-            q[0] = qr[0];
-        }
+        double *y = ya[ii];
+        uint16_t *q = qa[ii];
         int16_t dv[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -284,6 +294,7 @@ __global__ __launch_bounds__(256) void k_sm_apply(double *__restrict__ Y, int ld
             qr[0] = q[0];
             if (D) D[(size_t)i * n + j0] = dv[0];
         }
+    }
     }
     // one atomic per counter and workgroup: every workgroup adds into the same info
     __shared__ unsigned long long part[6][4];
