@@ -221,30 +221,50 @@ __global__ __launch_bounds__(256) void k_panel_finish(const double *__restrict__
 }
 
 // Standalone readout over Y (ld) into D (n x n).  A workgroup takes chunks
-// of 1024 columns of one row, four entries per thread; with VEC (Y 16-byte
-// aligned, ld even) the four are read as two 16-byte loads.
-template <bool VEC>
+// of 2048 columns of one row; each thread reads out two groups of four
+// entries 1024 columns apart, both groups' loads issued before either is read
+// out.  With VEC (Y 16-byte aligned, ld even) a group is read as two 16-byte
+// loads, with DV (n a multiple of 4, D 8-byte aligned) written as one 8-byte
+// store; groups that cross the row's end go entry by entry.
+template <bool VEC, bool DV>
 __global__ __launch_bounds__(256) void k_epilogue(const double *__restrict__ Y, int n, int ld,
                                                   int16_t *__restrict__ D, rdist_info *info) {
     if (info->status != RDIST_OK) return;
     const double lg = rd_inv_log(info->gamma);
     Counts cnt;
-    const int cpr = (n + 1023) / 1024;
+    const int cpr = (n + 2047) / 2048;
     const long long units = (long long)n * cpr;
     for (long long u = blockIdx.x; u < units; u += gridDim.x) {
         const int i = (int)(u / cpr), ch = (int)(u - (long long)i * cpr);
-        const int j0 = ch * 1024 + threadIdx.x * 4;
         const double *__restrict__ yr = Y + (size_t)i * ld;
         int16_t *__restrict__ dr = D + (size_t)i * n;
-        if (VEC && j0 + 3 < n) {
-            const double2 a = *reinterpret_cast<const double2 *>(yr + j0);
-            const double2 b = *reinterpret_cast<const double2 *>(yr + j0 + 2);
-            dr[j0] = rd_encode(a.x, lg, cnt);
-            dr[j0 + 1] = rd_encode(a.y, lg, cnt);
-            dr[j0 + 2] = rd_encode(b.x, lg, cnt);
-            dr[j0 + 3] = rd_encode(b.y, lg, cnt);
-        } else {
-            for (int j = j0; j < min(n, j0 + 4); ++j) dr[j] = rd_encode(yr[j], lg, cnt);
+        int jg[2];
+        double y[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            jg[h] = ch * 2048 + h * 1024 + threadIdx.x * 4;
+            if (VEC && jg[h] + 3 < n) {
+                const double2 a = *reinterpret_cast<const double2 *>(yr + jg[h]);
+                const double2 b = *reinterpret_cast<const double2 *>(yr + jg[h] + 2);
+                y[h][0] = a.x; y[h][1] = a.y; y[h][2] = b.x; y[h][3] = b.y;
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j0 = jg[h];
+            if (VEC && j0 + 3 < n) {
+                int16_t d[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) d[e] = rd_encode(y[h][e], lg, cnt);
+                if (DV) {
+                    *reinterpret_cast<short4 *>(dr + j0) = make_short4(d[0], d[1], d[2], d[3]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dr[j0 + e] = d[e];
+                }
+            } else {
+                for (int j = j0; j < min(n, j0 + 4); ++j) dr[j] = rd_encode(yr[j], lg, cnt);
+            }
         }
     }
     flush_counts(info, cnt);
@@ -324,12 +344,16 @@ void launch_panel_finish(const double *S, int lds, int b, int K0, double *Pt, do
 }
 
 void launch_epilogue(const double *Y, int n, int ld, int16_t *D, rdist_info *info, hipStream_t s) {
-    const long long units = (long long)n * ((n + 1023) / 1024);
+    const long long units = (long long)n * ((n + 2047) / 2048);
     const int blocks = (int)std::max<long long>(1, std::min<long long>(units, 8192));
-    if ((reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (ld & 1) == 0)
-        hipLaunchKernelGGL(k_epilogue<true>, dim3(blocks), dim3(256), 0, s, Y, n, ld, D, info);
+    const bool vec = (reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (ld & 1) == 0;
+    const bool dv = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 7) == 0;
+    if (vec && dv)
+        hipLaunchKernelGGL((k_epilogue<true, true>), dim3(blocks), dim3(256), 0, s, Y, n, ld, D, info);
+    else if (vec)
+        hipLaunchKernelGGL((k_epilogue<true, false>), dim3(blocks), dim3(256), 0, s, Y, n, ld, D, info);
     else
-        hipLaunchKernelGGL(k_epilogue<false>, dim3(blocks), dim3(256), 0, s, Y, n, ld, D, info);
+        hipLaunchKernelGGL((k_epilogue<false, false>), dim3(blocks), dim3(256), 0, s, Y, n, ld, D, info);
 }
 
 void launch_info_set(rdist_info *info, double gamma, hipStream_t s) {
