@@ -246,3 +246,29 @@ def test_rows_state_over_2_31_words():
             torch.cuda.empty_cache()
     finally:
         c.close()
+
+
+def test_rows_max_goal_count(ctx):
+    """q = 65535 (the largest accepted: 1024 chunks of 64, the last one
+    ragged), goals repeating and covering every node, on an ER graph with
+    n = 120: every row equals the oracle's inversion's row of its goal (D
+    exactly, Y within the tolerance); q = 65536 is refused."""
+    rng = gg.rng_for("rows", 1100)
+    A = gg.erdos_renyi(120, 0.05, rng)
+    sol = oracle.solve(A, -0.5)
+    ptr, idx, _ = gg.csr_from_dense(A)
+    q = 65535
+    goals = (np.arange(q) * 7 + rng.integers(0, 120)) % 120
+    goals = goals.astype(np.int32)
+    Y, D, info, steps = ctx.goal_rows(dev(ptr), dev(idx), torch.from_numpy(goals), -0.5)
+    note(f"[rows] n=120 q={q}: {steps} steps")
+    assert info["status"] == 0 and info["gamma"] == sol.gamma
+    Yg, Dg = Y.cpu().numpy(), D.cpu().numpy()
+    for g in range(120):                       # rows of one goal are identical wherever they sit
+        ks = np.flatnonzero(goals == g)
+        assert np.array_equal(Yg[ks], np.broadcast_to(Yg[ks[0]], (ks.size, 120))), g
+        assert np.array_equal(Dg[ks], np.broadcast_to(Dg[ks[0]], (ks.size, 120))), g
+    first = np.array([np.flatnonzero(goals == g)[0] for g in range(120)])
+    check_rows(Yg[first], Dg[first], sol.Y, sol.gamma, sol.delta, "q = 65535", Do=sol.D)
+    with pytest.raises(R.RdistError):
+        ctx.goal_rows(dev(ptr), dev(idx), torch.zeros(65536, dtype=torch.int32), -0.5)
