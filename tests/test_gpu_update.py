@@ -150,6 +150,32 @@ def test_removal_that_disconnects_reinverts(ctx):
     g.release()
 
 
+def test_weighted_removal_that_disconnects_reinverts(ctx):
+    """Cutting a weighted directed path (weights 1 .. 5, gamma = 0.5) re-inverts
+    through the weighted blocked plan; restoring the edge with its weight is
+    exact again.  D is the weighted distance (the sum of the weights)."""
+    n = 150
+    rng = gg.rng_for("update", 150)
+    W = gg.directed_path(n).astype(np.uint8)
+    W[W != 0] = rng.integers(1, 6, size=int((W != 0).sum()))
+    D, info, g = ctx.solve(dev(W), 0.5, flags=R.RDIST_WEIGHTED, keep=True)
+    w_cut = int(W[71, 70])
+    inf = g.update_edge(70, 71, 0, D=D)          # edge 70 -> 71 is W[71, 70]
+    W[71, 70] = 0
+    assert inf["n_uncertified"] > 0 and inf["fallback_fraction"] == 1.0
+    check_full(ctx, g, W, 0.5, D, inf, True, "weighted path cut")
+    inf = g.update_edge(70, 71, w_cut, D=D)
+    W[71, 70] = w_cut
+    assert inf["n_uncertified"] == 0 and inf["fallback_fraction"] == 0.0
+    check_full(ctx, g, W, 0.5, D, inf, True, "weighted path restored")
+    w = np.diag(W, -1).astype(np.int64)          # w[k]: weight of k -> k + 1
+    pre = np.concatenate([[0], np.cumsum(w)])
+    i, j = np.indices(W.shape)
+    Dh = D.cpu().numpy().astype(np.int64)
+    assert np.array_equal(Dh[i >= j], (pre[i] - pre[j])[i >= j])
+    g.release()
+
+
 def test_refused_change_leaves_graph(ctx):
     """A change that breaks the gate gamma * Delta' < 1 is refused and leaves
     Y, D and the graph as they were; the next change applies."""
