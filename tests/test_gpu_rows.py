@@ -123,6 +123,10 @@ def test_goal_paths(ctx):
         out = ctx.goal_paths(dev(ptr), dev(idx), Y, torch.from_numpy(pairs[:, 1].copy()),
                              torch.from_numpy(pairs[:, 0].copy()), n - 1).cpu().numpy()
         check_paths(A, sol.Y, pairs, out, n - 1)
+        short = ctx.goal_paths(dev(ptr), dev(idx), Y, torch.from_numpy(pairs[:, 1].copy()),
+                               torch.from_numpy(pairs[:, 0].copy()), 3).cpu().numpy()   # walks cut at 3 hops
+        assert short.shape == (48, 4)
+        check_paths(A, sol.Y, pairs, short, 3)
 
 
 def test_rows_refusals(ctx):
