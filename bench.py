@@ -157,11 +157,15 @@ def bench_c2(args, torch, R, gg):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
+        # the REST launches of every fifth solve are timed (a timed launch
+        # records two events, which slows the solve by about 0.5%)
+        ctx.timing_hold(k % 5 != 0)
         evs[k][0].record(stream)
         ctx.solve_async(A, -0.5, fl, D, info=info, stream=stream)
         evs[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ctx.timing_hold(False)
     step_ms = [a.elapsed_time(b) for a, b in evs]
     upd = ctx.kernel_stats(R.RDIST_K_UPDATE)
     # per-kernel split from a separate pass with every class timed (not the timed region)

@@ -462,6 +462,12 @@ typedef struct rdist_kernel_stats {
  * less).  Enabling resets the counters; RDIST_E_ARG for a negative value. */
 #define RDIST_TIMING_CLASS(k) (2 << (k))
 rdist_status rdist_set_timing(rdist_ctx ctx, int enable);
+/* Holds (hold != 0) or resumes event timing without draining or resetting
+ * anything: launches enqueued while held are not timed, the counters and
+ * the timed launches still in flight are kept.  Lets a caller time a sample
+ * of the launches of a run it does not want to stall.  Cheap, never
+ * synchronises; RDIST_E_ARG for a NULL context. */
+rdist_status rdist_timing_hold(rdist_ctx ctx, int hold);
 /* Reads the counters of kernel class `which` (RDIST_K_*); synchronises the
  * streams the timed launches ran on. */
 rdist_status rdist_kernel_stats_get(rdist_ctx ctx, int which, rdist_kernel_stats *out);

@@ -124,6 +124,7 @@ struct rdist_ctx_s {
     std::map<hipStream_t, rd::eng::Workspace> ws;
     std::set<rdist_graph_s *> graphs;
     uint32_t timing_mask = 0;   // bit k: kernel class k is timed
+    bool timing_hold = false;   // no launch is timed while set (rdist_timing_hold)
     std::vector<rd::eng::TimedLaunch> pending;
     std::vector<hipEvent_t> event_pool;
     rdist_kernel_stats stats[RDIST_K_COUNT];
@@ -170,7 +171,7 @@ struct Timer {
     double flops, bytes;
     hipEvent_t a = nullptr;
     Timer(rdist_ctx c_, hipStream_t s_, int w, double f, double b) : c(c_), s(s_), which(w), flops(f), bytes(b) {
-        if (c->timing_mask & (1u << w)) {
+        if ((c->timing_mask & (1u << w)) && !c->timing_hold) {
             a = take_event(c);
             if (a) (void)hipEventRecord(a, s);
         }

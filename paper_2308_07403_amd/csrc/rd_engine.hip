@@ -137,8 +137,11 @@ hipEvent_t take_event(rdist_ctx c) {
         c->event_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence at the record (nothing on the host
+    // reads device memory through these events), so timed launches run as
+    // they would untimed
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -961,6 +964,13 @@ rdist_status rdist_set_timing(rdist_ctx c, int enable) {
     drain_timing(c);
     c->timing_mask = enable == 1 ? (1u << RDIST_K_COUNT) - 1 : ((uint32_t)enable >> 1) & ((1u << RDIST_K_COUNT) - 1);
     if (enable) std::memset(c->stats, 0, sizeof(c->stats));
+    return RDIST_OK;
+}
+
+rdist_status rdist_timing_hold(rdist_ctx c, int hold) {
+    if (!c) return fail(RDIST_E_ARG, "ctx is NULL");
+    Guard g(c);
+    c->timing_hold = hold != 0;
     return RDIST_OK;
 }
 

@@ -146,6 +146,8 @@ _lib.rdist_epilogue.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c
 _lib.rdist_epilogue.restype = ctypes.c_int
 _lib.rdist_set_timing.argtypes = [_P, ctypes.c_int]
 _lib.rdist_set_timing.restype = ctypes.c_int
+_lib.rdist_timing_hold.argtypes = [_P, ctypes.c_int]
+_lib.rdist_timing_hold.restype = ctypes.c_int
 _lib.rdist_kernel_stats_get.argtypes = [_P, ctypes.c_int, ctypes.POINTER(rdist_kernel_stats)]
 _lib.rdist_kernel_stats_get.restype = ctypes.c_int
 _lib.rdist_hbm_in_use.argtypes = [_P]
@@ -182,6 +184,7 @@ rdist_graph_update_edge = _lib.rdist_graph_update_edge
 rdist_graph_update_edges = _lib.rdist_graph_update_edges
 rdist_epilogue = _lib.rdist_epilogue
 rdist_set_timing = _lib.rdist_set_timing
+rdist_timing_hold = _lib.rdist_timing_hold
 rdist_kernel_stats_get = _lib.rdist_kernel_stats_get
 rdist_hbm_in_use = _lib.rdist_hbm_in_use
 rdist_last_error = _lib.rdist_last_error
@@ -195,7 +198,7 @@ rdist_server_destroy = _lib.rdist_server_destroy
 EXPORTS = ("rdist_create", "rdist_destroy", "rdist_solve", "rdist_solve_batched", "rdist_next_hop",
            "rdist_graph_release", "rdist_graph_y", "rdist_graph_update_edge", "rdist_graph_update_edges", "rdist_goal_rows", "rdist_goal_paths",
            "rdist_gain_bounds", "rdist_certify",
-           "rdist_epilogue", "rdist_set_timing",
+           "rdist_epilogue", "rdist_set_timing", "rdist_timing_hold",
            "rdist_kernel_stats_get", "rdist_hbm_in_use", "rdist_last_error", "rdist_status_string",
            "rdist_server_create", "rdist_server_submit", "rdist_server_poll", "rdist_server_stats_get",
            "rdist_server_destroy")
@@ -463,6 +466,10 @@ class Context:
         """Event timing of every kernel class, or of the RDIST_K_* classes listed."""
         mask = (1 if on else 0) if classes is None else sum(RDIST_TIMING_CLASS(k) for k in classes)
         _check(rdist_set_timing(self.handle, mask), "rdist_set_timing")
+
+    def timing_hold(self, hold: bool):
+        """Launches enqueued while held are not timed; counters and pending timings are kept."""
+        _check(rdist_timing_hold(self.handle, 1 if hold else 0), "rdist_timing_hold")
 
     def kernel_stats(self, which: int) -> dict:
         s = rdist_kernel_stats()

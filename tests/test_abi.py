@@ -63,6 +63,7 @@ def test_synchronous_argument_errors_without_device(lib):
     assert R.rdist_goal_paths(None, 4, None, None, 0, None, None, None, 1, 1, None, None) == R.RDIST_E_ARG
     assert R.rdist_gain_bounds(None, None, 4, 0, 16, 0.0, None, None) == R.RDIST_E_ARG
     assert R.rdist_certify(None, None, None, None, None) == R.RDIST_E_ARG
+    assert R.rdist_timing_hold(None, 1) == R.RDIST_E_ARG
     R.rdist_graph_release(None)
     R.rdist_destroy(None)
 

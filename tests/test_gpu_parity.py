@@ -839,6 +839,30 @@ def test_timing_mask(ctx):
     assert R.rdist_set_timing(ctx.handle, -1) == R.RDIST_E_ARG
 
 
+def test_timing_hold(ctx):
+    """rdist_timing_hold: solves enqueued while held are not timed, the
+    counters are kept across hold and resume, and the held solves' results
+    are those of timed ones."""
+    A = dev(gg.erdos_renyi(1500, 0.01, gg.rng_for("parity", 9501)))
+    ctx.set_timing(True, classes=[R.RDIST_K_UPDATE])
+    try:
+        D1, _, _ = ctx.solve(A, -0.5)
+        one = ctx.kernel_stats(R.RDIST_K_UPDATE)["launches"]
+        assert one > 0
+        ctx.timing_hold(True)
+        D2, _, _ = ctx.solve(A, -0.5)
+        D3, _, _ = ctx.solve(A, -0.5)
+        assert ctx.kernel_stats(R.RDIST_K_UPDATE)["launches"] == one
+        ctx.timing_hold(False)
+        ctx.solve(A, -0.5)
+        assert ctx.kernel_stats(R.RDIST_K_UPDATE)["launches"] == 2 * one
+        assert torch.equal(D1, D2) and torch.equal(D1, D3)
+    finally:
+        ctx.timing_hold(False)
+        ctx.set_timing(False)
+    assert R.rdist_timing_hold(None, 1) == R.RDIST_E_ARG
+
+
 def test_budget_refusal():
     c = R.Context(0, hbm_budget=1 << 20)
     A = dev(gg.erdos_renyi(1024, 0.01, gg.rng_for("parity", 7000)))
