@@ -622,7 +622,8 @@ def bench_f3(args, torch, R, gg):
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for src, dst, w in timed:
+    for k, (src, dst, w) in enumerate(timed):
+        ctx.timing_hold(k % 5 != 0)          # every fifth change's apply pass is timed
         t1 = time.perf_counter()
         inf = g.update_edge(src, dst, w, D=D)
         lat.append((time.perf_counter() - t1) * 1e3)
@@ -631,6 +632,7 @@ def bench_f3(args, torch, R, gg):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ctx.kernel_stats(R.RDIST_K_EDGE_UPDATE)
+    ctx.timing_hold(False)
     ctx.set_timing(False)
     assert inf["status"] == 0, inf
     # the same kind of changes in batches: one call per step of 32 (4 passes of 8)
@@ -710,11 +712,15 @@ def bench_f4(args, torch, R, gg):
     steps_run = []
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
+        # the first timed call's steps are timed (eager launches with events);
+        # the others replay the captured chunk, as an untimed caller's would
+        ctx.timing_hold(k != args.warmup)
         Y, D, info, steps = ctx.goal_rows(ptr, idx, goal_sets[k], -0.5)
         steps_run.append(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ctx.kernel_stats(R.RDIST_K_ROWS_STEP)
+    ctx.timing_hold(False)
     ctx.set_timing(False)
     assert info["status"] == 0, info
     gamma, delta = info["gamma"], info["delta"]

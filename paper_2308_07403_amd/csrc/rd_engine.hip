@@ -779,9 +779,9 @@ rdist_status rdist_goal_rows(rdist_ctx c, int32_t n, const int64_t *succ_ptr, co
         }
         return hipMemcpyAsync(w.rflag_h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, cs);
     };
-    // per-step timing asks for the eager launches; otherwise the chunk is a
-    // HIP graph, captured once per (lists, weights, sizes, buffers)
-    const bool eager = (c->timing_mask & (1u << RDIST_K_ROWS_STEP)) != 0;
+    // per-step timing (not held) asks for the eager launches; otherwise the
+    // chunk is a HIP graph, captured once per (lists, weights, sizes, buffers)
+    const bool eager = (c->timing_mask & (1u << RDIST_K_ROWS_STEP)) != 0 && !c->timing_hold;
     if (!eager) {
         const void *key[6] = {succ_ptr, succ_idx, weights, w.rv.p, w.rmisc.p, wgoals};
         const int64_t key_n[3] = {n, nnz, q};
