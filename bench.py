@@ -511,7 +511,7 @@ def bench_f1(args, torch, R, gg):
         Dg, inf_g, gr = ctx.solve(W2, gam, flags=fl, keep=True)
         Yh = gr.y().cpu().numpy()
         hop = ctx.next_hop(gr, torch.from_numpy(pairs[:, 1].astype(np.int32)),
-                           torch.from_numpy(pairs[:, 0].astype(np.int32)), 1).cpu().numpy()[:, 1]
+                           torch.from_numpy(pairs[:, 0].astype(np.int32)), 1).cpu().numpy()
         gr.release()
         R = np.log(Yh[reach]) / np.log(gam)
         r2 = float(np.corrcoef(R, dist2[reach])[0, 1] ** 2)
@@ -848,7 +848,7 @@ def bench_f2(args, torch, R, gg):
             gamma = f / delta
             Dg, inf, gr = ctx.solve(G, gamma, keep=True)
             c, _ = ctx.certify(gr)
-            hop = ctx.next_hop(gr, cur_t, goal_t, 1).cpu().numpy()[:, 1]
+            hop = ctx.next_hop(gr, cur_t, goal_t, 1).cpu().numpy()
             gr.release()
             Dh = Dg.cpu().numpy()
             ok = np.where(dist >= 0, Dh == dist, Dh == R.RDIST_UNREACHABLE)

@@ -171,14 +171,18 @@ rdist_status rdist_solve_batched(rdist_ctx ctx, int32_t count, const int32_t *n,
 
 /*
  * Greedy local pursuit on a kept graph (Sec. 4.2, Eq. descent; Theorem 4 and
- * its corollary).  For query q with start cur_dev[q] and goal goal_dev[q]:
- *   out_dev[q*(max_hops+1) + 0] = start,
- *   out_dev[q*(max_hops+1) + h] = node reached after h hops, where each hop
- *     moves from i to the successor j of i (edge i -> j) with the largest
- *     Y[goal, j], the lowest j on exact ties;
- * the row ends at the goal; remaining entries are -1.  A hop that finds no
- * successor with Y[goal, j] > 0 (goal unreachable) writes -1 and ends the row.
- * Out-of-range node ids end the row with -1 as well.
+ * its corollary).  Each hop moves from node i to the successor j of i (edge
+ * i -> j) with the largest Y[goal, j], the lowest j on exact ties.  For query
+ * q with start cur_dev[q] and goal goal_dev[q]:
+ *   max_hops == 1 (next hop):  out_dev[q] = the next node from the start; the
+ *     start itself when it is the goal; -1 when no successor has
+ *     Y[goal, j] > 0 (goal unreachable) or a node id is out of range.
+ *   max_hops > 1 (paths), rows of max_hops + 1 entries:
+ *     out_dev[q*(max_hops+1) + 0] = start,
+ *     out_dev[q*(max_hops+1) + h] = node reached after h hops;
+ *     the row ends at the goal and the remaining entries are -1.  A hop that
+ *     finds no successor with Y[goal, j] > 0 writes -1 and ends the row; an
+ *     out-of-range start or goal leaves the whole row -1.
  * q >= 0, 1 <= max_hops <= 65535.  Needs a graph kept with RDIST_KEEP_Y.
  */
 rdist_status rdist_next_hop(rdist_ctx ctx, rdist_graph g, const int32_t *cur_dev,
@@ -285,7 +289,7 @@ rdist_status rdist_goal_rows(rdist_ctx ctx, int32_t n, const int64_t *succ_ptr, 
  * Greedy paths over goal rows (Sec. 4.2): query k walks from starts[k]
  * toward goals[k], each hop to the successor j (CSR as above) with the
  * largest Y_rows[k*n + j], the lowest j on exact ties; out_dev layout and
- * ending as rdist_next_hop (q x (max_hops+1) int32).  Y_rows as written by
+ * ending as rdist_next_hop (q int32 for max_hops == 1, else q x (max_hops+1)).  Y_rows as written by
  * rdist_goal_rows for the same goals (successor offsets are clamped to
  * [0, nnz), ids outside [0, n) skipped).  Asynchronous on the stream.
  */
@@ -395,8 +399,8 @@ typedef struct rdist_request {
     const int32_t *goal_host;  /* RDIST_QUERY_PATHS: q goal nodes (host) */
     int32_t q;                 /* RDIST_QUERY_PATHS: pairs, 0 <= q <= 4096 */
     int32_t max_hops;          /* RDIST_QUERY_PATHS: 1 .. 65535 */
-    int32_t *paths_host;       /* RDIST_QUERY_PATHS: q*(max_hops+1) int32 host buffer (pinned), layout as
-                                  rdist_next_hop's out */
+    int32_t *paths_host;       /* RDIST_QUERY_PATHS: host buffer (pinned) of q int32 for max_hops == 1,
+                                  else q*(max_hops+1); layout as rdist_next_hop's out */
     rdist_info *info_host;     /* nullable: the solve's info, valid once the request is reported done */
 } rdist_request;
 

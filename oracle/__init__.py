@@ -72,6 +72,7 @@ def lib():
         L.orc_next_hop.argtypes = [P, P, i32, i32, i32]
         L.orc_next_hop.restype = i32
         L.orc_path.argtypes = [P, P, i32, i32, i32, i32, P]
+        L.orc_path_row.argtypes = [P, P, i32, i32, i32, i32, P]
         L.orc_bfs.argtypes = [P, i32, P, P]
         L.orc_floyd_warshall.argtypes = [P, i32, i32, i32, P]
         L.orc_num_threads.restype = i32
@@ -247,6 +248,16 @@ def path(A, Y, cur: int, goal: int, max_hops: int) -> np.ndarray:
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     out = np.empty(max_hops + 1, dtype=np.int32)
     lib().orc_path(_p(A), _p(Y), A.shape[0], int(cur), int(goal), int(max_hops), _p(out))
+    return out
+
+
+def path_row(A, y_goal, cur: int, goal: int, max_hops: int) -> np.ndarray:
+    """The greedy walk of ``path`` given only row ``goal`` of Y (e.g. from ``y_row``)."""
+    A = _adj(A)
+    y = np.ascontiguousarray(y_goal, dtype=np.float64)
+    assert y.shape == (A.shape[0],)
+    out = np.empty(max_hops + 1, dtype=np.int32)
+    lib().orc_path_row(_p(A), _p(y), A.shape[0], int(cur), int(goal), int(max_hops), _p(out))
     return out
 
 

@@ -295,10 +295,16 @@ int orc_solve_weighted(const uint8_t *W, int n, double gamma_arg, double eta, do
 /* Local pursuit (Eq. descent; Theorem 4 and its corollary).                 */
 /* ------------------------------------------------------------------------ */
 
-int orc_next_hop(const uint8_t *A, const double *Y, int n, int cur, int goal) {
+/*
+ * Next hop from cur toward goal, given yg = row goal of Y (yg[j] = Y[goal][j]):
+ * the successor j of cur (edge cur -> j) with the largest yg[j] > 0, the
+ * lowest j on exact ties; cur itself at the goal; -1 without such a successor
+ * or for an id out of range.  Only row goal of Y is read, so a single row
+ * (computed by the series below) serves large graphs.
+ */
+int orc_next_hop_row(const uint8_t *A, const double *yg, int n, int cur, int goal) {
     if (cur < 0 || cur >= n || goal < 0 || goal >= n) return -1;
     if (cur == goal) return cur;
-    const double *yg = Y + (size_t)goal * n;
     int best = -1;
     double bestv = 0.0;
     for (int j = 0; j < n; ++j) {
@@ -308,21 +314,36 @@ int orc_next_hop(const uint8_t *A, const double *Y, int n, int cur, int goal) {
     return best;
 }
 
+int orc_next_hop(const uint8_t *A, const double *Y, int n, int cur, int goal) {
+    if (goal < 0 || goal >= n) return -1;
+    return orc_next_hop_row(A, Y + (size_t)goal * n, n, cur, goal);
+}
+
 /*
  * out[0] = cur; out[h] = node after h greedy hops; once the goal is reached or
  * a hop fails the remaining entries are -1.  Writes max_hops + 1 entries.
+ * orc_path_row takes row goal of Y only.
  */
-void orc_path(const uint8_t *A, const double *Y, int n, int cur, int goal, int max_hops,
-              int32_t *out) {
+void orc_path_row(const uint8_t *A, const double *yg, int n, int cur, int goal, int max_hops, int32_t *out) {
     for (int h = 0; h <= max_hops; ++h) out[h] = -1;
     out[0] = cur;
     int c = cur;
     for (int h = 1; h <= max_hops; ++h) {
         if (c == goal || c < 0) break;
-        int nx = orc_next_hop(A, Y, n, c, goal);
+        int nx = orc_next_hop_row(A, yg, n, c, goal);
         out[h] = nx;
         c = nx;
     }
+}
+
+void orc_path(const uint8_t *A, const double *Y, int n, int cur, int goal, int max_hops,
+              int32_t *out) {
+    if (goal < 0 || goal >= n) {
+        for (int h = 0; h <= max_hops; ++h) out[h] = -1;
+        out[0] = cur;
+        return;
+    }
+    orc_path_row(A, Y + (size_t)goal * n, n, cur, goal, max_hops, out);
 }
 
 /* ------------------------------------------------------------------------ */

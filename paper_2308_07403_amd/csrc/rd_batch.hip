@@ -78,14 +78,19 @@ struct BatchPlan {
     void *staging = nullptr;
     size_t staging_bytes = 0;
     hipEvent_t ev_upload = nullptr;
+    // recorded after every launch of the captured graph: eviction waits for
+    // it, not for the caller's stream, which may be gone by then
+    hipEvent_t ev_done = nullptr;
+    bool launched = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // fork, join, edge done, panel done
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t last_use = 0;
 
     bool matches(hipStream_t s, uint32_t f, int count, const int32_t *n_, const uint8_t *const *A_, const double *g_,
-                 int16_t *const *D_) const {
+                 int16_t *const *D_, const BatchTuning &t) const {
         if (s != stream || f != flags || (int)n.size() != count) return false;
+        if (t.persist_max_n != tune.persist_max_n || t.persist_grid != tune.persist_grid) return false;
         for (int i = 0; i < count; ++i)
             if (n[i] != n_[i] || A[i] != A_[i] || gamma[i] != g_[i] || D[i] != D_[i]) return false;
         return true;
@@ -101,15 +106,21 @@ rdist_status ensure_capture_streams(rdist_ctx c) {
 
 namespace {
 
+// Frees a plan once its last graph launch and its table upload have
+// finished (a transient plan's eager launches are the caller's to wait for).
 void free_plan(rdist_ctx c, BatchPlan *p) {
     if (!p) return;
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    for (Buf *b : {&p->infos, &p->table, &p->pool, &p->scratch}) release(c, *b);
+    if (p->ev_done) {
+        if (p->launched) (void)hipEventSynchronize(p->ev_done);
+        (void)hipEventDestroy(p->ev_done);
+    }
     if (p->ev_upload) {
         (void)hipEventSynchronize(p->ev_upload);
         (void)hipEventDestroy(p->ev_upload);
     }
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (Buf *b : {&p->infos, &p->table, &p->pool, &p->scratch}) release(c, *b);
     if (p->staging) (void)hipHostFree(p->staging);
     for (hipEvent_t e : p->ev)
         if (e) (void)hipEventDestroy(e);
@@ -468,9 +479,9 @@ rdist_status autotune(rdist_ctx c, hipStream_t s, uint32_t flags, int count, con
 }
 
 BatchPlan *lookup_plan(rdist_ctx c, hipStream_t s, uint32_t flags, int count, const int32_t *n,
-                       const uint8_t *const *A, const double *gamma, int16_t *const *D) {
+                       const uint8_t *const *A, const double *gamma, int16_t *const *D, const BatchTuning &tune) {
     for (BatchPlan *p : c->plans)
-        if (p->matches(s, flags, count, n, A, gamma, D)) return p;
+        if (p->matches(s, flags, count, n, A, gamma, D, tune)) return p;
     return nullptr;
 }
 
@@ -615,18 +626,25 @@ extern "C" rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const in
     std::vector<Buf> ys;
     const bool use_graph = !keep_y && !(flags & RDIST_NO_GRAPH);
     if (use_graph) {
-        p = lookup_plan(c, s, flags, count, n, A_dev, gamma, D_dev);
-        if (p && (p->tune.persist_max_n != tune.persist_max_n || p->tune.persist_grid != tune.persist_grid)) p = nullptr;
+        // the tuning is part of the key: a plan built under another tuning
+        // never matches and ages out of the cache
+        p = lookup_plan(c, s, flags, count, n, A_dev, gamma, D_dev, tune);
         if (!p) {
             if ((int)c->plans.size() >= kMaxCachedPlans) {
                 auto it = std::min_element(c->plans.begin(), c->plans.end(),
                                            [](BatchPlan *a, BatchPlan *b) { return a->last_use < b->last_use; });
-                (void)hipStreamSynchronize((*it)->stream);
-                free_plan(c, *it);
+                free_plan(c, *it);   // waits on the plan's own events, never on its stream
                 c->plans.erase(it);
             }
             p = new BatchPlan();
             st = build_plan(c, *p, s, flags, count, n, A_dev, gamma, D_dev, tune, false, ys);
+            if (!st && !p->ev_done) {
+                const hipError_t e = hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming);
+                if (e != hipSuccess) {
+                    p->ev_done = nullptr;
+                    st = fail(RDIST_E_HIP, std::string("hipEventCreateWithFlags: ") + hipGetErrorString(e));
+                }
+            }
             if (!st) st = capture_plan(c, *p);
             if (st) {
                 free_plan(c, p);
@@ -643,8 +661,11 @@ extern "C" rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const in
 
     if (!p->persist_ids.empty() || !p->level_ids.empty()) {
         Timer tm(c, s, RDIST_K_BATCHED, p->flops, p->bytes);
-        if (p->exec) RD_HIP(hipGraphLaunch(p->exec, s));
-        else {
+        if (p->exec) {
+            RD_HIP(hipGraphLaunch(p->exec, s));
+            RD_HIP(hipEventRecord(p->ev_done, s));
+            p->launched = true;
+        } else {
             const hipStream_t sts[3] = {s, w.aux, w.aux2};
             if ((st = enqueue_plan(*p, sts))) return st;
         }

@@ -112,6 +112,9 @@ void launch_fix(const float *X, int np, int n, const float *C, const int32_t *sl
 void launch_split_bf16(const float *src, size_t count, uint16_t *hi, uint16_t *lo, const unsigned *rmax,
                        hipStream_t s);
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s);
+// Entries per query of a path output: the next node alone for max_hops = 1,
+// else the start and max_hops hops.
+__host__ __device__ inline int path_row_len(int max_hops) { return max_hops == 1 ? 1 : max_hops + 1; }
 // Path requests of a batch (the request loop), one task per graph with q > 0
 // queries; blk0 and q0 are the prefix sums of path_task_blocks(n) and of q
 // over the tasks before it.
@@ -120,7 +123,7 @@ struct PathTask {
     const double *Y;             // Y with leading dimension ld (device)
     unsigned long long *bits;    // n x ceil(n/64) successor bitmap, written by launch_paths_multi
     const int32_t *cur, *goal;   // q start and goal nodes (device)
-    int32_t *out;                // q x (max_hops + 1), as rdist_next_hop's out
+    int32_t *out;                // q x path_row_len(max_hops), as rdist_next_hop's out
     int32_t n, ld, q, max_hops;
     int32_t blk0, q0;
 };

@@ -27,16 +27,20 @@ __device__ __forceinline__ void succ_word(const uint8_t *__restrict__ A, int n, 
 
 // One query on one wavefront: from c0, repeatedly move to the successor j
 // with the largest Y[goal][j] (lowest j among exact ties) until the goal,
-// a node without a successor of positive Y, or max_hops.  o: max_hops + 1
-// entries, -1 past the end of the path; an out-of-range start or goal
-// leaves the whole row -1.
+// a node without a successor of positive Y, or max_hops.  Path form
+// (max_hops > 1): o holds max_hops + 1 entries, the start first and -1 past
+// the end of the path; an out-of-range start or goal leaves the row -1.
+// Single-hop form (max_hops == 1): o[0] is the next node, the start itself
+// when it is the goal, -1 when no successor has positive Y or an id is out
+// of range.
 __device__ __forceinline__ void next_hop_wave(const double *__restrict__ Y, int ld, int n,
                                               const unsigned long long *__restrict__ bits, int nw, int c, int g,
                                               int max_hops, int32_t *__restrict__ o) {
     const int lane = threadIdx.x & 63;
-    for (int h = lane; h <= max_hops; h += 64) o[h] = -1;
+    const int sh = max_hops == 1 ? 1 : 0;   // hop h goes to o[h - sh]
+    for (int h = lane; h < path_row_len(max_hops); h += 64) o[h] = -1;
     if (c < 0 || c >= n || g < 0 || g >= n) return;
-    if (lane == 0) o[0] = c;
+    if (lane == 0) o[0] = c;   // the start; in the single-hop form replaced by hop 1 unless c is the goal
     const double *yg = Y + (size_t)g * ld;
     for (int h = 1; h <= max_hops; ++h) {
         if (c == g) break;
@@ -59,11 +63,11 @@ __device__ __forceinline__ void next_hop_wave(const double *__restrict__ Y, int 
             if (ov > bv || (ov == bv && oj < bj)) { bv = ov; bj = oj; }
         }
         if (!(bv > 0.0)) {
-            if (lane == 0) o[h] = -1;
+            if (lane == 0) o[h - sh] = -1;
             break;
         }
         c = bj;
-        if (lane == 0) o[h] = c;
+        if (lane == 0) o[h - sh] = c;
     }
 }
 
@@ -79,7 +83,7 @@ __global__ __launch_bounds__(256) void k_next_hop(const double *__restrict__ Y, 
                                                   int q, int max_hops, int32_t *__restrict__ out) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= q) return;
-    next_hop_wave(Y, ld, n, bits, nw, cur[w], goal[w], max_hops, out + (size_t)w * (max_hops + 1));
+    next_hop_wave(Y, ld, n, bits, nw, cur[w], goal[w], max_hops, out + (size_t)w * path_row_len(max_hops));
 }
 
 // The task whose range [key_of(t), key_of(t + 1)) holds key: the last task
@@ -116,7 +120,7 @@ __global__ __launch_bounds__(256) void k_next_hop_multi(const PathTask *__restri
     const PathTask t = tasks[find_task<true>(tasks, ntasks, gw)];
     const int w = gw - t.q0;
     next_hop_wave(t.Y, t.ld, t.n, t.bits, (t.n + 63) / 64, t.cur[w], t.goal[w], t.max_hops,
-                  t.out + (size_t)w * (t.max_hops + 1));
+                  t.out + (size_t)w * path_row_len(t.max_hops));
 }
 
 void launch_succ_bitmap(const uint8_t *A, int n, unsigned long long *bits, hipStream_t s) {

@@ -277,15 +277,16 @@ __global__ __launch_bounds__(256) void k_rows_paths(const int64_t *__restrict__ 
     const int lane = threadIdx.x & 63;
     const int k = (blockIdx.x * 256 + threadIdx.x) >> 6;
     if (k >= q) return;
-    int32_t *o = out + (size_t)k * (max_hops + 1);
+    const int sh = max_hops == 1 ? 1 : 0;   // hop h goes to o[h - sh]
+    int32_t *o = out + (size_t)k * path_row_len(max_hops);
     const int goal = goals[k];
     int cur = starts[k];
     const bool valid = cur >= 0 && cur < n && goal >= 0 && goal < n;
-    if (lane == 0) o[0] = valid ? cur : -1;
+    if (lane == 0) o[0] = valid ? cur : -1;   // single-hop form: replaced by hop 1 unless cur is the goal
     const double *__restrict__ row = Y + (size_t)k * n;
     for (int h = 1; h <= max_hops; ++h) {
         if (!valid || cur < 0 || cur == goal) {
-            for (int t = h + lane; t <= max_hops; t += 64) o[t] = -1;
+            for (int t = h + lane; t <= max_hops && !sh; t += 64) o[t] = -1;
             break;
         }
         double best = 0.0;
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(256) void k_rows_paths(const int64_t *__restrict__ 
             if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
         }
         cur = best > 0.0 ? bj : -1;
-        if (lane == 0) o[h] = cur;
+        if (lane == 0) o[h - sh] = cur;
     }
 }
 

@@ -109,7 +109,7 @@ rdist_status dispatch_single(rdist_server s, Slot &sl, const rdist_request &r0) 
         if (e) return e;
         RD_HIP(hipMemcpyAsync(r0.D_host, sl.D.p, n2 * 2, hipMemcpyDeviceToHost, st));
     } else {
-        const size_t pb = (size_t)r0.q * (r0.max_hops + 1) * 4;
+        const size_t pb = (size_t)r0.q * rd::path_row_len(r0.max_hops) * 4;
         if ((e = grow(c, sl.paths, pb))) return e;
         if ((e = grow(c, sl.pairs, (size_t)2 * kMaxPairs * 4))) return e;
         rdist_graph g = nullptr;
@@ -157,7 +157,7 @@ rdist_status dispatch_batch(rdist_server s, Slot &sl, const std::vector<Pending>
         offQ[i] = tQ;
         tQ += (size_t)r.q;
         offP[i] = tP;
-        tP += align256((size_t)r.q * (r.max_hops + 1) * 4);
+        tP += align256((size_t)r.q * rd::path_row_len(r.max_hops) * 4);
     }
     if ((e = grow(c, sl.D, tD))) return e;
     if (tY && ((e = grow(c, sl.Y, tY)) || (e = grow(c, sl.bits, tB)))) return e;
@@ -245,7 +245,7 @@ rdist_status dispatch_batch(rdist_server s, Slot &sl, const std::vector<Pending>
             if (r.kind == RDIST_QUERY_D)
                 RD_HIP(hipMemcpyAsync(r.D_host, Ds[i], (size_t)r.n * r.n * 2, hipMemcpyDeviceToHost, tail));
             else if (r.q > 0)
-                RD_HIP(hipMemcpyAsync(r.paths_host, (char *)sl.paths.p + offP[i], (size_t)r.q * (r.max_hops + 1) * 4,
+                RD_HIP(hipMemcpyAsync(r.paths_host, (char *)sl.paths.p + offP[i], (size_t)r.q * rd::path_row_len(r.max_hops) * 4,
                                       hipMemcpyDeviceToHost, tail));
         }
         RD_HIP(hipEventRecord(sl.gdone[G.index], tail));

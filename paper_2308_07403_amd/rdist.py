@@ -224,6 +224,11 @@ def _stream_ptr(stream) -> int:
     return int(stream.cuda_stream)
 
 
+def path_shape(q: int, max_hops: int) -> tuple:
+    """Shape of a path output: (q,) next nodes for max_hops = 1, else (q, max_hops + 1) rows."""
+    return (q,) if max_hops == 1 else (q, max_hops + 1)
+
+
 class PinnedInfo:
     """rdist_info records in pinned host memory (written asynchronously by the device)."""
 
@@ -390,7 +395,7 @@ class Context:
         cur = cur.to(device=self.device, dtype=torch.int32).contiguous()
         goal = goal.to(device=self.device, dtype=torch.int32).contiguous()
         if out is None:
-            out = torch.empty((q, max_hops + 1), dtype=torch.int32, device=self.device)
+            out = torch.empty(path_shape(q, max_hops), dtype=torch.int32, device=self.device)
         st = rdist_next_hop(self.handle, graph.handle, cur.data_ptr(), goal.data_ptr(), q, max_hops,
                             out.data_ptr(), _stream_ptr(stream))
         _check(st, "rdist_next_hop")
@@ -443,7 +448,7 @@ class Context:
         goals = goals.to(device=self.device, dtype=torch.int32).contiguous()
         starts = starts.to(device=self.device, dtype=torch.int32).contiguous()
         q = int(goals.numel())
-        out = torch.empty((q, max_hops + 1), dtype=torch.int32, device=self.device)
+        out = torch.empty(path_shape(q, max_hops), dtype=torch.int32, device=self.device)
         st = rdist_goal_paths(self.handle, n, ptr.data_ptr(), idx.data_ptr(), int(idx.numel()), Y_rows.data_ptr(),
                               goals.data_ptr(),
                               starts.data_ptr(), q, max_hops, out.data_ptr(), _stream_ptr(stream))

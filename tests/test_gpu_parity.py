@@ -340,13 +340,15 @@ def test_weighted_next_hop_and_refusals(ctx):
 # Next hop
 # ---------------------------------------------------------------------------
 
-def check_paths(A, Yo, pairs, out, max_hops, tol=1e-10):
-    n = A.shape[0]
+def check_paths_rows(A, row_of, pairs, out, max_hops, tol=1e-10):
+    """Each GPU path against the oracle's greedy walk on the oracle's row
+    Y[goal, :] (row_of(goal)); a divergence is allowed only at a near-tie of
+    the oracle's values, and every hop must still be a best successor."""
     for (cur, goal), row in zip(pairs, out):
-        ref = oracle.path(A, Yo, int(cur), int(goal), max_hops)
+        yg = row_of(int(goal))
+        ref = oracle.path_row(A, yg, int(cur), int(goal), max_hops)
         if np.array_equal(ref, row):
             continue
-        # divergence is allowed only at a near-tie of the oracle's Y
         assert row[0] == cur
         c = int(cur)
         for h in range(1, max_hops + 1):
@@ -354,18 +356,22 @@ def check_paths(A, Yo, pairs, out, max_hops, tol=1e-10):
                 assert row[h] == -1
                 break
             succ = np.nonzero(A[:, c])[0]
-            vals = Yo[goal, succ]
+            vals = yg[succ]
             if len(succ) == 0 or vals.max() <= 0:
                 assert row[h] == -1
                 break
             j = int(row[h])
             assert j in succ
             best = vals.max()
-            assert Yo[goal, j] >= (1 - tol) * best
+            assert yg[j] >= (1 - tol) * best
             top2 = np.sort(vals)[-2] if len(vals) > 1 else -np.inf
             if best - top2 > tol * best:
                 assert j == succ[np.argmax(vals)]
             c = j
+
+
+def check_paths(A, Yo, pairs, out, max_hops, tol=1e-10):
+    check_paths_rows(A, lambda g: Yo[g], pairs, out, max_hops, tol)
 
 
 @pytest.mark.parametrize("family,n", [("er", 100), ("lattice", 300), ("rgg", 250), ("tree", 120)])
@@ -381,9 +387,10 @@ def test_next_hop_paths(ctx, family, n):
     torch.cuda.synchronize()
     out = out.cpu().numpy()
     check_paths(A, sol.Y, pairs, out, max_hops)
-    # single hop view
+    # single-hop form: out[q] is the next node (the start when it is the goal)
     one = ctx.next_hop(g, torch.from_numpy(pairs[:, 0]), torch.from_numpy(pairs[:, 1]), 1).cpu().numpy()
-    assert np.array_equal(one[:, 0], pairs[:, 0])
+    assert one.shape == (len(pairs),)
+    assert np.array_equal(one, np.where(pairs[:, 0] == pairs[:, 1], pairs[:, 0], out[:, 1]))
     g.release()
 
 
@@ -395,6 +402,11 @@ def test_next_hop_bad_ids(ctx):
     out = ctx.next_hop(g, cur, goal, 4).cpu().numpy()
     assert (out[:3] == -1).all()
     assert out[3].tolist() == [2, -1, -1, -1, -1]
+    one = ctx.next_hop(g, cur, goal, 1).cpu().numpy()
+    assert one.tolist() == [-1, -1, -1, 2]
+    nxt = ctx.next_hop(g, torch.tensor([0, 9], dtype=torch.int32), torch.tensor([3, 0], dtype=torch.int32),
+                       1).cpu().numpy()
+    assert nxt.tolist() == [1, 0]   # the cycle's successors
     g.release()
 
 
@@ -539,6 +551,50 @@ def test_batched_graph_replay_matches_eager(ctx):
     # and the eager result is the oracle's
     idx = list(range(0, len(As), 6))
     check_batch([specs[k].build() for k in idx], -0.5, [eager[k] for k in idx], _Sub(einfo, idx), None, "eager")
+
+
+def test_batched_plan_cache_cycle(tmp_path):
+    """Regression test of the captured-plan cache: six distinct batch classes
+    (more than the four plans the cache keeps), each autotuned on first use,
+    cycled three times so that plans are evicted and rebuilt; one plan is
+    built on a HIP stream that the caller destroys before that plan is
+    evicted (eviction waits on the plan's own event, never on the stream).
+    Every captured call's D equals the eager launches' D, and sampled graphs
+    equal the oracle."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    c = R.Context(0, tile_cache=str(tmp_path / "tiles.json"))
+    try:
+        sets = []
+        for i, count in enumerate((3, 6, 12, 24, 48, 96)):
+            specs = gg.c3_specs(count, batch_index=40 + i)
+            As = [dev(s.build()) for s in specs]
+            ref, rinfo, _ = c.solve_batched(As, -0.5, flags=R.RDIST_NO_GRAPH)
+            sets.append((specs, R.Batch(As, -0.5), [d.cpu().numpy().copy() for d in ref]))
+        raw = ctypes.c_void_p()
+        assert hip.hipStreamCreate(ctypes.byref(raw)) == 0
+        side = torch.cuda.ExternalStream(raw.value)
+        specs_s = gg.c3_specs(20, batch_index=60)
+        As_s = [dev(s.build()) for s in specs_s]
+        torch.cuda.synchronize()
+        Ds_s, info_s, _ = c.solve_batched(As_s, -0.5, stream=side)
+        check_batch([s.build() for s in specs_s[:6]], -0.5, Ds_s[:6], info_s, None, "side stream")
+        side.synchronize()
+        del side
+        assert hip.hipStreamDestroy(raw) == 0
+        for cycle in range(3):
+            for k, (specs, b, ref) in enumerate(sets):
+                for d in b.Ds:
+                    d.fill_(0x1234)
+                Ds, info, _ = c.solve_batched(b)
+                note(f"[parity] plan cache cycle {cycle} batch {k} count {b.count}")
+                for g in range(b.count):
+                    assert np.array_equal(Ds[g].cpu().numpy(), ref[g]), f"cycle {cycle} batch {k} graph {g}"
+                idx = [0, b.count - 1]
+                check_batch([specs[g].build() for g in idx], -0.5, [Ds[g] for g in idx], _Sub(info, idx), None,
+                            f"cycle {cycle} batch {k}")
+    finally:
+        c.close()
 
 
 def test_batched_autotuner_and_tile_cache(tmp_path):
@@ -704,6 +760,53 @@ def test_c2_full_size_sampled_rows_and_columns(ctx):
     check_sampled(A_np, Yg, D, prep.gamma, cols=[0, 1234, 4097, 8191], rows=[7, 2048, 6000], label="c2")
     del Yg
     g.release()
+
+
+def test_next_hop_full_width_c2(ctx):
+    """Next hop at n = 8192, where a successor bitmap row has 128 words and each
+    lane walks two of them: 64 (start, goal) pairs on the C2 graph, each path
+    checked hop by hop against the oracle's greedy walk on the oracle's series
+    row Y[goal, :] (Sec. 4.2, Eq. descent; Theorem 4), in both output forms."""
+    A_np = gg.c2_graph(0)
+    n = A_np.shape[0]
+    note("[parity] next hop at n=8192 (two bitmap words per lane)")
+    prep = oracle.prepare(A_np, -0.5)
+    _, info, g = ctx.solve(dev(A_np), -0.5, keep=True)
+    assert info["status"] == 0 and info["gamma"] == prep.gamma
+    rng = gg.rng_for("parity", 9900)
+    goals = rng.choice(n, 4, replace=False)
+    starts = rng.choice(n, 16, replace=False)
+    starts[0] = goals[0]
+    pairs = np.array([[c, t] for t in goals for c in starts], dtype=np.int32)
+    # successors of the starts on both halves of the bitmap row
+    assert any(np.nonzero(A_np[:, c])[0].max() >= 4096 for c in starts)
+    rows = {int(t): oracle.y_row(A_np, prep.gamma, int(t)) for t in goals}
+    max_hops = 16
+    out = ctx.next_hop(g, torch.from_numpy(pairs[:, 0].copy()), torch.from_numpy(pairs[:, 1].copy()),
+                       max_hops).cpu().numpy()
+    check_paths_rows(A_np, rows.__getitem__, pairs, out, max_hops)
+    assert all(row[row >= 0][-1] == t for row, (_, t) in zip(out, pairs))   # every walk reaches its goal
+    one = ctx.next_hop(g, torch.from_numpy(pairs[:, 0].copy()), torch.from_numpy(pairs[:, 1].copy()),
+                       1).cpu().numpy()
+    assert np.array_equal(one, np.where(pairs[:, 0] == pairs[:, 1], pairs[:, 0], out[:, 1]))
+    g.release()
+
+
+def test_mixed_c4_full_size_matches_fp64(ctx):
+    """C4 at its own size (n = 16384, 128 slabs): the mixed plan's D equals the
+    FP64 plan's D entry for entry, with the same status and unreachable count,
+    and about a fifth of the entries fall back to FP64 (Sec. 5.1 restated for
+    FP32: entries near an integer or below the FP32 range)."""
+    A = dev(gg.c4_graph(0))
+    note("[parity] C4 n=16384 mixed vs FP64")
+    D64, i64, _ = ctx.solve(A, -0.5)
+    D32, i32, _ = ctx.solve(A, -0.5, flags=R.RDIST_MIXED_F32)
+    note(f"[parity] C4 mixed fallback {i32['fallback_fraction']:.4f} ({i32['n_uncertified']} entries)")
+    assert i64["status"] == 0 and i32["status"] == 0
+    assert i32["gamma"] == i64["gamma"] and i32["delta"] == i64["delta"]
+    assert i32["n_unreachable"] == i64["n_unreachable"]
+    assert bool(torch.equal(D32, D64))
+    assert 0.15 < i32["fallback_fraction"] < 0.25
 
 
 def test_c4_full_size_fp64_sampled(ctx):

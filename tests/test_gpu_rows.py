@@ -127,6 +127,10 @@ def test_goal_paths(ctx):
                                torch.from_numpy(pairs[:, 0].copy()), 3).cpu().numpy()   # walks cut at 3 hops
         assert short.shape == (48, 4)
         check_paths(A, sol.Y, pairs, short, 3)
+        one = ctx.goal_paths(dev(ptr), dev(idx), Y, torch.from_numpy(pairs[:, 1].copy()),
+                             torch.from_numpy(pairs[:, 0].copy()), 1).cpu().numpy()   # single-hop form
+        assert one.shape == (48,)
+        assert np.array_equal(one, np.where(pairs[:, 0] == pairs[:, 1], pairs[:, 0], out[:, 1]))
 
 
 def test_rows_refusals(ctx):

@@ -317,6 +317,28 @@ def test_next_hop_tie_break_and_unreachable():
     assert p.tolist() == [0, 1, 3, -1, -1]
 
 
+def test_path_from_one_series_row_cycle_closed_form():
+    """Greedy walk over one goal row (Sec. 4.2) on a directed 12-cycle: the row
+    from the walk series must be the closed form gamma^((g - j) mod n) / (1 - gamma^n)
+    up to the series' rounding, and the walk from c must run c, c+1, ..., g."""
+    n, gam = 12, 0.3
+    A = gg.directed_cycle(n)
+    for g in (0, 5, 11):
+        y = oracle.y_row(A, gam, g)
+        closed = np.array([gam ** ((g - j) % n) / (1 - gam ** n) for j in range(n)])
+        assert np.max(np.abs(y - closed) / closed) < 1e-14
+        for c in range(n):
+            p = oracle.path_row(A, y, c, g, n)
+            hops = (g - c) % n
+            assert p[:hops + 1].tolist() == [(c + h) % n for h in range(hops + 1)]
+            assert (p[hops + 1:] == -1).all()
+    # the tie rule and the unreachable cases on one row, as for the full-Y walk
+    B = gg.from_edges(5, [0, 0, 1, 2], [1, 2, 3, 3])
+    y3 = oracle.y_row(B, 0.25, 3)
+    assert oracle.path_row(B, y3, 0, 3, 4).tolist() == [0, 1, 3, -1, -1]
+    assert oracle.path_row(B, oracle.y_row(B, 0.25, 0), 3, 0, 2).tolist() == [3, -1, -1]
+
+
 # ---------------------------------------------------------------------------
 # Machine precision (Sec. 5.1)
 # ---------------------------------------------------------------------------
