@@ -170,6 +170,33 @@ rdist_status rdist_solve_batched(rdist_ctx ctx, int32_t count, const int32_t *n,
                                  rdist_info *info, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * solve of rdist_solve for graphs with n <= RDIST_NOALLOC_MAX_N, with no
+ * device allocation, no stream or event creation and no event timing.  Its
+ * kernels use a static device scratch of about 17.6 MiB (the blocked plan's
+ * matrix and step buffers for n = 1024, plus out-degrees and the device
+ * info) that every GPU the library runs on holds until the process ends;
+ * rdist_create takes its address for the context's device.  Every call on
+ * one GPU shares that scratch, whatever the context: calls that overlap on
+ * one GPU (on different streams, contexts or threads) race and must be
+ * serialised by the caller.  All steps run on `stream` in order (no
+ * lookahead stream), so a solve may take longer than with rdist_solve; D and
+ * info are those of rdist_solve with the same arguments (bit for bit).
+ *   flags: RDIST_F64 with optional RDIST_WEIGHTED, RDIST_PLAN_SMALL,
+ *          RDIST_PLAN_BLOCKED, RDIST_UNFUSED_EPILOGUE, RDIST_BLOCK_128,
+ *          RDIST_BLOCK_256 as for rdist_solve; RDIST_MIXED_F32, RDIST_KEEP_Y
+ *          and RDIST_NO_GRAPH are refused (RDIST_E_ARG).
+ *   info : nullable; pinned host memory (a pageable target makes the copy
+ *          synchronous).
+ * RDIST_E_ARG for n outside [1, RDIST_NOALLOC_MAX_N] or the flags above;
+ * RDIST_E_HIP if the scratch's device address could not be taken.
+ */
+#define RDIST_NOALLOC_MAX_N 1024
+rdist_status rdist_solve_noalloc(rdist_ctx ctx, const uint8_t *A_dev, int32_t n, double gamma, uint32_t flags,
+                                 int16_t *D_dev, rdist_info *info, void *stream);
+
+/*
  * Greedy local pursuit on a kept graph (Sec. 4.2, Eq. descent; Theorem 4 and
  * its corollary).  Each hop moves from node i to the successor j of i (edge
  * i -> j) with the largest Y[goal, j], the lowest j on exact ties.  For query

@@ -137,6 +137,8 @@ struct rdist_ctx_s {
     std::vector<std::pair<std::string, rd::eng::BatchTuning>> tuned;   // batch class -> tuning
     bool tuned_dirty = false;
     void *blas = nullptr;   // rocBLAS handle of the mixed-precision path (created on first use)
+    void *noalloc_scratch = nullptr;   // device address of this device's static scratch (rdist_solve_noalloc)
+    std::string noalloc_error;         // why that address is unavailable, if it is
 };
 
 namespace rd {
@@ -162,6 +164,10 @@ rdist_status ensure_aux2(Workspace &w);
 
 hipEvent_t take_event(rdist_ctx c);
 
+// Set while this thread runs a call that may not create events (the
+// allocation-free solve): its launches are never timed.
+extern thread_local bool g_untimed;
+
 // Records an event pair around the launches made during its lifetime when
 // timing is on; drain_timing folds finished pairs into the per-kernel stats.
 struct Timer {
@@ -171,7 +177,7 @@ struct Timer {
     double flops, bytes;
     hipEvent_t a = nullptr;
     Timer(rdist_ctx c_, hipStream_t s_, int w, double f, double b) : c(c_), s(s_), which(w), flops(f), bytes(b) {
-        if ((c->timing_mask & (1u << w)) && !c->timing_hold) {
+        if ((c->timing_mask & (1u << w)) && !c->timing_hold && !g_untimed) {
             a = take_event(c);
             if (a) (void)hipEventRecord(a, s);
         }

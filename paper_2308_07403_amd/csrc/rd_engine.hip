@@ -22,6 +22,33 @@
 #include "rd_engine.h"
 #include "rd_launch.h"
 
+// Static scratch of rdist_solve_noalloc (one copy per GPU the library runs
+// on, held until the process ends): the blocked plan's buffers for order up
+// to RDIST_NOALLOC_MAX_N -- M, Ut[2], V[2], Pt[2], the 256-block inverse's
+// Ut2, V2, Pt2 -- and the small buffer (out-degrees, input flag, device
+// info), at the 256-byte aligned offsets below.  Host code never passes
+// this name to a kernel: rdist_create takes the device address with
+// hipGetSymbolAddress once per device, and the launches receive that.
+namespace rd {
+namespace eng {
+constexpr size_t na_al(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNaMax = RDIST_NOALLOC_MAX_N;
+constexpr size_t kNaM = 0;
+constexpr size_t kNaUt = kNaM + na_al(kNaMax * kNaMax * 8);
+constexpr size_t kNaStep = na_al(256 * kNaMax * 8);   // one Ut or V buffer
+constexpr size_t kNaV = kNaUt + 2 * kNaStep;
+constexpr size_t kNaPt = kNaV + 2 * kNaStep;
+constexpr size_t kNaUt2 = kNaPt + 2 * na_al(256 * 256 * 8);
+constexpr size_t kNaV2 = kNaUt2 + na_al(128 * 256 * 8);
+constexpr size_t kNaPt2 = kNaV2 + na_al(128 * 256 * 8);
+constexpr size_t kNaSmall = kNaPt2 + na_al(128 * 128 * 8);
+constexpr size_t kNaSmallBytes = 256 * ((4 * (kNaMax + 2) + 255) / 256) + sizeof(rdist_info);
+constexpr size_t kNaBytes = kNaSmall + na_al(kNaSmallBytes);
+}  // namespace eng
+}  // namespace rd
+
+static __device__ __align__(256) unsigned char scratch[rd::eng::kNaBytes];
+
 namespace rd {
 namespace eng {
 
@@ -189,19 +216,19 @@ void enqueue_rowcol(rdist_ctx c, Workspace &w, int ld, int nt, int K0, int m, in
 // runs beside the big update.  U, V and P^T are double-buffered by step
 // parity; a step's buffers are rewritten only after the main stream has
 // passed the EDGEREST that follows the REST reading them.
-rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
-                           rdist_graph *keep, rdist_info *info, hipStream_t s) {
-    Workspace &w = c->ws[s];
+// The launch sequence of a blocked solve in workspace w (M, Ut, V, Pt and
+// the 256-block buffers sized for order ld, small for n), ending with D and
+// dinfo written.  as: the lookahead stream; as == s runs every step on s in
+// order (no events), which is correct for the same reason the two-stream
+// schedule is: each step's launches only read what earlier launches wrote.
+rdist_status enqueue_blocked(rdist_ctx c, Workspace &w, int ld, const uint8_t *A, int n, double gamma,
+                             uint32_t flags, int16_t *D, rdist_info *dinfo, hipStream_t s, hipStream_t as) {
     const int m = block_tiles(n, flags);
     const int bw = 128 * m;
     const int np = ((n + bw - 1) / bw) * bw;
     const int nt = np / kB, nbk = np / bw;
-    rdist_status st = ensure_small(c, w, n);
-    if (st) return st;
-    if ((st = ensure_big(c, w, np))) return st;
-    const int ld = w.np_cap;                     // M, Ut, V leading dimension
+    const bool two = as != s;
     double *M = w.m();
-    rdist_info *dinfo = w.dinfo();
     const bool keep_y = (flags & RDIST_KEEP_Y) != 0;
     const bool fused = !(flags & RDIST_UNFUSED_EPILOGUE);
     {
@@ -212,8 +239,8 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
     enqueue_inverse(c, w, ld, 0, m, 0, dinfo, s);
     enqueue_rowcol(c, w, ld, nt, 0, m, 0, dinfo, s);
     // streams of the step loop: the caller's stream and the lookahead stream
-    hipStream_t ms = s, as = w.aux;
-    if (nbk > 1) {
+    hipStream_t ms = s;
+    if (nbk > 1 && two) {
         RD_HIP(hipEventRecord(w.ev_panel, ms));          // block 0's row/column tiles are ready
         RD_HIP(hipStreamWaitEvent(as, w.ev_panel, 0));
     }
@@ -228,13 +255,13 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
             const int td = rd::update_tiles(rd::kUpdateDiag, nt, m, wt);
             const int te = rd::update_tiles(rd::kUpdateEdgeRest, nt, m, wt);
             const int tr = rd::update_tiles(rd::kUpdateRest, nt, m, wt);
-            if (K > 0) RD_HIP(hipStreamWaitEvent(ms, w.ev_panel, 0));
+            if (K > 0 && two) RD_HIP(hipStreamWaitEvent(ms, w.ev_panel, 0));
             {
                 Timer t(c, ms, RDIST_K_UPDATE_EDGE, tile_flops * te, 16.0 * kB * kB * te);
                 rd::launch_update(rd::kUpdateEdgeRest, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo,
                                   ms);
             }
-            RD_HIP(hipEventRecord(w.ev_er, ms));
+            if (two) RD_HIP(hipEventRecord(w.ev_er, ms));
             {
                 Timer t(c, ms, RDIST_K_UPDATE, tile_flops * tr, 16.0 * kB * kB * tr);
                 rd::launch_update(rd::kUpdateRest, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo, ms);
@@ -244,11 +271,11 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
                 rd::launch_update(rd::kUpdateDiag, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo, as);
             }
             enqueue_inverse(c, w, ld, L0, m, par ^ 1, dinfo, as);
-            RD_HIP(hipStreamWaitEvent(as, w.ev_er, 0));
+            if (two) RD_HIP(hipStreamWaitEvent(as, w.ev_er, 0));
             enqueue_rowcol(c, w, ld, nt, L0, m, par ^ 1, dinfo, as);
-            RD_HIP(hipEventRecord(w.ev_panel, as));
+            if (two) RD_HIP(hipEventRecord(w.ev_panel, as));
         } else {
-            if (K > 0) RD_HIP(hipStreamWaitEvent(ms, w.ev_panel, 0));
+            if (K > 0 && two) RD_HIP(hipStreamWaitEvent(ms, w.ev_panel, 0));
             Timer t(c, ms, RDIST_K_UPDATE_EDGE, tile_flops * nt * nt, 16.0 * kB * kB * nt * nt);
             rd::launch_update(rd::kUpdateAll, M, ld, nt, K0, m, 0, m, Ut, V, ld, fused, n, D, keep_y ? 1 : 0, dinfo,
                               ms);
@@ -261,7 +288,21 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
     }
     rd::launch_fill_sentinel(D, n, dinfo, s);
     RD_HIP(hipGetLastError());
-    if (keep_y && keep) {
+    return RDIST_OK;
+}
+
+rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
+                           rdist_graph *keep, rdist_info *info, hipStream_t s) {
+    Workspace &w = c->ws[s];
+    const int bw = 128 * block_tiles(n, flags);
+    const int np = ((n + bw - 1) / bw) * bw;
+    rdist_status st = ensure_small(c, w, n);
+    if (st) return st;
+    if ((st = ensure_big(c, w, np))) return st;
+    const int ld = w.np_cap;                     // M, Ut, V leading dimension
+    rdist_info *dinfo = w.dinfo();
+    if ((st = enqueue_blocked(c, w, ld, A, n, gamma, flags, D, dinfo, s, w.aux))) return st;
+    if ((flags & RDIST_KEEP_Y) && keep) {
         Buf y = w.M;          // the graph takes M over (its bytes stay counted)
         w.M = Buf{};
         st = make_graph(c, n, (double *)y.p, ld, y.bytes, A, s, keep, dinfo, (flags & RDIST_WEIGHTED) != 0);
@@ -271,6 +312,27 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
         }
     }
     return copy_info(info, dinfo, 1, s);
+}
+
+// Workspace view of the static scratch at its device address base, for a
+// blocked solve of padded order np <= RDIST_NOALLOC_MAX_N (leading
+// dimension np) or a small solve: nothing is allocated.
+Workspace noalloc_view(void *base, int np) {
+    char *b = (char *)base;
+    Workspace v;
+    v.np_cap = np;
+    v.M = Buf{b + kNaM, (size_t)np * np * 8};
+    for (int q = 0; q < 2; ++q) {
+        v.Ut[q] = Buf{b + kNaUt + q * kNaStep, (size_t)256 * np * 8};
+        v.V[q] = Buf{b + kNaV + q * kNaStep, (size_t)256 * np * 8};
+        v.Pt[q] = Buf{b + kNaPt + q * na_al(256 * 256 * 8), (size_t)256 * 256 * 8};
+    }
+    v.Ut2 = Buf{b + kNaUt2, (size_t)128 * 256 * 8};
+    v.V2 = Buf{b + kNaV2, (size_t)128 * 256 * 8};
+    v.Pt2 = Buf{b + kNaPt2, (size_t)128 * 128 * 8};
+    v.small = Buf{b + kNaSmall, kNaSmallBytes};
+    v.n_cap = (int)kNaMax;
+    return v;
 }
 
 rdist_status solve_small(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
@@ -355,8 +417,31 @@ rdist_status rdist_create(rdist_ctx *out, int device, size_t hbm_budget_bytes, c
     RD_HIP(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(RDIST_E_ARG, "no such device");
     RD_HIP(hipSetDevice(device));
+    // device address of this device's copy of the static scratch, taken
+    // once per device with the device current
+    static std::mutex na_mu;
+    static std::map<int, std::pair<void *, std::string>> na_addr;
+    void *na_ptr = nullptr;
+    std::string na_err;
+    {
+        std::lock_guard<std::mutex> lk(na_mu);
+        auto it = na_addr.find(device);
+        if (it == na_addr.end()) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) (void)hipGetLastError();
+            it = na_addr.emplace(device, std::make_pair(e == hipSuccess ? ptr : nullptr,
+                                                        e == hipSuccess ? std::string()
+                                                                        : std::string("hipGetSymbolAddress(scratch): ") +
+                                                                              hipGetErrorString(e))).first;
+        }
+        na_ptr = it->second.first;
+        na_err = it->second.second;
+    }
     auto *c = new rdist_ctx_s();
     c->device = device;
+    c->noalloc_scratch = na_ptr;
+    c->noalloc_error = na_err;
     c->budget = hbm_budget_bytes;
     c->threadsafe = (flags & RDIST_THREADSAFE) != 0;
     hipDeviceProp_t prop;
@@ -406,6 +491,41 @@ rdist_status rdist_solve(rdist_ctx c, const uint8_t *A_dev, int32_t n, double ga
     const bool small = !(flags & (RDIST_PLAN_BLOCKED | RDIST_WEIGHTED)) && n <= 128;
     if (small) return solve_small(c, A_dev, n, gamma, flags, D_dev, keep, info, s);
     return solve_blocked(c, A_dev, n, gamma, flags, D_dev, keep, info, s);
+}
+
+rdist_status rdist_solve_noalloc(rdist_ctx c, const uint8_t *A_dev, int32_t n, double gamma, uint32_t flags,
+                                 int16_t *D_dev, rdist_info *info, void *stream) {
+    if (!c) return fail(RDIST_E_ARG, "ctx is NULL");
+    if (!A_dev || !D_dev) return fail(RDIST_E_ARG, "A_dev and D_dev are required");
+    if (n < 1 || n > RDIST_NOALLOC_MAX_N)
+        return fail(RDIST_E_ARG, "rdist_solve_noalloc: n must lie in [1, " + std::to_string(RDIST_NOALLOC_MAX_N) +
+                                     "], the largest order its static scratch holds");
+    rdist_status st;
+    if ((st = check_flags(flags))) return st;
+    if ((st = check_gamma(gamma))) return st;
+    if (flags & (RDIST_MIXED_F32 | RDIST_KEEP_Y | RDIST_NO_GRAPH))
+        return fail(RDIST_E_ARG, "rdist_solve_noalloc takes no RDIST_MIXED_F32, RDIST_KEEP_Y or RDIST_NO_GRAPH");
+    if ((flags & RDIST_PLAN_SMALL) && n > 128) return fail(RDIST_E_ARG, "RDIST_PLAN_SMALL needs n <= 128");
+    Guard g(c);
+    if (!c->noalloc_scratch) return fail(RDIST_E_HIP, "rdist_solve_noalloc: " + c->noalloc_error);
+    RD_HIP(hipSetDevice(c->device));
+    struct Untimed {
+        Untimed() { g_untimed = true; }
+        ~Untimed() { g_untimed = false; }
+    } untimed;
+    hipStream_t s = (hipStream_t)stream;
+    const int bw = 128 * block_tiles(n, flags);
+    const int np = ((n + bw - 1) / bw) * bw;
+    Workspace v = noalloc_view(c->noalloc_scratch, np);
+    const bool small = !(flags & (RDIST_PLAN_BLOCKED | RDIST_WEIGHTED)) && n <= 128;
+    if (small) {
+        rd::SmallTask t{A_dev, D_dev, nullptr, n, n, gamma, v.dinfo()};
+        rd::launch_small_one(t, s);
+        RD_HIP(hipGetLastError());
+    } else if ((st = enqueue_blocked(c, v, np, A_dev, n, gamma, flags, D_dev, v.dinfo(), s, s))) {
+        return st;
+    }
+    return copy_info(info, v.dinfo(), 1, s);
 }
 
 rdist_status rdist_next_hop(rdist_ctx c, rdist_graph gr, const int32_t *cur_dev, const int32_t *goal_dev, int32_t q,
@@ -756,13 +876,13 @@ rdist_status rdist_gain_bounds(rdist_ctx c, const uint8_t *A_dev, int32_t n, int
     if ((st = ensure_grow(c, w.gb, 2 * vb + sb + db + 256))) return st;
     char *base = (char *)w.gb.p;
     double *x[2] = {(double *)base, (double *)(base + vb)};
-    void *scratch = base + 2 * vb;
+    void *pw = base + 2 * vb;
     int32_t *outdeg = (int32_t *)(base + 2 * vb + sb), *badp = outdeg + n + 1;
     rdist_info *ginf = (rdist_info *)(base + 2 * vb + sb + db);
     std::vector<char> host(rd::power_scratch_bytes());
     // Delta and the input check (0/1 entries, no self-loop): the solve's gate
     rd::launch_gate(A_dev, n, -0.5, outdeg, badp, ginf, s);
-    rd::launch_power_init(scratch, s);
+    rd::launch_power_init(pw, s);
     rdist_info gi{};
     RD_HIP(hipMemcpyAsync(&gi, ginf, sizeof(rdist_info), hipMemcpyDeviceToHost, s));
     RD_HIP(hipStreamSynchronize(s));
@@ -772,10 +892,10 @@ rdist_status rdist_gain_bounds(rdist_ctx c, const uint8_t *A_dev, int32_t n, int
     int k = 0;
     while (!bad && k < max_steps) {
         const int chunk = std::min(16, max_steps - k);
-        for (int t = 0; t < chunk; ++t, ++k) rd::launch_power_step(A_dev, n, x[k & 1], x[(k & 1) ^ 1], scratch, k, s);
-        rd::launch_power_fold(scratch, k - 1, s);
+        for (int t = 0; t < chunk; ++t, ++k) rd::launch_power_step(A_dev, n, x[k & 1], x[(k & 1) ^ 1], pw, k, s);
+        rd::launch_power_fold(pw, k - 1, s);
         RD_HIP(hipGetLastError());
-        RD_HIP(hipMemcpyAsync(host.data(), scratch, host.size(), hipMemcpyDeviceToHost, s));
+        RD_HIP(hipMemcpyAsync(host.data(), pw, host.size(), hipMemcpyDeviceToHost, s));
         RD_HIP(hipStreamSynchronize(s));
         double lr, hr;
         rd::power_read(host.data(), &lr, &hr);

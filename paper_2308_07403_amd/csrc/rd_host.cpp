@@ -17,6 +17,7 @@ namespace rd {
 namespace eng {
 
 thread_local std::string g_last_error;
+thread_local bool g_untimed = false;
 
 rdist_status dalloc(rdist_ctx c, void **p, size_t bytes) {
     *p = nullptr;

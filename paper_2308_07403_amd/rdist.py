@@ -109,6 +109,8 @@ _lib.rdist_destroy.restype = None
 _lib.rdist_solve.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_uint32, _P, ctypes.POINTER(_P),
                              _P, _P]
 _lib.rdist_solve.restype = ctypes.c_int
+_lib.rdist_solve_noalloc.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_uint32, _P, _P, _P]
+_lib.rdist_solve_noalloc.restype = ctypes.c_int
 _lib.rdist_solve_batched.argtypes = [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_uint32, _P, _P, _P, _P]
 _lib.rdist_solve_batched.restype = ctypes.c_int
 _lib.rdist_next_hop.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]
@@ -172,6 +174,7 @@ _lib.rdist_server_destroy.restype = None
 rdist_create = _lib.rdist_create
 rdist_destroy = _lib.rdist_destroy
 rdist_solve = _lib.rdist_solve
+rdist_solve_noalloc = _lib.rdist_solve_noalloc
 rdist_solve_batched = _lib.rdist_solve_batched
 rdist_next_hop = _lib.rdist_next_hop
 rdist_graph_release = _lib.rdist_graph_release
@@ -195,7 +198,7 @@ rdist_server_poll = _lib.rdist_server_poll
 rdist_server_stats_get = _lib.rdist_server_stats_get
 rdist_server_destroy = _lib.rdist_server_destroy
 
-EXPORTS = ("rdist_create", "rdist_destroy", "rdist_solve", "rdist_solve_batched", "rdist_next_hop",
+EXPORTS = ("rdist_create", "rdist_destroy", "rdist_solve", "rdist_solve_noalloc", "rdist_solve_batched", "rdist_next_hop",
            "rdist_graph_release", "rdist_graph_y", "rdist_graph_update_edge", "rdist_graph_update_edges", "rdist_goal_rows", "rdist_goal_paths",
            "rdist_gain_bounds", "rdist_certify",
            "rdist_epilogue", "rdist_set_timing", "rdist_timing_hold",
