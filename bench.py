@@ -121,7 +121,8 @@ def measure_mixed(ctx, R, torch, A, D_ref, steps, stream):
     ctx.solve_async(A, -0.5, R.RDIST_MIXED_F32, D, info=info, stream=stream)
     torch.cuda.synchronize()
     split = {name: ctx.kernel_stats(k)["total_ms"] for name, k in
-             (("ingest", R.RDIST_K_INGEST), ("panel_fp64", R.RDIST_K_PANEL), ("fp32_gemm", R.RDIST_K_MIXED_GEMM),
+             (("ingest", R.RDIST_K_INGEST), ("panel_fp64", R.RDIST_K_PANEL), ("fp32_rows", R.RDIST_K_ROWCOL),
+              ("fp32_gemm", R.RDIST_K_MIXED_GEMM),
               ("certify", R.RDIST_K_CERTIFY), ("refine", R.RDIST_K_REFINE))}
     ctx.set_timing(False)
     st = info.get(0).as_dict()
@@ -324,7 +325,7 @@ def bench_c4(args, torch, R, gg):
                    "seed": "c4/0"},
         "mixed": mixed,
         "fp64": {"ms_per_solve": ms64, "graphs_per_s": 1e3 / ms64, "eff_tflops": 2.0 * n ** 3 / (ms64 * 1e-3) / 1e12},
-        "roofline": {"bound": "mfma", "kernel": "FP32 trailing-update GEMM (rocBLAS sgemm, rank-256)",
+        "roofline": {"bound": "mfma", "kernel": "k_gemm32<1> (FP32 MFMA trailing update, rank 256, 128 x 128 tiles)",
                      "achieved": mixed["fp32_gemm_tflops"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": mixed["fp32_gemm_frac_of_peak"], "traffic": None},
     }

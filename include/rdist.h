@@ -481,7 +481,8 @@ typedef struct rdist_kernel_stats {
 #define RDIST_K_CERTIFY 8     /* mixed precision: certification + recompute; rdist_certify */
 #define RDIST_K_UPDATE_EDGE 9 /* update of the next block's row and column (lookahead) and the
                                  last, readout-fused update */
-#define RDIST_K_MIXED_GEMM 10  /* mixed precision: FP32 row products and trailing updates */
+#define RDIST_K_MIXED_GEMM 10  /* mixed precision: the FP32 trailing updates (row products, -U^T and
+                                  P^T count as RDIST_K_ROWCOL) */
 #define RDIST_K_REFINE 11     /* mixed precision: residual, correction product and recompute */
 #define RDIST_K_EDGE_UPDATE 12 /* rdist_graph_update_edge: the rank-1 pass over Y (and D) */
 #define RDIST_K_ROWS_STEP 13   /* rdist_goal_rows: one iteration step */

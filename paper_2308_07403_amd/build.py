@@ -15,9 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librdist.so")
-SOURCES = ["rd_engine.hip", "rd_host.cpp", "rd_batch.hip", "rd_mixed.hip", "rd_server.hip", "rd_kernels.hip", "rd_update.hip", "rd_level.hip", "rd_paths.hip", "rd_dynamic.hip", "rd_rows.hip", "rd_gamma.hip"]
-# rocBLAS provides the plain FP32 GEMMs of the mixed-precision plan
-LINK = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+SOURCES = ["rd_engine.hip", "rd_host.cpp", "rd_batch.hip", "rd_mixed.hip", "rd_server.hip", "rd_kernels.hip", "rd_update.hip", "rd_level.hip", "rd_paths.hip", "rd_dynamic.hip", "rd_rows.hip", "rd_gamma.hip", "rd_gemm.hip"]
+# every kernel is this project's own: no vendor math library is linked
+LINK = []
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 

@@ -203,6 +203,28 @@ struct RegGJ {
     __device__ __forceinline__ bool invert(int n, double *lds, int ty, int tx) { return run(0, n, lds, ty, tx); }
 };
 
+// Order of the tiles of an nr x nr grid for a big launch.  Workgroups are
+// handed to the 8 XCDs round-robin (workgroup b to XCD b % 8), and each XCD
+// has its own 4 MB L2.  Workgroup b = 8l + x is given position x*F + l of a
+// list that walks strips of 8 tile rows column by column (F = number of
+// workgroups per XCD), so the tiles an XCD holds at one time cover about 8
+// tile rows x 8 tile columns and share their U and V operand slabs in L2.
+// A bijection on [0, nr nc) whatever the hardware's actual assignment (nr x nc
+// grids; xcd_strip_order is the square case).
+__device__ __forceinline__ void xcd_strip_order_rect(int b, int nr, int nc, int &i, int &j) {
+    const int total = nr * nc;
+    const int full = total & ~7;
+    const int idx = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
+    const int s = idx / (8 * nc);
+    const int w = idx - s * 8 * nc;
+    const int h = min(8, nr - 8 * s);
+    j = w / h;
+    i = 8 * s + (w - j * h);
+}
+__device__ __forceinline__ void xcd_strip_order(int b, int nr, int &i, int &j) {
+    xcd_strip_order_rect(b, nr, nr, i, j);
+}
+
 // ---------------------------------------------------------------------------
 // 128 x 128 FP64 tile contraction on MFMA (v_mfma_f64_16x16x4_f64).
 // 256 threads = 4 waves; wave w owns the 64 x 64 quadrant (w >> 1, w & 1) as

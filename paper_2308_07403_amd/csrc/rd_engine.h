@@ -136,7 +136,6 @@ struct rdist_ctx_s {
     std::string tile_cache_path;
     std::vector<std::pair<std::string, rd::eng::BatchTuning>> tuned;   // batch class -> tuning
     bool tuned_dirty = false;
-    void *blas = nullptr;   // rocBLAS handle of the mixed-precision path (created on first use)
     void *noalloc_scratch = nullptr;   // device address of this device's static scratch (rdist_solve_noalloc)
     std::string noalloc_error;         // why that address is unavailable, if it is
 };
@@ -207,7 +206,6 @@ rdist_status solve_blocked(rdist_ctx c, const uint8_t *A, int n, double gamma, u
 // rd_mixed.hip
 rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
                          rdist_info *info, hipStream_t s);
-void destroy_blas(rdist_ctx c);
 
 void free_workspace(rdist_ctx c, Workspace &w);
 void release_stream_workspace(rdist_ctx c, hipStream_t s);

@@ -463,7 +463,6 @@ void rdist_destroy(rdist_ctx c) {
         (void)hipSetDevice(c->device);
         drain_timing(c);
         destroy_plans(c);
-        destroy_blas(c);
         if (c->tuned_dirty) save_tile_cache(c);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
         std::vector<rdist_graph_s *> gs(c->graphs.begin(), c->graphs.end());

@@ -1,0 +1,367 @@
+// rd_gemm.hip -- the matrix-core contractions of the mixed-precision plan
+// (RDIST_MIXED_F32, the FP64 precision limit of Sec. 5.1 restated for FP32):
+//
+//   k_gemm32     FP32 blocked Gauss-Jordan on v_mfma_f32_32x32x2f32:
+//                the row product V = P M_K,: and the trailing update
+//                M <- M~ - U V of one 256-wide step, over 128 x 128 tiles;
+//   k_corr_bf16  the refinement's correction C = X0 R from bf16 hi/lo parts,
+//                C = Xh Rh + Xh Rl + Xl Rh on v_mfma_f32_32x32x16_bf16 with
+//                FP32 accumulation, over 256 x 256 tiles;
+//   k_ut32, k_pt32, k_split_bf16_t: the operand layouts these read.
+//
+// Both contractions read k-chunks of their operands from LDS, copied there
+// by the load unit (global_load_lds, 16 bytes per lane, double-buffered), so
+// no VGPRs stage the copies; 256 threads = 4 waves, wave w owns a quadrant
+// (w >> 1, w & 1) of the tile as blocks of 32 x 32.  (Measured and dropped
+// for the FP32 update: 128 x 256 tiles with 2 x 4 blocks per wave, two
+// workgroups per compute unit, 1194 against 1140 us per C4 step.)
+// Accumulator element r of lane l in a 32 x 32 block is row
+// 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32 (both instructions; checked
+// on gfx950).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rd_device.h"
+#include "rd_launch.h"
+
+namespace rd {
+
+namespace {
+
+constexpr int kT = 128;                 // output tile
+constexpr int kMB = 256;                // step width of the FP32 Gauss-Jordan (inner dimension of k_gemm32)
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct Acc32 {
+    f32x16 v[2][2];
+};
+
+// Row / column within the tile of accumulator element (p, q, r) of this lane.
+__device__ __forceinline__ int acc_row(int p, int r) {
+    return ((threadIdx.x >> 6) >> 1) * 64 + 32 * p + 8 * (r >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (r & 3);
+}
+__device__ __forceinline__ int acc_col(int q) { return ((threadIdx.x >> 6) & 1) * 64 + 32 * q + (threadIdx.x & 31); }
+
+// ---- FP32: operands k-major, A_k[k][i], B_k[k][j] ----
+// 128 x 128 output tiles, wave w owns the 64 x 64 quadrant (w >> 1, w & 1)
+// as 2 x 2 blocks of 32 x 32; 32 KiB of LDS, so up to five workgroups share
+// a compute unit and hide each other's memory latency.
+constexpr int kKC32 = 16;                     // k-rows per chunk
+constexpr int kChunk32 = kKC32 * kT;          // floats per operand chunk (8 KiB)
+
+// Wave w copies k-rows 4w .. 4w+3 of both operands' chunk at k0; one
+// instruction moves two k-rows of 128 floats (lanes 0-31 the first).
+__device__ __forceinline__ void dma32(const float *__restrict__ A, int lda, const float *__restrict__ B, int ldb,
+                                      int k0, float *As, float *Bs) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int half = lane >> 5, c = (lane & 31) * 4;
+#pragma unroll
+    for (int q = 0; q < kKC32 / 8; ++q) {
+        const int r = w * (kKC32 / 4) + 2 * q;
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(A + (size_t)(k0 + r + half) * lda + c),
+                                         (lds_void *)(As + r * kT), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(B + (size_t)(k0 + r + half) * ldb + c),
+                                         (lds_void *)(Bs + r * kT), 16, 0, 0);
+    }
+}
+
+// One chunk: 8 k-steps of 2, four 32 x 32 blocks per step.
+__device__ __forceinline__ void mma32_chunk(const float *As, const float *Bs, Acc32 &acc) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m0 = (w >> 1) * 64 + (lane & 31), n0 = (w & 1) * 64 + (lane & 31), kr = lane >> 5;
+#pragma unroll
+    for (int ks = 0; ks < kKC32 / 2; ++ks) {
+        const float *ar = As + (2 * ks + kr) * kT, *br = Bs + (2 * ks + kr) * kT;
+        const float a0 = ar[m0], a1 = ar[m0 + 32], b0 = br[n0], b1 = br[n0 + 32];
+        acc.v[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc.v[0][0], 0, 0, 0);
+        acc.v[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc.v[0][1], 0, 0, 0);
+        acc.v[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc.v[1][0], 0, 0, 0);
+        acc.v[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc.v[1][1], 0, 0, 0);
+    }
+}
+
+// MODE 0 (row product): tile (I, J) = blockIdx.x as I * ntj + J, C = A_k^T B_k.
+// MODE 1 (trailing update): tiles of an ntj x ntj grid in XCD strip order,
+// C <- C~ + A_k^T B_k, where C~ is C with the tile rows and columns
+// [zk0, zk0 + 2) (the step's block) zeroed; A_k holds -U^T.
+// Inner dimension kMB (256).
+template <int MODE>
+__global__ __launch_bounds__(256, 4) void k_gemm32(float *__restrict__ C, int ldc, int ntj, int zk0,
+                                                   const float *__restrict__ Ak, int lda,
+                                                   const float *__restrict__ Bk, int ldb, const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ float lds[4 * kChunk32];   // A, B x two buffers: 32 KiB
+    int I, J;
+    if (MODE == 1) {
+        xcd_strip_order(blockIdx.x, ntj, I, J);
+    } else {
+        I = blockIdx.x / ntj;
+        J = blockIdx.x - I * ntj;
+    }
+    const float *A = Ak + (size_t)I * kT, *B = Bk + (size_t)J * kT;
+    float *base = C + (size_t)I * kT * ldc + (size_t)J * kT;
+    dma32(A, lda, B, ldb, 0, lds, lds + kChunk32);
+    Acc32 acc;
+    const bool zero = MODE == 0 || (I >= zk0 && I < zk0 + 2) || (J >= zk0 && J < zk0 + 2);
+    if (zero) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc.v[p][q][r] = 0.0f;
+    } else {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc.v[p][q][r] = base[(size_t)acc_row(p, r) * ldc + acc_col(q)];
+    }
+    wait_vm_all();
+    __syncthreads();
+    constexpr int nch = kMB / kKC32;
+#pragma unroll 1
+    for (int ch = 0; ch < nch; ++ch) {
+        float *cur = lds + (ch & 1) * (2 * kChunk32);
+        float *nxt = lds + ((ch + 1) & 1) * (2 * kChunk32);
+        if (ch + 1 < nch) dma32(A, lda, B, ldb, (ch + 1) * kKC32, nxt, nxt + kChunk32);
+        mma32_chunk(cur, cur + kChunk32, acc);
+        wait_vm_all();
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) base[(size_t)acc_row(p, r) * ldc + acc_col(q)] = acc.v[p][q][r];
+}
+
+// Ut (kMB x np, k-major) = -U^T for step K0: Ut[k][i] = -M[i][K0 + k] for
+// rows i outside the block, and the identity (U's rows there are -I) for
+// rows inside it.  64 x 64 pieces through LDS, both sides coalesced.
+__global__ __launch_bounds__(256) void k_ut32(const float *__restrict__ M, int np, int K0, float *__restrict__ Ut,
+                                              const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ float t[64][65];
+    const int i0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) t[r][tx] = M[(size_t)(i0 + r) * np + K0 + k0 + tx];
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int k = k0 + r, i = i0 + tx;
+        const bool in = i >= K0 && i < K0 + kMB;
+        Ut[(size_t)k * np + i] = in ? (i - K0 == k ? 1.0f : 0.0f) : -t[tx][r];
+    }
+}
+
+// Pt (kMB x kMB) = P^T rounded to FP32 (mode 0), or P into V's block
+// columns at K0 (mode 1); S holds P in FP64, row-major.
+__global__ __launch_bounds__(256) void k_pt32(const double *__restrict__ S, float *__restrict__ Pt,
+                                              float *__restrict__ V, int np, int K0, const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ double t[32][33];
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    if (V) {
+        for (int r = ty; r < 32; r += 8) V[(size_t)(r0 + r) * np + K0 + c0 + tx] = (float)S[(r0 + r) * kMB + c0 + tx];
+        return;
+    }
+    for (int r = ty; r < 32; r += 8) t[r][tx] = S[(r0 + r) * kMB + c0 + tx];
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) Pt[(c0 + r) * kMB + r0 + tx] = (float)t[tx][r];
+}
+
+// ---- bf16: operands m-major (k contiguous), A[i][k], B[j][k] ----
+// 256 x 256 output tiles; wave w owns the 128 x 128 quadrant (w >> 1, w & 1)
+// as 4 x 4 blocks of 32 x 32 (accumulators in 256 AGPRs, one wave per SIMD),
+// so each fragment read from LDS feeds four MFMAs.  The three products run
+// as one sequence of 64-k chunks, double-buffered, so the copy of the next
+// product's first chunk overlaps the last chunk of the one before.
+// (Measured and dropped: 2 x 2 blocks per wave, LDS-bound at 30.5 ms for
+// the C4 correction against 26.8 ms; the three products fused per k-step,
+// 27.4 ms; fused with a four-stage ring of 16-k chunks, 32.1 ms.)
+constexpr int kTB = 256;                // output tile of the bf16 contraction
+constexpr int kKCb = 64;                // k per chunk
+constexpr int kRowB = kKCb * 2;         // bytes per LDS row (eight 16-byte pieces)
+constexpr int kChunkB = kTB * kRowB;    // bytes per operand chunk (32 KiB)
+
+struct AccB {
+    f32x16 v[4][4];
+};
+
+// Wave w copies rows 64w .. 64w+63 of both operands' chunk at k0, eight rows
+// per instruction.  Piece c (k0 + 8c .. k0 + 8c + 7) of row r is stored at
+// position c ^ (r & 7) of the row, so that the rows a fragment load touches
+// at one piece index fall into distinct LDS banks.
+__device__ __forceinline__ void dmab(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, int K, int k0,
+                                     char *As, char *Bs) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rr = lane >> 3, c = (lane & 7) ^ rr;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int r0 = w * 64 + q * 8;
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(A + (size_t)(r0 + rr) * K + k0 + 8 * c),
+                                         (lds_void *)(As + r0 * kRowB), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(B + (size_t)(r0 + rr) * K + k0 + 8 * c),
+                                         (lds_void *)(Bs + r0 * kRowB), 16, 0, 0);
+    }
+}
+
+__device__ __forceinline__ bf16x8 frag_b(const char *S, int row, int c) {
+    return *reinterpret_cast<const bf16x8 *>(S + row * kRowB + ((c ^ (row & 7)) << 4));
+}
+
+// One chunk: 4 k-steps of 16; lane l reads k 8 (l / 32) .. +7 of its step.
+__device__ __forceinline__ void mmab_chunk(const char *As, const char *Bs, AccB &acc) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int mr = (w >> 1) * 128 + (lane & 31), nr = (w & 1) * 128 + (lane & 31), half = lane >> 5;
+#pragma unroll
+    for (int st = 0; st < kKCb / 16; ++st) {
+        const int c = 2 * st + half;
+        bf16x8 a[4], b[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) a[p] = frag_b(As, mr + 32 * p, c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = frag_b(Bs, nr + 32 * q, c);
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc.v[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[p], b[q], acc.v[p][q], 0, 0, 0);
+    }
+}
+
+// C (nti*256 x ntj*256, ldc) = Xh Rh + Xh Rl + Xl Rh, inner dimension K (a
+// multiple of 64): the X parts row-major (row i holds row i of X), the R
+// parts transposed (row j holds column j of R), all with row length K.
+__global__ __launch_bounds__(256, 1) void k_corr_bf16(float *__restrict__ C, int ldc, int nti, int ntj, int K,
+                                                      const uint16_t *__restrict__ Xh,
+                                                      const uint16_t *__restrict__ Xl,
+                                                      const uint16_t *__restrict__ Rh,
+                                                      const uint16_t *__restrict__ Rl, const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ __attribute__((aligned(16))) char lds[4 * kChunkB];   // A, B x two buffers: 128 KiB
+    int I, J;
+    xcd_strip_order_rect(blockIdx.x, nti, ntj, I, J);
+    const size_t ao = (size_t)I * kTB * K, bo = (size_t)J * kTB * K;
+    const int per = K / kKCb, total = 3 * per;
+    // chunk g: product g / per (Xh Rh, Xh Rl, Xl Rh), k0 = 64 (g mod per)
+    auto operands = [&](int g, const uint16_t *&A, const uint16_t *&B, int &k0) {
+        const int t = g / per;
+        k0 = (g - t * per) * kKCb;
+        A = (t < 2 ? Xh : Xl) + ao;
+        B = (t == 1 ? Rl : Rh) + bo;
+    };
+    const uint16_t *A, *B;
+    int k0;
+    operands(0, A, B, k0);
+    dmab(A, B, K, k0, lds, lds + kChunkB);
+    AccB acc;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc.v[p][q][r] = 0.0f;
+    wait_vm_all();
+    __syncthreads();
+#pragma unroll 1
+    for (int g = 0; g < total; ++g) {
+        char *cur = lds + (g & 1) * (2 * kChunkB);
+        char *nxt = lds + ((g + 1) & 1) * (2 * kChunkB);
+        if (g + 1 < total) {
+            operands(g + 1, A, B, k0);
+            dmab(A, B, K, k0, nxt, nxt + kChunkB);
+        }
+        mmab_chunk(cur, cur + kChunkB, acc);
+        wait_vm_all();
+        __syncthreads();
+    }
+    float *base = C + (size_t)I * kTB * ldc + (size_t)J * kTB;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = (w >> 1) * 128 + 32 * p + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = (w & 1) * 128 + 32 * q + (lane & 31);
+                base[(size_t)row * ldc + col] = acc.v[p][q][r];
+            }
+}
+
+// bf16 with round to nearest even of a finite float (its 16 high bits).
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Power-of-two exponent s with 2^s max|R| in [0.5, 1) (0 when R is zero).
+__device__ __forceinline__ int rscale(unsigned rmax_bits) {
+    if (rmax_bits == 0) return 0;
+    return -((int)((rmax_bits >> 23) & 0xFF) - 127 + 1);
+}
+
+// hi / lo bf16 parts of 2^s R, transposed: R is rows x cols (ld cols),
+// Ht / Lt are cols_pad x rows (ld rows), rows cols .. cols_pad - 1 zero; s
+// from rmax as for the residual.
+__global__ __launch_bounds__(256) void k_split_bf16_t(const float *__restrict__ R, int rows, int cols,
+                                                      uint16_t *__restrict__ Ht, uint16_t *__restrict__ Lt,
+                                                      const unsigned *__restrict__ rmax) {
+    __shared__ float t[64][65];
+    const float sc = ldexpf(1.0f, rscale(*rmax));
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) t[r][tx] = c0 + tx < cols ? R[(size_t)(r0 + r) * cols + c0 + tx] * sc : 0.0f;
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const float x = t[tx][r];
+        const uint16_t h = bf16_bits(x);
+        const size_t o = (size_t)(c0 + r) * rows + r0 + tx;
+        Ht[o] = h;
+        Lt[o] = bf16_bits(x - __uint_as_float((unsigned)h << 16));
+    }
+}
+
+}  // namespace
+
+void launch_gemm32_rows(const float *Pt, const float *M, int np, int K0, float *V, const rdist_info *info,
+                        hipStream_t s) {
+    const int nt = np / kT;
+    hipLaunchKernelGGL(k_gemm32<0>, dim3(2 * nt), dim3(256), 0, s, V, np, nt, 0, Pt, kMB, M + (size_t)K0 * np, np,
+                       info);
+}
+
+void launch_gemm32_update(float *M, int np, int K0, const float *Ut, const float *V, const rdist_info *info,
+                          hipStream_t s) {
+    const int nt = np / kT;
+    hipLaunchKernelGGL(k_gemm32<1>, dim3(nt * nt), dim3(256), 0, s, M, np, nt, K0 / kT, Ut, np, V, np, info);
+}
+
+void launch_ut32(const float *M, int np, int K0, float *Ut, const rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_ut32, dim3(np / 64, kMB / 64), dim3(256), 0, s, M, np, K0, Ut, info);
+}
+
+void launch_pt32(const double *S, float *Pt, float *V, int np, int K0, const rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_pt32, dim3(kMB / 32, kMB / 32), dim3(256), 0, s, S, Pt, V, np, K0, info);
+}
+
+int corr_cols(int cols) { return (cols + kTB - 1) / kTB * kTB; }
+
+void launch_corr_bf16(float *C, int rows, int cols_pad, int K, const uint16_t *Xh, const uint16_t *Xl,
+                      const uint16_t *Rht, const uint16_t *Rlt, const rdist_info *info, hipStream_t s) {
+    const int nti = rows / kTB, ntj = cols_pad / kTB;
+    hipLaunchKernelGGL(k_corr_bf16, dim3(nti * ntj), dim3(256), 0, s, C, cols_pad, nti, ntj, K, Xh, Xl, Rht, Rlt,
+                       info);
+}
+
+void launch_split_bf16_t(const float *R, int rows, int cols, int cols_pad, uint16_t *Ht, uint16_t *Lt,
+                         const unsigned *rmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_split_bf16_t, dim3(cols_pad / 64, rows / 64), dim3(256), 0, s, R, rows, cols, Ht, Lt, rmax);
+}
+
+}  // namespace rd

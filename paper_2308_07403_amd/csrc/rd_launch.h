@@ -94,8 +94,6 @@ void launch_lv(int phase, const LevelGraph *gs, const int *units, int grid, int 
 // Mixed precision (rd_mixed.hip).
 void launch_m32_build(const uint8_t *A, int n, int np, float *M, const rdist_info *info, hipStream_t s);
 void launch_diag_to_f64(const float *M, int np, int K0, double *S, hipStream_t s);
-void launch_p_to_f32(const double *S, float *P, float *V, int np, int K0, hipStream_t s);
-void launch_ucopy_zero(float *M, int np, int K0, float *U, hipStream_t s);
 void launch_certify(const float *X, int np, int n, double margin, int16_t *D, int32_t *slab_flag,
                     unsigned long long *cnt, rdist_info *info, hipStream_t s);
 void launch_row_count(const uint8_t *A, int n, int32_t *cnt, hipStream_t s);
@@ -103,14 +101,36 @@ void launch_row_fill(const uint8_t *A, int n, const int64_t *off, int32_t *cols,
 // rmax: device unsigned, zeroed by the caller; receives the bits of max |R|.
 void launch_residual(const float *X, int np, int n, const int64_t *off, const int32_t *cols, const int32_t *slabs,
                      int nslab, float *R, unsigned *rmax, const rdist_info *info, hipStream_t s);
-// rmax: as written by launch_residual when C was formed from the scaled
-// residual (launch_split_bf16 with rmax), else nullptr.
-void launch_fix(const float *X, int np, int n, const float *C, const int32_t *slabs, int nslab, double margin,
-                const unsigned *rmax, int16_t *D, rdist_info *info, hipStream_t s);
+// C: the correction X0 R of the slabs (np x ldc, column 128 s + c of slab s);
+// rmax as written by launch_residual (C formed from the residual scaled by
+// 2^s, undone here).
+void launch_fix(const float *X, int np, int n, const float *C, int ldc, const int32_t *slabs, int nslab,
+                double margin, const unsigned *rmax, int16_t *D, rdist_info *info, hipStream_t s);
 // hi/lo bf16 parts (16-bit patterns) of 2^s src, s = 0 or the residual's
 // scale (rmax given).
 void launch_split_bf16(const float *src, size_t count, uint16_t *hi, uint16_t *lo, const unsigned *rmax,
                        hipStream_t s);
+// FP32 matrix-core steps of the mixed plan (rd_gemm.hip), step width 256:
+// Pt = P^T in FP32 (V == nullptr) or P into V's block columns at K0; Ut = -U^T;
+// V = P M_K,: (Pt, 256 x np); M <- M~ - U V over every tile.
+void launch_pt32(const double *S, float *Pt, float *V, int np, int K0, const rdist_info *info, hipStream_t s);
+void launch_ut32(const float *M, int np, int K0, float *Ut, const rdist_info *info, hipStream_t s);
+void launch_gemm32_rows(const float *Pt, const float *M, int np, int K0, float *V, const rdist_info *info,
+                        hipStream_t s);
+void launch_gemm32_update(float *M, int np, int K0, const float *Ut, const float *V, const rdist_info *info,
+                          hipStream_t s);
+// C (rows x cols_pad, ld cols_pad) = Xh Rh + Xh Rl + Xl Rh from bf16 parts:
+// Xh, Xl rows x K row-major, Rht, Rlt cols_pad x K (R transposed, zero rows
+// past its columns); rows a multiple of 256, cols_pad = corr_cols(cols), K a
+// multiple of 64.
+int corr_cols(int cols);
+void launch_corr_bf16(float *C, int rows, int cols_pad, int K, const uint16_t *Xh, const uint16_t *Xl,
+                      const uint16_t *Rht, const uint16_t *Rlt, const rdist_info *info, hipStream_t s);
+// hi / lo bf16 parts of 2^s R (rows x cols, s from rmax), written transposed
+// (cols_pad x rows, the rows past cols zero); rows a multiple of 64, cols_pad
+// a multiple of 64 not below cols.
+void launch_split_bf16_t(const float *R, int rows, int cols, int cols_pad, uint16_t *Ht, uint16_t *Lt,
+                         const unsigned *rmax, hipStream_t s);
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s);
 // Entries per query of a path output: the next node alone for max_hops = 1,
 // else the start and max_hops hops.

@@ -3,7 +3,7 @@
 // Y is first formed in FP32: blocked Gauss-Jordan with b = 256, the 256 x 256
 // diagonal block inverted in FP64 (the FP64 register / MFMA kernels, in
 // place on a converted copy), and the row product V = P M_K,: and the
-// trailing update M <- M~ - U V as FP32 GEMMs (rocBLAS, FP32 matrix cores).
+// trailing update M <- M~ - U V on the FP32 matrix cores (rd_gemm.hip).
 // Every entry of the FP32 result X0 is then certified or not (Sec. 5, the
 // FP64 precision limit, restated for FP32):
 //   uncertified  iff  X0 < FLT_MIN (zero included: FP32 cannot tell an
@@ -15,13 +15,13 @@
 //   * no underflow: one refinement step Y = X0 + X0 (I - M X0) on the
 //     128-column slabs that hold them.  The residual is formed in FP64 from
 //     the sparse adjacency (it is of order eps32 * Y entrywise, M being an
-//     M-matrix with Y >= 0), so the FP32 product X0 R adds an error of order
-//     eps32^2 * Y;
+//     M-matrix with Y >= 0), so the product X0 R, formed from bf16 hi/lo
+//     parts on the bf16 matrix cores (rd_gemm.hip), adds an error of order
+//     2^-16 eps32 * Y;
 //   * some underflow: the whole graph goes through the FP64 blocked plan.
 // The call synchronises the stream once (after certification), because the
 // size of the recompute is data-dependent.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cfloat>
@@ -61,38 +61,6 @@ __global__ __launch_bounds__(256) void k_diag_to_f64(const float *__restrict__ M
     for (int e = blockIdx.x * 256 + threadIdx.x; e < kMB * kMB; e += gridDim.x * 256) {
         const int r = e >> 8, c = e & 255;
         S[e] = (double)M[(size_t)(K0 + r) * np + K0 + c];
-    }
-}
-
-// P (FP64, in S) rounded to FP32 into P (V == nullptr), or P copied into
-// V's block columns at K0.
-__global__ __launch_bounds__(256) void k_p_to_f32(const double *__restrict__ S, float *__restrict__ P,
-                                                  float *__restrict__ V, int np, int K0) {
-    for (int e = blockIdx.x * 256 + threadIdx.x; e < kMB * kMB; e += gridDim.x * 256) {
-        const int r = e >> 8, c = e & 255;
-        if (V) V[(size_t)r * np + K0 + c] = P[e];
-        else P[e] = (float)S[e];
-    }
-}
-
-// U (np x 256) = the column block K of M with its own rows replaced by -I;
-// then block row and block column K of M are zeroed (M~).
-__global__ __launch_bounds__(256) void k_ucopy_zero(float *__restrict__ M, int np, int K0, float *__restrict__ U) {
-    const size_t total = (size_t)np * kMB;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
-        const int i = (int)(e >> 8), c = (int)(e & 255);
-        float u;
-        if (i >= K0 && i < K0 + kMB) {
-            u = (i - K0 == c) ? -1.0f : 0.0f;
-        } else {
-            u = M[(size_t)i * np + K0 + c];
-            M[(size_t)i * np + K0 + c] = 0.0f;
-        }
-        U[e] = u;
-    }
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
-        const int r = (int)(e / np), j = (int)(e - (size_t)r * np);
-        M[(size_t)(K0 + r) * np + j] = 0.0f;
     }
 }
 
@@ -253,7 +221,7 @@ __global__ __launch_bounds__(256) void k_split_bf16(const float *__restrict__ sr
 // (np x w) from the GEMMs on the residual scaled by 2^s (undone here
 // exactly); D from Y in FP64.
 __global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np, int n, const float *__restrict__ C,
-                                             const int32_t *__restrict__ slabs, int nslab, double margin,
+                                             int ldc, const int32_t *__restrict__ slabs, int nslab, double margin,
                                              const unsigned *__restrict__ rmax, int16_t *__restrict__ D,
                                              rdist_info *info) {
     if (info->status != RDIST_OK) return;
@@ -266,7 +234,7 @@ __global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np
     if (i < n && j < n) {
         const float x = X[(size_t)i * np + j];
         if (uncertified(x, il, margin)) {
-            const double y = (double)x + unscale * (double)C[(size_t)i * ((size_t)nslab * kSlab) + (size_t)s * kSlab + c];
+            const double y = (double)x + unscale * (double)C[(size_t)i * ldc + (size_t)s * kSlab + c];
             D[(size_t)i * n + j] = rd_encode(y, il, cnt);
         }
     }
@@ -288,12 +256,6 @@ void launch_m32_build(const uint8_t *A, int n, int np, float *M, const rdist_inf
 void launch_diag_to_f64(const float *M, int np, int K0, double *S, hipStream_t s) {
     hipLaunchKernelGGL(k_diag_to_f64, dim3(256), dim3(256), 0, s, M, np, K0, S);
 }
-void launch_p_to_f32(const double *S, float *P, float *V, int np, int K0, hipStream_t s) {
-    hipLaunchKernelGGL(k_p_to_f32, dim3(256), dim3(256), 0, s, S, P, V, np, K0);
-}
-void launch_ucopy_zero(float *M, int np, int K0, float *U, hipStream_t s) {
-    hipLaunchKernelGGL(k_ucopy_zero, dim3(grid_for((size_t)np * kMB)), dim3(256), 0, s, M, np, K0, U);
-}
 void launch_certify(const float *X, int np, int n, double margin, int16_t *D, int32_t *slab_flag,
                     unsigned long long *cnt, rdist_info *info, hipStream_t s) {
     hipLaunchKernelGGL(k_certify, dim3(grid_for((size_t)n * n)), dim3(256), 0, s, X, np, n, margin, D, slab_flag,
@@ -310,9 +272,10 @@ void launch_residual(const float *X, int np, int n, const int64_t *off, const in
     hipLaunchKernelGGL(k_residual, dim3(np / 8, nslab), dim3(256), 0, s, X, np, n, off, cols, slabs, nslab, R, rmax,
                        info);
 }
-void launch_fix(const float *X, int np, int n, const float *C, const int32_t *slabs, int nslab, double margin,
-                const unsigned *rmax, int16_t *D, rdist_info *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_fix, dim3(np / 2, nslab), dim3(256), 0, s, X, np, n, C, slabs, nslab, margin, rmax, D, info);
+void launch_fix(const float *X, int np, int n, const float *C, int ldc, const int32_t *slabs, int nslab,
+                double margin, const unsigned *rmax, int16_t *D, rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_fix, dim3(np / 2, nslab), dim3(256), 0, s, X, np, n, C, ldc, slabs, nslab, margin, rmax, D,
+                       info);
 }
 void launch_split_bf16(const float *src, size_t count, uint16_t *hi, uint16_t *lo, const unsigned *rmax,
                        hipStream_t s) {
@@ -330,30 +293,7 @@ namespace {
 // within this of an integer is recomputed.
 constexpr double kCertMargin = 0.05;
 
-const char *blas_status_name(rocblas_status st) { return rocblas_status_to_string(st); }
-
-#define RD_BLAS(expr)                                                                              \
-    do {                                                                                           \
-        rocblas_status b_ = (expr);                                                                \
-        if (b_ != rocblas_status_success) return fail(RDIST_E_HIP, std::string(#expr) + ": " + blas_status_name(b_)); \
-    } while (0)
-
-rdist_status ensure_blas(rdist_ctx c, hipStream_t s) {
-    if (!c->blas) {
-        rocblas_handle h = nullptr;
-        RD_BLAS(rocblas_create_handle(&h));
-        c->blas = h;
-    }
-    RD_BLAS(rocblas_set_stream((rocblas_handle)c->blas, s));
-    return RDIST_OK;
-}
-
 }  // namespace
-
-void destroy_blas(rdist_ctx c) {
-    if (c->blas) (void)rocblas_destroy_handle((rocblas_handle)c->blas);
-    c->blas = nullptr;
-}
 
 rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uint32_t flags, int16_t *D,
                          rdist_info *info, hipStream_t s) {
@@ -373,10 +313,8 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
     if ((st = ensure(c, w.Pt2, (size_t)128 * 128 * 8))) return st;
     const int nslab_all = np / kSlab;
     if ((st = ensure(c, w.cert, 256 + (size_t)nslab_all * 4))) return st;
-    if ((st = ensure_blas(c, s))) return st;
-    rocblas_handle h = (rocblas_handle)c->blas;
     rdist_info *dinfo = w.dinfo();
-    float *M = (float *)w.m32.p, *V = (float *)w.v32.p, *U = (float *)w.u32.p, *P = (float *)w.p32.p;
+    float *M = (float *)w.m32.p, *V = (float *)w.v32.p, *Ut = (float *)w.u32.p, *Pt = (float *)w.p32.p;
     double *S = (double *)w.s64.p;
     {
         Timer t(c, s, RDIST_K_INGEST, 0.0, (double)n * n + 4.0 * np * np);
@@ -384,7 +322,6 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
         rd::launch_m32_build(A, n, np, M, dinfo, s);
     }
     RD_HIP(hipGetLastError());
-    const float one = 1.0f, zero = 0.0f, minus_one = -1.0f;
     for (int K = 0; K < nb; ++K) {
         const int K0 = K * kMB;
         {
@@ -400,17 +337,15 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
         }
         RD_HIP(hipGetLastError());
         {
-            Timer t(c, s, RDIST_K_MIXED_GEMM, 2.0 * np * (double)np * kMB + 2.0 * kMB * (double)kMB * np,
-                    4.0 * (3.0 * np * (double)np + 4.0 * kMB * np));
-            rd::launch_p_to_f32(S, P, nullptr, np, K0, s);   // P rounded to FP32
-            // V = P M_K,: (row-major), i.e. column-major V^T = M_K,:^T P^T; then V_K = P
-            RD_BLAS(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, np, kMB, kMB, &one,
-                                  M + (size_t)K0 * np, np, P, kMB, &zero, V, np));
-            rd::launch_p_to_f32(S, P, V, np, K0, s);
-            rd::launch_ucopy_zero(M, np, K0, U, s);
-            // M <- M~ - U V, i.e. column-major M^T <- M^T - V^T U^T
-            RD_BLAS(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, np, np, kMB, &minus_one, V, np,
-                                  U, kMB, &one, M, np));
+            Timer t(c, s, RDIST_K_ROWCOL, 2.0 * kMB * (double)kMB * np, 4.0 * (4.0 * kMB * np));
+            rd::launch_pt32(S, Pt, nullptr, np, K0, dinfo, s);         // P^T rounded to FP32
+            rd::launch_gemm32_rows(Pt, M, np, K0, V, dinfo, s);        // V = P M_K,:
+            rd::launch_pt32(S, nullptr, V, np, K0, dinfo, s);          // V_K = P
+            rd::launch_ut32(M, np, K0, Ut, dinfo, s);                  // Ut = -U^T (U_K = -I)
+        }
+        {
+            Timer t(c, s, RDIST_K_MIXED_GEMM, 2.0 * np * (double)np * kMB, 4.0 * (2.0 * np * (double)np));
+            rd::launch_gemm32_update(M, np, K0, Ut, V, dinfo, s);      // M <- M~ - U V
         }
         RD_HIP(hipGetLastError());
     }
@@ -457,7 +392,6 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
         if ((st = ensure(c, w.csr_off, (size_t)(n + 1) * 8 + (size_t)ns * 4))) return st;
         if ((st = ensure(c, w.csr_col, std::max<size_t>(4, (size_t)off[n] * 4)))) return st;
         if ((st = ensure(c, w.r32, (size_t)np * wcols * 4))) return st;
-        if ((st = ensure(c, w.c32, (size_t)np * wcols * 4))) return st;
         int64_t *doff = (int64_t *)w.csr_off.p;
         int32_t *dslabs = (int32_t *)((char *)w.csr_off.p + (size_t)(n + 1) * 8);
         RD_HIP(hipMemcpyAsync(doff, off.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
@@ -468,37 +402,22 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
         rd::launch_residual(M, np, n, doff, (const int32_t *)w.csr_col.p, dslabs, ns, (float *)w.r32.p, rmax, dinfo,
                             s);
         RD_HIP(hipGetLastError());
-        // C = X0 R (row-major np x w), i.e. column-major C^T = R^T X0^T, from
-        // the bf16 hi/lo parts of X0 and of 2^s R: Rh Xh + Rl Xh + Rh Xl with
-        // FP32 accumulation (the dropped parts are about 2^-16 of C, and C is
-        // about eps32 Y); FP32 GEMM if the bf16 GEMM is not available
-        const size_t nx = (size_t)np * np, nr = (size_t)np * wcols;
-        bool bf16 = false;
-        if (!ensure(c, w.xh, nx * 2) && !ensure(c, w.xl, nx * 2) && !ensure(c, w.rh, nr * 2) &&
-            !ensure(c, w.rl, nr * 2)) {
-            rd::launch_split_bf16(M, nx, (uint16_t *)w.xh.p, (uint16_t *)w.xl.p, nullptr, s);
-            rd::launch_split_bf16((const float *)w.r32.p, nr, (uint16_t *)w.rh.p, (uint16_t *)w.rl.p, rmax, s);
-            RD_HIP(hipGetLastError());
-            const void *ra[3] = {w.rh.p, w.rl.p, w.rh.p}, *xb[3] = {w.xh.p, w.xh.p, w.xl.p};
-            bf16 = true;
-            for (int t3 = 0; t3 < 3 && bf16; ++t3) {
-                const rocblas_status bs = rocblas_gemm_ex(
-                    h, rocblas_operation_none, rocblas_operation_none, (int)wcols, np, np, &one, ra[t3],
-                    rocblas_datatype_bf16_r, (int)wcols, xb[t3], rocblas_datatype_bf16_r, np, t3 ? &one : &zero,
-                    w.c32.p, rocblas_datatype_f32_r, (int)wcols, w.c32.p, rocblas_datatype_f32_r, (int)wcols,
-                    rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0);
-                if (bs == rocblas_status_not_implemented && t3 == 0) bf16 = false;
-                else if (bs != rocblas_status_success) RD_BLAS(bs);
-            }
-        }
-        if (!bf16) {
-            (void)hipGetLastError();
-            g_last_error.clear();
-            RD_HIP(hipMemsetAsync(rmax, 0, sizeof(unsigned), s));   // C from the unscaled residual
-            RD_BLAS(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, (int)wcols, np, np, &one,
-                                  (const float *)w.r32.p, (int)wcols, M, np, &zero, (float *)w.c32.p, (int)wcols));
-        }
-        rd::launch_fix(M, np, n, (const float *)w.c32.p, dslabs, ns, margin, rmax, D, dinfo, s);
+        // C = X0 R (np x w) from the bf16 hi/lo parts of X0 and of 2^s R:
+        // Xh Rh + Xh Rl + Xl Rh with FP32 accumulation (the dropped parts
+        // are about 2^-16 of C, and C is about eps32 Y)
+        // (the correction's columns are padded to its 256-wide tiles)
+        const int wpad = rd::corr_cols((int)wcols);
+        const size_t nx = (size_t)np * np, nr = (size_t)np * wpad;
+        if ((st = ensure(c, w.xh, nx * 2)) || (st = ensure(c, w.xl, nx * 2)) || (st = ensure(c, w.rh, nr * 2)) ||
+            (st = ensure(c, w.rl, nr * 2)) || (st = ensure(c, w.c32, nr * 4)))
+            return st;
+        rd::launch_split_bf16(M, nx, (uint16_t *)w.xh.p, (uint16_t *)w.xl.p, nullptr, s);
+        rd::launch_split_bf16_t((const float *)w.r32.p, np, (int)wcols, wpad, (uint16_t *)w.rh.p, (uint16_t *)w.rl.p,
+                                rmax, s);
+        rd::launch_corr_bf16((float *)w.c32.p, np, wpad, np, (const uint16_t *)w.xh.p, (const uint16_t *)w.xl.p,
+                             (const uint16_t *)w.rh.p, (const uint16_t *)w.rl.p, dinfo, s);
+        RD_HIP(hipGetLastError());
+        rd::launch_fix(M, np, n, (const float *)w.c32.p, wpad, dslabs, ns, margin, rmax, D, dinfo, s);
         RD_HIP(hipGetLastError());
         // keep the host vectors alive until the copies above have run
         RD_HIP(hipStreamSynchronize(s));

@@ -21,24 +21,6 @@ namespace rd {
 //   EDGEREST  the band's tile rows and columns minus DIAG.
 enum { kAll = 0, kDiag = 1, kRest = 2, kEdgeRest = 3 };
 
-// Order of the tiles of an nr x nr grid for a big launch.  Workgroups are
-// handed to the 8 XCDs round-robin (workgroup b to XCD b % 8), and each XCD
-// has its own 4 MB L2.  Workgroup b = 8l + x is given position x*F + l of a
-// list that walks strips of 8 tile rows column by column (F = number of
-// workgroups per XCD), so the tiles an XCD holds at one time cover about 8
-// tile rows x 8 tile columns and share their U and V operand slabs in L2.
-// A bijection on [0, nr^2) whatever the hardware's actual assignment.
-__device__ __forceinline__ void xcd_strip_order(int b, int nr, int &i, int &j) {
-    const int total = nr * nr;
-    const int full = total & ~7;
-    const int idx = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
-    const int s = idx / (8 * nr);
-    const int w = idx - s * 8 * nr;
-    const int h = min(8, nr - 8 * s);
-    j = w / h;
-    i = 8 * s + (w - j * h);
-}
-
 template <int MODE>
 __device__ __forceinline__ void update_tile_index(int b, int nt, int L0, int m, int wt, int &I, int &J) {
     if (MODE == kAll) {
