@@ -331,13 +331,17 @@ def spectral_radius(A) -> float:
     return float(np.max(np.abs(np.linalg.eigvals(A))))
 
 
-def certify(Y, D, gamma: float, delta: int) -> np.ndarray:
+def certify(Y, D, gamma: float, delta: int, rel: float = 0.0) -> np.ndarray:
     """Per-entry certificate (Eq. Y-bracket of Theorem 2's proof, from
     Eq. Y-series-trunc and Eq. Nijk-limit): with k = D, a true distance of
     k + 1 or more would give Y <= gamma^(k+1) Delta^k / (1 - gamma Delta); Y
-    above that proves D exact.  Y == 0 certifies unreachable when
-    e gamma^(n-1) > DBL_MIN (no reachable entry can underflow); Y below
-    DBL_MIN is not certified.  Returns a boolean mask."""
+    above that proves D exact, given that the true distance is at least k,
+    i.e. that Y is below gamma^(k - 1 + eta) (a walk of length d gives
+    Y >= gamma^d; the readout k = ceil(R - eta) of Y itself implies it).  With
+    rel > 0, Y is taken to carry a relative error up to rel, and both sides
+    must hold for every value in [Y (1 - rel), Y (1 + rel)].  Y == 0
+    certifies unreachable when e gamma^(n-1) > DBL_MIN (no reachable entry can
+    underflow); Y below DBL_MIN is not certified.  Returns a boolean mask."""
     Y = np.asarray(Y, dtype=np.float64)
     k = np.asarray(D, dtype=np.float64)
     dl = float(max(delta, 1))
@@ -347,18 +351,22 @@ def certify(Y, D, gamma: float, delta: int) -> np.ndarray:
     out = (Y == 0.0) & zero_ok
     pos = Y >= np.finfo(np.float64).tiny
     lb = (k + 1.0) * math.log(gamma * dl) - math.log(dl * (1.0 - gamma * dl))
-    out[pos] = np.log(Y[pos]) > lb[pos]
+    lny = np.log(Y[pos])
+    above = lny + math.log1p(-rel) > lb[pos]
+    below = lny + math.log1p(rel) < (k[pos] - 1.0 + ETA) * math.log(gamma)
+    out[pos] = above & below
     return out
 
 
-def certify_weighted(Y, D, gamma: float, delta: int) -> np.ndarray:
+def certify_weighted(Y, D, gamma: float, delta: int, rel: float = 0.0) -> np.ndarray:
     """Per-entry certificate for positive integer weights (Sec. 3.2 with the
     walk-count bound Eq. Nijk-limit): with k = D, a true distance of k + 1 or
     more makes every walk of l edges weigh at least max(l, k + 1), so
     Y <= sum_l Delta^(l-1) gamma^max(l, k+1)
       = gamma^(k+1) (Delta^(k+1) - 1) / (Delta - 1) + (gamma Delta)^(k+2) / (Delta (1 - gamma Delta))
     ((k + 1) gamma^(k+1) + gamma^(k+2) / (1 - gamma) for Delta = 1); Y above
-    that proves D exact.  Zeros and entries below DBL_MIN as in certify."""
+    that proves D exact.  The lower side (true distance at least k), rel,
+    zeros and entries below DBL_MIN as in certify."""
     Y = np.asarray(Y, dtype=np.float64)
     k = np.asarray(D, dtype=np.float64)
     dl = float(max(delta, 1))
@@ -376,7 +384,8 @@ def certify_weighted(Y, D, gamma: float, delta: int) -> np.ndarray:
                  - math.log(dl - 1.0))
         second = (kp + 2.0) * math.log(gamma * dl) - math.log(dl * (1.0 - gamma * dl))
     lb = np.logaddexp(first, second)
-    out[pos] = np.log(Y[pos]) > lb
+    lny = np.log(Y[pos])
+    out[pos] = (lny + math.log1p(-rel) > lb) & (lny + math.log1p(rel) < (kp - 1.0 + ETA) * math.log(gamma))
     return out
 
 

@@ -150,10 +150,13 @@ constexpr int kCertChunk = 2048;   // columns per step of the certificate pass (
 // Per-entry certificate over a kept graph's Y: mask (nullable, n x n bytes,
 // 1 = certified) and the certified count into *count.  Entries below
 // DBL_MIN, and zeros where gamma^(n-1) could underflow, are not certified
-// (their rounding has no relative bound).  Y is taken rel below and the
-// bound rel above, rel the larger of 2^-30, the inversion's error bound
-// 8 n u / (1 - gamma Delta) and err_floor (the cap on the error bounds of a
-// Y changed by edge updates, else 0), to cover Y's rounding.
+// (their rounding has no relative bound).  Y's relative error is taken as
+// rel, the larger of 2^-30, the inversion's error bound 8 n u / (1 - gamma
+// Delta) and err_floor (the cap on the error bounds of a Y changed by edge
+// updates, else 0), on both sides of the argument: with k the readout of
+// Y, the true distance is at least k only if the true Y is below
+// gamma^(k - 1 + eta), so Y (1 + rel) must be; and a distance of k + 1 or
+// more is excluded only if Y (1 - rel) is above the bound of Eq. Y-bracket.
 // First pass over a row: ln Y from the exponent bits and the FP32 logarithm
 // of the mantissa (within 1e-6 of ln Y, as in the readout's short path)
 // gives k and the decision for almost every entry; entries whose readout or
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(256) void k_certify(const double *__restrict__ Y, i
     const double gd = gamma * (double)ginfo->delta;
     const double rel = fmin(0.5, fmax(fmax(0x1p-30, err_floor), 8.0 * (double)n * 0x1p-53 / fmax(1.0 - gd, 1e-300)));
     const double margin = log1p(rel) - log1p(-rel);
+    const double up = log1p(rel);                  // ln of Y's largest true value over the computed one
     const double l0 = -log(delta * (1.0 - gamma * delta)) + margin;
     const double lg = log(gamma), lde = log(delta);
     // ln of the bound for readout k, the margins included
@@ -219,8 +223,11 @@ __global__ __launch_bounds__(256) void k_certify(const double *__restrict__ Y, i
                     ok = -1;
                     if (fabs(te - rint(te)) > band) {
                         const double k = fmin(fmax(ceil(te), kDMin), kDMax);
-                        const double diff = l2 * kLn2 - bound_ln(k);
-                        if (fabs(diff) > 1e-5) ok = diff > 0.0;
+                        const double lny = l2 * kLn2;
+                        const double diff = lny - bound_ln(k);                    // > 0: no distance above k
+                        const double low = (k - 1.0 + kEta) * lg - (lny + up);    // > 0: no distance below k
+                        if (diff < -1e-5 || low < -1e-5) ok = 0;
+                        else if (diff > 1e-5 && low > 1e-5) ok = 1;
                     }
                 }
                 if (ok < 0) {
@@ -236,7 +243,8 @@ __global__ __launch_bounds__(256) void k_certify(const double *__restrict__ Y, i
                 const int j = queue[t];
                 const double y = yr[j];
                 const int k = rd_encode(y, il, dummy);
-                const bool ok = log(y) > bound_ln((double)k);
+                const double lny = log(y);
+                const bool ok = lny > bound_ln((double)k) && lny + up < ((double)k - 1.0 + kEta) * lg;
                 if (mask) mask[(size_t)i * n + j] = ok ? 1 : 0;
                 c += ok ? 1 : 0;
             }

@@ -87,6 +87,14 @@ def test_gain_bounds_refusals(ctx):
     assert r["delta"] == 0 and r["rho_lo"] == 0.0 and r["rho_hi"] == 0.0
 
 
+def near_lower(Y, D, gamma, tol):
+    """Entries whose ln Y lies within tol of the certificate's lower boundary
+    (k - 1 + eta) ln gamma: the GPU takes Y's error into account there and
+    may refuse an entry the oracle (exact Y) accepts."""
+    k = D.astype(np.float64)
+    return np.abs(np.log(Y) - (k - 1.0 + oracle.ETA) * math.log(gamma)) < tol
+
+
 def test_certificate_matches_oracle(ctx):
     rng = gg.rng_for("gain", 3)
     for name, A in [("er", gg.erdos_renyi(300, 0.03, rng)), ("tree", gg.random_tree(200, rng)),
@@ -105,7 +113,8 @@ def test_certificate_matches_oracle(ctx):
                 Yo = sol.Y[diff]
                 k = sol.D[diff].astype(np.float64)
                 lb = (k + 1) * math.log(gamma * delta) - math.log(delta * (1 - gamma * delta))
-                assert np.all(np.abs(np.log(Yo) - lb) < 1e-8), (name, gamma, int(diff.sum()))
+                ok = (np.abs(np.log(Yo) - lb) < 1e-8) | near_lower(Yo, sol.D[diff], gamma, 1e-8)
+                assert np.all(ok), (name, gamma, int(diff.sum()))
             Dg = D.cpu().numpy()
             reach = dist >= 0
             assert np.all(Dg[m & reach] == dist[m & reach]), (name, gamma)
@@ -139,7 +148,8 @@ def test_certificate_weighted(ctx):
                 first = (k + 1) * math.log(gamma) + (k + 1) * math.log(d) + np.log1p(-d ** (-(k + 1))) - math.log(d - 1)
                 second = (k + 2) * math.log(gamma * d) - math.log(d * (1 - gamma * d))
                 lb = np.logaddexp(first, second)
-                assert np.all(np.abs(np.log(sol.Y[diff]) - lb) < 1e-8), (n, gamma, int(diff.sum()))
+                ok = (np.abs(np.log(sol.Y[diff]) - lb) < 1e-8) | near_lower(sol.Y[diff], sol.D[diff], gamma, 1e-8)
+                assert np.all(ok), (n, gamma, int(diff.sum()))
             Dg = D.cpu().numpy()
             assert np.all(Dg[m & reach] == dist[m & reach].astype(np.int64)), (n, gamma)
             assert np.all(Dg[m & ~reach] == R.RDIST_UNREACHABLE)
@@ -188,7 +198,8 @@ def test_certificate_after_changes(ctx):
     if diff.any():
         k = sol.D[diff].astype(np.float64)
         lb = (k + 1) * math.log(gamma * delta) - math.log(delta * (1 - gamma * delta))
-        assert np.all(np.abs(np.log(sol.Y[diff]) - lb) < 4e-6), int(diff.sum())
+        ok = (np.abs(np.log(sol.Y[diff]) - lb) < 4e-6) | near_lower(sol.Y[diff], sol.D[diff], gamma, 4e-6)
+        assert np.all(ok), int(diff.sum())
     dist, _ = oracle.bfs(A)
     Dg = D.cpu().numpy()
     reach = dist >= 0

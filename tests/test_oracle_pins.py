@@ -693,6 +693,25 @@ def test_spectral_radius_closed_forms():
         assert abs(oracle.spectral_radius(gg.square_grid(M)) - 4.0 * math.cos(math.pi / (M + 1))) < 1e-12
 
 
+
+def test_certificate_error_margin_on_both_sides():
+    """The certificate must allow for Y's error on the lower side too: on a
+    directed path every entry is one exact walk, Y = gamma^d.  Lowered by half
+    the assumed relative error, an entry reads out as d + 1; without a margin
+    the certificate would prove that wrong value, with the margin it refuses
+    it, while the exact entries stay certified."""
+    A = gg.directed_path(12)
+    g, rel = 0.3, 1e-6
+    sol = oracle.solve(A, g)
+    low = np.tril(np.ones((12, 12), dtype=bool))
+    assert oracle.certify(sol.Y, sol.D, g, 1, rel=rel)[low].all()
+    Yp = sol.Y * (1.0 - 0.5 * rel)
+    Dp = oracle.readout(Yp, g).D
+    flipped = low & (Dp != sol.D)
+    assert flipped.sum() > 0 and np.all(Dp[flipped] == sol.D[flipped] + 1)
+    assert oracle.certify(Yp, Dp, g, 1)[flipped].all()                 # the failure the margin prevents
+    assert not oracle.certify(Yp, Dp, g, 1, rel=rel)[flipped].any()
+
 @pytest.mark.parametrize("seed", range(8))
 def test_certificate_implies_bfs_distance(seed):
     """Every entry the certificate accepts has D equal to the BFS distance, at
