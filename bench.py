@@ -61,6 +61,20 @@ def read_traffic(profile_name: str, sha: str):
     return float(m_b.group(1))
 
 
+def read_mfma_flops(profile_name: str, sha: str):
+    """Matrix-core flops per launch from rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_*
+    (x 512); None if missing or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", profile_name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"source_sha:\s*([0-9a-f]+)", text)
+    m_f = re.search(r"mfma_flops_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_f or m_sha.group(1) != sha:
+        return None
+    return float(m_f.group(1))
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
@@ -248,6 +262,7 @@ def bench_c2(args, torch, R, gg):
     achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
     sha = source_sha(UPDATE_SOURCES)
     traffic = read_traffic("k_update_c2_n8192_pmc.md", sha)
+    mfma_flops = read_mfma_flops("k_update_c2_n8192_pmc.md", sha)
     out = {
         "metric": "APSP graphs/s + eff. TFLOP/s at n=8192 (FP64 vs mixed), p50/p99 latency",
         "value": args.steps / wall,
@@ -271,7 +286,9 @@ def bench_c2(args, torch, R, gg):
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic, "avg_launch_ms": avg_ms, "launches": upd["launches"],
-                     "flops_per_launch": per_launch_flops, "source_sha": sha},
+                     "flops_per_launch": per_launch_flops, "source_sha": sha,
+                     "mfma_counter_flops": mfma_flops,
+                     "mfma_counter_ratio": mfma_flops / per_launch_flops if mfma_flops else None},
         "kernel_ms_per_step": {k: v["total_ms"] / nsplit for k, v in
                                (("update_rest", rest_split), ("update_edge_and_last", edge), ("panel", panel),
                                 ("rowcol", rowcol), ("ingest", ingest))},
