@@ -79,28 +79,51 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
 
-def cpu_baseline_c2(A: np.ndarray, gjsteps: int, rows: int):
+def cpu_baseline_c2(A: np.ndarray, gjsteps: int, rows: int, runs: int = 5):
     """The oracle as it stands, on a bounded sample of the same n = 8192 solve:
     gate + M build on the whole graph, `gjsteps` of the n Gauss-Jordan steps,
     the readout of `rows` rows; scaled to one full solve (every GJ step and
-    every readout row costs the same)."""
+    every readout row costs the same).  The Gauss-Jordan sample and the
+    readout are timed `runs` times (M rebuilt before each) and the medians
+    used.  Beside it, full oracle solves of an n = 2048 graph of the same
+    density (the C2 subsample), median of `runs`."""
     import oracle
+    import graphgen as gg
     n = A.shape[0]
     t0 = time.perf_counter()
     prep = oracle.prepare(A, -0.5)
     M = oracle.build_m(A, prep.gamma)
-    t1 = time.perf_counter()
-    oracle.gj_steps_inplace(M, 0, gjsteps)
-    t2 = time.perf_counter()
-    oracle.readout(np.ascontiguousarray(M[:rows, :rows]), prep.gamma)   # rows x rows entries
-    t3 = time.perf_counter()
-    t_full = (t1 - t0) + (t2 - t1) * n / gjsteps + (t3 - t2) * (n * n) / (rows * rows)
-    sampled = (t1 - t0) + (t2 - t1) + (t3 - t2)
+    t_build = time.perf_counter() - t0
+    t_gj, t_rd = [], []
+    for r in range(runs):
+        if r:
+            M = oracle.build_m(A, prep.gamma)
+        t1 = time.perf_counter()
+        oracle.gj_steps_inplace(M, 0, gjsteps)
+        t2 = time.perf_counter()
+        oracle.readout(np.ascontiguousarray(M[:rows, :rows]), prep.gamma)   # rows x rows entries
+        t3 = time.perf_counter()
+        t_gj.append(t2 - t1)
+        t_rd.append(t3 - t2)
+    del M
+    gj, rd = float(np.median(t_gj)), float(np.median(t_rd))
+    t_full = t_build + gj * n / gjsteps + rd * (n * n) / (rows * rows)
+    sub = gg.c2_subsample(0, fresh=True)
+    t_sub = []
+    for _ in range(runs):
+        t4 = time.perf_counter()
+        oracle.solve(sub, -0.5, keep_y=False)
+        t_sub.append(time.perf_counter() - t4)
+    m_sub = float(np.median(t_sub))
     return {
         "value": 1.0 / t_full, "unit": "graphs/s", "cores": oracle.num_threads(), "kind": "oracle",
-        "sample": (f"n=8192 C2 graph: gate+M build in full, {gjsteps} of {n} Gauss-Jordan steps, "
-                   f"readout of {rows}x{rows} entries; scaled linearly to one solve "
-                   f"({sampled:.1f} s sampled, {t_full:.0f} s extrapolated)"),
+        "sample": (f"n=8192 C2 graph: gate+M build in full ({t_build:.2f} s), {gjsteps} of {n} Gauss-Jordan "
+                   f"steps (median of {runs} runs {gj:.2f} s, range {min(t_gj):.2f}-{max(t_gj):.2f}), readout of "
+                   f"{rows}x{rows} entries (median {rd:.3f} s); scaled linearly to one solve ({t_full:.0f} s "
+                   f"extrapolated)"),
+        "full_n2048": {"median_s": m_sub, "min_s": float(min(t_sub)), "max_s": float(max(t_sub)), "runs": runs,
+                       "graphs_per_s": 1.0 / m_sub, "scaled_to_n8192_s": m_sub * 64.0,
+                       "graph": "fresh ER(2048, 0.02), the C2 density (c2/sub seed 0)"},
     }
 
 
@@ -932,6 +955,17 @@ def bench_c1(args, torch, R, gg):
         ctx.solve_async(As[k % 100], gg.C1_GAMMA, 0, D, info=info, stream=stream)
         stream.synchronize()
         lat.append((time.perf_counter() - t0) * 1e3)
+    # the floor of that round trip: one minimal kernel launch and the same synchronisation
+    z = torch.zeros(1, device="cuda")
+    for _ in range(20):
+        z.add_(1.0)
+    stream.synchronize()
+    lat0 = []
+    for k in range(args.steps * 10):
+        t0 = time.perf_counter()
+        z.add_(1.0)
+        stream.synchronize()
+        lat0.append((time.perf_counter() - t0) * 1e3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = args.steps * 100
@@ -950,6 +984,8 @@ def bench_c1(args, torch, R, gg):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic", "config": {"workload": "C1: ER(64, 0.1), gamma=0.05, 100 seeds"},
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "empty_kernel_round_trip": {"p50_ms": percentile(lat0, 50), "p99_ms": percentile(lat0, 99),
+                                        "what": "one one-element torch add kernel + stream synchronise"},
             "cpu_baseline": {"value": 1.0 / tc, "unit": "graphs/s", "cores": oracle.num_threads(),
                              "kind": "oracle", "sample": "200 solves of the seed-0 graph"}}
 
@@ -1013,7 +1049,8 @@ def bench_c3(args, torch, R, gg):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "C3: 1024 graphs per step, n log-uniform in [32, 512], ER(p~U[0.05,0.2]) / "
-                               "torus lattice / RGG, gamma=0.5/max_out_degree, one persistent launch",
+                               "2-D grid lattice with 10% of directed edges deleted / RGG (mean degree 8), "
+                               "gamma=0.5/max_out_degree, one captured plan",
                    "graphs": len(As), "sum_n3": float(np.sum(ns ** 3)), "tuning": tuned[0],
                    "autotune_s": tune_s},
         "eager_ms_per_step": eager_ms,
