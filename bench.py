@@ -1039,10 +1039,23 @@ def bench_c3(args, torch, R, gg):
         ctx.solve_batched(batch, flags=R.RDIST_NO_GRAPH, info=info, stream=stream, sync=False)
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    # the dominant kernel, k_lv_update: every launch of it in eager runs of
+    # the plan timed with HIP events on its stream (a captured graph cannot
+    # hold per-launch events); flops per launch = its product tiles x
+    # 2 * 128^2 * inner dimension
+    ctx.set_timing(True, classes=[R.RDIST_K_UPDATE, R.RDIST_K_UPDATE_EDGE])
+    for _ in range(args.steps):
+        ctx.solve_batched(batch, flags=R.RDIST_NO_GRAPH, info=info, stream=stream, sync=False)
+    torch.cuda.synchronize()
+    ku, ke = ctx.kernel_stats(R.RDIST_K_UPDATE), ctx.kernel_stats(R.RDIST_K_UPDATE_EDGE)
+    ctx.set_timing(False)
     ctx.close()
     ms = wall * 1000.0 / args.steps
     avg_ms = bk["total_ms"] / max(bk["launches"], 1)
-    achieved = flops / (avg_ms * 1e-3) / 1e12
+    upd_launches = ku["launches"] + ke["launches"]
+    upd_ms = ku["total_ms"] + ke["total_ms"]
+    upd_flops = ku["flops"] + ke["flops"]
+    achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else None
     out = {
         "metric": "batched small-graph APSP graphs/s (1024 graphs, n in [32, 512])",
         "value": len(As) * args.steps / wall, "unit": "graphs/s",
@@ -1056,10 +1069,13 @@ def bench_c3(args, torch, R, gg):
         "eager_ms_per_step": eager_ms,
         "eff_tflops": flops / (ms * 1e-3) / 1e12,
         "p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
-        "roofline": {"bound": "mfma", "kernel": "k_batched (persistent: one workgroup per graph)",
+        "plan_ms_events": avg_ms,
+        "roofline": {"bound": "mfma",
+                     "kernel": "k_lv_update (level plan: diagonal, edge and rest tiles; eager runs of the plan)",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "avg_launch_ms": avg_ms,
-                     "launches": bk["launches"], "flops_per_launch": flops},
+                     "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": None,
+                     "avg_launch_ms": upd_ms / max(upd_launches, 1), "launches": upd_launches,
+                     "flops_per_launch": upd_flops / max(upd_launches, 1)},
     }
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle sample)")

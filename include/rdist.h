@@ -470,7 +470,8 @@ typedef struct rdist_kernel_stats {
 } rdist_kernel_stats;
 
 #define RDIST_K_UPDATE 0      /* trailing rank-b update over all tiles outside the next block's
-                                 row and column (the FP64/FP32 MFMA hot loop) */
+                                 row and column (the FP64/FP32 MFMA hot loop); batched plans
+                                 (eager launches, RDIST_NO_GRAPH): the level plan's rest tiles */
 #define RDIST_K_PANEL 1       /* diagonal-block inverse */
 #define RDIST_K_ROWCOL 2      /* pivot row/column block preparation */
 #define RDIST_K_INGEST 3      /* adjacency -> M, degrees, gate */
@@ -480,7 +481,8 @@ typedef struct rdist_kernel_stats {
 #define RDIST_K_NEXTHOP 7     /* next-hop queries */
 #define RDIST_K_CERTIFY 8     /* mixed precision: certification + recompute; rdist_certify */
 #define RDIST_K_UPDATE_EDGE 9 /* update of the next block's row and column (lookahead) and the
-                                 last, readout-fused update */
+                                 last, readout-fused update; batched plans (eager launches): the
+                                 level plan's diagonal and edge tiles */
 #define RDIST_K_MIXED_GEMM 10  /* mixed precision: the FP32 trailing updates (row products, -U^T and
                                   P^T count as RDIST_K_ROWCOL) */
 #define RDIST_K_REFINE 11     /* mixed precision: residual, correction product and recompute */

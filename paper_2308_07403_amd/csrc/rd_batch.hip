@@ -71,6 +71,7 @@ struct BatchPlan {
     enum OpKind { kLaunch = 0, kIngest = 1, kPersist = 2, kRecord = 3, kWait = 4, kFill = 5, kMark = 6 };
     struct Op {
         int kind, stream, phase, K, offset, grid, event;
+        double flops = 0.0, bytes = 0.0;   // update launches: algorithmic work, for per-kernel timing
     };
     std::vector<Op> ops;
     double flops = 0.0, bytes = 0.0;
@@ -82,7 +83,7 @@ struct BatchPlan {
     // it, not for the caller's stream, which may be gone by then
     hipEvent_t ev_done = nullptr;
     bool launched = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // fork, join, edge done, panel done
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // fork, join, edge done, row tiles done, diagonal done
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t last_use = 0;
@@ -287,32 +288,57 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
     // launch program
     using Op = BatchPlan::Op;
     std::vector<int> units;
+    // update launches: per graph, the tiles that take a product (block row K
+    // is a copy) at 2 * 128^2 * kd flops, and the tile's 256 KiB of old and
+    // new value
+    auto update_work = [](const rd::LevelGraph &L, int phase, int K, double &fl, double &by) {
+        const int nt = L.nt;
+        const bool last = K + 1 == nt;
+        const double kd = last ? rd::lv_last_inner(L.n, nt) : kB;
+        int prod = 0, all = 0;
+        if (phase == rd::kLvDiag) { prod = 1; all = 1; }
+        else if (phase == rd::kLvEdge) { all = 2 * nt - 2; prod = all - 1; }
+        else if (!last) { all = (nt - 1) * (nt - 1); prod = all - (nt - 1); }
+        else { all = nt * nt; prod = all - nt; }
+        fl += prod * 2.0 * kB * kB * kd;
+        by += all * 2.0 * kB * kB * 8.0;
+    };
     auto launch = [&](int stream, int phase, int K, auto items_of) {
         std::vector<std::pair<int, int>> gi;
+        double fl = 0.0, by = 0.0;
+        const bool upd = phase == rd::kLvDiag || phase == rd::kLvEdge || phase == rd::kLvRest;
         for (int q = 0; q < nl; ++q) {
             const int it = items_of(lgs[q]);
-            if (it > 0) gi.emplace_back(q, it);
+            if (it > 0) {
+                gi.emplace_back(q, it);
+                if (upd) update_work(lgs[q], phase, K, fl, by);
+            }
         }
         const int off = (int)units.size();
         const int grid = build_units(gi, units);
-        if (grid) p.ops.push_back(Op{BatchPlan::kLaunch, stream, phase, K, off, grid, 0});
+        if (grid) {
+            Op o{BatchPlan::kLaunch, stream, phase, K, off, grid, 0};
+            o.flops = fl;
+            o.bytes = by;
+            p.ops.push_back(o);
+        }
     };
     auto record = [&](int stream, int ev) { p.ops.push_back(Op{BatchPlan::kRecord, stream, 0, 0, 0, 0, ev}); };
     auto wait = [&](int stream, int ev) { p.ops.push_back(Op{BatchPlan::kWait, stream, 0, 0, 0, 0, ev}); };
-    // the persistent kernel forks off after the level plan's ingest and
-    // build (which use the whole device) and fills the narrow launches after
+    // the persistent kernel forks off first: its graphs run beside the
+    // level plan's ingest and build, which are bound by HBM and atomics
     using LG = rd::LevelGraph;
+    if (np_ && nl) {
+        record(0, 0);
+        wait(2, 0);
+    }
+    if (np_) p.ops.push_back(Op{BatchPlan::kPersist, nl ? 2 : 0, 0, 0, 0, p.persist_grid, 0});
     if (nl) {
         p.ops.push_back(Op{BatchPlan::kFill, 0, 0, 0, 0, 0, 0});       // zero the column sums
         launch(0, rd::kLvColsum, 0, [](const LG &L) { return L.nchunk; });
         p.ops.push_back(Op{BatchPlan::kIngest, 0, 0, 0, 0, nl, 0});   // the gate
         launch(0, rd::kLvBuild, 0, [](const LG &L) { return 2 * L.nt - 1; });
     }
-    if (np_ && nl) {
-        record(0, 0);
-        wait(2, 0);
-    }
-    if (np_) p.ops.push_back(Op{BatchPlan::kPersist, nl ? 2 : 0, 0, 0, 0, p.persist_grid, 0});
     if (np_) p.ops.push_back(Op{BatchPlan::kMark, nl ? 2 : 0, 0, 0, 0, 0, 0});
     if (np_ && nl) record(2, 1);
     if (nl) {
@@ -323,7 +349,11 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
             if (K > 0) wait(0, 3);                       // step K's row/column tiles are ready
             const bool next = max_nt > K + 1;
             if (next) {
-                launch(0, rd::kLvEdge, K, [K](const LG &L) { return L.nt > K + 1 ? 2 * L.nt - 1 : 0; });
+                // the next diagonal tiles first, so that the next panels
+                // start while the rest of the band is updated
+                launch(0, rd::kLvDiag, K, [K](const LG &L) { return L.nt > K + 1 ? 1 : 0; });
+                record(0, 4);
+                launch(0, rd::kLvEdge, K, [K](const LG &L) { return L.nt > K + 1 ? 2 * L.nt - 2 : 0; });
                 record(0, 2);
             }
             launch(0, rd::kLvRest, K, [K](const LG &L) {
@@ -331,8 +361,9 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
             });
             p.ops.push_back(Op{BatchPlan::kMark, 0, 0, K + 1, 0, 0, 0});   // graphs with nt = K + 1 are final
             if (next) {
-                wait(1, 2);
+                wait(1, 4);
                 launch(1, rd::kLvPanel, K + 1, [K](const LG &L) { return L.nt > K + 1 ? 1 : 0; });
+                wait(1, 2);
                 launch(1, rd::kLvRowcol, K + 1, [K](const LG &L) { return L.nt > K + 1 ? L.nt - 1 : 0; });
                 record(1, 3);
             }
@@ -369,15 +400,27 @@ rdist_status build_plan(rdist_ctx c, BatchPlan &p, hipStream_t s, uint32_t flags
 }
 
 // Runs the plan's launch program on the streams st[0] (the caller's),
-// st[1] (lookahead) and st[2] (persistent kernel).
-rdist_status enqueue_plan(BatchPlan &p, const hipStream_t st[3], hipEvent_t *marks = nullptr) {
+// st[1] (lookahead) and st[2] (persistent kernel).  timed (eager launches
+// only): the context whose per-kernel timing records the update launches
+// (RDIST_K_UPDATE_EDGE for the diagonal and edge tiles, RDIST_K_UPDATE for
+// the rest).
+rdist_status enqueue_plan(BatchPlan &p, const hipStream_t st[3], hipEvent_t *marks = nullptr,
+                          rdist_ctx timed = nullptr) {
     char *t = (char *)p.table.p;
     const rd::LevelGraph *lgs = (const rd::LevelGraph *)(t + p.off_level);
     const int *units = (const int *)(t + p.off_units);
     for (const BatchPlan::Op &o : p.ops) {
         hipStream_t s = st[o.stream];
         switch (o.kind) {
-            case BatchPlan::kLaunch: rd::launch_lv(o.phase, lgs, units + o.offset, o.grid, o.K, s); break;
+            case BatchPlan::kLaunch:
+                if (timed && (o.phase == rd::kLvDiag || o.phase == rd::kLvEdge || o.phase == rd::kLvRest)) {
+                    Timer tm(timed, s, o.phase == rd::kLvRest ? RDIST_K_UPDATE : RDIST_K_UPDATE_EDGE, o.flops,
+                             o.bytes);
+                    rd::launch_lv(o.phase, lgs, units + o.offset, o.grid, o.K, s);
+                } else {
+                    rd::launch_lv(o.phase, lgs, units + o.offset, o.grid, o.K, s);
+                }
+                break;
             case BatchPlan::kIngest: rd::launch_lv_gate(lgs, o.grid, s); break;
             case BatchPlan::kFill: rd::launch_fill_i32((int32_t *)p.pool.p, p.colsum_ints, s); break;
             case BatchPlan::kPersist:
@@ -667,7 +710,7 @@ extern "C" rdist_status rdist_solve_batched(rdist_ctx c, int32_t count, const in
             p->launched = true;
         } else {
             const hipStream_t sts[3] = {s, w.aux, w.aux2};
-            if ((st = enqueue_plan(*p, sts))) return st;
+            if ((st = enqueue_plan(*p, sts, nullptr, c))) return st;
         }
     }
     if (info && (!p->persist_ids.empty() || !p->level_ids.empty()))

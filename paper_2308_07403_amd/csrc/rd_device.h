@@ -134,37 +134,113 @@ struct RegGJ {
     static constexpr int NT = TY * TX;
     double m[RA][RC];
 
-    // Rank-1 steps k in [k_begin, k_end).  LDS scratch: 4 * NP doubles (pivot
-    // row and column, double-buffered).  Returns false (uniformly) if a pivot
-    // is not strictly positive.
+    // LDS scratch of run / invert, in doubles: pivot rows and columns of two
+    // steps, double-buffered.
+    static constexpr int kScratch = 8 * NP;
+
+    // Elimination steps k in [k_begin, k_end).  Returns false (uniformly) if
+    // a pivot is not strictly positive.
     // Step k = TY*ka + kt: the pivot row is register row ka of the lanes with
     // ty == kt, the pivot column register column ka of the lanes with
     // tx == kt (square thread grid).  The loop over ka is unrolled, so the
     // register indices are compile-time and the fix-ups of the pivot row and
     // column are a few lane selects; every entry costs one FMA per step.
+    // Steps are taken two per workgroup barrier: rows and columns k and k+1
+    // are published together, and every lane forms row and column k+1 after
+    // step k itself, with the FMAs their owners would have used, so the
+    // result is bitwise that of one step per barrier.
     __device__ __forceinline__ bool run(int k_begin, int k_end, double *lds, int ty, int tx) {
         static_assert(TY == TX && RA == RC, "square thread grid and register tile");
         bool ok = true;
-        run_from<0>(k_begin, k_end, lds, ty, tx, ok);
+        int phase = 0;
+        run_from<0>(k_begin, k_end, lds, ty, tx, ok, phase);
         return ok;
     }
 
     template <int KA>
-    __device__ __forceinline__ void run_from(int k_begin, int k_end, double *lds, int ty, int tx, bool &ok) {
+    __device__ __forceinline__ void run_from(int k_begin, int k_end, double *lds, int ty, int tx, bool &ok,
+                                             int &phase) {
         if constexpr (KA < RA) {
-            rank1_steps<KA>(k_begin, k_end, lds, ty, tx, ok);
-            run_from<KA + 1>(k_begin, k_end, lds, ty, tx, ok);
+            steps<KA>(k_begin, k_end, lds, ty, tx, ok, phase);
+            run_from<KA + 1>(k_begin, k_end, lds, ty, tx, ok, phase);
         }
     }
 
+    // The step with pivot row ci / column rj factors already formed: zero
+    // the pivot row and column (register row and column ka of the owning
+    // lanes) and apply the rank-1 update.
     template <int ka>
-    __device__ __forceinline__ void rank1_steps(int k_begin, int k_end, double *lds, int ty, int tx, bool &ok) {
+    __device__ __forceinline__ void apply(bool rowk, bool colk, const double (&ci)[RA], const double (&rj)[RC]) {
+#pragma unroll
+        for (int c = 0; c < RC; ++c) m[ka][c] = rowk ? 0.0 : m[ka][c];
+#pragma unroll
+        for (int a = 0; a < RA; ++a) m[a][ka] = colk ? 0.0 : m[a][ka];
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int c = 0; c < RC; ++c) m[a][c] = fma(-ci[a], rj[c], m[a][c]);
+    }
+
+    template <int ka>
+    __device__ __forceinline__ void steps(int k_begin, int k_end, double *lds, int ty, int tx, bool &ok, int &phase) {
         const int kt0 = k_begin > ka * TY ? k_begin - ka * TY : 0;
         const int kt1 = k_end < (ka + 1) * TY ? k_end - ka * TY : TY;
-        for (int kt = kt0; kt < kt1; ++kt) {
+        int kt = kt0;
+        for (; kt + 1 < kt1; kt += 2) {
+            const int k = ka * TY + kt, k1 = k + 1;
+            double *r0 = lds + phase * (4 * NP);   // row k, row k+1, column k, column k+1
+            double *r1 = r0 + NP, *c0 = r0 + 2 * NP, *c1 = r0 + 3 * NP;
+            phase ^= 1;
+            const bool rowk = ty == kt, colk = tx == kt, rowk1 = ty == kt + 1, colk1 = tx == kt + 1;
+            if (rowk || rowk1) {
+                double *rb = rowk ? r0 : r1;
+#pragma unroll
+                for (int c = 0; c < RC; ++c) rb[tx + TX * c] = m[ka][c];
+            }
+            if (colk || colk1) {
+                double *cb = colk ? c0 : c1;
+#pragma unroll
+                for (int a = 0; a < RA; ++a) cb[ty + TY * a] = m[a][ka];
+            }
+            __syncthreads();
+            // step k
+            const double p = c0[k];
+            ok = ok && (p > 0.0);
+            const double rp = recip(p);
+            double ci[RA], rj[RC];
+#pragma unroll
+            for (int a = 0; a < RA; ++a) ci[a] = c0[ty + TY * a];
+#pragma unroll
+            for (int c = 0; c < RC; ++c) rj[c] = r0[tx + TX * c] * rp;
+            ci[ka] = rowk ? -1.0 : ci[ka];
+            rj[ka] = colk ? rp : rj[ka];
+            // row k+1 and column k+1 after step k (entries of row / column k
+            // are zero before the update), and the pivot p' = M'[k+1][k+1]
+            const double r = c0[k1], q1 = r0[k1] * rp;
+            const double p1 = fma(-r, q1, r1[k1]);
+            ok = ok && (p1 > 0.0);
+            const double rp1 = recip(p1);
+            double ci1[RA], rj1[RC];
+#pragma unroll
+            for (int a = 0; a < RA; ++a) {
+                const double o = (rowk && a == ka) ? 0.0 : c1[ty + TY * a];
+                ci1[a] = fma(-ci[a], q1, o);
+            }
+#pragma unroll
+            for (int c = 0; c < RC; ++c) {
+                const double o = (colk && c == ka) ? 0.0 : r1[tx + TX * c];
+                rj1[c] = fma(-r, rj[c], o) * rp1;
+            }
+            ci1[ka] = rowk1 ? -1.0 : ci1[ka];
+            rj1[ka] = colk1 ? rp1 : rj1[ka];
+            apply<ka>(rowk, colk, ci, rj);
+            apply<ka>(rowk1, colk1, ci1, rj1);
+        }
+        if (kt < kt1) {
             const int k = ka * TY + kt;
-            double *rb = lds + (k & 1) * (2 * NP);
-            double *cb = rb + NP;
+            double *rb = lds + phase * (4 * NP);
+            double *cb = rb + 2 * NP;
+            phase ^= 1;
             const bool rowk = ty == kt, colk = tx == kt;
             if (rowk) {
 #pragma unroll
@@ -187,19 +263,12 @@ struct RegGJ {
             // pivot column: old entries become 0 and r_k = 1/p, so M'[i][k] = -M[i][k]/p
             ci[ka] = rowk ? -1.0 : ci[ka];
             rj[ka] = colk ? rp : rj[ka];
-#pragma unroll
-            for (int c = 0; c < RC; ++c) m[ka][c] = rowk ? 0.0 : m[ka][c];
-#pragma unroll
-            for (int a = 0; a < RA; ++a) m[a][ka] = colk ? 0.0 : m[a][ka];
-#pragma unroll
-            for (int a = 0; a < RA; ++a)
-#pragma unroll
-                for (int c = 0; c < RC; ++c) m[a][c] = fma(-ci[a], rj[c], m[a][c]);
+            apply<ka>(rowk, colk, ci, rj);
         }
     }
 
-    // The whole inverse of the leading n x n block (rank-1 steps 0 .. n-1).
-    // LDS scratch: 4 * NP doubles.
+    // The whole inverse of the leading n x n block (steps 0 .. n-1).  LDS
+    // scratch: kScratch doubles.
     __device__ __forceinline__ bool invert(int n, double *lds, int ty, int tx) { return run(0, n, lds, ty, tx); }
 };
 

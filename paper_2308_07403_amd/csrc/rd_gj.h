@@ -15,11 +15,14 @@ namespace rd {
 // P = M_KK^{-1}: writes P into V's column block K and P^T (k-major) to Pt.
 // Loads and the P store are coalesced straight from registers (lanes with
 // consecutive tx hold consecutive columns); P^T goes through a 64 x 65 LDS
-// quadrant.  About 37 KiB of LDS and under 192 VGPRs, so the kernel fits in
+// quadrant.  About 41 KiB of LDS and under 200 VGPRs, so the kernel fits in
 // the slot of one update workgroup and can run beside the update kernels.
+// pivots < 128: only the leading pivots are eliminated; the block's trailing
+// rows and columns must be those of an identity (the padding of the last
+// block), which elimination would leave unchanged.
 __device__ __forceinline__ void panel_core(const double *__restrict__ M, int ld, int K, double *__restrict__ Pt,
                                            double *__restrict__ V, int ldv, rdist_info *info, double *piv,
-                                           double (*tq)[65]) {
+                                           double (*tq)[65], int pivots = kTile) {
     const double *base = M + (size_t)K * kTile * ld + (size_t)K * kTile;
     RegGJ<16, 16, 8, 8> g;
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
@@ -27,7 +30,7 @@ __device__ __forceinline__ void panel_core(const double *__restrict__ M, int ld,
     for (int a = 0; a < 8; ++a)
 #pragma unroll
         for (int c = 0; c < 8; ++c) g.m[a][c] = base[(size_t)(ty + 16 * a) * ld + tx + 16 * c];
-    const bool ok = g.invert(kTile, piv, ty, tx);
+    const bool ok = g.invert(pivots, piv, ty, tx);
     double *vk = V + (size_t)K * kTile;
 #pragma unroll
     for (int a = 0; a < 8; ++a)

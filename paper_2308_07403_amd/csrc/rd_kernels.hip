@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int
                                                rdist_info *info) {
     if (info->status != RDIST_OK) return;
     lookahead_priority();
-    __shared__ double piv[4 * kTile];
+    __shared__ double piv[8 * kTile];   // RegGJ<16, 16, 8, 8>::kScratch
     __shared__ double tq[64][65];
     panel_core(M, ld, K, Pt, V, ldv, info, piv, tq);
 }
@@ -289,7 +289,7 @@ __global__ void k_info_set(rdist_info *info, double gamma) {
 template <int TY, int TX, int RA, int RC>
 __global__ __launch_bounds__(TY *TX) void k_small_one(SmallTask t) {
     constexpr int NP = TY * RA;
-    __shared__ double lds_gj[4 * NP];
+    __shared__ double lds_gj[8 * NP];   // RegGJ<TY, TX, RA, RC>::kScratch
     __shared__ int lds_int[NP + 2];
     solve_small<TY, TX, RA, RC>(t, lds_gj, lds_int);
 }

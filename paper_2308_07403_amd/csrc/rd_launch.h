@@ -57,8 +57,13 @@ struct LevelGraph {
 };
 constexpr int kLvMaxN = 4096;  // largest graph of the level plan
 constexpr int kLvShift = 10;   // unit = (graph << 10) | item, item < 1024 (nt^2 <= 1024)
-// Launch phases of the level plan (Edge and Rest are update tile sets).
-enum LevelPhase { kLvBuild = 0, kLvPanel = 1, kLvRowcol = 2, kLvEdge = 3, kLvRest = 4, kLvColsum = 5 };
+// Launch phases of the level plan (Diag, Edge and Rest are update tile sets).
+enum LevelPhase { kLvBuild = 0, kLvPanel = 1, kLvRowcol = 2, kLvEdge = 3, kLvRest = 4, kLvColsum = 5, kLvDiag = 6 };
+// Rows of the last block of a graph that hold pivots (n - 128 (nt - 1)),
+// rounded up to the contraction's k-chunk of 16: the inner dimension of the
+// last step's products (the block's padding rows and columns are an
+// identity, which contributes nothing to any other tile).
+__host__ __device__ inline int lv_last_inner(int n, int nt) { return ((n - 128 * (nt - 1) + 15) / 16) * 16; }
 
 // Out-degrees, validation and the gate: info (status, delta, gamma, zeroed counters).
 // weighted: A holds integer weights (0 = no edge); out-degrees count edges and

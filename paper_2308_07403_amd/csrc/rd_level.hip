@@ -14,6 +14,7 @@
 #include "rd_device.h"
 #include "rd_gj.h"
 #include "rd_launch.h"
+#include "rd_tile_kd.h"
 
 namespace rd {
 
@@ -327,7 +328,7 @@ __device__ __forceinline__ void solve_medium(const BatchTask &t, double *lds, do
 __global__ __launch_bounds__(256, 2) void k_batched(const BatchTask *__restrict__ tasks, int count, int *counter,
                                                  double *__restrict__ scratch, int scratch_stride) {
     __shared__ double lds[kTileLdsDoubles];
-    __shared__ double piv[4 * kTile];
+    __shared__ double piv[8 * kTile];   // RegGJ<16, 16, 8, 8>::kScratch
     __shared__ int ints[512 + 2];
     __shared__ unsigned long long red[8];
     __shared__ int next;
@@ -488,17 +489,20 @@ __global__ __launch_bounds__(256) void k_lv_panel(const LevelGraph *__restrict__
     const LevelGraph g = gs[gi];
     if (g.info->status != RDIST_OK) return;
     __builtin_amdgcn_s_setprio(3);   // lookahead chain: ahead of the update's waves on shared SIMDs
-    __shared__ double piv[4 * kTile];
+    __shared__ double piv[8 * kTile];   // RegGJ<16, 16, 8, 8>::kScratch
     __shared__ double tq[64][65];
     const int par = K & 1;
-    panel_core(g.M, g.np, K, g.Pt[par], g.V[par], g.np, g.info, piv, tq);
+    // the last block holds n - 128 K pivots; its padding is an identity
+    const int pivots = K == g.nt - 1 ? g.n - K * kTile : kTile;
+    panel_core(g.M, g.np, K, g.Pt[par], g.V[par], g.np, g.info, piv, tq, pivots);
 }
 
 // Row tiles of step K: items [0, nt-1) are V_J = P M_KJ for the tile
 // columns J != K (the column operand Ut of step K is written by the build for
-// K = 0 and by the edge update of step K-1 otherwise).
-__global__ __launch_bounds__(256) void k_lv_rowcol(const LevelGraph *__restrict__ gs, const int *__restrict__ units,
-                                                   int K) {
+// K = 0 and by the edge update of step K-1 otherwise).  On a graph's last
+// step the product runs over the block's pivot rows only.
+__global__ __launch_bounds__(256, 2) void k_lv_rowcol(const LevelGraph *__restrict__ gs,
+                                                      const int *__restrict__ units, int K) {
     int gi, item;
     if (!lv_unit(units, gi, item)) return;
     const LevelGraph g = gs[gi];
@@ -507,9 +511,10 @@ __global__ __launch_bounds__(256) void k_lv_rowcol(const LevelGraph *__restrict_
     __shared__ double lds[kTileLdsDoubles];
     const int np = g.np, par = K & 1;
     const int J = item < K ? item : item + 1;
+    const int kd = K == g.nt - 1 ? lv_last_inner(g.n, g.nt) : kTile;
     TileAcc acc;
     acc.zero();
-    tile_mma<kTile>(g.Pt[par], kTile, g.M + (size_t)K * kTile * np + (size_t)J * kTile, np, lds, acc);
+    tile_mma_kd(kd, g.Pt[par], kTile, g.M + (size_t)K * kTile * np + (size_t)J * kTile, np, lds, acc);
     double *out = g.V[par] + (size_t)J * kTile;
     tile_for_each(acc, [&](int r, int c, double v) { out[(size_t)r * np + c] = v; });
 }
@@ -532,16 +537,19 @@ __device__ __forceinline__ void tile_acc_from_adj(TileAcc &acc, const uint8_t *_
             }
 }
 
-// Trailing update of step K over the tiles of `kind`:
-//   kLvEdge  tile row and column L = K + 1 (what step K+1's panel and
-//            row tiles read): items [0, nt) are (L, j), items [nt, 2nt-1)
-//            are (i, L), i != L.  A column tile is not stored to M: it is
-//            written straight into step L's column operand as -(M'_iL)^T;
+// Trailing update of step K over the tiles of `kind`, L = K + 1:
+//   kLvDiag  the diagonal tile (L, L), all that step L's panel reads;
+//   kLvEdge  the rest of tile row and column L (what step L's row tiles and
+//            column operand read): items [0, nt-1) are (L, j), j != L, items
+//            [nt-1, 2nt-2) are (i, L), i != L.  A column tile is not stored
+//            to M: it is written straight into step L's column operand as
+//            -(M'_iL)^T;
 //   kLvRest  the other tiles: (nt-1)^2 items skipping row and column L when
 //            L < nt, all nt^2 tiles (item = I nt + J) on the graph's last step.
 // Block row K is V itself (U_K = -I), copied without a product.  On a
-// graph's last step the tile's final value is read out into D (stored to M
-// only with keep); a refused graph gets the sentinel there instead.
+// graph's last step the product runs over the block's pivot rows only, and
+// the tile's final value is read out into D (stored to M only with keep); a
+// refused graph gets the sentinel there instead.
 __global__ __launch_bounds__(256, 2) void k_lv_update(const LevelGraph *__restrict__ gs,
                                                       const int *__restrict__ units, int K, int kind) {
     int gi, item;
@@ -551,9 +559,11 @@ __global__ __launch_bounds__(256, 2) void k_lv_update(const LevelGraph *__restri
     const int L = K + 1;
     const bool last = L == nt;
     int I, J;
-    if (kind == kLvEdge) {
-        if (item < nt) { I = L; J = item; }
-        else { const int ip = item - nt; I = ip < L ? ip : ip + 1; J = L; }
+    if (kind == kLvDiag) {
+        I = J = L;
+    } else if (kind == kLvEdge) {
+        if (item < nt - 1) { I = L; J = item < L ? item : item + 1; }
+        else { const int ip = item - (nt - 1); I = ip < L ? ip : ip + 1; J = L; }
     } else if (last) {
         I = item / nt;
         J = item - (item / nt) * nt;
@@ -577,10 +587,12 @@ __global__ __launch_bounds__(256, 2) void k_lv_update(const LevelGraph *__restri
     if (I == K) {
         tile_load_acc(acc, g.V[par] + (size_t)J * kTile, np);
     } else {
+        const int kd = last ? lv_last_inner(n, nt) : kTile;
+        const double *ut = g.Ut[par] + (size_t)I * kTile, *v = g.V[par] + (size_t)J * kTile;
         if (J == K) acc.zero();
         else if (K == 0) tile_acc_from_adj(acc, g.A, n, I, J, g.info->gamma);
         else tile_load_acc(acc, base, np);
-        tile_mma<kTile>(g.Ut[par] + (size_t)I * kTile, np, g.V[par] + (size_t)J * kTile, np, lds, acc);
+        tile_mma_kd(kd, ut, np, v, np, lds, acc);
     }
     if (kind == kLvEdge && J == L && I != L) {
         double *out = g.Ut[par ^ 1] + (size_t)I * kTile;     // -(M'_IL)^T, k-major

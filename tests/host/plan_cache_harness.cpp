@@ -154,7 +154,8 @@ void launch_lv(int phase, const LevelGraph *gs, const int *units, int grid, int 
                 case kLvBuild: limit = 2 * L.nt - 1; break;
                 case kLvPanel: limit = K < L.nt ? 1 : 0; break;
                 case kLvRowcol: limit = K < L.nt ? L.nt - 1 : 0; break;
-                case kLvEdge: limit = K + 1 < L.nt ? 2 * L.nt - 1 : 0; break;
+                case kLvDiag: limit = K + 1 < L.nt ? 1 : 0; break;
+                case kLvEdge: limit = K + 1 < L.nt ? 2 * L.nt - 2 : 0; break;
                 case kLvRest: limit = L.nt * L.nt; break;
                 default: die("unknown level phase");
             }
