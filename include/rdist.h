@@ -80,7 +80,7 @@ typedef enum rdist_status {
 #define RDIST_PLAN_BLOCKED 0x200u   /* force the blocked multi-kernel plan, whatever n */
 #define RDIST_UNFUSED_EPILOGUE 0x400u /* run the readout as a standalone pass over Y */
 #define RDIST_BLOCK_128 0x800u      /* blocked plan: force block width b = 128 */
-#define RDIST_BLOCK_256 0x1000u     /* blocked plan: force block width b = 256 (default for n > 1024) */
+#define RDIST_BLOCK_256 0x1000u     /* blocked plan: force block width b = 256 (default for n > 7168) */
 #define RDIST_NO_GRAPH 0x2000u      /* rdist_solve_batched: launch eagerly, no HIP graph capture or replay */
 #define RDIST_WEIGHTED 0x4000u      /* rdist_solve: A_dev holds positive integer weights (Sec. 3.2) */
 
@@ -400,14 +400,15 @@ rdist_status rdist_epilogue(rdist_ctx ctx, const double *Y_dev, int32_t n, int32
  * together in one batched solve on one slot (as rdist_solve_batched with
  * T = 128, eager launches), up to max_batch of them; a path request keeps
  * its Y in the slot's buffers and its greedy paths (as rdist_next_hop) run
- * on the slot right after the batch.  A larger request takes a slot of its
- * own (rdist_solve, rdist_next_hop on its kept Y).  Requests on different
+ * on the slot right after the batch.  A larger request, and a request with
+ * n > 2048 that a slot takes alone, runs on a slot of its own as
+ * rdist_solve (and rdist_next_hop on its kept Y).  Requests on different
  * slots run concurrently on the device.  A slot's device buffers grow with
  * headroom and are kept until rdist_server_destroy.  Results are
  * bit-for-bit those of the same request solved alone (rdist_solve_batched
- * with count 1 and no tile cache for n <= 4096, rdist_solve above): every
- * slot has its own workspace and no kernel's arithmetic depends on what
- * else runs.  For the paper's query modes see Sec. 4.1 (full distance
+ * with count 1 and no tile cache for n <= 4096, rdist_solve above; for
+ * n <= 4096 the two give the same bits): every slot has its own workspace
+ * and no kernel's arithmetic depends on what else runs.  For the paper's query modes see Sec. 4.1 (full distance
  * matrix) and Sec. 4.2 (greedy routing).
  */
 typedef struct rdist_server_s *rdist_server;

@@ -163,10 +163,16 @@ void release_graph_locked(rdist_graph g) {
 // Block width of the blocked plan, in 128-tiles: 2 (b = 256) for large
 // graphs (half the passes over the matrix), 1 otherwise; the RDIST_BLOCK_*
 // flags override it.
+// Default block width: 128 up to n = 7168, 256 above.  Measured on one
+// graph per n (ER, single-graph plan): b = 128 takes 0.75x the time of
+// b = 256 for n from 1536 to 4096, 0.89x at 6144, but 1.05x at 8192 and
+// 1.16x at 16384, where the 256 block's rank-256 updates (half the passes
+// over M) outweigh its longer lookahead chain.
+constexpr int kBlock256MinN = 7169;
 int block_tiles(int n, uint32_t flags) {
     if (flags & RDIST_BLOCK_128) return 1;
     if (flags & RDIST_BLOCK_256) return 2;
-    return n > 1024 ? 2 : 1;
+    return n >= kBlock256MinN ? 2 : 1;
 }
 
 // P = M_KK^{-1} for the block at tile K0 (m tiles wide) into Pt (P^T) and

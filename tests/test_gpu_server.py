@@ -146,6 +146,42 @@ def test_server_large_request_takes_own_slot(ctx):
             assert np.array_equal(it["paths"].numpy(), paths.cpu().numpy()), f"request {it['id']} paths"
 
 
+def test_server_lone_large_request_single_plan_bitwise(ctx):
+    """Requests with 2048 < n <= 4096 that a slot takes alone run on the
+    single-graph plan; their D and paths equal those of a batch of one (the
+    reference for n <= 4096) bit for bit.  Submitted one at a time so that
+    each is alone."""
+    specs = ((3000, R.RDIST_QUERY_D, "er"), (2600, R.RDIST_QUERY_PATHS, "er"), (4096, R.RDIST_QUERY_D, "torus"))
+    srv = R.Server(ctx, slots=2, hbm_budget=0, max_batch=8)
+    items = []
+    for k, (n, kind, fam) in enumerate(specs):
+        A = (gg.erdos_renyi(n, 10.0 / n, gg.rng_for("parity", 9300 + k)) if fam == "er"
+             else gg.torus_lattice(n, "tri"))
+        n = A.shape[0]
+        it = {"id": 910000 + k, "A_np": A, "A": torch.from_numpy(A).cuda(), "kind": kind, "n": n,
+              "info": R.PinnedInfo(1)}
+        if kind == R.RDIST_QUERY_D:
+            it["D"] = torch.empty((n, n), dtype=torch.int16, pin_memory=True)
+        else:
+            pairs = gg.rng_for("parity", 9310).integers(0, n, size=(64, 2)).astype(np.int32)
+            it["cur"] = torch.from_numpy(pairs[:, 0].copy()).pin_memory()
+            it["goal"] = torch.from_numpy(pairs[:, 1].copy()).pin_memory()
+            it["paths"] = torch.empty((64, 33), dtype=torch.int32, pin_memory=True)
+        note(f"[server] lone request n={n} kind={kind}")
+        run_server(srv, [it])
+        items.append(it)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(items) and st["batched_requests"] == 0, st
+    for it in items:
+        D, status, paths = alone(ctx, it)
+        assert it["info"].get(0).status == status == 0
+        if it["kind"] == R.RDIST_QUERY_D:
+            assert np.array_equal(it["D"].numpy(), D.cpu().numpy()), f"request {it['id']} n={it['n']}"
+        else:
+            assert np.array_equal(it["paths"].numpy(), paths.cpu().numpy()), f"request {it['id']} paths"
+
+
 def test_server_reports_small_requests_of_a_batch_first(ctx):
     """One batch holding a large graph and small ones: requests are reported
     group by group (n <= 128 first, then by ceil(n / 128)), and every result
