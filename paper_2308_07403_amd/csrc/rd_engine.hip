@@ -160,10 +160,8 @@ void release_graph_locked(rdist_graph g) {
     delete g;
 }
 
-// Block width of the blocked plan, in 128-tiles: 2 (b = 256) for large
-// graphs (half the passes over the matrix), 1 otherwise; the RDIST_BLOCK_*
-// flags override it.
-// Default block width: 128 up to n = 7168, 256 above.  Measured on one
+// Block width of the blocked plan, in 128-tiles (1: b = 128, 2: b = 256);
+// the RDIST_BLOCK_* flags override the default: 128 up to n = 7168, 256 above.  Measured on one
 // graph per n (ER, single-graph plan): b = 128 takes 0.75x the time of
 // b = 256 for n from 1536 to 4096, 0.89x at 6144, but 1.05x at 8192 and
 // 1.16x at 16384, where the 256 block's rank-256 updates (half the passes
@@ -199,6 +197,65 @@ void enqueue_inverse(rdist_ctx c, Workspace &w, int ld, int K0, int m, int par, 
     rd::launch_panel_finish(S, ld, 256, K0, Pt, V, ld, dinfo, st);
 }
 
+// Zeroes the 128 x 128 blocks at column block J of rows [0, 128) of the
+// k-major slabs V and Ut (leading dimension ld).
+__global__ __launch_bounds__(128) void k_zero_pair_blocks(double *__restrict__ V, double *__restrict__ Ut, int ld,
+                                                          int J) {
+    double *slab = blockIdx.x < 128 ? V : Ut;
+    const int row = blockIdx.x & 127;
+    slab[(size_t)row * ld + (size_t)J * kB + threadIdx.x] = 0.0;
+}
+
+// The factors of the 256-wide block at tiles j, j+1 (b = 256) from two
+// 128-pivot steps over the whole band instead of inverting the 256 x 256
+// diagonal block first:
+//   step j    P^j = M_jj^{-1}; V rows [0, 128) = P^j M_j,: (P^j at block j),
+//             Ut rows [0, 128) = -(M_:,j)^T (identity at block j);
+//             then tile row and column j+1 take step j (a 128-wide update);
+//   step j+1  P^{j+1} = M'_{j+1,j+1}^{-1}; V rows [128, 256) = P^{j+1} M'_{j+1,:},
+//             Ut rows [128, 256) = -(M'_:,j+1)^T (identity at block j+1).
+// With V^j's block j+1 and Ut^j's block j+1 set to zero afterwards (their
+// contribution to row and column j+1 is inside step j+1's factors), the
+// rank-256 update M~ + Ut^T V over the concatenated slabs is the two steps
+// together: row j gets V^j + (Ut^{j+1}_j)^T V^{j+1}, row j+1 gets V^{j+1},
+// column j+1 gets (Ut^{j+1})^T P^{j+1}, every other tile both products.  The
+// DIAG, EDGEREST and REST updates of the 256 block run on these slabs
+// unchanged.  wait_ev (nullable): recorded on the main stream once tile rows
+// and columns j, j+1 are final (EDGEREST of the previous step); waited for
+// on st before the first launch that reads them in full.  The panel of step
+// j reads only the diagonal tile, which the previous step's DIAG updated.
+rdist_status enqueue_pair256(rdist_ctx c, Workspace &w, int ld, int nt, int j, int par, rdist_info *dinfo,
+                             hipStream_t st, hipEvent_t wait_ev) {
+    double *M = w.m();
+    double *Ut = (double *)w.Ut[par].p, *V = (double *)w.V[par].p, *Pt = (double *)w.Pt2.p;
+    const double b = 128.0;
+    const double rc_flops = 2.0 * b * b * (nt * 128.0 - b), rc_bytes = 8.0 * 4 * b * nt * 128.0;
+    for (int h = 0; h < 2; ++h) {
+        const int K = j + h;
+        double *Uh = Ut + (size_t)h * kB * ld, *Vh = V + (size_t)h * kB * ld;
+        {
+            Timer t(c, st, RDIST_K_PANEL, 2.0 * b * b * b, 16.0 * b * b);
+            rd::launch_panel(M, ld, K, Pt, Vh, ld, dinfo, st);
+        }
+        if (h == 0 && wait_ev) RD_HIP(hipStreamWaitEvent(st, wait_ev, 0));
+        {
+            Timer t(c, st, RDIST_K_ROWCOL, rc_flops, rc_bytes);
+            rd::launch_rowcol(M, ld, nt, K, 1, Pt, Uh, Vh, ld, dinfo, st);
+        }
+        if (h == 0) {
+            const int te = rd::update_tiles(rd::kUpdateEdgeRest, nt, 1, 1) + 1;
+            Timer t(c, st, RDIST_K_UPDATE_EDGE, 2.0 * b * b * b * te, 16.0 * b * b * te);
+            rd::launch_update(rd::kUpdateDiag, M, ld, nt, j, 1, j + 1, 1, Ut, V, ld, false, 0, nullptr, 0, dinfo,
+                              st);
+            rd::launch_update(rd::kUpdateEdgeRest, M, ld, nt, j, 1, j + 1, 1, Ut, V, ld, false, 0, nullptr, 0,
+                              dinfo, st);
+            hipLaunchKernelGGL(k_zero_pair_blocks, dim3(256), dim3(128), 0, st, V, Ut, ld, j + 1);
+        }
+    }
+    RD_HIP(hipGetLastError());
+    return RDIST_OK;
+}
+
 void enqueue_rowcol(rdist_ctx c, Workspace &w, int ld, int nt, int K0, int m, int par, rdist_info *dinfo,
                     hipStream_t st) {
     const double b = 128.0 * m;
@@ -217,6 +274,9 @@ void enqueue_rowcol(rdist_ctx c, Workspace &w, int ld, int nt, int K0, int m, in
 //        record ev_er; REST(K)
 //   aux: DIAG(K); inverse(K+1); wait ev_er; row/column tiles (K+1);
 //        record ev_panel
+// (for b = 256 the inverse and the row/column tiles of block K+1 are the two
+// 128-pivot steps of enqueue_pair256, which waits for ev_er after its first
+// panel)
 // DIAG(K) reads the next-next block's tiles as EDGEREST(K-1) left them, so the
 // lookahead chain never waits for a REST update: the next block's inverse
 // runs beside the big update.  U, V and P^T are double-buffered by step
@@ -242,8 +302,13 @@ rdist_status enqueue_blocked(rdist_ctx c, Workspace &w, int ld, const uint8_t *A
         rd::launch_ingest(A, n, np, ld, gamma, M, w.outdeg(), w.bad(), dinfo, s, (flags & RDIST_WEIGHTED) != 0);
     }
     RD_HIP(hipGetLastError());
-    enqueue_inverse(c, w, ld, 0, m, 0, dinfo, s);
-    enqueue_rowcol(c, w, ld, nt, 0, m, 0, dinfo, s);
+    if (m == 2) {
+        rdist_status st0 = enqueue_pair256(c, w, ld, nt, 0, 0, dinfo, s, nullptr);
+        if (st0) return st0;
+    } else {
+        enqueue_inverse(c, w, ld, 0, m, 0, dinfo, s);
+        enqueue_rowcol(c, w, ld, nt, 0, m, 0, dinfo, s);
+    }
     // streams of the step loop: the caller's stream and the lookahead stream
     hipStream_t ms = s;
     if (nbk > 1 && two) {
@@ -276,9 +341,14 @@ rdist_status enqueue_blocked(rdist_ctx c, Workspace &w, int ld, const uint8_t *A
                 Timer t(c, as, RDIST_K_UPDATE_EDGE, tile_flops * td, 16.0 * kB * kB * td);
                 rd::launch_update(rd::kUpdateDiag, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo, as);
             }
-            enqueue_inverse(c, w, ld, L0, m, par ^ 1, dinfo, as);
-            if (two) RD_HIP(hipStreamWaitEvent(as, w.ev_er, 0));
-            enqueue_rowcol(c, w, ld, nt, L0, m, par ^ 1, dinfo, as);
+            if (m == 2) {
+                rdist_status sp = enqueue_pair256(c, w, ld, nt, L0, par ^ 1, dinfo, as, two ? w.ev_er : nullptr);
+                if (sp) return sp;
+            } else {
+                enqueue_inverse(c, w, ld, L0, m, par ^ 1, dinfo, as);
+                if (two) RD_HIP(hipStreamWaitEvent(as, w.ev_er, 0));
+                enqueue_rowcol(c, w, ld, nt, L0, m, par ^ 1, dinfo, as);
+            }
             if (two) RD_HIP(hipEventRecord(w.ev_panel, as));
         } else {
             if (K > 0 && two) RD_HIP(hipStreamWaitEvent(ms, w.ev_panel, 0));
