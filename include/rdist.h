@@ -80,7 +80,7 @@ typedef enum rdist_status {
 #define RDIST_PLAN_BLOCKED 0x200u   /* force the blocked multi-kernel plan, whatever n */
 #define RDIST_UNFUSED_EPILOGUE 0x400u /* run the readout as a standalone pass over Y */
 #define RDIST_BLOCK_128 0x800u      /* blocked plan: force block width b = 128 */
-#define RDIST_BLOCK_256 0x1000u     /* blocked plan: force block width b = 256 (default for n > 7168) */
+#define RDIST_BLOCK_256 0x1000u     /* blocked plan: force block width b = 256 (default for n > 6400) */
 #define RDIST_NO_GRAPH 0x2000u      /* rdist_solve_batched: launch eagerly, no HIP graph capture or replay */
 #define RDIST_WEIGHTED 0x4000u      /* rdist_solve: A_dev holds positive integer weights (Sec. 3.2) */
 

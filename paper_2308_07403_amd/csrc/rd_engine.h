@@ -54,7 +54,8 @@ struct Workspace {
     int n_cap = 0;
     hipStream_t aux = nullptr;    // lookahead stream (default priority)
     hipStream_t aux2 = nullptr;   // batched plans: the persistent kernel's stream
-    hipEvent_t ev_er = nullptr, ev_rest = nullptr, ev_panel = nullptr;
+    hipEvent_t ev_er = nullptr, ev_panel = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;   // blocked plan (b = 256): the band update beside the second panel
     BatchPlan *transient = nullptr;   // batched plan rebuilt per call (not captured)
     // mixed precision: FP32 matrix, row product, column copy, FP64 diagonal
     // block, FP32 P, certification counters + slab flags, sparse rows of A,

@@ -81,7 +81,8 @@ rdist_status ensure_big(rdist_ctx c, Workspace &w, int np) {
     if ((st = ensure(c, w.Ut2, (size_t)128 * 256 * 8))) return st;
     if ((st = ensure(c, w.V2, (size_t)128 * 256 * 8))) return st;
     if ((st = ensure(c, w.Pt2, (size_t)128 * 128 * 8))) return st;
-    return ensure_aux(w);
+    if ((st = ensure_aux(w))) return st;
+    return ensure_aux2(w);   // the band update beside the second panel (b = 256)
 }
 
 void drain_timing(rdist_ctx c) {
@@ -161,12 +162,13 @@ void release_graph_locked(rdist_graph g) {
 }
 
 // Block width of the blocked plan, in 128-tiles (1: b = 128, 2: b = 256);
-// the RDIST_BLOCK_* flags override the default: 128 up to n = 7168, 256 above.  Measured on one
-// graph per n (ER, single-graph plan): b = 128 takes 0.75x the time of
-// b = 256 for n from 1536 to 4096, 0.89x at 6144, but 1.05x at 8192 and
-// 1.16x at 16384, where the 256 block's rank-256 updates (half the passes
-// over M) outweigh its longer lookahead chain.
-constexpr int kBlock256MinN = 7169;
+// the RDIST_BLOCK_* flags override the default: 128 up to n = 6400, 256
+// above.  Measured on one graph per n (ER, single-graph plan), time at
+// b = 128 over time at b = 256: 0.88 (n = 2048), 0.85 (3072), 0.86 (4096),
+// 0.89 (5120), 0.98 (6144), 1.07 (7168), 1.12 (8192), 1.14 (12288 and
+// 16384): above about 6400 the 256 block's rank-256 updates (half the
+// passes over M) outweigh its longer lookahead chain.
+constexpr int kBlock256MinN = 6401;
 int block_tiles(int n, uint32_t flags) {
     if (flags & RDIST_BLOCK_128) return 1;
     if (flags & RDIST_BLOCK_256) return 2;
@@ -224,34 +226,59 @@ __global__ __launch_bounds__(128) void k_zero_pair_blocks(double *__restrict__ V
 // and columns j, j+1 are final (EDGEREST of the previous step); waited for
 // on st before the first launch that reads them in full.  The panel of step
 // j reads only the diagonal tile, which the previous step's DIAG updated.
+// side (nullable): a second stream for step j's update of the rest of tile
+// row and column j+1, which only the row and column tiles of step j+1 read,
+// so that it runs beside the second panel (forked after the first row and
+// column tiles, joined before the second).
 rdist_status enqueue_pair256(rdist_ctx c, Workspace &w, int ld, int nt, int j, int par, rdist_info *dinfo,
-                             hipStream_t st, hipEvent_t wait_ev) {
+                             hipStream_t st, hipEvent_t wait_ev, hipStream_t side) {
     double *M = w.m();
     double *Ut = (double *)w.Ut[par].p, *V = (double *)w.V[par].p, *Pt = (double *)w.Pt2.p;
+    double *Ut1 = Ut + (size_t)kB * ld, *V1 = V + (size_t)kB * ld;   // rows [128, 256): step j+1
     const double b = 128.0;
+    const double p_flops = 2.0 * b * b * b, p_bytes = 16.0 * b * b;
     const double rc_flops = 2.0 * b * b * (nt * 128.0 - b), rc_bytes = 8.0 * 4 * b * nt * 128.0;
-    for (int h = 0; h < 2; ++h) {
-        const int K = j + h;
-        double *Uh = Ut + (size_t)h * kB * ld, *Vh = V + (size_t)h * kB * ld;
-        {
-            Timer t(c, st, RDIST_K_PANEL, 2.0 * b * b * b, 16.0 * b * b);
-            rd::launch_panel(M, ld, K, Pt, Vh, ld, dinfo, st);
-        }
-        if (h == 0 && wait_ev) RD_HIP(hipStreamWaitEvent(st, wait_ev, 0));
-        {
-            Timer t(c, st, RDIST_K_ROWCOL, rc_flops, rc_bytes);
-            rd::launch_rowcol(M, ld, nt, K, 1, Pt, Uh, Vh, ld, dinfo, st);
-        }
-        if (h == 0) {
-            const int te = rd::update_tiles(rd::kUpdateEdgeRest, nt, 1, 1) + 1;
-            Timer t(c, st, RDIST_K_UPDATE_EDGE, 2.0 * b * b * b * te, 16.0 * b * b * te);
-            rd::launch_update(rd::kUpdateDiag, M, ld, nt, j, 1, j + 1, 1, Ut, V, ld, false, 0, nullptr, 0, dinfo,
-                              st);
-            rd::launch_update(rd::kUpdateEdgeRest, M, ld, nt, j, 1, j + 1, 1, Ut, V, ld, false, 0, nullptr, 0,
-                              dinfo, st);
-            hipLaunchKernelGGL(k_zero_pair_blocks, dim3(256), dim3(128), 0, st, V, Ut, ld, j + 1);
-        }
+    const int te = rd::update_tiles(rd::kUpdateEdgeRest, nt, 1, 1);
+    // step j
+    {
+        Timer t(c, st, RDIST_K_PANEL, p_flops, p_bytes);
+        rd::launch_panel(M, ld, j, Pt, V, ld, dinfo, st);
     }
+    if (wait_ev) RD_HIP(hipStreamWaitEvent(st, wait_ev, 0));
+    {
+        Timer t(c, st, RDIST_K_ROWCOL, rc_flops, rc_bytes);
+        rd::launch_rowcol(M, ld, nt, j, 1, Pt, Ut, V, ld, dinfo, st);
+    }
+    // step j on tile row and column j+1: the rest of the band (on side if
+    // given) and the diagonal tile, which is all the second panel reads
+    hipStream_t es = side ? side : st;
+    if (side) {
+        RD_HIP(hipEventRecord(w.ev_fork, st));
+        RD_HIP(hipStreamWaitEvent(side, w.ev_fork, 0));
+    }
+    {
+        Timer t(c, es, RDIST_K_UPDATE_EDGE, p_flops * te, p_bytes * te);
+        rd::launch_update(rd::kUpdateEdgeRest, M, ld, nt, j, 1, j + 1, 1, Ut, V, ld, false, 0, nullptr, 0, dinfo,
+                          es);
+    }
+    if (side) RD_HIP(hipEventRecord(w.ev_join, side));
+    {
+        Timer t(c, st, RDIST_K_UPDATE_EDGE, p_flops, p_bytes);
+        rd::launch_update(rd::kUpdateDiag, M, ld, nt, j, 1, j + 1, 1, Ut, V, ld, false, 0, nullptr, 0, dinfo, st);
+    }
+    // step j+1
+    {
+        Timer t(c, st, RDIST_K_PANEL, p_flops, p_bytes);
+        rd::launch_panel(M, ld, j + 1, Pt, V1, ld, dinfo, st);
+    }
+    if (side) RD_HIP(hipStreamWaitEvent(st, w.ev_join, 0));
+    {
+        Timer t(c, st, RDIST_K_ROWCOL, rc_flops, rc_bytes);
+        rd::launch_rowcol(M, ld, nt, j + 1, 1, Pt, Ut1, V1, ld, dinfo, st);
+    }
+    // V^j's block j+1 and Ut^j's block j+1: read by step j's band and
+    // diagonal updates, both finished here
+    hipLaunchKernelGGL(k_zero_pair_blocks, dim3(256), dim3(128), 0, st, V, Ut, ld, j + 1);
     RD_HIP(hipGetLastError());
     return RDIST_OK;
 }
@@ -302,8 +329,13 @@ rdist_status enqueue_blocked(rdist_ctx c, Workspace &w, int ld, const uint8_t *A
         rd::launch_ingest(A, n, np, ld, gamma, M, w.outdeg(), w.bad(), dinfo, s, (flags & RDIST_WEIGHTED) != 0);
     }
     RD_HIP(hipGetLastError());
+    // a third stream for the band update only while this context drives one
+    // stream: the process has four hardware queues, and the streams of
+    // several concurrent solves already share them (three solves on three
+    // streams: 43 graphs/s with it against 52 without, at n = 8192)
+    hipStream_t side = two && c->ws.size() == 1 ? w.aux2 : nullptr;
     if (m == 2) {
-        rdist_status st0 = enqueue_pair256(c, w, ld, nt, 0, 0, dinfo, s, nullptr);
+        rdist_status st0 = enqueue_pair256(c, w, ld, nt, 0, 0, dinfo, s, nullptr, side);
         if (st0) return st0;
     } else {
         enqueue_inverse(c, w, ld, 0, m, 0, dinfo, s);
@@ -342,7 +374,8 @@ rdist_status enqueue_blocked(rdist_ctx c, Workspace &w, int ld, const uint8_t *A
                 rd::launch_update(rd::kUpdateDiag, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo, as);
             }
             if (m == 2) {
-                rdist_status sp = enqueue_pair256(c, w, ld, nt, L0, par ^ 1, dinfo, as, two ? w.ev_er : nullptr);
+                rdist_status sp = enqueue_pair256(c, w, ld, nt, L0, par ^ 1, dinfo, as, two ? w.ev_er : nullptr,
+                                                  side);
                 if (sp) return sp;
             } else {
                 enqueue_inverse(c, w, ld, L0, m, par ^ 1, dinfo, as);
@@ -444,7 +477,7 @@ void free_workspace(rdist_ctx c, Workspace &w) {
     if (w.rows_exec) (void)hipGraphExecDestroy(w.rows_exec);
     if (w.rows_graph) (void)hipGraphDestroy(w.rows_graph);
     if (w.rflag_h) (void)hipHostFree(w.rflag_h);
-    for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
+    for (hipEvent_t e : {w.ev_er, w.ev_panel, w.ev_fork, w.ev_join})
         if (e) (void)hipEventDestroy(e);
     if (w.aux) (void)hipStreamDestroy(w.aux);
     if (w.aux2) (void)hipStreamDestroy(w.aux2);

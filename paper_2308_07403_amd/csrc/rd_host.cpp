@@ -72,6 +72,14 @@ rdist_status ensure_aux2(Workspace &w) {
         w.aux2 = nullptr;
         return fail(RDIST_E_HIP, "hipStreamCreateWithFlags failed");
     }
+    if (!w.ev_fork && hipEventCreateWithFlags(&w.ev_fork, hipEventDisableTiming) != hipSuccess) {
+        w.ev_fork = nullptr;
+        return fail(RDIST_E_HIP, "hipEventCreateWithFlags failed");
+    }
+    if (!w.ev_join && hipEventCreateWithFlags(&w.ev_join, hipEventDisableTiming) != hipSuccess) {
+        w.ev_join = nullptr;
+        return fail(RDIST_E_HIP, "hipEventCreateWithFlags failed");
+    }
     return RDIST_OK;
 }
 
@@ -83,7 +91,6 @@ rdist_status ensure_aux(Workspace &w) {
             return fail(RDIST_E_HIP, "hipStreamCreateWithFlags failed");
         }
         if (hipEventCreateWithFlags(&w.ev_er, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&w.ev_rest, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&w.ev_panel, hipEventDisableTiming) != hipSuccess)
             return fail(RDIST_E_HIP, "hipEventCreateWithFlags failed");
     }

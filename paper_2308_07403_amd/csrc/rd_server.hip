@@ -258,7 +258,7 @@ rdist_status dispatch_batch(rdist_server s, Slot &sl, const std::vector<Pending>
 }
 
 // A request above this order that a slot takes alone runs on the
-// single-graph plan (width 128 up to n = 7168), which is faster than a
+// single-graph plan (width 128 up to n = 6400), which is faster than a
 // batch of one there (n = 4096: 4.97 against 6.42 ms) and gives the same
 // results bit for bit: both take the same 128-pivot steps with the same
 // products in the same order.

@@ -300,7 +300,7 @@ void free_workspace(rdist_ctx c, Workspace &w) {
     free_transient_plan(c, w);
     if (w.aux) (void)hipStreamDestroy(w.aux);
     if (w.aux2) (void)hipStreamDestroy(w.aux2);
-    for (hipEvent_t e : {w.ev_er, w.ev_rest, w.ev_panel})
+    for (hipEvent_t e : {w.ev_er, w.ev_panel, w.ev_fork, w.ev_join})
         if (e) (void)hipEventDestroy(e);
     w = Workspace{};
 }
