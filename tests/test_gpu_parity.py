@@ -144,13 +144,16 @@ def test_blocked_plan_forced_on_small_graph(ctx):
     g1.release()
 
 
+@pytest.mark.parametrize("bw", [0, R.RDIST_BLOCK_256])
 @pytest.mark.parametrize("family", ["lattice", "rgg", "tree", "path"])
-def test_blocked_plan_families(ctx, family):
+def test_blocked_plan_families(ctx, family, bw):
+    """Families at the default width and at b = 256 (whose factors come from
+    two 128-pivot steps over the band; the directed path is triangular)."""
     rng = gg.rng_for("parity", 2000 + len(family))
     n = 400
     A = {"lattice": lambda: gg.grid_lattice_deleted(n, rng), "rgg": lambda: gg.random_geometric(n, rng),
          "tree": lambda: gg.random_tree(n, rng), "path": lambda: gg.directed_path(n)}[family]()
-    _, _, _, g = check_against_oracle(ctx, A, -0.5, label=f"blocked {family}")
+    _, _, _, g = check_against_oracle(ctx, A, -0.5, flags=R.RDIST_F64 | bw, label=f"blocked {family} bw={bw:#x}")
     g.release()
 
 
