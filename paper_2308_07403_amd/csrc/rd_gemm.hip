@@ -45,12 +45,14 @@ __device__ __forceinline__ int acc_col(int q) { return ((threadIdx.x >> 6) & 1) 
 
 // ---- FP32: operands k-major, A_k[k][i], B_k[k][j] ----
 // 128 x 128 output tiles, wave w owns the 64 x 64 quadrant (w >> 1, w & 1)
-// as 2 x 2 blocks of 32 x 32; 32 KiB of LDS, so up to five workgroups share
-// a compute unit and hide each other's memory latency.
-constexpr int kKC32 = 16;                     // k-rows per chunk
-constexpr int kChunk32 = kKC32 * kT;          // floats per operand chunk (8 KiB)
+// as 2 x 2 blocks of 32 x 32; 16 KiB of LDS, so the registers (about 90
+// VGPRs) decide how many workgroups share a compute unit (five) and hide
+// each other's memory latency.  (In the C4 solve: 8-row k-chunks with
+// fragments read one k-step ahead 120.5 TFLOP/s, 16-row chunks without 119.6.)
+constexpr int kKC32 = 8;                      // k-rows per chunk
+constexpr int kChunk32 = kKC32 * kT;          // floats per operand chunk (4 KiB)
 
-// Wave w copies k-rows 4w .. 4w+3 of both operands' chunk at k0; one
+// Wave w copies k-rows (kKC32 / 4) w .. of both operands' chunk at k0; one
 // instruction moves two k-rows of 128 floats (lanes 0-31 the first).
 __device__ __forceinline__ void dma32(const float *__restrict__ A, int lda, const float *__restrict__ B, int ldb,
                                       int k0, float *As, float *Bs) {
@@ -66,18 +68,28 @@ __device__ __forceinline__ void dma32(const float *__restrict__ A, int lda, cons
     }
 }
 
-// One chunk: 8 k-steps of 2, four 32 x 32 blocks per step.
+// One chunk: kKC32 / 2 k-steps of 2, four 32 x 32 blocks per step, each
+// step's fragments read from LDS one step ahead.
 __device__ __forceinline__ void mma32_chunk(const float *As, const float *Bs, Acc32 &acc) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m0 = (w >> 1) * 64 + (lane & 31), n0 = (w & 1) * 64 + (lane & 31), kr = lane >> 5;
+    float a[2][2], b[2][2];
+    auto frags = [&](int ks, float *af, float *bf) {
+        const float *ar = As + (2 * ks + kr) * kT, *br = Bs + (2 * ks + kr) * kT;
+        af[0] = ar[m0];
+        af[1] = ar[m0 + 32];
+        bf[0] = br[n0];
+        bf[1] = br[n0 + 32];
+    };
+    frags(0, a[0], b[0]);
 #pragma unroll
     for (int ks = 0; ks < kKC32 / 2; ++ks) {
-        const float *ar = As + (2 * ks + kr) * kT, *br = Bs + (2 * ks + kr) * kT;
-        const float a0 = ar[m0], a1 = ar[m0 + 32], b0 = br[n0], b1 = br[n0 + 32];
-        acc.v[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc.v[0][0], 0, 0, 0);
-        acc.v[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc.v[0][1], 0, 0, 0);
-        acc.v[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc.v[1][0], 0, 0, 0);
-        acc.v[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc.v[1][1], 0, 0, 0);
+        const int cur = ks & 1;
+        if (ks + 1 < kKC32 / 2) frags(ks + 1, a[cur ^ 1], b[cur ^ 1]);
+        acc.v[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[cur][0], b[cur][0], acc.v[0][0], 0, 0, 0);
+        acc.v[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[cur][0], b[cur][1], acc.v[0][1], 0, 0, 0);
+        acc.v[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[cur][1], b[cur][0], acc.v[1][0], 0, 0, 0);
+        acc.v[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[cur][1], b[cur][1], acc.v[1][1], 0, 0, 0);
     }
 }
 
@@ -91,7 +103,7 @@ __global__ __launch_bounds__(256, 4) void k_gemm32(float *__restrict__ C, int ld
                                                    const float *__restrict__ Ak, int lda,
                                                    const float *__restrict__ Bk, int ldb, const rdist_info *info) {
     if (info->status != RDIST_OK) return;
-    __shared__ float lds[4 * kChunk32];   // A, B x two buffers: 32 KiB
+    __shared__ float lds[4 * kChunk32];   // A, B x two buffers: 16 KiB
     int I, J;
     if (MODE == 1) {
         xcd_strip_order(blockIdx.x, ntj, I, J);
