@@ -145,14 +145,13 @@ __global__ __launch_bounds__(256) void k_fill_sentinel(int16_t *D, size_t count,
 // Blocked Gauss-Jordan
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_panel(const double *__restrict__ M, int ld, int K,
-                                               double *__restrict__ Pt, double *__restrict__ V, int ldv,
-                                               rdist_info *info) {
+__global__ __launch_bounds__(256, 2) void k_panel(const double *__restrict__ M, int ld, int K,
+                                                  double *__restrict__ Pt, double *__restrict__ V, int ldv,
+                                                  rdist_info *info) {
     if (info->status != RDIST_OK) return;
     lookahead_priority();
-    __shared__ double piv[8 * kTile];   // RegGJ<16, 16, 8, 8>::kScratch
-    __shared__ double tq[64][65];
-    panel_core(M, ld, K, Pt, V, ldv, info, piv, tq);
+    __shared__ PanelLds lds;
+    panel_core(M, ld, K, Pt, V, ldv, info, lds);
 }
 
 // Step with block width b = 128*m whose block starts at tile K0 (tiles are

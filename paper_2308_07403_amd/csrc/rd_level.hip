@@ -482,19 +482,18 @@ __global__ __launch_bounds__(256) void k_lv_build(const LevelGraph *__restrict__
 }
 
 // Panel of step K (item unused).
-__global__ __launch_bounds__(256) void k_lv_panel(const LevelGraph *__restrict__ gs, const int *__restrict__ units,
-                                                  int K) {
+__global__ __launch_bounds__(256, 2) void k_lv_panel(const LevelGraph *__restrict__ gs, const int *__restrict__ units,
+                                                     int K) {
     int gi, item;
     if (!lv_unit(units, gi, item)) return;
     const LevelGraph g = gs[gi];
     if (g.info->status != RDIST_OK) return;
     __builtin_amdgcn_s_setprio(3);   // lookahead chain: ahead of the update's waves on shared SIMDs
-    __shared__ double piv[8 * kTile];   // RegGJ<16, 16, 8, 8>::kScratch
-    __shared__ double tq[64][65];
+    __shared__ PanelLds lds;
     const int par = K & 1;
     // the last block holds n - 128 K pivots; its padding is an identity
     const int pivots = K == g.nt - 1 ? g.n - K * kTile : kTile;
-    panel_core(g.M, g.np, K, g.Pt[par], g.V[par], g.np, g.info, piv, tq, pivots);
+    panel_core(g.M, g.np, K, g.Pt[par], g.V[par], g.np, g.info, lds, pivots);
 }
 
 // Row tiles of step K: items [0, nt-1) are V_J = P M_KJ for the tile
