@@ -400,10 +400,13 @@ rdist_status rdist_epilogue(rdist_ctx ctx, const double *Y_dev, int32_t n, int32
  * together in one batched solve on one slot (as rdist_solve_batched with
  * T = 128, eager launches), up to max_batch of them; a path request keeps
  * its Y in the slot's buffers and its greedy paths (as rdist_next_hop) run
- * on the slot right after the batch.  A larger request, and a request with
- * n > 2048 that a slot takes alone, runs on a slot of its own as
- * rdist_solve (and rdist_next_hop on its kept Y).  Requests on different
- * slots run concurrently on the device.  A slot's device buffers grow with
+ * on the slot right after the batch.  While at most 8 requests wait, one
+ * with n > 1024 stays out of the batch.  A request above 4096, and one with
+ * n > 1024 that is not batched, runs on a slot of its own as
+ * rdist_solve, its greedy paths (as rdist_next_hop) on the Y that solve
+ * leaves in the slot's workspace, so no graph handle is made or released
+ * per request.  Requests on different slots run concurrently on the
+ * device.  A slot's device buffers grow with
  * headroom and are kept until rdist_server_destroy.  Results are
  * bit-for-bit those of the same request solved alone (rdist_solve_batched
  * with count 1 and no tile cache for n <= 4096, rdist_solve above; for

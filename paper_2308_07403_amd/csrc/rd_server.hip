@@ -2,7 +2,8 @@
 // streams with their own workspaces), admission by HBM footprint and
 // continuous batching: every request with n <= 4096, full D or paths, joins
 // the next batch of a free slot (one level-synchronous batched solve; a path
-// request keeps Y in the slot's own buffer).  A batch completes in groups:
+// request keeps Y in the slot's own buffer), except that one with n > 1024
+// runs alone on the single-graph plan while at most 8 requests wait.  A batch completes in groups:
 // the graphs with n <= 128 when the persistent kernel ends, those with
 // ceil(n / 128) = t after blocked step t - 1; each group's results (D, infos,
 // and the greedy paths of its path requests) are copied out as soon as the
@@ -46,7 +47,6 @@ struct Slot {
     std::vector<Pending> reqs;           // in flight on this slot
     std::vector<Group> groups;           // their completion groups
     int groups_left = 0;
-    rdist_graph graph = nullptr;         // a path request above the batched range: its kept Y
     Buf D, Y, bits, paths, pairs, tasks; // device buffers, grown with headroom and kept
     rdist_info *info_h = nullptr;        // pinned, kBatchMarks blocks of max_batch infos
     int32_t *pairs_h = nullptr;          // pinned staging of (cur, goal), max_batch * kMaxPairs pairs
@@ -98,7 +98,8 @@ void fail_request(rdist_server s, const Pending &p, rdist_status why) {
 }
 
 // A request above the batched range, alone on the slot's stream: the
-// single-graph plan, its D or its paths on a kept Y; one group.
+// single-graph plan, its D, or its paths on Y left in the stream's workspace;
+// one group.
 rdist_status dispatch_single(rdist_server s, Slot &sl, const rdist_request &r0) {
     rdist_ctx c = s->ctx;
     hipStream_t st = sl.stream;
@@ -110,20 +111,47 @@ rdist_status dispatch_single(rdist_server s, Slot &sl, const rdist_request &r0) 
         if (e) return e;
         RD_HIP(hipMemcpyAsync(r0.D_host, sl.D.p, n2 * 2, hipMemcpyDeviceToHost, st));
     } else {
+        // Y stays in the workspace of the slot's stream (M, leading dimension
+        // its np_cap) until the next solve on that stream, which starts only
+        // after this request is reported: no graph handle, so nothing is
+        // allocated for the request and nothing freed when it completes (a
+        // free synchronises the whole device and would stall the caller's
+        // poll loop behind the other slots' work).  The paths come from the
+        // batched plan's path kernel (successor bitmap, then greedy hops).
         const size_t pb = (size_t)r0.q * rd::path_row_len(r0.max_hops) * 4;
+        const size_t nw = ((size_t)r0.n + 63) / 64;
         if ((e = grow(c, sl.paths, pb))) return e;
         if ((e = grow(c, sl.pairs, (size_t)2 * kMaxPairs * 4))) return e;
-        rdist_graph g = nullptr;
-        e = rdist_solve(c, r0.A_dev, r0.n, r0.gamma, RDIST_F64 | RDIST_KEEP_Y, (int16_t *)sl.D.p, &g, sl.info_h, st);
+        if ((e = grow(c, sl.bits, (size_t)r0.n * nw * 8))) return e;
+        if ((e = grow(c, sl.tasks, sizeof(rd::PathTask)))) return e;
+        e = rdist_solve(c, r0.A_dev, r0.n, r0.gamma, RDIST_F64 | RDIST_KEEP_Y, (int16_t *)sl.D.p, nullptr, sl.info_h,
+                        st);
         if (e) return e;
-        sl.graph = g;
         if (r0.q > 0) {
+            const Workspace &w = c->ws[st];
             std::memcpy(sl.pairs_h, r0.cur_host, (size_t)r0.q * 4);
             std::memcpy(sl.pairs_h + kMaxPairs, r0.goal_host, (size_t)r0.q * 4);
             int32_t *cur = (int32_t *)sl.pairs.p, *goal = cur + kMaxPairs;
             RD_HIP(hipMemcpyAsync(cur, sl.pairs_h, (size_t)2 * kMaxPairs * 4, hipMemcpyHostToDevice, st));
-            e = rdist_next_hop(c, g, cur, goal, r0.q, r0.max_hops, (int32_t *)sl.paths.p, st);
-            if (e) return e;
+            rd::PathTask &t = sl.tasks_h[0];
+            t.A = r0.A_dev;
+            t.Y = (const double *)w.M.p;
+            t.bits = (unsigned long long *)sl.bits.p;
+            t.cur = cur;
+            t.goal = goal;
+            t.out = (int32_t *)sl.paths.p;
+            t.n = r0.n;
+            t.ld = w.np_cap;
+            t.q = r0.q;
+            t.max_hops = r0.max_hops;
+            t.blk0 = 0;
+            t.q0 = 0;
+            RD_HIP(hipMemcpyAsync(sl.tasks.p, sl.tasks_h, sizeof(rd::PathTask), hipMemcpyHostToDevice, st));
+            {
+                Timer tm(c, st, RDIST_K_NEXTHOP, 0.0, 0.0);
+                rd::launch_paths_multi((const rd::PathTask *)sl.tasks.p, 1, rd::path_task_blocks(r0.n), r0.q, st);
+            }
+            RD_HIP(hipGetLastError());
             RD_HIP(hipMemcpyAsync(r0.paths_host, sl.paths.p, pb, hipMemcpyDeviceToHost, st));
         }
     }
@@ -257,18 +285,25 @@ rdist_status dispatch_batch(rdist_server s, Slot &sl, const std::vector<Pending>
     return RDIST_OK;
 }
 
-// A request above this order that a slot takes alone runs on the
-// single-graph plan (width 128 up to n = 6400), which is faster than a
-// batch of one there (n = 4096: 4.97 against 6.42 ms) and gives the same
-// results bit for bit: both take the same 128-pivot steps with the same
-// products in the same order.
-constexpr int kLoneSingleMinN = 2049;
+// A request from this order on runs alone on the single-graph plan (width
+// 128 up to n = 6400) when few requests wait: faster than the level plan for
+// one graph (n = 4096: 4.56 against 6.19 ms; n = 2048: 1.94 against 2.26)
+// and the same results bit for bit (both take the same 128-pivot steps with
+// the same products in the same order).  Behind a backlog it joins the batch
+// instead, whose level plan keeps many large graphs in flight at once.  At
+// the C5 request mix (two slots, 0.1x of saturation) this moved p99 from
+// 11.9 to 8.0 ms with the saturated rate unchanged; taking such requests out
+// of batches always cost a third of the saturated rate.
+constexpr int kLoneSingleMinN = 1025;
+bool lone(const rdist_request &r) { return r.n >= kLoneSingleMinN; }
+// Queue length up to which such requests are taken out of batches.
+constexpr size_t kLoneMaxQueue = 8;
 
 // Launches the requests of `batch` on slot k.  Returns RDIST_E_AGAIN when the
 // context's own budget is in use (the caller puts them back in the queue).
 rdist_status dispatch(rdist_server s, int k, std::vector<Pending> &batch) {
     Slot &sl = s->slots[k];
-    const bool single = batch.size() == 1 && (!batchable(batch[0].r) || batch[0].r.n >= kLoneSingleMinN);
+    const bool single = batch.size() == 1 && (!batchable(batch[0].r) || lone(batch[0].r));
     const rdist_status e = single ? dispatch_single(s, sl, batch[0].r) : dispatch_batch(s, sl, batch);
     if (e) return e;
     sl.busy = true;
@@ -298,14 +333,20 @@ void pump(rdist_server s) {
         if (k < 0) return;
         std::vector<Pending> batch;
         size_t f = 0;
-        if (batchable(s->queue.front().r)) {
-            // every batchable request in the queue, in order, while it fits
+        // With few requests waiting, one with n > 2048 runs alone on the
+        // single-graph plan (latency); with a backlog it joins the batch,
+        // whose level plan runs many large graphs at once (throughput).
+        const bool split = s->queue.size() <= kLoneMaxQueue;
+        auto batches = [&](const rdist_request &r) { return batchable(r) && !(split && lone(r)); };
+        if (batches(s->queue.front().r)) {
+            // every waiting request that batches, in order, while it fits;
+            // the ones that run alone stay queued for the next free slot
             for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < s->max_batch;) {
-                if (batchable(it->r) && fits(s, f + it->footprint)) {
+                if (batches(it->r) && fits(s, f + it->footprint)) {
                     f += it->footprint;
                     batch.push_back(*it);
                     it = s->queue.erase(it);
-                } else if (batchable(it->r)) {
+                } else if (batches(it->r)) {
                     break;
                 } else {
                     ++it;
@@ -324,15 +365,12 @@ void pump(rdist_server s) {
             (void)hipDeviceSynchronize();   // whatever the failed dispatch enqueued
             for (auto it = batch.rbegin(); it != batch.rend(); ++it) s->queue.push_front(*it);
             s->st.queued = (int64_t)s->queue.size();
-            Slot &sl = s->slots[k];
-            if (sl.graph) { rdist_graph_release(sl.graph); sl.graph = nullptr; }
-            sl.groups.clear();
+            s->slots[k].groups.clear();
             return;
         }
         if (e) {
             Slot &sl = s->slots[k];
             (void)hipDeviceSynchronize();   // the slot's stream and the plan's other streams
-            if (sl.graph) { rdist_graph_release(sl.graph); sl.graph = nullptr; }
             sl.groups.clear();
             for (auto &p : batch) fail_request(s, p, e);
         }
@@ -353,10 +391,6 @@ void complete_group(rdist_server s, Slot &sl, Group &G, bool single) {
 }
 
 void release_slot(rdist_server s, Slot &sl) {
-    if (sl.graph) {
-        rdist_graph_release(sl.graph);
-        sl.graph = nullptr;
-    }
     s->st.footprint_in_flight -= sl.footprint;
     sl.reqs.clear();
     sl.groups.clear();
@@ -477,7 +511,6 @@ void rdist_server_destroy(rdist_server s) {
         (void)hipSetDevice(s->ctx->device);
         (void)hipDeviceSynchronize();   // every slot's streams, the plans' tail streams included
         for (Slot &sl : s->slots) {
-            if (sl.graph) rdist_graph_release(sl.graph);
             for (Buf *b : {&sl.D, &sl.Y, &sl.bits, &sl.paths, &sl.pairs, &sl.tasks}) release(s->ctx, *b);
             if (sl.info_h) (void)hipHostFree(sl.info_h);
             if (sl.pairs_h) (void)hipHostFree(sl.pairs_h);

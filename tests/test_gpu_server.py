@@ -104,7 +104,10 @@ def test_server_mix_is_bitwise_alone(ctx):
     assert done == {it["id"] for it in items}
     assert st["completed"] == len(items) and st["failed"] == 0
     assert st["max_footprint_in_flight"] <= budget
-    assert st["batches"] >= 2 and st["batched_requests"] == len(items) and st["max_in_flight"] >= 2
+    # n <= 1024 always batches; a larger one batches behind a backlog and
+    # runs alone (single-graph plan) when few requests wait
+    n_small = sum(it["n"] <= 1024 for it in items)
+    assert st["batches"] >= 2 and n_small <= st["batched_requests"] <= len(items) and st["max_in_flight"] >= 2
     # each result equals the same request solved alone
     for it in items:
         info = it["info"].get(0)
@@ -147,11 +150,13 @@ def test_server_large_request_takes_own_slot(ctx):
 
 
 def test_server_lone_large_request_single_plan_bitwise(ctx):
-    """Requests with 2048 < n <= 4096 that a slot takes alone run on the
-    single-graph plan; their D and paths equal those of a batch of one (the
-    reference for n <= 4096) bit for bit.  Submitted one at a time so that
-    each is alone."""
-    specs = ((3000, R.RDIST_QUERY_D, "er"), (2600, R.RDIST_QUERY_PATHS, "er"), (4096, R.RDIST_QUERY_D, "torus"))
+    """Requests with 1024 < n <= 4096 that run alone (few requests waiting)
+    take the single-graph plan, paths on the Y it leaves in the slot's
+    workspace; their D and paths equal those of a batch of one (the reference
+    for n <= 4096) bit for bit.  Submitted one at a time; the path requests
+    back to back, so the second reuses the first one's workspace."""
+    specs = ((3000, R.RDIST_QUERY_D, "er"), (2600, R.RDIST_QUERY_PATHS, "er"), (1500, R.RDIST_QUERY_PATHS, "er"),
+             (4096, R.RDIST_QUERY_D, "torus"))
     srv = R.Server(ctx, slots=2, hbm_budget=0, max_batch=8)
     items = []
     for k, (n, kind, fam) in enumerate(specs):
@@ -182,12 +187,39 @@ def test_server_lone_large_request_single_plan_bitwise(ctx):
             assert np.array_equal(it["paths"].numpy(), paths.cpu().numpy()), f"request {it['id']} paths"
 
 
+def test_server_backlog_batches_larger_requests(ctx):
+    """With more requests waiting than the server takes out of batches, the
+    larger ones (1024 < n <= 4096) join the batch: one slot, all submitted
+    before the first poll, so the whole backlog goes out as one batch; results
+    still equal each request solved alone."""
+    items = make_requests(14, stream_index=11, n_hi=1200)
+    for k, n in enumerate((1500, 1800)):
+        A = gg.erdos_renyi(n, 8.0 / n, gg.rng_for("parity", 9400 + k))
+        it = {"id": 920000 + k, "A_np": A, "A": torch.from_numpy(A).cuda(), "kind": R.RDIST_QUERY_D, "n": n,
+              "info": R.PinnedInfo(1), "D": torch.empty((n, n), dtype=torch.int16, pin_memory=True)}
+        items.append(it)
+    srv = R.Server(ctx, slots=1, hbm_budget=0, max_batch=64)
+    run_server(srv, items)
+    st = srv.stats()
+    srv.close()
+    note(f"[server] backlog stats {st}")
+    assert st["completed"] == len(items) and st["batches"] == 1 and st["batched_requests"] == len(items), st
+    for it in items:
+        D, status, paths = alone(ctx, it)
+        assert it["info"].get(0).status == status == 0
+        if it["kind"] == R.RDIST_QUERY_D:
+            assert np.array_equal(it["D"].numpy(), D.cpu().numpy()), f"request {it['id']} n={it['n']}"
+        else:
+            assert np.array_equal(it["paths"].numpy(), paths.cpu().numpy()), f"request {it['id']} paths"
+
+
 def test_server_reports_small_requests_of_a_batch_first(ctx):
-    """One batch holding a large graph and small ones: requests are reported
+    """One batch holding a larger graph and small ones: requests are reported
     group by group (n <= 128 first, then by ceil(n / 128)), and every result
-    still equals the request solved alone."""
+    still equals the request solved alone.  (Sizes up to 1024: with this few
+    requests waiting, larger ones would run alone.)"""
     items = []
-    sizes = [4000, 70, 300, 1000, 100, 2000, 64]
+    sizes = [1000, 70, 300, 900, 100, 600, 64]
     for k, n in enumerate(sizes):
         A = gg.erdos_renyi(n, min(1.0, 8.0 / n), gg.rng_for("parity", 9300 + k))
         kind = R.RDIST_QUERY_PATHS if k % 2 else R.RDIST_QUERY_D
