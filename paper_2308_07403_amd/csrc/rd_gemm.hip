@@ -204,17 +204,28 @@ struct AccB {
     f32x16 v[4][4];
 };
 
+// Position of piece c (k0 + 8c .. k0 + 8c + 7) of row r within the row:
+// c ^ swz(r), swz(r) = (r & 7) ^ ((r >> 3) & 1).  A fragment load reads one
+// piece of 32 consecutive rows (16 bytes per lane); every 8 consecutive rows
+// aligned to 8 then sit in distinct 16-byte slots of a 128-byte bank window,
+// and every 16 aligned to 16 in distinct slots of a 256-byte one, so the
+// load is free of bank conflicts whether the LDS serves 8 lanes over 32
+// banks or 16 lanes over 64 banks per cycle.  (With swz(r) = r & 7 the
+// second case conflicts two ways on gfx950: SQ_LDS_BANK_CONFLICT was 4 cycles
+// per LDS instruction, now 0; the C4 correction went 27.1 -> 26.6 ms, its
+// chunk loads, not the LDS, being what holds it back.)
+__device__ __forceinline__ int swzb(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
 // Wave w copies rows 64w .. 64w+63 of both operands' chunk at k0, eight rows
-// per instruction.  Piece c (k0 + 8c .. k0 + 8c + 7) of row r is stored at
-// position c ^ (r & 7) of the row, so that the rows a fragment load touches
-// at one piece index fall into distinct LDS banks.
+// per instruction, each piece to its swizzled position.
 __device__ __forceinline__ void dmab(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, int K, int k0,
                                      char *As, char *Bs) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int rr = lane >> 3, c = (lane & 7) ^ rr;
+    const int rr = lane >> 3;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int r0 = w * 64 + q * 8;
+        const int c = (lane & 7) ^ swzb(r0 + rr);   // the piece that belongs at slot lane & 7
         __builtin_amdgcn_global_load_lds((global_cvoid *)(A + (size_t)(r0 + rr) * K + k0 + 8 * c),
                                          (lds_void *)(As + r0 * kRowB), 16, 0, 0);
         __builtin_amdgcn_global_load_lds((global_cvoid *)(B + (size_t)(r0 + rr) * K + k0 + 8 * c),
@@ -223,26 +234,38 @@ __device__ __forceinline__ void dmab(const uint16_t *__restrict__ A, const uint1
 }
 
 __device__ __forceinline__ bf16x8 frag_b(const char *S, int row, int c) {
-    return *reinterpret_cast<const bf16x8 *>(S + row * kRowB + ((c ^ (row & 7)) << 4));
+    return *reinterpret_cast<const bf16x8 *>(S + row * kRowB + ((c ^ swzb(row)) << 4));
 }
 
 // One chunk: 4 k-steps of 16; lane l reads k 8 (l / 32) .. +7 of its step.
+// The next step's eight fragments are read while this step's 16 MFMAs run
+// (two fragment sets, 64 VGPRs); the scheduling barriers keep the compiler
+// from sinking each read to just before its first use, which left the
+// matrix cores idle for an LDS round trip every four MFMAs (C4 correction
+// 26.6 -> 26.4 ms).
 __device__ __forceinline__ void mmab_chunk(const char *As, const char *Bs, AccB &acc) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int mr = (w >> 1) * 128 + (lane & 31), nr = (w & 1) * 128 + (lane & 31), half = lane >> 5;
+    bf16x8 a[2][4], b[2][4];
+    auto frags = [&](int st, bf16x8 *af, bf16x8 *bf) {
+        const int c = 2 * st + half;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) af[p] = frag_b(As, mr + 32 * p, c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bf[q] = frag_b(Bs, nr + 32 * q, c);
+    };
+    frags(0, a[0], b[0]);
 #pragma unroll
     for (int st = 0; st < kKCb / 16; ++st) {
-        const int c = 2 * st + half;
-        bf16x8 a[4], b[4];
-#pragma unroll
-        for (int p = 0; p < 4; ++p) a[p] = frag_b(As, mr + 32 * p, c);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = frag_b(Bs, nr + 32 * q, c);
+        const int cur = st & 1;
+        if (st + 1 < kKCb / 16) frags(st + 1, a[cur ^ 1], b[cur ^ 1]);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                acc.v[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[p], b[q], acc.v[p][q], 0, 0, 0);
+                acc.v[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cur][p], b[cur][q], acc.v[p][q], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
