@@ -735,6 +735,27 @@ def test_batched_level_matches_single_blocked_d(ctx):
         graphs[k].release()
 
 
+def test_level_panel_trimming_matches_single_plan(ctx):
+    """The level plan eliminates only a graph's real pivots in its last block
+    (the blocked panel skips 32-pivot sub-steps that are all padding and
+    rounds an odd count up to the next identity pivot); the single-graph plan
+    runs all 128.  Last-block pivot counts 1, 2, 31, 32, 33, 64, 65, 97 and
+    127, with two, three and four blocks: D and Y bit for bit against the
+    single-graph plan, and the batch against the oracle."""
+    sizes = [129, 130, 159, 160, 161, 192, 193, 225, 255, 257, 287, 320, 383, 385, 449]
+    A_np = [gg.erdos_renyi(n, min(1.0, 10.0 / n), gg.rng_for("parity", 8800 + k)) for k, n in enumerate(sizes)]
+    Ds, info, graphs = ctx.solve_batched([dev(A) for A in A_np], -0.5, keep=True)
+    check_batch(A_np, -0.5, Ds, info, graphs, "last-block pivots")
+    for k, A in enumerate(A_np):
+        D1, inf1, g1 = ctx.solve(dev(A), -0.5, keep=True)
+        assert info.get(k).status == inf1["status"] == 0
+        assert torch.equal(Ds[k], D1), f"n={A.shape[0]}"
+        assert torch.equal(graphs[k].y(), g1.y()), f"n={A.shape[0]}: Y differs from the single-graph plan's"
+        g1.release()
+    for g in graphs:
+        g.release()
+
+
 # ---------------------------------------------------------------------------
 # Full sizes (the bench's launch configuration): sampled rows and columns of Y
 # from the oracle's series, one by one; closed forms at any size
