@@ -32,9 +32,11 @@ namespace rd {
 //      ks takes V as its rows.
 // This is the blocked Gauss-Jordan step of the whole solve with width 32
 // inside the panel.  Its pivots are those of the unblocked elimination
-// (Schur complement diagonals), each checked positive.  The latency-bound
-// pivot loop touches 32 x 32 entries instead of 128 x 128; 75% of the flops
-// run as rank-32 products on v_mfma_f64_16x16x4f64.
+// (Schur complement diagonals), each checked positive.  The serial pivot
+// loop (one wave, VALU-issue bound) touches 32 x 32 entries instead of
+// 128 x 128; of the 2 * 128^3 flops, 94% run on v_mfma_f64_16x16x4f64 (per
+// sub-step 2 * 32^3 in the pivot loop, 2 * 3 * 32^3 in the row block and
+// 2 * 3 * 32^2 * 128 in the update).
 // ---------------------------------------------------------------------------
 constexpr int kPanS = 136;   // row stride (doubles) of the published strip
 constexpr int kPanU = 33;    // row stride of the 32 x 32 blocks in LDS

@@ -333,7 +333,7 @@ void pump(rdist_server s) {
         if (k < 0) return;
         std::vector<Pending> batch;
         size_t f = 0;
-        // With few requests waiting, one with n > 2048 runs alone on the
+        // With few requests waiting, one with n > 1024 runs alone on the
         // single-graph plan (latency); with a backlog it joins the batch,
         // whose level plan runs many large graphs at once (throughput).
         const bool split = s->queue.size() <= kLoneMaxQueue;
