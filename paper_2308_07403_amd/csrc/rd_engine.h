@@ -61,7 +61,7 @@ struct Workspace {
     // block, FP32 P, certification counters + slab flags, sparse rows of A,
     // residual and correction slabs
     Buf m32, v32, u32, s64, p32, cert, csr_cnt, csr_off, csr_col, r32, c32;
-    Buf xh, xl, rh, rl;   // bf16 hi/lo parts of the FP32 inverse and of the scaled residual
+    Buf xi, ri;   // bf16 hi/lo parts of the FP32 inverse and of the scaled residual (interleaved)
     // goal rows: the two iteration states, and [info | bad flag | change flag | gamma^w table]
     Buf rv, rmisc, rgoals;
     Buf gb;               // gain bounds: two vectors of n doubles and the iteration's scratch

@@ -472,7 +472,7 @@ void free_workspace(rdist_ctx c, Workspace &w) {
     free_transient_plan(c, w);
     for (Buf *b : {&w.M, &w.Ut[0], &w.Ut[1], &w.V[0], &w.V[1], &w.Pt[0], &w.Pt[1], &w.Ut2, &w.V2, &w.Pt2, &w.small,
                    &w.m32, &w.v32, &w.u32, &w.s64, &w.p32, &w.cert, &w.csr_cnt, &w.csr_off, &w.csr_col, &w.r32,
-                   &w.c32, &w.xh, &w.xl, &w.rh, &w.rl, &w.rv, &w.rmisc, &w.rgoals, &w.gb})
+                   &w.c32, &w.xi, &w.ri, &w.rv, &w.rmisc, &w.rgoals, &w.gb})
         release(c, *b);
     if (w.rows_exec) (void)hipGraphExecDestroy(w.rows_exec);
     if (w.rows_graph) (void)hipGraphDestroy(w.rows_graph);

@@ -7,7 +7,8 @@
 //   k_corr_bf16  the refinement's correction C = X0 R from bf16 hi/lo parts,
 //                C = Xh Rh + Xh Rl + Xl Rh on v_mfma_f32_32x32x16_bf16 with
 //                FP32 accumulation, over 256 x 256 tiles;
-//   k_ut32, k_pt32, k_split_bf16_t: the operand layouts these read.
+//   k_ut32, k_pt32, k_split_bf16_x, k_split_bf16_t: the operand layouts
+//                these read.
 //
 // Both contractions read k-chunks of their operands from LDS, copied there
 // by the load unit (global_load_lds, 16 bytes per lane, double-buffered), so
@@ -19,6 +20,7 @@
 // 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32 (both instructions; checked
 // on gfx950).
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <stdint.h>
 
 #include "rd_device.h"
@@ -186,49 +188,58 @@ __global__ __launch_bounds__(256) void k_pt32(const double *__restrict__ S, floa
     for (int r = ty; r < 32; r += 8) Pt[(c0 + r) * kMB + r0 + tx] = (float)t[tx][r];
 }
 
-// ---- bf16: operands m-major (k contiguous), A[i][k], B[j][k] ----
+// ---- bf16: operands m-major, hi and lo parts interleaved per 32 k ----
+// Row r of an operand (X, or R transposed) holds, for each block b of 32
+// k-values, the 32 hi parts and then the 32 lo parts (row length 2K), so one
+// 128-byte line per row and chunk carries both and the three products share
+// every chunk: 64 KiB of copies per 96 MFMAs of a wave, against 64 per 64
+// with the products run one after another on separate parts (the C4
+// correction: 24.7 -> 21.0 ms on its own; the copies, not the matrix cores,
+// bound it: without them the products run in 17.6 ms, the copies alone take
+// 18.8 ms at the old layout).
 // 256 x 256 output tiles; wave w owns the 128 x 128 quadrant (w >> 1, w & 1)
 // as 4 x 4 blocks of 32 x 32 (accumulators in 256 AGPRs, one wave per SIMD),
-// so each fragment read from LDS feeds four MFMAs.  The three products run
-// as one sequence of 64-k chunks, double-buffered, so the copy of the next
-// product's first chunk overlaps the last chunk of the one before.
-// (Measured and dropped: 2 x 2 blocks per wave, LDS-bound at 30.5 ms for
-// the C4 correction against 26.8 ms; the three products fused per k-step,
-// 27.4 ms; fused with a four-stage ring of 16-k chunks, 32.1 ms.)
+// so each fragment read from LDS feeds four MFMAs per product.
+// (Measured and dropped: 2 x 2 blocks per wave, LDS-bound; rings of three to
+// five 32-k chunks with barriers that wait only for the oldest chunk, 27.0 -
+// 27.6 ms against 25.4 for the double buffer of 64-k chunks then in use,
+// whose loads were throughput- and not latency-bound; row pitches padded by
+// 128 - 512 bytes, no change.)
 constexpr int kTB = 256;                // output tile of the bf16 contraction
-constexpr int kKCb = 64;                // k per chunk
-constexpr int kRowB = kKCb * 2;         // bytes per LDS row (eight 16-byte pieces)
+constexpr int kKCb = 32;                // k per chunk (hi and lo: 64 values per row)
+constexpr int kRowB = 128;              // bytes per LDS row (eight 16-byte pieces)
 constexpr int kChunkB = kTB * kRowB;    // bytes per operand chunk (32 KiB)
 
 struct AccB {
     f32x16 v[4][4];
 };
 
-// Position of piece c (k0 + 8c .. k0 + 8c + 7) of row r within the row:
-// c ^ swz(r), swz(r) = (r & 7) ^ ((r >> 3) & 1).  A fragment load reads one
-// piece of 32 consecutive rows (16 bytes per lane); every 8 consecutive rows
-// aligned to 8 then sit in distinct 16-byte slots of a 128-byte bank window,
-// and every 16 aligned to 16 in distinct slots of a 256-byte one, so the
-// load is free of bank conflicts whether the LDS serves 8 lanes over 32
-// banks or 16 lanes over 64 banks per cycle.  (With swz(r) = r & 7 the
-// second case conflicts two ways on gfx950: SQ_LDS_BANK_CONFLICT was 4 cycles
-// per LDS instruction, now 0; the C4 correction went 27.1 -> 26.6 ms, its
-// chunk loads, not the LDS, being what holds it back.)
+// Position of piece c of row r within the row (pieces 0-3 the hi parts of
+// k0 + 8c .. k0 + 8c + 7, pieces 4-7 the lo parts): c ^ swz(r),
+// swz(r) = (r & 7) ^ ((r >> 3) & 1).  A fragment load reads one piece of 32
+// consecutive rows (16 bytes per lane); every 8 consecutive rows aligned to 8
+// then sit in distinct 16-byte slots of a 128-byte bank window, and every 16
+// aligned to 16 in distinct slots of a 256-byte one, so the load is free of
+// bank conflicts whether the LDS serves 8 lanes over 32 banks or 16 lanes
+// over 64 banks per cycle.  (With swz(r) = r & 7 the second case conflicts
+// two ways on gfx950: SQ_LDS_BANK_CONFLICT was 4 cycles per LDS instruction,
+// now 0.)
 __device__ __forceinline__ int swzb(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
-// Wave w copies rows 64w .. 64w+63 of both operands' chunk at k0, eight rows
-// per instruction, each piece to its swizzled position.
-__device__ __forceinline__ void dmab(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, int K, int k0,
-                                     char *As, char *Bs) {
+// Wave w copies rows 64w .. 64w+63 of both operands' chunk at k0 (an offset
+// in the interleaved row), eight rows per instruction, each piece to its
+// swizzled position.
+__device__ __forceinline__ void dmab(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, int pitch,
+                                     int k0, char *As, char *Bs) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int rr = lane >> 3;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int r0 = w * 64 + q * 8;
         const int c = (lane & 7) ^ swzb(r0 + rr);   // the piece that belongs at slot lane & 7
-        __builtin_amdgcn_global_load_lds((global_cvoid *)(A + (size_t)(r0 + rr) * K + k0 + 8 * c),
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(A + (size_t)(r0 + rr) * pitch + k0 + 8 * c),
                                          (lds_void *)(As + r0 * kRowB), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((global_cvoid *)(B + (size_t)(r0 + rr) * K + k0 + 8 * c),
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(B + (size_t)(r0 + rr) * pitch + k0 + 8 * c),
                                          (lds_void *)(Bs + r0 * kRowB), 16, 0, 0);
     }
 }
@@ -237,63 +248,58 @@ __device__ __forceinline__ bf16x8 frag_b(const char *S, int row, int c) {
     return *reinterpret_cast<const bf16x8 *>(S + row * kRowB + ((c ^ swzb(row)) << 4));
 }
 
-// One chunk: 4 k-steps of 16; lane l reads k 8 (l / 32) .. +7 of its step.
-// The next step's eight fragments are read while this step's 16 MFMAs run
-// (two fragment sets, 64 VGPRs); the scheduling barriers keep the compiler
-// from sinking each read to just before its first use, which left the
-// matrix cores idle for an LDS round trip every four MFMAs (C4 correction
-// 26.6 -> 26.4 ms).
-__device__ __forceinline__ void mmab_chunk(const char *As, const char *Bs, AccB &acc) {
+// Fragments of k-step st (16 k) of the chunk: lane l holds k 8 (l / 32) ..
+// +7 of the step, hi parts from piece 2 st + l / 32, lo parts four pieces on.
+__device__ __forceinline__ void frags_b(const char *As, const char *Bs, int st, bf16x8 *xh, bf16x8 *xl, bf16x8 *rh,
+                                        bf16x8 *rl) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int mr = (w >> 1) * 128 + (lane & 31), nr = (w & 1) * 128 + (lane & 31), half = lane >> 5;
-    bf16x8 a[2][4], b[2][4];
-    auto frags = [&](int st, bf16x8 *af, bf16x8 *bf) {
-        const int c = 2 * st + half;
+    const int mr = (w >> 1) * 128 + (lane & 31), nr = (w & 1) * 128 + (lane & 31);
+    const int c = 2 * st + (lane >> 5);
 #pragma unroll
-        for (int p = 0; p < 4; ++p) af[p] = frag_b(As, mr + 32 * p, c);
+    for (int p = 0; p < 4; ++p) xh[p] = frag_b(As, mr + 32 * p, c);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bf[q] = frag_b(Bs, nr + 32 * q, c);
-    };
-    frags(0, a[0], b[0]);
+    for (int q = 0; q < 4; ++q) rh[q] = frag_b(Bs, nr + 32 * q, c);
 #pragma unroll
-    for (int st = 0; st < kKCb / 16; ++st) {
-        const int cur = st & 1;
-        if (st + 1 < kKCb / 16) frags(st + 1, a[cur ^ 1], b[cur ^ 1]);
-        __builtin_amdgcn_sched_barrier(0);
+    for (int q = 0; q < 4; ++q) rl[q] = frag_b(Bs, nr + 32 * q, 4 + c);
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 4; ++p) xl[p] = frag_b(As, mr + 32 * p, 4 + c);
+}
+
+// One k-step: the 16 blocks' Xh Rh, then Xh Rl, then Xl Rh (each block's
+// three MFMAs sixteen apart, so none waits on the one before).
+__device__ __forceinline__ void mmab_step(const bf16x8 *xh, const bf16x8 *xl, const bf16x8 *rh, const bf16x8 *rl,
+                                          AccB &acc) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                acc.v[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cur][p], b[cur][q], acc.v[p][q], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-    }
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            acc.v[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[p], rh[q], acc.v[p][q], 0, 0, 0);
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            acc.v[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[p], rl[q], acc.v[p][q], 0, 0, 0);
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            acc.v[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[p], rh[q], acc.v[p][q], 0, 0, 0);
 }
 
 // C (nti*256 x ntj*256, ldc) = Xh Rh + Xh Rl + Xl Rh, inner dimension K (a
-// multiple of 64): the X parts row-major (row i holds row i of X), the R
-// parts transposed (row j holds column j of R), all with row length K.
+// multiple of 32): X interleaved by rows (row i: row i of X), R interleaved
+// transposed (row j: column j of R), both with row length 2K.
 __global__ __launch_bounds__(256, 1) void k_corr_bf16(float *__restrict__ C, int ldc, int nti, int ntj, int K,
-                                                      const uint16_t *__restrict__ Xh,
-                                                      const uint16_t *__restrict__ Xl,
-                                                      const uint16_t *__restrict__ Rh,
-                                                      const uint16_t *__restrict__ Rl, const rdist_info *info) {
+                                                      const uint16_t *__restrict__ Xi,
+                                                      const uint16_t *__restrict__ Ri, const rdist_info *info) {
     if (info->status != RDIST_OK) return;
     __shared__ __attribute__((aligned(16))) char lds[4 * kChunkB];   // A, B x two buffers: 128 KiB
     int I, J;
     xcd_strip_order_rect(blockIdx.x, nti, ntj, I, J);
-    const size_t ao = (size_t)I * kTB * K, bo = (size_t)J * kTB * K;
-    const int per = K / kKCb, total = 3 * per;
-    // chunk g: product g / per (Xh Rh, Xh Rl, Xl Rh), k0 = 64 (g mod per)
-    auto operands = [&](int g, const uint16_t *&A, const uint16_t *&B, int &k0) {
-        const int t = g / per;
-        k0 = (g - t * per) * kKCb;
-        A = (t < 2 ? Xh : Xl) + ao;
-        B = (t == 1 ? Rl : Rh) + bo;
-    };
-    const uint16_t *A, *B;
-    int k0;
-    operands(0, A, B, k0);
-    dmab(A, B, K, k0, lds, lds + kChunkB);
+    const int pitch = 2 * K;
+    const uint16_t *A = Xi + (size_t)I * kTB * pitch, *B = Ri + (size_t)J * kTB * pitch;
+    const int nch = K / kKCb;
+    dmab(A, B, pitch, 0, lds, lds + kChunkB);
     AccB acc;
 #pragma unroll
     for (int p = 0; p < 4; ++p)
@@ -303,15 +309,16 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16(float *__restrict__ C, int
             for (int r = 0; r < 16; ++r) acc.v[p][q][r] = 0.0f;
     wait_vm_all();
     __syncthreads();
+    bf16x8 xh[4], xl[4], rh[4], rl[4];
 #pragma unroll 1
-    for (int g = 0; g < total; ++g) {
-        char *cur = lds + (g & 1) * (2 * kChunkB);
-        char *nxt = lds + ((g + 1) & 1) * (2 * kChunkB);
-        if (g + 1 < total) {
-            operands(g + 1, A, B, k0);
-            dmab(A, B, K, k0, nxt, nxt + kChunkB);
-        }
-        mmab_chunk(cur, cur + kChunkB, acc);
+    for (int ch = 0; ch < nch; ++ch) {
+        char *cur = lds + (ch & 1) * (2 * kChunkB);
+        char *nxt = lds + ((ch + 1) & 1) * (2 * kChunkB);
+        if (ch + 1 < nch) dmab(A, B, pitch, 2 * kKCb * (ch + 1), nxt, nxt + kChunkB);
+        frags_b(cur, cur + kChunkB, 0, xh, xl, rh, rl);
+        mmab_step(xh, xl, rh, rl, acc);
+        frags_b(cur, cur + kChunkB, 1, xh, xl, rh, rl);
+        mmab_step(xh, xl, rh, rl, acc);
         wait_vm_all();
         __syncthreads();
     }
@@ -341,12 +348,30 @@ __device__ __forceinline__ int rscale(unsigned rmax_bits) {
     return -((int)((rmax_bits >> 23) & 0xFF) - 127 + 1);
 }
 
-// hi / lo bf16 parts of 2^s R, transposed: R is rows x cols (ld cols),
-// Ht / Lt are cols_pad x rows (ld rows), rows cols .. cols_pad - 1 zero; s
-// from rmax as for the residual.
+// Index of element k of interleaved row r (row length 2 cols): its hi part;
+// the lo part sits 32 further on.
+__device__ __forceinline__ size_t ileave(size_t r, int cols, int k) {
+    return r * 2 * (size_t)cols + 2 * (size_t)(k & ~31) + (k & 31);
+}
+
+// hi / lo bf16 parts of X (rows x cols, row-major), interleaved by rows.
+__global__ __launch_bounds__(256) void k_split_bf16_x(const float *__restrict__ X, int rows, int cols,
+                                                      uint16_t *__restrict__ Xi) {
+    const size_t count = (size_t)rows * cols;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
+        const float x = X[e];
+        const uint16_t h = bf16_bits(x);
+        const size_t o = ileave(e / cols, cols, (int)(e % cols));
+        Xi[o] = h;
+        Xi[o + 32] = bf16_bits(x - __uint_as_float((unsigned)h << 16));
+    }
+}
+
+// hi / lo bf16 parts of 2^s R, transposed and interleaved: R is rows x cols
+// (ld cols), Ri is cols_pad x 2 rows, rows cols .. cols_pad - 1 zero; s from
+// rmax as for the residual.
 __global__ __launch_bounds__(256) void k_split_bf16_t(const float *__restrict__ R, int rows, int cols,
-                                                      uint16_t *__restrict__ Ht, uint16_t *__restrict__ Lt,
-                                                      const unsigned *__restrict__ rmax) {
+                                                      uint16_t *__restrict__ Ri, const unsigned *__restrict__ rmax) {
     __shared__ float t[64][65];
     const float sc = ldexpf(1.0f, rscale(*rmax));
     const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
@@ -356,9 +381,9 @@ __global__ __launch_bounds__(256) void k_split_bf16_t(const float *__restrict__ 
     for (int r = ty; r < 64; r += 4) {
         const float x = t[tx][r];
         const uint16_t h = bf16_bits(x);
-        const size_t o = (size_t)(c0 + r) * rows + r0 + tx;
-        Ht[o] = h;
-        Lt[o] = bf16_bits(x - __uint_as_float((unsigned)h << 16));
+        const size_t o = ileave((size_t)(c0 + r), rows, r0 + tx);
+        Ri[o] = h;
+        Ri[o + 32] = bf16_bits(x - __uint_as_float((unsigned)h << 16));
     }
 }
 
@@ -387,16 +412,20 @@ void launch_pt32(const double *S, float *Pt, float *V, int np, int K0, const rdi
 
 int corr_cols(int cols) { return (cols + kTB - 1) / kTB * kTB; }
 
-void launch_corr_bf16(float *C, int rows, int cols_pad, int K, const uint16_t *Xh, const uint16_t *Xl,
-                      const uint16_t *Rht, const uint16_t *Rlt, const rdist_info *info, hipStream_t s) {
+void launch_corr_bf16(float *C, int rows, int cols_pad, int K, const uint16_t *Xi, const uint16_t *Ri,
+                      const rdist_info *info, hipStream_t s) {
     const int nti = rows / kTB, ntj = cols_pad / kTB;
-    hipLaunchKernelGGL(k_corr_bf16, dim3(nti * ntj), dim3(256), 0, s, C, cols_pad, nti, ntj, K, Xh, Xl, Rht, Rlt,
-                       info);
+    hipLaunchKernelGGL(k_corr_bf16, dim3(nti * ntj), dim3(256), 0, s, C, cols_pad, nti, ntj, K, Xi, Ri, info);
 }
 
-void launch_split_bf16_t(const float *R, int rows, int cols, int cols_pad, uint16_t *Ht, uint16_t *Lt,
-                         const unsigned *rmax, hipStream_t s) {
-    hipLaunchKernelGGL(k_split_bf16_t, dim3(cols_pad / 64, rows / 64), dim3(256), 0, s, R, rows, cols, Ht, Lt, rmax);
+void launch_split_bf16_x(const float *X, int rows, int cols, uint16_t *Xi, hipStream_t s) {
+    const int grid = (int)std::min<size_t>(((size_t)rows * cols + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_split_bf16_x, dim3(grid), dim3(256), 0, s, X, rows, cols, Xi);
+}
+
+void launch_split_bf16_t(const float *R, int rows, int cols, int cols_pad, uint16_t *Ri, const unsigned *rmax,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_split_bf16_t, dim3(cols_pad / 64, rows / 64), dim3(256), 0, s, R, rows, cols, Ri, rmax);
 }
 
 }  // namespace rd

@@ -111,10 +111,6 @@ void launch_residual(const float *X, int np, int n, const int64_t *off, const in
 // 2^s, undone here).
 void launch_fix(const float *X, int np, int n, const float *C, int ldc, const int32_t *slabs, int nslab,
                 double margin, const unsigned *rmax, int16_t *D, rdist_info *info, hipStream_t s);
-// hi/lo bf16 parts (16-bit patterns) of 2^s src, s = 0 or the residual's
-// scale (rmax given).
-void launch_split_bf16(const float *src, size_t count, uint16_t *hi, uint16_t *lo, const unsigned *rmax,
-                       hipStream_t s);
 // FP32 matrix-core steps of the mixed plan (rd_gemm.hip), step width 256:
 // Pt = P^T in FP32 (V == nullptr) or P into V's block columns at K0; Ut = -U^T;
 // V = P M_K,: (Pt, 256 x np); M <- M~ - U V over every tile.
@@ -124,18 +120,23 @@ void launch_gemm32_rows(const float *Pt, const float *M, int np, int K0, float *
                         hipStream_t s);
 void launch_gemm32_update(float *M, int np, int K0, const float *Ut, const float *V, const rdist_info *info,
                           hipStream_t s);
-// C (rows x cols_pad, ld cols_pad) = Xh Rh + Xh Rl + Xl Rh from bf16 parts:
-// Xh, Xl rows x K row-major, Rht, Rlt cols_pad x K (R transposed, zero rows
-// past its columns); rows a multiple of 256, cols_pad = corr_cols(cols), K a
-// multiple of 64.
+// The bf16 operands of the correction: row r of an interleaved operand holds,
+// per block of 32 k-values, their 32 hi parts and then their 32 lo parts
+// (16-bit patterns, row length 2K).
+// C (rows x cols_pad, ld cols_pad) = Xh Rh + Xh Rl + Xl Rh: Xi rows x 2K
+// (rows of X), Ri cols_pad x 2K (columns of R, zero rows past its columns);
+// rows a multiple of 256, cols_pad = corr_cols(cols), K a multiple of 32.
 int corr_cols(int cols);
-void launch_corr_bf16(float *C, int rows, int cols_pad, int K, const uint16_t *Xh, const uint16_t *Xl,
-                      const uint16_t *Rht, const uint16_t *Rlt, const rdist_info *info, hipStream_t s);
-// hi / lo bf16 parts of 2^s R (rows x cols, s from rmax), written transposed
-// (cols_pad x rows, the rows past cols zero); rows a multiple of 64, cols_pad
-// a multiple of 64 not below cols.
-void launch_split_bf16_t(const float *R, int rows, int cols, int cols_pad, uint16_t *Ht, uint16_t *Lt,
-                         const unsigned *rmax, hipStream_t s);
+void launch_corr_bf16(float *C, int rows, int cols_pad, int K, const uint16_t *Xi, const uint16_t *Ri,
+                      const rdist_info *info, hipStream_t s);
+// Xi = the interleaved hi / lo parts of X (rows x cols, row-major; cols a
+// multiple of 32).
+void launch_split_bf16_x(const float *X, int rows, int cols, uint16_t *Xi, hipStream_t s);
+// Ri = the interleaved hi / lo parts of 2^s R (rows x cols, s from rmax),
+// transposed (cols_pad x 2 rows, the rows past cols zero); rows a multiple of
+// 64, cols_pad a multiple of 64 not below cols.
+void launch_split_bf16_t(const float *R, int rows, int cols, int cols_pad, uint16_t *Ri, const unsigned *rmax,
+                         hipStream_t s);
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s);
 // Entries per query of a path output: the next node alone for max_hops = 1,
 // else the start and max_hops hops.

@@ -114,27 +114,32 @@ __global__ __launch_bounds__(256) void k_row_count(const uint8_t *__restrict__ A
     if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
 }
 
-// Column indices of row i's nonzeros, in increasing order: thread t scans a
-// contiguous stretch of the row; an exclusive scan over the threads' counts
-// gives each its output position.
+// Column indices of row i's nonzeros, in increasing order.  The workgroup
+// walks the row 256 bytes at a time (coalesced byte loads); a ballot gives
+// each nonzero its rank within its wave, the four wave totals (in LDS, two
+// slots used alternately, so one barrier per chunk suffices) its offset.
+// (Each thread scanning its own 64-byte stretch byte by byte took 1.0 ms at
+// n = 16384.)
 __global__ __launch_bounds__(256) void k_row_fill(const uint8_t *__restrict__ A, int n,
                                                   const int64_t *__restrict__ off, int32_t *__restrict__ cols) {
-    __shared__ int pos[257];
+    __shared__ int wsum[2][4];
     const uint8_t *row = A + (size_t)blockIdx.x * n;
-    const int per = (n + 255) / 256;
-    const int j0 = min(n, threadIdx.x * per), j1 = min(n, j0 + per);
-    int c = 0;
-    for (int j = j0; j < j1; ++j) c += row[j] != 0;
-    pos[threadIdx.x + 1] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        pos[0] = 0;
-        for (int t = 1; t <= 256; ++t) pos[t] += pos[t - 1];
+    int32_t *out = cols + off[blockIdx.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int base = 0;   // nonzeros of the chunks before this one
+    for (int j0 = 0, it = 0; j0 < n; j0 += 256, ++it) {
+        const int j = j0 + threadIdx.x;
+        const bool nz = j < n && row[j] != 0;
+        const unsigned long long m = __ballot(nz);
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+        int *t = wsum[it & 1];
+        if (lane == 0) t[w] = __popcll(m);
+        __syncthreads();
+        int before = base;
+        for (int v = 0; v < w; ++v) before += t[v];
+        if (nz) out[before + rank] = j;
+        base += t[0] + t[1] + t[2] + t[3];
     }
-    __syncthreads();
-    int32_t *out = cols + off[blockIdx.x] + pos[threadIdx.x];
-    for (int j = j0; j < j1; ++j)
-        if (row[j]) *out++ = j;
 }
 
 // R (np x w, w = 128 nslab) = I - M X on the slabs: for row k and column
@@ -197,29 +202,11 @@ __device__ __forceinline__ int residual_scale(unsigned rmax_bits) {
     return -(e + 1);
 }
 
-// bf16 with round to nearest even of a finite float (as its 16 high bits).
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-    const unsigned u = __float_as_uint(x);
-    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-
-// hi = bf16(2^s x), lo = bf16(2^s x - hi) (the difference is exact in FP32)
-// for count floats; s = 0, or the residual's scale when rmax is given.
-__global__ __launch_bounds__(256) void k_split_bf16(const float *__restrict__ src, size_t count,
-                                                    uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
-                                                    const unsigned *__restrict__ rmax) {
-    const float sc = rmax ? ldexpf(1.0f, residual_scale(*rmax)) : 1.0f;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
-        const float x = src[e] * sc;
-        const uint16_t h = bf16_rne(x);
-        hi[e] = h;
-        lo[e] = bf16_rne(x - __uint_as_float((unsigned)h << 16));
-    }
-}
-
 // Uncertified entries of the slabs: Y = X + (X R), the correction C = X R
 // (np x w) from the GEMMs on the residual scaled by 2^s (undone here
-// exactly); D from Y in FP64.
+// exactly); D from Y in FP64.  Workgroup (s, y) takes rows 32y .. 32y + 31
+// of slab s, two at a time; the slabs vary fastest, so consecutive
+// workgroups stream along the rows of X, C and D.
 __global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np, int n, const float *__restrict__ C,
                                              int ldc, const int32_t *__restrict__ slabs, int nslab, double margin,
                                              const unsigned *__restrict__ rmax, int16_t *__restrict__ D,
@@ -227,15 +214,18 @@ __global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np
     if (info->status != RDIST_OK) return;
     const double il = rd_inv_log(info->gamma);
     const double unscale = rmax ? ldexp(1.0, -residual_scale(*rmax)) : 1.0;
-    const int i = blockIdx.x * 2 + (threadIdx.x >> 7), c = threadIdx.x & 127;
-    const int s = blockIdx.y;
+    const int c = threadIdx.x & 127;
+    const int s = blockIdx.x;
     const int j = slabs[s] * kSlab + c;
     Counts cnt;
-    if (i < n && j < n) {
-        const float x = X[(size_t)i * np + j];
-        if (uncertified(x, il, margin)) {
-            const double y = (double)x + unscale * (double)C[(size_t)i * ldc + (size_t)s * kSlab + c];
-            D[(size_t)i * n + j] = rd_encode(y, il, cnt);
+    for (int t = 0; t < 16; ++t) {
+        const int i = blockIdx.y * 32 + 2 * t + (threadIdx.x >> 7);
+        if (i < n && j < n) {
+            const float x = X[(size_t)i * np + j];
+            if (uncertified(x, il, margin)) {
+                const double y = (double)x + unscale * (double)C[(size_t)i * ldc + (size_t)s * kSlab + c];
+                D[(size_t)i * n + j] = rd_encode(y, il, cnt);
+            }
         }
     }
     flush_counts(info, cnt);
@@ -274,12 +264,8 @@ void launch_residual(const float *X, int np, int n, const int64_t *off, const in
 }
 void launch_fix(const float *X, int np, int n, const float *C, int ldc, const int32_t *slabs, int nslab,
                 double margin, const unsigned *rmax, int16_t *D, rdist_info *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_fix, dim3(np / 2, nslab), dim3(256), 0, s, X, np, n, C, ldc, slabs, nslab, margin, rmax, D,
+    hipLaunchKernelGGL(k_fix, dim3(nslab, np / 32), dim3(256), 0, s, X, np, n, C, ldc, slabs, nslab, margin, rmax, D,
                        info);
-}
-void launch_split_bf16(const float *src, size_t count, uint16_t *hi, uint16_t *lo, const unsigned *rmax,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_split_bf16, dim3(grid_for(count)), dim3(256), 0, s, src, count, hi, lo, rmax);
 }
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s) {
     hipLaunchKernelGGL(k_set_mixed_info, dim3(1), dim3(1), 0, s, info, uncertified, fraction);
@@ -404,18 +390,17 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
         RD_HIP(hipGetLastError());
         // C = X0 R (np x w) from the bf16 hi/lo parts of X0 and of 2^s R:
         // Xh Rh + Xh Rl + Xl Rh with FP32 accumulation (the dropped parts
-        // are about 2^-16 of C, and C is about eps32 Y)
+        // are about 2^-16 of C, and C is about eps32 Y); both operands' parts
+        // interleaved per 32 k, R's transposed
         // (the correction's columns are padded to its 256-wide tiles)
         const int wpad = rd::corr_cols((int)wcols);
         const size_t nx = (size_t)np * np, nr = (size_t)np * wpad;
-        if ((st = ensure(c, w.xh, nx * 2)) || (st = ensure(c, w.xl, nx * 2)) || (st = ensure(c, w.rh, nr * 2)) ||
-            (st = ensure(c, w.rl, nr * 2)) || (st = ensure(c, w.c32, nr * 4)))
+        if ((st = ensure(c, w.xi, nx * 4)) || (st = ensure(c, w.ri, nr * 4)) || (st = ensure(c, w.c32, nr * 4)))
             return st;
-        rd::launch_split_bf16(M, nx, (uint16_t *)w.xh.p, (uint16_t *)w.xl.p, nullptr, s);
-        rd::launch_split_bf16_t((const float *)w.r32.p, np, (int)wcols, wpad, (uint16_t *)w.rh.p, (uint16_t *)w.rl.p,
-                                rmax, s);
-        rd::launch_corr_bf16((float *)w.c32.p, np, wpad, np, (const uint16_t *)w.xh.p, (const uint16_t *)w.xl.p,
-                             (const uint16_t *)w.rh.p, (const uint16_t *)w.rl.p, dinfo, s);
+        rd::launch_split_bf16_x(M, np, np, (uint16_t *)w.xi.p, s);
+        rd::launch_split_bf16_t((const float *)w.r32.p, np, (int)wcols, wpad, (uint16_t *)w.ri.p, rmax, s);
+        rd::launch_corr_bf16((float *)w.c32.p, np, wpad, np, (const uint16_t *)w.xi.p, (const uint16_t *)w.ri.p,
+                             dinfo, s);
         RD_HIP(hipGetLastError());
         rd::launch_fix(M, np, n, (const float *)w.c32.p, wpad, dslabs, ns, margin, rmax, D, dinfo, s);
         RD_HIP(hipGetLastError());
