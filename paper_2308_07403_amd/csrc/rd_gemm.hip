@@ -7,8 +7,8 @@
 //   k_corr_bf16  the refinement's correction C = X0 R from bf16 hi/lo parts,
 //                C = Xh Rh + Xh Rl + Xl Rh on v_mfma_f32_32x32x16_bf16 with
 //                FP32 accumulation, over 256 x 256 tiles;
-//   k_ut32, k_pt32, k_split_bf16_x, k_split_bf16_t: the operand layouts
-//                these read.
+//   k_ut32, k_split_bf16_x, k_split_bf16_t: the operand layouts these
+//                read.
 //
 // Both contractions read k-chunks of their operands from LDS, copied there
 // by the load unit (global_load_lds, 16 bytes per lane, double-buffered), so
@@ -95,15 +95,40 @@ __device__ __forceinline__ void mma32_chunk(const float *As, const float *Bs, Ac
     }
 }
 
-// MODE 0 (row product): tile (I, J) = blockIdx.x as I * ntj + J, C = A_k^T B_k.
+// Ut (kMB x np, k-major) = -U^T for the step at column K0 of M (np x np):
+// Ut[k][i] = -M[i][K0 + k] for rows i outside the block, and the identity
+// (U's rows there are -I) for rows inside it.  64 x 64 pieces through LDS,
+// both sides coalesced.
+__global__ __launch_bounds__(256) void k_ut32(const float *__restrict__ M, int np, int K0, float *__restrict__ Ut,
+                                              const rdist_info *info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ float t[64][65];
+    const int i0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) t[r][tx] = M[(size_t)(i0 + r) * np + K0 + k0 + tx];
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int k = k0 + r, i = i0 + tx;
+        const bool in = i >= K0 && i < K0 + kMB;
+        Ut[(size_t)k * np + i] = in ? (i - K0 == k ? 1.0f : 0.0f) : -t[tx][r];
+    }
+}
+
+// MODE 0 (row product): tile (I, J) = blockIdx.x as I * ntj + J, C = A_k^T B_k,
+// except the tiles J in [zk0, zk0 + 2) (the step's block: its P is written
+// there by the block inverse).  (The step's Ut formed by extra workgroups of
+// this launch took 41 us against 26 + 13.5 us for the two launches.)
 // MODE 1 (trailing update): tiles of an ntj x ntj grid in XCD strip order,
 // C <- C~ + A_k^T B_k, where C~ is C with the tile rows and columns
-// [zk0, zk0 + 2) (the step's block) zeroed; A_k holds -U^T.
+// [zk0, zk0 + 2) (the step's block) zeroed; A_k holds -U^T.  The tiles of
+// the next block's diagonal (rows and columns [zk0 + 2, zk0 + 4)) also go to
+// Snext (256 x 256, FP64, exact), the input of its block inverse.
 // Inner dimension kMB (256).
 template <int MODE>
 __global__ __launch_bounds__(256, 4) void k_gemm32(float *__restrict__ C, int ldc, int ntj, int zk0,
                                                    const float *__restrict__ Ak, int lda,
-                                                   const float *__restrict__ Bk, int ldb, const rdist_info *info) {
+                                                   const float *__restrict__ Bk, int ldb, double *__restrict__ Snext,
+                                                   const rdist_info *info) {
     if (info->status != RDIST_OK) return;
     __shared__ float lds[4 * kChunk32];   // A, B x two buffers: 16 KiB
     int I, J;
@@ -112,6 +137,7 @@ __global__ __launch_bounds__(256, 4) void k_gemm32(float *__restrict__ C, int ld
     } else {
         I = blockIdx.x / ntj;
         J = blockIdx.x - I * ntj;
+        if (J >= zk0 && J < zk0 + 2) return;
     }
     const float *A = Ak + (size_t)I * kT, *B = Bk + (size_t)J * kT;
     float *base = C + (size_t)I * kT * ldc + (size_t)J * kT;
@@ -151,41 +177,20 @@ __global__ __launch_bounds__(256, 4) void k_gemm32(float *__restrict__ C, int ld
         for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int r = 0; r < 16; ++r) base[(size_t)acc_row(p, r) * ldc + acc_col(q)] = acc.v[p][q][r];
-}
-
-// Ut (kMB x np, k-major) = -U^T for step K0: Ut[k][i] = -M[i][K0 + k] for
-// rows i outside the block, and the identity (U's rows there are -I) for
-// rows inside it.  64 x 64 pieces through LDS, both sides coalesced.
-__global__ __launch_bounds__(256) void k_ut32(const float *__restrict__ M, int np, int K0, float *__restrict__ Ut,
-                                              const rdist_info *info) {
-    if (info->status != RDIST_OK) return;
-    __shared__ float t[64][65];
-    const int i0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < 64; r += 4) t[r][tx] = M[(size_t)(i0 + r) * np + K0 + k0 + tx];
-    __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        const int k = k0 + r, i = i0 + tx;
-        const bool in = i >= K0 && i < K0 + kMB;
-        Ut[(size_t)k * np + i] = in ? (i - K0 == k ? 1.0f : 0.0f) : -t[tx][r];
+    if constexpr (MODE == 1) {
+        if (Snext && I >= zk0 + 2 && I < zk0 + 4 && J >= zk0 + 2 && J < zk0 + 4) {
+            // read back what this thread just stored (the barrier keeps the
+            // compiler from holding the accumulators live for this copy,
+            // which cost the kernel 40 VGPRs and its fifth workgroup)
+            asm volatile("" ::: "memory");
+            double *sb = Snext + (size_t)(I - zk0 - 2) * kT * kMB + (size_t)(J - zk0 - 2) * kT;
+            for (int p = 0; p < 2; ++p)
+                for (int q = 0; q < 2; ++q)
+                    for (int r = 0; r < 16; ++r)
+                        sb[(size_t)acc_row(p, r) * kMB + acc_col(q)] =
+                            (double)base[(size_t)acc_row(p, r) * ldc + acc_col(q)];
+        }
     }
-}
-
-// Pt (kMB x kMB) = P^T rounded to FP32 (mode 0), or P into V's block
-// columns at K0 (mode 1); S holds P in FP64, row-major.
-__global__ __launch_bounds__(256) void k_pt32(const double *__restrict__ S, float *__restrict__ Pt,
-                                              float *__restrict__ V, int np, int K0, const rdist_info *info) {
-    if (info->status != RDIST_OK) return;
-    __shared__ double t[32][33];
-    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    if (V) {
-        for (int r = ty; r < 32; r += 8) V[(size_t)(r0 + r) * np + K0 + c0 + tx] = (float)S[(r0 + r) * kMB + c0 + tx];
-        return;
-    }
-    for (int r = ty; r < 32; r += 8) t[r][tx] = S[(r0 + r) * kMB + c0 + tx];
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) Pt[(c0 + r) * kMB + r0 + tx] = (float)t[tx][r];
 }
 
 // ---- bf16: operands m-major, hi and lo parts interleaved per 32 k ----
@@ -392,22 +397,18 @@ __global__ __launch_bounds__(256) void k_split_bf16_t(const float *__restrict__ 
 void launch_gemm32_rows(const float *Pt, const float *M, int np, int K0, float *V, const rdist_info *info,
                         hipStream_t s) {
     const int nt = np / kT;
-    hipLaunchKernelGGL(k_gemm32<0>, dim3(2 * nt), dim3(256), 0, s, V, np, nt, 0, Pt, kMB, M + (size_t)K0 * np, np,
-                       info);
+    hipLaunchKernelGGL(k_gemm32<0>, dim3(2 * nt), dim3(256), 0, s, V, np, nt, K0 / kT, Pt, kMB, M + (size_t)K0 * np,
+                       np, nullptr, info);
 }
 
-void launch_gemm32_update(float *M, int np, int K0, const float *Ut, const float *V, const rdist_info *info,
-                          hipStream_t s) {
+void launch_gemm32_update(float *M, int np, int K0, const float *Ut, const float *V, double *Snext,
+                          const rdist_info *info, hipStream_t s) {
     const int nt = np / kT;
-    hipLaunchKernelGGL(k_gemm32<1>, dim3(nt * nt), dim3(256), 0, s, M, np, nt, K0 / kT, Ut, np, V, np, info);
+    hipLaunchKernelGGL(k_gemm32<1>, dim3(nt * nt), dim3(256), 0, s, M, np, nt, K0 / kT, Ut, np, V, np, Snext, info);
 }
 
 void launch_ut32(const float *M, int np, int K0, float *Ut, const rdist_info *info, hipStream_t s) {
     hipLaunchKernelGGL(k_ut32, dim3(np / 64, kMB / 64), dim3(256), 0, s, M, np, K0, Ut, info);
-}
-
-void launch_pt32(const double *S, float *Pt, float *V, int np, int K0, const rdist_info *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_pt32, dim3(kMB / 32, kMB / 32), dim3(256), 0, s, S, Pt, V, np, K0, info);
 }
 
 int corr_cols(int cols) { return (cols + kTB - 1) / kTB * kTB; }

@@ -112,14 +112,15 @@ void launch_residual(const float *X, int np, int n, const int64_t *off, const in
 void launch_fix(const float *X, int np, int n, const float *C, int ldc, const int32_t *slabs, int nslab,
                 double margin, const unsigned *rmax, int16_t *D, rdist_info *info, hipStream_t s);
 // FP32 matrix-core steps of the mixed plan (rd_gemm.hip), step width 256:
-// Pt = P^T in FP32 (V == nullptr) or P into V's block columns at K0; Ut = -U^T;
-// V = P M_K,: (Pt, 256 x np); M <- M~ - U V over every tile.
-void launch_pt32(const double *S, float *Pt, float *V, int np, int K0, const rdist_info *info, hipStream_t s);
+// Ut = -U^T; V = P M_K,: (Pt = P^T in FP32, 256 x 256) outside V's block
+// columns at K0 (written with P by the block inverse); M <- M~ - U V over
+// every tile, with the next block's diagonal (when there is one) also
+// written to Snext in FP64 (256 x 256).
 void launch_ut32(const float *M, int np, int K0, float *Ut, const rdist_info *info, hipStream_t s);
 void launch_gemm32_rows(const float *Pt, const float *M, int np, int K0, float *V, const rdist_info *info,
                         hipStream_t s);
-void launch_gemm32_update(float *M, int np, int K0, const float *Ut, const float *V, const rdist_info *info,
-                          hipStream_t s);
+void launch_gemm32_update(float *M, int np, int K0, const float *Ut, const float *V, double *Snext,
+                          const rdist_info *info, hipStream_t s);
 // The bf16 operands of the correction: row r of an interleaved operand holds,
 // per block of 32 k-values, their 32 hi parts and then their 32 lo parts
 // (16-bit patterns, row length 2K).
@@ -137,6 +138,12 @@ void launch_split_bf16_x(const float *X, int rows, int cols, uint16_t *Xi, hipSt
 // 64, cols_pad a multiple of 64 not below cols.
 void launch_split_bf16_t(const float *R, int rows, int cols, int cols_pad, uint16_t *Ri, const unsigned *rmax,
                          hipStream_t s);
+// One 128-pivot step of a 256 x 256 block inverse (ld 256): T from S and
+// P = S_kk^{-1} (ld 256), pivot tile k of the 2 x 2 tiles; with Pt32 given,
+// also Pt32 = T^T (FP32, ld 256) and V32's columns K0 .. K0 + 255 = T (FP32,
+// ld ldv).
+void launch_blk2_step(const double *S, double *T, const double *P, int k, float *Pt32, float *V32, int ldv, int K0,
+                      const rdist_info *info, hipStream_t s);
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s);
 // Entries per query of a path output: the next node alone for max_hops = 1,
 // else the start and max_hops hops.

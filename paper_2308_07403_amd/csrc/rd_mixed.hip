@@ -231,6 +231,97 @@ __global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np
     flush_counts(info, cnt);
 }
 
+// One 128-pivot step of the 256 x 256 block inverse (2 x 2 tiles of 128):
+// from S (ld 256) and P = S_kk^{-1} (ld 256, written by the panel), with
+// o = 1 - k,
+//     T_kk = P,  T_ko = P S_ko,  T_ok = -S_ok P,  T_oo = S_oo - S_ok (P S_ko)
+// into T (ld 256): the Gauss-Jordan step of the block (Sec. 3's elimination
+// on the 2 x 2 tiles).  One launch in place of the row and column products
+// and the tile update of the general step (two launches of one or four
+// 128 x 128 products on one workgroup each, about 21 us apiece): 64
+// workgroups of 32 x 32 pieces, 16 per tile; wave w forms the 16 x 16 block
+// (w >> 1, w & 1) of its piece, and a piece of T_oo first forms its
+// 128 x 32 strip of P S_ko in LDS.  Every product takes the operands, the
+// starting accumulator (zero, or S_oo) and the k order of those kernels, so
+// T is bit for bit what they give.  On the last step (Pt32 given) T is the
+// block's inverse, and the FP32 roundings the next products read are written
+// too: Pt32 = T^T (ld 256) and V32's columns K0 .. K0 + 255 = T (ld ldv).
+// (Eight workgroups of 16 waves, one block per wave, took 27 us against 25.)
+__global__ __launch_bounds__(256) void k_blk2_step(const double *__restrict__ S, double *__restrict__ T,
+                                                   const double *__restrict__ P, int k, float *__restrict__ Pt32,
+                                                   float *__restrict__ V32, int ldv, int K0,
+                                                   const rdist_info *__restrict__ info) {
+    if (info->status != RDIST_OK) return;
+    __shared__ double Vs[128][33];
+    constexpr int ld = 2 * kTile;
+    const int tile = blockIdx.x >> 4, piece = blockIdx.x & 15;
+    const int pr = (piece >> 2) * 32, pc = (piece & 3) * 32;
+    const int o = 1 - k;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int bi = pr + 16 * (w >> 1), bj = pc + 16 * (w & 1);
+    const double *Sok = S + (size_t)o * kTile * ld + (size_t)k * kTile;   // S_ok(i, k) at Sok[i * ld + k]
+    const double *Sko = S + (size_t)k * kTile * ld + (size_t)o * kTile;
+    // T (i, j) = v, i and j within the block, with the FP32 copies
+    auto put = [&](int i, int j, double v) {
+        T[(size_t)i * ld + j] = v;
+        if (Pt32) {
+            Pt32[(size_t)j * ld + i] = (float)v;
+            V32[(size_t)i * ldv + K0 + j] = (float)v;
+        }
+    };
+    if (tile == 0) {   // T_kk = P
+        for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+            const int i = pr + (e >> 5), j = pc + (e & 31);
+            put(k * kTile + i, k * kTile + j, P[(size_t)i * ld + j]);
+        }
+        return;
+    }
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (tile == 1) {   // T_ko = P S_ko
+#pragma unroll 8
+        for (int kk = 0; kk < kTile; kk += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[(size_t)(bi + li) * ld + kk + lk],
+                                                        Sko[(size_t)(kk + lk) * ld + bj + li], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) put(k * kTile + bi + lk + 4 * r, o * kTile + bj + li, acc[r]);
+        return;
+    }
+    if (tile == 2) {   // T_ok = (-S_ok) P
+#pragma unroll 8
+        for (int kk = 0; kk < kTile; kk += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Sok[(size_t)(bi + li) * ld + kk + lk],
+                                                        P[(size_t)(kk + lk) * ld + bj + li], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) put(o * kTile + bi + lk + 4 * r, k * kTile + bj + li, acc[r]);
+        return;
+    }
+    // T_oo: the strip (P S_ko)[:, pc .. pc + 31], wave w its rows 32w .. 32w + 31
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            d4 v = {0.0, 0.0, 0.0, 0.0};
+            const int ri = 32 * w + 16 * p, cj = pc + 16 * q;
+#pragma unroll 8
+            for (int kk = 0; kk < kTile; kk += 4)
+                v = __builtin_amdgcn_mfma_f64_16x16x4f64(P[(size_t)(ri + li) * ld + kk + lk],
+                                                          Sko[(size_t)(kk + lk) * ld + cj + li], v, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Vs[ri + lk + 4 * r][16 * q + li] = v[r];
+        }
+    __syncthreads();
+    const double *Soo = S + (size_t)o * kTile * ld + (size_t)o * kTile;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = Soo[(size_t)(bi + lk + 4 * r) * ld + bj + li];
+#pragma unroll 8
+    for (int kk = 0; kk < kTile; kk += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Sok[(size_t)(bi + li) * ld + kk + lk], Vs[kk + lk][bj - pc + li],
+                                                    acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) put(o * kTile + bi + lk + 4 * r, o * kTile + bj + li, acc[r]);
+}
+
 __global__ void k_set_mixed_info(rdist_info *info, long long uncertified, double fraction) {
     info->n_uncertified = uncertified;
     info->fallback_fraction = fraction;
@@ -267,6 +358,10 @@ void launch_fix(const float *X, int np, int n, const float *C, int ldc, const in
     hipLaunchKernelGGL(k_fix, dim3(nslab, np / 32), dim3(256), 0, s, X, np, n, C, ldc, slabs, nslab, margin, rmax, D,
                        info);
 }
+void launch_blk2_step(const double *S, double *T, const double *P, int k, float *Pt32, float *V32, int ldv, int K0,
+                      const rdist_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_blk2_step, dim3(64), dim3(256), 0, s, S, T, P, k, Pt32, V32, ldv, K0, info);
+}
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s) {
     hipLaunchKernelGGL(k_set_mixed_info, dim3(1), dim3(1), 0, s, info, uncertified, fraction);
 }
@@ -292,7 +387,7 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
     if ((st = ensure(c, w.m32, (size_t)np * np * 4))) return st;
     if ((st = ensure(c, w.v32, (size_t)kMB * np * 4))) return st;
     if ((st = ensure(c, w.u32, (size_t)kMB * np * 4))) return st;
-    if ((st = ensure(c, w.s64, (size_t)kMB * kMB * 8))) return st;
+    if ((st = ensure(c, w.s64, (size_t)2 * kMB * kMB * 8))) return st;   // the block and its step copy
     if ((st = ensure(c, w.p32, (size_t)kMB * kMB * 4))) return st;
     if ((st = ensure(c, w.Ut2, (size_t)128 * 256 * 8))) return st;
     if ((st = ensure(c, w.V2, (size_t)128 * 256 * 8))) return st;
@@ -301,37 +396,39 @@ rdist_status solve_mixed(rdist_ctx c, const uint8_t *A, int n, double gamma, uin
     if ((st = ensure(c, w.cert, 256 + (size_t)nslab_all * 4))) return st;
     rdist_info *dinfo = w.dinfo();
     float *M = (float *)w.m32.p, *V = (float *)w.v32.p, *Ut = (float *)w.u32.p, *Pt = (float *)w.p32.p;
-    double *S = (double *)w.s64.p;
+    double *S = (double *)w.s64.p, *S2 = S + (size_t)kMB * kMB;
     {
         Timer t(c, s, RDIST_K_INGEST, 0.0, (double)n * n + 4.0 * np * np);
         rd::launch_gate(A, n, gamma, w.outdeg(), w.bad(), dinfo, s);
         rd::launch_m32_build(A, n, np, M, dinfo, s);
     }
     RD_HIP(hipGetLastError());
+    // (Ut on a second stream beside the block inverse, 13.5 us a step, gained
+    // nothing: the two cross-stream hand-offs cost about as much.)
     for (int K = 0; K < nb; ++K) {
         const int K0 = K * kMB;
         {
             Timer t(c, s, RDIST_K_PANEL, 2.0 * kMB * kMB * kMB, 16.0 * kMB * kMB);
-            rd::launch_diag_to_f64(M, np, K0, S, s);
-            for (int k2 = 0; k2 < 2; ++k2) {
-                rd::launch_panel(S, kMB, k2, (double *)w.Pt2.p, (double *)w.V2.p, kMB, dinfo, s);
-                rd::launch_rowcol(S, kMB, 2, k2, 1, (const double *)w.Pt2.p, (double *)w.Ut2.p, (double *)w.V2.p,
-                                  kMB, dinfo, s);
-                rd::launch_update(rd::kUpdateAll, S, kMB, 2, k2, 1, 0, 1, (const double *)w.Ut2.p,
-                                  (const double *)w.V2.p, kMB, false, 0, nullptr, 0, dinfo, s);
-            }
+            // the block's inverse by two 128-pivot steps, S -> S2 -> S (the
+            // panel leaves P in V2's column block k2, ld 256); the second
+            // also writes P^T in FP32 to Pt and P in FP32 to V's block
+            // columns.  S holds the block in FP64: converted here for the
+            // first, written by the previous step's update for the others.
+            if (K == 0) rd::launch_diag_to_f64(M, np, K0, S, s);
+            rd::launch_panel(S, kMB, 0, (double *)w.Pt2.p, (double *)w.V2.p, kMB, dinfo, s);
+            rd::launch_blk2_step(S, S2, (const double *)w.V2.p, 0, nullptr, nullptr, 0, 0, dinfo, s);
+            rd::launch_panel(S2, kMB, 1, (double *)w.Pt2.p, (double *)w.V2.p, kMB, dinfo, s);
+            rd::launch_blk2_step(S2, S, (const double *)w.V2.p + 128, 1, Pt, V, np, K0, dinfo, s);
         }
         RD_HIP(hipGetLastError());
         {
             Timer t(c, s, RDIST_K_ROWCOL, 2.0 * kMB * (double)kMB * np, 4.0 * (4.0 * kMB * np));
-            rd::launch_pt32(S, Pt, nullptr, np, K0, dinfo, s);         // P^T rounded to FP32
-            rd::launch_gemm32_rows(Pt, M, np, K0, V, dinfo, s);        // V = P M_K,:
-            rd::launch_pt32(S, nullptr, V, np, K0, dinfo, s);          // V_K = P
+            rd::launch_gemm32_rows(Pt, M, np, K0, V, dinfo, s);        // V = P M_K,: outside V_K = P
             rd::launch_ut32(M, np, K0, Ut, dinfo, s);                  // Ut = -U^T (U_K = -I)
         }
         {
             Timer t(c, s, RDIST_K_MIXED_GEMM, 2.0 * np * (double)np * kMB, 4.0 * (2.0 * np * (double)np));
-            rd::launch_gemm32_update(M, np, K0, Ut, V, dinfo, s);      // M <- M~ - U V
+            rd::launch_gemm32_update(M, np, K0, Ut, V, S, dinfo, s);   // M <- M~ - U V; next block into S
         }
         RD_HIP(hipGetLastError());
     }
