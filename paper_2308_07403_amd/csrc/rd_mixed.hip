@@ -238,15 +238,16 @@ __global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np
 // into T (ld 256): the Gauss-Jordan step of the block (Sec. 3's elimination
 // on the 2 x 2 tiles).  One launch in place of the row and column products
 // and the tile update of the general step (two launches of one or four
-// 128 x 128 products on one workgroup each, about 21 us apiece): 64
-// workgroups of 32 x 32 pieces, 16 per tile; wave w forms the 16 x 16 block
+// 128 x 128 products on one workgroup each, about 21 us apiece), 15.5 us:
+// 64 workgroups of 32 x 32 pieces, 16 per tile; wave w forms the 16 x 16 block
 // (w >> 1, w & 1) of its piece, and a piece of T_oo first forms its
 // 128 x 32 strip of P S_ko in LDS.  Every product takes the operands, the
 // starting accumulator (zero, or S_oo) and the k order of those kernels, so
 // T is bit for bit what they give.  On the last step (Pt32 given) T is the
 // block's inverse, and the FP32 roundings the next products read are written
 // too: Pt32 = T^T (ld 256) and V32's columns K0 .. K0 + 255 = T (ld ldv).
-// (Eight workgroups of 16 waves, one block per wave, took 27 us against 25.)
+// (Eight workgroups of 16 waves, one block per wave, took 27 us against 25
+// for this form before its passes over k were merged and unrolled.)
 __global__ __launch_bounds__(256) void k_blk2_step(const double *__restrict__ S, double *__restrict__ T,
                                                    const double *__restrict__ P, int k, float *__restrict__ Pt32,
                                                    float *__restrict__ V32, int ldv, int K0,
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(256) void k_blk2_step(const double *__restrict__ S,
     }
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     if (tile == 1) {   // T_ko = P S_ko
-#pragma unroll 8
+#pragma unroll
         for (int kk = 0; kk < kTile; kk += 4)
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[(size_t)(bi + li) * ld + kk + lk],
                                                         Sko[(size_t)(kk + lk) * ld + bj + li], acc, 0, 0, 0);
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) void k_blk2_step(const double *__restrict__ S,
         return;
     }
     if (tile == 2) {   // T_ok = (-S_ok) P
-#pragma unroll 8
+#pragma unroll
         for (int kk = 0; kk < kTile; kk += 4)
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Sok[(size_t)(bi + li) * ld + kk + lk],
                                                         P[(size_t)(kk + lk) * ld + bj + li], acc, 0, 0, 0);
@@ -297,24 +298,36 @@ __global__ __launch_bounds__(256) void k_blk2_step(const double *__restrict__ S,
         return;
     }
     // T_oo: the strip (P S_ko)[:, pc .. pc + 31], wave w its rows 32w .. 32w + 31
+    // as 2 x 2 blocks, all four in one pass over k (four separate passes
+    // waited on their operand loads four times as often); every pass over k
+    // unrolled so that its loads are issued together (25 us with four passes
+    // unrolled by 8, 17.5 with one, 15.5 fully unrolled)
+    {
+        d4 v[2][2] = {};
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+        for (int kk = 0; kk < kTile; kk += 4) {
+            double a[2], b[2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            d4 v = {0.0, 0.0, 0.0, 0.0};
-            const int ri = 32 * w + 16 * p, cj = pc + 16 * q;
-#pragma unroll 8
-            for (int kk = 0; kk < kTile; kk += 4)
-                v = __builtin_amdgcn_mfma_f64_16x16x4f64(P[(size_t)(ri + li) * ld + kk + lk],
-                                                          Sko[(size_t)(kk + lk) * ld + cj + li], v, 0, 0, 0);
+            for (int p = 0; p < 2; ++p) a[p] = P[(size_t)(32 * w + 16 * p + li) * ld + kk + lk];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Vs[ri + lk + 4 * r][16 * q + li] = v[r];
+            for (int q = 0; q < 2; ++q) b[q] = Sko[(size_t)(kk + lk) * ld + pc + 16 * q + li];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) v[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], v[p][q], 0, 0, 0);
         }
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Vs[32 * w + 16 * p + lk + 4 * r][16 * q + li] = v[p][q][r];
+    }
     __syncthreads();
     const double *Soo = S + (size_t)o * kTile * ld + (size_t)o * kTile;
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = Soo[(size_t)(bi + lk + 4 * r) * ld + bj + li];
-#pragma unroll 8
+#pragma unroll
     for (int kk = 0; kk < kTile; kk += 4)
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Sok[(size_t)(bi + li) * ld + kk + lk], Vs[kk + lk][bj - pc + li],
                                                     acc, 0, 0, 0);
