@@ -235,8 +235,8 @@ __global__ __launch_bounds__(256) void k_fix(const float *__restrict__ X, int np
 // from S (ld 256) and P = S_kk^{-1} (ld 256, written by the panel), with
 // o = 1 - k,
 //     T_kk = P,  T_ko = P S_ko,  T_ok = -S_ok P,  T_oo = S_oo - S_ok (P S_ko)
-// into T (ld 256): the Gauss-Jordan step of the block (Sec. 3's elimination
-// on the 2 x 2 tiles).  One launch in place of the row and column products
+// into T (ld 256): one Gauss-Jordan step of the inversion behind Eq. Y-defined
+// (the cost Sec. 5.2 names as dominant) on the block's 2 x 2 tiles.  One launch in place of the row and column products
 // and the tile update of the general step (two launches of one or four
 // 128 x 128 products on one workgroup each, about 21 us apiece), 15.5 us:
 // 64 workgroups of 32 x 32 pieces, 16 per tile; wave w forms the 16 x 16 block
