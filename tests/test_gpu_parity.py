@@ -904,8 +904,12 @@ def test_mixed_c2_subsample(ctx):
     check_mixed(ctx, gg.c2_subsample(0), -0.5, "c2 subsample 0")
 
 
-@pytest.mark.parametrize("family,n", [("er", 300), ("rgg", 700), ("lattice", 500), ("tree", 257)])
+@pytest.mark.parametrize("family,n", [("er", 300), ("rgg", 700), ("lattice", 500), ("tree", 257),
+                                      ("er", 200), ("rgg", 1100)])
 def test_mixed_families(ctx, family, n):
+    """The mixed plan against the oracle on the graph families: one 256-wide
+    block (n = 200), odd block counts with identity padding in the last block
+    (700, 1100), and a tree whose last block holds a single node (257)."""
     rng = gg.rng_for("parity", 8400 + n)
     A = {"er": lambda: gg.erdos_renyi(n, 0.05, rng),
          "rgg": lambda: gg.random_geometric(n, rng),
