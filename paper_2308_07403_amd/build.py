@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librdist.so")
-SOURCES = ["rd_engine.hip", "rd_host.cpp", "rd_batch.hip", "rd_mixed.hip", "rd_server.hip", "rd_kernels.hip", "rd_update.hip", "rd_level.hip", "rd_paths.hip", "rd_dynamic.hip", "rd_rows.hip", "rd_gamma.hip", "rd_gemm.hip"]
+SOURCES = ["rd_engine.hip", "rd_host.cpp", "rd_batch.hip", "rd_mixed.hip", "rd_server.hip", "rd_kernels.hip", "rd_update.hip", "rd_level.hip", "rd_paths.hip", "rd_dynamic.hip", "rd_rows.hip", "rd_gamma.hip", "rd_gemm.hip", "rd_chain.hip"]
 # every kernel is this project's own: no vendor math library is linked
 LINK = []
 OBJDIR = os.path.join(HERE, "_build")

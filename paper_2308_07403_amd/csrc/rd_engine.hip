@@ -287,8 +287,12 @@ void enqueue_rowcol(rdist_ctx c, Workspace &w, int ld, int nt, int K0, int m, in
                     hipStream_t st) {
     const double b = 128.0 * m;
     Timer t(c, st, RDIST_K_ROWCOL, 2.0 * b * b * (nt * 128.0 - b), 8.0 * 4 * b * nt * 128.0);
-    rd::launch_rowcol(w.m(), ld, nt, K0, m, (double *)w.Pt[par].p, (double *)w.Ut[par].p, (double *)w.V[par].p,
-                      ld, dinfo, st);
+    if (m == 1)
+        rd::launch_rowcol64(w.m(), ld, nt, K0, (double *)w.Pt[par].p, (double *)w.Ut[par].p, (double *)w.V[par].p, ld,
+                            dinfo, st);
+    else
+        rd::launch_rowcol(w.m(), ld, nt, K0, m, (double *)w.Pt[par].p, (double *)w.Ut[par].p, (double *)w.V[par].p,
+                          ld, dinfo, st);
 }
 
 // Blocked solve of one graph on stream s: blocks of b = 128*m columns.
@@ -371,7 +375,11 @@ rdist_status enqueue_blocked(rdist_ctx c, Workspace &w, int ld, const uint8_t *A
             }
             {
                 Timer t(c, as, RDIST_K_UPDATE_EDGE, tile_flops * td, 16.0 * kB * kB * td);
-                rd::launch_update(rd::kUpdateDiag, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo, as);
+                if (m == 1)
+                    rd::launch_diag64(M, ld, L0, Ut, V, ld, dinfo, as);
+                else
+                    rd::launch_update(rd::kUpdateDiag, M, ld, nt, K0, m, L0, wt, Ut, V, ld, false, n, D, 0, dinfo,
+                                      as);
             }
             if (m == 2) {
                 rdist_status sp = enqueue_pair256(c, w, ld, nt, L0, par ^ 1, dinfo, as, two ? w.ev_er : nullptr,

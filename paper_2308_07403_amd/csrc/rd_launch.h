@@ -145,6 +145,13 @@ void launch_split_bf16_t(const float *R, int rows, int cols, int cols_pad, uint1
 void launch_blk2_step(const double *S, double *T, const double *P, int k, float *Pt32, float *V32, int ldv, int K0,
                       const rdist_info *info, hipStream_t s);
 void launch_set_mixed_info(rdist_info *info, long long uncertified, double fraction, hipStream_t s);
+// The lookahead chain's products for 128-wide blocks (rd_chain.hip), as four
+// 64 x 64 workgroups each: the DIAG update of tile (L0, L0), and the row and
+// column tiles of step K (as launch_rowcol with m = 1).
+void launch_diag64(double *M, int ld, int L0, const double *Ut, const double *V, int ldv, const rdist_info *info,
+                   hipStream_t s);
+void launch_rowcol64(const double *M, int ld, int nt, int K, const double *Pt, double *Ut, double *V, int ldv,
+                     const rdist_info *info, hipStream_t s);
 // Entries per query of a path output: the next node alone for max_hops = 1,
 // else the start and max_hops hops.
 __host__ __device__ inline int path_row_len(int max_hops) { return max_hops == 1 ? 1 : max_hops + 1; }

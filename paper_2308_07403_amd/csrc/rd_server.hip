@@ -287,7 +287,7 @@ rdist_status dispatch_batch(rdist_server s, Slot &sl, const std::vector<Pending>
 
 // A request from this order on runs alone on the single-graph plan (width
 // 128 up to n = 6400) when few requests wait: faster than the level plan for
-// one graph (n = 4096: 4.56 against 6.19 ms; n = 2048: 1.94 against 2.26)
+// one graph (n = 4096: 4.40 against 6.19 ms; n = 2048: 1.82 against 2.26)
 // and the same results bit for bit (both take the same 128-pivot steps with
 // the same products in the same order).  Behind a backlog it joins the batch
 // instead, whose level plan keeps many large graphs in flight at once.  At
