@@ -12,7 +12,6 @@
 #include <hip/hip_runtime.h>
 
 #include "rd_device.h"
-#include "rd_gj.h"
 #include "rd_launch.h"
 
 namespace rd {
@@ -84,8 +83,10 @@ __global__ __launch_bounds__(256) void k_diag64(double *__restrict__ M, int ld, 
 
 // Row and column tiles of step K (block width 128): workgroups [0, 4 nt)
 // form V_J = P M_KJ for J != K, a 64 x 64 quarter each (Pt = P^T, ld 128);
-// workgroups [4 nt, 5 nt) the negated transposed column block,
-// Ut_I = -(M_IK)^T for I != K and +I for I = K (U_K = -I).
+// workgroups [4 nt, 8 nt) the negated transposed column block,
+// Ut_I = -(M_IK)^T for I != K and +I for I = K (U_K = -I), a 64 x 64 piece
+// each through LDS (one workgroup per tile, its four pieces in turn, held
+// the launch at the 22 us of the single-workgroup products).
 __global__ __launch_bounds__(256) void k_rowcol64(const double *__restrict__ M, int ld, int nt, int K,
                                                   const double *__restrict__ Pt, double *__restrict__ Ut,
                                                   double *__restrict__ V, int ldv, const rdist_info *info) {
@@ -105,17 +106,26 @@ __global__ __launch_bounds__(256) void k_rowcol64(const double *__restrict__ M, 
         piece_for_each(acc, [&](int r, int c, double v) { out[(size_t)r * ldv + c] = v; });
         return;
     }
-    __shared__ double lds[64 * 65];
-    const int I = blk - 4 * nt;
-    double *out = Ut + (size_t)I * kTile;          // Ut[k][I*128 + i]
+    __shared__ double t[64][65];
+    const int e0 = blk - 4 * nt, I = e0 >> 2, bi = (e0 >> 1) & 1, bk = e0 & 1;
+    double *out = Ut + (size_t)I * kTile + (size_t)bk * 64 * ldv + bi * 64;   // Ut[64 bk + k][I*128 + 64 bi + i]
     if (I == K) {
-        for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
-            const int k = e >> 7, i = e & 127;
-            out[(size_t)k * ldv + i] = (k == i) ? 1.0 : 0.0;
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int k = e >> 6, i = e & 63;
+            out[(size_t)k * ldv + i] = (bk * 64 + k == bi * 64 + i) ? 1.0 : 0.0;
         }
         return;
     }
-    transpose_neg(M + (size_t)I * kTile * ld + (size_t)K * kTile, ld, 2, out, ldv, lds);
+    const double *src = M + (size_t)(I * kTile + bi * 64) * ld + (size_t)K * kTile + bk * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;     // r: row i, c: column k
+        t[r][c] = src[(size_t)r * ld + c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int k = e >> 6, i = e & 63;
+        out[(size_t)k * ldv + i] = -t[i][k];
+    }
 }
 
 }  // namespace
@@ -127,7 +137,7 @@ void launch_diag64(double *M, int ld, int L0, const double *Ut, const double *V,
 
 void launch_rowcol64(const double *M, int ld, int nt, int K, const double *Pt, double *Ut, double *V, int ldv,
                      const rdist_info *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_rowcol64, dim3(5 * nt), dim3(256), 0, s, M, ld, nt, K, Pt, Ut, V, ldv, info);
+    hipLaunchKernelGGL(k_rowcol64, dim3(8 * nt), dim3(256), 0, s, M, ld, nt, K, Pt, Ut, V, ldv, info);
 }
 
 }  // namespace rd

@@ -287,12 +287,13 @@ rdist_status dispatch_batch(rdist_server s, Slot &sl, const std::vector<Pending>
 
 // A request from this order on runs alone on the single-graph plan (width
 // 128 up to n = 6400) when few requests wait: faster than the level plan for
-// one graph (n = 4096: 4.40 against 6.19 ms; n = 2048: 1.82 against 2.26)
+// one graph (n = 4096: 4.16 against 6.19 ms; n = 2048: 1.53 against 2.26)
 // and the same results bit for bit (both take the same 128-pivot steps with
 // the same products in the same order).  Behind a backlog it joins the batch
 // instead, whose level plan keeps many large graphs in flight at once.  At
 // the C5 request mix (two slots, 0.1x of saturation) this moved p99 from
-// 11.9 to 8.0 ms with the saturated rate unchanged; taking such requests out
+// 11.9 to 8.0 ms with the saturated rate unchanged (6.3 ms once the lone
+// plan's chain products were split into 64 x 64 pieces); taking such requests out
 // of batches always cost a third of the saturated rate.
 constexpr int kLoneSingleMinN = 1025;
 bool lone(const rdist_request &r) { return r.n >= kLoneSingleMinN; }
